@@ -1,0 +1,188 @@
+"""FP64 CPU oracle for the lambda-interpolated Coulomb solve.
+
+TEST INFRASTRUCTURE ONLY: the tests, the smoke check and the CPU-baseline leg
+of the benchmark may import this package; the product library never does, and
+this package never imports the product package.  The arithmetic lives in
+``coulomb_oracle.c`` (plain C, FP64, OpenMP over target atoms); this file only
+marshals numpy arrays and chooses Ewald parameters.
+
+What is computed (constant-pH lambda-dynamics paper, Methods, eq 1 with the
+charge-interpolated form, and "Calibration of Protonation Dynamics", where the
+lambda-derivative of the Hamiltonian is the Coulomb term alone):
+
+    q_i     = qA_i + lambda_{s(i)} (qB_i - qA_i)         (site -1: q_i = qA_i)
+    phi_i   = k_e sum_j' q_j psi(r_i - r_j)              (potential at atom i)
+    E       = 1/2 sum_i q_i phi_i
+    F_i     = -dE/dr_i
+    dVdl_s  = sum_{i in s} (qB_i - qA_i) phi_i           (= dE/dlambda_s)
+
+with psi = 1/r for open boundaries (direct sum) and psi the tin-foil,
+neutralising-background, zero-mean periodic Green's function for periodic ones
+(Ewald sum).
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "coulomb_oracle.c")
+_LIB_PATH = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+_f64p = np.ctypeslib.ndpointer(dtype=np.float64, flags="C_CONTIGUOUS")
+_i32p = np.ctypeslib.ndpointer(dtype=np.int32, flags="C_CONTIGUOUS")
+_i64p = np.ctypeslib.ndpointer(dtype=np.int64, flags="C_CONTIGUOUS")
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with gcc (-O2, OpenMP).  Returns the library path."""
+    if force or not os.path.exists(_LIB_PATH):
+        tmp = _LIB_PATH + ".tmp%d" % os.getpid()
+        subprocess.check_call(
+            ["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-std=c11",
+             "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, _LIB_PATH)
+    return _LIB_PATH
+
+
+def _load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if (not os.path.exists(_LIB_PATH)
+            or os.path.getmtime(_LIB_PATH) < os.path.getmtime(_SRC)):
+        build(force=True)
+    lib = ctypes.CDLL(_LIB_PATH)
+    lib.orc_num_threads.restype = ctypes.c_int
+    lib.orc_lambda_charges.restype = ctypes.c_int
+    lib.orc_lambda_charges.argtypes = [ctypes.c_int64, _f64p, _f64p, _i32p,
+                                       ctypes.c_int64, _f64p, _f64p]
+    lib.orc_direct.restype = None
+    lib.orc_direct.argtypes = [ctypes.c_int64, _f64p, _f64p, ctypes.c_int64,
+                               ctypes.c_void_p, _f64p, _f64p]
+    lib.orc_ewald.restype = ctypes.c_int
+    lib.orc_ewald.argtypes = [ctypes.c_int64, _f64p, _f64p, _f64p, ctypes.c_double,
+                              ctypes.c_double, _i32p, ctypes.c_int64,
+                              ctypes.c_void_p, _f64p, _f64p]
+    lib.orc_outputs.restype = ctypes.c_int
+    lib.orc_outputs.argtypes = [ctypes.c_int64, _f64p, _f64p, _f64p, _i32p,
+                                ctypes.c_int64, _f64p, _f64p, ctypes.c_double,
+                                ctypes.POINTER(ctypes.c_double), ctypes.c_void_p,
+                                ctypes.c_void_p]
+    _lib = lib
+    return lib
+
+
+def num_threads() -> int:
+    return int(_load().orc_num_threads())
+
+
+def _f64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def lambda_charges(qA, qB, site, lam):
+    """eq 1, charge-interpolated: q = qA + lambda_s (qB - qA); site -1 keeps qA."""
+    qA, qB, lam = _f64(qA), _f64(qB), _f64(np.atleast_1d(lam))
+    site = np.ascontiguousarray(site, dtype=np.int32)
+    q = np.empty_like(qA)
+    rc = _load().orc_lambda_charges(qA.size, qA, qB, site, lam.size, lam, q)
+    if rc != 0:
+        raise ValueError("site index outside [-1, n_sites)")
+    return q
+
+
+def _targets(targets, n):
+    if targets is None:
+        return None, n, None
+    t = np.ascontiguousarray(targets, dtype=np.int64)
+    if t.size and (t.min() < 0 or t.max() >= n):
+        raise ValueError("target index out of range")
+    return t, t.size, t.ctypes.data
+
+
+def direct(x, q, targets=None):
+    """Open-boundary direct sum: phi_i = sum_{j!=i} q_j/r_ij and the field at i."""
+    x, q = _f64(x).reshape(-1, 3), _f64(q)
+    t, nt, tp = _targets(targets, q.size)
+    phi = np.empty(nt)
+    field = np.empty((nt, 3))
+    _load().orc_direct(q.size, x, q, nt, tp, phi, field)
+    return phi, field
+
+
+def ewald_params(box, eps: float = 1e-13, rcut: float | None = None):
+    """Ewald parameters for a relative accuracy of about eps.
+
+    rcut defaults to half the shortest edge; beta = s / rcut with
+    erfc(s) ~ eps; kmax_a = ceil(2 beta s L_a / (2 pi)) so that
+    exp(-k^2 / 4 beta^2) < eps beyond it.
+    """
+    box = np.asarray(box, dtype=np.float64).reshape(3)
+    if rcut is None:
+        rcut = 0.5 * float(box.min())
+    s = math.sqrt(-math.log(eps))
+    while math.erfc(s) > eps:
+        s += 0.05
+    beta = s / rcut
+    kmax = np.array([int(math.ceil(2 * beta * s * L / (2 * math.pi))) for L in box],
+                    dtype=np.int32)
+    return float(beta), float(rcut), kmax
+
+
+def ewald(x, q, box, beta=None, rcut=None, kmax=None, eps=1e-13, targets=None):
+    """Periodic Ewald potential and field (tin-foil, background, zero mean)."""
+    x, q = _f64(x).reshape(-1, 3), _f64(q)
+    box = _f64(np.broadcast_to(np.asarray(box, dtype=np.float64), (3,)))
+    b0, r0, k0 = ewald_params(box, eps, rcut)
+    beta = b0 if beta is None else float(beta)
+    rcut = r0 if rcut is None else float(rcut)
+    if kmax is None:
+        s = beta * rcut
+        kmax = np.array([int(math.ceil(2 * beta * s * L / (2 * math.pi))) for L in box],
+                        dtype=np.int32)
+    kmax = np.ascontiguousarray(np.broadcast_to(np.asarray(kmax), (3,)), dtype=np.int32)
+    t, nt, tp = _targets(targets, q.size)
+    phi = np.empty(nt)
+    field = np.empty((nt, 3))
+    rc = _load().orc_ewald(q.size, x, q, box, beta, rcut, kmax, nt, tp, phi, field)
+    if rc != 0:
+        raise ValueError("orc_ewald: bad arguments or out of memory")
+    return phi, field
+
+
+def outputs(q, qA, qB, site, n_sites, phi, field, k_e=1.0):
+    """E = 1/2 k_e sum q phi ; F = k_e q field ; dVdl_s = k_e sum_{i in s} dq_i phi_i."""
+    q, qA, qB, phi = _f64(q), _f64(qA), _f64(qB), _f64(phi)
+    field = _f64(field).reshape(-1, 3)
+    site = np.ascontiguousarray(site, dtype=np.int32)
+    F = np.empty((q.size, 3))
+    dVdl = np.empty(max(int(n_sites), 0))
+    E = ctypes.c_double(0.0)
+    rc = _load().orc_outputs(q.size, q, qA, qB, site, int(n_sites), phi, field,
+                             float(k_e), ctypes.byref(E), F.ctypes.data,
+                             dVdl.ctypes.data if dVdl.size else None)
+    if rc != 0:
+        raise ValueError("site index outside [-1, n_sites)")
+    return E.value, F, dVdl
+
+
+def solve(x, qA, qB, site, lam, box=None, periodic=False, k_e=1.0, eps=1e-13,
+          ewald_kw=None):
+    """Full oracle solve.  Returns dict(E, F, phi, dVdl, q), all FP64.
+
+    phi is returned already multiplied by k_e.
+    """
+    lam = _f64(np.atleast_1d(lam))
+    q = lambda_charges(qA, qB, site, lam)
+    if periodic:
+        phi, field = ewald(x, q, box, eps=eps, **(ewald_kw or {}))
+    else:
+        phi, field = direct(x, q)
+    E, F, dVdl = outputs(q, qA, qB, site, lam.size, phi, field, k_e)
+    return {"E": E, "F": F, "phi": k_e * phi, "dVdl": dVdl, "q": q}

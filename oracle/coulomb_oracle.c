@@ -1,0 +1,281 @@
+/*
+ * coulomb_oracle.c -- plain, slow, FP64 CPU oracle for the lambda-interpolated
+ * Coulomb solve (energy, forces, potentials and per-site lambda-forces).
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the product path may link, load or
+ * call this file: only the tests, the smoke check and the CPU-baseline leg of
+ * the benchmark do.  It shares no code, header or table with the HIP library.
+ *
+ * What it computes (Kohnke et al., constant-pH lambda-dynamics with FMM
+ * electrostatics; Methods, "Constant pH Simulations Based on lambda-dynamics",
+ * eq 1 and the text that follows it, and "Calibration of Protonation
+ * Dynamics", where the derivative of the Hamiltonian with respect to lambda is
+ * stated to be purely Coulombic because forms differ only in their charges):
+ *
+ *   q_i       = qA_i + lambda_{s(i)} (qB_i - qA_i)      (q_i = qA_i if s(i) = -1)
+ *   phi_i     = k_e * sum_{j != i} q_j / r_ij           (open boundaries)
+ *   E         = 1/2 sum_i q_i phi_i
+ *   F_i       = q_i * field_i = -dE/dr_i
+ *   dV/dl_s   = sum_{i in s} (qB_i - qA_i) phi_i        (= dE/dlambda_s)
+ *
+ * Periodic boundaries (the paper's simulations are periodic and lattice-summed,
+ * Introduction, and it requires the box to stay neutral, "Sites Acting as
+ * Charge Buffers"): phi is the periodic solution of Poisson's equation with a
+ * uniform neutralising background, conducting ("tin-foil") surroundings and
+ * zero cell mean, with the self term removed.  It is evaluated by a plain
+ * Ewald sum: real-space erfc sum over images, reciprocal-space sum over k != 0,
+ * self term -2 beta q_i / sqrt(pi), background term -pi Q / (V beta^2).
+ *
+ * All arithmetic is FP64.  Loops are the textbook double loops, parallel over
+ * target atoms with OpenMP; no blocking, sorting or tree of any kind.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+#define ORC_PI 3.14159265358979323846
+
+/* Neumaier compensated accumulator. */
+typedef struct { double s, c; } acc_t;
+static inline void acc_add(acc_t* a, double v) {
+    double t = a->s + v;
+    if (fabs(a->s) >= fabs(v)) a->c += (a->s - t) + v;
+    else a->c += (v - t) + a->s;
+    a->s = t;
+}
+static inline double acc_get(const acc_t* a) { return a->s + a->c; }
+
+int orc_num_threads(void) {
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
+
+/* Charge interpolation of eq 1 written per atom: q = qA + lambda_s (qB - qA).
+ * Returns 0, or -1 if a site index lies outside [-1, nsites). */
+int orc_lambda_charges(int64_t n, const double* qA, const double* qB,
+                       const int32_t* site, int64_t nsites,
+                       const double* lam, double* q) {
+    for (int64_t i = 0; i < n; ++i) {
+        int32_t s = site ? site[i] : -1;
+        if (s < -1 || s >= nsites) return -1;
+        q[i] = (s < 0) ? qA[i] : qA[i] + lam[s] * (qB[i] - qA[i]);
+    }
+    return 0;
+}
+
+/* Open-boundary direct sum (the plain definition of the Coulomb potential).
+ * targets: ntarget indices into [0,n) (NULL means all n atoms, ntarget = n).
+ * phi[t] = sum_{j != i} q_j / |r_i - r_j|,
+ * field[3t..3t+2] = sum_{j != i} q_j (r_i - r_j) / |r_i - r_j|^3, with i = targets[t].
+ * x is n x 3 row-major.  k_e is applied by orc_outputs, not here. */
+void orc_direct(int64_t n, const double* x, const double* q,
+                int64_t ntarget, const int64_t* targets,
+                double* phi, double* field) {
+    if (!targets) ntarget = n;
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t t = 0; t < ntarget; ++t) {
+        int64_t i = targets ? targets[t] : t;
+        acc_t p = {0, 0}, fx = {0, 0}, fy = {0, 0}, fz = {0, 0};
+        double xi = x[3 * i], yi = x[3 * i + 1], zi = x[3 * i + 2];
+        for (int64_t j = 0; j < n; ++j) {
+            if (j == i) continue;
+            double dx = xi - x[3 * j], dy = yi - x[3 * j + 1], dz = zi - x[3 * j + 2];
+            double r2 = dx * dx + dy * dy + dz * dz;
+            double r = sqrt(r2);
+            double qr = q[j] / r;
+            double qr3 = qr / r2;
+            acc_add(&p, qr);
+            acc_add(&fx, qr3 * dx);
+            acc_add(&fy, qr3 * dy);
+            acc_add(&fz, qr3 * dz);
+        }
+        phi[t] = acc_get(&p);
+        field[3 * t] = acc_get(&fx);
+        field[3 * t + 1] = acc_get(&fy);
+        field[3 * t + 2] = acc_get(&fz);
+    }
+}
+
+/* Ewald sum for an orthorhombic box with edges box[0..2] (tin-foil surroundings,
+ * uniform background for a net charge, zero-mean potential).
+ *   beta  : splitting parameter (1/length)
+ *   rcut  : real-space cutoff; every image n with |r_ij + n L| < rcut is summed,
+ *           including self images (j = i, n != 0)
+ *   kmax  : |m_a| <= kmax[a] for k = 2 pi (m_x/Lx, m_y/Ly, m_z/Lz), k != 0
+ * Outputs as for orc_direct (potential excludes only the i = j, n = 0 term).
+ * Returns 0, or -1 on bad arguments / allocation failure. */
+int orc_ewald(int64_t n, const double* x, const double* q, const double* box,
+              double beta, double rcut, const int32_t* kmax,
+              int64_t ntarget, const int64_t* targets,
+              double* phi, double* field) {
+    if (!targets) ntarget = n;
+    if (box[0] <= 0 || box[1] <= 0 || box[2] <= 0 || beta <= 0 || rcut <= 0) return -1;
+    if (kmax[0] < 0 || kmax[1] < 0 || kmax[2] < 0) return -1;
+    const double L[3] = {box[0], box[1], box[2]};
+    const double V = L[0] * L[1] * L[2];
+    const double rc2 = rcut * rcut;
+    const double two_b_sqrtpi = 2.0 * beta / sqrt(ORC_PI);
+
+    double Q = 0.0;
+    for (int64_t j = 0; j < n; ++j) Q += q[j];
+
+    /* k-vectors on a half space: (mx > 0) or (mx = 0, my > 0) or (mx = my = 0, mz > 0);
+     * each carries the factor 2 of its -k partner. */
+    const int kx = kmax[0], ky = kmax[1], kz = kmax[2];
+    int64_t nk_max = (int64_t)(2 * kx + 1) * (2 * ky + 1) * (2 * kz + 1);
+    int32_t* km = (int32_t*)malloc(sizeof(int32_t) * 3 * (size_t)nk_max);
+    double* kc = (double*)malloc(sizeof(double) * (size_t)nk_max);
+    if (!km || !kc) { free(km); free(kc); return -1; }
+    int64_t nk = 0;
+    for (int mx = 0; mx <= kx; ++mx)
+        for (int my = -ky; my <= ky; ++my)
+            for (int mz = -kz; mz <= kz; ++mz) {
+                if (mx == 0 && (my < 0 || (my == 0 && mz <= 0))) continue;
+                double gx = 2 * ORC_PI * mx / L[0], gy = 2 * ORC_PI * my / L[1],
+                       gz = 2 * ORC_PI * mz / L[2];
+                double k2 = gx * gx + gy * gy + gz * gz;
+                km[3 * nk] = mx; km[3 * nk + 1] = my; km[3 * nk + 2] = mz;
+                kc[nk] = 2.0 * (4.0 * ORC_PI / V) * exp(-k2 / (4 * beta * beta)) / k2;
+                ++nk;
+            }
+
+    /* Per-atom tables cos/sin(2 pi m x_a / L_a) for |m| <= kmax_a, each entry
+     * from one direct libm call, so exp(i k.r) = product of three table entries. */
+    const int wx = 2 * kx + 1, wy = 2 * ky + 1, wz = 2 * kz + 1, w = wx + wy + wz;
+    double* tc = (double*)malloc(sizeof(double) * (size_t)n * w);
+    double* ts = (double*)malloc(sizeof(double) * (size_t)n * w);
+    double* Sre = (double*)calloc((size_t)(nk ? nk : 1), sizeof(double));
+    double* Sim = (double*)calloc((size_t)(nk ? nk : 1), sizeof(double));
+    if (!tc || !ts || !Sre || !Sim) {
+        free(km); free(kc); free(tc); free(ts); free(Sre); free(Sim); return -1;
+    }
+#pragma omp parallel for schedule(static)
+    for (int64_t j = 0; j < n; ++j) {
+        double* c = tc + (size_t)j * w;
+        double* s = ts + (size_t)j * w;
+        for (int m = -kx; m <= kx; ++m) {
+            double a = 2 * ORC_PI * m * x[3 * j] / L[0];
+            c[m + kx] = cos(a); s[m + kx] = sin(a);
+        }
+        for (int m = -ky; m <= ky; ++m) {
+            double a = 2 * ORC_PI * m * x[3 * j + 1] / L[1];
+            c[wx + m + ky] = cos(a); s[wx + m + ky] = sin(a);
+        }
+        for (int m = -kz; m <= kz; ++m) {
+            double a = 2 * ORC_PI * m * x[3 * j + 2] / L[2];
+            c[wx + wy + m + kz] = cos(a); s[wx + wy + m + kz] = sin(a);
+        }
+    }
+#define ORC_EIKR(j, k, RE, IM) do {                                              \
+        const double* c_ = tc + (size_t)(j) * w; const double* s_ = ts + (size_t)(j) * w; \
+        int ix_ = km[3 * (k)] + kx, iy_ = wx + km[3 * (k) + 1] + ky,              \
+            iz_ = wx + wy + km[3 * (k) + 2] + kz;                                 \
+        double ar_ = c_[ix_] * c_[iy_] - s_[ix_] * s_[iy_];                        \
+        double ai_ = c_[ix_] * s_[iy_] + s_[ix_] * c_[iy_];                        \
+        RE = ar_ * c_[iz_] - ai_ * s_[iz_];                                       \
+        IM = ar_ * s_[iz_] + ai_ * c_[iz_];                                       \
+    } while (0)
+
+    /* Structure factor S(k) = sum_j q_j exp(i k.r_j). */
+#pragma omp parallel for schedule(static)
+    for (int64_t k = 0; k < nk; ++k) {
+        acc_t re = {0, 0}, im = {0, 0};
+        for (int64_t j = 0; j < n; ++j) {
+            double er, ei;
+            ORC_EIKR(j, k, er, ei);
+            acc_add(&re, q[j] * er);
+            acc_add(&im, q[j] * ei);
+        }
+        Sre[k] = acc_get(&re);
+        Sim[k] = acc_get(&im);
+    }
+
+#pragma omp parallel for schedule(dynamic, 8)
+    for (int64_t t = 0; t < ntarget; ++t) {
+        int64_t i = targets ? targets[t] : t;
+        acc_t p = {0, 0}, fx = {0, 0}, fy = {0, 0}, fz = {0, 0};
+        /* real space: every image n with |r_i - r_j + n L| < rcut */
+        for (int64_t j = 0; j < n; ++j) {
+            double d0[3];
+            int lo[3], hi[3];
+            for (int a = 0; a < 3; ++a) {
+                d0[a] = x[3 * i + a] - x[3 * j + a];
+                lo[a] = (int)ceil((-rcut - d0[a]) / L[a]);
+                hi[a] = (int)floor((rcut - d0[a]) / L[a]);
+            }
+            for (int a = lo[0]; a <= hi[0]; ++a)
+                for (int b = lo[1]; b <= hi[1]; ++b)
+                    for (int c = lo[2]; c <= hi[2]; ++c) {
+                        if (j == i && a == 0 && b == 0 && c == 0) continue;
+                        double dx = d0[0] + a * L[0], dy = d0[1] + b * L[1], dz = d0[2] + c * L[2];
+                        double r2 = dx * dx + dy * dy + dz * dz;
+                        if (r2 >= rc2) continue;
+                        double r = sqrt(r2);
+                        double e = erfc(beta * r) / r;
+                        double g = (e + two_b_sqrtpi * exp(-beta * beta * r2)) / r2;
+                        acc_add(&p, q[j] * e);
+                        acc_add(&fx, q[j] * g * dx);
+                        acc_add(&fy, q[j] * g * dy);
+                        acc_add(&fz, q[j] * g * dz);
+                    }
+        }
+        /* reciprocal space: phi += sum_k c Re[S e^{-ik.r}], field -= sum_k c k Im[S e^{-ik.r}] */
+        for (int64_t k = 0; k < nk; ++k) {
+            double er, ei;
+            ORC_EIKR(i, k, er, ei);
+            double re = Sre[k] * er + Sim[k] * ei;   /* Re[S e^{-ik.r}] */
+            double im = Sim[k] * er - Sre[k] * ei;   /* Im[S e^{-ik.r}] */
+            double c = kc[k];
+            acc_add(&p, c * re);
+            acc_add(&fx, -c * (2 * ORC_PI * km[3 * k] / L[0]) * im);
+            acc_add(&fy, -c * (2 * ORC_PI * km[3 * k + 1] / L[1]) * im);
+            acc_add(&fz, -c * (2 * ORC_PI * km[3 * k + 2] / L[2]) * im);
+        }
+        /* self and background */
+        acc_add(&p, -two_b_sqrtpi * q[i]);
+        acc_add(&p, -ORC_PI * Q / (V * beta * beta));
+        phi[t] = acc_get(&p);
+        field[3 * t] = acc_get(&fx);
+        field[3 * t + 1] = acc_get(&fy);
+        field[3 * t + 2] = acc_get(&fz);
+    }
+#undef ORC_EIKR
+    free(km); free(kc); free(tc); free(ts); free(Sre); free(Sim);
+    return 0;
+}
+
+/* Assemble the method's outputs from per-atom potentials and fields (all n atoms):
+ *   E = 1/2 k_e sum q_i phi_i ;  F_i = k_e q_i field_i ;
+ *   dVdl_s = k_e sum_{i in s} (qB_i - qA_i) phi_i   (dV/dlambda_s, eq 1 with
+ *   charge interpolation; atoms with site -1 contribute nothing).
+ * Returns 0, or -1 on a site index outside [-1, nsites). */
+int orc_outputs(int64_t n, const double* q, const double* qA, const double* qB,
+                const int32_t* site, int64_t nsites, const double* phi,
+                const double* field, double k_e, double* E, double* F, double* dVdl) {
+    acc_t e = {0, 0};
+    acc_t* d = (acc_t*)calloc((size_t)(nsites > 0 ? nsites : 1), sizeof(acc_t));
+    if (!d) return -1;
+    for (int64_t i = 0; i < n; ++i) {
+        acc_add(&e, q[i] * phi[i]);
+        if (F) {
+            F[3 * i] = k_e * q[i] * field[3 * i];
+            F[3 * i + 1] = k_e * q[i] * field[3 * i + 1];
+            F[3 * i + 2] = k_e * q[i] * field[3 * i + 2];
+        }
+        int32_t s = site ? site[i] : -1;
+        if (s < -1 || s >= nsites) { free(d); return -1; }
+        if (s >= 0) acc_add(&d[s], (qB[i] - qA[i]) * phi[i]);
+    }
+    *E = 0.5 * k_e * acc_get(&e);
+    if (dVdl)
+        for (int64_t s = 0; s < nsites; ++s) dVdl[s] = k_e * acc_get(&d[s]);
+    free(d);
+    return 0;
+}
