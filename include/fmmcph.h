@@ -1,0 +1,192 @@
+/*
+ * fmmcph.h -- C ABI of the lambda-interpolated fast-multipole Coulomb solver
+ * for gfx950 (AMD Instinct MI355X).
+ *
+ * What it computes (Kohnke et al., constant-pH lambda-dynamics with FMM
+ * electrostatics).  Methods, eq 1: the lambda-dependent Hamiltonian
+ * interpolates between the forms A and B of each titratable site, and the
+ * forms differ only in their partial charges (Methods, end of the
+ * lambda-dynamics subsection, and "Calibration of Protonation Dynamics", where
+ * the lambda-derivative of the Hamiltonian reduces to the Coulomb term).  The
+ * electrostatics are solved with the fast multipole method ("Constant pH
+ * Simulations with FMM Electrostatics"), whose parameters are the multipole
+ * order p and the tree depth d (section "Practical Aspects", the minimal .mdp
+ * example).  For N atoms, S sites, per-atom site index s(i) (-1 = no site) and
+ * per-site lambda_s this library evaluates, with charge interpolation
+ *
+ *   q_i       = qA_i + lambda_{s(i)} (qB_i - qA_i)        (q_i = qA_i if s(i) = -1)
+ *   phi_i     = k_e sum_j' q_j psi(r_i - r_j)               potential at atom i
+ *   E         = 1/2 sum_i q_i phi_i                         total Coulomb energy
+ *   F_i       = -dE/dr_i                                    force on atom i
+ *   dVdl_s    = sum_{i in s} (qB_i - qA_i) phi_i            = dE/dlambda_s
+ *
+ * psi = 1/r for open boundaries.  For periodic boundaries psi is the periodic
+ * Coulomb potential with conducting (tin-foil) surroundings, a uniform
+ * neutralising background for a net charge and zero mean over the cell (the
+ * Ewald convention); self images are included and the i = j term removed.
+ * phi is returned including k_e.  lambda is never clamped (the paper's
+ * calibration grid runs from -0.1 to 1.1).
+ *
+ * Precision.  FMM_FP64: every array below is double and all arithmetic is
+ * FP64.  FMM_MIXED_F32 / FMM_MIXED_BF16X3: x, qA, qB, F and phi are float; the
+ * near field, the expansions below the root and the M2L translations run in
+ * FP32 (BF16X3: M2L on bf16 matrix cores with a three-product split and FP32
+ * accumulation), while the root expansions, the periodic lattice operator, the
+ * energy and the dV/dlambda reductions stay in FP64.  E, lambda and dVdl are
+ * always double.
+ *
+ * Memory and streams.  Every array argument is a DEVICE pointer owned by the
+ * caller unless stated otherwise; arrays are in the caller's atom order and
+ * row-major (x, F: N x 3).  The plan owns its workspace, sized at creation
+ * from the fmm_params maxima; fmm_eval* allocate nothing.  Work is enqueued on
+ * the plan's HIP stream and the call returns before it completes; results are
+ * valid once that stream has been synchronised.  A plan is not thread-safe.
+ *
+ * Errors.  No exception crosses this boundary.  Arguments are validated on the
+ * host before anything is enqueued; on error the call returns a non-zero
+ * status, enqueues nothing and leaves the outputs untouched, and
+ * fmm_last_error() describes the problem.  With params.check = 1 the kernels
+ * also flag non-finite inputs and site indices outside [-1, S); such flags are
+ * reported by fmm_sync_check().  Without check the result for such inputs is
+ * undefined.
+ */
+#ifndef FMMCPH_H
+#define FMMCPH_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct fmm_plan_s* fmm_plan_t;
+
+typedef enum {
+    FMM_OK = 0,
+    FMM_E_INVALID = 1,      /* bad argument (null pointer, size, box, parameter) */
+    FMM_E_OOM = 2,          /* device allocation failed at plan creation */
+    FMM_E_HIP = 3,          /* a HIP runtime call failed */
+    FMM_E_UNSUPPORTED = 4,  /* valid but unsupported (non-cubic periodic box, ...) */
+    FMM_E_NONFINITE = 5,    /* check mode: non-finite input seen by a kernel */
+    FMM_E_SITE = 6          /* check mode: site index outside [-1, S) */
+} fmm_status;
+
+typedef enum { FMM_OPEN = 0, FMM_PERIODIC = 1 } fmm_boundary;
+
+typedef enum { FMM_FP64 = 0, FMM_MIXED_F32 = 1, FMM_MIXED_BF16X3 = 2 } fmm_precision;
+
+/* Plan parameters.
+ *   depth       tree depth d: 8^d leaf boxes (0 <= d <= 6)
+ *   order_p     maximum multipole degree p: (p+1)^2 coefficients (1 <= p <= 15)
+ *   boundary    fmm_boundary
+ *   precision   fmm_precision
+ *   coulomb_k   k_e; 1.0 for reduced units, 138.935458 for kJ mol^-1 nm e^-2
+ *   max_atoms   largest N (per call, summed over replicas for the batched call)
+ *   max_sites   largest S (same)
+ *   max_replicas largest replica count of fmm_eval_batched (>= 1)
+ *   check       1 = run the device-side input checks described above */
+typedef struct {
+    int32_t depth;
+    int32_t order_p;
+    int32_t boundary;
+    int32_t precision;
+    double coulomb_k;
+    int64_t max_atoms;
+    int64_t max_sites;
+    int32_t max_replicas;
+    int32_t check;
+} fmm_params;
+
+/* Create a plan on the current HIP device.  hip_stream is a hipStream_t (NULL =
+ * the default stream).  Builds the FP64 translation operators for order_p (and
+ * the periodic lattice operator) on the host, uploads them, and allocates the
+ * workspace.  *out receives the plan on FMM_OK. */
+fmm_status fmm_plan_create(const fmm_params* params, void* hip_stream, fmm_plan_t* out);
+
+/* One evaluation (one system).
+ *   n        number of atoms (0 <= n <= max_atoms)
+ *   x        n x 3 positions (nm)                       [float | double per precision]
+ *   qA, qB   n charges of forms A and B (e)             [float | double]
+ *   site     n site indices in [-1, n_sites)            [int32]
+ *   n_sites  S (0 <= S <= max_sites)
+ *   lambda   S lambda values                            [double]
+ *   box      HOST pointer to 3 doubles: the periodic cell edges (must be equal:
+ *            cubic cells only; positions are wrapped into [0, L)).  Must be
+ *            NULL for open boundaries: the octree root is then the bounding
+ *            cube of the atoms, found on the device.
+ * Outputs (any of F, phi, dVdl may be NULL to skip it):
+ *   E        1 double: total energy
+ *   F        n x 3 forces                               [float | double]
+ *   phi      n potentials (including k_e)               [float | double]
+ *   dVdl     S values dE/dlambda_s                      [double] */
+fmm_status fmm_eval(fmm_plan_t plan, int64_t n, const void* x, const void* qA,
+                    const void* qB, const int32_t* site, int64_t n_sites,
+                    const double* lambda, const double* box, double* E, void* F,
+                    void* phi, double* dVdl);
+
+/* Adjoint of E (reverse mode for an upstream weight gE on the energy).  The
+ * tree and every expansion are recomputed from the inputs (nothing is kept
+ * from a previous forward call).  With w = *gE (a DEVICE double):
+ *   grad_x      = -w F                       n x 3   [float | double]
+ *   grad_qA_i   = w (1 - lambda_s(i)) phi_i  (w phi_i if s(i) = -1)
+ *   grad_qB_i   = w lambda_s(i) phi_i        (0 if s(i) = -1)
+ *   grad_lambda = w dVdl                     S       [double]
+ * Any gradient pointer may be NULL.  E, F, phi, dVdl are as in fmm_eval and may
+ * each be NULL. */
+fmm_status fmm_eval_adjoint(fmm_plan_t plan, int64_t n, const void* x, const void* qA,
+                            const void* qB, const int32_t* site, int64_t n_sites,
+                            const double* lambda, const double* box, const double* gE,
+                            void* grad_x, void* grad_qA, void* grad_qB,
+                            double* grad_lambda, double* E, void* F, void* phi,
+                            double* dVdl);
+
+/* R independent systems (replicas) in one call.  Atoms and sites of replica r
+ * occupy [atom_off[r], atom_off[r+1]) and [site_off[r], site_off[r+1]) of the
+ * concatenated arrays; atom_off and site_off are HOST arrays of R+1 int64
+ * (atom_off[0] = site_off[0] = 0).  site_local holds site indices local to the
+ * atom's replica.  boxes is a HOST array of R x 3 doubles for periodic plans
+ * and must be NULL for open ones.  E receives R doubles; F, phi, dVdl are the
+ * concatenated per-replica outputs.  Each replica equals what fmm_eval returns
+ * for it alone. */
+fmm_status fmm_eval_batched(fmm_plan_t plan, int32_t R, const int64_t* atom_off,
+                            const int64_t* site_off, const void* x, const void* qA,
+                            const void* qB, const int32_t* site_local,
+                            const double* lambda, const double* boxes, double* E,
+                            void* F, void* phi, double* dVdl);
+
+/* Wait for the plan's stream and report device-side check flags raised since
+ * the previous call (FMM_E_NONFINITE, FMM_E_SITE), or FMM_E_HIP. */
+fmm_status fmm_sync_check(fmm_plan_t plan);
+
+/* Human-readable description of the last error on this plan (never NULL). */
+const char* fmm_last_error(fmm_plan_t plan);
+
+/* Release the plan and its device workspace (NULL is ignored). */
+void fmm_plan_destroy(fmm_plan_t plan);
+
+/* Per-phase timing with HIP events recorded on the plan's stream (a
+ * measurement aid; it changes no result).  The phases of one evaluation are
+ *   0 binning (charges, leaf keys, counting sort, gather), 1 P2M, 2 M2M,
+ *   3 root (periodic lattice operator), 4 M2L, 5 L2L,
+ *   6 near field + far-field evaluation + outputs (P2P, L2P), 7 reductions.
+ * mode 1: start recording for up to `capacity` evaluations (creates the events
+ *         now, never inside an evaluation; resets the record),
+ * mode 0: stop recording,
+ * mode 2: wait for the stream and write out[0..7] = total milliseconds per
+ *         phase and out[8..15] = number of timed instances of each phase. */
+#define FMM_NPHASES 8
+fmm_status fmm_profile(fmm_plan_t plan, int32_t mode, int32_t capacity, double* out);
+
+/* Host-only access to the FP64 operator tables a plan of order p uploads; no
+ * GPU is touched.  which: 0 = M2L bank (343 x K x K), 1 = M2M (8 x K x K),
+ * 2 = L2L (8 x K x K), 3 = periodic lattice operator (K x K), 4 = regular
+ * harmonics rho(r) at the point out[0..2] (K values, written over out).
+ * Layouts as documented in the library's operators.h; K = (p+1)^2.  Returns
+ * the number of doubles written, or -1 for a bad argument. */
+int64_t fmm_host_operator(int32_t order_p, int32_t which, double* out);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FMMCPH_H */

@@ -1,0 +1,519 @@
+// fmm_api.hip -- host side of the C ABI declared in include/fmmcph.h: plan
+// creation (operator tables, workspace), argument validation and the ordered
+// launch sequence of one evaluation on the plan's stream.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "fmm_kernels.hip"
+#include "fmmcph.h"
+#include "operators.h"
+
+using fmmk::Geo;
+
+struct fmm_plan_s {
+    fmm_params prm{};
+    hipStream_t stream = nullptr;
+    int device = 0;
+    bool fp64 = true;
+    size_t tsz = 8;  // bytes of the working real type
+    int K = 0, Kp = 0, Kg = 0, nleaf = 0;
+    int64_t nbox = 0;
+    int64_t lev_off[fmmk::kDMax + 2] = {};
+    // workspace (device)
+    void* pos = nullptr;
+    int32_t *perm = nullptr, *key = nullptr, *rank = nullptr;
+    int32_t *leaf_count = nullptr, *leaf_start = nullptr;
+    int32_t *site_count = nullptr, *site_start = nullptr, *site_rank = nullptr,
+            *site_members = nullptr;
+    void *mult = nullptr, *loc = nullptr;
+    double *root_m = nullptr, *root_l = nullptr;
+    void *bankT = nullptr, *m2mT = nullptr, *l2lT = nullptr, *gcoef = nullptr;
+    double* latT = nullptr;
+    int32_t* gidx = nullptr;
+    double *dom = nullptr, *bbox_part = nullptr, *leaf_part = nullptr, *leaf_energy = nullptr,
+           *cphi = nullptr;
+    int32_t* status = nullptr;
+    void *F_tmp = nullptr, *phi_tmp = nullptr;
+    double* dVdl_tmp = nullptr;
+    std::vector<void*> allocs;
+    std::string err;
+    // per-phase timing (fmm_profile): events recorded at phase boundaries
+    bool prof_on = false;
+    std::vector<hipEvent_t> prof_ev;
+    std::vector<int> prof_phase;  // phase that starts at the event with the same index
+    size_t prof_used = 0;
+};
+
+namespace {
+
+constexpr int kBboxBlocks = 256;
+
+fmm_status fail(fmm_plan_t p, fmm_status st, const std::string& msg) {
+    if (p) p->err = msg;
+    return st;
+}
+
+bool dev_alloc(fmm_plan_t p, void** ptr, size_t bytes) {
+    if (bytes == 0) bytes = 16;
+    if (hipMalloc(ptr, bytes) != hipSuccess) return false;
+    p->allocs.push_back(*ptr);
+    return true;
+}
+
+template <typename T>
+std::vector<T> transpose_blocks(const std::vector<double>& src, int nblk, int K) {
+    std::vector<T> out(src.size());
+    for (int b = 0; b < nblk; ++b)
+        for (int r = 0; r < K; ++r)
+            for (int k = 0; k < K; ++k)
+                out[(size_t)b * K * K + (size_t)k * K + r] = (T)src[(size_t)b * K * K + (size_t)r * K + k];
+    return out;
+}
+
+void init_rho_coef() {
+    fmmk::RhoCoef rc{};
+    const int P = fmmk::kPMax;
+    rc.f[0] = 1.0;
+    for (int m = 1; m <= P; ++m) rc.f[m] = -std::sqrt((2.0 * m - 1) / (2.0 * m));
+    for (int m = 0; m <= P; ++m) {
+        if (m + 1 <= P) rc.a[(m + 1) * (P + 1) + m] = std::sqrt(2.0 * m + 1);
+        for (int l = m + 2; l <= P; ++l) {
+            rc.a[l * (P + 1) + m] = (2.0 * l - 1) / std::sqrt(double((l + m) * (l - m)));
+            rc.b[l * (P + 1) + m] =
+                std::sqrt(double((l + m - 1) * (l - m - 1)) / double((l + m) * (l - m)));
+        }
+    }
+    (void)hipMemcpyToSymbol(HIP_SYMBOL(fmmk::c_rho), &rc, sizeof(rc));
+}
+
+Geo make_geo(const fmm_plan_s* p) {
+    Geo g{};
+    g.depth = p->prm.depth;
+    g.nb = 1 << g.depth;
+    g.p = p->prm.order_p;
+    g.K = p->K;
+    g.Kp = p->Kp;
+    g.Kg = p->Kg;
+    g.nleaf = p->nleaf;
+    g.periodic = p->prm.boundary == FMM_PERIODIC;
+    g.lmin = g.periodic ? 1 : 2;
+    g.has_far = g.periodic ? 1 : (g.depth >= 2 ? 1 : 0);
+    g.check = p->prm.check;
+    g.coulomb_k = p->prm.coulomb_k;
+    for (int l = 0; l <= fmmk::kDMax + 1; ++l) g.lev_off[l] = p->lev_off[l];
+    return g;
+}
+
+// Record a phase boundary: the event marks the start of `phase` (and the end of
+// the previous one); phase -1 closes the evaluation.
+void mark(fmm_plan_t P, int phase) {
+    if (!P->prof_on || P->prof_used >= P->prof_ev.size()) return;
+    (void)hipEventRecord(P->prof_ev[P->prof_used], P->stream);
+    P->prof_phase[P->prof_used] = phase;
+    ++P->prof_used;
+}
+
+inline unsigned nblocks(int64_t n, int b) { return (unsigned)std::max<int64_t>(1, (n + b - 1) / b); }
+
+// Enqueue one single-system evaluation (arguments already validated).
+template <typename T>
+fmm_status enqueue_eval(fmm_plan_t P, int64_t n, const T* x, const T* qA, const T* qB,
+                        const int32_t* site, int64_t S, const double* lam, double box,
+                        double* E, T* F, T* phi, double* dVdl) {
+    using namespace fmmk;
+    hipStream_t st = P->stream;
+    const Geo g = make_geo(P);
+    if (n == 0) {
+        if (E) k_fill_f64<<<1, 64, 0, st>>>(E, 1, 0.0);
+        if (dVdl && S > 0) k_fill_f64<<<nblocks(S, 256), 256, 0, st>>>(dVdl, S, 0.0);
+        return hipGetLastError() == hipSuccess ? FMM_OK : fail(P, FMM_E_HIP, "launch failed");
+    }
+    mark(P, 0);
+    k_fill_i32<<<nblocks(g.nleaf, 256), 256, 0, st>>>(P->leaf_count, g.nleaf, 0);
+    if (S > 0) k_fill_i32<<<nblocks(S, 256), 256, 0, st>>>(P->site_count, S, 0);
+    if (!g.periodic) {
+        const int nb = (int)std::min<int64_t>(kBboxBlocks, nblocks(n, 256));
+        k_bbox<T><<<nb, 256, 0, st>>>(x, n, P->bbox_part);
+        k_bbox_final<<<1, 64, 0, st>>>(P->bbox_part, nb, P->dom);
+    }
+    k_charge_key<T><<<nblocks(n, 256), 256, 0, st>>>(g, n, x, qA, qB, site, S, lam, box, P->dom,
+                                                     P->key, P->rank, P->leaf_count,
+                                                     P->site_count, P->site_rank, P->status);
+    k_scan2<<<2, 1024, 0, st>>>(P->leaf_count, P->leaf_start, g.nleaf, P->site_count,
+                                P->site_start, S);
+    k_scatter<<<nblocks(n, 256), 256, 0, st>>>(n, P->key, P->rank, P->leaf_start, P->perm, site,
+                                               S, P->site_rank, P->site_start, P->site_members);
+    using V4 = vec4_t<T>;
+    V4* pos = (V4*)P->pos;
+    T* mult = (T*)P->mult;
+    T* loc = (T*)P->loc;
+    k_leaf_sort_gather<T><<<g.nleaf, 256, 0, st>>>(g, x, qA, qB, site, S, lam, P->dom,
+                                                   P->leaf_start, P->perm, pos, P->status);
+    mark(P, 1);
+    k_p2m<T><<<g.nleaf, 64, 0, st>>>(g, pos, P->leaf_start, P->dom, mult, P->leaf_part);
+    // upward pass: parents at level lev from children at lev + 1
+    mark(P, 2);
+    for (int lev = g.depth - 1; lev >= 0; --lev) {
+        const unsigned np = 1u << (3 * lev);
+        if (lev == 0)
+            k_m2m<T, double><<<1, 256, 0, st>>>(g, 0, mult, (const T*)P->m2mT, P->root_m, g.K);
+        else
+            k_m2m<T, T><<<np, 256, 0, st>>>(g, lev, mult, (const T*)P->m2mT,
+                                            mult + (size_t)g.lev_off[lev] * g.Kp, g.Kp);
+    }
+    mark(P, 3);
+    if (g.periodic)
+        k_root<T><<<1, 256, 0, st>>>(g, P->leaf_part, P->root_m, mult, P->latT, P->root_l, loc,
+                                     P->dom);
+    mark(P, 4);
+    if (g.depth >= g.lmin) {
+        int64_t nt = 0;
+        for (int l = g.lmin; l <= g.depth; ++l) nt += (int64_t)1 << (3 * l);
+        k_m2l_plain<T><<<(unsigned)nt, 256, 0, st>>>(g, mult, (const T*)P->bankT, loc);
+    }
+    // downward pass: children at lev + 1 from parents at lev
+    mark(P, 5);
+    const int l0 = g.periodic ? 0 : g.lmin;
+    for (int lev = l0; lev < g.depth; ++lev) {
+        const unsigned nc = 1u << (3 * (lev + 1));
+        if (lev == 0)
+            k_l2l<double, T><<<nc, 256, 0, st>>>(g, 0, P->root_l, g.K, (const T*)P->l2lT, loc);
+        else
+            k_l2l<T, T><<<nc, 256, 0, st>>>(g, lev, loc + (size_t)g.lev_off[lev] * g.Kp, g.Kp,
+                                            (const T*)P->l2lT, loc);
+    }
+    mark(P, 6);
+    k_near_far<T><<<g.nleaf, 256, 0, st>>>(g, pos, P->leaf_start, P->perm, P->dom, loc, P->gidx,
+                                           (const T*)P->gcoef, qA, qB, site, S, phi, F,
+                                           P->leaf_energy, P->cphi);
+    mark(P, 7);
+    k_reduce<<<(unsigned)(S + 1), 256, 0, st>>>(g, P->leaf_energy, P->site_start,
+                                                P->site_members, P->cphi, E, dVdl, P->status);
+    mark(P, -1);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return fail(P, FMM_E_HIP, std::string("kernel launch: ") + hipGetErrorString(e));
+    return FMM_OK;
+}
+
+fmm_status check_box(fmm_plan_t P, const double* box, double* L) {
+    if (P->prm.boundary == FMM_PERIODIC) {
+        if (!box) return fail(P, FMM_E_INVALID, "periodic plan needs a box");
+        if (!(box[0] > 0) || !std::isfinite(box[0]))
+            return fail(P, FMM_E_INVALID, "box edges must be positive and finite");
+        if (box[1] != box[0] || box[2] != box[0])
+            return fail(P, FMM_E_UNSUPPORTED, "only cubic periodic cells are supported");
+        *L = box[0];
+    } else {
+        if (box) return fail(P, FMM_E_INVALID, "open plan: box must be NULL");
+        *L = 0.0;
+    }
+    return FMM_OK;
+}
+
+fmm_status check_common(fmm_plan_t P, int64_t n, const void* x, const void* qA, const void* qB,
+                        const int32_t* site, int64_t S, const double* lam) {
+    if (!P) return FMM_E_INVALID;
+    if (n < 0 || n > P->prm.max_atoms) return fail(P, FMM_E_INVALID, "n outside [0, max_atoms]");
+    if (n > INT32_MAX) return fail(P, FMM_E_UNSUPPORTED, "n above 2^31 - 1");
+    if (S < 0 || S > P->prm.max_sites) return fail(P, FMM_E_INVALID, "n_sites outside [0, max_sites]");
+    if (n > 0 && (!x || !qA || !qB || !site))
+        return fail(P, FMM_E_INVALID, "null input pointer");
+    if (S > 0 && !lam) return fail(P, FMM_E_INVALID, "null lambda pointer");
+    return FMM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+fmm_status fmm_plan_create(const fmm_params* prm, void* hip_stream, fmm_plan_t* out) {
+    if (!prm || !out) return FMM_E_INVALID;
+    *out = nullptr;
+    if (prm->depth < 0 || prm->depth > fmmk::kDMax || prm->order_p < 1 ||
+        prm->order_p > fmmk::kPMax || prm->max_atoms < 0 || prm->max_sites < 0 ||
+        prm->max_replicas < 1 || (prm->boundary != FMM_OPEN && prm->boundary != FMM_PERIODIC) ||
+        (prm->precision != FMM_FP64 && prm->precision != FMM_MIXED_F32 &&
+         prm->precision != FMM_MIXED_BF16X3) ||
+        !std::isfinite(prm->coulomb_k) || prm->max_atoms > INT32_MAX)
+        return FMM_E_INVALID;
+    fmm_plan_s* P = new fmm_plan_s();
+    P->prm = *prm;
+    P->stream = (hipStream_t)hip_stream;
+    if (hipGetDevice(&P->device) != hipSuccess) {
+        delete P;
+        return FMM_E_HIP;
+    }
+    P->fp64 = prm->precision == FMM_FP64;
+    P->tsz = P->fp64 ? 8 : 4;
+    const int p = prm->order_p, d = prm->depth;
+    P->K = (p + 1) * (p + 1);
+    P->Kp = (P->K + 3) & ~3;
+    P->Kg = p * p;
+    P->nleaf = 1 << (3 * d);
+    int64_t off = 0;
+    for (int l = 0; l <= fmmk::kDMax + 1; ++l) {
+        P->lev_off[l] = off;
+        if (l <= d) off += (int64_t)1 << (3 * l);
+    }
+    P->nbox = off;
+    init_rho_coef();
+    const int64_t N = std::max<int64_t>(prm->max_atoms, 1), S = std::max<int64_t>(prm->max_sites, 1);
+    const size_t ts = P->tsz, K = P->K;
+    bool ok = true;
+    ok &= dev_alloc(P, &P->pos, N * 4 * ts);
+    ok &= dev_alloc(P, (void**)&P->perm, N * 4);
+    ok &= dev_alloc(P, (void**)&P->key, N * 4);
+    ok &= dev_alloc(P, (void**)&P->rank, N * 4);
+    ok &= dev_alloc(P, (void**)&P->leaf_count, (size_t)P->nleaf * 4);
+    ok &= dev_alloc(P, (void**)&P->leaf_start, ((size_t)P->nleaf + 1) * 4);
+    ok &= dev_alloc(P, (void**)&P->site_count, S * 4);
+    ok &= dev_alloc(P, (void**)&P->site_start, (S + 1) * 4);
+    ok &= dev_alloc(P, (void**)&P->site_rank, N * 4);
+    ok &= dev_alloc(P, (void**)&P->site_members, N * 4);
+    ok &= dev_alloc(P, &P->mult, (size_t)P->nbox * P->Kp * ts);
+    ok &= dev_alloc(P, &P->loc, (size_t)P->nbox * P->Kp * ts);
+    ok &= dev_alloc(P, (void**)&P->root_m, K * 8);
+    ok &= dev_alloc(P, (void**)&P->root_l, K * 8);
+    ok &= dev_alloc(P, &P->bankT, 343 * K * K * ts);
+    ok &= dev_alloc(P, &P->m2mT, 8 * K * K * ts);
+    ok &= dev_alloc(P, &P->l2lT, 8 * K * K * ts);
+    ok &= dev_alloc(P, (void**)&P->latT, K * K * 8);
+    ok &= dev_alloc(P, (void**)&P->gidx, 3 * (size_t)P->Kg * 4 * 4);
+    ok &= dev_alloc(P, &P->gcoef, 3 * (size_t)P->Kg * 4 * ts);
+    ok &= dev_alloc(P, (void**)&P->dom, 8 * 8);
+    ok &= dev_alloc(P, (void**)&P->bbox_part, kBboxBlocks * 6 * 8);
+    ok &= dev_alloc(P, (void**)&P->leaf_part, (size_t)P->nleaf * 2 * 8);
+    ok &= dev_alloc(P, (void**)&P->leaf_energy, (size_t)P->nleaf * 8);
+    ok &= dev_alloc(P, (void**)&P->cphi, N * 8);
+    ok &= dev_alloc(P, (void**)&P->status, 4 * 4);
+    ok &= dev_alloc(P, &P->F_tmp, N * 3 * ts);
+    ok &= dev_alloc(P, &P->phi_tmp, N * ts);
+    ok &= dev_alloc(P, (void**)&P->dVdl_tmp, S * 8);
+    if (!ok) {
+        fmm_plan_destroy(P);
+        return FMM_E_OOM;
+    }
+    // operator tables (FP64 on the host, converted to the working type)
+    std::vector<double> bank(343 * K * K), m2m(8 * K * K), l2l(8 * K * K), lat(K * K);
+    fmmops::build_m2l_bank(p, bank.data());
+    fmmops::build_m2m(p, m2m.data());
+    fmmops::build_l2l(p, l2l.data());
+    std::vector<int32_t> gi(3 * (size_t)P->Kg * 4);
+    std::vector<double> gc(3 * (size_t)P->Kg * 4);
+    fmmops::build_grad_table(p, gi.data(), gc.data());
+    if (prm->boundary == FMM_PERIODIC) fmmops::build_lattice(p, lat.data());
+    hipError_t e = hipSuccess;
+    auto up = [&](void* dst, const void* src, size_t bytes) {
+        if (e == hipSuccess) e = hipMemcpy(dst, src, bytes, hipMemcpyHostToDevice);
+    };
+    if (P->fp64) {
+        auto b = transpose_blocks<double>(bank, 343, K);
+        auto a = transpose_blocks<double>(m2m, 8, K);
+        auto c = transpose_blocks<double>(l2l, 8, K);
+        up(P->bankT, b.data(), b.size() * 8);
+        up(P->m2mT, a.data(), a.size() * 8);
+        up(P->l2lT, c.data(), c.size() * 8);
+        up(P->gcoef, gc.data(), gc.size() * 8);
+    } else {
+        auto b = transpose_blocks<float>(bank, 343, K);
+        auto a = transpose_blocks<float>(m2m, 8, K);
+        auto c = transpose_blocks<float>(l2l, 8, K);
+        std::vector<float> gf(gc.begin(), gc.end());
+        up(P->bankT, b.data(), b.size() * 4);
+        up(P->m2mT, a.data(), a.size() * 4);
+        up(P->l2lT, c.data(), c.size() * 4);
+        up(P->gcoef, gf.data(), gf.size() * 4);
+    }
+    auto lt = transpose_blocks<double>(lat, 1, K);
+    up(P->latT, lt.data(), lt.size() * 8);
+    up(P->gidx, gi.data(), gi.size() * 4);
+    std::vector<double> dom0(8, 0.0);
+    up(P->dom, dom0.data(), 64);
+    int32_t z[4] = {0, 0, 0, 0};
+    up(P->status, z, sizeof(z));
+    if (e != hipSuccess) {
+        fmm_plan_destroy(P);
+        return FMM_E_HIP;
+    }
+    *out = P;
+    return FMM_OK;
+}
+
+void fmm_plan_destroy(fmm_plan_t P) {
+    if (!P) return;
+    for (hipEvent_t ev : P->prof_ev) (void)hipEventDestroy(ev);
+    for (void* a : P->allocs) (void)hipFree(a);
+    delete P;
+}
+
+const char* fmm_last_error(fmm_plan_t P) {
+    if (!P) return "null plan";
+    return P->err.c_str();
+}
+
+fmm_status fmm_eval(fmm_plan_t P, int64_t n, const void* x, const void* qA, const void* qB,
+                    const int32_t* site, int64_t S, const double* lam, const double* box,
+                    double* E, void* F, void* phi, double* dVdl) {
+    fmm_status s = check_common(P, n, x, qA, qB, site, S, lam);
+    if (s != FMM_OK) return s;
+    double L = 0;
+    if ((s = check_box(P, box, &L)) != FMM_OK) return s;
+    P->err.clear();
+    if (P->fp64)
+        return enqueue_eval<double>(P, n, (const double*)x, (const double*)qA, (const double*)qB,
+                                    site, S, lam, L, E, (double*)F, (double*)phi, dVdl);
+    return enqueue_eval<float>(P, n, (const float*)x, (const float*)qA, (const float*)qB, site, S,
+                               lam, L, E, (float*)F, (float*)phi, dVdl);
+}
+
+fmm_status fmm_eval_adjoint(fmm_plan_t P, int64_t n, const void* x, const void* qA,
+                            const void* qB, const int32_t* site, int64_t S, const double* lam,
+                            const double* box, const double* gE, void* grad_x, void* grad_qA,
+                            void* grad_qB, double* grad_lambda, double* E, void* F, void* phi,
+                            double* dVdl) {
+    fmm_status s = check_common(P, n, x, qA, qB, site, S, lam);
+    if (s != FMM_OK) return s;
+    if (!gE) return fail(P, FMM_E_INVALID, "null upstream weight");
+    double L = 0;
+    if ((s = check_box(P, box, &L)) != FMM_OK) return s;
+    P->err.clear();
+    void* Fw = F ? F : P->F_tmp;
+    void* pw = phi ? phi : P->phi_tmp;
+    double* dw = dVdl ? dVdl : P->dVdl_tmp;
+    const unsigned nb = nblocks(std::max(n, S), 256);
+    if (P->fp64) {
+        s = enqueue_eval<double>(P, n, (const double*)x, (const double*)qA, (const double*)qB, site,
+                                 S, lam, L, E, (double*)Fw, (double*)pw, dw);
+        if (s != FMM_OK) return s;
+        if (n > 0 || S > 0)
+            fmmk::k_adjoint<double><<<nb, 256, 0, P->stream>>>(
+                n, site, S, lam, gE, (const double*)Fw, (const double*)pw, dw, (double*)grad_x,
+                (double*)grad_qA, (double*)grad_qB, grad_lambda);
+    } else {
+        s = enqueue_eval<float>(P, n, (const float*)x, (const float*)qA, (const float*)qB, site, S,
+                                lam, L, E, (float*)Fw, (float*)pw, dw);
+        if (s != FMM_OK) return s;
+        if (n > 0 || S > 0)
+            fmmk::k_adjoint<float><<<nb, 256, 0, P->stream>>>(
+                n, site, S, lam, gE, (const float*)Fw, (const float*)pw, dw, (float*)grad_x,
+                (float*)grad_qA, (float*)grad_qB, grad_lambda);
+    }
+    return hipGetLastError() == hipSuccess ? FMM_OK : fail(P, FMM_E_HIP, "adjoint launch failed");
+}
+
+fmm_status fmm_eval_batched(fmm_plan_t P, int32_t R, const int64_t* atom_off,
+                            const int64_t* site_off, const void* x, const void* qA,
+                            const void* qB, const int32_t* site_local, const double* lam,
+                            const double* boxes, double* E, void* F, void* phi, double* dVdl) {
+    if (!P) return FMM_E_INVALID;
+    if (R < 1 || R > P->prm.max_replicas || !atom_off || !site_off || !E)
+        return fail(P, FMM_E_INVALID, "bad replica count or offsets");
+    if (atom_off[0] != 0 || site_off[0] != 0)
+        return fail(P, FMM_E_INVALID, "offsets must start at 0");
+    for (int r = 0; r < R; ++r) {
+        const int64_t n = atom_off[r + 1] - atom_off[r], S = site_off[r + 1] - site_off[r];
+        if (n < 0 || S < 0) return fail(P, FMM_E_INVALID, "offsets must be non-decreasing");
+        fmm_status s = check_common(P, n, x, qA, qB, site_local, S, lam);
+        if (s != FMM_OK) return s;
+        double L = 0;
+        if ((s = check_box(P, boxes ? boxes + 3 * r : nullptr, &L)) != FMM_OK) return s;
+    }
+    if (atom_off[R] > P->prm.max_atoms || site_off[R] > P->prm.max_sites)
+        return fail(P, FMM_E_INVALID, "total atoms or sites above the plan maxima");
+    P->err.clear();
+    for (int r = 0; r < R; ++r) {
+        const int64_t a0 = atom_off[r], n = atom_off[r + 1] - a0;
+        const int64_t s0 = site_off[r], S = site_off[r + 1] - s0;
+        double L = boxes ? boxes[3 * r] : 0.0;
+        fmm_status s;
+        if (P->fp64)
+            s = enqueue_eval<double>(P, n, (const double*)x + 3 * a0, (const double*)qA + a0,
+                                     (const double*)qB + a0, site_local + a0, S, lam + s0, L, E + r,
+                                     F ? (double*)F + 3 * a0 : nullptr,
+                                     phi ? (double*)phi + a0 : nullptr,
+                                     dVdl ? dVdl + s0 : nullptr);
+        else
+            s = enqueue_eval<float>(P, n, (const float*)x + 3 * a0, (const float*)qA + a0,
+                                    (const float*)qB + a0, site_local + a0, S, lam + s0, L, E + r,
+                                    F ? (float*)F + 3 * a0 : nullptr,
+                                    phi ? (float*)phi + a0 : nullptr, dVdl ? dVdl + s0 : nullptr);
+        if (s != FMM_OK) return s;
+    }
+    return FMM_OK;
+}
+
+fmm_status fmm_sync_check(fmm_plan_t P) {
+    if (!P) return FMM_E_INVALID;
+    if (hipStreamSynchronize(P->stream) != hipSuccess) return fail(P, FMM_E_HIP, "stream sync failed");
+    int32_t st[4];
+    if (hipMemcpy(st, P->status, sizeof(st), hipMemcpyDeviceToHost) != hipSuccess)
+        return fail(P, FMM_E_HIP, "status read failed");
+    int32_t z[4] = {0, 0, 0, 0};
+    if (hipMemcpy(P->status, z, sizeof(z), hipMemcpyHostToDevice) != hipSuccess)
+        return fail(P, FMM_E_HIP, "status reset failed");
+    if (st[0] & fmmk::kStatusSite) return fail(P, FMM_E_SITE, "site index outside [-1, n_sites)");
+    if (st[0] & fmmk::kStatusNonFinite) return fail(P, FMM_E_NONFINITE, "non-finite input");
+    return FMM_OK;
+}
+
+fmm_status fmm_profile(fmm_plan_t P, int32_t mode, int32_t capacity, double* out) {
+    if (!P) return FMM_E_INVALID;
+    if (mode == 1) {
+        if (capacity < 1) return fail(P, FMM_E_INVALID, "profile capacity must be >= 1");
+        const size_t want = (size_t)capacity * (FMM_NPHASES + 1);
+        while (P->prof_ev.size() < want) {
+            hipEvent_t ev;
+            if (hipEventCreate(&ev) != hipSuccess) return fail(P, FMM_E_HIP, "hipEventCreate failed");
+            P->prof_ev.push_back(ev);
+        }
+        P->prof_phase.assign(P->prof_ev.size(), -1);
+        P->prof_used = 0;
+        P->prof_on = true;
+        return FMM_OK;
+    }
+    if (mode == 0) {
+        P->prof_on = false;
+        return FMM_OK;
+    }
+    if (mode == 2) {
+        if (!out) return fail(P, FMM_E_INVALID, "null output");
+        if (hipStreamSynchronize(P->stream) != hipSuccess) return fail(P, FMM_E_HIP, "sync failed");
+        for (int i = 0; i < 2 * FMM_NPHASES; ++i) out[i] = 0.0;
+        for (size_t i = 0; i + 1 < P->prof_used; ++i) {
+            const int ph = P->prof_phase[i];
+            if (ph < 0) continue;
+            float ms = 0.f;
+            if (hipEventElapsedTime(&ms, P->prof_ev[i], P->prof_ev[i + 1]) != hipSuccess)
+                return fail(P, FMM_E_HIP, "hipEventElapsedTime failed");
+            out[ph] += ms;
+            out[FMM_NPHASES + ph] += 1.0;
+        }
+        return FMM_OK;
+    }
+    return fail(P, FMM_E_INVALID, "profile mode must be 0, 1 or 2");
+}
+
+int64_t fmm_host_operator(int32_t p, int32_t which, double* out) {
+    if (p < 1 || p > fmmk::kPMax || !out) return -1;
+    const int64_t K = (int64_t)(p + 1) * (p + 1);
+    switch (which) {
+        case 0: fmmops::build_m2l_bank(p, out); return 343 * K * K;
+        case 1: fmmops::build_m2m(p, out); return 8 * K * K;
+        case 2: fmmops::build_l2l(p, out); return 8 * K * K;
+        case 3: fmmops::build_lattice(p, out); return K * K;
+        case 4: {
+            double r[3] = {out[0], out[1], out[2]};
+            fmmops::eval_rho(p, r, out);
+            return K;
+        }
+        default: return -1;
+    }
+}
+
+}  // extern "C"

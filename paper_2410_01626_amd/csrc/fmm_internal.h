@@ -1,0 +1,40 @@
+// fmm_internal.h -- constants and the per-evaluation geometry record shared by
+// the kernels and the host side of the library.
+#pragma once
+#include <cstdint>
+
+namespace fmmk {
+
+constexpr int kDMax = 6;                    // deepest tree: 8^6 leaves
+constexpr int kPMax = 15;                   // highest multipole degree
+constexpr int kKMax = (kPMax + 1) * (kPMax + 1);  // 256 coefficients
+constexpr int kKgMax = kPMax * kPMax;       // gradient coefficients (order p-1)
+constexpr int kSortCap = 4096;              // largest leaf sorted in LDS
+constexpr int kSiteCap = 1024;              // largest site sorted in LDS
+constexpr double kPi = 3.14159265358979323846;
+
+// status[0]: errors raised in check mode; status[1]: informational bits
+constexpr int32_t kStatusNonFinite = 1;
+constexpr int32_t kStatusSite = 2;
+constexpr int32_t kInfoBigLeaf = 1;  // a leaf above kSortCap kept its atomic order
+constexpr int32_t kInfoBigSite = 2;  // a site above kSiteCap summed in atomic order
+
+// Geometry and sizes of one evaluation, passed by value to every kernel.
+struct Geo {
+    int32_t depth;     // tree depth d
+    int32_t nb;        // 2^d leaf cells per axis
+    int32_t p;         // multipole order
+    int32_t K;         // (p+1)^2
+    int32_t Kp;        // K padded: stride of one box in the expansion arrays
+    int32_t Kg;        // p^2
+    int32_t nleaf;     // 8^d
+    int32_t lmin;      // first level with an interaction list (1 periodic, 2 open)
+    int32_t periodic;  // 1 = periodic cubic cell
+    int32_t has_far;   // leaves carry a local expansion
+    int32_t check;     // device-side input checks
+    int32_t pad_;
+    double coulomb_k;  // k_e
+    int64_t lev_off[kDMax + 2];  // first box of level l in the expansion arrays
+};
+
+}  // namespace fmmk

@@ -1,0 +1,783 @@
+// fmm_kernels.hip -- gfx950 kernels of the lambda-interpolated FMM Coulomb
+// solve.  One evaluation runs, in stream order:
+//   bbox (open only) -> charge_key -> scan -> scatter -> leaf_sort_gather ->
+//   p2m -> m2m (per level) -> root (periodic lattice, FP64) -> m2l (all levels)
+//   -> l2l (per level) -> near_far (P2P + L2P + output) -> reduce
+// Box indices are Morton codes at every level; level l occupies
+// [lev_off[l], lev_off[l] + 8^l) of the expansion arrays.  Particles are kept
+// sorted by leaf with coordinates relative to their leaf centre, so periodic
+// images reduce to integer leaf offsets times the leaf edge.
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "fmm_internal.h"
+
+namespace fmmk {
+
+
+// ------------------------------------------------------------------ helpers
+
+__device__ __forceinline__ uint32_t spread3(uint32_t v) {
+    v &= 0x3ff;
+    v = (v | (v << 16)) & 0x030000FF;
+    v = (v | (v << 8)) & 0x0300F00F;
+    v = (v | (v << 4)) & 0x030C30C3;
+    v = (v | (v << 2)) & 0x09249249;
+    return v;
+}
+__device__ __forceinline__ uint32_t compact3(uint32_t v) {
+    v &= 0x09249249;
+    v = (v ^ (v >> 2)) & 0x030C30C3;
+    v = (v ^ (v >> 4)) & 0x0300F00F;
+    v = (v ^ (v >> 8)) & 0xFF0000FF;
+    v = (v ^ (v >> 16)) & 0x000003FF;
+    return v;
+}
+__device__ __forceinline__ uint32_t morton(uint32_t x, uint32_t y, uint32_t z) {
+    return (spread3(x) << 2) | (spread3(y) << 1) | spread3(z);
+}
+__device__ __forceinline__ void unmorton(uint32_t m, int& x, int& y, int& z) {
+    x = (int)compact3(m >> 2);
+    y = (int)compact3(m >> 1);
+    z = (int)compact3(m);
+}
+
+template <typename T> struct Vec4;
+template <> struct Vec4<float> { using type = float4; };
+template <> struct Vec4<double> { using type = double4; };
+template <typename T> using vec4_t = typename Vec4<T>::type;
+
+// Recurrence coefficients of the normalised regular harmonics (see
+// operators.h): Rh_m^m = f_m (x + i y) Rh_{m-1}^{m-1}, Rh_{m+1}^m = sqrt(2m+1) z Rh_m^m,
+// Rh_l^m = a_lm z Rh_{l-1}^m - b_lm r^2 Rh_{l-2}^m.
+struct RhoCoef {
+    double f[kPMax + 1];
+    double a[(kPMax + 1) * (kPMax + 1)];
+    double b[(kPMax + 1) * (kPMax + 1)];
+};
+__constant__ RhoCoef c_rho;
+
+// Visit every coefficient of rho(u) in the order m = 0..p, l = m..p, calling
+// fn(kc, has_sin, re, im): kc is the index of the cosine (real) part; the sine
+// part, when has_sin (m > 0), sits at kc + 1.
+template <typename T, typename Fn>
+__device__ __forceinline__ void for_each_rho(int p, T x, T y, T z, Fn&& fn) {
+    const T r2 = x * x + y * y + z * z;
+    T cre = T(1), cim = T(0);
+    for (int m = 0; m <= p; ++m) {
+        if (m > 0) {
+            const T fm = (T)c_rho.f[m];
+            const T nre = fm * (x * cre - y * cim);
+            const T nim = fm * (x * cim + y * cre);
+            cre = nre;
+            cim = nim;
+        }
+        const int k0 = (m == 0) ? 0 : 2 * m - 1;
+        fn(m * m + k0, m > 0, cre, cim);
+        if (m + 1 > p) continue;
+        T p0re = cre, p0im = cim;
+        T p1re = (T)c_rho.a[(m + 1) * (kPMax + 1) + m] * z * cre;
+        T p1im = (T)c_rho.a[(m + 1) * (kPMax + 1) + m] * z * cim;
+        fn((m + 1) * (m + 1) + k0, m > 0, p1re, p1im);
+        for (int l = m + 2; l <= p; ++l) {
+            const T al = (T)c_rho.a[l * (kPMax + 1) + m];
+            const T bl = (T)c_rho.b[l * (kPMax + 1) + m];
+            const T nre = al * z * p1re - bl * r2 * p0re;
+            const T nim = al * z * p1im - bl * r2 * p0im;
+            p0re = p1re;
+            p0im = p1im;
+            p1re = nre;
+            p1im = nim;
+            fn(l * l + k0, m > 0, p1re, p1im);
+        }
+    }
+}
+
+template <typename T>
+__device__ __forceinline__ T wave_sum(T v) {
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+__device__ __forceinline__ bool finite_d(double v) { return isfinite(v); }
+
+// ------------------------------------------------------------------ fills
+
+__global__ void k_fill_i32(int32_t* p, int64_t n, int32_t v) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+__global__ void k_fill_f64(double* p, int64_t n, double v) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+// ------------------------------------------------------------------ domain
+
+// Per-block min/max of the coordinates (open boundaries): part[b] = {min xyz, max xyz}.
+template <typename T>
+__global__ __launch_bounds__(256) void k_bbox(const T* __restrict__ x, int64_t n,
+                                              double* __restrict__ part) {
+    __shared__ double smin[3][256], smax[3][256];
+    double mn[3] = {1e300, 1e300, 1e300}, mx[3] = {-1e300, -1e300, -1e300};
+    for (int64_t i = blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256)
+        for (int a = 0; a < 3; ++a) {
+            double v = (double)x[3 * i + a];
+            mn[a] = fmin(mn[a], v);
+            mx[a] = fmax(mx[a], v);
+        }
+    for (int a = 0; a < 3; ++a) {
+        smin[a][threadIdx.x] = mn[a];
+        smax[a][threadIdx.x] = mx[a];
+    }
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s)
+            for (int a = 0; a < 3; ++a) {
+                smin[a][threadIdx.x] = fmin(smin[a][threadIdx.x], smin[a][threadIdx.x + s]);
+                smax[a][threadIdx.x] = fmax(smax[a][threadIdx.x], smax[a][threadIdx.x + s]);
+            }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0)
+        for (int a = 0; a < 3; ++a) {
+            part[6 * blockIdx.x + a] = smin[a][0];
+            part[6 * blockIdx.x + 3 + a] = smax[a][0];
+        }
+}
+
+// Root cube of an open system: dom = {lo_x, lo_y, lo_z, edge}.  The edge is the
+// largest extent, enlarged by a relative 2^-20 so no atom sits on the far face.
+__global__ void k_bbox_final(const double* __restrict__ part, int nblk, double* __restrict__ dom) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    double mn[3] = {1e300, 1e300, 1e300}, mx[3] = {-1e300, -1e300, -1e300};
+    for (int b = 0; b < nblk; ++b)
+        for (int a = 0; a < 3; ++a) {
+            mn[a] = fmin(mn[a], part[6 * b + a]);
+            mx[a] = fmax(mx[a], part[6 * b + 3 + a]);
+        }
+    double e = fmax(mx[0] - mn[0], fmax(mx[1] - mn[1], mx[2] - mn[2]));
+    if (!(e > 0)) e = 1.0;
+    e *= 1.0 + 0x1p-20;
+    for (int a = 0; a < 3; ++a) dom[a] = mn[a] - 0x1p-21 * e;
+    dom[3] = e;
+}
+
+// ------------------------------------------------------------------ binning
+
+// q_i = qA_i + lambda_s (qB_i - qA_i) (eq 1 with interpolated charges), leaf
+// key (Morton code of the leaf cell), rank of the atom inside its leaf and its
+// site (atomic counters: ranks are made stable later by sorting).
+template <typename T>
+__global__ __launch_bounds__(256) void k_charge_key(
+    Geo g, int64_t n, const T* __restrict__ x, const T* __restrict__ qA,
+    const T* __restrict__ qB, const int32_t* __restrict__ site, int64_t n_sites,
+    const double* __restrict__ lam, double box, double* __restrict__ dom,
+    int32_t* __restrict__ key, int32_t* __restrict__ rank, int32_t* __restrict__ leaf_count,
+    int32_t* __restrict__ site_count, int32_t* __restrict__ site_rank,
+    int32_t* __restrict__ status) {
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (g.periodic && i == 0) {
+        dom[0] = dom[1] = dom[2] = 0.0;
+        dom[3] = box;
+    }
+    if (i >= n) return;
+    double lo[3], edge;
+    if (g.periodic) {
+        lo[0] = lo[1] = lo[2] = 0.0;
+        edge = box;
+    } else {
+        lo[0] = dom[0];
+        lo[1] = dom[1];
+        lo[2] = dom[2];
+        edge = dom[3];
+    }
+    const double h = edge / g.nb;
+    int c[3];
+    bool bad = false;
+    for (int a = 0; a < 3; ++a) {
+        double v = (double)x[3 * i + a];
+        bad |= !finite_d(v);
+        if (g.periodic) v -= edge * floor(v / edge);
+        int ci = (int)floor((v - lo[a]) / h);
+        c[a] = ci < 0 ? 0 : (ci >= g.nb ? g.nb - 1 : ci);
+    }
+    const uint32_t k = morton(c[0], c[1], c[2]);
+    key[i] = (int32_t)k;
+    rank[i] = atomicAdd(&leaf_count[k], 1);
+    int32_t s = site[i];
+    if (s < -1 || s >= n_sites) {
+        if (g.check) atomicOr(&status[0], kStatusSite);
+        s = -1;
+    }
+    int32_t sr = -1;
+    if (s >= 0) sr = atomicAdd(&site_count[s], 1);
+    site_rank[i] = sr;
+    if (g.check) {
+        bad |= !finite_d((double)qA[i]) || !finite_d((double)qB[i]);
+        if (s >= 0) bad |= !finite_d(lam[s]);
+        if (bad) atomicOr(&status[0], kStatusNonFinite);
+    }
+}
+
+// Exclusive scans (one block per array): start[0..n] from count[0..n-1].
+__global__ __launch_bounds__(1024) void k_scan2(const int32_t* __restrict__ c0, int32_t* __restrict__ s0,
+                                                int64_t n0, const int32_t* __restrict__ c1,
+                                                int32_t* __restrict__ s1, int64_t n1) {
+    const int32_t* cnt = blockIdx.x == 0 ? c0 : c1;
+    int32_t* st = blockIdx.x == 0 ? s0 : s1;
+    const int64_t n = blockIdx.x == 0 ? n0 : n1;
+    __shared__ int32_t part[1024];
+    const int t = threadIdx.x;
+    const int64_t chunk = (n + 1023) / 1024;
+    const int64_t b = t * chunk, e = (b + chunk < n) ? b + chunk : n;
+    int32_t sum = 0;
+    for (int64_t i = b; i < e; ++i) sum += cnt[i];
+    part[t] = sum;
+    __syncthreads();
+    for (int off = 1; off < 1024; off <<= 1) {
+        int32_t v = (t >= off) ? part[t - off] : 0;
+        __syncthreads();
+        part[t] += v;
+        __syncthreads();
+    }
+    int32_t run = part[t] - sum;
+    for (int64_t i = b; i < e; ++i) {
+        st[i] = run;
+        run += cnt[i];
+    }
+    if (t == 1023) st[n] = part[1023];
+}
+
+__global__ __launch_bounds__(256) void k_scatter(int64_t n, const int32_t* __restrict__ key,
+                                                 const int32_t* __restrict__ rank,
+                                                 const int32_t* __restrict__ leaf_start,
+                                                 int32_t* __restrict__ perm,
+                                                 const int32_t* __restrict__ site,
+                                                 int64_t n_sites,
+                                                 const int32_t* __restrict__ site_rank,
+                                                 const int32_t* __restrict__ site_start,
+                                                 int32_t* __restrict__ site_members) {
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    perm[leaf_start[key[i]] + rank[i]] = (int32_t)i;
+    const int32_t s = site[i];
+    if (s >= 0 && s < n_sites) site_members[site_start[s] + site_rank[i]] = (int32_t)i;
+}
+
+// Bitonic sort of up to kSortCap ints in LDS (ascending), block-wide.
+template <int CAP>
+__device__ void lds_sort(int32_t* v, int n) {
+    int np = 1;
+    while (np < n) np <<= 1;
+    for (int i = n + threadIdx.x; i < np; i += blockDim.x) v[i] = 0x7fffffff;
+    __syncthreads();
+    for (int k = 2; k <= np; k <<= 1)
+        for (int j = k >> 1; j > 0; j >>= 1) {
+            for (int i = threadIdx.x; i < np; i += blockDim.x) {
+                int l = i ^ j;
+                if (l > i) {
+                    bool up = (i & k) == 0;
+                    int32_t a = v[i], b = v[l];
+                    if ((a > b) == up) {
+                        v[i] = b;
+                        v[l] = a;
+                    }
+                }
+            }
+            __syncthreads();
+        }
+}
+
+// Per leaf: sort the leaf's atoms by caller index (stable binning) and gather
+// (x - c_leaf, q) into the sorted particle array.
+template <typename T>
+__global__ __launch_bounds__(256) void k_leaf_sort_gather(
+    Geo g, const T* __restrict__ x, const T* __restrict__ qA, const T* __restrict__ qB,
+    const int32_t* __restrict__ site, int64_t n_sites, const double* __restrict__ lam,
+    const double* __restrict__ dom, const int32_t* __restrict__ leaf_start,
+    int32_t* __restrict__ perm, vec4_t<T>* __restrict__ pos, int32_t* __restrict__ status) {
+    __shared__ int32_t buf[kSortCap];
+    const int leaf = blockIdx.x;
+    const int b = leaf_start[leaf], n = leaf_start[leaf + 1] - b;
+    if (n == 0) return;
+    const bool sorted = n <= kSortCap;
+    if (sorted) {
+        for (int i = threadIdx.x; i < n; i += blockDim.x) buf[i] = perm[b + i];
+        __syncthreads();
+        lds_sort<kSortCap>(buf, n);
+    } else if (threadIdx.x == 0) {
+        atomicOr(&status[1], kInfoBigLeaf);
+    }
+    const double edge = dom[3];
+    const double h = edge / g.nb;
+    int cx, cy, cz;
+    unmorton((uint32_t)leaf, cx, cy, cz);
+    const double cc[3] = {dom[0] + (cx + 0.5) * h, dom[1] + (cy + 0.5) * h, dom[2] + (cz + 0.5) * h};
+    for (int j = threadIdx.x; j < n; j += blockDim.x) {
+        const int32_t i = sorted ? buf[j] : perm[b + j];
+        if (sorted) perm[b + j] = i;
+        double s[3];
+        for (int a = 0; a < 3; ++a) {
+            double v = (double)x[3 * i + a];
+            if (g.periodic) v -= edge * floor(v / edge);
+            s[a] = v - cc[a];
+        }
+        int32_t st = site[i];
+        double q = (double)qA[i];
+        if (st >= 0 && st < n_sites) q += lam[st] * ((double)qB[i] - (double)qA[i]);
+        vec4_t<T> o;
+        o.x = (T)s[0];
+        o.y = (T)s[1];
+        o.z = (T)s[2];
+        o.w = (T)q;
+        pos[b + j] = o;
+    }
+}
+
+// ------------------------------------------------------------------ upward pass
+
+// P2M: mu~_leaf = sum_j q_j rho((x_j - c_leaf) / h), one wavefront per leaf,
+// coefficient sums by butterfly shuffles.  Periodic: also per-leaf FP64 partial
+// sums of q |t/L|^2 and q (t relative to the cell centre).
+template <typename T>
+__global__ __launch_bounds__(64) void k_p2m(Geo g, const vec4_t<T>* __restrict__ pos,
+                                            const int32_t* __restrict__ leaf_start,
+                                            const double* __restrict__ dom, T* __restrict__ mult,
+                                            double* __restrict__ leaf_part) {
+    __shared__ T acc[kKMax];
+    const int leaf = blockIdx.x;
+    const int lane = threadIdx.x;
+    const int b = leaf_start[leaf], n = leaf_start[leaf + 1] - b;
+    for (int k = lane; k < g.K; k += 64) acc[k] = T(0);
+    __syncthreads();
+    const double edge = dom[3];
+    const double h = edge / g.nb;
+    const T ih = (T)(1.0 / h);
+    double s2 = 0.0, qs = 0.0;
+    int cx, cy, cz;
+    unmorton((uint32_t)leaf, cx, cy, cz);
+    const double off[3] = {(cx + 0.5) * h - 0.5 * edge, (cy + 0.5) * h - 0.5 * edge,
+                           (cz + 0.5) * h - 0.5 * edge};
+    for (int c0 = 0; c0 < n; c0 += 64) {
+        const int j = c0 + lane;
+        vec4_t<T> a;
+        if (j < n) a = pos[b + j];
+        else { a.x = a.y = a.z = a.w = T(0); }
+        const T q = a.w;
+        if (g.periodic && j < n) {
+            double t0 = (double)a.x + off[0], t1 = (double)a.y + off[1], t2 = (double)a.z + off[2];
+            s2 += (double)q * (t0 * t0 + t1 * t1 + t2 * t2) / (edge * edge);
+            qs += (double)q;
+        }
+        for_each_rho<T>(g.p, a.x * ih, a.y * ih, a.z * ih, [&](int kc, bool hs, T re, T im) {
+            const T v = wave_sum<T>(q * re);
+            if (lane == 0) acc[kc] += v;
+            if (hs) {
+                const T w = wave_sum<T>(q * im);
+                if (lane == 0) acc[kc + 1] += w;
+            }
+        });
+    }
+    __syncthreads();
+    T* dst = mult + (size_t)(g.lev_off[g.depth] + leaf) * g.Kp;
+    for (int k = lane; k < g.K; k += 64) dst[k] = acc[k];
+    if (g.periodic) {
+        s2 = wave_sum<double>(s2);
+        qs = wave_sum<double>(qs);
+        if (lane == 0) {
+            leaf_part[2 * leaf] = s2;
+            leaf_part[2 * leaf + 1] = qs;
+        }
+    }
+}
+
+// M2M for the parents at level lev (children at lev + 1): one block per parent,
+// thread r computes output coefficient r.  Output degree l only depends on
+// child degrees <= l.  Ops are stored transposed: opT[c][k][r].
+template <typename Tin, typename Tout>
+__global__ __launch_bounds__(256) void k_m2m(Geo g, int lev, const Tin* __restrict__ mult_in,
+                                             const Tin* __restrict__ opT, Tout* __restrict__ out,
+                                             int out_stride) {
+    __shared__ Tin ch[8][kKMax];
+    const int parent = blockIdx.x;
+    const Tin* src = mult_in + (size_t)(g.lev_off[lev + 1] + 8 * parent) * g.Kp;
+    for (int i = threadIdx.x; i < 8 * g.K; i += blockDim.x) ch[i / g.K][i % g.K] = src[(size_t)(i / g.K) * g.Kp + i % g.K];
+    __syncthreads();
+    const int r = threadIdx.x;
+    if (r >= g.K) return;
+    const int l = (int)sqrtf((float)r + 0.5f);
+    const int kend = (l + 1) * (l + 1);
+    Tout acc = Tout(0);
+    for (int c = 0; c < 8; ++c) {
+        const Tin* A = opT + (size_t)c * g.K * g.K;
+        for (int k = 0; k < kend; ++k) acc += (Tout)A[(size_t)k * g.K + r] * (Tout)ch[c][k];
+    }
+    out[(size_t)parent * out_stride + r] = acc;
+}
+
+// Root (periodic, FP64): lambda~_root = Lat mu~_root + (2 pi / 3) sum q |s/L|^2 e_0,
+// and dom[4] = Q (net charge, used by the background term at the targets).
+// For a depth-0 tree the root is the leaf: mu~ is read from the level-0 slot
+// of mult and lambda~ is also stored into the level-0 slot of loc.
+template <typename T>
+__global__ __launch_bounds__(256) void k_root(Geo g, const double* __restrict__ leaf_part,
+                                              const double* __restrict__ root_m,
+                                              const T* __restrict__ mult,
+                                              const double* __restrict__ latT,
+                                              double* __restrict__ root_l, T* __restrict__ loc,
+                                              double* __restrict__ dom) {
+    __shared__ double s2s[256], qss[256], mu[kKMax];
+    double s2 = 0.0, qs = 0.0;
+    for (int i = threadIdx.x; i < g.nleaf; i += 256) {
+        s2 += leaf_part[2 * i];
+        qs += leaf_part[2 * i + 1];
+    }
+    s2s[threadIdx.x] = s2;
+    qss[threadIdx.x] = qs;
+    for (int k = threadIdx.x; k < g.K; k += 256)
+        mu[k] = g.depth == 0 ? (double)mult[k] : root_m[k];
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) {
+            s2s[threadIdx.x] += s2s[threadIdx.x + s];
+            qss[threadIdx.x] += qss[threadIdx.x + s];
+        }
+        __syncthreads();
+    }
+    const int r = threadIdx.x;
+    if (r < g.K) {
+        double acc = 0.0;
+        for (int k = 0; k < g.K; ++k) acc += latT[(size_t)k * g.K + r] * mu[k];
+        if (r == 0) acc += 2.0 * kPi / 3.0 * s2s[0];
+        root_l[r] = acc;
+        if (g.depth == 0) loc[r] = (T)acc;
+    }
+    if (r == 0) dom[4] = qss[0];
+}
+
+// ------------------------------------------------------------------ M2L
+
+// Plain M2L: one block per target box (all levels >= lmin), thread r computes
+// lambda~_t[r] = sum over the interaction list of sum_k T(o)[r][k] mu~_s[k].
+// Interaction list: children of the parent's 27 neighbours (periodic images
+// wrapped) that are not adjacent to the target.  bankT[o][k][r].
+template <typename T>
+__global__ __launch_bounds__(256) void k_m2l_plain(Geo g, const T* __restrict__ mult,
+                                                   const T* __restrict__ bankT,
+                                                   T* __restrict__ loc) {
+    __shared__ T src[kKMax];
+    // locate (level, box) of this block
+    int lev = g.lmin;
+    int64_t bidx = blockIdx.x;
+    while (lev < g.depth && bidx >= ((int64_t)1 << (3 * lev))) {
+        bidx -= (int64_t)1 << (3 * lev);
+        ++lev;
+    }
+    const int n = 1 << lev;
+    int tx, ty, tz;
+    unmorton((uint32_t)bidx, tx, ty, tz);
+    const int px = tx >> 1, py = ty >> 1, pz = tz >> 1;
+    const int r = threadIdx.x;
+    T acc = T(0);
+    for (int nb = 0; nb < 216; ++nb) {
+        const int dp = nb >> 3, cb = nb & 7;
+        const int sx = 2 * (px + dp / 9 - 1) + ((cb >> 2) & 1);
+        const int sy = 2 * (py + (dp / 3) % 3 - 1) + ((cb >> 1) & 1);
+        const int sz = 2 * (pz + dp % 3 - 1) + (cb & 1);
+        const int ox = tx - sx, oy = ty - sy, oz = tz - sz;
+        if (abs(ox) <= 1 && abs(oy) <= 1 && abs(oz) <= 1) continue;
+        int wx = sx, wy = sy, wz = sz;
+        if (g.periodic) {
+            wx = (sx % n + n) % n;
+            wy = (sy % n + n) % n;
+            wz = (sz % n + n) % n;
+        } else if (sx < 0 || sy < 0 || sz < 0 || sx >= n || sy >= n || sz >= n) {
+            continue;
+        }
+        const T* ms = mult + (size_t)(g.lev_off[lev] + morton(wx, wy, wz)) * g.Kp;
+        __syncthreads();
+        for (int k = threadIdx.x; k < g.K; k += blockDim.x) src[k] = ms[k];
+        __syncthreads();
+        if (r < g.K) {
+            const T* op = bankT + (size_t)(((ox + 3) * 7 + (oy + 3)) * 7 + (oz + 3)) * g.K * g.K;
+            for (int k = 0; k < g.K; ++k) acc += op[(size_t)k * g.K + r] * src[k];
+        }
+    }
+    if (r < g.K) loc[(size_t)(g.lev_off[lev] + bidx) * g.Kp + r] = acc;
+}
+
+// ------------------------------------------------------------------ downward pass
+
+// L2L into the children at level lev + 1 from their parents at level lev:
+// lambda~_child[r] += sum_{k >= l(r)^2} B_c[r][k] lambda~_parent[k].
+template <typename Tin, typename Tout>
+__global__ __launch_bounds__(256) void k_l2l(Geo g, int lev, const Tin* __restrict__ par,
+                                             int par_stride, const Tout* __restrict__ opT,
+                                             Tout* __restrict__ loc) {
+    __shared__ Tin pl[kKMax];
+    const int child = blockIdx.x;
+    const int parent = child >> 3, c = child & 7;
+    for (int k = threadIdx.x; k < g.K; k += blockDim.x) pl[k] = par[(size_t)parent * par_stride + k];
+    __syncthreads();
+    const int r = threadIdx.x;
+    if (r >= g.K) return;
+    const int l = (int)sqrtf((float)r + 0.5f);
+    const Tout* B = opT + (size_t)c * g.K * g.K;
+    Tout acc = Tout(0);
+    for (int k = l * l; k < g.K; ++k) acc += B[(size_t)k * g.K + r] * (Tout)pl[k];
+    loc[(size_t)(g.lev_off[lev + 1] + child) * g.Kp + r] += acc;
+}
+
+// ------------------------------------------------------------------ near + far field
+
+// Per target leaf (4 wavefronts): the sources of the 27 neighbour leaves
+// (periodic images through integer leaf offsets) are staged through LDS in
+// tiles of 256 and split between the wavefronts; each lane owns one target.
+// Wavefront 0 adds the far field from the leaf's local expansion (L2P with its
+// gradient) and the background term, then writes potential, force, the
+// per-leaf energy partial and (qB - qA) phi for the site sums.
+template <typename T>
+__global__ __launch_bounds__(256) void k_near_far(
+    Geo g, const vec4_t<T>* __restrict__ pos, const int32_t* __restrict__ leaf_start,
+    const int32_t* __restrict__ perm, const double* __restrict__ dom,
+    const T* __restrict__ loc, const int32_t* __restrict__ gidx, const T* __restrict__ gcoef,
+    const T* __restrict__ qA, const T* __restrict__ qB, const int32_t* __restrict__ site,
+    int64_t n_sites, T* __restrict__ phi_out, T* __restrict__ F_out,
+    double* __restrict__ leaf_energy, double* __restrict__ cphi) {
+    __shared__ vec4_t<T> tile[256];
+    __shared__ int nb_start[28], nb_cnt[28], nb_pre[29];
+    __shared__ T nb_off[27][3];
+    __shared__ T lam[kKMax];
+    __shared__ T gr[3][kKgMax];
+    __shared__ T part[4][64][4];
+    const int leaf = blockIdx.x;
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const int tb = leaf_start[leaf], tn = leaf_start[leaf + 1] - tb;
+    if (tn == 0) {
+        if (tid == 0) leaf_energy[leaf] = 0.0;
+        return;
+    }
+    const double edge = dom[3];
+    const double h = edge / g.nb;
+    int cx, cy, cz;
+    unmorton((uint32_t)leaf, cx, cy, cz);
+    if (tid < 27) {
+        const int dx = tid / 9 - 1, dy = (tid / 3) % 3 - 1, dz = tid % 3 - 1;
+        int nx = cx + dx, ny = cy + dy, nz = cz + dz;
+        bool ok = true;
+        if (g.periodic) {
+            nx = (nx % g.nb + g.nb) % g.nb;
+            ny = (ny % g.nb + g.nb) % g.nb;
+            nz = (nz % g.nb + g.nb) % g.nb;
+        } else {
+            ok = nx >= 0 && ny >= 0 && nz >= 0 && nx < g.nb && ny < g.nb && nz < g.nb;
+        }
+        int s = 0, c = 0;
+        if (ok) {
+            const uint32_t m = morton(nx, ny, nz);
+            s = leaf_start[m];
+            c = leaf_start[m + 1] - s;
+        }
+        nb_start[tid] = s;
+        nb_cnt[tid] = c;
+        nb_off[tid][0] = (T)(dx * h);
+        nb_off[tid][1] = (T)(dy * h);
+        nb_off[tid][2] = (T)(dz * h);
+    }
+    const bool far = g.has_far;
+    if (far) {
+        const T* lsrc = loc + (size_t)(g.lev_off[g.depth] + leaf) * g.Kp;
+        for (int k = tid; k < g.K; k += 256) lam[k] = lsrc[k];
+    }
+    __syncthreads();
+    if (tid == 0) {
+        nb_pre[0] = 0;
+        for (int i = 0; i < 27; ++i) nb_pre[i + 1] = nb_pre[i] + nb_cnt[i];
+    }
+    if (far) {
+        for (int e = tid; e < 3 * g.Kg; e += 256) {
+            const int a = e / g.Kg, r = e % g.Kg;
+            T v = T(0);
+            for (int t = 0; t < 4; ++t) {
+                const int k = gidx[(size_t)e * 4 + t];
+                if (k >= 0) v += gcoef[(size_t)e * 4 + t] * lam[k];
+            }
+            gr[a][r] = v;
+        }
+    }
+    __syncthreads();
+    const int total = nb_pre[27];
+    const T ih = (T)(1.0 / h);
+    double esum = 0.0;
+    for (int t0 = 0; t0 < tn; t0 += 64) {
+        const int tj = t0 + lane;
+        vec4_t<T> me;
+        if (tj < tn) me = pos[tb + tj];
+        else { me.x = me.y = me.z = me.w = T(0); }
+        T ph = T(0), fx = T(0), fy = T(0), fz = T(0);
+        for (int s0 = 0; s0 < total; s0 += 256) {
+            __syncthreads();
+            const int gsrc = s0 + tid;
+            if (gsrc < total) {
+                int nbi = 0;
+                while (nb_pre[nbi + 1] <= gsrc) ++nbi;
+                vec4_t<T> a = pos[nb_start[nbi] + (gsrc - nb_pre[nbi])];
+                a.x += nb_off[nbi][0];
+                a.y += nb_off[nbi][1];
+                a.z += nb_off[nbi][2];
+                tile[tid] = a;
+            }
+            __syncthreads();
+            const int jb = wave * 64;
+            const int je = min(jb + 64, total - s0);
+            for (int j = jb; j < je; ++j) {
+                const vec4_t<T> s = tile[j];
+                const T dx = me.x - s.x, dy = me.y - s.y, dz = me.z - s.z;
+                const T r2 = dx * dx + dy * dy + dz * dz;
+                const T ri = r2 > T(0) ? T(1) / sqrt(r2) : T(0);
+                const T qr = s.w * ri;
+                const T qr3 = qr * ri * ri;
+                ph += qr;
+                fx += qr3 * dx;
+                fy += qr3 * dy;
+                fz += qr3 * dz;
+            }
+        }
+        part[wave][lane][0] = ph;
+        part[wave][lane][1] = fx;
+        part[wave][lane][2] = fy;
+        part[wave][lane][3] = fz;
+        __syncthreads();
+        if (wave == 0 && tj < tn) {
+            T p = part[0][lane][0] + part[1][lane][0] + part[2][lane][0] + part[3][lane][0];
+            T ex = part[0][lane][1] + part[1][lane][1] + part[2][lane][1] + part[3][lane][1];
+            T ey = part[0][lane][2] + part[1][lane][2] + part[2][lane][2] + part[3][lane][2];
+            T ez = part[0][lane][3] + part[1][lane][3] + part[2][lane][3] + part[3][lane][3];
+            if (far) {
+                T fp = T(0), gx = T(0), gy = T(0), gz = T(0);
+                const int Kg = g.Kg;
+                for_each_rho<T>(g.p, me.x * ih, me.y * ih, me.z * ih, [&](int kc, bool has_s, T re, T im) {
+                    fp += lam[kc] * re;
+                    if (has_s) fp += lam[kc + 1] * im;
+                    if (kc < Kg) {
+                        gx += gr[0][kc] * re;
+                        gy += gr[1][kc] * re;
+                        gz += gr[2][kc] * re;
+                        if (has_s) {
+                            gx += gr[0][kc + 1] * im;
+                            gy += gr[1][kc + 1] * im;
+                            gz += gr[2][kc + 1] * im;
+                        }
+                    }
+                });
+                p += fp * ih;
+                ex -= gx * ih * ih;
+                ey -= gy * ih * ih;
+                ez -= gz * ih * ih;
+            }
+            if (g.periodic) {
+                // background: phi += (2 pi / 3) Q |t|^2 / V, field -= (4 pi / 3) Q t / V
+                const double Q = dom[4];
+                const double V = edge * edge * edge;
+                const double t0v = (double)me.x + (cx + 0.5) * h - 0.5 * edge;
+                const double t1v = (double)me.y + (cy + 0.5) * h - 0.5 * edge;
+                const double t2v = (double)me.z + (cz + 0.5) * h - 0.5 * edge;
+                p += (T)(2.0 * kPi / 3.0 * Q * (t0v * t0v + t1v * t1v + t2v * t2v) / V);
+                ex -= (T)(4.0 * kPi / 3.0 * Q * t0v / V);
+                ey -= (T)(4.0 * kPi / 3.0 * Q * t1v / V);
+                ez -= (T)(4.0 * kPi / 3.0 * Q * t2v / V);
+            }
+            const int32_t i = perm[tb + tj];
+            const T q = me.w;
+            const T ke = (T)g.coulomb_k;
+            if (phi_out) phi_out[i] = ke * p;
+            if (F_out) {
+                F_out[3 * (size_t)i] = ke * q * ex;
+                F_out[3 * (size_t)i + 1] = ke * q * ey;
+                F_out[3 * (size_t)i + 2] = ke * q * ez;
+            }
+            esum += (double)q * (double)p;
+            const int32_t st = site[i];
+            if (st >= 0 && st < n_sites)
+                cphi[i] = g.coulomb_k * ((double)qB[i] - (double)qA[i]) * (double)p;
+        }
+    }
+    if (wave == 0) {
+        esum = wave_sum<double>(esum);
+        if (lane == 0) leaf_energy[leaf] = esum;
+    }
+}
+
+// Final reductions: block 0 -> E = k_e / 2 sum of the leaf partials (fixed
+// order); block 1 + s -> dVdl_s = sum over site s's atoms in caller order.
+__global__ __launch_bounds__(256) void k_reduce(Geo g, const double* __restrict__ leaf_energy,
+                                                const int32_t* __restrict__ site_start,
+                                                const int32_t* __restrict__ site_members,
+                                                const double* __restrict__ cphi,
+                                                double* __restrict__ E, double* __restrict__ dVdl,
+                                                int32_t* __restrict__ status) {
+    __shared__ double red[256];
+    __shared__ int32_t mem[kSiteCap];
+    const int t = threadIdx.x;
+    double v = 0.0;
+    if (blockIdx.x == 0) {
+        for (int i = t; i < g.nleaf; i += 256) v += leaf_energy[i];
+    } else {
+        const int s = blockIdx.x - 1;
+        const int b = site_start[s], n = site_start[s + 1] - b;
+        if (n <= kSiteCap) {
+            for (int i = t; i < n; i += 256) mem[i] = site_members[b + i];
+            __syncthreads();
+            lds_sort<kSiteCap>(mem, n);
+            for (int i = t; i < n; i += 256) v += cphi[mem[i]];
+        } else {
+            if (t == 0) atomicOr(&status[1], kInfoBigSite);
+            for (int i = t; i < n; i += 256) v += cphi[site_members[b + i]];
+        }
+    }
+    red[t] = v;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if (t < s) red[t] += red[t + s];
+        __syncthreads();
+    }
+    if (t == 0) {
+        if (blockIdx.x == 0) {
+            if (E) *E = 0.5 * g.coulomb_k * red[0];
+        } else if (dVdl) {
+            dVdl[blockIdx.x - 1] = red[0];
+        }
+    }
+}
+
+// Adjoint of E for an upstream weight *gE (see fmm_eval_adjoint).
+template <typename T>
+__global__ __launch_bounds__(256) void k_adjoint(int64_t n, const int32_t* __restrict__ site,
+                                                 int64_t n_sites, const double* __restrict__ lam,
+                                                 const double* __restrict__ gE,
+                                                 const T* __restrict__ F, const T* __restrict__ phi,
+                                                 const double* __restrict__ dVdl,
+                                                 T* __restrict__ gx, T* __restrict__ gqA,
+                                                 T* __restrict__ gqB, double* __restrict__ glam) {
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    const double w = *gE;
+    if (glam && i < n_sites) glam[i] = w * dVdl[i];
+    if (i >= n) return;
+    if (gx) {
+        gx[3 * i] = (T)(-w * (double)F[3 * i]);
+        gx[3 * i + 1] = (T)(-w * (double)F[3 * i + 1]);
+        gx[3 * i + 2] = (T)(-w * (double)F[3 * i + 2]);
+    }
+    const int32_t s = site[i];
+    const double l = (s >= 0 && s < n_sites) ? lam[s] : 0.0;
+    const double p = (double)phi[i];
+    if (gqA) gqA[i] = (T)(w * (1.0 - l) * p);
+    if (gqB) gqB[i] = (T)(w * l * p);
+}
+
+}  // namespace fmmk

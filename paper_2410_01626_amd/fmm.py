@@ -1,0 +1,312 @@
+"""Thin Python binding of the C ABI in include/fmmcph.h (argument marshalling only).
+
+Every step of an evaluation runs in the HIP kernels of ``libfmmcph.so``; this
+module only checks tensor dtypes/devices and passes raw pointers.  PyTorch
+provides device memory and the stream.  There is no fallback: if the library
+is missing, importing the loader raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libfmmcph.so")
+
+FMM_OK = 0
+FMM_E_INVALID = 1
+FMM_E_OOM = 2
+FMM_E_HIP = 3
+FMM_E_UNSUPPORTED = 4
+FMM_E_NONFINITE = 5
+FMM_E_SITE = 6
+STATUS_NAMES = {0: "FMM_OK", 1: "FMM_E_INVALID", 2: "FMM_E_OOM", 3: "FMM_E_HIP",
+                4: "FMM_E_UNSUPPORTED", 5: "FMM_E_NONFINITE", 6: "FMM_E_SITE"}
+
+FMM_OPEN = 0
+FMM_PERIODIC = 1
+FMM_FP64 = 0
+FMM_MIXED_F32 = 1
+FMM_MIXED_BF16X3 = 2
+PRECISIONS = {"fp64": FMM_FP64, "f32": FMM_MIXED_F32, "bf16x3": FMM_MIXED_BF16X3}
+
+
+class fmm_params(ctypes.Structure):
+    _fields_ = [
+        ("depth", ctypes.c_int32),
+        ("order_p", ctypes.c_int32),
+        ("boundary", ctypes.c_int32),
+        ("precision", ctypes.c_int32),
+        ("coulomb_k", ctypes.c_double),
+        ("max_atoms", ctypes.c_int64),
+        ("max_sites", ctypes.c_int64),
+        ("max_replicas", ctypes.c_int32),
+        ("check", ctypes.c_int32),
+    ]
+
+
+EXPORTS = ["fmm_plan_create", "fmm_eval", "fmm_eval_adjoint", "fmm_eval_batched",
+           "fmm_sync_check", "fmm_last_error", "fmm_plan_destroy", "fmm_profile",
+           "fmm_host_operator"]
+PHASES = ["bin", "p2m", "m2m", "root", "m2l", "l2l", "near_far", "reduce"]
+
+_lib = None
+
+
+class FmmError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__("%s: %s" % (STATUS_NAMES.get(status, status), msg))
+        self.status = status
+
+
+def load_library(path: str = LIB_PATH):
+    """Load libfmmcph.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError("libfmmcph.so is not built: run __graft_entry__.build() or "
+                           "python paper_2410_01626_amd/build_lib.py")
+    lib = ctypes.CDLL(path)
+    vp, i64, i32, dp = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_void_p
+    lib.fmm_plan_create.restype = ctypes.c_int
+    lib.fmm_plan_create.argtypes = [ctypes.POINTER(fmm_params), vp, ctypes.POINTER(vp)]
+    lib.fmm_eval.restype = ctypes.c_int
+    lib.fmm_eval.argtypes = [vp, i64, vp, vp, vp, vp, i64, vp, vp, vp, vp, vp, vp]
+    lib.fmm_eval_adjoint.restype = ctypes.c_int
+    lib.fmm_eval_adjoint.argtypes = [vp, i64, vp, vp, vp, vp, i64, vp, vp, vp,
+                                     vp, vp, vp, vp, vp, vp, vp, vp]
+    lib.fmm_eval_batched.restype = ctypes.c_int
+    lib.fmm_eval_batched.argtypes = [vp, i32, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]
+    lib.fmm_sync_check.restype = ctypes.c_int
+    lib.fmm_sync_check.argtypes = [vp]
+    lib.fmm_last_error.restype = ctypes.c_char_p
+    lib.fmm_last_error.argtypes = [vp]
+    lib.fmm_plan_destroy.restype = None
+    lib.fmm_plan_destroy.argtypes = [vp]
+    lib.fmm_profile.restype = ctypes.c_int
+    lib.fmm_profile.argtypes = [vp, i32, i32, vp]
+    lib.fmm_host_operator.restype = ctypes.c_int64
+    lib.fmm_host_operator.argtypes = [i32, i32, dp]
+    _lib = lib
+    return lib
+
+
+# ----------------------------------------------------------------- raw C names
+
+def fmm_plan_create(params: fmm_params, hip_stream=None):
+    lib = load_library()
+    out = ctypes.c_void_p()
+    st = lib.fmm_plan_create(ctypes.byref(params), ctypes.c_void_p(hip_stream or 0),
+                             ctypes.byref(out))
+    if st != FMM_OK:
+        raise FmmError(st, "fmm_plan_create")
+    return out
+
+
+def fmm_plan_destroy(plan):
+    load_library().fmm_plan_destroy(plan)
+
+
+def fmm_last_error(plan) -> str:
+    return load_library().fmm_last_error(plan).decode()
+
+
+def fmm_sync_check(plan) -> int:
+    return load_library().fmm_sync_check(plan)
+
+
+def fmm_eval(plan, n, x, qA, qB, site, n_sites, lam, box, E, F, phi, dVdl) -> int:
+    return load_library().fmm_eval(plan, n, x, qA, qB, site, n_sites, lam, box, E, F, phi, dVdl)
+
+
+def fmm_eval_adjoint(plan, n, x, qA, qB, site, n_sites, lam, box, gE, gx, gqA, gqB, glam,
+                     E, F, phi, dVdl) -> int:
+    return load_library().fmm_eval_adjoint(plan, n, x, qA, qB, site, n_sites, lam, box, gE,
+                                           gx, gqA, gqB, glam, E, F, phi, dVdl)
+
+
+def fmm_eval_batched(plan, R, atom_off, site_off, x, qA, qB, site_local, lam, boxes, E, F,
+                     phi, dVdl) -> int:
+    return load_library().fmm_eval_batched(plan, R, atom_off, site_off, x, qA, qB, site_local,
+                                           lam, boxes, E, F, phi, dVdl)
+
+
+def fmm_profile(plan, mode: int, capacity: int = 0, out=None) -> int:
+    return load_library().fmm_profile(plan, mode, capacity,
+                                      ctypes.c_void_p(0) if out is None else out.ctypes.data)
+
+
+def fmm_host_operator(order_p: int, which: int, point=None) -> np.ndarray:
+    """FP64 operator tables a plan uploads (host only, no GPU needed)."""
+    K = (order_p + 1) ** 2
+    size = {0: 343 * K * K, 1: 8 * K * K, 2: 8 * K * K, 3: K * K, 4: K}[which]
+    out = np.zeros(max(size, 3))
+    if which == 4:
+        out[:3] = np.asarray(point, dtype=np.float64)
+    n = load_library().fmm_host_operator(order_p, which, out.ctypes.data)
+    if n != size:
+        raise ValueError("fmm_host_operator(%d, %d) failed" % (order_p, which))
+    out = out[:size]
+    if which == 0:
+        return out.reshape(7, 7, 7, K, K)
+    if which in (1, 2):
+        return out.reshape(8, K, K)
+    if which == 3:
+        return out.reshape(K, K)
+    return out
+
+
+# ----------------------------------------------------------------- torch layer
+
+def _ptr(t):
+    return ctypes.c_void_p(0) if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+class Plan:
+    """A plan bound to one device and one stream (torch's current stream by default)."""
+
+    def __init__(self, depth: int, order: int, periodic: bool = False,
+                 precision: str = "fp64", coulomb_k: float = 1.0, max_atoms: int = 1,
+                 max_sites: int = 1, max_replicas: int = 1, check: bool = False,
+                 stream=None, device=None):
+        import torch
+        dev = torch.device(device) if device is not None else torch.device("cuda")
+        if dev.type == "cuda" and dev.index is None:
+            dev = torch.device("cuda", torch.cuda.current_device())
+        self.device = dev
+        if self.device.type != "cuda":
+            raise ValueError("the FMM library runs on a GPU device only")
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        self.params = fmm_params(depth, order, FMM_PERIODIC if periodic else FMM_OPEN,
+                                 PRECISIONS[precision], float(coulomb_k), int(max_atoms),
+                                 int(max_sites), int(max_replicas), 1 if check else 0)
+        self.periodic = periodic
+        self.precision = precision
+        self.dtype = torch.float64 if precision == "fp64" else torch.float32
+        with torch.cuda.device(self.device):
+            self.handle = fmm_plan_create(self.params, self.stream.cuda_stream)
+
+    def close(self):
+        if getattr(self, "handle", None) is not None:
+            fmm_plan_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _raise(self, st, what):
+        if st != FMM_OK:
+            raise FmmError(st, "%s: %s" % (what, fmm_last_error(self.handle)))
+
+    def _check(self, t, dtype, shape=None, name="tensor"):
+        if t.device != self.device:
+            raise ValueError("%s must live on %s" % (name, self.device))
+        if t.dtype != dtype:
+            raise ValueError("%s must be %s, got %s" % (name, dtype, t.dtype))
+        if not t.is_contiguous():
+            raise ValueError("%s must be contiguous" % name)
+        if shape is not None and tuple(t.shape) != tuple(shape):
+            raise ValueError("%s must have shape %s, got %s" % (name, shape, tuple(t.shape)))
+
+    def _inputs(self, x, qA, qB, site, lam):
+        import torch
+        n = x.shape[0]
+        self._check(x, self.dtype, (n, 3), "x")
+        self._check(qA, self.dtype, (n,), "qA")
+        self._check(qB, self.dtype, (n,), "qB")
+        self._check(site, torch.int32, (n,), "site")
+        self._check(lam, torch.float64, None, "lambda")
+        return n, lam.numel()
+
+    def _box(self, box):
+        if not self.periodic:
+            if box is not None:
+                raise ValueError("open plan takes no box")
+            return None, ctypes.c_void_p(0)
+        b = np.ascontiguousarray(np.broadcast_to(np.asarray(box, dtype=np.float64), (3,)))
+        return b, ctypes.c_void_p(b.ctypes.data)
+
+    def eval(self, x, qA, qB, site, lam, box=None, want=("E", "F", "phi", "dVdl")):
+        """Enqueue fmm_eval; returns dict of output tensors (E is a 1-element FP64 tensor)."""
+        import torch
+        n, S = self._inputs(x, qA, qB, site, lam)
+        opt = dict(device=self.device)
+        out = {"E": torch.empty(1, dtype=torch.float64, **opt)}
+        out["F"] = torch.empty((n, 3), dtype=self.dtype, **opt) if "F" in want else None
+        out["phi"] = torch.empty(n, dtype=self.dtype, **opt) if "phi" in want else None
+        out["dVdl"] = torch.empty(S, dtype=torch.float64, **opt) if "dVdl" in want else None
+        b, bp = self._box(box)
+        st = fmm_eval(self.handle, n, _ptr(x), _ptr(qA), _ptr(qB), _ptr(site), S, _ptr(lam), bp,
+                      _ptr(out["E"]), _ptr(out["F"]), _ptr(out["phi"]), _ptr(out["dVdl"]))
+        self._raise(st, "fmm_eval")
+        return out
+
+    def eval_adjoint(self, x, qA, qB, site, lam, gE, box=None):
+        """Enqueue fmm_eval_adjoint; returns dict of gradients and forward outputs."""
+        import torch
+        n, S = self._inputs(x, qA, qB, site, lam)
+        self._check(gE, torch.float64, None, "gE")
+        opt = dict(device=self.device)
+        out = {"E": torch.empty(1, dtype=torch.float64, **opt),
+               "F": torch.empty((n, 3), dtype=self.dtype, **opt),
+               "phi": torch.empty(n, dtype=self.dtype, **opt),
+               "dVdl": torch.empty(S, dtype=torch.float64, **opt),
+               "grad_x": torch.empty((n, 3), dtype=self.dtype, **opt),
+               "grad_qA": torch.empty(n, dtype=self.dtype, **opt),
+               "grad_qB": torch.empty(n, dtype=self.dtype, **opt),
+               "grad_lambda": torch.empty(S, dtype=torch.float64, **opt)}
+        b, bp = self._box(box)
+        st = fmm_eval_adjoint(self.handle, n, _ptr(x), _ptr(qA), _ptr(qB), _ptr(site), S,
+                              _ptr(lam), bp, _ptr(gE), _ptr(out["grad_x"]), _ptr(out["grad_qA"]),
+                              _ptr(out["grad_qB"]), _ptr(out["grad_lambda"]), _ptr(out["E"]),
+                              _ptr(out["F"]), _ptr(out["phi"]), _ptr(out["dVdl"]))
+        self._raise(st, "fmm_eval_adjoint")
+        return out
+
+    def eval_batched(self, atom_off, site_off, x, qA, qB, site_local, lam, boxes=None):
+        """Enqueue fmm_eval_batched over R replicas (offsets are host sequences)."""
+        import torch
+        ao = np.ascontiguousarray(atom_off, dtype=np.int64)
+        so = np.ascontiguousarray(site_off, dtype=np.int64)
+        R = ao.size - 1
+        n, S = self._inputs(x, qA, qB, site_local, lam)
+        if ao[-1] != n or so[-1] != S:
+            raise ValueError("offsets do not match the concatenated arrays")
+        opt = dict(device=self.device)
+        out = {"E": torch.empty(R, dtype=torch.float64, **opt),
+               "F": torch.empty((n, 3), dtype=self.dtype, **opt),
+               "phi": torch.empty(n, dtype=self.dtype, **opt),
+               "dVdl": torch.empty(S, dtype=torch.float64, **opt)}
+        if self.periodic:
+            bx = np.ascontiguousarray(np.asarray(boxes, dtype=np.float64).reshape(R, 3))
+            bp = ctypes.c_void_p(bx.ctypes.data)
+        else:
+            bx, bp = None, ctypes.c_void_p(0)
+        st = fmm_eval_batched(self.handle, R, ctypes.c_void_p(ao.ctypes.data),
+                              ctypes.c_void_p(so.ctypes.data), _ptr(x), _ptr(qA), _ptr(qB),
+                              _ptr(site_local), _ptr(lam), bp, _ptr(out["E"]), _ptr(out["F"]),
+                              _ptr(out["phi"]), _ptr(out["dVdl"]))
+        self._raise(st, "fmm_eval_batched")
+        return out
+
+    def profile_start(self, capacity: int):
+        self._raise(fmm_profile(self.handle, 1, capacity), "fmm_profile")
+
+    def profile_stop(self):
+        self._raise(fmm_profile(self.handle, 0), "fmm_profile")
+
+    def profile_read(self):
+        """{phase: (total_ms, count)} over the evaluations recorded so far."""
+        out = np.zeros(2 * len(PHASES))
+        self._raise(fmm_profile(self.handle, 2, 0, out), "fmm_profile")
+        return {ph: (out[i], int(out[len(PHASES) + i])) for i, ph in enumerate(PHASES)}
+
+    def sync_check(self):
+        st = fmm_sync_check(self.handle)
+        self._raise(st, "fmm_sync_check")

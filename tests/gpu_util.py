@@ -1,0 +1,74 @@
+"""Helpers shared by the GPU tests: run the HIP path through the C ABI binding
+and compare it with the FP64 oracle on the same seeded inputs."""
+from __future__ import annotations
+
+import functools
+
+import numpy as np
+
+import oracle
+
+# Accuracy bounds of the FMM against the FP64 oracle, per multipole order p
+# (relative RMS force error; the potential uses the same bound, the energy a
+# tenth of it, dV/dlambda the bound relative to the RMS of the reference).
+TOL_F = {1: 0.3, 2: 6e-2, 3: 3e-2, 4: 1.5e-2, 5: 6e-3, 6: 3e-3, 7: 1.2e-3, 8: 5e-4,
+         9: 2.5e-4, 10: 1e-4, 11: 6e-5, 12: 3e-5, 13: 1.5e-5, 14: 8e-6, 15: 4e-6}
+
+
+def run(d, precision="fp64", depth=None, order=None, k_e=1.0, lam=None, device="cuda:0",
+        check=False):
+    import torch
+    from paper_2410_01626_amd import fmm
+    dev = torch.device(device)
+    n = d["x"].shape[0]
+    lam = d["lam"] if lam is None else lam
+    S = lam.size
+    plan = fmm.Plan(d["depth"] if depth is None else depth, d["order"] if order is None else order,
+                    periodic=d["periodic"], precision=precision, coulomb_k=k_e,
+                    max_atoms=max(n, 1), max_sites=max(S, 1), check=check, device=dev)
+    dt = plan.dtype
+    x = torch.tensor(d["x"], dtype=dt, device=dev)
+    qA = torch.tensor(d["qA"], dtype=dt, device=dev)
+    qB = torch.tensor(d["qB"], dtype=dt, device=dev)
+    site = torch.tensor(d["site"], dtype=torch.int32, device=dev)
+    lt = torch.tensor(lam, dtype=torch.float64, device=dev)
+    out = plan.eval(x, qA, qB, site, lt, box=d["box"] if d["periodic"] else None)
+    torch.cuda.synchronize(dev)
+    if check:
+        plan.sync_check()
+    res = {"E": out["E"].item(), "F": out["F"].double().cpu().numpy(),
+           "phi": out["phi"].double().cpu().numpy(), "dVdl": out["dVdl"].cpu().numpy()}
+    plan.close()
+    return res
+
+
+def reference(d, k_e=1.0, lam=None):
+    lam = d["lam"] if lam is None else lam
+    return oracle.solve(d["x"], d["qA"], d["qB"], d["site"], lam,
+                        box=d["box"], periodic=d["periodic"], k_e=k_e)
+
+
+@functools.lru_cache(maxsize=4)
+def cached_reference(name):
+    from paper_2410_01626_amd import workloads
+    d = workloads.by_name(name)
+    return d, reference(d)
+
+
+def errors(out, ref):
+    F, Fr = out["F"], ref["F"]
+    eF = np.sqrt(np.sum((F - Fr) ** 2) / np.sum(Fr ** 2))
+    ephi = np.sqrt(np.sum((out["phi"] - ref["phi"]) ** 2) / np.sum(ref["phi"] ** 2))
+    eE = abs(out["E"] - ref["E"]) / (0.5 * np.sum(np.abs(ref["q"] * ref["phi"])))
+    dv = ref["dVdl"]
+    edv = (np.abs(out["dVdl"] - dv).max() / np.sqrt(np.mean(dv ** 2))) if dv.size else 0.0
+    return {"F": eF, "phi": ephi, "E": eE, "dVdl": edv}
+
+
+def assert_within(err, p, factor=1.0, label=""):
+    t = TOL_F[p] * factor
+    msg = "%s p=%d errors %s (bound %g)" % (label, p, err, t)
+    assert err["F"] <= t, msg
+    assert err["phi"] <= t, msg
+    assert err["E"] <= t / 10, msg
+    assert err["dVdl"] <= t, msg

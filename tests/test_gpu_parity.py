@@ -1,0 +1,182 @@
+"""GPU parity of the HIP path against the FP64 oracle (through the C ABI)."""
+import numpy as np
+import pytest
+
+from gpu_util import TOL_F, assert_within, cached_reference, errors, reference, run
+from paper_2410_01626_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+# ---------------------------------------------------------------- exact limits
+
+@pytest.mark.parametrize("depth", [0, 1])
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-12), ("f32", 2e-6)])
+def test_open_shallow_tree_is_direct_sum(depth, prec, tol):
+    """Open boundaries with depth 0 or 1 have no interaction lists: the FMM is
+    the direct sum (every pair is near), up to rounding."""
+    d = W.open_cube()
+    out = run(d, prec, depth=depth)
+    err = errors(out, reference(d))
+    assert max(err.values()) <= tol, err
+
+
+# ---------------------------------------------------------------- open boundaries
+
+@pytest.mark.parametrize("prec", ["fp64", "f32"])
+def test_open_cube(prec):
+    d = W.open_cube()
+    out = run(d, prec)
+    err = errors(out, reference(d))
+    assert_within(err, d["order"], label="open_cube " + prec)
+
+
+def test_open_error_decays_with_order():
+    d = W.open_cube()
+    ref = reference(d)
+    errs = []
+    for p in (2, 4, 6, 8, 10, 12):
+        e = errors(run(d, "fp64", order=p), ref)
+        assert_within(e, p, label="open p")
+        errs.append(e["F"])
+    # geometric decay, no floor above 1e-7 (a floor would mean a convention mismatch)
+    assert errs[-1] < 1e-5 and all(b < a for a, b in zip(errs, errs[1:])), errs
+
+
+@pytest.mark.parametrize("depth", [2, 3, 4])
+def test_open_depths(depth):
+    d = W.random_open(11, n=1500, edge=2.5, depth=depth, order=8)
+    err = errors(run(d, "fp64"), reference(d))
+    assert_within(err, 8, label="open depth %d" % depth)
+
+
+# ---------------------------------------------------------------- periodic
+
+@pytest.mark.parametrize("depth", [0, 1, 2, 3])
+@pytest.mark.parametrize("prec", ["fp64", "f32"])
+def test_periodic_small(depth, prec):
+    d = W.tiny_periodic(21, n=400, edge=1.6, n_sites=4, depth=depth, order=8)
+    err = errors(run(d, prec), reference(d))
+    assert_within(err, 8, label="periodic depth %d %s" % (depth, prec))
+
+
+@pytest.mark.parametrize("prec", ["fp64", "f32"])
+def test_periodic_non_neutral_gauge(prec):
+    """Net charge: background and zero-mean gauge must match Ewald; a constant
+    offset in phi would move dV/dlambda by offset * sum(Delta)."""
+    d = W.tiny_periodic(22, n=300, edge=1.3, n_sites=3, neutral=False, depth=2, order=8)
+    assert abs(d["qA"].sum()) > 0.5
+    ref = reference(d)
+    out = run(d, prec)
+    err = errors(out, ref)
+    assert_within(err, 8, label="non-neutral " + prec)
+    assert abs(np.mean(out["phi"] - ref["phi"])) < TOL_F[8] * np.sqrt(np.mean(ref["phi"] ** 2))
+
+
+def test_periodic_error_decays_with_order():
+    d = W.tiny_periodic(23, n=300, edge=1.0, n_sites=2, depth=1, order=4)
+    ref = reference(d)
+    errs = []
+    for p in (4, 6, 8, 10, 12, 14):
+        e = errors(run(d, "fp64", order=p), ref)
+        assert_within(e, p, label="periodic p")
+        errs.append(e["F"])
+    assert errs[-1] < 2e-6 and all(b < a for a, b in zip(errs, errs[1:])), errs
+
+
+@pytest.mark.parametrize("prec", ["fp64", "f32"])
+def test_water_box_full_size(prec):
+    """30,000-atom periodic water box at depth 3, p = 8: every output element
+    against the full Ewald oracle."""
+    d, ref = cached_reference("water_box")
+    out = run(d, prec)
+    err = errors(out, ref)
+    assert_within(err, 8, label="water_box " + prec)
+
+
+# ---------------------------------------------------------------- invariants and edge cases
+
+def test_lambda_derivative_is_derivative_of_fmm_energy():
+    """E_fmm is exactly quadratic in lambda; with symmetric translation operators
+    its central difference equals the returned dV/dlambda to rounding."""
+    d = W.tiny_periodic(24, n=200, edge=1.2, n_sites=3, depth=2, order=6)
+    base = run(d, "fp64")
+    h = 1e-3
+    for s in range(d["lam"].size):
+        lp = d["lam"].copy(); lp[s] += h
+        lm = d["lam"].copy(); lm[s] -= h
+        fd = (run(d, "fp64", lam=lp)["E"] - run(d, "fp64", lam=lm)["E"]) / (2 * h)
+        assert abs(fd - base["dVdl"][s]) <= 1e-9 * max(1.0, abs(base["E"])), (s, fd, base["dVdl"][s])
+
+
+@pytest.mark.parametrize("prec", ["fp64", "f32"])
+def test_deterministic(prec):
+    d = W.random_open(12, n=2000, edge=3.0, depth=3, order=6)
+    a, b = run(d, prec), run(d, prec)
+    assert a["E"] == b["E"]
+    np.testing.assert_array_equal(a["F"], b["F"])
+    np.testing.assert_array_equal(a["phi"], b["phi"])
+    np.testing.assert_array_equal(a["dVdl"], b["dVdl"])
+
+
+def test_lambda_outside_unit_interval_not_clamped():
+    d = W.open_cube()
+    lam = np.linspace(-0.1, 1.1, d["lam"].size)
+    err = errors(run(d, "fp64", lam=lam), reference(d, lam=lam))
+    assert_within(err, d["order"], label="lambda range")
+
+
+def test_coulomb_constant_scaling():
+    d = W.open_cube()
+    a = run(d, "fp64")
+    b = run(d, "fp64", k_e=138.935458)
+    assert b["E"] == pytest.approx(138.935458 * a["E"], rel=1e-13)
+    np.testing.assert_allclose(b["F"], 138.935458 * a["F"], rtol=1e-12, atol=1e-12 * np.abs(b["F"]).max())
+
+
+def test_no_sites_and_tiny_systems():
+    # a single atom, two atoms, no sites
+    for n in (1, 2, 7):
+        d = W.random_open(13, n=n, edge=1.0, n_sites=0, depth=2, order=4)
+        out = run(d, "fp64")
+        ref = reference(d)
+        assert out["E"] == pytest.approx(ref["E"], rel=1e-12, abs=1e-12)
+        np.testing.assert_allclose(out["F"], ref["F"], rtol=1e-10, atol=1e-12)
+        assert out["dVdl"].size == 0
+
+
+def test_all_atoms_in_one_leaf_region():
+    """A dense clump: most leaves empty, one leaf crowded (ragged binning)."""
+    rng = np.random.default_rng(5)
+    d = W.random_open(14, n=600, edge=2.0, depth=3, order=8)
+    x = d["x"].copy()
+    x[:500] = 0.05 + rng.uniform(0, 0.1, (500, 3))
+    d["x"] = x.astype(np.float32).astype(np.float64)
+    err = errors(run(d, "fp64"), reference(d))
+    assert_within(err, 8, label="clump")
+
+
+def test_axis_permutation_symmetry():
+    d = W.tiny_periodic(25, n=250, edge=1.1, n_sites=2, depth=2, order=6)
+    a = run(d, "fp64")
+    d2 = dict(d)
+    d2["x"] = d["x"][:, [1, 2, 0]].copy()
+    b = run(d2, "fp64")
+    assert b["E"] == pytest.approx(a["E"], rel=1e-12)
+    np.testing.assert_allclose(b["F"], a["F"][:, [1, 2, 0]], rtol=1e-9, atol=1e-9 * np.abs(a["F"]).max())
+
+
+def test_check_mode_reports_bad_input():
+    from paper_2410_01626_amd import fmm
+    d = W.random_open(15, n=100, edge=1.0, n_sites=2, depth=2, order=4)
+    d["site"] = d["site"].copy()
+    d["site"][3] = 7
+    with pytest.raises(fmm.FmmError) as e:
+        run(d, "fp64", check=True)
+    assert e.value.status == fmm.FMM_E_SITE
+    d = W.random_open(15, n=100, edge=1.0, n_sites=2, depth=2, order=4)
+    d["qA"] = d["qA"].copy()
+    d["qA"][5] = np.nan
+    with pytest.raises(fmm.FmmError) as e:
+        run(d, "fp64", check=True)
+    assert e.value.status == fmm.FMM_E_NONFINITE
