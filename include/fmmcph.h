@@ -84,7 +84,12 @@ typedef enum { FMM_FP64 = 0, FMM_MIXED_F32 = 1, FMM_MIXED_BF16X3 = 2 } fmm_preci
  *   max_atoms   largest N (per call, summed over replicas for the batched call)
  *   max_sites   largest S (same)
  *   max_replicas largest replica count of fmm_eval_batched (>= 1)
- *   check       1 = run the device-side input checks described above */
+ *   check       1 = run the device-side input checks described above
+ *   m2l_kernel  0 = automatic, 1 = plain (vector ALU) M2L, 2 = matrix-core M2L
+ *               (available for p <= 10; FP64 needs p <= 8)
+ *   m2l_chunk   offsets per matrix-core M2L work-group (0 = automatic, else 1..189)
+ *   p2p_waves   reserved tuning knob of the near-field kernel (0 = automatic)
+ *   reserved    must be 0 */
 typedef struct {
     int32_t depth;
     int32_t order_p;
@@ -95,6 +100,10 @@ typedef struct {
     int64_t max_sites;
     int32_t max_replicas;
     int32_t check;
+    int32_t m2l_kernel;
+    int32_t m2l_chunk;
+    int32_t p2p_waves;
+    int32_t reserved;
 } fmm_params;
 
 /* Create a plan on the current HIP device.  hip_stream is a hipStream_t (NULL =

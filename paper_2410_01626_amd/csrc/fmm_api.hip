@@ -41,6 +41,15 @@ struct fmm_plan_s {
     int32_t* status = nullptr;
     void *F_tmp = nullptr, *phi_tmp = nullptr;
     double* dVdl_tmp = nullptr;
+    // matrix-core M2L
+    int m2l_mode = 0;  // 0 plain, 1 f32, 2 f64, 3 bf16x3
+    fmmk::M2LGeom mg{};
+    int m2l_rt = 0;
+    size_t m2l_lds = 0;
+    int64_t n_tasks = 0;
+    fmmk::M2LTask* tasks = nullptr;
+    int16_t* olist = nullptr;
+    void *bank_mma = nullptr, *bank_mma_lo = nullptr, *m2l_part = nullptr;
     std::vector<void*> allocs;
     std::string err;
     // per-phase timing (fmm_profile): events recorded at phase boundaries
@@ -92,6 +101,52 @@ void init_rho_coef() {
     (void)hipMemcpyToSymbol(HIP_SYMBOL(fmmk::c_rho), &rc, sizeof(rc));
 }
 
+// Offset list of every child class: o = t - s for the children s of the
+// parent's 27 neighbours that are not adjacent to t, in a fixed order.
+std::vector<int16_t> class_offsets() {
+    std::vector<int16_t> out;
+    for (int c = 0; c < 8; ++c) {
+        const int tb[3] = {(c >> 2) & 1, (c >> 1) & 1, c & 1};
+        int cnt = 0;
+        for (int nb = 0; nb < 216; ++nb) {
+            const int dp[3] = {nb / 72 - 1, (nb / 24) % 3 - 1, (nb / 8) % 3 - 1};
+            const int cb[3] = {(nb >> 2) & 1, (nb >> 1) & 1, nb & 1};
+            int o[3];
+            for (int a = 0; a < 3; ++a) o[a] = tb[a] - 2 * dp[a] - cb[a];
+            if (std::abs(o[0]) <= 1 && std::abs(o[1]) <= 1 && std::abs(o[2]) <= 1) continue;
+            out.push_back((int16_t)(((o[0] + 3) * 7 + (o[1] + 3)) * 7 + (o[2] + 3)));
+            ++cnt;
+        }
+        if (cnt != 189) return {};
+    }
+    return out;
+}
+
+uint16_t to_bf16(float f) {  // round to nearest even
+    uint32_t u;
+    std::memcpy(&u, &f, 4);
+    if ((u & 0x7f800000u) == 0x7f800000u) return (uint16_t)(u >> 16);
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+float from_bf16(uint16_t h) {
+    uint32_t u = (uint32_t)h << 16;
+    float f;
+    std::memcpy(&f, &u, 4);
+    return f;
+}
+
+int round_up(int v, int m) { return (v + m - 1) / m * m; }
+
+// LDS row stride (elements) of a matrix-core operand: f32 rows are padded to
+// 2 mod 32 words (16-lane groups reading 4 consecutive k hit distinct banks),
+// f64 rows to an odd number of elements, bf16 rows to 8 mod 64 elements.
+int lds_stride(int mode, int kp) {
+    if (mode == 1) { int s = kp; while (s % 32 != 2) ++s; return s; }
+    if (mode == 2) return kp | 1;
+    int s = kp; while (s % 64 != 40 && s % 64 != 8) s += 8; return s;
+}
+
 Geo make_geo(const fmm_plan_s* p) {
     Geo g{};
     g.depth = p->prm.depth;
@@ -120,6 +175,53 @@ void mark(fmm_plan_t P, int phase) {
 }
 
 inline unsigned nblocks(int64_t n, int b) { return (unsigned)std::max<int64_t>(1, (n + b - 1) / b); }
+
+// Matrix-core M2L launch: the kernel instance for the plan's precision and row
+// tile count, then the fixed-order chunk reduction.
+template <typename T>
+void launch_m2l_mma(fmm_plan_t P, const Geo& g) {
+    using namespace fmmk;
+    hipStream_t st = P->stream;
+    const M2LGeom mg = P->mg;
+    const unsigned nt = (unsigned)P->n_tasks;
+    const size_t lds = P->m2l_lds;
+    T* loc = (T*)P->loc;
+    T* part = (T*)P->m2l_part;
+    const T* mult = (const T*)P->mult;
+    switch (P->m2l_mode * 16 + P->m2l_rt) {
+#define FMM_M2L_F32(RTV)                                                                    \
+    case 16 + RTV:                                                                          \
+        k_m2l_f32<RTV><<<nt, 256, lds, st>>>(g, mg, P->tasks, P->olist, (const float*)mult, \
+                                             (const float*)P->bank_mma, (float*)loc,         \
+                                             (float*)part);                                  \
+        break;
+#define FMM_M2L_F64(RTV)                                                                      \
+    case 32 + RTV:                                                                            \
+        k_m2l_f64<RTV><<<nt, 256, lds, st>>>(g, mg, P->tasks, P->olist, (const double*)mult, \
+                                             (const double*)P->bank_mma, (double*)loc,         \
+                                             (double*)part);                                   \
+        break;
+#define FMM_M2L_BF(RTV)                                                                         \
+    case 48 + RTV:                                                                              \
+        k_m2l_bf16x3<RTV><<<nt, 256, lds, st>>>(g, mg, P->tasks, P->olist, (const float*)mult, \
+                                                (const __bf16*)P->bank_mma,                     \
+                                                (const __bf16*)P->bank_mma_lo, (float*)loc,     \
+                                                (float*)part);                                  \
+        break;
+        FMM_M2L_F32(1) FMM_M2L_F32(2) FMM_M2L_F32(3) FMM_M2L_F32(4)
+        FMM_M2L_F32(5) FMM_M2L_F32(6) FMM_M2L_F32(7) FMM_M2L_F32(8)
+        FMM_M2L_F64(1) FMM_M2L_F64(2) FMM_M2L_F64(3) FMM_M2L_F64(4)
+        FMM_M2L_F64(5) FMM_M2L_F64(6)
+        FMM_M2L_BF(1) FMM_M2L_BF(2) FMM_M2L_BF(3) FMM_M2L_BF(4)
+        FMM_M2L_BF(5) FMM_M2L_BF(6) FMM_M2L_BF(7) FMM_M2L_BF(8)
+        default: break;
+    }
+    if (mg.nchunk > 1) {
+        const int64_t tot = mg.nt_all * g.Kp;
+        const unsigned nb = (unsigned)std::min<int64_t>(4096, (tot + 255) / 256);
+        k_m2l_reduce<T><<<nb, 256, 0, st>>>(g, mg, part, loc);
+    }
+}
 
 // Enqueue one single-system evaluation (arguments already validated).
 template <typename T>
@@ -173,9 +275,13 @@ fmm_status enqueue_eval(fmm_plan_t P, int64_t n, const T* x, const T* qA, const 
                                      P->dom);
     mark(P, 4);
     if (g.depth >= g.lmin) {
-        int64_t nt = 0;
-        for (int l = g.lmin; l <= g.depth; ++l) nt += (int64_t)1 << (3 * l);
-        k_m2l_plain<T><<<(unsigned)nt, 256, 0, st>>>(g, mult, (const T*)P->bankT, loc);
+        if (P->m2l_mode == 0) {
+            int64_t nt = 0;
+            for (int l = g.lmin; l <= g.depth; ++l) nt += (int64_t)1 << (3 * l);
+            k_m2l_plain<T><<<(unsigned)nt, 256, 0, st>>>(g, mult, (const T*)P->bankT, loc);
+        } else {
+            launch_m2l_mma<T>(P, g);
+        }
     }
     // downward pass: children at lev + 1 from parents at lev
     mark(P, 5);
@@ -240,8 +346,15 @@ fmm_status fmm_plan_create(const fmm_params* prm, void* hip_stream, fmm_plan_t* 
         prm->max_replicas < 1 || (prm->boundary != FMM_OPEN && prm->boundary != FMM_PERIODIC) ||
         (prm->precision != FMM_FP64 && prm->precision != FMM_MIXED_F32 &&
          prm->precision != FMM_MIXED_BF16X3) ||
-        !std::isfinite(prm->coulomb_k) || prm->max_atoms > INT32_MAX)
+        !std::isfinite(prm->coulomb_k) || prm->max_atoms > INT32_MAX ||
+        prm->m2l_kernel < 0 || prm->m2l_kernel > 2 || prm->m2l_chunk < 0 || prm->m2l_chunk > 189 ||
+        prm->p2p_waves < 0 || prm->reserved != 0)
         return FMM_E_INVALID;
+    {
+        const int K = (prm->order_p + 1) * (prm->order_p + 1);
+        const bool mma_ok = K <= 16 * fmmk::kM2LMaxRT && (prm->precision != FMM_FP64 || K <= 96);
+        if (prm->m2l_kernel == 2 && !mma_ok) return FMM_E_INVALID;
+    }
     fmm_plan_s* P = new fmm_plan_s();
     P->prm = *prm;
     P->stream = (hipStream_t)hip_stream;
@@ -333,6 +446,109 @@ fmm_status fmm_plan_create(const fmm_params* prm, void* hip_stream, fmm_plan_t* 
     auto lt = transpose_blocks<double>(lat, 1, K);
     up(P->latT, lt.data(), lt.size() * 8);
     up(P->gidx, gi.data(), gi.size() * 4);
+    // matrix-core M2L: mode, tile geometry, offset lists, task list, banks
+    {
+        const int lmin = prm->boundary == FMM_PERIODIC ? 1 : 2;
+        const bool mma_ok = (int)K <= 16 * fmmk::kM2LMaxRT && (!P->fp64 || K <= 96);
+        if (d >= lmin && mma_ok && prm->m2l_kernel != 1)
+            P->m2l_mode = P->fp64 ? 2 : (prm->precision == FMM_MIXED_BF16X3 ? 3 : 1);
+    }
+    if (P->m2l_mode && e == hipSuccess) {
+        fmmk::M2LGeom& mg = P->mg;
+        const int lmin = prm->boundary == FMM_PERIODIC ? 1 : 2;
+        mg.RP = round_up((int)K, 16);
+        mg.KP = round_up((int)K, P->m2l_mode == 3 ? 32 : 4);
+        mg.SA = lds_stride(P->m2l_mode, mg.KP);
+        mg.SB = mg.SA;
+        P->m2l_rt = mg.RP / 16;
+        int64_t items = 0, nt_all = 0;
+        for (int l = lmin; l <= d; ++l) {
+            const int64_t ntc = (int64_t)1 << (3 * (l - 1));
+            items += 8 * ((ntc + fmmk::kM2LTile - 1) / fmmk::kM2LTile);
+            nt_all += (int64_t)1 << (3 * l);
+        }
+        int csize = prm->m2l_chunk;
+        if (csize == 0) {
+            const int64_t want = std::max<int64_t>(1, std::min<int64_t>(27, (2048 + items - 1) / items));
+            csize = (int)((189 + want - 1) / want);
+        }
+        mg.csize = csize;
+        mg.nchunk = (189 + csize - 1) / csize;
+        mg.nt_all = nt_all;
+        std::vector<fmmk::M2LTask> tl;
+        for (int l = lmin; l <= d; ++l) {
+            const int64_t ntc = (int64_t)1 << (3 * (l - 1));
+            const int ntile = (int)((ntc + fmmk::kM2LTile - 1) / fmmk::kM2LTile);
+            for (int c = 0; c < 8; ++c)
+                for (int t = 0; t < ntile; ++t)
+                    for (int ch = 0; ch < mg.nchunk; ++ch) tl.push_back({l, c, t, ch});
+        }
+        P->n_tasks = (int64_t)tl.size();
+        const size_t esz = P->m2l_mode == 2 ? 8 : (P->m2l_mode == 1 ? 4 : 2);
+        P->m2l_lds = esz * ((size_t)mg.RP * mg.SA + (size_t)fmmk::kM2LTile * mg.SB) *
+                     (P->m2l_mode == 3 ? 2 : 1);
+        std::vector<int16_t> ol = class_offsets();
+        bool ok2 = !ol.empty();
+        ok2 &= dev_alloc(P, (void**)&P->tasks, tl.size() * sizeof(fmmk::M2LTask));
+        ok2 &= dev_alloc(P, (void**)&P->olist, ol.size() * sizeof(int16_t));
+        const size_t nb = (size_t)343 * mg.RP * mg.KP;
+        ok2 &= dev_alloc(P, &P->bank_mma, nb * esz);
+        if (P->m2l_mode == 3) ok2 &= dev_alloc(P, &P->bank_mma_lo, nb * esz);
+        if (mg.nchunk > 1)
+            ok2 &= dev_alloc(P, &P->m2l_part, (size_t)mg.nchunk * nt_all * P->Kp * P->tsz);
+        if (!ok2) {
+            fmm_plan_destroy(P);
+            return FMM_E_OOM;
+        }
+        up(P->tasks, tl.data(), tl.size() * sizeof(fmmk::M2LTask));
+        up(P->olist, ol.data(), ol.size() * sizeof(int16_t));
+        if (P->m2l_mode == 2) {
+            std::vector<double> bm(nb, 0.0);
+            for (int o = 0; o < 343; ++o)
+                for (size_t r = 0; r < K; ++r)
+                    for (size_t k = 0; k < K; ++k)
+                        bm[((size_t)o * mg.RP + r) * mg.KP + k] = bank[((size_t)o * K + r) * K + k];
+            up(P->bank_mma, bm.data(), nb * 8);
+        } else if (P->m2l_mode == 1) {
+            std::vector<float> bm(nb, 0.f);
+            for (int o = 0; o < 343; ++o)
+                for (size_t r = 0; r < K; ++r)
+                    for (size_t k = 0; k < K; ++k)
+                        bm[((size_t)o * mg.RP + r) * mg.KP + k] = (float)bank[((size_t)o * K + r) * K + k];
+            up(P->bank_mma, bm.data(), nb * 4);
+        } else {
+            std::vector<uint16_t> hi(nb, 0), lo(nb, 0);
+            for (int o = 0; o < 343; ++o)
+                for (size_t r = 0; r < K; ++r)
+                    for (size_t k = 0; k < K; ++k) {
+                        const double v = bank[((size_t)o * K + r) * K + k];
+                        const uint16_t h = to_bf16((float)v);
+                        const size_t idx = ((size_t)o * mg.RP + r) * mg.KP + k;
+                        hi[idx] = h;
+                        lo[idx] = to_bf16((float)(v - (double)from_bf16(h)));
+                    }
+            up(P->bank_mma, hi.data(), nb * 2);
+            up(P->bank_mma_lo, lo.data(), nb * 2);
+        }
+        hipError_t ea = hipSuccess;
+        auto setlds = [&](const void* fn) {
+            if (ea == hipSuccess)
+                ea = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)P->m2l_lds);
+        };
+        switch (P->m2l_mode * 16 + P->m2l_rt) {
+#define FMM_LDS_CASE(MODE, RTV, KER) \
+    case MODE * 16 + RTV: setlds((const void*)&KER<RTV>); break;
+#define FMM_LDS_ALL(MODE, KER) \
+    FMM_LDS_CASE(MODE, 1, KER) FMM_LDS_CASE(MODE, 2, KER) FMM_LDS_CASE(MODE, 3, KER) \
+    FMM_LDS_CASE(MODE, 4, KER) FMM_LDS_CASE(MODE, 5, KER) FMM_LDS_CASE(MODE, 6, KER) \
+    FMM_LDS_CASE(MODE, 7, KER) FMM_LDS_CASE(MODE, 8, KER)
+            FMM_LDS_ALL(1, fmmk::k_m2l_f32)
+            FMM_LDS_ALL(2, fmmk::k_m2l_f64)
+            FMM_LDS_ALL(3, fmmk::k_m2l_bf16x3)
+            default: break;
+        }
+        if (ea != hipSuccess) e = ea;
+    }
     std::vector<double> dom0(8, 0.0);
     up(P->dom, dom0.data(), 64);
     int32_t z[4] = {0, 0, 0, 0};

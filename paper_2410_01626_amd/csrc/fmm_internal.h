@@ -38,3 +38,17 @@ struct Geo {
 };
 
 }  // namespace fmmk
+
+namespace fmmk {
+
+// Matrix-core M2L: work items and tile sizes.
+constexpr int kM2LTile = 64;    // targets per work-group (4 wavefronts x 16 columns)
+constexpr int kM2LMaxRT = 8;    // row tiles of 16: K <= 128 (p <= 10)
+
+// One M2L work item: level, child class (4 bx + 2 by + bz), target tile of
+// that class and chunk of the class's 189-entry offset list.
+struct M2LTask {
+    int32_t lev, cls, tile, chunk;
+};
+
+}  // namespace fmmk

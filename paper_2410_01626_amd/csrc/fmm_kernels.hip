@@ -511,6 +511,273 @@ __global__ __launch_bounds__(256) void k_m2l_plain(Geo g, const T* __restrict__ 
     if (r < g.K) loc[(size_t)(g.lev_off[lev] + bidx) * g.Kp + r] = acc;
 }
 
+// ------------------------------------------------------------------ M2L on matrix cores
+//
+// For one tree level, the targets that share a child class (position inside
+// their parent) share the same 189 translation offsets, so for every offset o
+// the class does lambda~[:, T] += T(o) mu~[:, T - o]: a dense (K x K) x (K x 64)
+// product.  A work-group takes one (level, class, 64-target tile, offset
+// chunk); per offset it stages T(o) and the 64 gathered source expansions in
+// LDS (k contiguous) and each wavefront multiplies one 16-target column tile
+// on the matrix cores, all row tiles, accumulating in registers across the
+// chunk.  Chunks write partial sums that k_m2l_reduce adds in a fixed order.
+//
+// Policies:
+//   F32    v_mfma_f32_16x16x4_f32   A lane l: A[l%16][l/16], B: B[l/16][l%16]
+//   F64    v_mfma_f64_16x16x4_f64   same inputs, output D[4v + l/16][l%16]
+//   BF16X3 v_mfma_f32_16x16x32_bf16 A lane l: A[l%16][8(l/16)+e], B: B[8(l/16)+e][l%16];
+//          T = Th + Tl, mu = mh + ml (bf16 parts), product Th mh + Th ml + Tl mh
+// FP32 and BF16 outputs: lane l holds D[4(l/16) + v][l%16].
+
+typedef float mf4 __attribute__((ext_vector_type(4)));
+typedef double md4 __attribute__((ext_vector_type(4)));
+typedef __bf16 mbf8 __attribute__((ext_vector_type(8)));
+
+struct M2LGeom {
+    int32_t RP;      // output rows padded to 16
+    int32_t KP;      // contraction length padded (4 for f32/f64, 32 for bf16)
+    int32_t SA;      // LDS row stride of the operator (elements)
+    int32_t SB;      // LDS row stride of the sources (elements)
+    int32_t nchunk;  // offset chunks
+    int32_t csize;   // offsets per chunk
+    int64_t nt_all;  // boxes at levels >= lmin (partial-buffer stride)
+};
+
+// Decode the target column j of a work item into its box at level lev.
+__device__ __forceinline__ bool m2l_target(int lev, int cls, int tile, int j, int& tx, int& ty,
+                                           int& tz) {
+    const int half = lev >= 1 ? (1 << (lev - 1)) : 1;
+    const int ntc = half * half * half;
+    const int u = tile * kM2LTile + j;
+    if (u >= ntc) return false;
+    const int ux = u / (half * half), uy = (u / half) % half, uz = u % half;
+    tx = 2 * ux + ((cls >> 2) & 1);
+    ty = 2 * uy + ((cls >> 1) & 1);
+    tz = 2 * uz + (cls & 1);
+    return true;
+}
+
+// Stage the 64 source expansions of offset o (bank index oi) into LDS as
+// B[j][k] (k contiguous); missing sources (outside an open domain, or beyond
+// the class) are zero.  Returns nothing; caller synchronises.
+template <typename TS, typename TL>
+__device__ __forceinline__ void m2l_stage_sources(const Geo& g, const M2LGeom& mg, int lev, int cls,
+                                                  int tile, int oi, const TS* __restrict__ mult,
+                                                  TL* __restrict__ Bh, TL* __restrict__ Bl) {
+    const int n = 1 << lev;
+    const int ox = oi / 49 - 3, oy = (oi / 7) % 7 - 3, oz = oi % 7 - 3;
+    const int tot = kM2LTile * mg.KP;
+    for (int e = threadIdx.x; e < tot; e += blockDim.x) {
+        const int j = e / mg.KP, k = e % mg.KP;
+        float v = 0.f;
+        double vd = 0.0;
+        int tx, ty, tz;
+        if (k < g.K && m2l_target(lev, cls, tile, j, tx, ty, tz)) {
+            int sx = tx - ox, sy = ty - oy, sz = tz - oz;
+            bool ok = true;
+            if (g.periodic) {
+                sx = (sx % n + n) % n;
+                sy = (sy % n + n) % n;
+                sz = (sz % n + n) % n;
+            } else {
+                ok = sx >= 0 && sy >= 0 && sz >= 0 && sx < n && sy < n && sz < n;
+            }
+            if (ok) {
+                const TS m = mult[(size_t)(g.lev_off[lev] + morton(sx, sy, sz)) * g.Kp + k];
+                vd = (double)m;
+                v = (float)m;
+            }
+        }
+        if constexpr (sizeof(TL) == 2) {
+            const __bf16 hi = (__bf16)v;
+            Bh[j * mg.SB + k] = hi;
+            Bl[j * mg.SB + k] = (__bf16)(v - (float)hi);
+        } else if constexpr (sizeof(TL) == 4) {
+            Bh[j * mg.SB + k] = v;
+        } else {
+            Bh[j * mg.SB + k] = vd;
+        }
+    }
+}
+
+// Copy operator block oi (rows RP x KP, row-major, zero padded) into LDS rows
+// of stride SA.
+template <typename TL>
+__device__ __forceinline__ void m2l_stage_op(const M2LGeom& mg, const TL* __restrict__ bank, int oi,
+                                             TL* __restrict__ A) {
+    const TL* src = bank + (size_t)oi * mg.RP * mg.KP;
+    const int tot = mg.RP * mg.KP;
+    for (int e = threadIdx.x; e < tot; e += blockDim.x) {
+        const int r = e / mg.KP, k = e % mg.KP;
+        A[r * mg.SA + k] = src[e];
+    }
+}
+
+// Write the accumulator of row tile rt, lane layout given by `f64layout`.
+template <typename TA, typename TO>
+__device__ __forceinline__ void m2l_store(const Geo& g, const M2LGeom& mg, int lev, int cls, int tile,
+                                          int chunk, int wave, int lane, int rt, const TA& acc,
+                                          bool f64layout, TO* __restrict__ loc,
+                                          TO* __restrict__ part) {
+    const int j = 16 * wave + (lane & 15);
+    int tx, ty, tz;
+    if (!m2l_target(lev, cls, tile, j, tx, ty, tz)) return;
+    const int64_t box = g.lev_off[lev] + morton(tx, ty, tz);
+    TO* dst;
+    if (mg.nchunk == 1) dst = loc + (size_t)box * g.Kp;
+    else dst = part + ((size_t)chunk * mg.nt_all + (box - g.lev_off[g.lmin])) * g.Kp;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+        const int r = 16 * rt + (f64layout ? 4 * v + (lane >> 4) : 4 * (lane >> 4) + v);
+        if (r < g.K) dst[r] = (TO)acc[v];
+    }
+}
+
+template <int RT>
+__global__ __launch_bounds__(256) void k_m2l_f32(Geo g, M2LGeom mg, const M2LTask* __restrict__ tasks,
+                                                 const int16_t* __restrict__ olist,
+                                                 const float* __restrict__ mult,
+                                                 const float* __restrict__ bank,
+                                                 float* __restrict__ loc, float* __restrict__ part) {
+    extern __shared__ float lds_f32[];
+    float* A = lds_f32;
+    float* B = lds_f32 + mg.RP * mg.SA;
+    const M2LTask tk = tasks[blockIdx.x];
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int half = tk.lev >= 1 ? (1 << (tk.lev - 1)) : 1;
+    const bool active = tk.tile * kM2LTile + 16 * wave < half * half * half;
+    mf4 acc[RT];
+#pragma unroll
+    for (int r = 0; r < RT; ++r) acc[r] = mf4{0.f, 0.f, 0.f, 0.f};
+    const int o0 = tk.chunk * mg.csize, o1 = min(o0 + mg.csize, 189);
+    for (int oc = o0; oc < o1; ++oc) {
+        const int oi = olist[tk.cls * 189 + oc];
+        __syncthreads();
+        m2l_stage_op<float>(mg, bank, oi, A);
+        m2l_stage_sources<float, float>(g, mg, tk.lev, tk.cls, tk.tile, oi, mult, B, nullptr);
+        __syncthreads();
+        if (!active) continue;
+        const float* Bw = B + (16 * wave + (lane & 15)) * mg.SB + (lane >> 4);
+        const float* Aw = A + (lane & 15) * mg.SA + (lane >> 4);
+        for (int ks = 0; ks < mg.KP; ks += 4) {
+            const float b = Bw[ks];
+#pragma unroll
+            for (int r = 0; r < RT; ++r)
+                acc[r] = __builtin_amdgcn_mfma_f32_16x16x4f32(Aw[16 * r * mg.SA + ks], b, acc[r], 0, 0, 0);
+        }
+    }
+    if (!active) return;
+#pragma unroll
+    for (int r = 0; r < RT; ++r)
+        m2l_store<mf4, float>(g, mg, tk.lev, tk.cls, tk.tile, tk.chunk, wave, lane, r, acc[r], false,
+                              loc, part);
+}
+
+template <int RT>
+__global__ __launch_bounds__(256) void k_m2l_f64(Geo g, M2LGeom mg, const M2LTask* __restrict__ tasks,
+                                                 const int16_t* __restrict__ olist,
+                                                 const double* __restrict__ mult,
+                                                 const double* __restrict__ bank,
+                                                 double* __restrict__ loc, double* __restrict__ part) {
+    extern __shared__ double lds_f64[];
+    double* A = lds_f64;
+    double* B = lds_f64 + mg.RP * mg.SA;
+    const M2LTask tk = tasks[blockIdx.x];
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int half = tk.lev >= 1 ? (1 << (tk.lev - 1)) : 1;
+    const bool active = tk.tile * kM2LTile + 16 * wave < half * half * half;
+    md4 acc[RT];
+#pragma unroll
+    for (int r = 0; r < RT; ++r) acc[r] = md4{0.0, 0.0, 0.0, 0.0};
+    const int o0 = tk.chunk * mg.csize, o1 = min(o0 + mg.csize, 189);
+    for (int oc = o0; oc < o1; ++oc) {
+        const int oi = olist[tk.cls * 189 + oc];
+        __syncthreads();
+        m2l_stage_op<double>(mg, bank, oi, A);
+        m2l_stage_sources<double, double>(g, mg, tk.lev, tk.cls, tk.tile, oi, mult, B, nullptr);
+        __syncthreads();
+        if (!active) continue;
+        const double* Bw = B + (16 * wave + (lane & 15)) * mg.SB + (lane >> 4);
+        const double* Aw = A + (lane & 15) * mg.SA + (lane >> 4);
+        for (int ks = 0; ks < mg.KP; ks += 4) {
+            const double b = Bw[ks];
+#pragma unroll
+            for (int r = 0; r < RT; ++r)
+                acc[r] = __builtin_amdgcn_mfma_f64_16x16x4f64(Aw[16 * r * mg.SA + ks], b, acc[r], 0, 0, 0);
+        }
+    }
+    if (!active) return;
+#pragma unroll
+    for (int r = 0; r < RT; ++r)
+        m2l_store<md4, double>(g, mg, tk.lev, tk.cls, tk.tile, tk.chunk, wave, lane, r, acc[r], true,
+                               loc, part);
+}
+
+template <int RT>
+__global__ __launch_bounds__(256) void k_m2l_bf16x3(Geo g, M2LGeom mg,
+                                                    const M2LTask* __restrict__ tasks,
+                                                    const int16_t* __restrict__ olist,
+                                                    const float* __restrict__ mult,
+                                                    const __bf16* __restrict__ bank_hi,
+                                                    const __bf16* __restrict__ bank_lo,
+                                                    float* __restrict__ loc, float* __restrict__ part) {
+    extern __shared__ __bf16 lds_bf[];
+    __bf16* Ah = lds_bf;
+    __bf16* Al = Ah + mg.RP * mg.SA;
+    __bf16* Bh = Al + mg.RP * mg.SA;
+    __bf16* Bl = Bh + kM2LTile * mg.SB;
+    const M2LTask tk = tasks[blockIdx.x];
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int half = tk.lev >= 1 ? (1 << (tk.lev - 1)) : 1;
+    const bool active = tk.tile * kM2LTile + 16 * wave < half * half * half;
+    mf4 acc[RT];
+#pragma unroll
+    for (int r = 0; r < RT; ++r) acc[r] = mf4{0.f, 0.f, 0.f, 0.f};
+    const int o0 = tk.chunk * mg.csize, o1 = min(o0 + mg.csize, 189);
+    for (int oc = o0; oc < o1; ++oc) {
+        const int oi = olist[tk.cls * 189 + oc];
+        __syncthreads();
+        m2l_stage_op<__bf16>(mg, bank_hi, oi, Ah);
+        m2l_stage_op<__bf16>(mg, bank_lo, oi, Al);
+        m2l_stage_sources<float, __bf16>(g, mg, tk.lev, tk.cls, tk.tile, oi, mult, Bh, Bl);
+        __syncthreads();
+        if (!active) continue;
+        const int boff = (16 * wave + (lane & 15)) * mg.SB + 8 * (lane >> 4);
+        const int aoff = (lane & 15) * mg.SA + 8 * (lane >> 4);
+        for (int ks = 0; ks < mg.KP; ks += 32) {
+            const mbf8 bh = *(const mbf8*)(Bh + boff + ks);
+            const mbf8 bl = *(const mbf8*)(Bl + boff + ks);
+#pragma unroll
+            for (int r = 0; r < RT; ++r) {
+                const mbf8 ah = *(const mbf8*)(Ah + aoff + 16 * r * mg.SA + ks);
+                const mbf8 al = *(const mbf8*)(Al + aoff + 16 * r * mg.SA + ks);
+                acc[r] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh, acc[r], 0, 0, 0);
+                acc[r] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl, acc[r], 0, 0, 0);
+                acc[r] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh, acc[r], 0, 0, 0);
+            }
+        }
+    }
+    if (!active) return;
+#pragma unroll
+    for (int r = 0; r < RT; ++r)
+        m2l_store<mf4, float>(g, mg, tk.lev, tk.cls, tk.tile, tk.chunk, wave, lane, r, acc[r], false,
+                              loc, part);
+}
+
+// Sum the offset-chunk partials into the local expansions (fixed chunk order).
+template <typename T>
+__global__ __launch_bounds__(256) void k_m2l_reduce(Geo g, M2LGeom mg, const T* __restrict__ part,
+                                                    T* __restrict__ loc) {
+    const int64_t tot = mg.nt_all * g.Kp;
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < tot;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        if ((int)(e % g.Kp) >= g.K) continue;
+        T s = T(0);
+        for (int c = 0; c < mg.nchunk; ++c) s += part[(size_t)c * tot + e];
+        loc[(size_t)g.lev_off[g.lmin] * g.Kp + e] = s;
+    }
+}
+
 // ------------------------------------------------------------------ downward pass
 
 // L2L into the children at level lev + 1 from their parents at level lev:

@@ -44,6 +44,10 @@ class fmm_params(ctypes.Structure):
         ("max_sites", ctypes.c_int64),
         ("max_replicas", ctypes.c_int32),
         ("check", ctypes.c_int32),
+        ("m2l_kernel", ctypes.c_int32),
+        ("m2l_chunk", ctypes.c_int32),
+        ("p2p_waves", ctypes.c_int32),
+        ("reserved", ctypes.c_int32),
     ]
 
 
@@ -171,7 +175,8 @@ class Plan:
     def __init__(self, depth: int, order: int, periodic: bool = False,
                  precision: str = "fp64", coulomb_k: float = 1.0, max_atoms: int = 1,
                  max_sites: int = 1, max_replicas: int = 1, check: bool = False,
-                 stream=None, device=None):
+                 stream=None, device=None, m2l_kernel: int = 0, m2l_chunk: int = 0,
+                 p2p_waves: int = 0):
         import torch
         dev = torch.device(device) if device is not None else torch.device("cuda")
         if dev.type == "cuda" and dev.index is None:
@@ -182,7 +187,8 @@ class Plan:
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
         self.params = fmm_params(depth, order, FMM_PERIODIC if periodic else FMM_OPEN,
                                  PRECISIONS[precision], float(coulomb_k), int(max_atoms),
-                                 int(max_sites), int(max_replicas), 1 if check else 0)
+                                 int(max_sites), int(max_replicas), 1 if check else 0,
+                                 int(m2l_kernel), int(m2l_chunk), int(p2p_waves), 0)
         self.periodic = periodic
         self.precision = precision
         self.dtype = torch.float64 if precision == "fp64" else torch.float32

@@ -16,7 +16,7 @@ TOL_F = {1: 0.3, 2: 6e-2, 3: 3e-2, 4: 1.5e-2, 5: 6e-3, 6: 3e-3, 7: 1.2e-3, 8: 5e
 
 
 def run(d, precision="fp64", depth=None, order=None, k_e=1.0, lam=None, device="cuda:0",
-        check=False):
+        check=False, **plan_kw):
     import torch
     from paper_2410_01626_amd import fmm
     dev = torch.device(device)
@@ -25,7 +25,8 @@ def run(d, precision="fp64", depth=None, order=None, k_e=1.0, lam=None, device="
     S = lam.size
     plan = fmm.Plan(d["depth"] if depth is None else depth, d["order"] if order is None else order,
                     periodic=d["periodic"], precision=precision, coulomb_k=k_e,
-                    max_atoms=max(n, 1), max_sites=max(S, 1), check=check, device=dev)
+                    max_atoms=max(n, 1), max_sites=max(S, 1), check=check, device=dev,
+                    **plan_kw)
     dt = plan.dtype
     x = torch.tensor(d["x"], dtype=dt, device=dev)
     qA = torch.tensor(d["qA"], dtype=dt, device=dev)

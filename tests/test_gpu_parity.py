@@ -23,7 +23,7 @@ def test_open_shallow_tree_is_direct_sum(depth, prec, tol):
 
 # ---------------------------------------------------------------- open boundaries
 
-@pytest.mark.parametrize("prec", ["fp64", "f32"])
+@pytest.mark.parametrize("prec", ["fp64", "f32", "bf16x3"])
 def test_open_cube(prec):
     d = W.open_cube()
     out = run(d, prec)
@@ -53,7 +53,7 @@ def test_open_depths(depth):
 # ---------------------------------------------------------------- periodic
 
 @pytest.mark.parametrize("depth", [0, 1, 2, 3])
-@pytest.mark.parametrize("prec", ["fp64", "f32"])
+@pytest.mark.parametrize("prec", ["fp64", "f32", "bf16x3"])
 def test_periodic_small(depth, prec):
     d = W.tiny_periodic(21, n=400, edge=1.6, n_sites=4, depth=depth, order=8)
     err = errors(run(d, prec), reference(d))
@@ -84,7 +84,7 @@ def test_periodic_error_decays_with_order():
     assert errs[-1] < 2e-6 and all(b < a for a, b in zip(errs, errs[1:])), errs
 
 
-@pytest.mark.parametrize("prec", ["fp64", "f32"])
+@pytest.mark.parametrize("prec", ["fp64", "f32", "bf16x3"])
 def test_water_box_full_size(prec):
     """30,000-atom periodic water box at depth 3, p = 8: every output element
     against the full Ewald oracle."""
@@ -183,3 +183,39 @@ def test_check_mode_reports_bad_input():
     with pytest.raises(fmm.FmmError) as e:
         run(d, "fp64", check=True)
     assert e.value.status == fmm.FMM_E_NONFINITE
+
+
+# ---------------------------------------------------------------- matrix-core M2L
+
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-12), ("f32", 2e-6), ("bf16x3", 2e-5)])
+@pytest.mark.parametrize("periodic", [False, True])
+def test_matrix_core_m2l_matches_plain(prec, tol, periodic):
+    """The matrix-core M2L (FP64 / FP32 / bf16 three-product) and the plain
+    vector-ALU M2L compute the same translations; compare complete outputs."""
+    if periodic:
+        d = W.tiny_periodic(31, n=3000, edge=2.4, n_sites=4, depth=3, order=8)
+    else:
+        d = W.random_open(32, n=3000, edge=2.4, n_sites=4, depth=3, order=8)
+    a = run(d, "fp64" if prec == "fp64" else "f32", m2l_kernel=1)
+    b = run(d, prec, m2l_kernel=2)
+    eF = np.sqrt(np.sum((a["F"] - b["F"]) ** 2) / np.sum(a["F"] ** 2))
+    ep = np.sqrt(np.sum((a["phi"] - b["phi"]) ** 2) / np.sum(a["phi"] ** 2))
+    assert eF <= tol and ep <= tol, (eF, ep)
+
+
+@pytest.mark.parametrize("order", [2, 4, 6, 10])
+def test_matrix_core_m2l_orders(order):
+    d = W.tiny_periodic(33, n=1500, edge=2.0, n_sites=3, depth=2, order=order)
+    ref = reference(d)
+    for prec in ("f32", "bf16x3"):
+        assert_within(errors(run(d, prec, m2l_kernel=2), ref), order, label=prec)
+
+
+@pytest.mark.parametrize("chunk", [1, 7, 50, 189])
+def test_m2l_offset_chunking_invariant(chunk):
+    """Splitting the 189 offsets over work-groups only regroups a fixed-order sum."""
+    d = W.tiny_periodic(34, n=2000, edge=2.0, n_sites=3, depth=3, order=6)
+    a = run(d, "fp64", m2l_kernel=2, m2l_chunk=189)
+    b = run(d, "fp64", m2l_kernel=2, m2l_chunk=chunk)
+    np.testing.assert_allclose(b["phi"], a["phi"], rtol=1e-12, atol=1e-12 * np.abs(a["phi"]).max())
+    np.testing.assert_allclose(b["F"], a["F"], rtol=1e-11, atol=1e-11 * np.abs(a["F"]).max())

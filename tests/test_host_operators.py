@@ -31,8 +31,8 @@ def test_library_exports_every_declared_symbol():
 
 
 def test_params_struct_layout():
-    # int32 x4, double, int64 x2, int32 x2 -> 48 bytes with natural alignment
-    assert ctypes.sizeof(fmm.fmm_params) == 48
+    # int32 x4, double, int64 x2, int32 x6 -> 64 bytes with natural alignment
+    assert ctypes.sizeof(fmm.fmm_params) == 64
     assert fmm.fmm_params.coulomb_k.offset == 16
     assert fmm.fmm_params.max_atoms.offset == 24
 
@@ -42,9 +42,12 @@ def test_plan_create_rejects_bad_params_without_gpu():
     out = ctypes.c_void_p()
     for bad in (dict(depth=-1), dict(depth=7), dict(order_p=0), dict(order_p=16),
                 dict(boundary=2), dict(precision=3), dict(max_replicas=0),
-                dict(max_atoms=-5), dict(coulomb_k=float("nan"))):
+                dict(max_atoms=-5), dict(coulomb_k=float("nan")), dict(m2l_kernel=3),
+                dict(m2l_chunk=190), dict(reserved=1), dict(order_p=11, m2l_kernel=2),
+                dict(order_p=9, precision=0, m2l_kernel=2)):
         kw = dict(depth=2, order_p=4, boundary=0, precision=0, coulomb_k=1.0,
-                  max_atoms=10, max_sites=1, max_replicas=1, check=0)
+                  max_atoms=10, max_sites=1, max_replicas=1, check=0, m2l_kernel=0,
+                  m2l_chunk=0, p2p_waves=0, reserved=0)
         kw.update(bad)
         prm = fmm.fmm_params(**kw)
         assert lib.fmm_plan_create(ctypes.byref(prm), None, ctypes.byref(out)) == fmm.FMM_E_INVALID
