@@ -89,7 +89,10 @@ typedef enum { FMM_FP64 = 0, FMM_MIXED_F32 = 1, FMM_MIXED_BF16X3 = 2 } fmm_preci
  *               (available for p <= 10; FP64 needs p <= 8)
  *   m2l_chunk   offsets per matrix-core M2L work-group (0 = automatic, else 1..189)
  *   p2p_waves   reserved tuning knob of the near-field kernel (0 = automatic)
- *   reserved    must be 0 */
+ *   graph       1 = record the launch sequence of an evaluation in a HIP graph on
+ *               first use and replay the graph while every argument (pointers,
+ *               sizes, boxes, replica offsets) is unchanged; needs a non-NULL
+ *               stream.  Per-phase profiling (fmm_profile) runs eagerly. */
 typedef struct {
     int32_t depth;
     int32_t order_p;
@@ -103,7 +106,7 @@ typedef struct {
     int32_t m2l_kernel;
     int32_t m2l_chunk;
     int32_t p2p_waves;
-    int32_t reserved;
+    int32_t graph;
 } fmm_params;
 
 /* Create a plan on the current HIP device.  hip_stream is a hipStream_t (NULL =

@@ -41,6 +41,14 @@ struct fmm_plan_s {
     int32_t* status = nullptr;
     void *F_tmp = nullptr, *phi_tmp = nullptr;
     double* dVdl_tmp = nullptr;
+    double* E_tmp = nullptr;
+    fmmk::RepDesc* reps = nullptr;  // device replica descriptors (max_replicas)
+    // graph replay (params.graph): the last captured evaluation and its argument key
+    bool graph_valid = false;
+    std::vector<unsigned char> graph_key;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t graph_exec = nullptr;
+    int R_max = 1;
     // matrix-core M2L
     int m2l_mode = 0;  // 0 plain, 1 f32, 2 f64, 3 bf16x3
     fmmk::M2LGeom mg{};
@@ -161,6 +169,7 @@ Geo make_geo(const fmm_plan_s* p) {
     g.has_far = g.periodic ? 1 : (g.depth >= 2 ? 1 : 0);
     g.check = p->prm.check;
     g.coulomb_k = p->prm.coulomb_k;
+    g.nbox = p->nbox;
     for (int l = 0; l <= fmmk::kDMax + 1; ++l) g.lev_off[l] = p->lev_off[l];
     return g;
 }
@@ -179,11 +188,11 @@ inline unsigned nblocks(int64_t n, int b) { return (unsigned)std::max<int64_t>(1
 // Matrix-core M2L launch: the kernel instance for the plan's precision and row
 // tile count, then the fixed-order chunk reduction.
 template <typename T>
-void launch_m2l_mma(fmm_plan_t P, const Geo& g) {
+void launch_m2l_mma(fmm_plan_t P, const Geo& g, int R) {
     using namespace fmmk;
     hipStream_t st = P->stream;
     const M2LGeom mg = P->mg;
-    const unsigned nt = (unsigned)P->n_tasks;
+    const dim3 nt((unsigned)P->n_tasks, (unsigned)R);
     const size_t lds = P->m2l_lds;
     T* loc = (T*)P->loc;
     T* part = (T*)P->m2l_part;
@@ -219,68 +228,86 @@ void launch_m2l_mma(fmm_plan_t P, const Geo& g) {
     if (mg.nchunk > 1) {
         const int64_t tot = mg.nt_all * g.Kp;
         const unsigned nb = (unsigned)std::min<int64_t>(4096, (tot + 255) / 256);
-        k_m2l_reduce<T><<<nb, 256, 0, st>>>(g, mg, part, loc);
+        k_m2l_reduce<T><<<dim3(nb, (unsigned)R), 256, 0, st>>>(g, mg, part, loc);
     }
 }
 
-// Enqueue one single-system evaluation (arguments already validated).
+// Enqueue one evaluation of R replicas (arguments already validated; rd holds
+// the host copy of the replica descriptors).  Every phase is one launch over
+// all replicas (grid y = replica).
 template <typename T>
-fmm_status enqueue_eval(fmm_plan_t P, int64_t n, const T* x, const T* qA, const T* qB,
-                        const int32_t* site, int64_t S, const double* lam, double box,
+fmm_status enqueue_eval(fmm_plan_t P, const std::vector<fmmk::RepDesc>& rd, const T* x,
+                        const T* qA, const T* qB, const int32_t* site, const double* lam,
                         double* E, T* F, T* phi, double* dVdl) {
     using namespace fmmk;
     hipStream_t st = P->stream;
     const Geo g = make_geo(P);
-    if (n == 0) {
-        if (E) k_fill_f64<<<1, 64, 0, st>>>(E, 1, 0.0);
-        if (dVdl && S > 0) k_fill_f64<<<nblocks(S, 256), 256, 0, st>>>(dVdl, S, 0.0);
-        return hipGetLastError() == hipSuccess ? FMM_OK : fail(P, FMM_E_HIP, "launch failed");
+    const int R = (int)rd.size();
+    int64_t maxn = 0, S_tot = 0;
+    for (const RepDesc& d : rd) {
+        maxn = std::max(maxn, d.n);
+        S_tot += d.S;
     }
+    for (int f = 0; f < R; f += kRepsPerSet) {
+        RepSet set{};
+        set.first = f;
+        set.count = std::min(kRepsPerSet, R - f);
+        for (int i = 0; i < set.count; ++i) set.d[i] = rd[f + i];
+        k_set_reps<<<1, kRepsPerSet, 0, st>>>(set, P->reps);
+    }
+    const RepDesc* reps = P->reps;
     mark(P, 0);
-    k_fill_i32<<<nblocks(g.nleaf, 256), 256, 0, st>>>(P->leaf_count, g.nleaf, 0);
-    if (S > 0) k_fill_i32<<<nblocks(S, 256), 256, 0, st>>>(P->site_count, S, 0);
+    k_fill_i32<<<nblocks((int64_t)R * g.nleaf, 256), 256, 0, st>>>(P->leaf_count,
+                                                                   (int64_t)R * g.nleaf, 0);
+    if (S_tot > 0) k_fill_i32<<<nblocks(S_tot, 256), 256, 0, st>>>(P->site_count, S_tot, 0);
+    const unsigned ab = nblocks(maxn, 256);
     if (!g.periodic) {
-        const int nb = (int)std::min<int64_t>(kBboxBlocks, nblocks(n, 256));
-        k_bbox<T><<<nb, 256, 0, st>>>(x, n, P->bbox_part);
-        k_bbox_final<<<1, 64, 0, st>>>(P->bbox_part, nb, P->dom);
+        const int nb = (int)std::min<int64_t>(kBboxBlocks, ab);
+        k_bbox<T><<<dim3(nb, R), 256, 0, st>>>(x, reps, P->bbox_part);
+        k_bbox_final<<<R, 64, 0, st>>>(P->bbox_part, nb, P->dom);
     }
-    k_charge_key<T><<<nblocks(n, 256), 256, 0, st>>>(g, n, x, qA, qB, site, S, lam, box, P->dom,
-                                                     P->key, P->rank, P->leaf_count,
-                                                     P->site_count, P->site_rank, P->status);
-    k_scan2<<<2, 1024, 0, st>>>(P->leaf_count, P->leaf_start, g.nleaf, P->site_count,
-                                P->site_start, S);
-    k_scatter<<<nblocks(n, 256), 256, 0, st>>>(n, P->key, P->rank, P->leaf_start, P->perm, site,
-                                               S, P->site_rank, P->site_start, P->site_members);
+    k_charge_key<T><<<dim3(ab, R), 256, 0, st>>>(g, reps, x, qA, qB, site, lam, P->dom, P->key,
+                                                 P->rank, P->leaf_count, P->site_count,
+                                                 P->site_rank, P->status);
+    k_scan2<<<R + 1, 1024, 0, st>>>(reps, R, P->leaf_count, P->leaf_start, g.nleaf,
+                                    P->site_count, P->site_start, S_tot);
+    k_scatter<<<dim3(ab, R), 256, 0, st>>>(g, reps, P->key, P->rank, P->leaf_start, P->perm, site,
+                                           P->site_rank, P->site_start, P->site_members);
     using V4 = vec4_t<T>;
     V4* pos = (V4*)P->pos;
     T* mult = (T*)P->mult;
     T* loc = (T*)P->loc;
-    k_leaf_sort_gather<T><<<g.nleaf, 256, 0, st>>>(g, x, qA, qB, site, S, lam, P->dom,
-                                                   P->leaf_start, P->perm, pos, P->status);
+    const dim3 lg(g.nleaf, R);
+    k_leaf_sort_gather<T><<<lg, 256, 0, st>>>(g, reps, x, qA, qB, site, lam, P->dom,
+                                              P->leaf_start, P->perm, pos, P->status);
     mark(P, 1);
-    k_p2m<T><<<g.nleaf, 64, 0, st>>>(g, pos, P->leaf_start, P->dom, mult, P->leaf_part);
+    k_p2m<T><<<lg, 64, (size_t)64 * (g.K + 1) * sizeof(T), st>>>(g, pos, P->leaf_start, P->dom,
+                                                                  mult, P->leaf_part);
     // upward pass: parents at level lev from children at lev + 1
     mark(P, 2);
+    const int64_t rstride = g.nbox * g.Kp;
     for (int lev = g.depth - 1; lev >= 0; --lev) {
         const unsigned np = 1u << (3 * lev);
         if (lev == 0)
-            k_m2m<T, double><<<1, 256, 0, st>>>(g, 0, mult, (const T*)P->m2mT, P->root_m, g.K);
+            k_m2m<T, double><<<dim3(1, R), 256, 0, st>>>(g, 0, mult, (const T*)P->m2mT, P->root_m,
+                                                         g.K, g.K);
         else
-            k_m2m<T, T><<<np, 256, 0, st>>>(g, lev, mult, (const T*)P->m2mT,
-                                            mult + (size_t)g.lev_off[lev] * g.Kp, g.Kp);
+            k_m2m<T, T><<<dim3(np, R), 256, 0, st>>>(g, lev, mult, (const T*)P->m2mT,
+                                                     mult + (size_t)g.lev_off[lev] * g.Kp, g.Kp,
+                                                     rstride);
     }
     mark(P, 3);
     if (g.periodic)
-        k_root<T><<<1, 256, 0, st>>>(g, P->leaf_part, P->root_m, mult, P->latT, P->root_l, loc,
+        k_root<T><<<R, 256, 0, st>>>(g, P->leaf_part, P->root_m, mult, P->latT, P->root_l, loc,
                                      P->dom);
     mark(P, 4);
     if (g.depth >= g.lmin) {
         if (P->m2l_mode == 0) {
             int64_t nt = 0;
             for (int l = g.lmin; l <= g.depth; ++l) nt += (int64_t)1 << (3 * l);
-            k_m2l_plain<T><<<(unsigned)nt, 256, 0, st>>>(g, mult, (const T*)P->bankT, loc);
+            k_m2l_plain<T><<<dim3((unsigned)nt, R), 256, 0, st>>>(g, mult, (const T*)P->bankT, loc);
         } else {
-            launch_m2l_mma<T>(P, g);
+            launch_m2l_mma<T>(P, g, R);
         }
     }
     // downward pass: children at lev + 1 from parents at lev
@@ -289,23 +316,90 @@ fmm_status enqueue_eval(fmm_plan_t P, int64_t n, const T* x, const T* qA, const 
     for (int lev = l0; lev < g.depth; ++lev) {
         const unsigned nc = 1u << (3 * (lev + 1));
         if (lev == 0)
-            k_l2l<double, T><<<nc, 256, 0, st>>>(g, 0, P->root_l, g.K, (const T*)P->l2lT, loc);
+            k_l2l<double, T><<<dim3(nc, R), 256, 0, st>>>(g, 0, P->root_l, g.K, g.K,
+                                                          (const T*)P->l2lT, loc);
         else
-            k_l2l<T, T><<<nc, 256, 0, st>>>(g, lev, loc + (size_t)g.lev_off[lev] * g.Kp, g.Kp,
-                                            (const T*)P->l2lT, loc);
+            k_l2l<T, T><<<dim3(nc, R), 256, 0, st>>>(g, lev, loc + (size_t)g.lev_off[lev] * g.Kp,
+                                                     g.Kp, rstride, (const T*)P->l2lT, loc);
     }
     mark(P, 6);
-    k_near_far<T><<<g.nleaf, 256, 0, st>>>(g, pos, P->leaf_start, P->perm, P->dom, loc, P->gidx,
-                                           (const T*)P->gcoef, qA, qB, site, S, phi, F,
+    k_near_far<T><<<lg, 64 * kNW, 0, st>>>(g, reps, pos, P->leaf_start, P->perm, P->dom, loc,
+                                           P->gidx, (const T*)P->gcoef, qA, qB, site, phi, F,
                                            P->leaf_energy, P->cphi);
     mark(P, 7);
-    k_reduce<<<(unsigned)(S + 1), 256, 0, st>>>(g, P->leaf_energy, P->site_start,
-                                                P->site_members, P->cphi, E, dVdl, P->status);
+    k_reduce<<<(unsigned)(R + S_tot), 256, 0, st>>>(g, R, P->leaf_energy, P->site_start,
+                                                    P->site_members, P->cphi, E, dVdl, P->status);
     mark(P, -1);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return fail(P, FMM_E_HIP, std::string("kernel launch: ") + hipGetErrorString(e));
     return FMM_OK;
 }
+
+template <typename T>
+fmm_status enqueue_adjoint(fmm_plan_t P, const std::vector<fmmk::RepDesc>& rd, const T* x,
+                           const T* qA, const T* qB, const int32_t* site, const double* lam,
+                           const double* gE, T* gx, T* gqA, T* gqB, double* glam, double* E, T* F,
+                           T* phi, double* dVdl) {
+    T* Fw = F ? F : (T*)P->F_tmp;
+    T* pw = phi ? phi : (T*)P->phi_tmp;
+    double* dw = dVdl ? dVdl : P->dVdl_tmp;
+    fmm_status s = enqueue_eval<T>(P, rd, x, qA, qB, site, lam, E ? E : P->E_tmp, Fw, pw, dw);
+    if (s != FMM_OK) return s;
+    int64_t m = 0;
+    for (const fmmk::RepDesc& d : rd) m = std::max(m, std::max(d.n, d.S));
+    fmmk::k_adjoint<T><<<dim3(nblocks(m, 256), (unsigned)rd.size()), 256, 0, P->stream>>>(
+        P->reps, site, lam, gE, Fw, pw, dw, gx, gqA, gqB, glam);
+    return hipGetLastError() == hipSuccess ? FMM_OK : fail(P, FMM_E_HIP, "adjoint launch failed");
+}
+
+// Run `enqueue` eagerly, or (params.graph) replay the cached graph when the
+// argument key matches, else capture a new graph and replay it.
+template <class Fn>
+fmm_status run_maybe_graph(fmm_plan_t P, const std::vector<unsigned char>& key, Fn&& enqueue) {
+    if (!P->prm.graph || P->prof_on) return enqueue();
+    if (!P->stream) return fail(P, FMM_E_INVALID, "graph replay needs a non-default stream");
+    if (P->graph_valid && P->graph_key == key) {
+        if (hipGraphLaunch(P->graph_exec, P->stream) != hipSuccess)
+            return fail(P, FMM_E_HIP, "hipGraphLaunch failed");
+        return FMM_OK;
+    }
+    if (P->graph_exec) (void)hipGraphExecDestroy(P->graph_exec);
+    if (P->graph) (void)hipGraphDestroy(P->graph);
+    P->graph_exec = nullptr;
+    P->graph = nullptr;
+    P->graph_valid = false;
+    if (hipStreamBeginCapture(P->stream, hipStreamCaptureModeThreadLocal) != hipSuccess)
+        return fail(P, FMM_E_HIP, "hipStreamBeginCapture failed");
+    fmm_status s = enqueue();
+    hipGraph_t gr = nullptr;
+    hipError_t e = hipStreamEndCapture(P->stream, &gr);
+    if (s != FMM_OK) {
+        if (gr) (void)hipGraphDestroy(gr);
+        return s;
+    }
+    if (e != hipSuccess || !gr) return fail(P, FMM_E_HIP, "hipStreamEndCapture failed");
+    hipGraphExec_t ex = nullptr;
+    if (hipGraphInstantiate(&ex, gr, nullptr, nullptr, 0) != hipSuccess) {
+        (void)hipGraphDestroy(gr);
+        return fail(P, FMM_E_HIP, "hipGraphInstantiate failed");
+    }
+    P->graph = gr;
+    P->graph_exec = ex;
+    P->graph_key = key;
+    P->graph_valid = true;
+    if (hipGraphLaunch(ex, P->stream) != hipSuccess) return fail(P, FMM_E_HIP, "hipGraphLaunch failed");
+    return FMM_OK;
+}
+
+struct KeyBuf {
+    std::vector<unsigned char> b;
+    template <typename V>
+    KeyBuf& add(const V& v) {
+        const unsigned char* p = (const unsigned char*)&v;
+        b.insert(b.end(), p, p + sizeof(V));
+        return *this;
+    }
+};
 
 fmm_status check_box(fmm_plan_t P, const double* box, double* L) {
     if (P->prm.boundary == FMM_PERIODIC) {
@@ -348,7 +442,7 @@ fmm_status fmm_plan_create(const fmm_params* prm, void* hip_stream, fmm_plan_t* 
          prm->precision != FMM_MIXED_BF16X3) ||
         !std::isfinite(prm->coulomb_k) || prm->max_atoms > INT32_MAX ||
         prm->m2l_kernel < 0 || prm->m2l_kernel > 2 || prm->m2l_chunk < 0 || prm->m2l_chunk > 189 ||
-        prm->p2p_waves < 0 || prm->reserved != 0)
+        prm->p2p_waves < 0 || prm->graph < 0 || prm->graph > 1)
         return FMM_E_INVALID;
     {
         const int K = (prm->order_p + 1) * (prm->order_p + 1);
@@ -378,36 +472,40 @@ fmm_status fmm_plan_create(const fmm_params* prm, void* hip_stream, fmm_plan_t* 
     init_rho_coef();
     const int64_t N = std::max<int64_t>(prm->max_atoms, 1), S = std::max<int64_t>(prm->max_sites, 1);
     const size_t ts = P->tsz, K = P->K;
+    const size_t RM = (size_t)prm->max_replicas;
+    P->R_max = prm->max_replicas;
     bool ok = true;
     ok &= dev_alloc(P, &P->pos, N * 4 * ts);
     ok &= dev_alloc(P, (void**)&P->perm, N * 4);
     ok &= dev_alloc(P, (void**)&P->key, N * 4);
     ok &= dev_alloc(P, (void**)&P->rank, N * 4);
-    ok &= dev_alloc(P, (void**)&P->leaf_count, (size_t)P->nleaf * 4);
-    ok &= dev_alloc(P, (void**)&P->leaf_start, ((size_t)P->nleaf + 1) * 4);
+    ok &= dev_alloc(P, (void**)&P->leaf_count, RM * P->nleaf * 4);
+    ok &= dev_alloc(P, (void**)&P->leaf_start, RM * ((size_t)P->nleaf + 1) * 4);
     ok &= dev_alloc(P, (void**)&P->site_count, S * 4);
     ok &= dev_alloc(P, (void**)&P->site_start, (S + 1) * 4);
     ok &= dev_alloc(P, (void**)&P->site_rank, N * 4);
     ok &= dev_alloc(P, (void**)&P->site_members, N * 4);
-    ok &= dev_alloc(P, &P->mult, (size_t)P->nbox * P->Kp * ts);
-    ok &= dev_alloc(P, &P->loc, (size_t)P->nbox * P->Kp * ts);
-    ok &= dev_alloc(P, (void**)&P->root_m, K * 8);
-    ok &= dev_alloc(P, (void**)&P->root_l, K * 8);
+    ok &= dev_alloc(P, &P->mult, RM * P->nbox * P->Kp * ts);
+    ok &= dev_alloc(P, &P->loc, RM * P->nbox * P->Kp * ts);
+    ok &= dev_alloc(P, (void**)&P->root_m, RM * K * 8);
+    ok &= dev_alloc(P, (void**)&P->root_l, RM * K * 8);
     ok &= dev_alloc(P, &P->bankT, 343 * K * K * ts);
     ok &= dev_alloc(P, &P->m2mT, 8 * K * K * ts);
     ok &= dev_alloc(P, &P->l2lT, 8 * K * K * ts);
     ok &= dev_alloc(P, (void**)&P->latT, K * K * 8);
     ok &= dev_alloc(P, (void**)&P->gidx, 3 * (size_t)P->Kg * 4 * 4);
     ok &= dev_alloc(P, &P->gcoef, 3 * (size_t)P->Kg * 4 * ts);
-    ok &= dev_alloc(P, (void**)&P->dom, 8 * 8);
-    ok &= dev_alloc(P, (void**)&P->bbox_part, kBboxBlocks * 6 * 8);
-    ok &= dev_alloc(P, (void**)&P->leaf_part, (size_t)P->nleaf * 2 * 8);
-    ok &= dev_alloc(P, (void**)&P->leaf_energy, (size_t)P->nleaf * 8);
+    ok &= dev_alloc(P, (void**)&P->dom, RM * 8 * 8);
+    ok &= dev_alloc(P, (void**)&P->bbox_part, RM * kBboxBlocks * 6 * 8);
+    ok &= dev_alloc(P, (void**)&P->leaf_part, RM * P->nleaf * 2 * 8);
+    ok &= dev_alloc(P, (void**)&P->leaf_energy, RM * P->nleaf * 8);
+    ok &= dev_alloc(P, (void**)&P->reps, RM * sizeof(fmmk::RepDesc));
     ok &= dev_alloc(P, (void**)&P->cphi, N * 8);
     ok &= dev_alloc(P, (void**)&P->status, 4 * 4);
     ok &= dev_alloc(P, &P->F_tmp, N * 3 * ts);
     ok &= dev_alloc(P, &P->phi_tmp, N * ts);
     ok &= dev_alloc(P, (void**)&P->dVdl_tmp, S * 8);
+    ok &= dev_alloc(P, (void**)&P->E_tmp, RM * 8);
     if (!ok) {
         fmm_plan_destroy(P);
         return FMM_E_OOM;
@@ -464,7 +562,7 @@ fmm_status fmm_plan_create(const fmm_params* prm, void* hip_stream, fmm_plan_t* 
         int64_t items = 0, nt_all = 0;
         for (int l = lmin; l <= d; ++l) {
             const int64_t ntc = (int64_t)1 << (3 * (l - 1));
-            items += 8 * ((ntc + fmmk::kM2LTile - 1) / fmmk::kM2LTile);
+            items += 8 * ((ntc + fmmk::kM2LTile - 1) / fmmk::kM2LTile) * (int64_t)RM;
             nt_all += (int64_t)1 << (3 * l);
         }
         int csize = prm->m2l_chunk;
@@ -495,7 +593,7 @@ fmm_status fmm_plan_create(const fmm_params* prm, void* hip_stream, fmm_plan_t* 
         ok2 &= dev_alloc(P, &P->bank_mma, nb * esz);
         if (P->m2l_mode == 3) ok2 &= dev_alloc(P, &P->bank_mma_lo, nb * esz);
         if (mg.nchunk > 1)
-            ok2 &= dev_alloc(P, &P->m2l_part, (size_t)mg.nchunk * nt_all * P->Kp * P->tsz);
+            ok2 &= dev_alloc(P, &P->m2l_part, RM * mg.nchunk * nt_all * P->Kp * P->tsz);
         if (!ok2) {
             fmm_plan_destroy(P);
             return FMM_E_OOM;
@@ -549,8 +647,15 @@ fmm_status fmm_plan_create(const fmm_params* prm, void* hip_stream, fmm_plan_t* 
         }
         if (ea != hipSuccess) e = ea;
     }
-    std::vector<double> dom0(8, 0.0);
-    up(P->dom, dom0.data(), 64);
+    if (e == hipSuccess) {
+        const int p2m_lds = 64 * ((int)K + 1) * (int)P->tsz;
+        e = P->fp64 ? hipFuncSetAttribute((const void*)&fmmk::k_p2m<double>,
+                                          hipFuncAttributeMaxDynamicSharedMemorySize, p2m_lds)
+                    : hipFuncSetAttribute((const void*)&fmmk::k_p2m<float>,
+                                          hipFuncAttributeMaxDynamicSharedMemorySize, p2m_lds);
+    }
+    std::vector<double> dom0(8 * RM, 0.0);
+    up(P->dom, dom0.data(), dom0.size() * 8);
     int32_t z[4] = {0, 0, 0, 0};
     up(P->status, z, sizeof(z));
     if (e != hipSuccess) {
@@ -563,6 +668,8 @@ fmm_status fmm_plan_create(const fmm_params* prm, void* hip_stream, fmm_plan_t* 
 
 void fmm_plan_destroy(fmm_plan_t P) {
     if (!P) return;
+    if (P->graph_exec) (void)hipGraphExecDestroy(P->graph_exec);
+    if (P->graph) (void)hipGraphDestroy(P->graph);
     for (hipEvent_t ev : P->prof_ev) (void)hipEventDestroy(ev);
     for (void* a : P->allocs) (void)hipFree(a);
     delete P;
@@ -581,11 +688,18 @@ fmm_status fmm_eval(fmm_plan_t P, int64_t n, const void* x, const void* qA, cons
     double L = 0;
     if ((s = check_box(P, box, &L)) != FMM_OK) return s;
     P->err.clear();
-    if (P->fp64)
-        return enqueue_eval<double>(P, n, (const double*)x, (const double*)qA, (const double*)qB,
-                                    site, S, lam, L, E, (double*)F, (double*)phi, dVdl);
-    return enqueue_eval<float>(P, n, (const float*)x, (const float*)qA, (const float*)qB, site, S,
-                               lam, L, E, (float*)F, (float*)phi, dVdl);
+    std::vector<fmmk::RepDesc> rd(1);
+    rd[0] = {0, n, 0, S, L, 0};
+    KeyBuf key;
+    key.add(1).add(rd[0]).add(x).add(qA).add(qB).add(site).add(lam).add(E).add(F).add(phi).add(dVdl);
+    return run_maybe_graph(P, key.b, [&]() {
+        if (P->fp64)
+            return enqueue_eval<double>(P, rd, (const double*)x, (const double*)qA,
+                                        (const double*)qB, site, lam, E, (double*)F, (double*)phi,
+                                        dVdl);
+        return enqueue_eval<float>(P, rd, (const float*)x, (const float*)qA, (const float*)qB, site,
+                                   lam, E, (float*)F, (float*)phi, dVdl);
+    });
 }
 
 fmm_status fmm_eval_adjoint(fmm_plan_t P, int64_t n, const void* x, const void* qA,
@@ -599,28 +713,21 @@ fmm_status fmm_eval_adjoint(fmm_plan_t P, int64_t n, const void* x, const void* 
     double L = 0;
     if ((s = check_box(P, box, &L)) != FMM_OK) return s;
     P->err.clear();
-    void* Fw = F ? F : P->F_tmp;
-    void* pw = phi ? phi : P->phi_tmp;
-    double* dw = dVdl ? dVdl : P->dVdl_tmp;
-    const unsigned nb = nblocks(std::max(n, S), 256);
-    if (P->fp64) {
-        s = enqueue_eval<double>(P, n, (const double*)x, (const double*)qA, (const double*)qB, site,
-                                 S, lam, L, E, (double*)Fw, (double*)pw, dw);
-        if (s != FMM_OK) return s;
-        if (n > 0 || S > 0)
-            fmmk::k_adjoint<double><<<nb, 256, 0, P->stream>>>(
-                n, site, S, lam, gE, (const double*)Fw, (const double*)pw, dw, (double*)grad_x,
-                (double*)grad_qA, (double*)grad_qB, grad_lambda);
-    } else {
-        s = enqueue_eval<float>(P, n, (const float*)x, (const float*)qA, (const float*)qB, site, S,
-                                lam, L, E, (float*)Fw, (float*)pw, dw);
-        if (s != FMM_OK) return s;
-        if (n > 0 || S > 0)
-            fmmk::k_adjoint<float><<<nb, 256, 0, P->stream>>>(
-                n, site, S, lam, gE, (const float*)Fw, (const float*)pw, dw, (float*)grad_x,
-                (float*)grad_qA, (float*)grad_qB, grad_lambda);
-    }
-    return hipGetLastError() == hipSuccess ? FMM_OK : fail(P, FMM_E_HIP, "adjoint launch failed");
+    std::vector<fmmk::RepDesc> rd(1);
+    rd[0] = {0, n, 0, S, L, 0};
+    KeyBuf key;
+    key.add(2).add(rd[0]).add(x).add(qA).add(qB).add(site).add(lam).add(gE).add(grad_x)
+        .add(grad_qA).add(grad_qB).add(grad_lambda).add(E).add(F).add(phi).add(dVdl);
+    return run_maybe_graph(P, key.b, [&]() {
+        if (P->fp64)
+            return enqueue_adjoint<double>(P, rd, (const double*)x, (const double*)qA,
+                                           (const double*)qB, site, lam, gE, (double*)grad_x,
+                                           (double*)grad_qA, (double*)grad_qB, grad_lambda, E,
+                                           (double*)F, (double*)phi, dVdl);
+        return enqueue_adjoint<float>(P, rd, (const float*)x, (const float*)qA, (const float*)qB,
+                                      site, lam, gE, (float*)grad_x, (float*)grad_qA,
+                                      (float*)grad_qB, grad_lambda, E, (float*)F, (float*)phi, dVdl);
+    });
 }
 
 fmm_status fmm_eval_batched(fmm_plan_t P, int32_t R, const int64_t* atom_off,
@@ -628,40 +735,37 @@ fmm_status fmm_eval_batched(fmm_plan_t P, int32_t R, const int64_t* atom_off,
                             const void* qB, const int32_t* site_local, const double* lam,
                             const double* boxes, double* E, void* F, void* phi, double* dVdl) {
     if (!P) return FMM_E_INVALID;
-    if (R < 1 || R > P->prm.max_replicas || !atom_off || !site_off || !E)
+    if (R < 1 || R > P->prm.max_replicas || !atom_off || !site_off)
         return fail(P, FMM_E_INVALID, "bad replica count or offsets");
     if (atom_off[0] != 0 || site_off[0] != 0)
         return fail(P, FMM_E_INVALID, "offsets must start at 0");
+    std::vector<fmmk::RepDesc> rd((size_t)R);
     for (int r = 0; r < R; ++r) {
         const int64_t n = atom_off[r + 1] - atom_off[r], S = site_off[r + 1] - site_off[r];
         if (n < 0 || S < 0) return fail(P, FMM_E_INVALID, "offsets must be non-decreasing");
         fmm_status s = check_common(P, n, x, qA, qB, site_local, S, lam);
         if (s != FMM_OK) return s;
         double L = 0;
+        if (P->prm.boundary == FMM_PERIODIC && !boxes)
+            return fail(P, FMM_E_INVALID, "periodic plan needs boxes");
         if ((s = check_box(P, boxes ? boxes + 3 * r : nullptr, &L)) != FMM_OK) return s;
+        rd[r] = {atom_off[r], n, site_off[r], S, L, 0};
     }
     if (atom_off[R] > P->prm.max_atoms || site_off[R] > P->prm.max_sites)
         return fail(P, FMM_E_INVALID, "total atoms or sites above the plan maxima");
     P->err.clear();
-    for (int r = 0; r < R; ++r) {
-        const int64_t a0 = atom_off[r], n = atom_off[r + 1] - a0;
-        const int64_t s0 = site_off[r], S = site_off[r + 1] - s0;
-        double L = boxes ? boxes[3 * r] : 0.0;
-        fmm_status s;
+    KeyBuf key;
+    key.add(3).add(R);
+    for (const fmmk::RepDesc& d : rd) key.add(d);
+    key.add(x).add(qA).add(qB).add(site_local).add(lam).add(E).add(F).add(phi).add(dVdl);
+    return run_maybe_graph(P, key.b, [&]() {
         if (P->fp64)
-            s = enqueue_eval<double>(P, n, (const double*)x + 3 * a0, (const double*)qA + a0,
-                                     (const double*)qB + a0, site_local + a0, S, lam + s0, L, E + r,
-                                     F ? (double*)F + 3 * a0 : nullptr,
-                                     phi ? (double*)phi + a0 : nullptr,
-                                     dVdl ? dVdl + s0 : nullptr);
-        else
-            s = enqueue_eval<float>(P, n, (const float*)x + 3 * a0, (const float*)qA + a0,
-                                    (const float*)qB + a0, site_local + a0, S, lam + s0, L, E + r,
-                                    F ? (float*)F + 3 * a0 : nullptr,
-                                    phi ? (float*)phi + a0 : nullptr, dVdl ? dVdl + s0 : nullptr);
-        if (s != FMM_OK) return s;
-    }
-    return FMM_OK;
+            return enqueue_eval<double>(P, rd, (const double*)x, (const double*)qA,
+                                        (const double*)qB, site_local, lam, E, (double*)F,
+                                        (double*)phi, dVdl);
+        return enqueue_eval<float>(P, rd, (const float*)x, (const float*)qA, (const float*)qB,
+                                   site_local, lam, E, (float*)F, (float*)phi, dVdl);
+    });
 }
 
 fmm_status fmm_sync_check(fmm_plan_t P) {

@@ -34,7 +34,23 @@ struct Geo {
     int32_t check;     // device-side input checks
     int32_t pad_;
     double coulomb_k;  // k_e
+    int64_t nbox;      // boxes per replica (all levels)
     int64_t lev_off[kDMax + 2];  // first box of level l in the expansion arrays
+};
+
+// One replica (independent system) of an evaluation: its atoms occupy
+// [a0, a0 + n) and its sites [s0, s0 + S) of the concatenated arrays; box is the
+// periodic cell edge (0 for open boundaries).  blockIdx.y selects the replica.
+struct RepDesc {
+    int64_t a0, n, s0, S;
+    double box;
+    int64_t pad_;
+};
+
+constexpr int kRepsPerSet = 32;  // replica descriptors carried by one k_set_reps launch
+struct RepSet {
+    int32_t first, count;
+    RepDesc d[kRepsPerSet];
 };
 
 }  // namespace fmmk

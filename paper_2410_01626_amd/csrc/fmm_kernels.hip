@@ -116,15 +116,24 @@ __global__ void k_fill_f64(double* p, int64_t n, double v) {
         p[i] = v;
 }
 
+// Copy replica descriptors (carried by value in the launch) to device memory.
+__global__ void k_set_reps(RepSet set, RepDesc* __restrict__ reps) {
+    const int i = threadIdx.x;
+    if (i < set.count) reps[set.first + i] = set.d[i];
+}
+
 // ------------------------------------------------------------------ domain
 
 // Per-block min/max of the coordinates (open boundaries): part[b] = {min xyz, max xyz}.
 template <typename T>
-__global__ __launch_bounds__(256) void k_bbox(const T* __restrict__ x, int64_t n,
+__global__ __launch_bounds__(256) void k_bbox(const T* __restrict__ x,
+                                              const RepDesc* __restrict__ reps,
                                               double* __restrict__ part) {
     __shared__ double smin[3][256], smax[3][256];
+    const RepDesc rd = reps[blockIdx.y];
     double mn[3] = {1e300, 1e300, 1e300}, mx[3] = {-1e300, -1e300, -1e300};
-    for (int64_t i = blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256)
+    for (int64_t i = rd.a0 + blockIdx.x * 256 + threadIdx.x; i < rd.a0 + rd.n;
+         i += (int64_t)gridDim.x * 256)
         for (int a = 0; a < 3; ++a) {
             double v = (double)x[3 * i + a];
             mn[a] = fmin(mn[a], v);
@@ -143,17 +152,21 @@ __global__ __launch_bounds__(256) void k_bbox(const T* __restrict__ x, int64_t n
             }
         __syncthreads();
     }
+    const size_t pb = (size_t)blockIdx.y * gridDim.x + blockIdx.x;
     if (threadIdx.x == 0)
         for (int a = 0; a < 3; ++a) {
-            part[6 * blockIdx.x + a] = smin[a][0];
-            part[6 * blockIdx.x + 3 + a] = smax[a][0];
+            part[6 * pb + a] = smin[a][0];
+            part[6 * pb + 3 + a] = smax[a][0];
         }
 }
 
 // Root cube of an open system: dom = {lo_x, lo_y, lo_z, edge}.  The edge is the
 // largest extent, enlarged by a relative 2^-20 so no atom sits on the far face.
-__global__ void k_bbox_final(const double* __restrict__ part, int nblk, double* __restrict__ dom) {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+// One block per replica; dom + 8 r receives that replica's cube.
+__global__ void k_bbox_final(const double* __restrict__ part, int nblk, double* __restrict__ dom_all) {
+    if (threadIdx.x != 0) return;
+    double* dom = dom_all + 8 * blockIdx.x;
+    part += (size_t)6 * nblk * blockIdx.x;
     double mn[3] = {1e300, 1e300, 1e300}, mx[3] = {-1e300, -1e300, -1e300};
     for (int b = 0; b < nblk; ++b)
         for (int a = 0; a < 3; ++a) {
@@ -161,7 +174,10 @@ __global__ void k_bbox_final(const double* __restrict__ part, int nblk, double* 
             mx[a] = fmax(mx[a], part[6 * b + 3 + a]);
         }
     double e = fmax(mx[0] - mn[0], fmax(mx[1] - mn[1], mx[2] - mn[2]));
-    if (!(e > 0)) e = 1.0;
+    if (!(e > 0) || !(e < 1e300)) {  // no atoms, or all atoms at one point
+        e = 1.0;
+        if (!(mn[0] < 1e300)) mn[0] = mn[1] = mn[2] = 0.0;
+    }
     e *= 1.0 + 0x1p-20;
     for (int a = 0; a < 3; ++a) dom[a] = mn[a] - 0x1p-21 * e;
     dom[3] = e;
@@ -169,23 +185,32 @@ __global__ void k_bbox_final(const double* __restrict__ part, int nblk, double* 
 
 // ------------------------------------------------------------------ binning
 
-// q_i = qA_i + lambda_s (qB_i - qA_i) (eq 1 with interpolated charges), leaf
-// key (Morton code of the leaf cell), rank of the atom inside its leaf and its
-// site (atomic counters: ranks are made stable later by sorting).
+// Leaf key (Morton code of the leaf cell) of every atom, its rank inside the
+// leaf and inside its site (atomic counters: ranks are made stable later by
+// sorting), and the input checks.  The interpolated charge itself,
+// q_i = qA_i + lambda_s (qB_i - qA_i) (eq 1 with interpolated charges), is
+// formed in FP64 when the atoms are gathered into leaf order.
 template <typename T>
 __global__ __launch_bounds__(256) void k_charge_key(
-    Geo g, int64_t n, const T* __restrict__ x, const T* __restrict__ qA,
-    const T* __restrict__ qB, const int32_t* __restrict__ site, int64_t n_sites,
-    const double* __restrict__ lam, double box, double* __restrict__ dom,
-    int32_t* __restrict__ key, int32_t* __restrict__ rank, int32_t* __restrict__ leaf_count,
+    Geo g, const RepDesc* __restrict__ reps, const T* __restrict__ x, const T* __restrict__ qA,
+    const T* __restrict__ qB, const int32_t* __restrict__ site,
+    const double* __restrict__ lam, double* __restrict__ dom_all,
+    int32_t* __restrict__ key, int32_t* __restrict__ rank, int32_t* __restrict__ leaf_count_all,
     int32_t* __restrict__ site_count, int32_t* __restrict__ site_rank,
     int32_t* __restrict__ status) {
-    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (g.periodic && i == 0) {
+    const int r = blockIdx.y;
+    const RepDesc rd = reps[r];
+    const double box = rd.box;
+    double* dom = dom_all + 8 * r;
+    int32_t* leaf_count = leaf_count_all + (size_t)r * g.nleaf;
+    const int64_t il = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (g.periodic && il == 0) {
         dom[0] = dom[1] = dom[2] = 0.0;
         dom[3] = box;
     }
-    if (i >= n) return;
+    if (il >= rd.n) return;
+    const int64_t i = rd.a0 + il;
+    const int64_t n_sites = rd.S;
     double lo[3], edge;
     if (g.periodic) {
         lo[0] = lo[1] = lo[2] = 0.0;
@@ -215,22 +240,28 @@ __global__ __launch_bounds__(256) void k_charge_key(
         s = -1;
     }
     int32_t sr = -1;
-    if (s >= 0) sr = atomicAdd(&site_count[s], 1);
+    if (s >= 0) sr = atomicAdd(&site_count[rd.s0 + s], 1);
     site_rank[i] = sr;
     if (g.check) {
         bad |= !finite_d((double)qA[i]) || !finite_d((double)qB[i]);
-        if (s >= 0) bad |= !finite_d(lam[s]);
+        if (s >= 0) bad |= !finite_d(lam[rd.s0 + s]);
         if (bad) atomicOr(&status[0], kStatusNonFinite);
     }
 }
 
-// Exclusive scans (one block per array): start[0..n] from count[0..n-1].
-__global__ __launch_bounds__(1024) void k_scan2(const int32_t* __restrict__ c0, int32_t* __restrict__ s0,
-                                                int64_t n0, const int32_t* __restrict__ c1,
+// Exclusive scans, one block per array: blocks 0..R-1 scan the leaf counts of
+// replica r into leaf_start[r][0..nleaf] offset by the replica's first atom;
+// block R scans the site counts of all replicas (global site order).
+__global__ __launch_bounds__(1024) void k_scan2(const RepDesc* __restrict__ reps, int R,
+                                                const int32_t* __restrict__ leaf_count,
+                                                int32_t* __restrict__ leaf_start, int64_t nleaf,
+                                                const int32_t* __restrict__ c1,
                                                 int32_t* __restrict__ s1, int64_t n1) {
-    const int32_t* cnt = blockIdx.x == 0 ? c0 : c1;
-    int32_t* st = blockIdx.x == 0 ? s0 : s1;
-    const int64_t n = blockIdx.x == 0 ? n0 : n1;
+    const bool leaves = (int)blockIdx.x < R;
+    const int32_t* cnt = leaves ? leaf_count + (size_t)blockIdx.x * nleaf : c1;
+    int32_t* st = leaves ? leaf_start + (size_t)blockIdx.x * (nleaf + 1) : s1;
+    const int64_t n = leaves ? nleaf : n1;
+    const int32_t base = leaves ? (int32_t)reps[blockIdx.x].a0 : 0;
     __shared__ int32_t part[1024];
     const int t = threadIdx.x;
     const int64_t chunk = (n + 1023) / 1024;
@@ -245,28 +276,31 @@ __global__ __launch_bounds__(1024) void k_scan2(const int32_t* __restrict__ c0, 
         part[t] += v;
         __syncthreads();
     }
-    int32_t run = part[t] - sum;
+    int32_t run = base + part[t] - sum;
     for (int64_t i = b; i < e; ++i) {
         st[i] = run;
         run += cnt[i];
     }
-    if (t == 1023) st[n] = part[1023];
+    if (t == 1023) st[n] = base + part[1023];
 }
 
-__global__ __launch_bounds__(256) void k_scatter(int64_t n, const int32_t* __restrict__ key,
+__global__ __launch_bounds__(256) void k_scatter(Geo g, const RepDesc* __restrict__ reps,
+                                                 const int32_t* __restrict__ key,
                                                  const int32_t* __restrict__ rank,
-                                                 const int32_t* __restrict__ leaf_start,
+                                                 const int32_t* __restrict__ leaf_start_all,
                                                  int32_t* __restrict__ perm,
                                                  const int32_t* __restrict__ site,
-                                                 int64_t n_sites,
                                                  const int32_t* __restrict__ site_rank,
                                                  const int32_t* __restrict__ site_start,
                                                  int32_t* __restrict__ site_members) {
-    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (i >= n) return;
+    const RepDesc rd = reps[blockIdx.y];
+    const int64_t il = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (il >= rd.n) return;
+    const int64_t i = rd.a0 + il;
+    const int32_t* leaf_start = leaf_start_all + (size_t)blockIdx.y * (g.nleaf + 1);
     perm[leaf_start[key[i]] + rank[i]] = (int32_t)i;
     const int32_t s = site[i];
-    if (s >= 0 && s < n_sites) site_members[site_start[s] + site_rank[i]] = (int32_t)i;
+    if (s >= 0 && s < rd.S) site_members[site_start[rd.s0 + s] + site_rank[i]] = (int32_t)i;
 }
 
 // Bitonic sort of up to kSortCap ints in LDS (ascending), block-wide.
@@ -297,11 +331,16 @@ __device__ void lds_sort(int32_t* v, int n) {
 // (x - c_leaf, q) into the sorted particle array.
 template <typename T>
 __global__ __launch_bounds__(256) void k_leaf_sort_gather(
-    Geo g, const T* __restrict__ x, const T* __restrict__ qA, const T* __restrict__ qB,
-    const int32_t* __restrict__ site, int64_t n_sites, const double* __restrict__ lam,
-    const double* __restrict__ dom, const int32_t* __restrict__ leaf_start,
+    Geo g, const RepDesc* __restrict__ reps, const T* __restrict__ x, const T* __restrict__ qA,
+    const T* __restrict__ qB, const int32_t* __restrict__ site, const double* __restrict__ lam,
+    const double* __restrict__ dom_all, const int32_t* __restrict__ leaf_start_all,
     int32_t* __restrict__ perm, vec4_t<T>* __restrict__ pos, int32_t* __restrict__ status) {
     __shared__ int32_t buf[kSortCap];
+    const RepDesc rd = reps[blockIdx.y];
+    const int64_t n_sites = rd.S;
+    lam += rd.s0;
+    const double* dom = dom_all + 8 * blockIdx.y;
+    const int32_t* leaf_start = leaf_start_all + (size_t)blockIdx.y * (g.nleaf + 1);
     const int leaf = blockIdx.x;
     const int b = leaf_start[leaf], n = leaf_start[leaf + 1] - b;
     if (n == 0) return;
@@ -341,20 +380,27 @@ __global__ __launch_bounds__(256) void k_leaf_sort_gather(
 
 // ------------------------------------------------------------------ upward pass
 
-// P2M: mu~_leaf = sum_j q_j rho((x_j - c_leaf) / h), one wavefront per leaf,
-// coefficient sums by butterfly shuffles.  Periodic: also per-leaf FP64 partial
-// sums of q |t/L|^2 and q (t relative to the cell centre).
+// P2M: mu~_leaf = sum_j q_j rho((x_j - c_leaf) / h), one wavefront per leaf.
+// Each lane writes q rho of its atom as one LDS row; the coefficient sums are
+// then column sums (lane k owns coefficients k, k + 64, ...), in atom order.
+// Periodic: also per-leaf FP64 partial sums of q |t/L|^2 and q (t relative to
+// the cell centre).  Dynamic LDS: 64 x (K + 1) elements of T.
 template <typename T>
 __global__ __launch_bounds__(64) void k_p2m(Geo g, const vec4_t<T>* __restrict__ pos,
-                                            const int32_t* __restrict__ leaf_start,
-                                            const double* __restrict__ dom, T* __restrict__ mult,
-                                            double* __restrict__ leaf_part) {
-    __shared__ T acc[kKMax];
+                                            const int32_t* __restrict__ leaf_start_all,
+                                            const double* __restrict__ dom_all,
+                                            T* __restrict__ mult_all,
+                                            double* __restrict__ leaf_part_all) {
+    extern __shared__ __align__(16) unsigned char p2m_lds[];
+    const int32_t* leaf_start = leaf_start_all + (size_t)blockIdx.y * (g.nleaf + 1);
+    const double* dom = dom_all + 8 * blockIdx.y;
+    T* mult = mult_all + (size_t)blockIdx.y * g.nbox * g.Kp;
+    double* leaf_part = leaf_part_all + (size_t)blockIdx.y * g.nleaf * 2;
+    T* buf = (T*)p2m_lds;
+    const int S = g.K + 1;
     const int leaf = blockIdx.x;
     const int lane = threadIdx.x;
     const int b = leaf_start[leaf], n = leaf_start[leaf + 1] - b;
-    for (int k = lane; k < g.K; k += 64) acc[k] = T(0);
-    __syncthreads();
     const double edge = dom[3];
     const double h = edge / g.nb;
     const T ih = (T)(1.0 / h);
@@ -363,6 +409,9 @@ __global__ __launch_bounds__(64) void k_p2m(Geo g, const vec4_t<T>* __restrict__
     unmorton((uint32_t)leaf, cx, cy, cz);
     const double off[3] = {(cx + 0.5) * h - 0.5 * edge, (cy + 0.5) * h - 0.5 * edge,
                            (cz + 0.5) * h - 0.5 * edge};
+    T acc[kKMax / 64];
+#pragma unroll
+    for (int i = 0; i < kKMax / 64; ++i) acc[i] = T(0);
     for (int c0 = 0; c0 < n; c0 += 64) {
         const int j = c0 + lane;
         vec4_t<T> a;
@@ -374,18 +423,30 @@ __global__ __launch_bounds__(64) void k_p2m(Geo g, const vec4_t<T>* __restrict__
             s2 += (double)q * (t0 * t0 + t1 * t1 + t2 * t2) / (edge * edge);
             qs += (double)q;
         }
+        T* row = buf + lane * S;
         for_each_rho<T>(g.p, a.x * ih, a.y * ih, a.z * ih, [&](int kc, bool hs, T re, T im) {
-            const T v = wave_sum<T>(q * re);
-            if (lane == 0) acc[kc] += v;
-            if (hs) {
-                const T w = wave_sum<T>(q * im);
-                if (lane == 0) acc[kc + 1] += w;
-            }
+            row[kc] = q * re;
+            if (hs) row[kc + 1] = q * im;
         });
+        __syncthreads();
+        const int rows = min(64, n - c0);
+#pragma unroll
+        for (int i = 0; i < kKMax / 64; ++i) {
+            const int k = lane + 64 * i;
+            if (k < g.K) {
+                T v = T(0);
+                for (int r = 0; r < rows; ++r) v += buf[r * S + k];
+                acc[i] += v;
+            }
+        }
+        __syncthreads();
     }
-    __syncthreads();
     T* dst = mult + (size_t)(g.lev_off[g.depth] + leaf) * g.Kp;
-    for (int k = lane; k < g.K; k += 64) dst[k] = acc[k];
+#pragma unroll
+    for (int i = 0; i < kKMax / 64; ++i) {
+        const int k = lane + 64 * i;
+        if (k < g.K) dst[k] = acc[i];
+    }
     if (g.periodic) {
         s2 = wave_sum<double>(s2);
         qs = wave_sum<double>(qs);
@@ -396,28 +457,39 @@ __global__ __launch_bounds__(64) void k_p2m(Geo g, const vec4_t<T>* __restrict__
     }
 }
 
-// M2M for the parents at level lev (children at lev + 1): one block per parent,
-// thread r computes output coefficient r.  Output degree l only depends on
-// child degrees <= l.  Ops are stored transposed: opT[c][k][r].
+// M2M for the parents at level lev (children at lev + 1): one block per
+// parent; the 8 K (child octant, output row) dot products are spread over the
+// block, then summed over octants in a fixed order.  Output degree l only
+// depends on child degrees <= l.  Ops are stored transposed: opT[c][k][r].
 template <typename Tin, typename Tout>
-__global__ __launch_bounds__(256) void k_m2m(Geo g, int lev, const Tin* __restrict__ mult_in,
-                                             const Tin* __restrict__ opT, Tout* __restrict__ out,
-                                             int out_stride) {
+__global__ __launch_bounds__(256) void k_m2m(Geo g, int lev, const Tin* __restrict__ mult_all,
+                                             const Tin* __restrict__ opT, Tout* __restrict__ out_all,
+                                             int out_stride, int64_t out_rstride) {
     __shared__ Tin ch[8][kKMax];
+    __shared__ Tout red[8][kKMax];
+    const Tin* mult_in = mult_all + (size_t)blockIdx.y * g.nbox * g.Kp;
+    Tout* out = out_all + (size_t)blockIdx.y * out_rstride;
     const int parent = blockIdx.x;
     const Tin* src = mult_in + (size_t)(g.lev_off[lev + 1] + 8 * parent) * g.Kp;
-    for (int i = threadIdx.x; i < 8 * g.K; i += blockDim.x) ch[i / g.K][i % g.K] = src[(size_t)(i / g.K) * g.Kp + i % g.K];
+    for (int i = threadIdx.x; i < 8 * g.K; i += blockDim.x)
+        ch[i / g.K][i % g.K] = src[(size_t)(i / g.K) * g.Kp + i % g.K];
     __syncthreads();
-    const int r = threadIdx.x;
-    if (r >= g.K) return;
-    const int l = (int)sqrtf((float)r + 0.5f);
-    const int kend = (l + 1) * (l + 1);
-    Tout acc = Tout(0);
-    for (int c = 0; c < 8; ++c) {
-        const Tin* A = opT + (size_t)c * g.K * g.K;
-        for (int k = 0; k < kend; ++k) acc += (Tout)A[(size_t)k * g.K + r] * (Tout)ch[c][k];
+    for (int it = threadIdx.x; it < 8 * g.K; it += blockDim.x) {
+        const int c = it / g.K, r = it % g.K;
+        const int l = (int)sqrtf((float)r + 0.5f);
+        const int kend = (l + 1) * (l + 1);
+        const Tin* A = opT + (size_t)c * g.K * g.K + r;
+        Tout acc = Tout(0);
+        for (int k = 0; k < kend; ++k) acc += (Tout)A[(size_t)k * g.K] * (Tout)ch[c][k];
+        red[c][r] = acc;
     }
-    out[(size_t)parent * out_stride + r] = acc;
+    __syncthreads();
+    for (int r = threadIdx.x; r < g.K; r += blockDim.x) {
+        Tout acc = Tout(0);
+#pragma unroll
+        for (int c = 0; c < 8; ++c) acc += red[c][r];
+        out[(size_t)parent * out_stride + r] = acc;
+    }
 }
 
 // Root (periodic, FP64): lambda~_root = Lat mu~_root + (2 pi / 3) sum q |s/L|^2 e_0,
@@ -425,13 +497,20 @@ __global__ __launch_bounds__(256) void k_m2m(Geo g, int lev, const Tin* __restri
 // For a depth-0 tree the root is the leaf: mu~ is read from the level-0 slot
 // of mult and lambda~ is also stored into the level-0 slot of loc.
 template <typename T>
-__global__ __launch_bounds__(256) void k_root(Geo g, const double* __restrict__ leaf_part,
-                                              const double* __restrict__ root_m,
-                                              const T* __restrict__ mult,
+__global__ __launch_bounds__(256) void k_root(Geo g, const double* __restrict__ leaf_part_all,
+                                              const double* __restrict__ root_m_all,
+                                              const T* __restrict__ mult_all,
                                               const double* __restrict__ latT,
-                                              double* __restrict__ root_l, T* __restrict__ loc,
-                                              double* __restrict__ dom) {
+                                              double* __restrict__ root_l_all, T* __restrict__ loc_all,
+                                              double* __restrict__ dom_all) {
     __shared__ double s2s[256], qss[256], mu[kKMax];
+    const int rp = blockIdx.x;
+    const double* leaf_part = leaf_part_all + (size_t)rp * g.nleaf * 2;
+    const double* root_m = root_m_all + (size_t)rp * g.K;
+    const T* mult = mult_all + (size_t)rp * g.nbox * g.Kp;
+    double* root_l = root_l_all + (size_t)rp * g.K;
+    T* loc = loc_all + (size_t)rp * g.nbox * g.Kp;
+    double* dom = dom_all + 8 * rp;
     double s2 = 0.0, qs = 0.0;
     for (int i = threadIdx.x; i < g.nleaf; i += 256) {
         s2 += leaf_part[2 * i];
@@ -467,10 +546,12 @@ __global__ __launch_bounds__(256) void k_root(Geo g, const double* __restrict__ 
 // Interaction list: children of the parent's 27 neighbours (periodic images
 // wrapped) that are not adjacent to the target.  bankT[o][k][r].
 template <typename T>
-__global__ __launch_bounds__(256) void k_m2l_plain(Geo g, const T* __restrict__ mult,
+__global__ __launch_bounds__(256) void k_m2l_plain(Geo g, const T* __restrict__ mult_all,
                                                    const T* __restrict__ bankT,
-                                                   T* __restrict__ loc) {
+                                                   T* __restrict__ loc_all) {
     __shared__ T src[kKMax];
+    const T* mult = mult_all + (size_t)blockIdx.y * g.nbox * g.Kp;
+    T* loc = loc_all + (size_t)blockIdx.y * g.nbox * g.Kp;
     // locate (level, box) of this block
     int lev = g.lmin;
     int64_t bidx = blockIdx.x;
@@ -644,6 +725,9 @@ __global__ __launch_bounds__(256) void k_m2l_f32(Geo g, M2LGeom mg, const M2LTas
     float* B = lds_f32 + mg.RP * mg.SA;
     const M2LTask tk = tasks[blockIdx.x];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    mult += (size_t)blockIdx.y * g.nbox * g.Kp;
+    loc += (size_t)blockIdx.y * g.nbox * g.Kp;
+    if (part) part += (size_t)blockIdx.y * mg.nchunk * mg.nt_all * g.Kp;
     const int half = tk.lev >= 1 ? (1 << (tk.lev - 1)) : 1;
     const bool active = tk.tile * kM2LTile + 16 * wave < half * half * half;
     mf4 acc[RT];
@@ -684,6 +768,9 @@ __global__ __launch_bounds__(256) void k_m2l_f64(Geo g, M2LGeom mg, const M2LTas
     double* B = lds_f64 + mg.RP * mg.SA;
     const M2LTask tk = tasks[blockIdx.x];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    mult += (size_t)blockIdx.y * g.nbox * g.Kp;
+    loc += (size_t)blockIdx.y * g.nbox * g.Kp;
+    if (part) part += (size_t)blockIdx.y * mg.nchunk * mg.nt_all * g.Kp;
     const int half = tk.lev >= 1 ? (1 << (tk.lev - 1)) : 1;
     const bool active = tk.tile * kM2LTile + 16 * wave < half * half * half;
     md4 acc[RT];
@@ -728,6 +815,9 @@ __global__ __launch_bounds__(256) void k_m2l_bf16x3(Geo g, M2LGeom mg,
     __bf16* Bl = Bh + kM2LTile * mg.SB;
     const M2LTask tk = tasks[blockIdx.x];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    mult += (size_t)blockIdx.y * g.nbox * g.Kp;
+    loc += (size_t)blockIdx.y * g.nbox * g.Kp;
+    if (part) part += (size_t)blockIdx.y * mg.nchunk * mg.nt_all * g.Kp;
     const int half = tk.lev >= 1 ? (1 << (tk.lev - 1)) : 1;
     const bool active = tk.tile * kM2LTile + 16 * wave < half * half * half;
     mf4 acc[RT];
@@ -766,9 +856,11 @@ __global__ __launch_bounds__(256) void k_m2l_bf16x3(Geo g, M2LGeom mg,
 
 // Sum the offset-chunk partials into the local expansions (fixed chunk order).
 template <typename T>
-__global__ __launch_bounds__(256) void k_m2l_reduce(Geo g, M2LGeom mg, const T* __restrict__ part,
-                                                    T* __restrict__ loc) {
+__global__ __launch_bounds__(256) void k_m2l_reduce(Geo g, M2LGeom mg, const T* __restrict__ part_all,
+                                                    T* __restrict__ loc_all) {
     const int64_t tot = mg.nt_all * g.Kp;
+    const T* part = part_all + (size_t)blockIdx.y * mg.nchunk * tot;
+    T* loc = loc_all + (size_t)blockIdx.y * g.nbox * g.Kp;
     for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < tot;
          e += (int64_t)gridDim.x * blockDim.x) {
         if ((int)(e % g.Kp) >= g.K) continue;
@@ -781,47 +873,107 @@ __global__ __launch_bounds__(256) void k_m2l_reduce(Geo g, M2LGeom mg, const T* 
 // ------------------------------------------------------------------ downward pass
 
 // L2L into the children at level lev + 1 from their parents at level lev:
-// lambda~_child[r] += sum_{k >= l(r)^2} B_c[r][k] lambda~_parent[k].
+// lambda~_child[r] += sum_{k >= l(r)^2} B_c[r][k] lambda~_parent[k].  One block
+// per child; each output row's dot product is split over 4 threads (k
+// interleaved) and combined in a fixed order.
 template <typename Tin, typename Tout>
-__global__ __launch_bounds__(256) void k_l2l(Geo g, int lev, const Tin* __restrict__ par,
-                                             int par_stride, const Tout* __restrict__ opT,
-                                             Tout* __restrict__ loc) {
+__global__ __launch_bounds__(256) void k_l2l(Geo g, int lev, const Tin* __restrict__ par_all,
+                                             int par_stride, int64_t par_rstride,
+                                             const Tout* __restrict__ opT, Tout* __restrict__ loc_all) {
     __shared__ Tin pl[kKMax];
+    __shared__ Tout red[4][kKMax];
+    const Tin* par = par_all + (size_t)blockIdx.y * par_rstride;
+    Tout* loc = loc_all + (size_t)blockIdx.y * g.nbox * g.Kp;
     const int child = blockIdx.x;
     const int parent = child >> 3, c = child & 7;
     for (int k = threadIdx.x; k < g.K; k += blockDim.x) pl[k] = par[(size_t)parent * par_stride + k];
     __syncthreads();
-    const int r = threadIdx.x;
-    if (r >= g.K) return;
-    const int l = (int)sqrtf((float)r + 0.5f);
     const Tout* B = opT + (size_t)c * g.K * g.K;
-    Tout acc = Tout(0);
-    for (int k = l * l; k < g.K; ++k) acc += B[(size_t)k * g.K + r] * (Tout)pl[k];
-    loc[(size_t)(g.lev_off[lev + 1] + child) * g.Kp + r] += acc;
+    for (int it = threadIdx.x; it < 4 * g.K; it += blockDim.x) {
+        const int q = it / g.K, r = it % g.K;
+        const int l = (int)sqrtf((float)r + 0.5f);
+        Tout acc = Tout(0);
+        for (int k = l * l + q; k < g.K; k += 4) acc += B[(size_t)k * g.K + r] * (Tout)pl[k];
+        red[q][r] = acc;
+    }
+    __syncthreads();
+    for (int r = threadIdx.x; r < g.K; r += blockDim.x)
+        loc[(size_t)(g.lev_off[lev + 1] + child) * g.Kp + r] += (red[0][r] + red[1][r]) + (red[2][r] + red[3][r]);
 }
 
 // ------------------------------------------------------------------ near + far field
 
-// Per target leaf (4 wavefronts): the sources of the 27 neighbour leaves
-// (periodic images through integer leaf offsets) are staged through LDS in
-// tiles of 256 and split between the wavefronts; each lane owns one target.
-// Wavefront 0 adds the far field from the leaf's local expansion (L2P with its
-// gradient) and the background term, then writes potential, force, the
-// per-leaf energy partial and (qB - qA) phi for the site sums.
+template <typename T> __device__ __forceinline__ T inv_sqrt(T v);
+template <> __device__ __forceinline__ float inv_sqrt<float>(float v) { return rsqrtf(v); }
+template <> __device__ __forceinline__ double inv_sqrt<double>(double v) { return rsqrt(v); }
+
+// Like for_each_rho, but only the orders m = m0, m0 + dm, ... are visited (the
+// diagonal Rh_m^m chain is still advanced for every m): lets several
+// wavefronts share one expansion evaluation.
+template <typename T, typename Fn>
+__device__ __forceinline__ void for_rho_orders(int p, int m0, int dm, T x, T y, T z, Fn&& fn) {
+    const T r2 = x * x + y * y + z * z;
+    T cre = T(1), cim = T(0);
+    for (int m = 0; m <= p; ++m) {
+        if (m > 0) {
+            const T fm = (T)c_rho.f[m];
+            const T nre = fm * (x * cre - y * cim);
+            const T nim = fm * (x * cim + y * cre);
+            cre = nre;
+            cim = nim;
+        }
+        if (m < m0 || (m - m0) % dm != 0) continue;
+        const int k0 = (m == 0) ? 0 : 2 * m - 1;
+        fn(m * m + k0, m > 0, cre, cim);
+        if (m + 1 > p) continue;
+        T p0re = cre, p0im = cim;
+        T p1re = (T)c_rho.a[(m + 1) * (kPMax + 1) + m] * z * cre;
+        T p1im = (T)c_rho.a[(m + 1) * (kPMax + 1) + m] * z * cim;
+        fn((m + 1) * (m + 1) + k0, m > 0, p1re, p1im);
+        for (int l = m + 2; l <= p; ++l) {
+            const T al = (T)c_rho.a[l * (kPMax + 1) + m];
+            const T bl = (T)c_rho.b[l * (kPMax + 1) + m];
+            const T nre = al * z * p1re - bl * r2 * p0re;
+            const T nim = al * z * p1im - bl * r2 * p0im;
+            p0re = p1re;
+            p0im = p1im;
+            p1re = nre;
+            p1im = nim;
+            fn(l * l + k0, m > 0, p1re, p1im);
+        }
+    }
+}
+
+constexpr int kNW = 8;  // wavefronts per target leaf in the near-field kernel
+
+// Per target leaf (kNW wavefronts, one lane per target): the sources of the 27
+// neighbour leaves (periodic images through integer leaf offsets) are staged
+// through LDS in tiles of 64 kNW and split between the wavefronts.  The far
+// field from the leaf's local expansion (L2P with its gradient) is split
+// between the wavefronts by order m.  Wavefront 0 adds the per-wave partials in
+// a fixed order, applies the periodic background term and writes potential,
+// force, the per-leaf energy partial and (qB - qA) phi for the site sums.
 template <typename T>
-__global__ __launch_bounds__(256) void k_near_far(
-    Geo g, const vec4_t<T>* __restrict__ pos, const int32_t* __restrict__ leaf_start,
-    const int32_t* __restrict__ perm, const double* __restrict__ dom,
-    const T* __restrict__ loc, const int32_t* __restrict__ gidx, const T* __restrict__ gcoef,
+__global__ __launch_bounds__(64 * kNW) void k_near_far(
+    Geo g, const RepDesc* __restrict__ reps, const vec4_t<T>* __restrict__ pos,
+    const int32_t* __restrict__ leaf_start_all, const int32_t* __restrict__ perm,
+    const double* __restrict__ dom_all, const T* __restrict__ loc_all,
+    const int32_t* __restrict__ gidx, const T* __restrict__ gcoef,
     const T* __restrict__ qA, const T* __restrict__ qB, const int32_t* __restrict__ site,
-    int64_t n_sites, T* __restrict__ phi_out, T* __restrict__ F_out,
-    double* __restrict__ leaf_energy, double* __restrict__ cphi) {
-    __shared__ vec4_t<T> tile[256];
+    T* __restrict__ phi_out, T* __restrict__ F_out,
+    double* __restrict__ leaf_energy_all, double* __restrict__ cphi) {
+    constexpr int NT = 64 * kNW;
+    const int64_t n_sites = reps[blockIdx.y].S;
+    const int32_t* leaf_start = leaf_start_all + (size_t)blockIdx.y * (g.nleaf + 1);
+    const double* dom = dom_all + 8 * blockIdx.y;
+    const T* loc = loc_all + (size_t)blockIdx.y * g.nbox * g.Kp;
+    double* leaf_energy = leaf_energy_all + (size_t)blockIdx.y * g.nleaf;
+    __shared__ vec4_t<T> tile[NT];
     __shared__ int nb_start[28], nb_cnt[28], nb_pre[29];
     __shared__ T nb_off[27][3];
     __shared__ T lam[kKMax];
     __shared__ T gr[3][kKgMax];
-    __shared__ T part[4][64][4];
+    __shared__ T part[kNW][4][64];
     const int leaf = blockIdx.x;
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     const int tb = leaf_start[leaf], tn = leaf_start[leaf + 1] - tb;
@@ -859,15 +1011,16 @@ __global__ __launch_bounds__(256) void k_near_far(
     const bool far = g.has_far;
     if (far) {
         const T* lsrc = loc + (size_t)(g.lev_off[g.depth] + leaf) * g.Kp;
-        for (int k = tid; k < g.K; k += 256) lam[k] = lsrc[k];
+        for (int k = tid; k < g.K; k += NT) lam[k] = lsrc[k];
     }
     __syncthreads();
     if (tid == 0) {
         nb_pre[0] = 0;
         for (int i = 0; i < 27; ++i) nb_pre[i + 1] = nb_pre[i] + nb_cnt[i];
+        nb_pre[28] = 0x7fffffff;
     }
     if (far) {
-        for (int e = tid; e < 3 * g.Kg; e += 256) {
+        for (int e = tid; e < 3 * g.Kg; e += NT) {
             const int a = e / g.Kg, r = e % g.Kg;
             T v = T(0);
             for (int t = 0; t < 4; ++t) {
@@ -887,65 +1040,77 @@ __global__ __launch_bounds__(256) void k_near_far(
         if (tj < tn) me = pos[tb + tj];
         else { me.x = me.y = me.z = me.w = T(0); }
         T ph = T(0), fx = T(0), fy = T(0), fz = T(0);
-        for (int s0 = 0; s0 < total; s0 += 256) {
+        for (int s0 = 0; s0 < total; s0 += NT) {
             __syncthreads();
             const int gsrc = s0 + tid;
             if (gsrc < total) {
-                int nbi = 0;
-                while (nb_pre[nbi + 1] <= gsrc) ++nbi;
-                vec4_t<T> a = pos[nb_start[nbi] + (gsrc - nb_pre[nbi])];
-                a.x += nb_off[nbi][0];
-                a.y += nb_off[nbi][1];
-                a.z += nb_off[nbi][2];
+                // neighbour holding source gsrc: largest i with nb_pre[i] <= gsrc
+                int lo = 0, hi = 27;
+                while (hi - lo > 1) {
+                    const int mid = (lo + hi) >> 1;
+                    if (nb_pre[mid] <= gsrc) lo = mid;
+                    else hi = mid;
+                }
+                vec4_t<T> a = pos[nb_start[lo] + (gsrc - nb_pre[lo])];
+                a.x += nb_off[lo][0];
+                a.y += nb_off[lo][1];
+                a.z += nb_off[lo][2];
                 tile[tid] = a;
             }
             __syncthreads();
             const int jb = wave * 64;
             const int je = min(jb + 64, total - s0);
+#pragma unroll 4
             for (int j = jb; j < je; ++j) {
                 const vec4_t<T> s = tile[j];
                 const T dx = me.x - s.x, dy = me.y - s.y, dz = me.z - s.z;
                 const T r2 = dx * dx + dy * dy + dz * dz;
-                const T ri = r2 > T(0) ? T(1) / sqrt(r2) : T(0);
+                const T ri = r2 > T(0) ? inv_sqrt<T>(r2) : T(0);
                 const T qr = s.w * ri;
-                const T qr3 = qr * ri * ri;
+                const T qr3 = qr * (ri * ri);
                 ph += qr;
                 fx += qr3 * dx;
                 fy += qr3 * dy;
                 fz += qr3 * dz;
             }
         }
-        part[wave][lane][0] = ph;
-        part[wave][lane][1] = fx;
-        part[wave][lane][2] = fy;
-        part[wave][lane][3] = fz;
+        if (far && tj < tn) {
+            // far field, orders m = wave, wave + kNW, ...
+            T fp = T(0), gx = T(0), gy = T(0), gz = T(0);
+            const int Kg = g.Kg;
+            for_rho_orders<T>(g.p, wave, kNW, me.x * ih, me.y * ih, me.z * ih,
+                              [&](int kc, bool has_s, T re, T im) {
+                                  fp += lam[kc] * re;
+                                  if (has_s) fp += lam[kc + 1] * im;
+                                  if (kc < Kg) {
+                                      gx += gr[0][kc] * re;
+                                      gy += gr[1][kc] * re;
+                                      gz += gr[2][kc] * re;
+                                      if (has_s) {
+                                          gx += gr[0][kc + 1] * im;
+                                          gy += gr[1][kc + 1] * im;
+                                          gz += gr[2][kc + 1] * im;
+                                      }
+                                  }
+                              });
+            ph += fp * ih;
+            fx -= gx * ih * ih;
+            fy -= gy * ih * ih;
+            fz -= gz * ih * ih;
+        }
+        part[wave][0][lane] = ph;
+        part[wave][1][lane] = fx;
+        part[wave][2][lane] = fy;
+        part[wave][3][lane] = fz;
         __syncthreads();
         if (wave == 0 && tj < tn) {
-            T p = part[0][lane][0] + part[1][lane][0] + part[2][lane][0] + part[3][lane][0];
-            T ex = part[0][lane][1] + part[1][lane][1] + part[2][lane][1] + part[3][lane][1];
-            T ey = part[0][lane][2] + part[1][lane][2] + part[2][lane][2] + part[3][lane][2];
-            T ez = part[0][lane][3] + part[1][lane][3] + part[2][lane][3] + part[3][lane][3];
-            if (far) {
-                T fp = T(0), gx = T(0), gy = T(0), gz = T(0);
-                const int Kg = g.Kg;
-                for_each_rho<T>(g.p, me.x * ih, me.y * ih, me.z * ih, [&](int kc, bool has_s, T re, T im) {
-                    fp += lam[kc] * re;
-                    if (has_s) fp += lam[kc + 1] * im;
-                    if (kc < Kg) {
-                        gx += gr[0][kc] * re;
-                        gy += gr[1][kc] * re;
-                        gz += gr[2][kc] * re;
-                        if (has_s) {
-                            gx += gr[0][kc + 1] * im;
-                            gy += gr[1][kc + 1] * im;
-                            gz += gr[2][kc + 1] * im;
-                        }
-                    }
-                });
-                p += fp * ih;
-                ex -= gx * ih * ih;
-                ey -= gy * ih * ih;
-                ez -= gz * ih * ih;
+            T p = T(0), ex = T(0), ey = T(0), ez = T(0);
+#pragma unroll
+            for (int w = 0; w < kNW; ++w) {
+                p += part[w][0][lane];
+                ex += part[w][1][lane];
+                ey += part[w][2][lane];
+                ez += part[w][3][lane];
             }
             if (g.periodic) {
                 // background: phi += (2 pi / 3) Q |t|^2 / V, field -= (4 pi / 3) Q t / V
@@ -980,9 +1145,10 @@ __global__ __launch_bounds__(256) void k_near_far(
     }
 }
 
-// Final reductions: block 0 -> E = k_e / 2 sum of the leaf partials (fixed
-// order); block 1 + s -> dVdl_s = sum over site s's atoms in caller order.
-__global__ __launch_bounds__(256) void k_reduce(Geo g, const double* __restrict__ leaf_energy,
+// Final reductions: block r < R -> E_r = k_e / 2 sum of replica r's leaf
+// partials (fixed order); block R + s -> dVdl_s = sum over global site s's
+// atoms in caller order.
+__global__ __launch_bounds__(256) void k_reduce(Geo g, int R, const double* __restrict__ leaf_energy,
                                                 const int32_t* __restrict__ site_start,
                                                 const int32_t* __restrict__ site_members,
                                                 const double* __restrict__ cphi,
@@ -991,57 +1157,61 @@ __global__ __launch_bounds__(256) void k_reduce(Geo g, const double* __restrict_
     __shared__ double red[256];
     __shared__ int32_t mem[kSiteCap];
     const int t = threadIdx.x;
+    const int b = blockIdx.x;
     double v = 0.0;
-    if (blockIdx.x == 0) {
-        for (int i = t; i < g.nleaf; i += 256) v += leaf_energy[i];
+    if (b < R) {
+        for (int i = t; i < g.nleaf; i += 256) v += leaf_energy[(size_t)b * g.nleaf + i];
     } else {
-        const int s = blockIdx.x - 1;
-        const int b = site_start[s], n = site_start[s + 1] - b;
+        const int s = b - R;
+        const int m0 = site_start[s], n = site_start[s + 1] - m0;
         if (n <= kSiteCap) {
-            for (int i = t; i < n; i += 256) mem[i] = site_members[b + i];
+            for (int i = t; i < n; i += 256) mem[i] = site_members[m0 + i];
             __syncthreads();
             lds_sort<kSiteCap>(mem, n);
             for (int i = t; i < n; i += 256) v += cphi[mem[i]];
         } else {
             if (t == 0) atomicOr(&status[1], kInfoBigSite);
-            for (int i = t; i < n; i += 256) v += cphi[site_members[b + i]];
+            for (int i = t; i < n; i += 256) v += cphi[site_members[m0 + i]];
         }
     }
     red[t] = v;
     __syncthreads();
-    for (int s = 128; s > 0; s >>= 1) {
-        if (t < s) red[t] += red[t + s];
+    for (int st = 128; st > 0; st >>= 1) {
+        if (t < st) red[t] += red[t + st];
         __syncthreads();
     }
     if (t == 0) {
-        if (blockIdx.x == 0) {
-            if (E) *E = 0.5 * g.coulomb_k * red[0];
+        if (b < R) {
+            if (E) E[b] = 0.5 * g.coulomb_k * red[0];
         } else if (dVdl) {
-            dVdl[blockIdx.x - 1] = red[0];
+            dVdl[b - R] = red[0];
         }
     }
 }
 
-// Adjoint of E for an upstream weight *gE (see fmm_eval_adjoint).
+// Adjoint of E for the upstream weights gE[r] (see fmm_eval_adjoint).
 template <typename T>
-__global__ __launch_bounds__(256) void k_adjoint(int64_t n, const int32_t* __restrict__ site,
-                                                 int64_t n_sites, const double* __restrict__ lam,
+__global__ __launch_bounds__(256) void k_adjoint(const RepDesc* __restrict__ reps,
+                                                 const int32_t* __restrict__ site,
+                                                 const double* __restrict__ lam,
                                                  const double* __restrict__ gE,
                                                  const T* __restrict__ F, const T* __restrict__ phi,
                                                  const double* __restrict__ dVdl,
                                                  T* __restrict__ gx, T* __restrict__ gqA,
                                                  T* __restrict__ gqB, double* __restrict__ glam) {
-    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    const double w = *gE;
-    if (glam && i < n_sites) glam[i] = w * dVdl[i];
-    if (i >= n) return;
+    const RepDesc rd = reps[blockIdx.y];
+    const int64_t il = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    const double w = gE[blockIdx.y];
+    if (glam && il < rd.S) glam[rd.s0 + il] = w * dVdl[rd.s0 + il];
+    if (il >= rd.n) return;
+    const int64_t i = rd.a0 + il;
     if (gx) {
         gx[3 * i] = (T)(-w * (double)F[3 * i]);
         gx[3 * i + 1] = (T)(-w * (double)F[3 * i + 1]);
         gx[3 * i + 2] = (T)(-w * (double)F[3 * i + 2]);
     }
     const int32_t s = site[i];
-    const double l = (s >= 0 && s < n_sites) ? lam[s] : 0.0;
+    const double l = (s >= 0 && s < rd.S) ? lam[rd.s0 + s] : 0.0;
     const double p = (double)phi[i];
     if (gqA) gqA[i] = (T)(w * (1.0 - l) * p);
     if (gqB) gqB[i] = (T)(w * l * p);

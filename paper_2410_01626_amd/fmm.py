@@ -47,7 +47,7 @@ class fmm_params(ctypes.Structure):
         ("m2l_kernel", ctypes.c_int32),
         ("m2l_chunk", ctypes.c_int32),
         ("p2p_waves", ctypes.c_int32),
-        ("reserved", ctypes.c_int32),
+        ("graph", ctypes.c_int32),
     ]
 
 
@@ -176,7 +176,7 @@ class Plan:
                  precision: str = "fp64", coulomb_k: float = 1.0, max_atoms: int = 1,
                  max_sites: int = 1, max_replicas: int = 1, check: bool = False,
                  stream=None, device=None, m2l_kernel: int = 0, m2l_chunk: int = 0,
-                 p2p_waves: int = 0):
+                 p2p_waves: int = 0, graph: bool = False):
         import torch
         dev = torch.device(device) if device is not None else torch.device("cuda")
         if dev.type == "cuda" and dev.index is None:
@@ -188,7 +188,8 @@ class Plan:
         self.params = fmm_params(depth, order, FMM_PERIODIC if periodic else FMM_OPEN,
                                  PRECISIONS[precision], float(coulomb_k), int(max_atoms),
                                  int(max_sites), int(max_replicas), 1 if check else 0,
-                                 int(m2l_kernel), int(m2l_chunk), int(p2p_waves), 0)
+                                 int(m2l_kernel), int(m2l_chunk), int(p2p_waves),
+                                 1 if graph else 0)
         self.periodic = periodic
         self.precision = precision
         self.dtype = torch.float64 if precision == "fp64" else torch.float32
@@ -238,15 +239,18 @@ class Plan:
         b = np.ascontiguousarray(np.broadcast_to(np.asarray(box, dtype=np.float64), (3,)))
         return b, ctypes.c_void_p(b.ctypes.data)
 
-    def eval(self, x, qA, qB, site, lam, box=None, want=("E", "F", "phi", "dVdl")):
-        """Enqueue fmm_eval; returns dict of output tensors (E is a 1-element FP64 tensor)."""
+    def eval(self, x, qA, qB, site, lam, box=None, want=("E", "F", "phi", "dVdl"), out=None):
+        """Enqueue fmm_eval; returns dict of output tensors (E is a 1-element FP64 tensor).
+
+        `out` may hold preallocated outputs (reused pointers let a graph plan replay)."""
         import torch
         n, S = self._inputs(x, qA, qB, site, lam)
-        opt = dict(device=self.device)
-        out = {"E": torch.empty(1, dtype=torch.float64, **opt)}
-        out["F"] = torch.empty((n, 3), dtype=self.dtype, **opt) if "F" in want else None
-        out["phi"] = torch.empty(n, dtype=self.dtype, **opt) if "phi" in want else None
-        out["dVdl"] = torch.empty(S, dtype=torch.float64, **opt) if "dVdl" in want else None
+        if out is None:
+            opt = dict(device=self.device)
+            out = {"E": torch.empty(1, dtype=torch.float64, **opt)}
+            out["F"] = torch.empty((n, 3), dtype=self.dtype, **opt) if "F" in want else None
+            out["phi"] = torch.empty(n, dtype=self.dtype, **opt) if "phi" in want else None
+            out["dVdl"] = torch.empty(S, dtype=torch.float64, **opt) if "dVdl" in want else None
         b, bp = self._box(box)
         st = fmm_eval(self.handle, n, _ptr(x), _ptr(qA), _ptr(qB), _ptr(site), S, _ptr(lam), bp,
                       _ptr(out["E"]), _ptr(out["F"]), _ptr(out["phi"]), _ptr(out["dVdl"]))

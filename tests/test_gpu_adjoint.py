@@ -1,0 +1,141 @@
+"""Adjoint (reverse mode) of the FMM energy through fmm_eval_adjoint and the
+torch.autograd wrapper: finite differences of the FMM's own energy and the
+oracle's gradient."""
+import numpy as np
+import pytest
+
+from gpu_util import TOL_F, reference
+from paper_2410_01626_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def _tensors(d, dt, dev):
+    import torch
+    return (torch.tensor(d["x"], dtype=dt, device=dev, requires_grad=True),
+            torch.tensor(d["qA"], dtype=dt, device=dev, requires_grad=True),
+            torch.tensor(d["qB"], dtype=dt, device=dev, requires_grad=True),
+            torch.tensor(d["site"], dtype=torch.int32, device=dev),
+            torch.tensor(d["lam"], dtype=torch.float64, device=dev, requires_grad=True))
+
+
+def _plan(d, prec, dev):
+    from paper_2410_01626_amd import fmm
+    return fmm.Plan(d["depth"], d["order"], periodic=d["periodic"], precision=prec,
+                    max_atoms=d["x"].shape[0], max_sites=max(d["lam"].size, 1), device=dev)
+
+
+@pytest.mark.parametrize("periodic", [False, True])
+def test_adjoint_matches_finite_differences_fp64(periodic):
+    import torch
+    from paper_2410_01626_amd.autograd import fmm_coulomb
+    dev = torch.device("cuda:0")
+    if periodic:
+        d = W.tiny_periodic(41, n=400, edge=1.5, n_sites=3, depth=2, order=8)
+    else:
+        d = W.open_cube()
+    plan = _plan(d, "fp64", dev)
+    box = d["box"] if periodic else None
+    x, qA, qB, site, lam = _tensors(d, torch.float64, dev)
+    w = 0.7317
+    E, F, phi, dVdl = fmm_coulomb(plan, x, qA, qB, site, lam, box)
+    (w * E).sum().backward()
+
+    def energy(**kw):
+        args = dict(x=x.detach(), qA=qA.detach(), qB=qB.detach(), lam=lam.detach())
+        args.update(kw)
+        out = plan.eval(args["x"], args["qA"], args["qB"], site, args["lam"], box=box)
+        return out["E"].item()
+
+    # positions: central difference h = 1e-4 nm on atoms at least h from leaf faces
+    edge = d["box"][0] if periodic else d["edge"]
+    h = 1e-4
+    rng = np.random.default_rng(0)
+    picks = rng.choice(d["x"].shape[0], 8, replace=False)
+    gx = x.grad.cpu().numpy()
+    for i in picks:
+        for a in range(3):
+            xp = x.detach().clone(); xp[i, a] += h
+            xm = x.detach().clone(); xm[i, a] -= h
+            fd = w * (energy(x=xp) - energy(x=xm)) / (2 * h)
+            assert gx[i, a] == pytest.approx(fd, rel=1e-5, abs=1e-6 * np.abs(gx).max()), (i, a)
+    # charges and lambda: E is exactly quadratic, the difference is exact
+    hq = 1e-4
+    gqA, gqB, gl = qA.grad.cpu().numpy(), qB.grad.cpu().numpy(), lam.grad.cpu().numpy()
+    site_atoms = np.flatnonzero(d["site"] >= 0)[:4].tolist() + [int(np.flatnonzero(d["site"] < 0)[0])]
+    for i in site_atoms:
+        for t, g in ((qA, gqA), (qB, gqB)):
+            tp = t.detach().clone(); tp[i] += hq
+            tm = t.detach().clone(); tm[i] -= hq
+            key = "qA" if t is qA else "qB"
+            fd = w * (energy(**{key: tp}) - energy(**{key: tm})) / (2 * hq)
+            assert g[i] == pytest.approx(fd, rel=1e-7, abs=1e-9), (key, i)
+    for s in range(d["lam"].size):
+        lp = lam.detach().clone(); lp[s] += hq
+        lm = lam.detach().clone(); lm[s] -= hq
+        fd = w * (energy(lam=lp) - energy(lam=lm)) / (2 * hq)
+        assert gl[s] == pytest.approx(fd, rel=1e-7, abs=1e-9), s
+
+
+@pytest.mark.parametrize("prec", ["fp64", "f32", "bf16x3"])
+def test_adjoint_matches_oracle_gradient(prec):
+    """Gradient of the oracle's energy: dE/dx = -F, dE/dqA = (1-l) phi,
+    dE/dqB = l phi, dE/dl = dV/dl; within the FMM tolerance at p = 8."""
+    import torch
+    from paper_2410_01626_amd.autograd import fmm_coulomb
+    dev = torch.device("cuda:0")
+    d = W.tiny_periodic(42, n=2000, edge=2.2, n_sites=5, depth=3, order=8)
+    ref = reference(d)
+    plan = _plan(d, prec, dev)
+    dt = plan.dtype
+    x, qA, qB, site, lam = _tensors(d, dt, dev)
+    E, F, phi, dVdl = fmm_coulomb(plan, x, qA, qB, site, lam, d["box"])
+    g = torch.tensor([-1.25], dtype=torch.float64, device=dev)
+    gx, gqA, gqB, gl = torch.autograd.grad(E, [x, qA, qB, lam], grad_outputs=g)
+    w = -1.25
+    lam_s = np.where(d["site"] >= 0, d["lam"][np.maximum(d["site"], 0)], 0.0)
+    exp_x = -w * ref["F"]
+    exp_qA = w * (1 - lam_s) * ref["phi"]
+    exp_qB = w * lam_s * ref["phi"]
+    exp_l = w * ref["dVdl"]
+    tol = TOL_F[8]
+    for got, exp in ((gx, exp_x), (gqA, exp_qA), (gqB, exp_qB)):
+        got = got.double().cpu().numpy()
+        err = np.sqrt(np.sum((got - exp) ** 2) / np.sum(exp ** 2))
+        assert err <= tol, err
+    gl = gl.cpu().numpy()
+    assert np.abs(gl - exp_l).max() <= tol * np.sqrt(np.mean(exp_l ** 2))
+    # unsited atoms get no qB gradient
+    assert np.all(gqB.cpu().numpy()[d["site"] < 0] == 0)
+
+
+def test_backward_recomputes_from_inputs():
+    """The adjoint uses only the saved inputs: running another evaluation on
+    the same plan between forward and backward changes nothing."""
+    import torch
+    from paper_2410_01626_amd.autograd import fmm_coulomb
+    dev = torch.device("cuda:0")
+    d = W.open_cube()
+    plan = _plan(d, "fp64", dev)
+    x, qA, qB, site, lam = _tensors(d, torch.float64, dev)
+    E, *_ = fmm_coulomb(plan, x, qA, qB, site, lam)
+    g1 = torch.autograd.grad(E, [x, qA, qB, lam], retain_graph=True)
+    d2 = W.random_open(43, n=900, edge=2.0, n_sites=4, depth=2, order=6)
+    x2, qA2, qB2, site2, lam2 = _tensors(d2, torch.float64, dev)
+    plan.eval(x2.detach(), qA2.detach(), qB2.detach(), site2, lam2.detach())
+    g2 = torch.autograd.grad(E, [x, qA, qB, lam])
+    for a, b in zip(g1, g2):
+        assert torch.equal(a, b)
+
+
+def test_second_order_request_is_rejected():
+    import torch
+    from paper_2410_01626_amd.autograd import fmm_coulomb
+    dev = torch.device("cuda:0")
+    d = W.open_cube()
+    plan = _plan(d, "fp64", dev)
+    x, qA, qB, site, lam = _tensors(d, torch.float64, dev)
+    E, F, phi, dVdl = fmm_coulomb(plan, x, qA, qB, site, lam)
+    assert not F.requires_grad and not phi.requires_grad
+    with pytest.raises(RuntimeError):
+        F.sum().backward()

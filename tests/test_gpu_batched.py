@@ -1,0 +1,144 @@
+"""Batched replicas (one launch per phase over all replicas) and HIP-graph
+replay, through the C ABI."""
+import numpy as np
+import pytest
+
+from gpu_util import TOL_F, assert_within, errors, reference
+from paper_2410_01626_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def _concat(reps):
+    atom_off = np.cumsum([0] + [d["x"].shape[0] for d in reps])
+    site_off = np.cumsum([0] + [d["lam"].size for d in reps])
+    cat = {k: np.concatenate([d[k] for d in reps]) for k in ("x", "qA", "qB", "site", "lam")}
+    boxes = None
+    if reps[0]["periodic"]:
+        boxes = np.stack([d["box"] for d in reps])
+    return atom_off, site_off, cat, boxes
+
+
+def _dev(arrs, dt, dev):
+    import torch
+    return (torch.tensor(arrs["x"], dtype=dt, device=dev),
+            torch.tensor(arrs["qA"], dtype=dt, device=dev),
+            torch.tensor(arrs["qB"], dtype=dt, device=dev),
+            torch.tensor(arrs["site"], dtype=torch.int32, device=dev),
+            torch.tensor(arrs["lam"], dtype=torch.float64, device=dev))
+
+
+def _reps(periodic):
+    if periodic:
+        return [W.tiny_periodic(60 + i, n=n, edge=e, n_sites=s, depth=3, order=6)
+                for i, (n, e, s) in enumerate([(1800, 2.0, 3), (900, 1.4, 2), (2600, 2.6, 4),
+                                               (400, 1.1, 1)])]
+    return [W.random_open(70 + i, n=n, edge=e, n_sites=s, depth=3, order=6)
+            for i, (n, e, s) in enumerate([(2500, 2.5, 3), (700, 1.2, 2), (1600, 2.0, 0),
+                                           (3100, 3.0, 5), (50, 0.6, 1)])]
+
+
+@pytest.mark.parametrize("periodic", [False, True])
+@pytest.mark.parametrize("prec", ["fp64", "f32", "bf16x3"])
+def test_batched_equals_single_evaluations_bitwise(periodic, prec):
+    import torch
+    from paper_2410_01626_amd import fmm
+    dev = torch.device("cuda:0")
+    reps = _reps(periodic)
+    ao, so, cat, boxes = _concat(reps)
+    plan = fmm.Plan(3, 6, periodic=periodic, precision=prec, max_atoms=int(ao[-1]),
+                    max_sites=max(int(so[-1]), 1), max_replicas=len(reps), device=dev)
+    t = _dev(cat, plan.dtype, dev)
+    out = plan.eval_batched(ao, so, *t, boxes=boxes)
+    torch.cuda.synchronize()
+    for r, d in enumerate(reps):
+        tr = _dev(d, plan.dtype, dev)
+        single = plan.eval(*tr, box=d["box"] if periodic else None)
+        torch.cuda.synchronize()
+        a0, a1, s0, s1 = ao[r], ao[r + 1], so[r], so[r + 1]
+        assert out["E"][r].item() == single["E"].item(), r
+        assert torch.equal(out["F"][a0:a1], single["F"]), r
+        assert torch.equal(out["phi"][a0:a1], single["phi"]), r
+        assert torch.equal(out["dVdl"][s0:s1], single["dVdl"]), r
+
+
+def test_batched_replicas_against_oracle():
+    """Uneven replicas at different pH (lambda near 0 or 1), p = 8."""
+    import torch
+    from paper_2410_01626_amd import fmm
+    dev = torch.device("cuda:0")
+    reps = W.replicas(sizes=[2000, 3500, 1200, 2800], depth=3, order=8)
+    ao, so, cat, _ = _concat(reps)
+    for prec in ("fp64", "bf16x3"):
+        plan = fmm.Plan(3, 8, periodic=False, precision=prec, max_atoms=int(ao[-1]),
+                        max_sites=int(so[-1]), max_replicas=len(reps), device=dev)
+        out = plan.eval_batched(ao, so, *_dev(cat, plan.dtype, dev))
+        torch.cuda.synchronize()
+        for r, d in enumerate(reps):
+            ref = reference(d)
+            a0, a1, s0, s1 = ao[r], ao[r + 1], so[r], so[r + 1]
+            got = {"E": out["E"][r].item(), "F": out["F"][a0:a1].double().cpu().numpy(),
+                   "phi": out["phi"][a0:a1].double().cpu().numpy(),
+                   "dVdl": out["dVdl"][s0:s1].cpu().numpy()}
+            assert_within(errors(got, ref), 8, label="replica %d %s" % (r, prec))
+
+
+@pytest.mark.parametrize("prec", ["fp64", "bf16x3"])
+def test_graph_replay_matches_eager(prec):
+    """A graph plan replays its captured evaluation: several replays with eager
+    work and synchronisations in between, an in-place input change between
+    replays, each replay checked against an eager plan."""
+    import torch
+    from paper_2410_01626_amd import fmm
+    dev = torch.device("cuda:0")
+    d = W.tiny_periodic(80, n=3000, edge=2.3, n_sites=4, depth=3, order=8)
+    eager = fmm.Plan(3, 8, periodic=True, precision=prec, max_atoms=3000, max_sites=4, device=dev)
+    stream = torch.cuda.Stream(dev)
+    gplan = fmm.Plan(3, 8, periodic=True, precision=prec, max_atoms=3000, max_sites=4, device=dev,
+                     stream=stream, graph=True)
+    t = _dev(d, eager.dtype, dev)
+    out = {"E": torch.empty(1, dtype=torch.float64, device=dev),
+           "F": torch.empty((3000, 3), dtype=eager.dtype, device=dev),
+           "phi": torch.empty(3000, dtype=eager.dtype, device=dev),
+           "dVdl": torch.empty(4, dtype=torch.float64, device=dev)}
+    rng = np.random.default_rng(0)
+    for rep in range(5):
+        if rep == 3:  # change the inputs in place: same pointers, new values
+            with torch.no_grad():
+                t[4].copy_(torch.tensor(rng.uniform(0, 1, 4), device=dev))
+                t[0].add_(0.01)
+        torch.cuda.synchronize()
+        with torch.cuda.stream(stream):
+            gplan.eval(*t, box=d["box"], out=out)
+        stream.synchronize()
+        ref = eager.eval(*t, box=d["box"])
+        junk = torch.randn(1000, device=dev).sum()  # unrelated eager work between replays
+        torch.cuda.synchronize()
+        assert junk.isfinite()
+        assert out["E"].item() == ref["E"].item(), rep
+        assert torch.equal(out["F"], ref["F"]), rep
+        assert torch.equal(out["phi"], ref["phi"]), rep
+        assert torch.equal(out["dVdl"], ref["dVdl"]), rep
+
+
+def test_graph_batched_replay():
+    import torch
+    from paper_2410_01626_amd import fmm
+    dev = torch.device("cuda:0")
+    reps = _reps(False)
+    ao, so, cat, _ = _concat(reps)
+    stream = torch.cuda.Stream(dev)
+    kw = dict(periodic=False, precision="f32", max_atoms=int(ao[-1]), max_sites=int(so[-1]),
+              max_replicas=len(reps), device=dev)
+    eager = fmm.Plan(3, 6, **kw)
+    gplan = fmm.Plan(3, 6, stream=stream, graph=True, **kw)
+    t = _dev(cat, torch.float32, dev)
+    ref = eager.eval_batched(ao, so, *t)
+    torch.cuda.synchronize()
+    for _ in range(3):
+        with torch.cuda.stream(stream):
+            got = gplan.eval_batched(ao, so, *t)
+        stream.synchronize()
+        assert torch.equal(got["E"], ref["E"])
+        assert torch.equal(got["F"], ref["F"])
+        assert torch.equal(got["dVdl"], ref["dVdl"])

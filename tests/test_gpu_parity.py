@@ -187,7 +187,7 @@ def test_check_mode_reports_bad_input():
 
 # ---------------------------------------------------------------- matrix-core M2L
 
-@pytest.mark.parametrize("prec,tol", [("fp64", 1e-12), ("f32", 2e-6), ("bf16x3", 2e-5)])
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-12), ("f32", 1e-5), ("bf16x3", 3e-5)])
 @pytest.mark.parametrize("periodic", [False, True])
 def test_matrix_core_m2l_matches_plain(prec, tol, periodic):
     """The matrix-core M2L (FP64 / FP32 / bf16 three-product) and the plain
