@@ -88,7 +88,7 @@ typedef enum { FMM_FP64 = 0, FMM_MIXED_F32 = 1, FMM_MIXED_BF16X3 = 2 } fmm_preci
  *   m2l_kernel  0 = automatic, 1 = plain (vector ALU) M2L, 2 = matrix-core M2L
  *               (available for p <= 10; FP64 needs p <= 8)
  *   m2l_chunk   offsets per matrix-core M2L work-group (0 = automatic, else 1..189)
- *   p2p_waves   reserved tuning knob of the near-field kernel (0 = automatic)
+ *   p2p_waves   wavefronts per leaf in the near-field kernel: 4, 8 or 16 (0 = 8)
  *   graph       1 = record the launch sequence of an evaluation in a HIP graph on
  *               first use and replay the graph while every argument (pointers,
  *               sizes, boxes, replica offsets) is unchanged; needs a non-NULL
@@ -188,6 +188,14 @@ void fmm_plan_destroy(fmm_plan_t plan);
  *         phase and out[8..15] = number of timed instances of each phase. */
 #define FMM_NPHASES 8
 fmm_status fmm_profile(fmm_plan_t plan, int32_t mode, int32_t capacity, double* out);
+
+/* Resolved launch configuration of a plan (host only, no GPU work):
+ *   out[0] M2L kernel (0 plain, 1 FP32, 2 FP64, 3 bf16x3 matrix cores)
+ *   out[1] offsets per M2L work-group   out[2] offset chunks
+ *   out[3] M2L work-groups per replica  out[4] near-field wavefronts per leaf
+ *   out[5] M2L LDS bytes per work-group out[6] device workspace bytes
+ *   out[7] graph replay enabled */
+fmm_status fmm_plan_info(fmm_plan_t plan, int64_t out[8]);
 
 /* Host-only access to the FP64 operator tables a plan of order p uploads; no
  * GPU is touched.  which: 0 = M2L bank (343 x K x K), 1 = M2M (8 x K x K),

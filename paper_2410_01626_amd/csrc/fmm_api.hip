@@ -50,6 +50,7 @@ struct fmm_plan_s {
     hipGraphExec_t graph_exec = nullptr;
     int R_max = 1;
     // matrix-core M2L
+    int p2p_waves = 8;  // wavefronts per leaf in the near-field kernel (4, 8 or 16)
     int m2l_mode = 0;  // 0 plain, 1 f32, 2 f64, 3 bf16x3
     fmmk::M2LGeom mg{};
     int m2l_rt = 0;
@@ -59,6 +60,7 @@ struct fmm_plan_s {
     int16_t* olist = nullptr;
     void *bank_mma = nullptr, *bank_mma_lo = nullptr, *m2l_part = nullptr;
     std::vector<void*> allocs;
+    size_t ws_bytes = 0;
     std::string err;
     // per-phase timing (fmm_profile): events recorded at phase boundaries
     bool prof_on = false;
@@ -80,6 +82,7 @@ bool dev_alloc(fmm_plan_t p, void** ptr, size_t bytes) {
     if (bytes == 0) bytes = 16;
     if (hipMalloc(ptr, bytes) != hipSuccess) return false;
     p->allocs.push_back(*ptr);
+    p->ws_bytes += bytes;
     return true;
 }
 
@@ -323,9 +326,18 @@ fmm_status enqueue_eval(fmm_plan_t P, const std::vector<fmmk::RepDesc>& rd, cons
                                                      g.Kp, rstride, (const T*)P->l2lT, loc);
     }
     mark(P, 6);
-    k_near_far<T><<<lg, 64 * kNW, 0, st>>>(g, reps, pos, P->leaf_start, P->perm, P->dom, loc,
-                                           P->gidx, (const T*)P->gcoef, qA, qB, site, phi, F,
-                                           P->leaf_energy, P->cphi);
+    switch (P->p2p_waves) {
+#define FMM_NEAR(NWV)                                                                            \
+    case NWV:                                                                                    \
+        k_near_far<T, NWV><<<lg, 64 * NWV, 0, st>>>(g, reps, pos, P->leaf_start, P->perm, P->dom, \
+                                                    loc, P->gidx, (const T*)P->gcoef, qA, qB, site, \
+                                                    phi, F, P->leaf_energy, P->cphi);              \
+        break;
+        FMM_NEAR(4)
+        FMM_NEAR(8)
+        FMM_NEAR(16)
+        default: break;
+    }
     mark(P, 7);
     k_reduce<<<(unsigned)(R + S_tot), 256, 0, st>>>(g, R, P->leaf_energy, P->site_start,
                                                     P->site_members, P->cphi, E, dVdl, P->status);
@@ -442,7 +454,8 @@ fmm_status fmm_plan_create(const fmm_params* prm, void* hip_stream, fmm_plan_t* 
          prm->precision != FMM_MIXED_BF16X3) ||
         !std::isfinite(prm->coulomb_k) || prm->max_atoms > INT32_MAX ||
         prm->m2l_kernel < 0 || prm->m2l_kernel > 2 || prm->m2l_chunk < 0 || prm->m2l_chunk > 189 ||
-        prm->p2p_waves < 0 || prm->graph < 0 || prm->graph > 1)
+        (prm->p2p_waves != 0 && prm->p2p_waves != 4 && prm->p2p_waves != 8 &&
+         prm->p2p_waves != 16) || prm->graph < 0 || prm->graph > 1)
         return FMM_E_INVALID;
     {
         const int K = (prm->order_p + 1) * (prm->order_p + 1);
@@ -457,6 +470,7 @@ fmm_status fmm_plan_create(const fmm_params* prm, void* hip_stream, fmm_plan_t* 
         return FMM_E_HIP;
     }
     P->fp64 = prm->precision == FMM_FP64;
+    P->p2p_waves = prm->p2p_waves ? prm->p2p_waves : 8;
     P->tsz = P->fp64 ? 8 : 4;
     const int p = prm->order_p, d = prm->depth;
     P->K = (p + 1) * (p + 1);
@@ -817,6 +831,19 @@ fmm_status fmm_profile(fmm_plan_t P, int32_t mode, int32_t capacity, double* out
         return FMM_OK;
     }
     return fail(P, FMM_E_INVALID, "profile mode must be 0, 1 or 2");
+}
+
+fmm_status fmm_plan_info(fmm_plan_t P, int64_t out[8]) {
+    if (!P || !out) return FMM_E_INVALID;
+    out[0] = P->m2l_mode;
+    out[1] = P->m2l_mode ? P->mg.csize : 0;
+    out[2] = P->m2l_mode ? P->mg.nchunk : 0;
+    out[3] = P->n_tasks;
+    out[4] = P->p2p_waves;
+    out[5] = (int64_t)P->m2l_lds;
+    out[6] = (int64_t)P->ws_bytes;
+    out[7] = P->prm.graph;
+    return FMM_OK;
 }
 
 int64_t fmm_host_operator(int32_t p, int32_t which, double* out) {

@@ -944,8 +944,6 @@ __device__ __forceinline__ void for_rho_orders(int p, int m0, int dm, T x, T y, 
     }
 }
 
-constexpr int kNW = 8;  // wavefronts per target leaf in the near-field kernel
-
 // Per target leaf (kNW wavefronts, one lane per target): the sources of the 27
 // neighbour leaves (periodic images through integer leaf offsets) are staged
 // through LDS in tiles of 64 kNW and split between the wavefronts.  The far
@@ -953,7 +951,7 @@ constexpr int kNW = 8;  // wavefronts per target leaf in the near-field kernel
 // between the wavefronts by order m.  Wavefront 0 adds the per-wave partials in
 // a fixed order, applies the periodic background term and writes potential,
 // force, the per-leaf energy partial and (qB - qA) phi for the site sums.
-template <typename T>
+template <typename T, int kNW>
 __global__ __launch_bounds__(64 * kNW) void k_near_far(
     Geo g, const RepDesc* __restrict__ reps, const vec4_t<T>* __restrict__ pos,
     const int32_t* __restrict__ leaf_start_all, const int32_t* __restrict__ perm,

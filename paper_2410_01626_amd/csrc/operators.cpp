@@ -20,6 +20,8 @@
 #include <cmath>
 #include <complex>
 #include <cstring>
+#include <map>
+#include <mutex>
 #include <vector>
 
 namespace fmmops {
@@ -371,6 +373,18 @@ void build_grad_table(int p, int32_t* out_idx, double* out_coef) {
 }
 
 void build_lattice(int p, double* out) {
+    // the lattice sum is the costly table (a sphere quadrature of an Ewald
+    // sum): keep it per order for the life of the process
+    static std::mutex mu;
+    static std::map<int, std::vector<double>> cache;
+    {
+        std::lock_guard<std::mutex> lk(mu);
+        auto it = cache.find(p);
+        if (it != cache.end()) {
+            std::memcpy(out, it->second.data(), it->second.size() * sizeof(double));
+            return;
+        }
+    }
     std::vector<cplx> c;
     lattice_coeffs(2 * p, c);
     build_real(p, Kind::Multipole, p, Kind::Local,
@@ -391,6 +405,8 @@ void build_lattice(int p, double* out) {
                    }
                },
                out);
+    std::lock_guard<std::mutex> lk(mu);
+    cache[p].assign(out, out + (size_t)ncoef(p) * ncoef(p));
 }
 
 }  // namespace fmmops

@@ -53,7 +53,7 @@ class fmm_params(ctypes.Structure):
 
 EXPORTS = ["fmm_plan_create", "fmm_eval", "fmm_eval_adjoint", "fmm_eval_batched",
            "fmm_sync_check", "fmm_last_error", "fmm_plan_destroy", "fmm_profile",
-           "fmm_host_operator"]
+           "fmm_plan_info", "fmm_host_operator"]
 PHASES = ["bin", "p2m", "m2m", "root", "m2l", "l2l", "near_far", "reduce"]
 
 _lib = None
@@ -92,6 +92,8 @@ def load_library(path: str = LIB_PATH):
     lib.fmm_plan_destroy.argtypes = [vp]
     lib.fmm_profile.restype = ctypes.c_int
     lib.fmm_profile.argtypes = [vp, i32, i32, vp]
+    lib.fmm_plan_info.restype = ctypes.c_int
+    lib.fmm_plan_info.argtypes = [vp, vp]
     lib.fmm_host_operator.restype = ctypes.c_int64
     lib.fmm_host_operator.argtypes = [i32, i32, dp]
     _lib = lib
@@ -316,6 +318,17 @@ class Plan:
         out = np.zeros(2 * len(PHASES))
         self._raise(fmm_profile(self.handle, 2, 0, out), "fmm_profile")
         return {ph: (out[i], int(out[len(PHASES) + i])) for i, ph in enumerate(PHASES)}
+
+    def info(self):
+        """Resolved launch configuration of the plan (see fmm_plan_info)."""
+        out = (ctypes.c_int64 * 8)()
+        self._raise(load_library().fmm_plan_info(self.handle, out), "fmm_plan_info")
+        keys = ["m2l_kernel", "m2l_chunk", "m2l_chunks", "m2l_workgroups", "p2p_waves",
+                "m2l_lds_bytes", "workspace_bytes", "graph"]
+        return dict(zip(keys, list(out)))
+
+    def m2l_kernel_mode(self):
+        return self.info()["m2l_kernel"]
 
     def sync_check(self):
         st = fmm_sync_check(self.handle)

@@ -219,3 +219,35 @@ def test_m2l_offset_chunking_invariant(chunk):
     b = run(d, "fp64", m2l_kernel=2, m2l_chunk=chunk)
     np.testing.assert_allclose(b["phi"], a["phi"], rtol=1e-12, atol=1e-12 * np.abs(a["phi"]).max())
     np.testing.assert_allclose(b["F"], a["F"], rtol=1e-11, atol=1e-11 * np.abs(a["F"]).max())
+
+
+@pytest.mark.parametrize("waves", [4, 16])
+def test_near_field_wave_count_invariant(waves):
+    """4, 8 or 16 wavefronts per leaf only regroup the near-field sums."""
+    d = W.tiny_periodic(35, n=2500, edge=2.0, n_sites=3, depth=3, order=6)
+    a = run(d, "fp64", p2p_waves=8)
+    b = run(d, "fp64", p2p_waves=waves)
+    np.testing.assert_allclose(b["phi"], a["phi"], rtol=1e-12, atol=1e-12 * np.abs(a["phi"]).max())
+    np.testing.assert_allclose(b["F"], a["F"], rtol=1e-11, atol=1e-11 * np.abs(a["F"]).max())
+
+
+def test_autotuner_picks_valid_shapes(tmp_path):
+    import torch
+    from paper_2410_01626_amd import autotune, fmm
+    dev = torch.device("cuda:0")
+    d = W.tiny_periodic(36, n=4000, edge=2.2, n_sites=3, depth=3, order=6)
+    t = [torch.tensor(d[k], dtype=torch.float32, device=dev) for k in ("x", "qA", "qB")]
+    site = torch.tensor(d["site"], device=dev)
+    lam = torch.tensor(d["lam"], device=dev)
+
+    def make_run(plan):
+        return lambda: plan.eval(t[0], t[1], t[2], site, lam, box=d["box"])
+    make_run.max_sites = 3
+    cache = str(tmp_path / "tune.json")
+    res = autotune.tune(make_run, 3, 6, True, "bf16x3", 4000, cache=cache, steps=2)
+    assert res["m2l_chunk"] in autotune.CHUNKS and res["p2p_waves"] in autotune.WAVES
+    assert autotune.tune(make_run, 3, 6, True, "bf16x3", 4000, cache=cache) == res  # cached
+    plan = fmm.Plan(3, 6, periodic=True, precision="bf16x3", max_atoms=4000, max_sites=3,
+                    device=dev, m2l_chunk=res["m2l_chunk"], p2p_waves=res["p2p_waves"])
+    info = plan.info()
+    assert info["m2l_chunk"] == res["m2l_chunk"] and info["p2p_waves"] == res["p2p_waves"]

@@ -43,7 +43,7 @@ def test_plan_create_rejects_bad_params_without_gpu():
     for bad in (dict(depth=-1), dict(depth=7), dict(order_p=0), dict(order_p=16),
                 dict(boundary=2), dict(precision=3), dict(max_replicas=0),
                 dict(max_atoms=-5), dict(coulomb_k=float("nan")), dict(m2l_kernel=3),
-                dict(m2l_chunk=190), dict(graph=2), dict(order_p=11, m2l_kernel=2),
+                dict(m2l_chunk=190), dict(graph=2), dict(p2p_waves=5), dict(order_p=11, m2l_kernel=2),
                 dict(order_p=9, precision=0, m2l_kernel=2)):
         kw = dict(depth=2, order_p=4, boundary=0, precision=0, coulomb_k=1.0,
                   max_atoms=10, max_sites=1, max_replicas=1, check=0, m2l_kernel=0,
