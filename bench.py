@@ -64,6 +64,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--fp64-steps", type=int, default=50)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
+    ap.add_argument("--no-batched", action="store_true", help="skip the replica-batch leg")
+    ap.add_argument("--batched-steps", type=int, default=10)
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: the solver runs on a single device and this "
@@ -115,6 +117,58 @@ def main():
     sec32, prof32 = timed(plan32, inp32, args.fp64_steps, max(2, args.warmup // 4), True)
     plan64, inp64 = make("fp64")
     sec64, prof64 = timed(plan64, inp64, args.fp64_steps, max(2, args.warmup // 4), True)
+
+    # graph replay of the same evaluation (dedicated stream, fixed output buffers)
+    gstream = torch.cuda.Stream(dev)
+    gplan = fmm.Plan(depth, order, periodic=True, precision="bf16x3", max_atoms=n, max_sites=S,
+                     device=dev, stream=gstream, graph=True)
+    gout = {"E": torch.empty(1, dtype=torch.float64, device=dev),
+            "F": torch.empty((n, 3), dtype=torch.float32, device=dev),
+            "phi": torch.empty(n, dtype=torch.float32, device=dev),
+            "dVdl": torch.empty(S, dtype=torch.float64, device=dev)}
+    torch.cuda.synchronize(dev)
+    with torch.cuda.stream(gstream):
+        for _ in range(args.warmup):
+            gplan.eval(*inp, box=d["box"], out=gout)
+        gstream.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            gplan.eval(*inp, box=d["box"], out=gout)
+        gstream.synchronize()
+        t1 = time.perf_counter()
+    sec_graph = (t1 - t0) / args.steps
+
+    # 16 open replicas of 10k-60k atoms at pH 2-9 in one batched call per step
+    batched = None
+    if not args.no_batched:
+        reps = workloads.replicas()
+        ao = np.cumsum([0] + [r["x"].shape[0] for r in reps])
+        so = np.cumsum([0] + [r["lam"].size for r in reps])
+        cat = {k: np.concatenate([r[k] for r in reps]) for k in ("x", "qA", "qB", "site", "lam")}
+        bplan = fmm.Plan(3, 8, periodic=False, precision="bf16x3", max_atoms=int(ao[-1]),
+                         max_sites=int(so[-1]), max_replicas=len(reps), device=dev)
+        bin_ = (torch.tensor(cat["x"], dtype=torch.float32, device=dev),
+                torch.tensor(cat["qA"], dtype=torch.float32, device=dev),
+                torch.tensor(cat["qB"], dtype=torch.float32, device=dev),
+                torch.tensor(cat["site"], dtype=torch.int32, device=dev),
+                torch.tensor(cat["lam"], dtype=torch.float64, device=dev))
+        for _ in range(2):
+            bplan.eval_batched(ao, so, *bin_)
+        torch.cuda.synchronize(dev)
+        bplan.profile_start(args.batched_steps)
+        t0 = time.perf_counter()
+        for _ in range(args.batched_steps):
+            bplan.eval_batched(ao, so, *bin_)
+        torch.cuda.synchronize(dev)
+        t1 = time.perf_counter()
+        bplan.profile_stop()
+        bprof = bplan.profile_read()
+        bsec = (t1 - t0) / args.batched_steps
+        batched = {"workload": "16 open replicas, 10,000-60,000 atoms (%d total), depth 3, p = 8, "
+                               "pH 2-9" % int(ao[-1]),
+                   "batch_evals_per_s": 1.0 / bsec, "replica_evals_per_s": len(reps) / bsec,
+                   "ms_per_batch": bsec * 1e3, "atoms_per_s": float(ao[-1]) / bsec,
+                   "phase_ms": {k: (v[0] / v[1] if v[1] else 0.0) for k, v in bprof.items()}}
 
     # per-phase means (ms) and the dominant kernel
     phase_ms = {k: (v[0] / v[1] if v[1] else 0.0) for k, v in prof.items()}
@@ -168,6 +222,8 @@ def main():
         "fp64": {"value": 1.0 / sec64, "ms_per_step": sec64 * 1e3, "steps": args.fp64_steps},
         "f32": {"value": 1.0 / sec32, "ms_per_step": sec32 * 1e3, "steps": args.fp64_steps},
         "speedup_mixed_vs_fp64": sec64 / sec,
+        "graph_replay": {"value": 1.0 / sec_graph, "ms_per_step": sec_graph * 1e3},
+        "batched": batched,
         "phase_ms": phase_ms,
         "phase_ms_fp64": phase_ms64,
         "phase_ms_f32": phase_ms32,

@@ -972,6 +972,7 @@ __global__ __launch_bounds__(64 * kNW) void k_near_far(
     __shared__ T lam[kKMax];
     __shared__ T gr[3][kKgMax];
     __shared__ T part[kNW][4][64];
+    __shared__ double esum_part[kNW][64];
     const int leaf = blockIdx.x;
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     const int tb = leaf_start[leaf], tn = leaf_start[leaf + 1] - tb;
@@ -1032,12 +1033,23 @@ __global__ __launch_bounds__(64 * kNW) void k_near_far(
     const int total = nb_pre[27];
     const T ih = (T)(1.0 / h);
     double esum = 0.0;
-    for (int t0 = 0; t0 < tn; t0 += 64) {
-        const int tj = t0 + lane;
+    // Targets are processed in rounds of up to kNW chunks of 64; within a round
+    // the wavefronts are split evenly between the chunks (wpc wavefronts per
+    // chunk, a power of two), each taking a contiguous slice of every source
+    // tile, so no wavefront idles on an empty chunk.
+    for (int t0 = 0; t0 < tn; t0 += 64 * kNW) {
+        const int nch = min(kNW, (tn - t0 + 63) / 64);
+        int wpc = kNW;
+        while (wpc * nch > kNW) wpc >>= 1;
+        const int chunk = wave / wpc, slice = wave % wpc;
+        const bool live = chunk < nch;
+        const int tj = t0 + 64 * chunk + lane;
+        const bool tv = live && tj < tn;
         vec4_t<T> me;
-        if (tj < tn) me = pos[tb + tj];
+        if (tv) me = pos[tb + tj];
         else { me.x = me.y = me.z = me.w = T(0); }
         T ph = T(0), fx = T(0), fy = T(0), fz = T(0);
+        const int sl = NT / wpc;
         for (int s0 = 0; s0 < total; s0 += NT) {
             __syncthreads();
             const int gsrc = s0 + tid;
@@ -1056,8 +1068,9 @@ __global__ __launch_bounds__(64 * kNW) void k_near_far(
                 tile[tid] = a;
             }
             __syncthreads();
-            const int jb = wave * 64;
-            const int je = min(jb + 64, total - s0);
+            if (!live) continue;
+            const int jb = slice * sl;
+            const int je = min(jb + sl, total - s0);
 #pragma unroll 4
             for (int j = jb; j < je; ++j) {
                 const vec4_t<T> s = tile[j];
@@ -1072,11 +1085,11 @@ __global__ __launch_bounds__(64 * kNW) void k_near_far(
                 fz += qr3 * dz;
             }
         }
-        if (far && tj < tn) {
-            // far field, orders m = wave, wave + kNW, ...
+        if (far && tv) {
+            // far field, orders m = slice, slice + wpc, ...
             T fp = T(0), gx = T(0), gy = T(0), gz = T(0);
             const int Kg = g.Kg;
-            for_rho_orders<T>(g.p, wave, kNW, me.x * ih, me.y * ih, me.z * ih,
+            for_rho_orders<T>(g.p, slice, wpc, me.x * ih, me.y * ih, me.z * ih,
                               [&](int kc, bool has_s, T re, T im) {
                                   fp += lam[kc] * re;
                                   if (has_s) fp += lam[kc + 1] * im;
@@ -1101,10 +1114,10 @@ __global__ __launch_bounds__(64 * kNW) void k_near_far(
         part[wave][2][lane] = fy;
         part[wave][3][lane] = fz;
         __syncthreads();
-        if (wave == 0 && tj < tn) {
+        // the first wavefront of each chunk adds the chunk's slices in order
+        if (live && slice == 0 && tj < tn) {
             T p = T(0), ex = T(0), ey = T(0), ez = T(0);
-#pragma unroll
-            for (int w = 0; w < kNW; ++w) {
+            for (int w = wave; w < wave + wpc; ++w) {
                 p += part[w][0][lane];
                 ex += part[w][1][lane];
                 ey += part[w][2][lane];
@@ -1131,10 +1144,20 @@ __global__ __launch_bounds__(64 * kNW) void k_near_far(
                 F_out[3 * (size_t)i + 1] = ke * q * ey;
                 F_out[3 * (size_t)i + 2] = ke * q * ez;
             }
-            esum += (double)q * (double)p;
+            const double qp = (double)q * (double)p;
+            esum_part[wave][lane] = qp;
             const int32_t st = site[i];
             if (st >= 0 && st < n_sites)
                 cphi[i] = g.coulomb_k * ((double)qB[i] - (double)qA[i]) * (double)p;
+        } else if (slice == 0 && live) {
+            esum_part[wave][lane] = 0.0;
+        }
+        __syncthreads();
+        // energy partial of this round, in target order
+        if (wave == 0) {
+            double v = 0.0;
+            for (int c = 0; c < nch; ++c) v += esum_part[c * wpc][lane];
+            esum += v;
         }
     }
     if (wave == 0) {
