@@ -587,14 +587,33 @@ fmm_status fmm_plan_create(const fmm_params* prm, void* hip_stream, fmm_plan_t* 
         mg.csize = csize;
         mg.nchunk = (189 + csize - 1) / csize;
         mg.nt_all = nt_all;
-        std::vector<fmmk::M2LTask> tl;
+        // Work-groups are dispatched round-robin over the 8 XCDs (group i on XCD
+        // i mod 8), each with its own L2.  Tasks are ordered so that slot i
+        // holds a task of an offset chunk assigned to XCD i mod 8: every XCD
+        // then reads only its share of the operator bank, which stays in its L2.
+        const int kXcd = 8;
+        std::vector<std::vector<fmmk::M2LTask>> byx(kXcd);
         for (int l = lmin; l <= d; ++l) {
             const int64_t ntc = (int64_t)1 << (3 * (l - 1));
             const int ntile = (int)((ntc + fmmk::kM2LTile - 1) / fmmk::kM2LTile);
             for (int c = 0; c < 8; ++c)
                 for (int t = 0; t < ntile; ++t)
-                    for (int ch = 0; ch < mg.nchunk; ++ch) tl.push_back({l, c, t, ch});
+                    for (int ch = 0; ch < mg.nchunk; ++ch) {
+                        int x;
+                        if (mg.nchunk >= kXcd) x = ch % kXcd;
+                        else {  // several XCDs share one chunk: spread its tasks over them
+                            const int per = kXcd / mg.nchunk;
+                            x = ch + mg.nchunk * ((c * ntile + t) % per);
+                        }
+                        byx[x].push_back({l, c, t, ch});
+                    }
         }
+        std::vector<fmmk::M2LTask> tl;
+        size_t longest = 0;
+        for (auto& v : byx) longest = std::max(longest, v.size());
+        for (size_t j = 0; j < longest; ++j)
+            for (int x = 0; x < kXcd; ++x)
+                if (j < byx[x].size()) tl.push_back(byx[x][j]);
         P->n_tasks = (int64_t)tl.size();
         const size_t esz = P->m2l_mode == 2 ? 8 : (P->m2l_mode == 1 ? 4 : 2);
         P->m2l_lds = esz * ((size_t)mg.RP * mg.SA + (size_t)fmmk::kM2LTile * mg.SB) *
