@@ -322,7 +322,8 @@ class Plan:
     def info(self):
         """Resolved launch configuration of the plan (see fmm_plan_info)."""
         out = (ctypes.c_int64 * 8)()
-        self._raise(load_library().fmm_plan_info(self.handle, out), "fmm_plan_info")
+        self._raise(load_library().fmm_plan_info(self.handle, ctypes.cast(out, ctypes.c_void_p)),
+                    "fmm_plan_info")
         keys = ["m2l_kernel", "m2l_chunk", "m2l_chunks", "m2l_workgroups", "p2p_waves",
                 "m2l_lds_bytes", "workspace_bytes", "graph"]
         return dict(zip(keys, list(out)))
