@@ -83,7 +83,8 @@ def tune(make_run, depth, order, periodic, precision, n_atoms, replicas=1, steps
             print("p2p_waves %2d: %.1f us" % (w, 1e3 * wave_t[w]), flush=True)
     res = {"m2l_chunk": min(chunk_t, key=chunk_t.get) if chunk_t else 0,
            "p2p_waves": min(wave_t, key=wave_t.get),
-           "m2l_ms": chunk_t, "near_far_ms": wave_t}
+           "m2l_ms": {str(k): v for k, v in chunk_t.items()},
+           "near_far_ms": {str(k): v for k, v in wave_t.items()}}
     db = _load(cache)
     db[key] = res
     try:
