@@ -154,7 +154,7 @@ int round_up(int v, int m) { return (v + m - 1) / m * m; }
 // f64 rows to an odd number of elements, bf16 rows to 8 mod 64 elements.
 int lds_stride(int mode, int kp) {
     if (mode == 1) { int s = kp; while (s % 32 != 2) ++s; return s; }
-    if (mode == 2) return kp | 1;
+    if (mode == 2) return kp + 2;  // even: 16-byte aligned rows
     int s = kp; while (s % 64 != 40 && s % 64 != 8) s += 8; return s;
 }
 

@@ -638,59 +638,88 @@ __device__ __forceinline__ bool m2l_target(int lev, int cls, int tile, int j, in
     return true;
 }
 
-// Stage the 64 source expansions of offset o (bank index oi) into LDS as
-// B[j][k] (k contiguous); missing sources (outside an open domain, or beyond
-// the class) are zero.  Returns nothing; caller synchronises.
-template <typename TS, typename TL>
-__device__ __forceinline__ void m2l_stage_sources(const Geo& g, const M2LGeom& mg, int lev, int cls,
-                                                  int tile, int oi, const TS* __restrict__ mult,
-                                                  TL* __restrict__ Bh, TL* __restrict__ Bl) {
+// Per offset, the 64 target columns of a work item read their sources from
+// these boxes (index into the level's expansion rows, or -1: no source).
+__device__ __forceinline__ void m2l_source_boxes(const Geo& g, int lev, int cls, int tile, int oi,
+                                                 int* __restrict__ sbox) {
+    const int j = threadIdx.x;
+    if (j >= kM2LTile) return;
     const int n = 1 << lev;
     const int ox = oi / 49 - 3, oy = (oi / 7) % 7 - 3, oz = oi % 7 - 3;
-    const int tot = kM2LTile * mg.KP;
-    for (int e = threadIdx.x; e < tot; e += blockDim.x) {
-        const int j = e / mg.KP, k = e % mg.KP;
-        float v = 0.f;
-        double vd = 0.0;
-        int tx, ty, tz;
-        if (k < g.K && m2l_target(lev, cls, tile, j, tx, ty, tz)) {
-            int sx = tx - ox, sy = ty - oy, sz = tz - oz;
-            bool ok = true;
-            if (g.periodic) {
-                sx = (sx % n + n) % n;
-                sy = (sy % n + n) % n;
-                sz = (sz % n + n) % n;
-            } else {
-                ok = sx >= 0 && sy >= 0 && sz >= 0 && sx < n && sy < n && sz < n;
-            }
-            if (ok) {
-                const TS m = mult[(size_t)(g.lev_off[lev] + morton(sx, sy, sz)) * g.Kp + k];
-                vd = (double)m;
-                v = (float)m;
-            }
-        }
-        if constexpr (sizeof(TL) == 2) {
-            const __bf16 hi = (__bf16)v;
-            Bh[j * mg.SB + k] = hi;
-            Bl[j * mg.SB + k] = (__bf16)(v - (float)hi);
-        } else if constexpr (sizeof(TL) == 4) {
-            Bh[j * mg.SB + k] = v;
+    int tx, ty, tz, b = -1;
+    if (m2l_target(lev, cls, tile, j, tx, ty, tz)) {
+        int sx = tx - ox, sy = ty - oy, sz = tz - oz;
+        bool ok = true;
+        if (g.periodic) {
+            sx = (sx % n + n) % n;
+            sy = (sy % n + n) % n;
+            sz = (sz % n + n) % n;
         } else {
-            Bh[j * mg.SB + k] = vd;
+            ok = sx >= 0 && sy >= 0 && sz >= 0 && sx < n && sy < n && sz < n;
         }
+        if (ok) b = (int)(g.lev_off[lev] + morton(sx, sy, sz));
+    }
+    sbox[j] = b;
+}
+
+// Copy operator block oi (RP x KP, row-major) into LDS rows of stride SA in
+// vector chunks of type V (KP and SA are multiples of the chunk).
+template <typename TE, typename V>
+__device__ __forceinline__ void m2l_stage_op(const M2LGeom& mg, const TE* __restrict__ bank, int oi,
+                                             TE* __restrict__ A) {
+    constexpr int E = sizeof(V) / sizeof(TE);
+    const V* src = (const V*)(bank + (size_t)oi * mg.RP * mg.KP);
+    const int cpr = mg.KP / E;  // chunks per row
+    const int tot = mg.RP * cpr;
+    for (int c = threadIdx.x; c < tot; c += blockDim.x) {
+        const int r = c / cpr, k = (c % cpr) * E;
+        *(V*)(A + r * mg.SA + k) = src[c];
     }
 }
 
-// Copy operator block oi (rows RP x KP, row-major, zero padded) into LDS rows
-// of stride SA.
-template <typename TL>
-__device__ __forceinline__ void m2l_stage_op(const M2LGeom& mg, const TL* __restrict__ bank, int oi,
-                                             TL* __restrict__ A) {
-    const TL* src = bank + (size_t)oi * mg.RP * mg.KP;
-    const int tot = mg.RP * mg.KP;
-    for (int e = threadIdx.x; e < tot; e += blockDim.x) {
-        const int r = e / mg.KP, k = e % mg.KP;
-        A[r * mg.SA + k] = src[e];
+// Gather the 64 source expansions (16-byte chunks of the expansion rows,
+// masked past K) into LDS as B[j][k]; bf16: split into hi and lo parts.
+template <typename TS, typename TL>
+__device__ __forceinline__ void m2l_stage_src(const Geo& g, const M2LGeom& mg, const int* __restrict__ sbox,
+                                              const TS* __restrict__ mult, TL* __restrict__ Bh,
+                                              TL* __restrict__ Bl) {
+    constexpr int E = 16 / sizeof(TS);
+    const int cpr = mg.KP / E;
+    const int tot = kM2LTile * cpr;
+    for (int c = threadIdx.x; c < tot; c += blockDim.x) {
+        const int j = c / cpr, k = (c % cpr) * E;
+        const int b = sbox[j];
+        uint4 v = make_uint4(0u, 0u, 0u, 0u);
+        if (b >= 0 && k < g.K) {
+            v = *(const uint4*)(mult + (size_t)b * g.Kp + k);
+            const int valid = g.K - k;  // the row padding [K, Kp) is never written
+            if (E == 4) {
+                if (valid < 2) v.y = 0u;
+                if (valid < 3) v.z = 0u;
+                if (valid < 4) v.w = 0u;
+            } else if (valid < 2) {
+                v.z = 0u;
+                v.w = 0u;
+            }
+        }
+        if constexpr (sizeof(TL) == 2) {
+            const float f0 = __uint_as_float(v.x), f1 = __uint_as_float(v.y);
+            const float f2 = __uint_as_float(v.z), f3 = __uint_as_float(v.w);
+            const __bf16 h0 = (__bf16)f0, h1 = (__bf16)f1, h2 = (__bf16)f2, h3 = (__bf16)f3;
+            const __bf16 l0 = (__bf16)(f0 - (float)h0), l1 = (__bf16)(f1 - (float)h1);
+            const __bf16 l2 = (__bf16)(f2 - (float)h2), l3 = (__bf16)(f3 - (float)h3);
+            auto pk = [](__bf16 a, __bf16 c2) {
+                return (uint32_t)__builtin_bit_cast(uint16_t, a) |
+                       ((uint32_t)__builtin_bit_cast(uint16_t, c2) << 16);
+            };
+            *(uint2*)(Bh + j * mg.SB + k) = make_uint2(pk(h0, h1), pk(h2, h3));
+            *(uint2*)(Bl + j * mg.SB + k) = make_uint2(pk(l0, l1), pk(l2, l3));
+        } else if constexpr (sizeof(TL) == 4) {
+            *(uint2*)(Bh + j * mg.SB + k) = make_uint2(v.x, v.y);
+            *(uint2*)(Bh + j * mg.SB + k + 2) = make_uint2(v.z, v.w);
+        } else {
+            *(uint4*)(Bh + j * mg.SB + k) = v;
+        }
     }
 }
 
@@ -720,9 +749,10 @@ __global__ __launch_bounds__(256) void k_m2l_f32(Geo g, M2LGeom mg, const M2LTas
                                                  const float* __restrict__ mult,
                                                  const float* __restrict__ bank,
                                                  float* __restrict__ loc, float* __restrict__ part) {
-    extern __shared__ float lds_f32[];
+    extern __shared__ __align__(16) float lds_f32[];
     float* A = lds_f32;
     float* B = lds_f32 + mg.RP * mg.SA;
+    __shared__ int sbox[kM2LTile];
     const M2LTask tk = tasks[blockIdx.x];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     mult += (size_t)blockIdx.y * g.nbox * g.Kp;
@@ -737,8 +767,10 @@ __global__ __launch_bounds__(256) void k_m2l_f32(Geo g, M2LGeom mg, const M2LTas
     for (int oc = o0; oc < o1; ++oc) {
         const int oi = olist[tk.cls * 189 + oc];
         __syncthreads();
-        m2l_stage_op<float>(mg, bank, oi, A);
-        m2l_stage_sources<float, float>(g, mg, tk.lev, tk.cls, tk.tile, oi, mult, B, nullptr);
+        m2l_source_boxes(g, tk.lev, tk.cls, tk.tile, oi, sbox);
+        m2l_stage_op<float, uint2>(mg, bank, oi, A);
+        __syncthreads();
+        m2l_stage_src<float, float>(g, mg, sbox, mult, B, nullptr);
         __syncthreads();
         if (!active) continue;
         const float* Bw = B + (16 * wave + (lane & 15)) * mg.SB + (lane >> 4);
@@ -763,9 +795,10 @@ __global__ __launch_bounds__(256) void k_m2l_f64(Geo g, M2LGeom mg, const M2LTas
                                                  const double* __restrict__ mult,
                                                  const double* __restrict__ bank,
                                                  double* __restrict__ loc, double* __restrict__ part) {
-    extern __shared__ double lds_f64[];
+    extern __shared__ __align__(16) double lds_f64[];
     double* A = lds_f64;
     double* B = lds_f64 + mg.RP * mg.SA;
+    __shared__ int sbox[kM2LTile];
     const M2LTask tk = tasks[blockIdx.x];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     mult += (size_t)blockIdx.y * g.nbox * g.Kp;
@@ -780,8 +813,10 @@ __global__ __launch_bounds__(256) void k_m2l_f64(Geo g, M2LGeom mg, const M2LTas
     for (int oc = o0; oc < o1; ++oc) {
         const int oi = olist[tk.cls * 189 + oc];
         __syncthreads();
-        m2l_stage_op<double>(mg, bank, oi, A);
-        m2l_stage_sources<double, double>(g, mg, tk.lev, tk.cls, tk.tile, oi, mult, B, nullptr);
+        m2l_source_boxes(g, tk.lev, tk.cls, tk.tile, oi, sbox);
+        m2l_stage_op<double, uint4>(mg, bank, oi, A);
+        __syncthreads();
+        m2l_stage_src<double, double>(g, mg, sbox, mult, B, nullptr);
         __syncthreads();
         if (!active) continue;
         const double* Bw = B + (16 * wave + (lane & 15)) * mg.SB + (lane >> 4);
@@ -808,11 +843,12 @@ __global__ __launch_bounds__(256) void k_m2l_bf16x3(Geo g, M2LGeom mg,
                                                     const __bf16* __restrict__ bank_hi,
                                                     const __bf16* __restrict__ bank_lo,
                                                     float* __restrict__ loc, float* __restrict__ part) {
-    extern __shared__ __bf16 lds_bf[];
+    extern __shared__ __align__(16) __bf16 lds_bf[];
     __bf16* Ah = lds_bf;
     __bf16* Al = Ah + mg.RP * mg.SA;
     __bf16* Bh = Al + mg.RP * mg.SA;
     __bf16* Bl = Bh + kM2LTile * mg.SB;
+    __shared__ int sbox[kM2LTile];
     const M2LTask tk = tasks[blockIdx.x];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     mult += (size_t)blockIdx.y * g.nbox * g.Kp;
@@ -827,9 +863,11 @@ __global__ __launch_bounds__(256) void k_m2l_bf16x3(Geo g, M2LGeom mg,
     for (int oc = o0; oc < o1; ++oc) {
         const int oi = olist[tk.cls * 189 + oc];
         __syncthreads();
-        m2l_stage_op<__bf16>(mg, bank_hi, oi, Ah);
-        m2l_stage_op<__bf16>(mg, bank_lo, oi, Al);
-        m2l_stage_sources<float, __bf16>(g, mg, tk.lev, tk.cls, tk.tile, oi, mult, Bh, Bl);
+        m2l_source_boxes(g, tk.lev, tk.cls, tk.tile, oi, sbox);
+        m2l_stage_op<__bf16, uint4>(mg, bank_hi, oi, Ah);
+        m2l_stage_op<__bf16, uint4>(mg, bank_lo, oi, Al);
+        __syncthreads();
+        m2l_stage_src<float, __bf16>(g, mg, sbox, mult, Bh, Bl);
         __syncthreads();
         if (!active) continue;
         const int boff = (16 * wave + (lane & 15)) * mg.SB + 8 * (lane >> 4);
