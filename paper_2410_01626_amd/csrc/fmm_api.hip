@@ -58,6 +58,7 @@ struct fmm_plan_s {
     int64_t n_tasks = 0;
     fmmk::M2LTask* tasks = nullptr;
     int16_t* olist = nullptr;
+    int16_t* cstart = nullptr;
     void *bank_mma = nullptr, *bank_mma_lo = nullptr, *m2l_part = nullptr;
     std::vector<void*> allocs;
     size_t ws_bytes = 0;
@@ -203,19 +204,19 @@ void launch_m2l_mma(fmm_plan_t P, const Geo& g, int R) {
     switch (P->m2l_mode * 16 + P->m2l_rt) {
 #define FMM_M2L_F32(RTV)                                                                    \
     case 16 + RTV:                                                                          \
-        k_m2l_f32<RTV><<<nt, 256, lds, st>>>(g, mg, P->tasks, P->olist, (const float*)mult, \
+        k_m2l_f32<RTV><<<nt, 64 * kM2LWaves, lds, st>>>(g, mg, P->tasks, P->olist, P->cstart, (const float*)mult, \
                                              (const float*)P->bank_mma, (float*)loc,         \
                                              (float*)part);                                  \
         break;
 #define FMM_M2L_F64(RTV)                                                                      \
     case 32 + RTV:                                                                            \
-        k_m2l_f64<RTV><<<nt, 256, lds, st>>>(g, mg, P->tasks, P->olist, (const double*)mult, \
+        k_m2l_f64<RTV><<<nt, 64 * kM2LWaves, lds, st>>>(g, mg, P->tasks, P->olist, P->cstart, (const double*)mult, \
                                              (const double*)P->bank_mma, (double*)loc,         \
                                              (double*)part);                                   \
         break;
 #define FMM_M2L_BF(RTV)                                                                         \
     case 48 + RTV:                                                                              \
-        k_m2l_bf16x3<RTV><<<nt, 256, lds, st>>>(g, mg, P->tasks, P->olist, (const float*)mult, \
+        k_m2l_bf16x3<RTV><<<nt, 64 * kM2LWaves, lds, st>>>(g, mg, P->tasks, P->olist, P->cstart, (const float*)mult, \
                                                 (const __bf16*)P->bank_mma,                     \
                                                 (const __bf16*)P->bank_mma_lo, (float*)loc,     \
                                                 (float*)part);                                  \
@@ -573,12 +574,16 @@ fmm_status fmm_plan_create(const fmm_params* prm, void* hip_stream, fmm_plan_t* 
         mg.SA = lds_stride(P->m2l_mode, mg.KP);
         mg.SB = mg.SA;
         P->m2l_rt = mg.RP / 16;
-        int64_t items = 0, nt_all = 0;
+        // target columns of one class: its boxes at every level >= lmin
+        int64_t ncol = 0, nt_all = 0;
         for (int l = lmin; l <= d; ++l) {
-            const int64_t ntc = (int64_t)1 << (3 * (l - 1));
-            items += 8 * ((ntc + fmmk::kM2LTile - 1) / fmmk::kM2LTile) * (int64_t)RM;
+            ncol += (int64_t)1 << (3 * (l - 1));
             nt_all += (int64_t)1 << (3 * l);
         }
+        mg.ncol = (int)ncol;
+        mg.nt_all = nt_all;
+        const int ntile = (int)((ncol + fmmk::kM2LTile - 1) / fmmk::kM2LTile);
+        const int64_t items = 8 * (int64_t)ntile * (int64_t)RM;
         int csize = prm->m2l_chunk;
         if (csize == 0) {
             const int64_t want = std::max<int64_t>(1, std::min<int64_t>(27, (2048 + items - 1) / items));
@@ -586,28 +591,45 @@ fmm_status fmm_plan_create(const fmm_params* prm, void* hip_stream, fmm_plan_t* 
         }
         mg.csize = csize;
         mg.nchunk = (189 + csize - 1) / csize;
-        mg.nt_all = nt_all;
+        // Offset chunks are contiguous ranges of the global (bank-index sorted)
+        // offset set, so a chunk's operators are the same for every class; each
+        // class takes the part of its 189 offsets that falls in the range.
+        std::vector<int16_t> cls_off = class_offsets();
+        std::vector<int> used;
+        {
+            std::vector<char> seen(343, 0);
+            for (int16_t o : cls_off) seen[o] = 1;
+            for (int o = 0; o < 343; ++o)
+                if (seen[o]) used.push_back(o);
+        }
+        std::vector<int> bound(mg.nchunk + 1);
+        for (int k = 0; k <= mg.nchunk; ++k) {
+            const size_t u = (size_t)k * used.size() / mg.nchunk;
+            bound[k] = u < used.size() ? used[u] : 343;
+        }
+        std::vector<int16_t> cstart(8 * (mg.nchunk + 1));
+        for (int c = 0; c < 8; ++c) {
+            std::sort(cls_off.begin() + 189 * c, cls_off.begin() + 189 * (c + 1));
+            int pos = 0;
+            for (int k = 0; k <= mg.nchunk; ++k) {
+                while (pos < 189 && cls_off[189 * c + pos] < bound[k]) ++pos;
+                cstart[c * (mg.nchunk + 1) + k] = (int16_t)pos;
+            }
+        }
         // Work-groups are dispatched round-robin over the 8 XCDs (group i on XCD
-        // i mod 8), each with its own L2.  Tasks are ordered so that slot i
-        // holds a task of an offset chunk assigned to XCD i mod 8: every XCD
-        // then reads only its share of the operator bank, which stays in its L2.
+        // i mod 8), each with its own L2.  Tasks are ordered so that slot i holds
+        // a task of an offset chunk assigned to XCD i mod 8: every XCD then reads
+        // only its share of the operator bank, which stays in its L2.
         const int kXcd = 8;
         std::vector<std::vector<fmmk::M2LTask>> byx(kXcd);
-        for (int l = lmin; l <= d; ++l) {
-            const int64_t ntc = (int64_t)1 << (3 * (l - 1));
-            const int ntile = (int)((ntc + fmmk::kM2LTile - 1) / fmmk::kM2LTile);
+        for (int ch = 0; ch < mg.nchunk; ++ch)
             for (int c = 0; c < 8; ++c)
-                for (int t = 0; t < ntile; ++t)
-                    for (int ch = 0; ch < mg.nchunk; ++ch) {
-                        int x;
-                        if (mg.nchunk >= kXcd) x = ch % kXcd;
-                        else {  // several XCDs share one chunk: spread its tasks over them
-                            const int per = kXcd / mg.nchunk;
-                            x = ch + mg.nchunk * ((c * ntile + t) % per);
-                        }
-                        byx[x].push_back({l, c, t, ch});
-                    }
-        }
+                for (int t = 0; t < ntile; ++t) {
+                    int x;
+                    if (mg.nchunk >= kXcd) x = ch % kXcd;
+                    else x = ch + mg.nchunk * ((c * ntile + t) % (kXcd / mg.nchunk));
+                    byx[x].push_back({c, t, ch, 0});
+                }
         std::vector<fmmk::M2LTask> tl;
         size_t longest = 0;
         for (auto& v : byx) longest = std::max(longest, v.size());
@@ -618,10 +640,11 @@ fmm_status fmm_plan_create(const fmm_params* prm, void* hip_stream, fmm_plan_t* 
         const size_t esz = P->m2l_mode == 2 ? 8 : (P->m2l_mode == 1 ? 4 : 2);
         P->m2l_lds = esz * ((size_t)mg.RP * mg.SA + (size_t)fmmk::kM2LTile * mg.SB) *
                      (P->m2l_mode == 3 ? 2 : 1);
-        std::vector<int16_t> ol = class_offsets();
+        const std::vector<int16_t>& ol = cls_off;
         bool ok2 = !ol.empty();
         ok2 &= dev_alloc(P, (void**)&P->tasks, tl.size() * sizeof(fmmk::M2LTask));
         ok2 &= dev_alloc(P, (void**)&P->olist, ol.size() * sizeof(int16_t));
+        ok2 &= dev_alloc(P, (void**)&P->cstart, cstart.size() * sizeof(int16_t));
         const size_t nb = (size_t)343 * mg.RP * mg.KP;
         ok2 &= dev_alloc(P, &P->bank_mma, nb * esz);
         if (P->m2l_mode == 3) ok2 &= dev_alloc(P, &P->bank_mma_lo, nb * esz);
@@ -633,6 +656,7 @@ fmm_status fmm_plan_create(const fmm_params* prm, void* hip_stream, fmm_plan_t* 
         }
         up(P->tasks, tl.data(), tl.size() * sizeof(fmmk::M2LTask));
         up(P->olist, ol.data(), ol.size() * sizeof(int16_t));
+        up(P->cstart, cstart.data(), cstart.size() * sizeof(int16_t));
         if (P->m2l_mode == 2) {
             std::vector<double> bm(nb, 0.0);
             for (int o = 0; o < 343; ++o)

@@ -58,13 +58,15 @@ struct RepSet {
 namespace fmmk {
 
 // Matrix-core M2L: work items and tile sizes.
-constexpr int kM2LTile = 64;    // targets per work-group (4 wavefronts x 16 columns)
+constexpr int kM2LWaves = 5;                 // wavefronts per matrix-core M2L work-group
+constexpr int kM2LTile = 16 * kM2LWaves;     // target columns per work-group
 constexpr int kM2LMaxRT = 8;    // row tiles of 16: K <= 128 (p <= 10)
 
-// One M2L work item: level, child class (4 bx + 2 by + bz), target tile of
-// that class and chunk of the class's 189-entry offset list.
+// One M2L work item: child class (4 bx + 2 by + bz), tile of that class's
+// target columns (the class's boxes of every level, deepest level first) and
+// chunk of translation offsets (a range of the global offset set).
 struct M2LTask {
-    int32_t lev, cls, tile, chunk;
+    int32_t cls, tile, chunk, pad;
 };
 
 }  // namespace fmmk

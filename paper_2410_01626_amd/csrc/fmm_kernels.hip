@@ -620,34 +620,42 @@ struct M2LGeom {
     int32_t SA;      // LDS row stride of the operator (elements)
     int32_t SB;      // LDS row stride of the sources (elements)
     int32_t nchunk;  // offset chunks
-    int32_t csize;   // offsets per chunk
+    int32_t csize;   // nominal offsets per chunk
+    int32_t ncol;    // target columns per class (all levels)
+    int32_t pad_;
     int64_t nt_all;  // boxes at levels >= lmin (partial-buffer stride)
 };
 
-// Decode the target column j of a work item into its box at level lev.
-__device__ __forceinline__ bool m2l_target(int lev, int cls, int tile, int j, int& tx, int& ty,
-                                           int& tz) {
-    const int half = lev >= 1 ? (1 << (lev - 1)) : 1;
-    const int ntc = half * half * half;
-    const int u = tile * kM2LTile + j;
-    if (u >= ntc) return false;
-    const int ux = u / (half * half), uy = (u / half) % half, uz = u % half;
-    tx = 2 * ux + ((cls >> 2) & 1);
-    ty = 2 * uy + ((cls >> 1) & 1);
-    tz = 2 * uz + (cls & 1);
-    return true;
+// Decode target column j of a work item: the class's boxes of every level,
+// deepest level first.  Returns false past the class's last column.
+__device__ __forceinline__ bool m2l_column(const Geo& g, int cls, int tile, int j, int& lev, int& tx,
+                                           int& ty, int& tz) {
+    int u = tile * kM2LTile + j;
+    for (lev = g.depth; lev >= g.lmin; --lev) {
+        const int half = 1 << (lev - 1);
+        const int ntc = half * half * half;
+        if (u < ntc) {
+            const int ux = u / (half * half), uy = (u / half) % half, uz = u % half;
+            tx = 2 * ux + ((cls >> 2) & 1);
+            ty = 2 * uy + ((cls >> 1) & 1);
+            tz = 2 * uz + (cls & 1);
+            return true;
+        }
+        u -= ntc;
+    }
+    return false;
 }
 
-// Per offset, the 64 target columns of a work item read their sources from
-// these boxes (index into the level's expansion rows, or -1: no source).
-__device__ __forceinline__ void m2l_source_boxes(const Geo& g, int lev, int cls, int tile, int oi,
+// Per offset, the target columns of a work item read their sources from
+// these boxes (row of the expansion arrays, or -1: no source).
+__device__ __forceinline__ void m2l_source_boxes(const Geo& g, int cls, int tile, int oi,
                                                  int* __restrict__ sbox) {
     const int j = threadIdx.x;
     if (j >= kM2LTile) return;
-    const int n = 1 << lev;
     const int ox = oi / 49 - 3, oy = (oi / 7) % 7 - 3, oz = oi % 7 - 3;
-    int tx, ty, tz, b = -1;
-    if (m2l_target(lev, cls, tile, j, tx, ty, tz)) {
+    int lev, tx, ty, tz, b = -1;
+    if (m2l_column(g, cls, tile, j, lev, tx, ty, tz)) {
+        const int n = 1 << lev;
         int sx = tx - ox, sy = ty - oy, sz = tz - oz;
         bool ok = true;
         if (g.periodic) {
@@ -725,13 +733,13 @@ __device__ __forceinline__ void m2l_stage_src(const Geo& g, const M2LGeom& mg, c
 
 // Write the accumulator of row tile rt, lane layout given by `f64layout`.
 template <typename TA, typename TO>
-__device__ __forceinline__ void m2l_store(const Geo& g, const M2LGeom& mg, int lev, int cls, int tile,
+__device__ __forceinline__ void m2l_store(const Geo& g, const M2LGeom& mg, int cls, int tile,
                                           int chunk, int wave, int lane, int rt, const TA& acc,
                                           bool f64layout, TO* __restrict__ loc,
                                           TO* __restrict__ part) {
     const int j = 16 * wave + (lane & 15);
-    int tx, ty, tz;
-    if (!m2l_target(lev, cls, tile, j, tx, ty, tz)) return;
+    int lev, tx, ty, tz;
+    if (!m2l_column(g, cls, tile, j, lev, tx, ty, tz)) return;
     const int64_t box = g.lev_off[lev] + morton(tx, ty, tz);
     TO* dst;
     if (mg.nchunk == 1) dst = loc + (size_t)box * g.Kp;
@@ -744,8 +752,9 @@ __device__ __forceinline__ void m2l_store(const Geo& g, const M2LGeom& mg, int l
 }
 
 template <int RT>
-__global__ __launch_bounds__(256) void k_m2l_f32(Geo g, M2LGeom mg, const M2LTask* __restrict__ tasks,
+__global__ __launch_bounds__(64 * kM2LWaves) void k_m2l_f32(Geo g, M2LGeom mg, const M2LTask* __restrict__ tasks,
                                                  const int16_t* __restrict__ olist,
+                                                 const int16_t* __restrict__ cstart,
                                                  const float* __restrict__ mult,
                                                  const float* __restrict__ bank,
                                                  float* __restrict__ loc, float* __restrict__ part) {
@@ -758,16 +767,16 @@ __global__ __launch_bounds__(256) void k_m2l_f32(Geo g, M2LGeom mg, const M2LTas
     mult += (size_t)blockIdx.y * g.nbox * g.Kp;
     loc += (size_t)blockIdx.y * g.nbox * g.Kp;
     if (part) part += (size_t)blockIdx.y * mg.nchunk * mg.nt_all * g.Kp;
-    const int half = tk.lev >= 1 ? (1 << (tk.lev - 1)) : 1;
-    const bool active = tk.tile * kM2LTile + 16 * wave < half * half * half;
+    const bool active = tk.tile * kM2LTile + 16 * wave < mg.ncol;
     mf4 acc[RT];
 #pragma unroll
     for (int r = 0; r < RT; ++r) acc[r] = mf4{0.f, 0.f, 0.f, 0.f};
-    const int o0 = tk.chunk * mg.csize, o1 = min(o0 + mg.csize, 189);
+    const int o0 = cstart[tk.cls * (mg.nchunk + 1) + tk.chunk];
+    const int o1 = cstart[tk.cls * (mg.nchunk + 1) + tk.chunk + 1];
     for (int oc = o0; oc < o1; ++oc) {
         const int oi = olist[tk.cls * 189 + oc];
         __syncthreads();
-        m2l_source_boxes(g, tk.lev, tk.cls, tk.tile, oi, sbox);
+        m2l_source_boxes(g, tk.cls, tk.tile, oi, sbox);
         m2l_stage_op<float, uint2>(mg, bank, oi, A);
         __syncthreads();
         m2l_stage_src<float, float>(g, mg, sbox, mult, B, nullptr);
@@ -785,13 +794,14 @@ __global__ __launch_bounds__(256) void k_m2l_f32(Geo g, M2LGeom mg, const M2LTas
     if (!active) return;
 #pragma unroll
     for (int r = 0; r < RT; ++r)
-        m2l_store<mf4, float>(g, mg, tk.lev, tk.cls, tk.tile, tk.chunk, wave, lane, r, acc[r], false,
+        m2l_store<mf4, float>(g, mg, tk.cls, tk.tile, tk.chunk, wave, lane, r, acc[r], false,
                               loc, part);
 }
 
 template <int RT>
-__global__ __launch_bounds__(256) void k_m2l_f64(Geo g, M2LGeom mg, const M2LTask* __restrict__ tasks,
+__global__ __launch_bounds__(64 * kM2LWaves) void k_m2l_f64(Geo g, M2LGeom mg, const M2LTask* __restrict__ tasks,
                                                  const int16_t* __restrict__ olist,
+                                                 const int16_t* __restrict__ cstart,
                                                  const double* __restrict__ mult,
                                                  const double* __restrict__ bank,
                                                  double* __restrict__ loc, double* __restrict__ part) {
@@ -804,16 +814,16 @@ __global__ __launch_bounds__(256) void k_m2l_f64(Geo g, M2LGeom mg, const M2LTas
     mult += (size_t)blockIdx.y * g.nbox * g.Kp;
     loc += (size_t)blockIdx.y * g.nbox * g.Kp;
     if (part) part += (size_t)blockIdx.y * mg.nchunk * mg.nt_all * g.Kp;
-    const int half = tk.lev >= 1 ? (1 << (tk.lev - 1)) : 1;
-    const bool active = tk.tile * kM2LTile + 16 * wave < half * half * half;
+    const bool active = tk.tile * kM2LTile + 16 * wave < mg.ncol;
     md4 acc[RT];
 #pragma unroll
     for (int r = 0; r < RT; ++r) acc[r] = md4{0.0, 0.0, 0.0, 0.0};
-    const int o0 = tk.chunk * mg.csize, o1 = min(o0 + mg.csize, 189);
+    const int o0 = cstart[tk.cls * (mg.nchunk + 1) + tk.chunk];
+    const int o1 = cstart[tk.cls * (mg.nchunk + 1) + tk.chunk + 1];
     for (int oc = o0; oc < o1; ++oc) {
         const int oi = olist[tk.cls * 189 + oc];
         __syncthreads();
-        m2l_source_boxes(g, tk.lev, tk.cls, tk.tile, oi, sbox);
+        m2l_source_boxes(g, tk.cls, tk.tile, oi, sbox);
         m2l_stage_op<double, uint4>(mg, bank, oi, A);
         __syncthreads();
         m2l_stage_src<double, double>(g, mg, sbox, mult, B, nullptr);
@@ -831,14 +841,15 @@ __global__ __launch_bounds__(256) void k_m2l_f64(Geo g, M2LGeom mg, const M2LTas
     if (!active) return;
 #pragma unroll
     for (int r = 0; r < RT; ++r)
-        m2l_store<md4, double>(g, mg, tk.lev, tk.cls, tk.tile, tk.chunk, wave, lane, r, acc[r], true,
+        m2l_store<md4, double>(g, mg, tk.cls, tk.tile, tk.chunk, wave, lane, r, acc[r], true,
                                loc, part);
 }
 
 template <int RT>
-__global__ __launch_bounds__(256) void k_m2l_bf16x3(Geo g, M2LGeom mg,
+__global__ __launch_bounds__(64 * kM2LWaves) void k_m2l_bf16x3(Geo g, M2LGeom mg,
                                                     const M2LTask* __restrict__ tasks,
                                                     const int16_t* __restrict__ olist,
+                                                    const int16_t* __restrict__ cstart,
                                                     const float* __restrict__ mult,
                                                     const __bf16* __restrict__ bank_hi,
                                                     const __bf16* __restrict__ bank_lo,
@@ -854,16 +865,16 @@ __global__ __launch_bounds__(256) void k_m2l_bf16x3(Geo g, M2LGeom mg,
     mult += (size_t)blockIdx.y * g.nbox * g.Kp;
     loc += (size_t)blockIdx.y * g.nbox * g.Kp;
     if (part) part += (size_t)blockIdx.y * mg.nchunk * mg.nt_all * g.Kp;
-    const int half = tk.lev >= 1 ? (1 << (tk.lev - 1)) : 1;
-    const bool active = tk.tile * kM2LTile + 16 * wave < half * half * half;
+    const bool active = tk.tile * kM2LTile + 16 * wave < mg.ncol;
     mf4 acc[RT];
 #pragma unroll
     for (int r = 0; r < RT; ++r) acc[r] = mf4{0.f, 0.f, 0.f, 0.f};
-    const int o0 = tk.chunk * mg.csize, o1 = min(o0 + mg.csize, 189);
+    const int o0 = cstart[tk.cls * (mg.nchunk + 1) + tk.chunk];
+    const int o1 = cstart[tk.cls * (mg.nchunk + 1) + tk.chunk + 1];
     for (int oc = o0; oc < o1; ++oc) {
         const int oi = olist[tk.cls * 189 + oc];
         __syncthreads();
-        m2l_source_boxes(g, tk.lev, tk.cls, tk.tile, oi, sbox);
+        m2l_source_boxes(g, tk.cls, tk.tile, oi, sbox);
         m2l_stage_op<__bf16, uint4>(mg, bank_hi, oi, Ah);
         m2l_stage_op<__bf16, uint4>(mg, bank_lo, oi, Al);
         __syncthreads();
@@ -888,7 +899,7 @@ __global__ __launch_bounds__(256) void k_m2l_bf16x3(Geo g, M2LGeom mg,
     if (!active) return;
 #pragma unroll
     for (int r = 0; r < RT; ++r)
-        m2l_store<mf4, float>(g, mg, tk.lev, tk.cls, tk.tile, tk.chunk, wave, lane, r, acc[r], false,
+        m2l_store<mf4, float>(g, mg, tk.cls, tk.tile, tk.chunk, wave, lane, r, acc[r], false,
                               loc, part);
 }
 
