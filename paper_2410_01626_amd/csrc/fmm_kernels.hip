@@ -670,63 +670,105 @@ __device__ __forceinline__ void m2l_source_boxes(const Geo& g, int cls, int tile
     sbox[j] = b;
 }
 
+// Index split c -> (c / d, c % d) for small non-negative c by a float
+// reciprocal (exact for c < 2^20: the fraction (c mod d + 1/2) / d stays
+// inside (0, 1)).
+__device__ __forceinline__ void divmod_small(int c, int d, float inv_d, int& q, int& r) {
+    q = (int)(((float)c + 0.5f) * inv_d);
+    r = c - q * d;
+}
+
+constexpr int kStageGroup = 8;  // loads in flight per thread while staging
+
 // Copy operator block oi (RP x KP, row-major) into LDS rows of stride SA in
-// vector chunks of type V (KP and SA are multiples of the chunk).
+// vector chunks of type V (KP and SA are multiples of the chunk).  Loads are
+// issued in groups of kStageGroup per thread before their LDS stores.
 template <typename TE, typename V>
 __device__ __forceinline__ void m2l_stage_op(const M2LGeom& mg, const TE* __restrict__ bank, int oi,
                                              TE* __restrict__ A) {
     constexpr int E = sizeof(V) / sizeof(TE);
     const V* src = (const V*)(bank + (size_t)oi * mg.RP * mg.KP);
     const int cpr = mg.KP / E;  // chunks per row
+    const float inv = 1.0f / (float)cpr;
     const int tot = mg.RP * cpr;
-    for (int c = threadIdx.x; c < tot; c += blockDim.x) {
-        const int r = c / cpr, k = (c % cpr) * E;
-        *(V*)(A + r * mg.SA + k) = src[c];
+    const int nt = blockDim.x;
+    for (int c0 = threadIdx.x; c0 < tot; c0 += kStageGroup * nt) {
+        V v[kStageGroup];
+#pragma unroll
+        for (int m = 0; m < kStageGroup; ++m) v[m] = src[min(c0 + m * nt, tot - 1)];
+#pragma unroll
+        for (int m = 0; m < kStageGroup; ++m) {
+            const int c = c0 + m * nt;
+            if (c < tot) {
+                int r, k;
+                divmod_small(c, cpr, inv, r, k);
+                *(V*)(A + r * mg.SA + k * E) = v[m];
+            }
+        }
     }
 }
 
-// Gather the 64 source expansions (16-byte chunks of the expansion rows,
-// masked past K) into LDS as B[j][k]; bf16: split into hi and lo parts.
+// Gather the target columns' source expansions (16-byte chunks of the
+// expansion rows, masked past K) into LDS as B[j][k]; bf16: split into hi and
+// lo parts.  Loads are issued in groups of kStageGroup per thread.
 template <typename TS, typename TL>
 __device__ __forceinline__ void m2l_stage_src(const Geo& g, const M2LGeom& mg, const int* __restrict__ sbox,
                                               const TS* __restrict__ mult, TL* __restrict__ Bh,
                                               TL* __restrict__ Bl) {
     constexpr int E = 16 / sizeof(TS);
     const int cpr = mg.KP / E;
+    const float inv = 1.0f / (float)cpr;
     const int tot = kM2LTile * cpr;
-    for (int c = threadIdx.x; c < tot; c += blockDim.x) {
-        const int j = c / cpr, k = (c % cpr) * E;
-        const int b = sbox[j];
-        uint4 v = make_uint4(0u, 0u, 0u, 0u);
-        if (b >= 0 && k < g.K) {
-            v = *(const uint4*)(mult + (size_t)b * g.Kp + k);
-            const int valid = g.K - k;  // the row padding [K, Kp) is never written
-            if (E == 4) {
-                if (valid < 2) v.y = 0u;
-                if (valid < 3) v.z = 0u;
-                if (valid < 4) v.w = 0u;
-            } else if (valid < 2) {
-                v.z = 0u;
-                v.w = 0u;
-            }
+    const int nt = blockDim.x;
+    for (int c0 = threadIdx.x; c0 < tot; c0 += kStageGroup * nt) {
+        uint4 v[kStageGroup];
+#pragma unroll
+        for (int m = 0; m < kStageGroup; ++m) {
+            const int c = min(c0 + m * nt, tot - 1);
+            int j, kc;
+            divmod_small(c, cpr, inv, j, kc);
+            const int k = kc * E;
+            const int b = sbox[j];
+            // rows past the class's columns or without a source read row 0 and
+            // are zeroed below; k < KP <= Kp keeps the read inside the row
+            v[m] = *(const uint4*)(mult + (size_t)(b >= 0 ? b : 0) * g.Kp + (k < g.Kp ? k : 0));
         }
-        if constexpr (sizeof(TL) == 2) {
-            const float f0 = __uint_as_float(v.x), f1 = __uint_as_float(v.y);
-            const float f2 = __uint_as_float(v.z), f3 = __uint_as_float(v.w);
-            const __bf16 h0 = (__bf16)f0, h1 = (__bf16)f1, h2 = (__bf16)f2, h3 = (__bf16)f3;
-            const __bf16 l0 = (__bf16)(f0 - (float)h0), l1 = (__bf16)(f1 - (float)h1);
-            const __bf16 l2 = (__bf16)(f2 - (float)h2), l3 = (__bf16)(f3 - (float)h3);
-            auto pk = [](__bf16 a, __bf16 c2) {
-                return (uint32_t)__builtin_bit_cast(uint16_t, a) |
-                       ((uint32_t)__builtin_bit_cast(uint16_t, c2) << 16);
-            };
-            *(uint2*)(Bh + j * mg.SB + k) = make_uint2(pk(h0, h1), pk(h2, h3));
-            *(uint2*)(Bl + j * mg.SB + k) = make_uint2(pk(l0, l1), pk(l2, l3));
-        } else if constexpr (sizeof(TL) == 4) {
-            *(uint2*)(Bh + j * mg.SB + k) = make_uint2(v.x, v.y);
-            *(uint2*)(Bh + j * mg.SB + k + 2) = make_uint2(v.z, v.w);
-        } else {
-            *(uint4*)(Bh + j * mg.SB + k) = v;
+#pragma unroll
+        for (int m = 0; m < kStageGroup; ++m) {
+            const int c = c0 + m * nt;
+            if (c >= tot) continue;
+            int j, kc;
+            divmod_small(c, cpr, inv, j, kc);
+            const int k = kc * E;
+            uint4 w = v[m];
+            const int valid = sbox[j] >= 0 ? g.K - k : 0;  // the row padding [K, Kp) is never written
+            if (E == 4) {
+                if (valid < 1) w.x = 0u;
+                if (valid < 2) w.y = 0u;
+                if (valid < 3) w.z = 0u;
+                if (valid < 4) w.w = 0u;
+            } else {
+                if (valid < 1) { w.x = 0u; w.y = 0u; }
+                if (valid < 2) { w.z = 0u; w.w = 0u; }
+            }
+            if constexpr (sizeof(TL) == 2) {
+                const float f0 = __uint_as_float(w.x), f1 = __uint_as_float(w.y);
+                const float f2 = __uint_as_float(w.z), f3 = __uint_as_float(w.w);
+                const __bf16 h0 = (__bf16)f0, h1 = (__bf16)f1, h2 = (__bf16)f2, h3 = (__bf16)f3;
+                const __bf16 l0 = (__bf16)(f0 - (float)h0), l1 = (__bf16)(f1 - (float)h1);
+                const __bf16 l2 = (__bf16)(f2 - (float)h2), l3 = (__bf16)(f3 - (float)h3);
+                auto pk = [](__bf16 a, __bf16 c2) {
+                    return (uint32_t)__builtin_bit_cast(uint16_t, a) |
+                           ((uint32_t)__builtin_bit_cast(uint16_t, c2) << 16);
+                };
+                *(uint2*)(Bh + j * mg.SB + k) = make_uint2(pk(h0, h1), pk(h2, h3));
+                *(uint2*)(Bl + j * mg.SB + k) = make_uint2(pk(l0, l1), pk(l2, l3));
+            } else if constexpr (sizeof(TL) == 4) {
+                *(uint2*)(Bh + j * mg.SB + k) = make_uint2(w.x, w.y);
+                *(uint2*)(Bh + j * mg.SB + k + 2) = make_uint2(w.z, w.w);
+            } else {
+                *(uint4*)(Bh + j * mg.SB + k) = w;
+            }
         }
     }
 }
