@@ -995,7 +995,9 @@ __global__ __launch_bounds__(256) void k_l2l(Geo g, int lev, const Tin* __restri
 // ------------------------------------------------------------------ near + far field
 
 template <typename T> __device__ __forceinline__ T inv_sqrt(T v);
-template <> __device__ __forceinline__ float inv_sqrt<float>(float v) { return rsqrtf(v); }
+// hardware reciprocal square root (about 1 ulp); pair distances squared are
+// far from the denormal range, so no range scaling is needed
+template <> __device__ __forceinline__ float inv_sqrt<float>(float v) { return __builtin_amdgcn_rsqf(v); }
 template <> __device__ __forceinline__ double inv_sqrt<double>(double v) { return rsqrt(v); }
 
 // Like for_each_rho, but only the orders m = m0, m0 + dm, ... are visited (the
@@ -1052,12 +1054,14 @@ __global__ __launch_bounds__(64 * kNW) void k_near_far(
     T* __restrict__ phi_out, T* __restrict__ F_out,
     double* __restrict__ leaf_energy_all, double* __restrict__ cphi) {
     constexpr int NT = 64 * kNW;
+    // sources staged per pass: the whole 27-leaf neighbourhood of a typical leaf
+    constexpr int CAP = sizeof(T) == 4 ? 2048 : 1024;
     const int64_t n_sites = reps[blockIdx.y].S;
     const int32_t* leaf_start = leaf_start_all + (size_t)blockIdx.y * (g.nleaf + 1);
     const double* dom = dom_all + 8 * blockIdx.y;
     const T* loc = loc_all + (size_t)blockIdx.y * g.nbox * g.Kp;
     double* leaf_energy = leaf_energy_all + (size_t)blockIdx.y * g.nleaf;
-    __shared__ vec4_t<T> tile[NT];
+    __shared__ vec4_t<T> tile[CAP];
     __shared__ int nb_start[28], nb_cnt[28], nb_pre[29];
     __shared__ T nb_off[27][3];
     __shared__ T lam[kKMax];
@@ -1140,11 +1144,16 @@ __global__ __launch_bounds__(64 * kNW) void k_near_far(
         if (tv) me = pos[tb + tj];
         else { me.x = me.y = me.z = me.w = T(0); }
         T ph = T(0), fx = T(0), fy = T(0), fz = T(0);
-        const int sl = NT / wpc;
-        for (int s0 = 0; s0 < total; s0 += NT) {
+        for (int s0 = 0; s0 < total; s0 += CAP) {
+            const int cnt = min(CAP, total - s0);
             __syncthreads();
-            const int gsrc = s0 + tid;
-            if (gsrc < total) {
+            // stage the pass's sources, CAP / NT loads in flight per thread
+            constexpr int G = CAP / NT;
+            vec4_t<T> a[G];
+            int lo_[G];
+#pragma unroll
+            for (int m = 0; m < G; ++m) {
+                const int gsrc = s0 + min(tid + m * NT, cnt - 1);
                 // neighbour holding source gsrc: largest i with nb_pre[i] <= gsrc
                 int lo = 0, hi = 27;
                 while (hi - lo > 1) {
@@ -1152,16 +1161,24 @@ __global__ __launch_bounds__(64 * kNW) void k_near_far(
                     if (nb_pre[mid] <= gsrc) lo = mid;
                     else hi = mid;
                 }
-                vec4_t<T> a = pos[nb_start[lo] + (gsrc - nb_pre[lo])];
-                a.x += nb_off[lo][0];
-                a.y += nb_off[lo][1];
-                a.z += nb_off[lo][2];
-                tile[tid] = a;
+                lo_[m] = lo;
+                a[m] = pos[nb_start[lo] + (gsrc - nb_pre[lo])];
+            }
+#pragma unroll
+            for (int m = 0; m < G; ++m) {
+                if (tid + m * NT < cnt) {
+                    vec4_t<T> v = a[m];
+                    v.x += nb_off[lo_[m]][0];
+                    v.y += nb_off[lo_[m]][1];
+                    v.z += nb_off[lo_[m]][2];
+                    tile[tid + m * NT] = v;
+                }
             }
             __syncthreads();
             if (!live) continue;
+            const int sl = (cnt + wpc - 1) / wpc;
             const int jb = slice * sl;
-            const int je = min(jb + sl, total - s0);
+            const int je = min(jb + sl, cnt);
 #pragma unroll 4
             for (int j = jb; j < je; ++j) {
                 const vec4_t<T> s = tile[j];
