@@ -36,6 +36,9 @@ struct fmm_plan_s {
     void *bankT = nullptr, *m2mT = nullptr, *l2lT = nullptr, *gcoef = nullptr;
     double* latT = nullptr;
     int32_t* gidx = nullptr;
+    double *box_part = nullptr;  // per-box FP64 sums of q |t/L|^2 and q (upward pass)
+    uint32_t* tree_cnt = nullptr;  // upward-pass arrival counters per non-leaf parent
+    int64_t ncnt = 1;
     double *dom = nullptr, *bbox_part = nullptr, *leaf_part = nullptr, *leaf_energy = nullptr,
            *cphi = nullptr;
     int32_t* status = nullptr;
@@ -287,21 +290,15 @@ fmm_status enqueue_eval(fmm_plan_t P, const std::vector<fmmk::RepDesc>& rd, cons
     mark(P, 1);
     k_p2m<T><<<lg, 64, (size_t)64 * (g.K + 1) * sizeof(T), st>>>(g, pos, P->leaf_start, P->dom,
                                                                   mult, P->leaf_part);
-    // upward pass: parents at level lev from children at lev + 1
+    // upward pass (M2M to the coarsest level in use, periodic root and lattice)
     mark(P, 2);
-    const int64_t rstride = g.nbox * g.Kp;
-    for (int lev = g.depth - 1; lev >= 0; --lev) {
-        const unsigned np = 1u << (3 * lev);
-        if (lev == 0)
-            k_m2m<T, double><<<dim3(1, R), 256, 0, st>>>(g, 0, mult, (const T*)P->m2mT, P->root_m,
-                                                         g.K, g.K);
-        else
-            k_m2m<T, T><<<dim3(np, R), 256, 0, st>>>(g, lev, mult, (const T*)P->m2mT,
-                                                     mult + (size_t)g.lev_off[lev] * g.Kp, g.Kp,
-                                                     rstride);
-    }
+    const int lstop = g.periodic ? 0 : g.lmin;
+    if (g.depth >= 1 && g.depth - 1 >= lstop)
+        k_upward<T><<<dim3(1u << (3 * (g.depth - 1)), R), kTreeThreads, 0, st>>>(
+            g, lstop, mult, (const T*)P->m2mT, P->tree_cnt, P->ncnt, P->leaf_part, P->box_part,
+            P->root_m, P->latT, P->root_l, P->dom);
     mark(P, 3);
-    if (g.periodic)
+    if (g.periodic && g.depth == 0)
         k_root<T><<<R, 256, 0, st>>>(g, P->leaf_part, P->root_m, mult, P->latT, P->root_l, loc,
                                      P->dom);
     mark(P, 4);
@@ -314,18 +311,12 @@ fmm_status enqueue_eval(fmm_plan_t P, const std::vector<fmmk::RepDesc>& rd, cons
             launch_m2l_mma<T>(P, g, R);
         }
     }
-    // downward pass: children at lev + 1 from parents at lev
+    // downward pass: ancestors' local expansions and the L2L into the leaves
     mark(P, 5);
     const int l0 = g.periodic ? 0 : g.lmin;
-    for (int lev = l0; lev < g.depth; ++lev) {
-        const unsigned nc = 1u << (3 * (lev + 1));
-        if (lev == 0)
-            k_l2l<double, T><<<dim3(nc, R), 256, 0, st>>>(g, 0, P->root_l, g.K, g.K,
-                                                          (const T*)P->l2lT, loc);
-        else
-            k_l2l<T, T><<<dim3(nc, R), 256, 0, st>>>(g, lev, loc + (size_t)g.lev_off[lev] * g.Kp,
-                                                     g.Kp, rstride, (const T*)P->l2lT, loc);
-    }
+    if (g.depth >= 1 && g.depth - 1 >= l0)
+        k_downward<T><<<dim3(1u << (3 * (g.depth - 1)), R), kTreeThreads, 0, st>>>(
+            g, l0, loc, (const T*)P->l2lT, P->root_l);
     mark(P, 6);
     switch (P->p2p_waves) {
 #define FMM_NEAR(NWV)                                                                            \
@@ -505,14 +496,19 @@ fmm_status fmm_plan_create(const fmm_params* prm, void* hip_stream, fmm_plan_t* 
     ok &= dev_alloc(P, (void**)&P->root_m, RM * K * 8);
     ok &= dev_alloc(P, (void**)&P->root_l, RM * K * 8);
     ok &= dev_alloc(P, &P->bankT, 343 * K * K * ts);
-    ok &= dev_alloc(P, &P->m2mT, 8 * K * K * ts);
-    ok &= dev_alloc(P, &P->l2lT, 8 * K * K * ts);
+    ok &= dev_alloc(P, &P->m2mT, K * K * ts);  // octant 0; the others are its reflections
+    ok &= dev_alloc(P, &P->l2lT, K * K * ts);
     ok &= dev_alloc(P, (void**)&P->latT, K * K * 8);
     ok &= dev_alloc(P, (void**)&P->gidx, 3 * (size_t)P->Kg * 4 * 4);
     ok &= dev_alloc(P, &P->gcoef, 3 * (size_t)P->Kg * 4 * ts);
     ok &= dev_alloc(P, (void**)&P->dom, RM * 8 * 8);
     ok &= dev_alloc(P, (void**)&P->bbox_part, RM * kBboxBlocks * 6 * 8);
     ok &= dev_alloc(P, (void**)&P->leaf_part, RM * P->nleaf * 2 * 8);
+    ok &= dev_alloc(P, (void**)&P->box_part, RM * P->nbox * 2 * 8);
+    P->ncnt = std::max<int64_t>(1, P->lev_off[d > 0 ? d - 1 : 0]);
+    ok &= dev_alloc(P, (void**)&P->tree_cnt, RM * P->ncnt * 4);
+    // upward-pass counters start at zero once and count up by 8 per evaluation
+    if (ok) ok &= hipMemset(P->tree_cnt, 0, RM * P->ncnt * 4) == hipSuccess;
     ok &= dev_alloc(P, (void**)&P->leaf_energy, RM * P->nleaf * 8);
     ok &= dev_alloc(P, (void**)&P->reps, RM * sizeof(fmmk::RepDesc));
     ok &= dev_alloc(P, (void**)&P->cphi, N * 8);
@@ -540,20 +536,20 @@ fmm_status fmm_plan_create(const fmm_params* prm, void* hip_stream, fmm_plan_t* 
     };
     if (P->fp64) {
         auto b = transpose_blocks<double>(bank, 343, K);
-        auto a = transpose_blocks<double>(m2m, 8, K);
-        auto c = transpose_blocks<double>(l2l, 8, K);
+        auto a = transpose_blocks<double>(m2m, 1, K);
+        auto c = transpose_blocks<double>(l2l, 1, K);
         up(P->bankT, b.data(), b.size() * 8);
-        up(P->m2mT, a.data(), a.size() * 8);
-        up(P->l2lT, c.data(), c.size() * 8);
+        up(P->m2mT, a.data(), K * K * 8);
+        up(P->l2lT, c.data(), K * K * 8);
         up(P->gcoef, gc.data(), gc.size() * 8);
     } else {
         auto b = transpose_blocks<float>(bank, 343, K);
-        auto a = transpose_blocks<float>(m2m, 8, K);
-        auto c = transpose_blocks<float>(l2l, 8, K);
+        auto a = transpose_blocks<float>(m2m, 1, K);
+        auto c = transpose_blocks<float>(l2l, 1, K);
         std::vector<float> gf(gc.begin(), gc.end());
         up(P->bankT, b.data(), b.size() * 4);
-        up(P->m2mT, a.data(), a.size() * 4);
-        up(P->l2lT, c.data(), c.size() * 4);
+        up(P->m2mT, a.data(), K * K * 4);
+        up(P->l2lT, c.data(), K * K * 4);
         up(P->gcoef, gf.data(), gf.size() * 4);
     }
     auto lt = transpose_blocks<double>(lat, 1, K);

@@ -185,6 +185,31 @@ __global__ void k_bbox_final(const double* __restrict__ part, int nblk, double* 
 
 // ------------------------------------------------------------------ binning
 
+// Wave-aggregated counter increment: the lanes of a wavefront that hold the
+// same key share one atomic add on counter[key] and split the returned range
+// in lane order.  Returns the lane's slot (unique per key); inactive lanes get
+// -1.  Atoms arrive grouped by molecule, so a wavefront touches few distinct
+// leaves and one atomic replaces many same-address ones.
+__device__ __forceinline__ int32_t agg_increment(int32_t* counter, uint32_t key, bool active) {
+    const int lane = (int)__lane_id();
+    uint64_t todo = __ballot(active);
+    int32_t got = 0;
+    int my_leader = 0, my_off = -1;
+    while (todo) {
+        const int leader = __ffsll((unsigned long long)todo) - 1;
+        const uint32_t lk = (uint32_t)__shfl((int)key, leader, 64);
+        const uint64_t peers = __ballot(active && key == lk) & todo;
+        if (lane == leader) got = atomicAdd(&counter[lk], __popcll(peers));
+        if ((peers >> lane) & 1) {
+            my_leader = leader;
+            my_off = __popcll(peers & ((1ull << lane) - 1));
+        }
+        todo &= ~peers;
+    }
+    const int32_t base = __shfl(got, my_leader, 64);
+    return my_off < 0 ? -1 : base + my_off;
+}
+
 // Leaf key (Morton code of the leaf cell) of every atom, its rank inside the
 // leaf and inside its site (atomic counters: ranks are made stable later by
 // sorting), and the input checks.  The interpolated charge itself,
@@ -208,8 +233,8 @@ __global__ __launch_bounds__(256) void k_charge_key(
         dom[0] = dom[1] = dom[2] = 0.0;
         dom[3] = box;
     }
-    if (il >= rd.n) return;
-    const int64_t i = rd.a0 + il;
+    const bool live = il < rd.n;
+    const int64_t i = rd.a0 + (live ? il : 0);
     const int64_t n_sites = rd.S;
     double lo[3], edge;
     if (g.periodic) {
@@ -225,22 +250,24 @@ __global__ __launch_bounds__(256) void k_charge_key(
     int c[3];
     bool bad = false;
     for (int a = 0; a < 3; ++a) {
-        double v = (double)x[3 * i + a];
+        double v = live ? (double)x[3 * i + a] : 0.0;
         bad |= !finite_d(v);
         if (g.periodic) v -= edge * floor(v / edge);
         int ci = (int)floor((v - lo[a]) / h);
         c[a] = ci < 0 ? 0 : (ci >= g.nb ? g.nb - 1 : ci);
     }
     const uint32_t k = morton(c[0], c[1], c[2]);
-    key[i] = (int32_t)k;
-    rank[i] = atomicAdd(&leaf_count[k], 1);
-    int32_t s = site[i];
+    int32_t s = live ? site[i] : -1;
     if (s < -1 || s >= n_sites) {
         if (g.check) atomicOr(&status[0], kStatusSite);
         s = -1;
     }
-    int32_t sr = -1;
-    if (s >= 0) sr = atomicAdd(&site_count[rd.s0 + s], 1);
+    // every lane of the wavefront takes part in the aggregated increments
+    const int32_t lr = agg_increment(leaf_count, k, live);
+    const int32_t sr = agg_increment(site_count + rd.s0, (uint32_t)max(s, 0), live && s >= 0);
+    if (!live) return;
+    key[i] = (int32_t)k;
+    rank[i] = lr;
     site_rank[i] = sr;
     if (g.check) {
         bad |= !finite_d((double)qA[i]) || !finite_d((double)qB[i]);
@@ -457,38 +484,213 @@ __global__ __launch_bounds__(64) void k_p2m(Geo g, const vec4_t<T>* __restrict__
     }
 }
 
-// M2M for the parents at level lev (children at lev + 1): one block per
-// parent; the 8 K (child octant, output row) dot products are spread over the
-// block, then summed over octants in a fixed order.  Output degree l only
-// depends on child degrees <= l.  Ops are stored transposed: opT[c][k][r].
-template <typename Tin, typename Tout>
-__global__ __launch_bounds__(256) void k_m2m(Geo g, int lev, const Tin* __restrict__ mult_all,
-                                             const Tin* __restrict__ opT, Tout* __restrict__ out_all,
-                                             int out_stride, int64_t out_rstride) {
-    __shared__ Tin ch[8][kKMax];
-    __shared__ Tout red[8][kKMax];
-    const Tin* mult_in = mult_all + (size_t)blockIdx.y * g.nbox * g.Kp;
-    Tout* out = out_all + (size_t)blockIdx.y * out_rstride;
-    const int parent = blockIdx.x;
-    const Tin* src = mult_in + (size_t)(g.lev_off[lev + 1] + 8 * parent) * g.Kp;
-    for (int i = threadIdx.x; i < 8 * g.K; i += blockDim.x)
-        ch[i / g.K][i % g.K] = src[(size_t)(i / g.K) * g.Kp + i % g.K];
-    __syncthreads();
-    for (int it = threadIdx.x; it < 8 * g.K; it += blockDim.x) {
-        const int c = it / g.K, r = it % g.K;
+// ------------------------------------------------------------------ tree passes
+//
+// The eight child-octant operators of M2M (and of L2L) are one operator seen
+// through the reflections of the axes: reflecting x, y or z maps every real
+// harmonic onto +-itself, so A_c = S_c A_0 S_c with S_c diagonal +-1 (exactly,
+// entry by entry).  The tree kernels load rows of the octant-0 operator once
+// and apply them to all eight signed children.
+
+constexpr int kTreeThreads = 512;
+
+// Reflection parity of real coefficient k: bit 2 set when the coefficient
+// changes sign under x -> -x, bit 1 under y -> -y, bit 0 under z -> -z.  The
+// octant index c = 4 bx + 2 by + bz flips the axes whose bit is set, so the
+// sign of coefficient k for octant c is (-1)^popcount(c & bits).
+__device__ __forceinline__ int refl_bits(int k) {
+    const int l = (int)sqrtf((float)k + 0.5f);
+    const int rem = k - l * l;
+    const int m = (rem + 1) >> 1;
+    const int sn = (rem > 0 && !(rem & 1)) ? 1 : 0;  // sine part
+    const int xo = sn ? !(m & 1) : (m & 1);
+    return (xo << 2) | (sn << 1) | ((l + m) & 1);
+}
+__device__ __forceinline__ double refl_sign(int c, int bits) {
+    return (__popc((unsigned)(c & bits)) & 1) ? -1.0 : 1.0;
+}
+
+enum TriShape { kTriLower = 0, kTriUpper = 1, kTriFull = 2 };
+
+// ys[c][r] = sum_k A[r][k] xs[c][k] for the NC right-hand sides in LDS, A given
+// transposed (At[k K + r]) and visited only where it can be non-zero: output
+// degree l takes input degrees <= l (M2M, kTriLower), >= l (L2L, kTriUpper) or
+// all (kTriFull).  Each row's k range is cut into nseg contiguous segments
+// spread over the block; a segment's operator loads are issued 16 at a time
+// before they are used, and the segment sums are added in a fixed order.
+// part: LDS scratch of kTreeThreads * NC doubles; ys may alias xs.
+template <typename TO, int NC, int kShape>
+__device__ void tri_matvec(int K, const TO* __restrict__ At, double* xs, double* part, double* ys) {
+    const int nseg = max(1, min(8, kTreeThreads / K));
+    const int slen = (K + nseg - 1) / nseg;
+    for (int it = threadIdx.x; it < nseg * K; it += kTreeThreads) {
+        const int s = it / K, r = it - s * K;
         const int l = (int)sqrtf((float)r + 0.5f);
-        const int kend = (l + 1) * (l + 1);
-        const Tin* A = opT + (size_t)c * g.K * g.K + r;
-        Tout acc = Tout(0);
-        for (int k = 0; k < kend; ++k) acc += (Tout)A[(size_t)k * g.K] * (Tout)ch[c][k];
-        red[c][r] = acc;
+        const int kb = max(s * slen, kShape == kTriUpper ? l * l : 0);
+        const int ke = min(min(K, (s + 1) * slen), kShape == kTriLower ? (l + 1) * (l + 1) : K);
+        double acc[NC];
+#pragma unroll
+        for (int c = 0; c < NC; ++c) acc[c] = 0.0;
+        for (int k0 = kb; k0 < ke; k0 += 16) {
+            TO a[16];
+#pragma unroll
+            for (int j = 0; j < 16; ++j) a[j] = At[(size_t)min(k0 + j, ke - 1) * K + r];
+#pragma unroll
+            for (int j = 0; j < 16; ++j) {
+                const int k = min(k0 + j, ke - 1);
+                const double aj = (k0 + j < ke) ? (double)a[j] : 0.0;
+#pragma unroll
+                for (int c = 0; c < NC; ++c) acc[c] += aj * xs[c * K + k];
+            }
+        }
+#pragma unroll
+        for (int c = 0; c < NC; ++c) part[(s * NC + c) * K + r] = acc[c];
     }
     __syncthreads();
-    for (int r = threadIdx.x; r < g.K; r += blockDim.x) {
-        Tout acc = Tout(0);
+    for (int it = threadIdx.x; it < NC * K; it += kTreeThreads) {
+        double v = 0.0;
+        for (int s = 0; s < nseg; ++s) v += part[s * NC * K + it];
+        ys[it] = v;
+    }
+    __syncthreads();
+}
+
+// Upward pass in one launch: M2M from the leaves to level lev_stop (0 for
+// periodic systems, else the coarsest level with interactions) and, for
+// periodic systems, the root: lambda~_0 = Lat mu~_0 + (2 pi / 3) sum q |s/L|^2 e_0
+// and dom[4] = Q.  One block per box of level depth - 1 combines its 8 leaves;
+// the last of 8 sibling blocks to finish (device-scope counter per parent)
+// goes on with the parent, so every level is combined in the fixed octant
+// order whichever block arrives last.  Per-leaf FP64 sums of q |t/L|^2 and q
+// are carried up the same tree.  Accumulation is FP64; levels >= 1 are
+// stored in T, the root in FP64.  The counters count up by 8 per evaluation
+// and need no reset.
+template <typename T>
+__global__ __launch_bounds__(kTreeThreads) void k_upward(
+    Geo g, int lev_stop, T* mult_all, const T* __restrict__ op0, uint32_t* cnt_all, int64_t ncnt,
+    const double* __restrict__ leaf_part_all, double* box_part_all, double* __restrict__ root_m_all,
+    const double* __restrict__ latT, double* __restrict__ root_l_all, double* __restrict__ dom_all) {
+    __shared__ double xs[8 * kKMax], part[8 * kTreeThreads];
+    __shared__ double ps[2][8];
+    __shared__ int go_on;
+    const int rp = blockIdx.y, K = g.K;
+    T* mult = mult_all + (size_t)rp * g.nbox * g.Kp;
+    uint32_t* cnt = cnt_all + (size_t)rp * ncnt;
+    const double* leaf_part = leaf_part_all + (size_t)rp * g.nleaf * 2;
+    double* box_part = box_part_all + (size_t)rp * g.nbox * 2;
+    int lev = g.depth - 1, box = blockIdx.x;
+    double s2 = 0.0, qs = 0.0;
+    for (;;) {
+        const T* src = mult + (size_t)(g.lev_off[lev + 1] + 8 * (size_t)box) * g.Kp;
+        for (int i = threadIdx.x; i < 8 * K; i += kTreeThreads) {
+            const int c = i / K, k = i - c * K;
+            xs[i] = refl_sign(c, refl_bits(k)) * (double)src[(size_t)c * g.Kp + k];
+        }
+        if (g.periodic && threadIdx.x < 16) {
+            const int c = threadIdx.x >> 1, w = threadIdx.x & 1;
+            ps[w][c] = lev + 1 == g.depth ? leaf_part[2 * (8 * (size_t)box + c) + w]
+                                          : box_part[2 * (g.lev_off[lev + 1] + 8 * (size_t)box + c) + w];
+        }
+        __syncthreads();
+        if (g.periodic) {
+            s2 = qs = 0.0;
+            for (int c = 0; c < 8; ++c) {
+                s2 += ps[0][c];
+                qs += ps[1][c];
+            }
+        }
+        tri_matvec<T, 8, kTriLower>(K, op0, xs, part, xs);
+        // parent[r] = sum_c s_c(r) (A_0 S_c mu_c)[r]; the root is kept in LDS (part)
+        for (int r = threadIdx.x; r < K; r += kTreeThreads) {
+            const int b = refl_bits(r);
+            double acc = 0.0;
 #pragma unroll
-        for (int c = 0; c < 8; ++c) acc += red[c][r];
-        out[(size_t)parent * out_stride + r] = acc;
+            for (int c = 0; c < 8; ++c) acc += refl_sign(c, b) * xs[c * K + r];
+            if (lev > 0) mult[(size_t)(g.lev_off[lev] + box) * g.Kp + r] = (T)acc;
+            else {
+                root_m_all[(size_t)rp * K + r] = acc;
+                part[kTreeThreads * 8 - kKMax + r] = acc;
+            }
+        }
+        if (lev > 0 && g.periodic && threadIdx.x == 0) {
+            box_part[2 * (g.lev_off[lev] + box)] = s2;
+            box_part[2 * (g.lev_off[lev] + box) + 1] = qs;
+        }
+        if (lev == lev_stop) break;
+        // hand over to the parent: release this block's stores device-wide,
+        // count the sibling in, and continue only as the eighth
+        __threadfence();
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            const uint32_t old = __hip_atomic_fetch_add(&cnt[g.lev_off[lev - 1] + (box >> 3)], 1u,
+                                                         __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+            go_on = (old & 7u) == 7u;
+        }
+        __syncthreads();
+        if (!go_on) return;
+        __threadfence();
+        lev -= 1;
+        box >>= 3;
+    }
+    if (lev != 0 || !g.periodic) return;
+    // periodic root: the lattice operator on mu~_0 (FP64)
+    __syncthreads();
+    for (int k = threadIdx.x; k < K; k += kTreeThreads) xs[k] = part[kTreeThreads * 8 - kKMax + k];
+    __syncthreads();
+    tri_matvec<double, 1, kTriFull>(K, latT, xs, part, xs);
+    for (int r = threadIdx.x; r < K; r += kTreeThreads)
+        root_l_all[(size_t)rp * K + r] = xs[r] + (r == 0 ? 2.0 * kPi / 3.0 * s2 : 0.0);
+    if (threadIdx.x == 0) dom_all[8 * rp + 4] = qs;
+}
+
+// Downward pass in one launch: one block per box b of level depth - 1 forms
+// lambda~ of its ancestors from level l0 down (L2L of the parent's total
+// plus the box's own M2L sum, in FP64, the periodic root from the lattice
+// operator) and adds the L2L of lambda~_b into its 8 leaves.  Ancestors shared
+// by several blocks are recomputed by each; only the leaf expansions are
+// stored.  root_l is read when l0 == 0 (periodic), else level l0 starts from
+// its M2L sum alone.
+template <typename T>
+__global__ __launch_bounds__(kTreeThreads) void k_downward(Geo g, int l0, T* __restrict__ loc_all,
+                                                           const T* __restrict__ op0,
+                                                           const double* __restrict__ root_l_all) {
+    __shared__ double xs[8 * kKMax], part[8 * kTreeThreads];
+    __shared__ double v[kKMax];
+    __shared__ T anc[kDMax * kKMax];
+    const int rp = blockIdx.y, K = g.K, D = g.depth;
+    T* loc = loc_all + (size_t)rp * g.nbox * g.Kp;
+    const int b = blockIdx.x;
+    // prefetch the M2L sums of the ancestors at levels l0 + 1 .. D - 1 (and l0 when open)
+    const int la = g.periodic ? l0 + 1 : l0;
+    for (int i = threadIdx.x; i < (D - la) * K; i += kTreeThreads) {
+        const int li = i / K, k = i - li * K, lev = la + li;
+        anc[i] = loc[(size_t)(g.lev_off[lev] + (b >> (3 * (D - 1 - lev)))) * g.Kp + k];
+    }
+    for (int k = threadIdx.x; k < K; k += kTreeThreads)
+        if (g.periodic) v[k] = root_l_all[(size_t)rp * K + k];
+    __syncthreads();
+    if (!g.periodic)
+        for (int k = threadIdx.x; k < K; k += kTreeThreads) v[k] = (double)anc[k];
+    __syncthreads();
+    for (int lev = l0 + 1; lev < D; ++lev) {
+        const int a = b >> (3 * (D - 1 - lev)), c = a & 7;
+        for (int k = threadIdx.x; k < K; k += kTreeThreads) xs[k] = refl_sign(c, refl_bits(k)) * v[k];
+        __syncthreads();
+        tri_matvec<T, 1, kTriUpper>(K, op0, xs, part, xs);
+        for (int r = threadIdx.x; r < K; r += kTreeThreads)
+            v[r] = (double)anc[(lev - la) * K + r] + refl_sign(c, refl_bits(r)) * xs[r];
+        __syncthreads();
+    }
+    for (int i = threadIdx.x; i < 8 * K; i += kTreeThreads) {
+        const int c = i / K, k = i - c * K;
+        xs[i] = refl_sign(c, refl_bits(k)) * v[k];
+    }
+    __syncthreads();
+    tri_matvec<T, 8, kTriUpper>(K, op0, xs, part, xs);
+    T* dst = loc + (size_t)(g.lev_off[D] + 8 * (size_t)b) * g.Kp;
+    for (int i = threadIdx.x; i < 8 * K; i += kTreeThreads) {
+        const int c = i / K, r = i - c * K;
+        dst[(size_t)c * g.Kp + r] = (T)((double)dst[(size_t)c * g.Kp + r] + refl_sign(c, refl_bits(r)) * xs[i]);
     }
 }
 
@@ -962,35 +1164,6 @@ __global__ __launch_bounds__(256) void k_m2l_reduce(Geo g, M2LGeom mg, const T* 
 }
 
 // ------------------------------------------------------------------ downward pass
-
-// L2L into the children at level lev + 1 from their parents at level lev:
-// lambda~_child[r] += sum_{k >= l(r)^2} B_c[r][k] lambda~_parent[k].  One block
-// per child; each output row's dot product is split over 4 threads (k
-// interleaved) and combined in a fixed order.
-template <typename Tin, typename Tout>
-__global__ __launch_bounds__(256) void k_l2l(Geo g, int lev, const Tin* __restrict__ par_all,
-                                             int par_stride, int64_t par_rstride,
-                                             const Tout* __restrict__ opT, Tout* __restrict__ loc_all) {
-    __shared__ Tin pl[kKMax];
-    __shared__ Tout red[4][kKMax];
-    const Tin* par = par_all + (size_t)blockIdx.y * par_rstride;
-    Tout* loc = loc_all + (size_t)blockIdx.y * g.nbox * g.Kp;
-    const int child = blockIdx.x;
-    const int parent = child >> 3, c = child & 7;
-    for (int k = threadIdx.x; k < g.K; k += blockDim.x) pl[k] = par[(size_t)parent * par_stride + k];
-    __syncthreads();
-    const Tout* B = opT + (size_t)c * g.K * g.K;
-    for (int it = threadIdx.x; it < 4 * g.K; it += blockDim.x) {
-        const int q = it / g.K, r = it % g.K;
-        const int l = (int)sqrtf((float)r + 0.5f);
-        Tout acc = Tout(0);
-        for (int k = l * l + q; k < g.K; k += 4) acc += B[(size_t)k * g.K + r] * (Tout)pl[k];
-        red[q][r] = acc;
-    }
-    __syncthreads();
-    for (int r = threadIdx.x; r < g.K; r += blockDim.x)
-        loc[(size_t)(g.lev_off[lev + 1] + child) * g.Kp + r] += (red[0][r] + red[1][r]) + (red[2][r] + red[3][r]);
-}
 
 // ------------------------------------------------------------------ near + far field
 

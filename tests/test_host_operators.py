@@ -141,6 +141,31 @@ def test_l2l_is_exact():
         np.testing.assert_allclose(phi_c, phi_p, rtol=1e-12, atol=1e-12)
 
 
+def _reflection_bits(p):
+    """Per real coefficient: bit 2 if it flips sign under x -> -x, bit 1 under
+    y -> -y, bit 0 under z -> -z (cos m phi, sin m phi and P_l^m parities)."""
+    out = []
+    for l in range(p + 1):
+        for m in range(l + 1):
+            zo = (l + m) & 1
+            out.append(((m & 1) << 2) | zo)                 # cos part
+            if m:
+                out.append(((1 - (m & 1)) << 2) | 2 | zo)   # sin part
+    return np.array(out)
+
+
+@pytest.mark.parametrize("which", [1, 2])
+def test_octant_operators_are_reflections_of_octant_0(which):
+    """The device tree passes keep only octant 0 of M2M and L2L and form the
+    other seven as S_c A_0 S_c; that must hold entry by entry."""
+    p = 9
+    A = fmm.fmm_host_operator(p, which)
+    bits = _reflection_bits(p)
+    for c in range(8):
+        s = np.where(np.array([bin(c & b).count("1") & 1 for b in bits]) == 1, -1.0, 1.0)
+        np.testing.assert_array_equal(A[c], s[:, None] * A[0] * s[None, :])
+
+
 @pytest.mark.parametrize("neutral", [True, False])
 def test_lattice_operator_matches_ewald(neutral):
     """Depth-0 periodic FMM assembled from the host lattice operator: near field
