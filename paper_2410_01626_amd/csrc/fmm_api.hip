@@ -63,6 +63,8 @@ struct fmm_plan_s {
     int16_t* olist = nullptr;
     int16_t* cstart = nullptr;
     void *bank_mma = nullptr, *bank_mma_lo = nullptr, *m2l_part = nullptr;
+    void* msplit = nullptr;  // bf16x3: source expansions split into hi/lo (replicas x (nbox + 1) rows)
+    int m2l_nbuf = 1;        // bf16x3: LDS staging buffers (2: copy of the next offset overlaps)
     std::vector<void*> allocs;
     size_t ws_bytes = 0;
     std::string err;
@@ -219,10 +221,10 @@ void launch_m2l_mma(fmm_plan_t P, const Geo& g, int R) {
         break;
 #define FMM_M2L_BF(RTV)                                                                         \
     case 48 + RTV:                                                                              \
-        k_m2l_bf16x3<RTV><<<nt, 64 * kM2LWaves, lds, st>>>(g, mg, P->tasks, P->olist, P->cstart, (const float*)mult, \
-                                                (const __bf16*)P->bank_mma,                     \
-                                                (const __bf16*)P->bank_mma_lo, (float*)loc,     \
-                                                (float*)part);                                  \
+        k_m2l_bf16x3<RTV><<<nt, kM2LThreads, lds, st>>>(g, mg, P->tasks, P->olist, P->cstart,   \
+                                                (const uint4*)P->msplit,                        \
+                                                (const uint4*)P->bank_mma, P->m2l_nbuf,         \
+                                                (float*)loc, (float*)part);                     \
         break;
         FMM_M2L_F32(1) FMM_M2L_F32(2) FMM_M2L_F32(3) FMM_M2L_F32(4)
         FMM_M2L_F32(5) FMM_M2L_F32(6) FMM_M2L_F32(7) FMM_M2L_F32(8)
@@ -289,14 +291,15 @@ fmm_status enqueue_eval(fmm_plan_t P, const std::vector<fmmk::RepDesc>& rd, cons
                                               P->leaf_start, P->perm, pos, P->status);
     mark(P, 1);
     k_p2m<T><<<lg, 64, (size_t)64 * (g.K + 1) * sizeof(T), st>>>(g, pos, P->leaf_start, P->dom,
-                                                                  mult, P->leaf_part);
+                                                                  mult, P->leaf_part,
+                                                                  (uint16_t*)P->msplit, P->mg.KP);
     // upward pass (M2M to the coarsest level in use, periodic root and lattice)
     mark(P, 2);
     const int lstop = g.periodic ? 0 : g.lmin;
     if (g.depth >= 1 && g.depth - 1 >= lstop)
         k_upward<T><<<dim3(1u << (3 * (g.depth - 1)), R), kTreeThreads, 0, st>>>(
             g, lstop, mult, (const T*)P->m2mT, P->tree_cnt, P->ncnt, P->leaf_part, P->box_part,
-            P->root_m, P->latT, P->root_l, P->dom);
+            P->root_m, P->latT, P->root_l, P->dom, (uint16_t*)P->msplit, P->mg.KP);
     mark(P, 3);
     if (g.periodic && g.depth == 0)
         k_root<T><<<R, 256, 0, st>>>(g, P->leaf_part, P->root_m, mult, P->latT, P->root_l, loc,
@@ -582,7 +585,10 @@ fmm_status fmm_plan_create(const fmm_params* prm, void* hip_stream, fmm_plan_t* 
         const int64_t items = 8 * (int64_t)ntile * (int64_t)RM;
         int csize = prm->m2l_chunk;
         if (csize == 0) {
-            const int64_t want = std::max<int64_t>(1, std::min<int64_t>(27, (2048 + items - 1) / items));
+            // bf16x3 runs one double-buffered work-group per CU: about one task per CU;
+            // the others overlap two single-buffered work-groups per CU
+            const int64_t target = P->m2l_mode == 3 ? 256 : 2048, cap = P->m2l_mode == 3 ? 63 : 27;
+            const int64_t want = std::max<int64_t>(1, std::min<int64_t>(cap, (target + items - 1) / items));
             csize = (int)((189 + want - 1) / want);
         }
         mg.csize = csize;
@@ -634,16 +640,27 @@ fmm_status fmm_plan_create(const fmm_params* prm, void* hip_stream, fmm_plan_t* 
                 if (j < byx[x].size()) tl.push_back(byx[x][j]);
         P->n_tasks = (int64_t)tl.size();
         const size_t esz = P->m2l_mode == 2 ? 8 : (P->m2l_mode == 1 ? 4 : 2);
-        P->m2l_lds = esz * ((size_t)mg.RP * mg.SA + (size_t)fmmk::kM2LTile * mg.SB) *
-                     (P->m2l_mode == 3 ? 2 : 1);
+        P->m2l_lds = esz * ((size_t)mg.RP * mg.SA + (size_t)fmmk::kM2LTile * mg.SB);
+        const int KC = mg.KP / 8;
+        if (P->m2l_mode == 3) {
+            // one staging buffer: operator (2 KC RP chunks) + sources (2 KC 80 chunks)
+            const size_t one = (size_t)16 * 2 * KC * (mg.RP + fmmk::kM2LTile);
+            P->m2l_nbuf = 2 * one <= fmmk::kLdsBytes ? 2 : 1;
+            P->m2l_lds = P->m2l_nbuf * one;
+        }
         const std::vector<int16_t>& ol = cls_off;
         bool ok2 = !ol.empty();
         ok2 &= dev_alloc(P, (void**)&P->tasks, tl.size() * sizeof(fmmk::M2LTask));
         ok2 &= dev_alloc(P, (void**)&P->olist, ol.size() * sizeof(int16_t));
         ok2 &= dev_alloc(P, (void**)&P->cstart, cstart.size() * sizeof(int16_t));
         const size_t nb = (size_t)343 * mg.RP * mg.KP;
-        ok2 &= dev_alloc(P, &P->bank_mma, nb * esz);
-        if (P->m2l_mode == 3) ok2 &= dev_alloc(P, &P->bank_mma_lo, nb * esz);
+        ok2 &= dev_alloc(P, &P->bank_mma, nb * esz * (P->m2l_mode == 3 ? 2 : 1));
+        if (P->m2l_mode == 3) {
+            const size_t ms = RM * ((size_t)P->nbox + 1) * 2 * mg.KP * 2;
+            ok2 &= dev_alloc(P, &P->msplit, ms);
+            // the zero row and the padding past K are never written again
+            if (ok2) ok2 &= hipMemset(P->msplit, 0, ms) == hipSuccess;
+        }
         if (mg.nchunk > 1)
             ok2 &= dev_alloc(P, &P->m2l_part, RM * mg.nchunk * nt_all * P->Kp * P->tsz);
         if (!ok2) {
@@ -668,18 +685,20 @@ fmm_status fmm_plan_create(const fmm_params* prm, void* hip_stream, fmm_plan_t* 
                         bm[((size_t)o * mg.RP + r) * mg.KP + k] = (float)bank[((size_t)o * K + r) * K + k];
             up(P->bank_mma, bm.data(), nb * 4);
         } else {
-            std::vector<uint16_t> hi(nb, 0), lo(nb, 0);
+            // per offset: [part hi/lo][KC][RP][8], the LDS image of the operator
+            std::vector<uint16_t> bm(2 * nb, 0);
             for (int o = 0; o < 343; ++o)
                 for (size_t r = 0; r < K; ++r)
                     for (size_t k = 0; k < K; ++k) {
                         const double v = bank[((size_t)o * K + r) * K + k];
                         const uint16_t h = to_bf16((float)v);
-                        const size_t idx = ((size_t)o * mg.RP + r) * mg.KP + k;
-                        hi[idx] = h;
-                        lo[idx] = to_bf16((float)(v - (double)from_bf16(h)));
+                        const uint16_t l = to_bf16((float)(v - (double)from_bf16(h)));
+                        const size_t kc = k / 8, e8 = k % 8;
+                        const size_t base = (size_t)o * 2 * mg.RP * mg.KP;
+                        bm[base + ((0 * KC + kc) * mg.RP + r) * 8 + e8] = h;
+                        bm[base + (((size_t)KC + kc) * mg.RP + r) * 8 + e8] = l;
                     }
-            up(P->bank_mma, hi.data(), nb * 2);
-            up(P->bank_mma_lo, lo.data(), nb * 2);
+            up(P->bank_mma, bm.data(), 2 * nb * 2);
         }
         hipError_t ea = hipSuccess;
         auto setlds = [&](const void* fn) {

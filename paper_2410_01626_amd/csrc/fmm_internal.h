@@ -58,6 +58,7 @@ struct RepSet {
 namespace fmmk {
 
 // Matrix-core M2L: work items and tile sizes.
+constexpr size_t kLdsBytes = 160 * 1024;  // LDS per compute unit (gfx950)
 constexpr int kM2LWaves = 5;                 // wavefronts per matrix-core M2L work-group
 constexpr int kM2LTile = 16 * kM2LWaves;     // target columns per work-group
 constexpr int kM2LMaxRT = 8;    // row tiles of 16: K <= 128 (p <= 10)

@@ -103,6 +103,17 @@ __device__ __forceinline__ T wave_sum(T v) {
 
 __device__ __forceinline__ bool finite_d(double v) { return isfinite(v); }
 
+// Split FP32 expansion coefficients into bf16 hi + lo parts (the source
+// layout of the bf16x3 M2L): row `box` of the replica's split array.
+__device__ __forceinline__ void store_split(uint16_t* __restrict__ msplit_rep, int KP, int64_t box, int k,
+                                            float v) {
+    const __bf16 h = (__bf16)v;
+    const __bf16 l = (__bf16)(v - (float)h);
+    uint16_t* row = msplit_rep + (size_t)box * 2 * KP;
+    row[k] = __builtin_bit_cast(uint16_t, h);
+    row[KP + k] = __builtin_bit_cast(uint16_t, l);
+}
+
 // ------------------------------------------------------------------ fills
 
 __global__ void k_fill_i32(int32_t* p, int64_t n, int32_t v) {
@@ -417,7 +428,8 @@ __global__ __launch_bounds__(64) void k_p2m(Geo g, const vec4_t<T>* __restrict__
                                             const int32_t* __restrict__ leaf_start_all,
                                             const double* __restrict__ dom_all,
                                             T* __restrict__ mult_all,
-                                            double* __restrict__ leaf_part_all) {
+                                            double* __restrict__ leaf_part_all,
+                                            uint16_t* __restrict__ msplit_all, int split_kp) {
     extern __shared__ __align__(16) unsigned char p2m_lds[];
     const int32_t* leaf_start = leaf_start_all + (size_t)blockIdx.y * (g.nleaf + 1);
     const double* dom = dom_all + 8 * blockIdx.y;
@@ -469,10 +481,15 @@ __global__ __launch_bounds__(64) void k_p2m(Geo g, const vec4_t<T>* __restrict__
         __syncthreads();
     }
     T* dst = mult + (size_t)(g.lev_off[g.depth] + leaf) * g.Kp;
+    uint16_t* msplit = msplit_all ? msplit_all + (size_t)blockIdx.y * (g.nbox + 1) * 2 * split_kp : nullptr;
 #pragma unroll
     for (int i = 0; i < kKMax / 64; ++i) {
         const int k = lane + 64 * i;
-        if (k < g.K) dst[k] = acc[i];
+        if (k < g.K) {
+            dst[k] = acc[i];
+            if constexpr (sizeof(T) == 4)
+                if (msplit) store_split(msplit, split_kp, g.lev_off[g.depth] + leaf, k, acc[i]);
+        }
     }
     if (g.periodic) {
         s2 = wave_sum<double>(s2);
@@ -569,7 +586,8 @@ template <typename T>
 __global__ __launch_bounds__(kTreeThreads) void k_upward(
     Geo g, int lev_stop, T* mult_all, const T* __restrict__ op0, uint32_t* cnt_all, int64_t ncnt,
     const double* __restrict__ leaf_part_all, double* box_part_all, double* __restrict__ root_m_all,
-    const double* __restrict__ latT, double* __restrict__ root_l_all, double* __restrict__ dom_all) {
+    const double* __restrict__ latT, double* __restrict__ root_l_all, double* __restrict__ dom_all,
+    uint16_t* __restrict__ msplit_all, int split_kp) {
     __shared__ double xs[8 * kKMax], part[8 * kTreeThreads];
     __shared__ double ps[2][8];
     __shared__ int go_on;
@@ -606,7 +624,13 @@ __global__ __launch_bounds__(kTreeThreads) void k_upward(
             double acc = 0.0;
 #pragma unroll
             for (int c = 0; c < 8; ++c) acc += refl_sign(c, b) * xs[c * K + r];
-            if (lev > 0) mult[(size_t)(g.lev_off[lev] + box) * g.Kp + r] = (T)acc;
+            if (lev > 0) {
+                mult[(size_t)(g.lev_off[lev] + box) * g.Kp + r] = (T)acc;
+                if constexpr (sizeof(T) == 4)
+                    if (msplit_all)
+                        store_split(msplit_all + (size_t)rp * (g.nbox + 1) * 2 * split_kp, split_kp,
+                                    g.lev_off[lev] + box, r, (float)acc);
+            }
             else {
                 root_m_all[(size_t)rp * K + r] = acc;
                 part[kTreeThreads * 8 - kKMax + r] = acc;
@@ -1089,55 +1113,105 @@ __global__ __launch_bounds__(64 * kM2LWaves) void k_m2l_f64(Geo g, M2LGeom mg, c
                                loc, part);
 }
 
+// bf16x3 matrix-core M2L with direct global-to-LDS staging (gfx950
+// global_load_lds_dwordx4: each lane's 16 bytes land at the wavefront's LDS
+// base + 16 lane).  The operator bank and the source expansions are stored
+// pre-split into bf16 hi/lo parts in layouts that are their own LDS images:
+//   operator o: [part][KC][RP] chunks of 8 bf16 (chunk kc of row r holds
+//               k = 8 kc .. 8 kc + 7), 2 KC RP chunks, zero padded;
+//   box b:      [part][KC] chunks, row nbox of each replica all zero.
+// A step (one offset) copies the operator contiguously and, per target
+// column, the source box's 2 KC chunks into [part][KC][column] order; the
+// fragment reads of both are then 16 consecutive 16-byte chunks per quarter
+// wavefront (no LDS bank conflicts).  With two buffers the copy of offset
+// i + 1 is in flight while offset i is multiplied: one wait and one barrier
+// per offset.  Products Th mh + Th ml + Tl mh accumulate in FP32.
+constexpr int kM2LThreads = 64 * kM2LWaves;
+static_assert(kM2LThreads == 4 * kM2LTile, "source copy mapping: 4 lanes per column");
+
+__device__ __forceinline__ void lds_dma16(const uint4* gsrc, uint4* lds_wave_base) {
+    __builtin_amdgcn_global_load_lds((const void*)gsrc,
+                                     (__attribute__((address_space(3))) void*)lds_wave_base, 16, 0, 0);
+}
+
 template <int RT>
-__global__ __launch_bounds__(64 * kM2LWaves) void k_m2l_bf16x3(Geo g, M2LGeom mg,
-                                                    const M2LTask* __restrict__ tasks,
-                                                    const int16_t* __restrict__ olist,
-                                                    const int16_t* __restrict__ cstart,
-                                                    const float* __restrict__ mult,
-                                                    const __bf16* __restrict__ bank_hi,
-                                                    const __bf16* __restrict__ bank_lo,
-                                                    float* __restrict__ loc, float* __restrict__ part) {
-    extern __shared__ __align__(16) __bf16 lds_bf[];
-    __bf16* Ah = lds_bf;
-    __bf16* Al = Ah + mg.RP * mg.SA;
-    __bf16* Bh = Al + mg.RP * mg.SA;
-    __bf16* Bl = Bh + kM2LTile * mg.SB;
-    __shared__ int sbox[kM2LTile];
+__global__ __launch_bounds__(kM2LThreads) void k_m2l_bf16x3(Geo g, M2LGeom mg,
+                                                           const M2LTask* __restrict__ tasks,
+                                                           const int16_t* __restrict__ olist,
+                                                           const int16_t* __restrict__ cstart,
+                                                           const uint4* __restrict__ msplit,
+                                                           const uint4* __restrict__ bank, int nbuf,
+                                                           float* __restrict__ loc, float* __restrict__ part) {
+    extern __shared__ __align__(16) uint4 lds_q[];
+    const int KC = mg.KP / 8;
+    const int a_chunks = 2 * KC * mg.RP, b_chunks = 2 * KC * kM2LTile;
     const M2LTask tk = tasks[blockIdx.x];
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    mult += (size_t)blockIdx.y * g.nbox * g.Kp;
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    msplit += (size_t)blockIdx.y * (g.nbox + 1) * 2 * KC;
     loc += (size_t)blockIdx.y * g.nbox * g.Kp;
     if (part) part += (size_t)blockIdx.y * mg.nchunk * mg.nt_all * g.Kp;
     const bool active = tk.tile * kM2LTile + 16 * wave < mg.ncol;
+    // the staging lane's source column and its place in the tree
+    const int jc = tid % kM2LTile, q = tid / kM2LTile;
+    int clev = 0, ctx = 0, cty = 0, ctz = 0;
+    const bool col_ok = m2l_column(g, tk.cls, tk.tile, jc, clev, ctx, cty, ctz);
+    const int cn = 1 << clev;
+    const int64_t clo = g.lev_off[clev];
+    const int o0 = cstart[tk.cls * (mg.nchunk + 1) + tk.chunk];
+    const int o1 = cstart[tk.cls * (mg.nchunk + 1) + tk.chunk + 1];
+
+    auto issue = [&](int oc, uint4* dst) {
+        const int oi = olist[tk.cls * 189 + oc];
+        const uint4* src = bank + (size_t)oi * a_chunks;
+        for (int c0 = 0; c0 < a_chunks; c0 += kM2LThreads)
+            if (c0 + tid < a_chunks) lds_dma16(src + c0 + tid, dst + c0 + 64 * wave);
+        const int ox = oi / 49 - 3, oy = (oi / 7) % 7 - 3, oz = oi % 7 - 3;
+        int sx = ctx - ox, sy = cty - oy, sz = ctz - oz;
+        bool ok = col_ok;
+        if (g.periodic) {
+            sx &= cn - 1;
+            sy &= cn - 1;
+            sz &= cn - 1;
+        } else {
+            ok = ok && sx >= 0 && sy >= 0 && sz >= 0 && sx < cn && sy < cn && sz < cn;
+        }
+        const int64_t b = ok ? clo + morton(sx, sy, sz) : g.nbox;
+        const uint4* s = msplit + b * 2 * KC + q;
+        uint4* d = dst + a_chunks;
+        for (int m = 0; m < 2 * KC / 4; ++m) lds_dma16(s + 4 * m, d + m * kM2LThreads + 64 * wave);
+    };
+
     mf4 acc[RT];
 #pragma unroll
     for (int r = 0; r < RT; ++r) acc[r] = mf4{0.f, 0.f, 0.f, 0.f};
-    const int o0 = cstart[tk.cls * (mg.nchunk + 1) + tk.chunk];
-    const int o1 = cstart[tk.cls * (mg.nchunk + 1) + tk.chunk + 1];
+    const int col = 16 * wave + (lane & 15), kq = lane >> 4, row = lane & 15;
+    if (o0 < o1) issue(o0, lds_q);
     for (int oc = o0; oc < o1; ++oc) {
-        const int oi = olist[tk.cls * 189 + oc];
-        __syncthreads();
-        m2l_source_boxes(g, tk.cls, tk.tile, oi, sbox);
-        m2l_stage_op<__bf16, uint4>(mg, bank_hi, oi, Ah);
-        m2l_stage_op<__bf16, uint4>(mg, bank_lo, oi, Al);
-        __syncthreads();
-        m2l_stage_src<float, __bf16>(g, mg, sbox, mult, Bh, Bl);
-        __syncthreads();
-        if (!active) continue;
-        const int boff = (16 * wave + (lane & 15)) * mg.SB + 8 * (lane >> 4);
-        const int aoff = (lane & 15) * mg.SA + 8 * (lane >> 4);
-        for (int ks = 0; ks < mg.KP; ks += 32) {
-            const mbf8 bh = *(const mbf8*)(Bh + boff + ks);
-            const mbf8 bl = *(const mbf8*)(Bl + boff + ks);
+        const int st = oc - o0;
+        uint4* cur = lds_q + (size_t)(st & (nbuf - 1)) * (a_chunks + b_chunks);
+        __builtin_amdgcn_s_waitcnt(0);  // this lane's copies of offset oc have landed
+        __syncthreads();                // everyone's have; the other buffer is free
+        if (nbuf == 2 && oc + 1 < o1) issue(oc + 1, lds_q + (size_t)((st + 1) & 1) * (a_chunks + b_chunks));
+        if (active) {
+            const uint4* A = cur;
+            const uint4* B = cur + a_chunks;
+            for (int ks = 0; ks < KC; ks += 4) {
+                const int kc = ks + kq;
+                const mbf8 bh = __builtin_bit_cast(mbf8, B[kc * kM2LTile + col]);
+                const mbf8 bl = __builtin_bit_cast(mbf8, B[(KC + kc) * kM2LTile + col]);
 #pragma unroll
-            for (int r = 0; r < RT; ++r) {
-                const mbf8 ah = *(const mbf8*)(Ah + aoff + 16 * r * mg.SA + ks);
-                const mbf8 al = *(const mbf8*)(Al + aoff + 16 * r * mg.SA + ks);
-                acc[r] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh, acc[r], 0, 0, 0);
-                acc[r] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl, acc[r], 0, 0, 0);
-                acc[r] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh, acc[r], 0, 0, 0);
+                for (int r = 0; r < RT; ++r) {
+                    const mbf8 ah = __builtin_bit_cast(mbf8, A[kc * mg.RP + 16 * r + row]);
+                    const mbf8 al = __builtin_bit_cast(mbf8, A[(KC + kc) * mg.RP + 16 * r + row]);
+                    acc[r] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh, acc[r], 0, 0, 0);
+                    acc[r] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl, acc[r], 0, 0, 0);
+                    acc[r] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh, acc[r], 0, 0, 0);
+                }
             }
+        }
+        if (nbuf == 1 && oc + 1 < o1) {
+            __syncthreads();
+            issue(oc + 1, lds_q);
         }
     }
     if (!active) return;
