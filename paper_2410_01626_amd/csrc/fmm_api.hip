@@ -37,8 +37,6 @@ struct fmm_plan_s {
     double* latT = nullptr;
     int32_t* gidx = nullptr;
     double *box_part = nullptr;  // per-box FP64 sums of q |t/L|^2 and q (upward pass)
-    uint32_t* tree_cnt = nullptr;  // upward-pass arrival counters per non-leaf parent
-    int64_t ncnt = 1;
     double *dom = nullptr, *bbox_part = nullptr, *leaf_part = nullptr, *leaf_energy = nullptr,
            *cphi = nullptr;
     int32_t* status = nullptr;
@@ -257,18 +255,23 @@ fmm_status enqueue_eval(fmm_plan_t P, const std::vector<fmmk::RepDesc>& rd, cons
         maxn = std::max(maxn, d.n);
         S_tot += d.S;
     }
+    mark(P, 0);
+    // first launch: replica descriptors (up to kRepsPerSet, by value) and the
+    // cleared leaf and site counters; further descriptor sets follow
     for (int f = 0; f < R; f += kRepsPerSet) {
         RepSet set{};
         set.first = f;
         set.count = std::min(kRepsPerSet, R - f);
         for (int i = 0; i < set.count; ++i) set.d[i] = rd[f + i];
-        k_set_reps<<<1, kRepsPerSet, 0, st>>>(set, P->reps);
+        if (f == 0) {
+            const int64_t nl = (int64_t)R * g.nleaf;
+            k_prologue<<<nblocks(std::max(nl, S_tot), 256), 256, 0, st>>>(set, P->reps, P->leaf_count,
+                                                                          nl, P->site_count, S_tot);
+        } else {
+            k_set_reps<<<1, kRepsPerSet, 0, st>>>(set, P->reps);
+        }
     }
     const RepDesc* reps = P->reps;
-    mark(P, 0);
-    k_fill_i32<<<nblocks((int64_t)R * g.nleaf, 256), 256, 0, st>>>(P->leaf_count,
-                                                                   (int64_t)R * g.nleaf, 0);
-    if (S_tot > 0) k_fill_i32<<<nblocks(S_tot, 256), 256, 0, st>>>(P->site_count, S_tot, 0);
     const unsigned ab = nblocks(maxn, 256);
     if (!g.periodic) {
         const int nb = (int)std::min<int64_t>(kBboxBlocks, ab);
@@ -293,13 +296,13 @@ fmm_status enqueue_eval(fmm_plan_t P, const std::vector<fmmk::RepDesc>& rd, cons
     k_p2m<T><<<lg, 64, (size_t)64 * (g.K + 1) * sizeof(T), st>>>(g, pos, P->leaf_start, P->dom,
                                                                   mult, P->leaf_part,
                                                                   (uint16_t*)P->msplit, P->mg.KP);
-    // upward pass (M2M to the coarsest level in use, periodic root and lattice)
+    // upward pass: one launch per level down to the coarsest interacting
+    // level (1 periodic, 2 open); the periodic root and its lattice operator
+    // are formed at the start of the downward pass
     mark(P, 2);
-    const int lstop = g.periodic ? 0 : g.lmin;
-    if (g.depth >= 1 && g.depth - 1 >= lstop)
-        k_upward<T><<<dim3(1u << (3 * (g.depth - 1)), R), kTreeThreads, 0, st>>>(
-            g, lstop, mult, (const T*)P->m2mT, P->tree_cnt, P->ncnt, P->leaf_part, P->box_part,
-            P->root_m, P->latT, P->root_l, P->dom, (uint16_t*)P->msplit, P->mg.KP);
+    for (int lev = g.depth - 1; lev >= g.lmin; --lev)
+        k_m2m<T><<<dim3(1u << (3 * lev), R), kTreeThreads, 0, st>>>(
+            g, lev, mult, (const T*)P->m2mT, P->leaf_part, P->box_part, (uint16_t*)P->msplit, P->mg.KP);
     mark(P, 3);
     if (g.periodic && g.depth == 0)
         k_root<T><<<R, 256, 0, st>>>(g, P->leaf_part, P->root_m, mult, P->latT, P->root_l, loc,
@@ -319,7 +322,8 @@ fmm_status enqueue_eval(fmm_plan_t P, const std::vector<fmmk::RepDesc>& rd, cons
     const int l0 = g.periodic ? 0 : g.lmin;
     if (g.depth >= 1 && g.depth - 1 >= l0)
         k_downward<T><<<dim3(1u << (3 * (g.depth - 1)), R), kTreeThreads, 0, st>>>(
-            g, l0, loc, (const T*)P->l2lT, P->root_l);
+            g, l0, loc, (const T*)P->l2lT, mult, (const T*)P->m2mT, P->leaf_part, P->box_part, P->latT,
+            P->root_m, P->root_l, P->dom);
     mark(P, 6);
     switch (P->p2p_waves) {
 #define FMM_NEAR(NWV)                                                                            \
@@ -508,10 +512,6 @@ fmm_status fmm_plan_create(const fmm_params* prm, void* hip_stream, fmm_plan_t* 
     ok &= dev_alloc(P, (void**)&P->bbox_part, RM * kBboxBlocks * 6 * 8);
     ok &= dev_alloc(P, (void**)&P->leaf_part, RM * P->nleaf * 2 * 8);
     ok &= dev_alloc(P, (void**)&P->box_part, RM * P->nbox * 2 * 8);
-    P->ncnt = std::max<int64_t>(1, P->lev_off[d > 0 ? d - 1 : 0]);
-    ok &= dev_alloc(P, (void**)&P->tree_cnt, RM * P->ncnt * 4);
-    // upward-pass counters start at zero once and count up by 8 per evaluation
-    if (ok) ok &= hipMemset(P->tree_cnt, 0, RM * P->ncnt * 4) == hipSuccess;
     ok &= dev_alloc(P, (void**)&P->leaf_energy, RM * P->nleaf * 8);
     ok &= dev_alloc(P, (void**)&P->reps, RM * sizeof(fmmk::RepDesc));
     ok &= dev_alloc(P, (void**)&P->cphi, N * 8);

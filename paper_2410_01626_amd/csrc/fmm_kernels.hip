@@ -7,6 +7,7 @@
 // [lev_off[l], lev_off[l] + 8^l) of the expansion arrays.  Particles are kept
 // sorted by leaf with coordinates relative to their leaf centre, so periodic
 // images reduce to integer leaf offsets times the leaf edge.
+#include <type_traits>
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
@@ -131,6 +132,18 @@ __global__ void k_fill_f64(double* p, int64_t n, double v) {
 __global__ void k_set_reps(RepSet set, RepDesc* __restrict__ reps) {
     const int i = threadIdx.x;
     if (i < set.count) reps[set.first + i] = set.d[i];
+}
+
+// Start of an evaluation: replica descriptors of the first set, leaf and site
+// counters cleared (a fill kernel: graph replays record no memset nodes).
+__global__ void k_prologue(RepSet set, RepDesc* __restrict__ reps, int32_t* __restrict__ leaf_count,
+                           int64_t nl, int32_t* __restrict__ site_count, int64_t ns) {
+    const int64_t i0 = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i0 < set.count) reps[set.first + i0] = set.d[i0];
+    for (int64_t i = i0; i < nl || i < ns; i += (int64_t)gridDim.x * blockDim.x) {
+        if (i < nl) leaf_count[i] = 0;
+        if (i < ns) site_count[i] = 0;
+    }
 }
 
 // ------------------------------------------------------------------ domain
@@ -528,40 +541,71 @@ __device__ __forceinline__ double refl_sign(int c, int bits) {
 }
 
 enum TriShape { kTriLower = 0, kTriUpper = 1, kTriFull = 2 };
+constexpr int kTriCache = 32;  // operator entries a thread keeps in registers
 
-// ys[c][r] = sum_k A[r][k] xs[c][k] for the NC right-hand sides in LDS, A given
-// transposed (At[k K + r]) and visited only where it can be non-zero: output
-// degree l takes input degrees <= l (M2M, kTriLower), >= l (L2L, kTriUpper) or
-// all (kTriFull).  Each row's k range is cut into nseg contiguous segments
-// spread over the block; a segment's operator loads are issued 16 at a time
-// before they are used, and the segment sums are added in a fixed order.
-// part: LDS scratch of kTreeThreads * NC doubles; ys may alias xs.
+// One thread's share of a degree-triangular K x K operator A (given
+// transposed, At[k K + r]): a row r and a contiguous k range [kb, ke) of it.
+// Output degree l takes input degrees <= l (M2M, kTriLower), >= l (L2L,
+// kTriUpper) or all (kTriFull).  Each row is cut into nseg = 512 / K
+// segments (at most 8), so a block of kTreeThreads holds every (segment,
+// row) pair once.  The first kTriCache entries of the range are loaded once
+// into registers and reused by every product the block forms.
+template <typename TO, int kShape>
+struct TriPart {
+    int r, s, kb, ke;
+    TO a[kTriCache];
+    __device__ __forceinline__ void load(int K, const TO* __restrict__ At) {
+        const int nseg = max(1, min(8, kTreeThreads / K));
+        const int slen = (K + nseg - 1) / nseg;
+        const int it = threadIdx.x;
+        r = -1;
+        s = kb = ke = 0;
+        if (it < nseg * K) {
+            s = it / K;
+            r = it - s * K;
+            const int l = (int)sqrtf((float)r + 0.5f);
+            kb = max(s * slen, kShape == kTriUpper ? l * l : 0);
+            ke = min(min(K, (s + 1) * slen), kShape == kTriLower ? (l + 1) * (l + 1) : K);
+        }
+        const int last = max(kb, ke - 1);
+        const int rr = max(r, 0);
+#pragma unroll
+        for (int j = 0; j < kTriCache; ++j) a[j] = At[(size_t)min(kb + j, last) * K + rr];
+    }
+};
+
+// ys[c][r] = sum_k A[r][k] xs[c][k] for the NC right-hand sides in LDS
+// (FP64), with the thread's part of A from `tp` and any entries past the
+// register cache loaded 16 at a time.  Segment sums are added in a fixed
+// order.  part: LDS scratch of kTreeThreads * NC doubles; ys may alias xs.
 template <typename TO, int NC, int kShape>
-__device__ void tri_matvec(int K, const TO* __restrict__ At, double* xs, double* part, double* ys) {
+__device__ void tri_matvec(const TriPart<TO, kShape>& tp, int K, const TO* __restrict__ At, double* xs,
+                           double* part, double* ys) {
     const int nseg = max(1, min(8, kTreeThreads / K));
-    const int slen = (K + nseg - 1) / nseg;
-    for (int it = threadIdx.x; it < nseg * K; it += kTreeThreads) {
-        const int s = it / K, r = it - s * K;
-        const int l = (int)sqrtf((float)r + 0.5f);
-        const int kb = max(s * slen, kShape == kTriUpper ? l * l : 0);
-        const int ke = min(min(K, (s + 1) * slen), kShape == kTriLower ? (l + 1) * (l + 1) : K);
+    if (tp.r >= 0) {
         double acc[NC];
 #pragma unroll
         for (int c = 0; c < NC; ++c) acc[c] = 0.0;
-        for (int k0 = kb; k0 < ke; k0 += 16) {
+        const int n = tp.ke - tp.kb;
+#pragma unroll
+        for (int j = 0; j < kTriCache; ++j)
+            if (j < n)
+#pragma unroll
+                for (int c = 0; c < NC; ++c) acc[c] += (double)tp.a[j] * xs[c * K + tp.kb + j];
+        for (int k0 = tp.kb + kTriCache; k0 < tp.ke; k0 += 16) {
             TO a[16];
 #pragma unroll
-            for (int j = 0; j < 16; ++j) a[j] = At[(size_t)min(k0 + j, ke - 1) * K + r];
+            for (int j = 0; j < 16; ++j) a[j] = At[(size_t)min(k0 + j, tp.ke - 1) * K + tp.r];
 #pragma unroll
             for (int j = 0; j < 16; ++j) {
-                const int k = min(k0 + j, ke - 1);
-                const double aj = (k0 + j < ke) ? (double)a[j] : 0.0;
+                const int k = min(k0 + j, tp.ke - 1);
+                const double aj = (k0 + j < tp.ke) ? (double)a[j] : 0.0;
 #pragma unroll
                 for (int c = 0; c < NC; ++c) acc[c] += aj * xs[c * K + k];
             }
         }
 #pragma unroll
-        for (int c = 0; c < NC; ++c) part[(s * NC + c) * K + r] = acc[c];
+        for (int c = 0; c < NC; ++c) part[(tp.s * NC + c) * K + tp.r] = acc[c];
     }
     __syncthreads();
     for (int it = threadIdx.x; it < NC * K; it += kTreeThreads) {
@@ -572,115 +616,89 @@ __device__ void tri_matvec(int K, const TO* __restrict__ At, double* xs, double*
     __syncthreads();
 }
 
-// Upward pass in one launch: M2M from the leaves to level lev_stop (0 for
-// periodic systems, else the coarsest level with interactions) and, for
-// periodic systems, the root: lambda~_0 = Lat mu~_0 + (2 pi / 3) sum q |s/L|^2 e_0
-// and dom[4] = Q.  One block per box of level depth - 1 combines its 8 leaves;
-// the last of 8 sibling blocks to finish (device-scope counter per parent)
-// goes on with the parent, so every level is combined in the fixed octant
-// order whichever block arrives last.  Per-leaf FP64 sums of q |t/L|^2 and q
-// are carried up the same tree.  Accumulation is FP64; levels >= 1 are
-// stored in T, the root in FP64.  The counters count up by 8 per evaluation
-// and need no reset.
+// Signed children of one parent into xs[c][k] (FP64) and, for periodic
+// systems, the sum of their FP64 partials (q |t/L|^2, q) into ps2.
 template <typename T>
-__global__ __launch_bounds__(kTreeThreads) void k_upward(
-    Geo g, int lev_stop, T* mult_all, const T* __restrict__ op0, uint32_t* cnt_all, int64_t ncnt,
-    const double* __restrict__ leaf_part_all, double* box_part_all, double* __restrict__ root_m_all,
-    const double* __restrict__ latT, double* __restrict__ root_l_all, double* __restrict__ dom_all,
-    uint16_t* __restrict__ msplit_all, int split_kp) {
-    __shared__ double xs[8 * kKMax], part[8 * kTreeThreads];
-    __shared__ double ps[2][8];
-    __shared__ int go_on;
-    const int rp = blockIdx.y, K = g.K;
-    T* mult = mult_all + (size_t)rp * g.nbox * g.Kp;
-    uint32_t* cnt = cnt_all + (size_t)rp * ncnt;
-    const double* leaf_part = leaf_part_all + (size_t)rp * g.nleaf * 2;
-    double* box_part = box_part_all + (size_t)rp * g.nbox * 2;
-    int lev = g.depth - 1, box = blockIdx.x;
-    double s2 = 0.0, qs = 0.0;
-    for (;;) {
-        const T* src = mult + (size_t)(g.lev_off[lev + 1] + 8 * (size_t)box) * g.Kp;
-        for (int i = threadIdx.x; i < 8 * K; i += kTreeThreads) {
-            const int c = i / K, k = i - c * K;
-            xs[i] = refl_sign(c, refl_bits(k)) * (double)src[(size_t)c * g.Kp + k];
-        }
-        if (g.periodic && threadIdx.x < 16) {
-            const int c = threadIdx.x >> 1, w = threadIdx.x & 1;
-            ps[w][c] = lev + 1 == g.depth ? leaf_part[2 * (8 * (size_t)box + c) + w]
-                                          : box_part[2 * (g.lev_off[lev + 1] + 8 * (size_t)box + c) + w];
-        }
-        __syncthreads();
-        if (g.periodic) {
-            s2 = qs = 0.0;
-            for (int c = 0; c < 8; ++c) {
-                s2 += ps[0][c];
-                qs += ps[1][c];
-            }
-        }
-        tri_matvec<T, 8, kTriLower>(K, op0, xs, part, xs);
-        // parent[r] = sum_c s_c(r) (A_0 S_c mu_c)[r]; the root is kept in LDS (part)
-        for (int r = threadIdx.x; r < K; r += kTreeThreads) {
-            const int b = refl_bits(r);
-            double acc = 0.0;
-#pragma unroll
-            for (int c = 0; c < 8; ++c) acc += refl_sign(c, b) * xs[c * K + r];
-            if (lev > 0) {
-                mult[(size_t)(g.lev_off[lev] + box) * g.Kp + r] = (T)acc;
-                if constexpr (sizeof(T) == 4)
-                    if (msplit_all)
-                        store_split(msplit_all + (size_t)rp * (g.nbox + 1) * 2 * split_kp, split_kp,
-                                    g.lev_off[lev] + box, r, (float)acc);
-            }
-            else {
-                root_m_all[(size_t)rp * K + r] = acc;
-                part[kTreeThreads * 8 - kKMax + r] = acc;
-            }
-        }
-        if (lev > 0 && g.periodic && threadIdx.x == 0) {
-            box_part[2 * (g.lev_off[lev] + box)] = s2;
-            box_part[2 * (g.lev_off[lev] + box) + 1] = qs;
-        }
-        if (lev == lev_stop) break;
-        // hand over to the parent: release this block's stores device-wide,
-        // count the sibling in, and continue only as the eighth
-        __threadfence();
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            const uint32_t old = __hip_atomic_fetch_add(&cnt[g.lev_off[lev - 1] + (box >> 3)], 1u,
-                                                         __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-            go_on = (old & 7u) == 7u;
-        }
-        __syncthreads();
-        if (!go_on) return;
-        __threadfence();
-        lev -= 1;
-        box >>= 3;
+__device__ __forceinline__ void gather_children(const Geo& g, int clev, int64_t first, const T* mult,
+                                                const double* leaf_part, const double* box_part,
+                                                double* xs, double* ps) {
+    const int K = g.K;
+    const T* src = mult + (size_t)(g.lev_off[clev] + first) * g.Kp;
+    for (int i = threadIdx.x; i < 8 * K; i += kTreeThreads) {
+        const int c = i / K, k = i - c * K;
+        xs[i] = refl_sign(c, refl_bits(k)) * (double)src[(size_t)c * g.Kp + k];
     }
-    if (lev != 0 || !g.periodic) return;
-    // periodic root: the lattice operator on mu~_0 (FP64)
+    if (g.periodic && threadIdx.x < 16) {
+        const int c = threadIdx.x >> 1, w = threadIdx.x & 1;
+        ps[threadIdx.x] = clev == g.depth ? leaf_part[2 * (first + c) + w]
+                                          : box_part[2 * (g.lev_off[clev] + first + c) + w];
+    }
+}
+
+// parent[r] = sum_c s_c(r) (A_0 S_c mu_c)[r] from the products in ys.
+__device__ __forceinline__ double combine_octants(const double* ys, int K, int r) {
+    const int b = refl_bits(r);
+    double acc = 0.0;
+#pragma unroll
+    for (int c = 0; c < 8; ++c) acc += refl_sign(c, b) * ys[c * K + r];
+    return acc;
+}
+
+// M2M into the boxes of level lev (>= 2, or >= the coarsest interacting level
+// of an open system) from level lev + 1: one block per parent.  Stores the
+// parent in T (and its bf16 split when the M2L wants one) and, for periodic
+// systems, its FP64 partial sums.
+template <typename T>
+__global__ __launch_bounds__(kTreeThreads) void k_m2m(Geo g, int lev, T* __restrict__ mult_all,
+                                                      const T* __restrict__ op0,
+                                                      const double* __restrict__ leaf_part_all,
+                                                      double* __restrict__ box_part_all,
+                                                      uint16_t* __restrict__ msplit_all, int split_kp) {
+    __shared__ double xs[8 * kKMax], part[8 * kTreeThreads], ps[16];
+    TriPart<T, kTriLower> tp;
+    tp.load(g.K, op0);
+    const int rp = blockIdx.y, K = g.K, box = blockIdx.x;
+    T* mult = mult_all + (size_t)rp * g.nbox * g.Kp;
+    double* box_part = box_part_all + (size_t)rp * g.nbox * 2;
+    gather_children<T>(g, lev + 1, 8 * (int64_t)box, mult, leaf_part_all + (size_t)rp * g.nleaf * 2,
+                       box_part, xs, ps);
     __syncthreads();
-    for (int k = threadIdx.x; k < K; k += kTreeThreads) xs[k] = part[kTreeThreads * 8 - kKMax + k];
-    __syncthreads();
-    tri_matvec<double, 1, kTriFull>(K, latT, xs, part, xs);
-    for (int r = threadIdx.x; r < K; r += kTreeThreads)
-        root_l_all[(size_t)rp * K + r] = xs[r] + (r == 0 ? 2.0 * kPi / 3.0 * s2 : 0.0);
-    if (threadIdx.x == 0) dom_all[8 * rp + 4] = qs;
+    tri_matvec<T, 8, kTriLower>(tp, K, op0, xs, part, xs);
+    const int64_t gb = g.lev_off[lev] + box;
+    for (int r = threadIdx.x; r < K; r += kTreeThreads) {
+        const double v = combine_octants(xs, K, r);
+        mult[(size_t)gb * g.Kp + r] = (T)v;
+        if constexpr (sizeof(T) == 4)
+            if (msplit_all)
+                store_split(msplit_all + (size_t)rp * (g.nbox + 1) * 2 * split_kp, split_kp, gb, r, (float)v);
+    }
+    if (g.periodic && threadIdx.x < 2) {
+        double v = 0.0;
+        for (int c = 0; c < 8; ++c) v += ps[2 * c + threadIdx.x];
+        box_part[2 * gb + threadIdx.x] = v;
+    }
 }
 
 // Downward pass in one launch: one block per box b of level depth - 1 forms
-// lambda~ of its ancestors from level l0 down (L2L of the parent's total
-// plus the box's own M2L sum, in FP64, the periodic root from the lattice
-// operator) and adds the L2L of lambda~_b into its 8 leaves.  Ancestors shared
-// by several blocks are recomputed by each; only the leaf expansions are
-// stored.  root_l is read when l0 == 0 (periodic), else level l0 starts from
+// lambda~ of its ancestors from level l0 down (L2L of the parent's total plus
+// the box's own M2L sum, in FP64) and adds the L2L of lambda~_b into its 8
+// leaves.  Periodic systems (l0 = 0) start from the root: every block forms
+// mu~_0 by M2M from the 8 level-1 multipoles and lambda~_0 = Lat mu~_0 +
+// (2 pi / 3) sum q |s/L|^2 e_0 itself (block 0 also stores mu~_0, lambda~_0 and
+// dom[4] = Q).  Ancestors shared by several blocks are recomputed by each;
+// only the leaf expansions are stored.  Open systems start at level l0 from
 // its M2L sum alone.
 template <typename T>
-__global__ __launch_bounds__(kTreeThreads) void k_downward(Geo g, int l0, T* __restrict__ loc_all,
-                                                           const T* __restrict__ op0,
-                                                           const double* __restrict__ root_l_all) {
+__global__ __launch_bounds__(kTreeThreads) void k_downward(
+    Geo g, int l0, T* __restrict__ loc_all, const T* __restrict__ l2l0, const T* __restrict__ mult_all,
+    const T* __restrict__ m2m0, const double* __restrict__ leaf_part_all,
+    const double* __restrict__ box_part_all, const double* __restrict__ latT,
+    double* __restrict__ root_m_all, double* __restrict__ root_l_all, double* __restrict__ dom_all) {
     __shared__ double xs[8 * kKMax], part[8 * kTreeThreads];
-    __shared__ double v[kKMax];
+    __shared__ double v[kKMax], ps[16];
     __shared__ T anc[kDMax * kKMax];
+    TriPart<T, kTriUpper> tp;
+    tp.load(g.K, l2l0);
     const int rp = blockIdx.y, K = g.K, D = g.depth;
     T* loc = loc_all + (size_t)rp * g.nbox * g.Kp;
     const int b = blockIdx.x;
@@ -690,17 +708,46 @@ __global__ __launch_bounds__(kTreeThreads) void k_downward(Geo g, int l0, T* __r
         const int li = i / K, k = i - li * K, lev = la + li;
         anc[i] = loc[(size_t)(g.lev_off[lev] + (b >> (3 * (D - 1 - lev)))) * g.Kp + k];
     }
-    for (int k = threadIdx.x; k < K; k += kTreeThreads)
-        if (g.periodic) v[k] = root_l_all[(size_t)rp * K + k];
-    __syncthreads();
-    if (!g.periodic)
+    if (g.periodic) {
+        TriPart<T, kTriLower> tm;
+        tm.load(K, m2m0);
+        TriPart<double, kTriFull> tl;
+        tl.load(K, latT);
+        gather_children<T>(g, 1, 0, mult_all + (size_t)rp * g.nbox * g.Kp,
+                           leaf_part_all + (size_t)rp * g.nleaf * 2, box_part_all + (size_t)rp * g.nbox * 2,
+                           xs, ps);
+        __syncthreads();
+        tri_matvec<T, 8, kTriLower>(tm, K, m2m0, xs, part, xs);
+        for (int r = threadIdx.x; r < K; r += kTreeThreads) v[r] = combine_octants(xs, K, r);
+        __syncthreads();
+        for (int k = threadIdx.x; k < K; k += kTreeThreads) xs[k] = v[k];
+        __syncthreads();
+        tri_matvec<double, 1, kTriFull>(tl, K, latT, xs, part, xs);
+        double s2 = 0.0, qs = 0.0;
+        for (int c = 0; c < 8; ++c) {
+            s2 += ps[2 * c];
+            qs += ps[2 * c + 1];
+        }
+        const bool first = b == 0;
+        for (int r = threadIdx.x; r < K; r += kTreeThreads) {
+            const double lr = xs[r] + (r == 0 ? 2.0 * kPi / 3.0 * s2 : 0.0);
+            if (first) {
+                root_m_all[(size_t)rp * K + r] = v[r];
+                root_l_all[(size_t)rp * K + r] = lr;
+            }
+            v[r] = lr;
+        }
+        if (first && threadIdx.x == 0) dom_all[8 * rp + 4] = qs;
+    } else {
+        __syncthreads();
         for (int k = threadIdx.x; k < K; k += kTreeThreads) v[k] = (double)anc[k];
+    }
     __syncthreads();
     for (int lev = l0 + 1; lev < D; ++lev) {
         const int a = b >> (3 * (D - 1 - lev)), c = a & 7;
         for (int k = threadIdx.x; k < K; k += kTreeThreads) xs[k] = refl_sign(c, refl_bits(k)) * v[k];
         __syncthreads();
-        tri_matvec<T, 1, kTriUpper>(K, op0, xs, part, xs);
+        tri_matvec<T, 1, kTriUpper>(tp, K, l2l0, xs, part, xs);
         for (int r = threadIdx.x; r < K; r += kTreeThreads)
             v[r] = (double)anc[(lev - la) * K + r] + refl_sign(c, refl_bits(r)) * xs[r];
         __syncthreads();
@@ -710,7 +757,7 @@ __global__ __launch_bounds__(kTreeThreads) void k_downward(Geo g, int l0, T* __r
         xs[i] = refl_sign(c, refl_bits(k)) * v[k];
     }
     __syncthreads();
-    tri_matvec<T, 8, kTriUpper>(K, op0, xs, part, xs);
+    tri_matvec<T, 8, kTriUpper>(tp, K, l2l0, xs, part, xs);
     T* dst = loc + (size_t)(g.lev_off[D] + 8 * (size_t)b) * g.Kp;
     for (int i = threadIdx.x; i < 8 * K; i += kTreeThreads) {
         const int c = i / K, r = i - c * K;
@@ -1231,8 +1278,18 @@ __global__ __launch_bounds__(256) void k_m2l_reduce(Geo g, M2LGeom mg, const T* 
     for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < tot;
          e += (int64_t)gridDim.x * blockDim.x) {
         if ((int)(e % g.Kp) >= g.K) continue;
-        T s = T(0);
-        for (int c = 0; c < mg.nchunk; ++c) s += part[(size_t)c * tot + e];
+        // four independent partial sums keep 16 loads in flight; fixed order
+        T s0 = T(0), s1 = T(0), s2 = T(0), s3 = T(0);
+        int c = 0;
+#pragma unroll 4
+        for (; c + 4 <= mg.nchunk; c += 4) {
+            s0 += part[(size_t)c * tot + e];
+            s1 += part[(size_t)(c + 1) * tot + e];
+            s2 += part[(size_t)(c + 2) * tot + e];
+            s3 += part[(size_t)(c + 3) * tot + e];
+        }
+        for (; c < mg.nchunk; ++c) s0 += part[(size_t)c * tot + e];
+        const T s = (s0 + s1) + (s2 + s3);
         loc[(size_t)g.lev_off[g.lmin] * g.Kp + e] = s;
     }
 }
@@ -1426,19 +1483,30 @@ __global__ __launch_bounds__(64 * kNW) void k_near_far(
             const int sl = (cnt + wpc - 1) / wpc;
             const int jb = slice * sl;
             const int je = min(jb + sl, cnt);
+            // Only the target's own leaf (neighbour 13, zero offset) can hold a
+            // source at distance 0 (the target itself, or a duplicate position):
+            // the r > 0 guard runs on that range alone.
+            const int own_b = nb_pre[13] - s0, own_e = nb_pre[14] - s0;
+            auto sweep = [&](int j0, int j1, auto guard) {
 #pragma unroll 4
-            for (int j = jb; j < je; ++j) {
-                const vec4_t<T> s = tile[j];
-                const T dx = me.x - s.x, dy = me.y - s.y, dz = me.z - s.z;
-                const T r2 = dx * dx + dy * dy + dz * dz;
-                const T ri = r2 > T(0) ? inv_sqrt<T>(r2) : T(0);
-                const T qr = s.w * ri;
-                const T qr3 = qr * (ri * ri);
-                ph += qr;
-                fx += qr3 * dx;
-                fy += qr3 * dy;
-                fz += qr3 * dz;
-            }
+                for (int j = j0; j < j1; ++j) {
+                    const vec4_t<T> s = tile[j];
+                    const T dx = me.x - s.x, dy = me.y - s.y, dz = me.z - s.z;
+                    const T r2 = dx * dx + dy * dy + dz * dz;
+                    T ri;
+                    if constexpr (decltype(guard)::value) ri = r2 > T(0) ? inv_sqrt<T>(r2) : T(0);
+                    else ri = inv_sqrt<T>(r2);
+                    const T qr = s.w * ri;
+                    const T qr3 = qr * (ri * ri);
+                    ph += qr;
+                    fx += qr3 * dx;
+                    fy += qr3 * dy;
+                    fz += qr3 * dz;
+                }
+            };
+            sweep(jb, min(je, own_b), std::false_type{});
+            sweep(max(jb, own_b), min(je, own_e), std::true_type{});
+            sweep(max(jb, own_e), je, std::false_type{});
         }
         if (far && tv) {
             // far field, orders m = slice, slice + wpc, ...
