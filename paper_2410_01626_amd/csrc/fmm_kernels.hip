@@ -1432,18 +1432,45 @@ __global__ __launch_bounds__(64 * kNW) void k_near_far(
     const int total = nb_pre[27];
     const T ih = (T)(1.0 / h);
     double esum = 0.0;
-    // Targets are processed in rounds of up to kNW chunks of 64; within a round
-    // the wavefronts are split evenly between the chunks (wpc wavefronts per
-    // chunk, a power of two), each taking a contiguous slice of every source
-    // tile, so no wavefront idles on an empty chunk.
+    // Targets are processed in rounds of up to kNW chunks of 64.  A chunk of
+    // tc targets runs on lane groups of gsz = pow2ceil(tc) lanes: the 64 / gsz
+    // groups of a wavefront take interleaved sources and are added by
+    // shuffles at the end, so a short chunk does not leave lanes idle.  The
+    // kNW wavefronts are shared between the chunks in proportion to their
+    // work (sources x gsz); each wavefront of a chunk takes a contiguous slice
+    // of every source tile.
+    __shared__ int w_first[kNW + 1];
     for (int t0 = 0; t0 < tn; t0 += 64 * kNW) {
         const int nch = min(kNW, (tn - t0 + 63) / 64);
-        int wpc = kNW;
-        while (wpc * nch > kNW) wpc >>= 1;
-        const int chunk = wave / wpc, slice = wave % wpc;
-        const bool live = chunk < nch;
-        const int tj = t0 + 64 * chunk + lane;
-        const bool tv = live && tj < tn;
+        if (tid == 0) {
+            int w[kNW];
+            int gs[kNW];
+            for (int c = 0; c < nch; ++c) {
+                const int tc = min(64, tn - t0 - 64 * c);
+                int gz = 1;
+                while (gz < tc) gz <<= 1;
+                gs[c] = gz;
+                w[c] = 1;
+            }
+            for (int k = nch; k < kNW; ++k) {
+                int best = 0;
+                for (int c = 1; c < nch; ++c)  // largest gs / w, ties to the lower chunk
+                    if (gs[c] * w[best] > gs[best] * w[c]) best = c;
+                ++w[best];
+            }
+            w_first[0] = 0;
+            for (int c = 0; c < nch; ++c) w_first[c + 1] = w_first[c] + w[c];
+        }
+        __syncthreads();
+        int chunk = 0;
+        while (chunk + 1 < nch && w_first[chunk + 1] <= wave) ++chunk;
+        const int wpc = w_first[chunk + 1] - w_first[chunk], slice = wave - w_first[chunk];
+        const int tc = min(64, tn - t0 - 64 * chunk);
+        int gsz = 1;
+        while (gsz < tc) gsz <<= 1;
+        const int ngrp = 64 / gsz, grp = lane / gsz, tl = lane & (gsz - 1);
+        const int tj = t0 + 64 * chunk + tl;
+        const bool tv = tl < tc;
         vec4_t<T> me;
         if (tv) me = pos[tb + tj];
         else { me.x = me.y = me.z = me.w = T(0); }
@@ -1479,17 +1506,18 @@ __global__ __launch_bounds__(64 * kNW) void k_near_far(
                 }
             }
             __syncthreads();
-            if (!live) continue;
             const int sl = (cnt + wpc - 1) / wpc;
             const int jb = slice * sl;
             const int je = min(jb + sl, cnt);
             // Only the target's own leaf (neighbour 13, zero offset) can hold a
             // source at distance 0 (the target itself, or a duplicate position):
-            // the r > 0 guard runs on that range alone.
+            // the r > 0 guard runs on that range alone.  Lane group grp takes
+            // the sources jb + grp, jb + grp + ngrp, ...
             const int own_b = nb_pre[13] - s0, own_e = nb_pre[14] - s0;
             auto sweep = [&](int j0, int j1, auto guard) {
+                const int first = j0 + ((grp - (j0 - jb)) & (ngrp - 1));
 #pragma unroll 4
-                for (int j = j0; j < j1; ++j) {
+                for (int j = first; j < j1; j += ngrp) {
                     const vec4_t<T> s = tile[j];
                     const T dx = me.x - s.x, dy = me.y - s.y, dz = me.z - s.z;
                     const T r2 = dx * dx + dy * dy + dz * dz;
@@ -1509,10 +1537,10 @@ __global__ __launch_bounds__(64 * kNW) void k_near_far(
             sweep(max(jb, own_e), je, std::false_type{});
         }
         if (far && tv) {
-            // far field, orders m = slice, slice + wpc, ...
+            // far field, orders m = slice + wpc grp, stepping by wpc ngrp
             T fp = T(0), gx = T(0), gy = T(0), gz = T(0);
             const int Kg = g.Kg;
-            for_rho_orders<T>(g.p, slice, wpc, me.x * ih, me.y * ih, me.z * ih,
+            for_rho_orders<T>(g.p, slice + wpc * grp, wpc * ngrp, me.x * ih, me.y * ih, me.z * ih,
                               [&](int kc, bool has_s, T re, T im) {
                                   fp += lam[kc] * re;
                                   if (has_s) fp += lam[kc + 1] * im;
@@ -1532,19 +1560,28 @@ __global__ __launch_bounds__(64 * kNW) void k_near_far(
             fy -= gy * ih * ih;
             fz -= gz * ih * ih;
         }
-        part[wave][0][lane] = ph;
-        part[wave][1][lane] = fx;
-        part[wave][2][lane] = fy;
-        part[wave][3][lane] = fz;
+        // add the lane groups (fixed butterfly order)
+        for (int off = gsz; off < 64; off <<= 1) {
+            ph += __shfl_xor(ph, off, 64);
+            fx += __shfl_xor(fx, off, 64);
+            fy += __shfl_xor(fy, off, 64);
+            fz += __shfl_xor(fz, off, 64);
+        }
+        if (grp == 0) {
+            part[wave][0][tl] = ph;
+            part[wave][1][tl] = fx;
+            part[wave][2][tl] = fy;
+            part[wave][3][tl] = fz;
+        }
         __syncthreads();
         // the first wavefront of each chunk adds the chunk's slices in order
-        if (live && slice == 0 && tj < tn) {
+        if (slice == 0 && grp == 0 && tv) {
             T p = T(0), ex = T(0), ey = T(0), ez = T(0);
             for (int w = wave; w < wave + wpc; ++w) {
-                p += part[w][0][lane];
-                ex += part[w][1][lane];
-                ey += part[w][2][lane];
-                ez += part[w][3][lane];
+                p += part[w][0][tl];
+                ex += part[w][1][tl];
+                ey += part[w][2][tl];
+                ez += part[w][3][tl];
             }
             if (g.periodic) {
                 // background: phi += (2 pi / 3) Q |t|^2 / V, field -= (4 pi / 3) Q t / V
@@ -1572,14 +1609,14 @@ __global__ __launch_bounds__(64 * kNW) void k_near_far(
             const int32_t st = site[i];
             if (st >= 0 && st < n_sites)
                 cphi[i] = g.coulomb_k * ((double)qB[i] - (double)qA[i]) * (double)p;
-        } else if (slice == 0 && live) {
+        } else if (slice == 0) {
             esum_part[wave][lane] = 0.0;
         }
         __syncthreads();
         // energy partial of this round, in target order
         if (wave == 0) {
             double v = 0.0;
-            for (int c = 0; c < nch; ++c) v += esum_part[c * wpc][lane];
+            for (int c = 0; c < nch; ++c) v += esum_part[w_first[c]][lane];
             esum += v;
         }
     }
