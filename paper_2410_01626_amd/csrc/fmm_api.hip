@@ -281,10 +281,17 @@ fmm_status enqueue_eval(fmm_plan_t P, const std::vector<fmmk::RepDesc>& rd, cons
     k_charge_key<T><<<dim3(ab, R), 256, 0, st>>>(g, reps, x, qA, qB, site, lam, P->dom, P->key,
                                                  P->rank, P->leaf_count, P->site_count,
                                                  P->site_rank, P->status);
-    k_scan2<<<R + 1, 1024, 0, st>>>(reps, R, P->leaf_count, P->leaf_start, g.nleaf,
-                                    P->site_count, P->site_start, S_tot);
-    k_scatter<<<dim3(ab, R), 256, 0, st>>>(g, reps, P->key, P->rank, P->leaf_start, P->perm, site,
-                                           P->site_rank, P->site_start, P->site_members);
+    if (g.nleaf <= kScanFuseCap && S_tot <= kScanFuseCap) {
+        k_scan_scatter<<<dim3(ab, R), 256, 0, st>>>(g, reps, P->key, P->rank, P->leaf_count,
+                                                    P->leaf_start, P->perm, site, P->site_rank,
+                                                    P->site_count, P->site_start, (int)S_tot,
+                                                    P->site_members);
+    } else {
+        k_scan2<<<R + 1, 1024, 0, st>>>(reps, R, P->leaf_count, P->leaf_start, g.nleaf,
+                                        P->site_count, P->site_start, S_tot);
+        k_scatter<<<dim3(ab, R), 256, 0, st>>>(g, reps, P->key, P->rank, P->leaf_start, P->perm,
+                                               site, P->site_rank, P->site_start, P->site_members);
+    }
     using V4 = vec4_t<T>;
     V4* pos = (V4*)P->pos;
     T* mult = (T*)P->mult;

@@ -59,16 +59,34 @@ struct RhoCoef {
 };
 __constant__ RhoCoef c_rho;
 
+// The recurrence coefficients in the working type, staged in LDS once per
+// block: the recurrences read them at independent addresses, so the reads
+// pipeline (scalar constant loads would each wait in turn).
+template <typename T>
+struct RhoLds {
+    T f[kPMax + 1];
+    T a[(kPMax + 1) * (kPMax + 1)];
+    T b[(kPMax + 1) * (kPMax + 1)];
+};
+template <typename T>
+__device__ __forceinline__ void load_rho_lds(RhoLds<T>& rc, int p) {
+    for (int i = threadIdx.x; i < (p + 1) * (kPMax + 1); i += blockDim.x) {
+        rc.a[i] = (T)c_rho.a[i];
+        rc.b[i] = (T)c_rho.b[i];
+    }
+    for (int i = threadIdx.x; i <= p; i += blockDim.x) rc.f[i] = (T)c_rho.f[i];
+}
+
 // Visit every coefficient of rho(u) in the order m = 0..p, l = m..p, calling
 // fn(kc, has_sin, re, im): kc is the index of the cosine (real) part; the sine
 // part, when has_sin (m > 0), sits at kc + 1.
 template <typename T, typename Fn>
-__device__ __forceinline__ void for_each_rho(int p, T x, T y, T z, Fn&& fn) {
+__device__ __forceinline__ void for_each_rho(int p, const RhoLds<T>& rc, T x, T y, T z, Fn&& fn) {
     const T r2 = x * x + y * y + z * z;
     T cre = T(1), cim = T(0);
     for (int m = 0; m <= p; ++m) {
         if (m > 0) {
-            const T fm = (T)c_rho.f[m];
+            const T fm = rc.f[m];
             const T nre = fm * (x * cre - y * cim);
             const T nim = fm * (x * cim + y * cre);
             cre = nre;
@@ -78,12 +96,12 @@ __device__ __forceinline__ void for_each_rho(int p, T x, T y, T z, Fn&& fn) {
         fn(m * m + k0, m > 0, cre, cim);
         if (m + 1 > p) continue;
         T p0re = cre, p0im = cim;
-        T p1re = (T)c_rho.a[(m + 1) * (kPMax + 1) + m] * z * cre;
-        T p1im = (T)c_rho.a[(m + 1) * (kPMax + 1) + m] * z * cim;
+        T p1re = rc.a[(m + 1) * (kPMax + 1) + m] * z * cre;
+        T p1im = rc.a[(m + 1) * (kPMax + 1) + m] * z * cim;
         fn((m + 1) * (m + 1) + k0, m > 0, p1re, p1im);
         for (int l = m + 2; l <= p; ++l) {
-            const T al = (T)c_rho.a[l * (kPMax + 1) + m];
-            const T bl = (T)c_rho.b[l * (kPMax + 1) + m];
+            const T al = rc.a[l * (kPMax + 1) + m];
+            const T bl = rc.b[l * (kPMax + 1) + m];
             const T nre = al * z * p1re - bl * r2 * p0re;
             const T nim = al * z * p1im - bl * r2 * p0im;
             p0re = p1re;
@@ -209,29 +227,36 @@ __global__ void k_bbox_final(const double* __restrict__ part, int nblk, double* 
 
 // ------------------------------------------------------------------ binning
 
-// Wave-aggregated counter increment: the lanes of a wavefront that hold the
+// Wave-aggregated counter increments: the lanes of a wavefront that hold the
 // same key share one atomic add on counter[key] and split the returned range
-// in lane order.  Returns the lane's slot (unique per key); inactive lanes get
-// -1.  Atoms arrive grouped by molecule, so a wavefront touches few distinct
-// leaves and one atomic replaces many same-address ones.
-__device__ __forceinline__ int32_t agg_increment(int32_t* counter, uint32_t key, bool active) {
+// in lane order, so every lane gets a slot unique per key.  agg_plan finds
+// the key groups (leader lane, offset inside the group, group size on the
+// leader); the leaders then issue their adds as one instruction (distinct
+// addresses, one round trip) and agg_slot spreads the result.  Atoms arrive
+// grouped by molecule, so a wavefront touches few distinct leaves.
+struct AggPlan {
+    int leader, off, count;  // off < 0: lane not taking part
+};
+__device__ __forceinline__ AggPlan agg_plan(uint32_t key, bool active) {
     const int lane = (int)__lane_id();
     uint64_t todo = __ballot(active);
-    int32_t got = 0;
-    int my_leader = 0, my_off = -1;
+    AggPlan pl{0, -1, 0};
     while (todo) {
         const int leader = __ffsll((unsigned long long)todo) - 1;
         const uint32_t lk = (uint32_t)__shfl((int)key, leader, 64);
         const uint64_t peers = __ballot(active && key == lk) & todo;
-        if (lane == leader) got = atomicAdd(&counter[lk], __popcll(peers));
+        if (lane == leader) pl.count = __popcll(peers);
         if ((peers >> lane) & 1) {
-            my_leader = leader;
-            my_off = __popcll(peers & ((1ull << lane) - 1));
+            pl.leader = leader;
+            pl.off = __popcll(peers & ((1ull << lane) - 1));
         }
         todo &= ~peers;
     }
-    const int32_t base = __shfl(got, my_leader, 64);
-    return my_off < 0 ? -1 : base + my_off;
+    return pl;
+}
+__device__ __forceinline__ int32_t agg_slot(const AggPlan& pl, int32_t got) {
+    const int32_t base = __shfl(got, pl.leader, 64);
+    return pl.off < 0 ? -1 : base + pl.off;
 }
 
 // Leaf key (Morton code of the leaf cell) of every atom, its rank inside the
@@ -257,8 +282,13 @@ __global__ __launch_bounds__(256) void k_charge_key(
         dom[0] = dom[1] = dom[2] = 0.0;
         dom[3] = box;
     }
+    if (rd.n == 0) return;
+    // every input of the lane is loaded up front (idle lanes read the
+    // replica's last atom), so the loads are in flight together
     const bool live = il < rd.n;
-    const int64_t i = rd.a0 + (live ? il : 0);
+    const int64_t i = rd.a0 + (live ? il : rd.n - 1);
+    const double xv[3] = {(double)x[3 * i], (double)x[3 * i + 1], (double)x[3 * i + 2]};
+    const int32_t s_in = site[i];
     const int64_t n_sites = rd.S;
     double lo[3], edge;
     if (g.periodic) {
@@ -274,21 +304,26 @@ __global__ __launch_bounds__(256) void k_charge_key(
     int c[3];
     bool bad = false;
     for (int a = 0; a < 3; ++a) {
-        double v = live ? (double)x[3 * i + a] : 0.0;
-        bad |= !finite_d(v);
+        double v = xv[a];
+        bad |= live && !finite_d(v);
         if (g.periodic) v -= edge * floor(v / edge);
         int ci = (int)floor((v - lo[a]) / h);
         c[a] = ci < 0 ? 0 : (ci >= g.nb ? g.nb - 1 : ci);
     }
     const uint32_t k = morton(c[0], c[1], c[2]);
-    int32_t s = live ? site[i] : -1;
+    int32_t s = live ? s_in : -1;
     if (s < -1 || s >= n_sites) {
         if (g.check) atomicOr(&status[0], kStatusSite);
         s = -1;
     }
-    // every lane of the wavefront takes part in the aggregated increments
-    const int32_t lr = agg_increment(leaf_count, k, live);
-    const int32_t sr = agg_increment(site_count + rd.s0, (uint32_t)max(s, 0), live && s >= 0);
+    // every lane of the wavefront takes part in the aggregated increments;
+    // both adds are in flight together
+    const uint32_t sk = (uint32_t)max(s, 0);
+    const AggPlan pl = agg_plan(k, live), ps = agg_plan(sk, live && s >= 0);
+    int32_t gl = 0, gs = 0;
+    if (pl.count > 0) gl = atomicAdd(&leaf_count[k], pl.count);
+    if (ps.count > 0) gs = atomicAdd(&site_count[rd.s0 + sk], ps.count);
+    const int32_t lr = agg_slot(pl, gl), sr = agg_slot(ps, gs);
     if (!live) return;
     key[i] = (int32_t)k;
     rank[i] = lr;
@@ -352,6 +387,70 @@ __global__ __launch_bounds__(256) void k_scatter(Geo g, const RepDesc* __restric
     perm[leaf_start[key[i]] + rank[i]] = (int32_t)i;
     const int32_t s = site[i];
     if (s >= 0 && s < rd.S) site_members[site_start[rd.s0 + s] + site_rank[i]] = (int32_t)i;
+}
+
+// Exclusive scan of n <= kScanFuseCap global counts into LDS (out[0..n],
+// offset by base) by a 256-thread block; each thread's 16 counts are loaded
+// together.  tmp: 256 ints of LDS.
+__device__ void block_scan_256(const int32_t* __restrict__ cnt, int n, int32_t base, int32_t* out,
+                               int32_t* tmp) {
+    const int t = threadIdx.x;
+    constexpr int E = kScanFuseCap / 256;
+    const int chunk = (n + 255) / 256;
+    const int b = min(n, t * chunk), e = min(n, b + chunk);
+    int32_t v[E];
+    int32_t sum = 0;
+#pragma unroll
+    for (int j = 0; j < E; ++j) {
+        v[j] = (b + j < e) ? cnt[b + j] : 0;
+        sum += v[j];
+    }
+    tmp[t] = sum;
+    __syncthreads();
+    for (int off = 1; off < 256; off <<= 1) {
+        const int32_t u = t >= off ? tmp[t - off] : 0;
+        __syncthreads();
+        tmp[t] += u;
+        __syncthreads();
+    }
+    int32_t run = base + tmp[t] - sum;
+#pragma unroll
+    for (int j = 0; j < E; ++j)
+        if (b + j < e) {
+            out[b + j] = run;
+            run += v[j];
+        }
+    if (t == 255) out[n] = base + tmp[255];
+    __syncthreads();
+}
+
+// Counting-sort placement with the scans fused in (nleaf and the site count
+// at most kScanFuseCap): every block scans its replica's leaf counts and all
+// site counts in LDS, block 0 of each replica publishes leaf_start (and block
+// (0, 0) site_start), then atoms are placed at start + rank.
+__global__ __launch_bounds__(256) void k_scan_scatter(
+    Geo g, const RepDesc* __restrict__ reps, const int32_t* __restrict__ key,
+    const int32_t* __restrict__ rank, const int32_t* __restrict__ leaf_count_all,
+    int32_t* __restrict__ leaf_start_all, int32_t* __restrict__ perm, const int32_t* __restrict__ site,
+    const int32_t* __restrict__ site_rank, const int32_t* __restrict__ site_count,
+    int32_t* __restrict__ site_start, int S_tot, int32_t* __restrict__ site_members) {
+    __shared__ int32_t ls[kScanFuseCap + 1], ss[kScanFuseCap + 1], tmp[256];
+    const int r = blockIdx.y;
+    const RepDesc rd = reps[r];
+    block_scan_256(leaf_count_all + (size_t)r * g.nleaf, (int)g.nleaf, (int32_t)rd.a0, ls, tmp);
+    if (S_tot > 0) block_scan_256(site_count, S_tot, 0, ss, tmp);
+    if (blockIdx.x == 0) {
+        int32_t* leaf_start = leaf_start_all + (size_t)r * (g.nleaf + 1);
+        for (int i = threadIdx.x; i <= g.nleaf; i += 256) leaf_start[i] = ls[i];
+        if (r == 0)
+            for (int i = threadIdx.x; i <= S_tot; i += 256) site_start[i] = S_tot > 0 ? ss[i] : 0;
+    }
+    const int64_t il = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (il >= rd.n) return;
+    const int64_t i = rd.a0 + il;
+    perm[ls[key[i]] + rank[i]] = (int32_t)i;
+    const int32_t s = site[i];
+    if (s >= 0 && s < rd.S) site_members[ss[rd.s0 + s] + site_rank[i]] = (int32_t)i;
 }
 
 // Bitonic sort of up to kSortCap ints in LDS (ascending), block-wide.
@@ -444,6 +543,9 @@ __global__ __launch_bounds__(64) void k_p2m(Geo g, const vec4_t<T>* __restrict__
                                             double* __restrict__ leaf_part_all,
                                             uint16_t* __restrict__ msplit_all, int split_kp) {
     extern __shared__ __align__(16) unsigned char p2m_lds[];
+    __shared__ RhoLds<T> rho;
+    load_rho_lds<T>(rho, g.p);
+    __syncthreads();
     const int32_t* leaf_start = leaf_start_all + (size_t)blockIdx.y * (g.nleaf + 1);
     const double* dom = dom_all + 8 * blockIdx.y;
     T* mult = mult_all + (size_t)blockIdx.y * g.nbox * g.Kp;
@@ -476,7 +578,7 @@ __global__ __launch_bounds__(64) void k_p2m(Geo g, const vec4_t<T>* __restrict__
             qs += (double)q;
         }
         T* row = buf + lane * S;
-        for_each_rho<T>(g.p, a.x * ih, a.y * ih, a.z * ih, [&](int kc, bool hs, T re, T im) {
+        for_each_rho<T>(g.p, rho, a.x * ih, a.y * ih, a.z * ih, [&](int kc, bool hs, T re, T im) {
             row[kc] = q * re;
             if (hs) row[kc + 1] = q * im;
         });
@@ -616,23 +718,42 @@ __device__ void tri_matvec(const TriPart<TO, kShape>& tp, int K, const TO* __res
     __syncthreads();
 }
 
+// First box of level l in the level-major box order: (8^l - 1) / 7.
+__device__ __forceinline__ int64_t lev_offset(int l) { return (((int64_t)1 << (3 * l)) - 1) / 7; }
+
+constexpr int kGatherPer = 8 * kKMax / kTreeThreads;  // child coefficients per thread
+
 // Signed children of one parent into xs[c][k] (FP64) and, for periodic
-// systems, the sum of their FP64 partials (q |t/L|^2, q) into ps2.
+// systems, their FP64 partials (q |t/L|^2, q) into ps[2 c + w].  All loads are
+// issued before any is used.
 template <typename T>
 __device__ __forceinline__ void gather_children(const Geo& g, int clev, int64_t first, const T* mult,
                                                 const double* leaf_part, const double* box_part,
                                                 double* xs, double* ps) {
     const int K = g.K;
-    const T* src = mult + (size_t)(g.lev_off[clev] + first) * g.Kp;
-    for (int i = threadIdx.x; i < 8 * K; i += kTreeThreads) {
+    const T* src = mult + (size_t)(lev_offset(clev) + first) * g.Kp;
+    T v[kGatherPer];
+#pragma unroll
+    for (int m = 0; m < kGatherPer; ++m) {
+        const int i = min((int)threadIdx.x + m * kTreeThreads, 8 * K - 1);
         const int c = i / K, k = i - c * K;
-        xs[i] = refl_sign(c, refl_bits(k)) * (double)src[(size_t)c * g.Kp + k];
+        v[m] = src[(size_t)c * g.Kp + k];
     }
+    double pv = 0.0;
     if (g.periodic && threadIdx.x < 16) {
         const int c = threadIdx.x >> 1, w = threadIdx.x & 1;
-        ps[threadIdx.x] = clev == g.depth ? leaf_part[2 * (first + c) + w]
-                                          : box_part[2 * (g.lev_off[clev] + first + c) + w];
+        pv = clev == g.depth ? leaf_part[2 * (first + c) + w]
+                             : box_part[2 * (lev_offset(clev) + first + c) + w];
     }
+#pragma unroll
+    for (int m = 0; m < kGatherPer; ++m) {
+        const int i = threadIdx.x + m * kTreeThreads;
+        if (i < 8 * K) {
+            const int c = i / K, k = i - c * K;
+            xs[i] = refl_sign(c, refl_bits(k)) * (double)v[m];
+        }
+    }
+    if (g.periodic && threadIdx.x < 16) ps[threadIdx.x] = pv;
 }
 
 // parent[r] = sum_c s_c(r) (A_0 S_c mu_c)[r] from the products in ys.
@@ -702,11 +823,29 @@ __global__ __launch_bounds__(kTreeThreads) void k_downward(
     const int rp = blockIdx.y, K = g.K, D = g.depth;
     T* loc = loc_all + (size_t)rp * g.nbox * g.Kp;
     const int b = blockIdx.x;
-    // prefetch the M2L sums of the ancestors at levels l0 + 1 .. D - 1 (and l0 when open)
+    // prefetch, all loads in flight together: the M2L sums of the ancestors at
+    // levels la .. D - 1 and the 8 leaves' own expansions
     const int la = g.periodic ? l0 + 1 : l0;
-    for (int i = threadIdx.x; i < (D - la) * K; i += kTreeThreads) {
+    constexpr int kAncPer = (kDMax * kKMax + kTreeThreads - 1) / kTreeThreads;
+    const int nanc = (D - la) * K;
+    T av[kAncPer], lv[kGatherPer];
+#pragma unroll
+    for (int m = 0; m < kAncPer; ++m) {
+        const int i = min((int)threadIdx.x + m * kTreeThreads, max(nanc - 1, 0));
         const int li = i / K, k = i - li * K, lev = la + li;
-        anc[i] = loc[(size_t)(g.lev_off[lev] + (b >> (3 * (D - 1 - lev)))) * g.Kp + k];
+        av[m] = nanc > 0 ? loc[(size_t)(lev_offset(lev) + (b >> (3 * (D - 1 - lev)))) * g.Kp + k] : T(0);
+    }
+    T* dst = loc + (size_t)(lev_offset(D) + 8 * (size_t)b) * g.Kp;
+#pragma unroll
+    for (int m = 0; m < kGatherPer; ++m) {
+        const int i = min((int)threadIdx.x + m * kTreeThreads, 8 * K - 1);
+        const int c = i / K, r = i - c * K;
+        lv[m] = dst[(size_t)c * g.Kp + r];
+    }
+#pragma unroll
+    for (int m = 0; m < kAncPer; ++m) {
+        const int i = threadIdx.x + m * kTreeThreads;
+        if (i < nanc) anc[i] = av[m];
     }
     if (g.periodic) {
         TriPart<T, kTriLower> tm;
@@ -758,10 +897,13 @@ __global__ __launch_bounds__(kTreeThreads) void k_downward(
     }
     __syncthreads();
     tri_matvec<T, 8, kTriUpper>(tp, K, l2l0, xs, part, xs);
-    T* dst = loc + (size_t)(g.lev_off[D] + 8 * (size_t)b) * g.Kp;
-    for (int i = threadIdx.x; i < 8 * K; i += kTreeThreads) {
-        const int c = i / K, r = i - c * K;
-        dst[(size_t)c * g.Kp + r] = (T)((double)dst[(size_t)c * g.Kp + r] + refl_sign(c, refl_bits(r)) * xs[i]);
+#pragma unroll
+    for (int m = 0; m < kGatherPer; ++m) {
+        const int i = threadIdx.x + m * kTreeThreads;
+        if (i < 8 * K) {
+            const int c = i / K, r = i - c * K;
+            dst[(size_t)c * g.Kp + r] = (T)((double)lv[m] + refl_sign(c, refl_bits(r)) * xs[i]);
+        }
     }
 }
 
@@ -1308,12 +1450,13 @@ template <> __device__ __forceinline__ double inv_sqrt<double>(double v) { retur
 // diagonal Rh_m^m chain is still advanced for every m): lets several
 // wavefronts share one expansion evaluation.
 template <typename T, typename Fn>
-__device__ __forceinline__ void for_rho_orders(int p, int m0, int dm, T x, T y, T z, Fn&& fn) {
+__device__ __forceinline__ void for_rho_orders(int p, const RhoLds<T>& rc, int m0, int dm, T x, T y, T z,
+                                               Fn&& fn) {
     const T r2 = x * x + y * y + z * z;
     T cre = T(1), cim = T(0);
     for (int m = 0; m <= p; ++m) {
         if (m > 0) {
-            const T fm = (T)c_rho.f[m];
+            const T fm = rc.f[m];
             const T nre = fm * (x * cre - y * cim);
             const T nim = fm * (x * cim + y * cre);
             cre = nre;
@@ -1324,12 +1467,12 @@ __device__ __forceinline__ void for_rho_orders(int p, int m0, int dm, T x, T y, 
         fn(m * m + k0, m > 0, cre, cim);
         if (m + 1 > p) continue;
         T p0re = cre, p0im = cim;
-        T p1re = (T)c_rho.a[(m + 1) * (kPMax + 1) + m] * z * cre;
-        T p1im = (T)c_rho.a[(m + 1) * (kPMax + 1) + m] * z * cim;
+        T p1re = rc.a[(m + 1) * (kPMax + 1) + m] * z * cre;
+        T p1im = rc.a[(m + 1) * (kPMax + 1) + m] * z * cim;
         fn((m + 1) * (m + 1) + k0, m > 0, p1re, p1im);
         for (int l = m + 2; l <= p; ++l) {
-            const T al = (T)c_rho.a[l * (kPMax + 1) + m];
-            const T bl = (T)c_rho.b[l * (kPMax + 1) + m];
+            const T al = rc.a[l * (kPMax + 1) + m];
+            const T bl = rc.b[l * (kPMax + 1) + m];
             const T nre = al * z * p1re - bl * r2 * p0re;
             const T nim = al * z * p1im - bl * r2 * p0im;
             p0re = p1re;
@@ -1370,6 +1513,8 @@ __global__ __launch_bounds__(64 * kNW) void k_near_far(
     __shared__ T nb_off[27][3];
     __shared__ T lam[kKMax];
     __shared__ T gr[3][kKgMax];
+    __shared__ RhoLds<T> rho;
+    load_rho_lds<T>(rho, g.p);
     __shared__ T part[kNW][4][64];
     __shared__ double esum_part[kNW][64];
     const int leaf = blockIdx.x;
@@ -1540,7 +1685,7 @@ __global__ __launch_bounds__(64 * kNW) void k_near_far(
             // far field, orders m = slice + wpc grp, stepping by wpc ngrp
             T fp = T(0), gx = T(0), gy = T(0), gz = T(0);
             const int Kg = g.Kg;
-            for_rho_orders<T>(g.p, slice + wpc * grp, wpc * ngrp, me.x * ih, me.y * ih, me.z * ih,
+            for_rho_orders<T>(g.p, rho, slice + wpc * grp, wpc * ngrp, me.x * ih, me.y * ih, me.z * ih,
                               [&](int kc, bool has_s, T re, T im) {
                                   fp += lam[kc] * re;
                                   if (has_s) fp += lam[kc + 1] * im;
