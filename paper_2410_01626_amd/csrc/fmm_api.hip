@@ -34,6 +34,8 @@ struct fmm_plan_s {
     void *mult = nullptr, *loc = nullptr;
     double *root_m = nullptr, *root_l = nullptr;
     void *bankT = nullptr, *m2mT = nullptr, *l2lT = nullptr, *gcoef = nullptr;
+    void *m2m_seg = nullptr, *l2l_seg = nullptr;  // tree-pass register caches (thread order)
+    double* lat_seg = nullptr;
     double* latT = nullptr;
     int32_t* gidx = nullptr;
     double *box_part = nullptr;  // per-box FP64 sums of q |t/L|^2 and q (upward pass)
@@ -62,6 +64,7 @@ struct fmm_plan_s {
     int16_t* cstart = nullptr;
     void *bank_mma = nullptr, *bank_mma_lo = nullptr, *m2l_part = nullptr;
     void* msplit = nullptr;  // bf16x3: source expansions split into hi/lo (replicas x (nbox + 1) rows)
+    void* sign_tab = nullptr;  // bf16x3: reflection sign-bit masks [class][k chunk of 8]
     int m2l_nbuf = 1;        // bf16x3: LDS staging buffers (2: copy of the next offset overlaps)
     std::vector<void*> allocs;
     size_t ws_bytes = 0;
@@ -88,6 +91,36 @@ bool dev_alloc(fmm_plan_t p, void** ptr, size_t bytes) {
     p->allocs.push_back(*ptr);
     p->ws_bytes += bytes;
     return true;
+}
+
+// Reflection parity bits of real coefficient k (bit 2: x -> -x, bit 1:
+// y -> -y, bit 0: z -> -z), as the kernels' refl_bits.
+int refl_bits_host(int k) {
+    const int l = (int)std::floor(std::sqrt((double)k + 0.5));
+    const int rem = k - l * l;
+    const int m = (rem + 1) >> 1;
+    const int sn = (rem > 0 && !(rem & 1)) ? 1 : 0;
+    const int xo = sn ? !(m & 1) : (m & 1);
+    return (xo << 2) | (sn << 1) | ((l + m) & 1);
+}
+
+// Pack a K x K row-major operator in the tree kernels' thread order: entry j
+// of thread t (row r, k range [kb, ke) of its segment, as the kernels derive
+// it) at j kTreeThreads + t, zero past the range.
+template <typename T>
+std::vector<T> pack_tri(const double* A, int K, int shape) {
+    using namespace fmmk;
+    std::vector<T> out((size_t)kTriCache * kTreeThreads, T(0));
+    const int nseg = tri_nseg(K), slen = (K + nseg - 1) / nseg;
+    for (int it = 0; it < nseg * K && it < kTreeThreads; ++it) {
+        const int s = it / K, r = it % K;
+        const int l = (int)std::floor(std::sqrt((double)r + 0.5));
+        const int kb = std::max(s * slen, shape == kTriUpper ? l * l : 0);
+        const int ke = std::min(std::min(K, (s + 1) * slen), shape == kTriLower ? (l + 1) * (l + 1) : K);
+        for (int j = 0; j < kTriCache && kb + j < ke; ++j)
+            out[(size_t)j * kTreeThreads + it] = (T)A[(size_t)r * K + kb + j];
+    }
+    return out;
 }
 
 template <typename T>
@@ -222,7 +255,8 @@ void launch_m2l_mma(fmm_plan_t P, const Geo& g, int R) {
         k_m2l_bf16x3<RTV><<<nt, kM2LThreads, lds, st>>>(g, mg, P->tasks, P->olist, P->cstart,   \
                                                 (const uint4*)P->msplit,                        \
                                                 (const uint4*)P->bank_mma, P->m2l_nbuf,         \
-                                                (float*)loc, (float*)part);                     \
+                                                (const uint4*)P->sign_tab, (float*)loc,         \
+                                                (float*)part);                                  \
         break;
         FMM_M2L_F32(1) FMM_M2L_F32(2) FMM_M2L_F32(3) FMM_M2L_F32(4)
         FMM_M2L_F32(5) FMM_M2L_F32(6) FMM_M2L_F32(7) FMM_M2L_F32(8)
@@ -309,7 +343,8 @@ fmm_status enqueue_eval(fmm_plan_t P, const std::vector<fmmk::RepDesc>& rd, cons
     mark(P, 2);
     for (int lev = g.depth - 1; lev >= g.lmin; --lev)
         k_m2m<T><<<dim3(1u << (3 * lev), R), kTreeThreads, 0, st>>>(
-            g, lev, mult, (const T*)P->m2mT, P->leaf_part, P->box_part, (uint16_t*)P->msplit, P->mg.KP);
+            g, lev, mult, (const T*)P->m2mT, (const T*)P->m2m_seg, P->leaf_part, P->box_part,
+            (uint16_t*)P->msplit, P->mg.KP);
     mark(P, 3);
     if (g.periodic && g.depth == 0)
         k_root<T><<<R, 256, 0, st>>>(g, P->leaf_part, P->root_m, mult, P->latT, P->root_l, loc,
@@ -329,8 +364,9 @@ fmm_status enqueue_eval(fmm_plan_t P, const std::vector<fmmk::RepDesc>& rd, cons
     const int l0 = g.periodic ? 0 : g.lmin;
     if (g.depth >= 1 && g.depth - 1 >= l0)
         k_downward<T><<<dim3(1u << (3 * (g.depth - 1)), R), kTreeThreads, 0, st>>>(
-            g, l0, loc, (const T*)P->l2lT, mult, (const T*)P->m2mT, P->leaf_part, P->box_part, P->latT,
-            P->root_m, P->root_l, P->dom);
+            g, l0, loc, (const T*)P->l2lT, (const T*)P->l2l_seg, mult, (const T*)P->m2mT,
+            (const T*)P->m2m_seg, P->leaf_part, P->box_part, P->latT, P->lat_seg, P->root_m, P->root_l,
+            P->dom);
     mark(P, 6);
     switch (P->p2p_waves) {
 #define FMM_NEAR(NWV)                                                                            \
@@ -513,6 +549,10 @@ fmm_status fmm_plan_create(const fmm_params* prm, void* hip_stream, fmm_plan_t* 
     ok &= dev_alloc(P, &P->m2mT, K * K * ts);  // octant 0; the others are its reflections
     ok &= dev_alloc(P, &P->l2lT, K * K * ts);
     ok &= dev_alloc(P, (void**)&P->latT, K * K * 8);
+    const size_t seg = (size_t)fmmk::kTriCache * fmmk::kTreeThreads;
+    ok &= dev_alloc(P, &P->m2m_seg, seg * ts);
+    ok &= dev_alloc(P, &P->l2l_seg, seg * ts);
+    ok &= dev_alloc(P, (void**)&P->lat_seg, seg * 8);
     ok &= dev_alloc(P, (void**)&P->gidx, 3 * (size_t)P->Kg * 4 * 4);
     ok &= dev_alloc(P, &P->gcoef, 3 * (size_t)P->Kg * 4 * ts);
     ok &= dev_alloc(P, (void**)&P->dom, RM * 8 * 8);
@@ -564,6 +604,21 @@ fmm_status fmm_plan_create(const fmm_params* prm, void* hip_stream, fmm_plan_t* 
     }
     auto lt = transpose_blocks<double>(lat, 1, K);
     up(P->latT, lt.data(), lt.size() * 8);
+    {
+        auto ls = pack_tri<double>(lat.data(), (int)K, fmmk::kTriFull);
+        up(P->lat_seg, ls.data(), ls.size() * 8);
+        if (P->fp64) {
+            auto a = pack_tri<double>(m2m.data(), (int)K, fmmk::kTriLower);
+            auto c = pack_tri<double>(l2l.data(), (int)K, fmmk::kTriUpper);
+            up(P->m2m_seg, a.data(), a.size() * 8);
+            up(P->l2l_seg, c.data(), c.size() * 8);
+        } else {
+            auto a = pack_tri<float>(m2m.data(), (int)K, fmmk::kTriLower);
+            auto c = pack_tri<float>(l2l.data(), (int)K, fmmk::kTriUpper);
+            up(P->m2m_seg, a.data(), a.size() * 4);
+            up(P->l2l_seg, c.data(), c.size() * 4);
+        }
+    }
     up(P->gidx, gi.data(), gi.size() * 4);
     // matrix-core M2L: mode, tile geometry, offset lists, task list, banks
     {
@@ -611,18 +666,29 @@ fmm_status fmm_plan_create(const fmm_params* prm, void* hip_stream, fmm_plan_t* 
             for (int o = 0; o < 343; ++o)
                 if (seen[o]) used.push_back(o);
         }
-        std::vector<int> bound(mg.nchunk + 1);
-        for (int k = 0; k <= mg.nchunk; ++k) {
-            const size_t u = (size_t)k * used.size() / mg.nchunk;
-            bound[k] = u < used.size() ? used[u] : 343;
-        }
         std::vector<int16_t> cstart(8 * (mg.nchunk + 1));
-        for (int c = 0; c < 8; ++c) {
-            std::sort(cls_off.begin() + 189 * c, cls_off.begin() + 189 * (c + 1));
-            int pos = 0;
+        if (P->m2l_mode == 3) {
+            // every class runs on class 0's (canonical) offsets, mirrored by
+            // the class's reflection; chunks are equal slices of that list
+            std::sort(cls_off.begin(), cls_off.begin() + 189);
+            for (int c = 1; c < 8; ++c)
+                std::copy(cls_off.begin(), cls_off.begin() + 189, cls_off.begin() + 189 * c);
+            for (int c = 0; c < 8; ++c)
+                for (int k = 0; k <= mg.nchunk; ++k)
+                    cstart[c * (mg.nchunk + 1) + k] = (int16_t)(k * 189 / mg.nchunk);
+        } else {
+            std::vector<int> bound(mg.nchunk + 1);
             for (int k = 0; k <= mg.nchunk; ++k) {
-                while (pos < 189 && cls_off[189 * c + pos] < bound[k]) ++pos;
-                cstart[c * (mg.nchunk + 1) + k] = (int16_t)pos;
+                const size_t u = (size_t)k * used.size() / mg.nchunk;
+                bound[k] = u < used.size() ? used[u] : 343;
+            }
+            for (int c = 0; c < 8; ++c) {
+                std::sort(cls_off.begin() + 189 * c, cls_off.begin() + 189 * (c + 1));
+                int pos = 0;
+                for (int k = 0; k <= mg.nchunk; ++k) {
+                    while (pos < 189 && cls_off[189 * c + pos] < bound[k]) ++pos;
+                    cstart[c * (mg.nchunk + 1) + k] = (int16_t)pos;
+                }
             }
         }
         // Work-groups are dispatched round-robin over the 8 XCDs (group i on XCD
@@ -667,6 +733,7 @@ fmm_status fmm_plan_create(const fmm_params* prm, void* hip_stream, fmm_plan_t* 
             ok2 &= dev_alloc(P, &P->msplit, ms);
             // the zero row and the padding past K are never written again
             if (ok2) ok2 &= hipMemset(P->msplit, 0, ms) == hipSuccess;
+            ok2 &= dev_alloc(P, &P->sign_tab, 8 * 4 * fmmk::kM2LMaxKs * 16);
         }
         if (mg.nchunk > 1)
             ok2 &= dev_alloc(P, &P->m2l_part, RM * mg.nchunk * nt_all * P->Kp * P->tsz);
@@ -692,12 +759,13 @@ fmm_status fmm_plan_create(const fmm_params* prm, void* hip_stream, fmm_plan_t* 
                         bm[((size_t)o * mg.RP + r) * mg.KP + k] = (float)bank[((size_t)o * K + r) * K + k];
             up(P->bank_mma, bm.data(), nb * 4);
         } else {
-            // per offset: [part hi/lo][KC][RP][8], the LDS image of the operator
+            // slot j = canonical offset j: [part hi/lo][KC][RP][8], the LDS image
+            // of the operator
             std::vector<uint16_t> bm(2 * nb, 0);
-            for (int o = 0; o < 343; ++o)
+            for (int o = 0; o < 189; ++o)
                 for (size_t r = 0; r < K; ++r)
                     for (size_t k = 0; k < K; ++k) {
-                        const double v = bank[((size_t)o * K + r) * K + k];
+                        const double v = bank[((size_t)ol[o] * K + r) * K + k];
                         const uint16_t h = to_bf16((float)v);
                         const uint16_t l = to_bf16((float)(v - (double)from_bf16(h)));
                         const size_t kc = k / 8, e8 = k % 8;
@@ -706,6 +774,15 @@ fmm_status fmm_plan_create(const fmm_params* prm, void* hip_stream, fmm_plan_t* 
                         bm[base + (((size_t)KC + kc) * mg.RP + r) * 8 + e8] = l;
                     }
             up(P->bank_mma, bm.data(), 2 * nb * 2);
+            // sign-bit masks of S for class c: chunk kc covers k = 8 kc .. 8 kc + 7
+            // (bf16 entry e at bit 16 (e % 2) + 15 of dword e / 2)
+            std::vector<uint32_t> sg(8 * 4 * fmmk::kM2LMaxKs * 4, 0u);
+            for (int c = 0; c < 8; ++c)
+                for (int k = 0; k < (int)K; ++k)
+                    if (__builtin_popcount((unsigned)(c & refl_bits_host(k))) & 1)
+                        sg[((size_t)c * 4 * fmmk::kM2LMaxKs + k / 8) * 4 + (k % 8) / 2] |=
+                            (k & 1) ? 0x80000000u : 0x8000u;
+            up(P->sign_tab, sg.data(), sg.size() * 4);
         }
         hipError_t ea = hipSuccess;
         auto setlds = [&](const void* fn) {

@@ -60,9 +60,20 @@ namespace fmmk {
 
 // Matrix-core M2L: work items and tile sizes.
 constexpr size_t kLdsBytes = 160 * 1024;  // LDS per compute unit (gfx950)
+
+// Tree-pass kernels (M2M, L2L, root): block size and the split of a K x K
+// degree-triangular operator into (segment, row) work items, one per thread.
+constexpr int kTreeThreads = 512;
+constexpr int kTriCache = 32;  // operator entries a thread keeps in registers
+enum TriShape { kTriLower = 0, kTriUpper = 1, kTriFull = 2 };
+__host__ __device__ inline int tri_nseg(int K) {
+    const int n = kTreeThreads / K;
+    return n < 1 ? 1 : (n > 8 ? 8 : n);
+}
 constexpr int kM2LWaves = 5;                 // wavefronts per matrix-core M2L work-group
 constexpr int kM2LTile = 16 * kM2LWaves;     // target columns per work-group
 constexpr int kM2LMaxRT = 8;    // row tiles of 16: K <= 128 (p <= 10)
+constexpr int kM2LMaxKs = 4;    // bf16 k-steps of 32: K <= 128
 
 // One M2L work item: child class (4 bx + 2 by + bz), tile of that class's
 // target columns (the class's boxes of every level, deepest level first) and

@@ -68,13 +68,27 @@ struct RhoLds {
     T a[(kPMax + 1) * (kPMax + 1)];
     T b[(kPMax + 1) * (kPMax + 1)];
 };
-template <typename T>
+template <typename T, int NT>
 __device__ __forceinline__ void load_rho_lds(RhoLds<T>& rc, int p) {
-    for (int i = threadIdx.x; i < (p + 1) * (kPMax + 1); i += blockDim.x) {
-        rc.a[i] = (T)c_rho.a[i];
-        rc.b[i] = (T)c_rho.b[i];
+    constexpr int E = ((kPMax + 1) * (kPMax + 1) + NT - 1) / NT;
+    const int n = (p + 1) * (kPMax + 1);
+    double va[E], vb[E];
+#pragma unroll
+    for (int m = 0; m < E; ++m) {
+        const int i = min((int)threadIdx.x + m * NT, n - 1);
+        va[m] = c_rho.a[i];
+        vb[m] = c_rho.b[i];
     }
-    for (int i = threadIdx.x; i <= p; i += blockDim.x) rc.f[i] = (T)c_rho.f[i];
+    const double vf = c_rho.f[min((int)threadIdx.x, p)];
+#pragma unroll
+    for (int m = 0; m < E; ++m) {
+        const int i = threadIdx.x + m * NT;
+        if (i < n) {
+            rc.a[i] = (T)va[m];
+            rc.b[i] = (T)vb[m];
+        }
+    }
+    if ((int)threadIdx.x <= p) rc.f[threadIdx.x] = (T)vf;
 }
 
 // Visit every coefficient of rho(u) in the order m = 0..p, l = m..p, calling
@@ -544,8 +558,6 @@ __global__ __launch_bounds__(64) void k_p2m(Geo g, const vec4_t<T>* __restrict__
                                             uint16_t* __restrict__ msplit_all, int split_kp) {
     extern __shared__ __align__(16) unsigned char p2m_lds[];
     __shared__ RhoLds<T> rho;
-    load_rho_lds<T>(rho, g.p);
-    __syncthreads();
     const int32_t* leaf_start = leaf_start_all + (size_t)blockIdx.y * (g.nleaf + 1);
     const double* dom = dom_all + 8 * blockIdx.y;
     T* mult = mult_all + (size_t)blockIdx.y * g.nbox * g.Kp;
@@ -556,6 +568,8 @@ __global__ __launch_bounds__(64) void k_p2m(Geo g, const vec4_t<T>* __restrict__
     const int lane = threadIdx.x;
     const int b = leaf_start[leaf], n = leaf_start[leaf + 1] - b;
     const double edge = dom[3];
+    load_rho_lds<T, 64>(rho, g.p);  // in flight with the leaf bounds
+    __syncthreads();
     const double h = edge / g.nb;
     const T ih = (T)(1.0 / h);
     double s2 = 0.0, qs = 0.0;
@@ -588,9 +602,17 @@ __global__ __launch_bounds__(64) void k_p2m(Geo g, const vec4_t<T>* __restrict__
         for (int i = 0; i < kKMax / 64; ++i) {
             const int k = lane + 64 * i;
             if (k < g.K) {
-                T v = T(0);
-                for (int r = 0; r < rows; ++r) v += buf[r * S + k];
-                acc[i] += v;
+                // four interleaved partial sums keep the LDS reads in flight
+                T v0 = T(0), v1 = T(0), v2 = T(0), v3 = T(0);
+                int r = 0;
+                for (; r + 4 <= rows; r += 4) {
+                    v0 += buf[r * S + k];
+                    v1 += buf[(r + 1) * S + k];
+                    v2 += buf[(r + 2) * S + k];
+                    v3 += buf[(r + 3) * S + k];
+                }
+                for (; r < rows; ++r) v0 += buf[r * S + k];
+                acc[i] += (v0 + v1) + (v2 + v3);
             }
         }
         __syncthreads();
@@ -624,7 +646,6 @@ __global__ __launch_bounds__(64) void k_p2m(Geo g, const vec4_t<T>* __restrict__
 // entry by entry).  The tree kernels load rows of the octant-0 operator once
 // and apply them to all eight signed children.
 
-constexpr int kTreeThreads = 512;
 
 // Reflection parity of real coefficient k: bit 2 set when the coefficient
 // changes sign under x -> -x, bit 1 under y -> -y, bit 0 under z -> -z.  The
@@ -642,8 +663,6 @@ __device__ __forceinline__ double refl_sign(int c, int bits) {
     return (__popc((unsigned)(c & bits)) & 1) ? -1.0 : 1.0;
 }
 
-enum TriShape { kTriLower = 0, kTriUpper = 1, kTriFull = 2 };
-constexpr int kTriCache = 32;  // operator entries a thread keeps in registers
 
 // One thread's share of a degree-triangular K x K operator A (given
 // transposed, At[k K + r]): a row r and a contiguous k range [kb, ke) of it.
@@ -652,12 +671,15 @@ constexpr int kTriCache = 32;  // operator entries a thread keeps in registers
 // segments (at most 8), so a block of kTreeThreads holds every (segment,
 // row) pair once.  The first kTriCache entries of the range are loaded once
 // into registers and reused by every product the block forms.
+// The register cache comes from a table packed on the host in the same
+// thread order (entry j of thread t at j kTreeThreads + t, zero past the
+// range), so its loads are coalesced.
 template <typename TO, int kShape>
 struct TriPart {
     int r, s, kb, ke;
     TO a[kTriCache];
-    __device__ __forceinline__ void load(int K, const TO* __restrict__ At) {
-        const int nseg = max(1, min(8, kTreeThreads / K));
+    __device__ __forceinline__ void load(int K, const TO* __restrict__ packed) {
+        const int nseg = tri_nseg(K);
         const int slen = (K + nseg - 1) / nseg;
         const int it = threadIdx.x;
         r = -1;
@@ -669,10 +691,8 @@ struct TriPart {
             kb = max(s * slen, kShape == kTriUpper ? l * l : 0);
             ke = min(min(K, (s + 1) * slen), kShape == kTriLower ? (l + 1) * (l + 1) : K);
         }
-        const int last = max(kb, ke - 1);
-        const int rr = max(r, 0);
 #pragma unroll
-        for (int j = 0; j < kTriCache; ++j) a[j] = At[(size_t)min(kb + j, last) * K + rr];
+        for (int j = 0; j < kTriCache; ++j) a[j] = packed[j * kTreeThreads + it];
     }
 };
 
@@ -683,7 +703,7 @@ struct TriPart {
 template <typename TO, int NC, int kShape>
 __device__ void tri_matvec(const TriPart<TO, kShape>& tp, int K, const TO* __restrict__ At, double* xs,
                            double* part, double* ys) {
-    const int nseg = max(1, min(8, kTreeThreads / K));
+    const int nseg = tri_nseg(K);
     if (tp.r >= 0) {
         double acc[NC];
 #pragma unroll
@@ -772,12 +792,13 @@ __device__ __forceinline__ double combine_octants(const double* ys, int K, int r
 template <typename T>
 __global__ __launch_bounds__(kTreeThreads) void k_m2m(Geo g, int lev, T* __restrict__ mult_all,
                                                       const T* __restrict__ op0,
+                                                      const T* __restrict__ op0_seg,
                                                       const double* __restrict__ leaf_part_all,
                                                       double* __restrict__ box_part_all,
                                                       uint16_t* __restrict__ msplit_all, int split_kp) {
     __shared__ double xs[8 * kKMax], part[8 * kTreeThreads], ps[16];
     TriPart<T, kTriLower> tp;
-    tp.load(g.K, op0);
+    tp.load(g.K, op0_seg);
     const int rp = blockIdx.y, K = g.K, box = blockIdx.x;
     T* mult = mult_all + (size_t)rp * g.nbox * g.Kp;
     double* box_part = box_part_all + (size_t)rp * g.nbox * 2;
@@ -811,15 +832,16 @@ __global__ __launch_bounds__(kTreeThreads) void k_m2m(Geo g, int lev, T* __restr
 // its M2L sum alone.
 template <typename T>
 __global__ __launch_bounds__(kTreeThreads) void k_downward(
-    Geo g, int l0, T* __restrict__ loc_all, const T* __restrict__ l2l0, const T* __restrict__ mult_all,
-    const T* __restrict__ m2m0, const double* __restrict__ leaf_part_all,
-    const double* __restrict__ box_part_all, const double* __restrict__ latT,
-    double* __restrict__ root_m_all, double* __restrict__ root_l_all, double* __restrict__ dom_all) {
+    Geo g, int l0, T* __restrict__ loc_all, const T* __restrict__ l2l0, const T* __restrict__ l2l0_seg,
+    const T* __restrict__ mult_all, const T* __restrict__ m2m0, const T* __restrict__ m2m0_seg,
+    const double* __restrict__ leaf_part_all, const double* __restrict__ box_part_all,
+    const double* __restrict__ latT, const double* __restrict__ lat_seg, double* __restrict__ root_m_all,
+    double* __restrict__ root_l_all, double* __restrict__ dom_all) {
     __shared__ double xs[8 * kKMax], part[8 * kTreeThreads];
     __shared__ double v[kKMax], ps[16];
     __shared__ T anc[kDMax * kKMax];
     TriPart<T, kTriUpper> tp;
-    tp.load(g.K, l2l0);
+    tp.load(g.K, l2l0_seg);
     const int rp = blockIdx.y, K = g.K, D = g.depth;
     T* loc = loc_all + (size_t)rp * g.nbox * g.Kp;
     const int b = blockIdx.x;
@@ -849,9 +871,9 @@ __global__ __launch_bounds__(kTreeThreads) void k_downward(
     }
     if (g.periodic) {
         TriPart<T, kTriLower> tm;
-        tm.load(K, m2m0);
+        tm.load(K, m2m0_seg);
         TriPart<double, kTriFull> tl;
-        tl.load(K, latT);
+        tl.load(K, lat_seg);
         gather_children<T>(g, 1, 0, mult_all + (size_t)rp * g.nbox * g.Kp,
                            leaf_part_all + (size_t)rp * g.nleaf * 2, box_part_all + (size_t)rp * g.nbox * 2,
                            xs, ps);
@@ -1197,10 +1219,10 @@ __device__ __forceinline__ void m2l_store(const Geo& g, const M2LGeom& mg, int c
     const int j = 16 * wave + (lane & 15);
     int lev, tx, ty, tz;
     if (!m2l_column(g, cls, tile, j, lev, tx, ty, tz)) return;
-    const int64_t box = g.lev_off[lev] + morton(tx, ty, tz);
+    const int64_t box = lev_offset(lev) + morton(tx, ty, tz);
     TO* dst;
     if (mg.nchunk == 1) dst = loc + (size_t)box * g.Kp;
-    else dst = part + ((size_t)chunk * mg.nt_all + (box - g.lev_off[g.lmin])) * g.Kp;
+    else dst = part + ((size_t)chunk * mg.nt_all + (box - lev_offset(g.lmin))) * g.Kp;
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
         const int r = 16 * rt + (f64layout ? 4 * v + (lane >> 4) : 4 * (lane >> 4) + v);
@@ -1315,6 +1337,14 @@ __global__ __launch_bounds__(64 * kM2LWaves) void k_m2l_f64(Geo g, M2LGeom mg, c
 // wavefront (no LDS bank conflicts).  With two buffers the copy of offset
 // i + 1 is in flight while offset i is multiplied: one wait and one barrier
 // per offset.  Products Th mh + Th ml + Tl mh accumulate in FP32.
+//
+// Every class works from the 189 operators of class 0 (the bank holds those
+// only, in list order): reflecting the axes whose bit is set in the class
+// maps class 0's offsets onto the class's own, and T(P o) = S T(o) S with S
+// the diagonal +-1 reflection signs.  So a column of class c applies T(o') of
+// the canonical offset o' to S mu of the source at offset P o' (signs flipped
+// on the B fragments) and its result is S times the accumulator (at the
+// store).  Offset chunks are then equal for all classes.
 constexpr int kM2LThreads = 64 * kM2LWaves;
 static_assert(kM2LThreads == 4 * kM2LTile, "source copy mapping: 4 lanes per column");
 
@@ -1330,8 +1360,10 @@ __global__ __launch_bounds__(kM2LThreads) void k_m2l_bf16x3(Geo g, M2LGeom mg,
                                                            const int16_t* __restrict__ cstart,
                                                            const uint4* __restrict__ msplit,
                                                            const uint4* __restrict__ bank, int nbuf,
+                                                           const uint4* __restrict__ sign_tab,
                                                            float* __restrict__ loc, float* __restrict__ part) {
     extern __shared__ __align__(16) uint4 lds_q[];
+    __shared__ int col_box[kM2LTile];
     const int KC = mg.KP / 8;
     const int a_chunks = 2 * KC * mg.RP, b_chunks = 2 * KC * kM2LTile;
     const M2LTask tk = tasks[blockIdx.x];
@@ -1345,16 +1377,18 @@ __global__ __launch_bounds__(kM2LThreads) void k_m2l_bf16x3(Geo g, M2LGeom mg,
     int clev = 0, ctx = 0, cty = 0, ctz = 0;
     const bool col_ok = m2l_column(g, tk.cls, tk.tile, jc, clev, ctx, cty, ctz);
     const int cn = 1 << clev;
-    const int64_t clo = g.lev_off[clev];
+    const int64_t clo = lev_offset(clev);
+    if (tid < kM2LTile) col_box[tid] = col_ok ? (int)(clo + morton(ctx, cty, ctz)) : -1;
     const int o0 = cstart[tk.cls * (mg.nchunk + 1) + tk.chunk];
     const int o1 = cstart[tk.cls * (mg.nchunk + 1) + tk.chunk + 1];
+    const int fx = (tk.cls & 4) ? -1 : 1, fy = (tk.cls & 2) ? -1 : 1, fz = (tk.cls & 1) ? -1 : 1;
 
     auto issue = [&](int oc, uint4* dst) {
-        const int oi = olist[tk.cls * 189 + oc];
-        const uint4* src = bank + (size_t)oi * a_chunks;
+        const int oi = olist[tk.cls * 189 + oc];  // canonical offset; operator slot oc
+        const uint4* src = bank + (size_t)oc * a_chunks;
         for (int c0 = 0; c0 < a_chunks; c0 += kM2LThreads)
             if (c0 + tid < a_chunks) lds_dma16(src + c0 + tid, dst + c0 + 64 * wave);
-        const int ox = oi / 49 - 3, oy = (oi / 7) % 7 - 3, oz = oi % 7 - 3;
+        const int ox = fx * (oi / 49 - 3), oy = fy * ((oi / 7) % 7 - 3), oz = fz * (oi % 7 - 3);
         int sx = ctx - ox, sy = cty - oy, sz = ctz - oz;
         bool ok = col_ok;
         if (g.periodic) {
@@ -1374,6 +1408,11 @@ __global__ __launch_bounds__(kM2LThreads) void k_m2l_bf16x3(Geo g, M2LGeom mg,
 #pragma unroll
     for (int r = 0; r < RT; ++r) acc[r] = mf4{0.f, 0.f, 0.f, 0.f};
     const int col = 16 * wave + (lane & 15), kq = lane >> 4, row = lane & 15;
+    // sign bits of S for the lane's B fragments (k = 8 kc + e, kc = 4 si + kq),
+    // from the table sign_tab[class][kc] (bf16 sign-bit masks of 8 entries)
+    uint4 bsg[kM2LMaxKs];
+#pragma unroll
+    for (int si = 0; si < kM2LMaxKs; ++si) bsg[si] = sign_tab[tk.cls * 4 * kM2LMaxKs + 4 * si + kq];
     if (o0 < o1) issue(o0, lds_q);
     for (int oc = o0; oc < o1; ++oc) {
         const int st = oc - o0;
@@ -1384,10 +1423,21 @@ __global__ __launch_bounds__(kM2LThreads) void k_m2l_bf16x3(Geo g, M2LGeom mg,
         if (active) {
             const uint4* A = cur;
             const uint4* B = cur + a_chunks;
-            for (int ks = 0; ks < KC; ks += 4) {
-                const int kc = ks + kq;
-                const mbf8 bh = __builtin_bit_cast(mbf8, B[kc * kM2LTile + col]);
-                const mbf8 bl = __builtin_bit_cast(mbf8, B[(KC + kc) * kM2LTile + col]);
+#pragma unroll
+            for (int si = 0; si < kM2LMaxKs; ++si) {
+                if (4 * si >= KC) break;
+                const int kc = 4 * si + kq;
+                uint4 uh = B[kc * kM2LTile + col], ul = B[(KC + kc) * kM2LTile + col];
+                uh.x ^= bsg[si].x;
+                uh.y ^= bsg[si].y;
+                uh.z ^= bsg[si].z;
+                uh.w ^= bsg[si].w;
+                ul.x ^= bsg[si].x;
+                ul.y ^= bsg[si].y;
+                ul.z ^= bsg[si].z;
+                ul.w ^= bsg[si].w;
+                const mbf8 bh = __builtin_bit_cast(mbf8, uh);
+                const mbf8 bl = __builtin_bit_cast(mbf8, ul);
 #pragma unroll
                 for (int r = 0; r < RT; ++r) {
                     const mbf8 ah = __builtin_bit_cast(mbf8, A[kc * mg.RP + 16 * r + row]);
@@ -1403,11 +1453,37 @@ __global__ __launch_bounds__(kM2LThreads) void k_m2l_bf16x3(Geo g, M2LGeom mg,
             issue(oc + 1, lds_q);
         }
     }
-    if (!active) return;
+    // Output rows get the class's signs S; the block's results are transposed
+    // through LDS (the staging buffers are free now) so that each box row is
+    // written as contiguous 16-byte chunks, padding rows (zero) included.
+    __syncthreads();
+    float* tt = (float*)lds_q;
+    const int ts = mg.RP + 4;
+    if (active) {
 #pragma unroll
-    for (int r = 0; r < RT; ++r)
-        m2l_store<mf4, float>(g, mg, tk.cls, tk.tile, tk.chunk, wave, lane, r, acc[r], false,
-                              loc, part);
+        for (int r = 0; r < RT; ++r) {
+            // row 16 r + 4 kq + v is entry 4 (kq & 1) + v of sign chunk 2 r + kq / 2
+            const uint4 m = sign_tab[tk.cls * 4 * kM2LMaxKs + 2 * r + (kq >> 1)];
+            const uint32_t lo = (kq & 1) ? m.z : m.x, hi = (kq & 1) ? m.w : m.y;
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const uint32_t wd = v < 2 ? lo : hi;
+                const bool neg = (wd >> ((v & 1) ? 31 : 15)) & 1u;
+                tt[col * ts + 16 * r + 4 * kq + v] = neg ? -acc[r][v] : acc[r][v];
+            }
+        }
+    }
+    __syncthreads();
+    const int cpb = g.Kp / 4;
+    for (int c = tid; c < kM2LTile * cpb; c += kM2LThreads) {
+        const int j = c / cpb, q4 = c - j * cpb;
+        const int box = col_box[j];
+        if (box < 0) continue;
+        float* dst = mg.nchunk == 1
+                         ? loc + (size_t)box * g.Kp
+                         : part + ((size_t)tk.chunk * mg.nt_all + (box - lev_offset(g.lmin))) * g.Kp;
+        *(float4*)(dst + 4 * q4) = *(const float4*)(tt + j * ts + 4 * q4);
+    }
 }
 
 // Sum the offset-chunk partials into the local expansions (fixed chunk order).
@@ -1514,7 +1590,7 @@ __global__ __launch_bounds__(64 * kNW) void k_near_far(
     __shared__ T lam[kKMax];
     __shared__ T gr[3][kKgMax];
     __shared__ RhoLds<T> rho;
-    load_rho_lds<T>(rho, g.p);
+    load_rho_lds<T, 64 * kNW>(rho, g.p);
     __shared__ T part[kNW][4][64];
     __shared__ double esum_part[kNW][64];
     const int leaf = blockIdx.x;

@@ -166,6 +166,22 @@ def test_octant_operators_are_reflections_of_octant_0(which):
         np.testing.assert_array_equal(A[c], s[:, None] * A[0] * s[None, :])
 
 
+def test_m2l_operators_of_mirrored_offsets():
+    """The bf16x3 M2L keeps one class's 189 operators and applies the others as
+    T(P o) = S T(o) S (P a reflection of axes, S its diagonal signs)."""
+    p = 7
+    bank = fmm.fmm_host_operator(p, 0)
+    bits = _reflection_bits(p)
+    import itertools
+    for c in range(1, 8):
+        f = np.array([-1 if (c >> 2) & 1 else 1, -1 if (c >> 1) & 1 else 1, -1 if c & 1 else 1])
+        s = np.where(np.array([bin(c & b).count("1") & 1 for b in bits]) == 1, -1.0, 1.0)
+        for o in itertools.product(range(-3, 4), repeat=3):
+            po = np.array(o) * f + 3
+            np.testing.assert_array_equal(bank[po[0], po[1], po[2]],
+                                          s[:, None] * bank[o[0] + 3, o[1] + 3, o[2] + 3] * s[None, :])
+
+
 @pytest.mark.parametrize("neutral", [True, False])
 def test_lattice_operator_matches_ewald(neutral):
     """Depth-0 periodic FMM assembled from the host lattice operator: near field
