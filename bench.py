@@ -52,6 +52,28 @@ def p2p_pairs(cnt, periodic=True):
     return int(np.sum(cnt * tot) - cnt.sum())
 
 
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_water_box_30k_p8.md")
+KERNEL_SRC = os.path.join(ROOT, "paper_2410_01626_amd", "csrc", "fmm_kernels.hip")
+PHASE_KERNEL = {"near_far": "k_near_far<float, 8>", "m2l": "k_m2l_bf16x3<6>"}
+
+
+def measured_traffic(phase):
+    """HBM bytes per launch of the phase's kernel from the committed FETCH_SIZE /
+    WRITE_SIZE summary, or None when there is none or the kernel source has
+    changed since the counters were taken (hash recorded in the summary)."""
+    import hashlib
+    import re
+    name = PHASE_KERNEL.get(phase)
+    if name is None or not os.path.exists(TRAFFIC_FILE):
+        return None
+    text = open(TRAFFIC_FILE).read()
+    m = re.search(r"^source_sha256 = ([0-9a-f]{64})$", text, re.M)
+    if not m or m.group(1) != hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest():
+        return None
+    m = re.search(r"^traffic\[%s\] = (\d+)$" % re.escape(name), text, re.M)
+    return int(m.group(1)) if m else None
+
+
 def m2l_translations(depth, periodic=True):
     lmin = 1 if periodic else 2
     return sum(189 * 8 ** l for l in range(lmin, depth + 1))
@@ -66,7 +88,20 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
     ap.add_argument("--no-batched", action="store_true", help="skip the replica-batch leg")
     ap.add_argument("--batched-steps", type=int, default=10)
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="only run a plain 256 MiB device copy (3 times): the reference for "
+                         "scaling the FETCH_SIZE / WRITE_SIZE counters")
     args = ap.parse_args()
+    if args.copy_probe:
+        import torch
+        a = torch.ones(64 * 1024 * 1024, device="cuda")
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes": 4 * a.numel(), "copies": 3}), flush=True)
+        return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: the solver runs on a single device and this "
               "build has no multi-GPU path (run with --gpus 1)", file=sys.stderr)
@@ -185,7 +220,7 @@ def main():
         flops, bound, peak, unit = work[dom]
         achieved = flops / (phase_ms[dom] * 1e-3)
         roof = {"kernel": dom, "bound": bound, "achieved": achieved / 1e12, "peak": peak / 1e12,
-                "unit": unit, "frac": achieved / peak, "traffic": None,
+                "unit": unit, "frac": achieved / peak, "traffic": measured_traffic(dom),
                 "work": {"flops_per_launch": flops, "near_field_pairs": pairs,
                          "m2l_translations": n_m2l}}
     else:
