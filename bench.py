@@ -129,29 +129,51 @@ def main():
                torch.tensor(d["lam"], dtype=torch.float64, device=dev))
         return plan, inp
 
-    def timed(plan, inp, steps, warmup, profile):
+    def breakdown(plan, inp, n=20):
+        """Per-phase mean ms from an untimed pass with events at every phase
+        boundary (each event costs GPU time, so this pass is not the timed one)."""
+        plan.profile_select(None, 1)
+        plan.profile_start(n)
+        for _ in range(n):
+            plan.eval(*inp, box=d["box"])
+        plan.profile_stop()
+        prof = plan.profile_read()
+        return {k: (v[0] / v[1] if v[1] else 0.0) for k, v in prof.items()}
+
+    def timed(plan, inp, steps, warmup, roof_phase=None, every=4):
+        """Seconds per evaluation over `steps` timed evaluations; with roof_phase,
+        HIP events on the plan's stream around that phase on every `every`-th
+        timed evaluation give its mean duration (ms) inside the timed region."""
         for _ in range(warmup):
             plan.eval(*inp, box=d["box"])
         torch.cuda.synchronize(dev)
-        if profile:
+        if roof_phase:
+            plan.profile_select([roof_phase], every)
             plan.profile_start(steps)
         t0 = time.perf_counter()
         for _ in range(steps):
             plan.eval(*inp, box=d["box"])
         torch.cuda.synchronize(dev)
         t1 = time.perf_counter()
-        prof = None
-        if profile:
+        dur = None
+        if roof_phase:
             plan.profile_stop()
-            prof = plan.profile_read()
-        return (t1 - t0) / steps, prof
+            tot, cnt = plan.profile_read()[roof_phase]
+            dur = tot / cnt if cnt else None
+        return (t1 - t0) / steps, dur
 
     plan, inp = make("bf16x3")
-    sec, prof = timed(plan, inp, args.steps, args.warmup, True)
+    for _ in range(args.warmup):
+        plan.eval(*inp, box=d["box"])
+    phase_ms = breakdown(plan, inp)
+    dom = max(phase_ms, key=phase_ms.get)
+    sec, dom_ms = timed(plan, inp, args.steps, args.warmup, roof_phase=dom)
     plan32, inp32 = make("f32")
-    sec32, prof32 = timed(plan32, inp32, args.fp64_steps, max(2, args.warmup // 4), True)
+    sec32, _ = timed(plan32, inp32, args.fp64_steps, max(2, args.warmup // 4))
+    phase_ms32 = breakdown(plan32, inp32)
     plan64, inp64 = make("fp64")
-    sec64, prof64 = timed(plan64, inp64, args.fp64_steps, max(2, args.warmup // 4), True)
+    sec64, _ = timed(plan64, inp64, args.fp64_steps, max(2, args.warmup // 4))
+    phase_ms64 = breakdown(plan64, inp64)
 
     # graph replay of the same evaluation (dedicated stream, fixed output buffers)
     gstream = torch.cuda.Stream(dev)
@@ -190,26 +212,25 @@ def main():
         for _ in range(2):
             bplan.eval_batched(ao, so, *bin_)
         torch.cuda.synchronize(dev)
-        bplan.profile_start(args.batched_steps)
         t0 = time.perf_counter()
         for _ in range(args.batched_steps):
             bplan.eval_batched(ao, so, *bin_)
         torch.cuda.synchronize(dev)
         t1 = time.perf_counter()
+        bsec = (t1 - t0) / args.batched_steps
+        # phase breakdown from a separate pass (events at every phase boundary)
+        bplan.profile_start(3)
+        for _ in range(3):
+            bplan.eval_batched(ao, so, *bin_)
         bplan.profile_stop()
         bprof = bplan.profile_read()
-        bsec = (t1 - t0) / args.batched_steps
         batched = {"workload": "16 open replicas, 10,000-60,000 atoms (%d total), depth 3, p = 8, "
                                "pH 2-9" % int(ao[-1]),
                    "batch_evals_per_s": 1.0 / bsec, "replica_evals_per_s": len(reps) / bsec,
                    "ms_per_batch": bsec * 1e3, "atoms_per_s": float(ao[-1]) / bsec,
                    "phase_ms": {k: (v[0] / v[1] if v[1] else 0.0) for k, v in bprof.items()}}
 
-    # per-phase means (ms) and the dominant kernel
-    phase_ms = {k: (v[0] / v[1] if v[1] else 0.0) for k, v in prof.items()}
-    phase_ms64 = {k: (v[0] / v[1] if v[1] else 0.0) for k, v in prof64.items()}
-    phase_ms32 = {k: (v[0] / v[1] if v[1] else 0.0) for k, v in prof32.items()}
-    dom = max(phase_ms, key=phase_ms.get)
+    # the dominant kernel's work over its duration measured inside the timed region
     pairs = p2p_pairs(leaf_counts(d["x"], box, depth))
     n_m2l = m2l_translations(depth)
     # the headline plan runs M2L as bf16 matrix-core products (three per
@@ -218,9 +239,10 @@ def main():
             "m2l": (2.0 * K * K * n_m2l, "mfma", PEAK["bf16_mfma"], "TFLOP/s")}
     if dom in work:
         flops, bound, peak, unit = work[dom]
-        achieved = flops / (phase_ms[dom] * 1e-3)
+        achieved = flops / (dom_ms * 1e-3)
         roof = {"kernel": dom, "bound": bound, "achieved": achieved / 1e12, "peak": peak / 1e12,
                 "unit": unit, "frac": achieved / peak, "traffic": measured_traffic(dom),
+                "duration_ms": dom_ms,
                 "work": {"flops_per_launch": flops, "near_field_pairs": pairs,
                          "m2l_translations": n_m2l}}
     else:

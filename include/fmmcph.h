@@ -190,6 +190,14 @@ void fmm_plan_destroy(fmm_plan_t plan);
 #define FMM_NPHASES 8
 fmm_status fmm_profile(fmm_plan_t plan, int32_t mode, int32_t capacity, double* out);
 
+/* Restrict the events fmm_profile records (each event is a marker in the
+ * stream and costs a few microseconds of GPU time): only the boundaries of
+ * the phases whose bit is set in phase_mask, and only on every `every`-th
+ * evaluation (1 = all), counted from fmm_profile mode 1.  Call before mode 1;
+ * the default is all phases on every evaluation.  Returns FMM_E_INVALID for
+ * every < 1 or while recording. */
+fmm_status fmm_profile_select(fmm_plan_t plan, uint32_t phase_mask, int32_t every);
+
 /* Resolved launch configuration of a plan (host only, no GPU work):
  *   out[0] M2L kernel (0 plain, 1 FP32, 2 FP64, 3 bf16x3 matrix cores)
  *   out[1] offsets per M2L work-group   out[2] offset chunks

@@ -74,6 +74,10 @@ struct fmm_plan_s {
     std::vector<hipEvent_t> prof_ev;
     std::vector<int> prof_phase;  // phase that starts at the event with the same index
     size_t prof_used = 0;
+    uint32_t prof_mask = 0xffffffffu;  // phases whose boundaries get events
+    int prof_every = 1;                // events on every prof_every-th evaluation
+    int64_t prof_evals = 0;
+    bool prof_sample = false, prof_open = false;
 };
 
 namespace {
@@ -216,11 +220,22 @@ Geo make_geo(const fmm_plan_s* p) {
 
 // Record a phase boundary: the event marks the start of `phase` (and the end of
 // the previous one); phase -1 closes the evaluation.
+// Only the boundaries of the selected phases are recorded (an event opens a
+// selected phase; the next mark closes it), on every prof_every-th evaluation.
 void mark(fmm_plan_t P, int phase) {
-    if (!P->prof_on || P->prof_used >= P->prof_ev.size()) return;
+    if (!P->prof_on) return;
+    if (phase == 0) {
+        P->prof_sample = (P->prof_evals++ % P->prof_every) == 0;
+        P->prof_open = false;
+    }
+    if (!P->prof_sample) return;
+    const bool sel = phase >= 0 && ((P->prof_mask >> phase) & 1u);
+    if (!sel && !P->prof_open) return;
+    if (P->prof_used >= P->prof_ev.size()) return;
     (void)hipEventRecord(P->prof_ev[P->prof_used], P->stream);
-    P->prof_phase[P->prof_used] = phase;
+    P->prof_phase[P->prof_used] = sel ? phase : -1;
     ++P->prof_used;
+    P->prof_open = sel;
 }
 
 inline unsigned nblocks(int64_t n, int b) { return (unsigned)std::max<int64_t>(1, (n + b - 1) / b); }
@@ -950,6 +965,7 @@ fmm_status fmm_profile(fmm_plan_t P, int32_t mode, int32_t capacity, double* out
         }
         P->prof_phase.assign(P->prof_ev.size(), -1);
         P->prof_used = 0;
+        P->prof_evals = 0;
         P->prof_on = true;
         return FMM_OK;
     }
@@ -973,6 +989,15 @@ fmm_status fmm_profile(fmm_plan_t P, int32_t mode, int32_t capacity, double* out
         return FMM_OK;
     }
     return fail(P, FMM_E_INVALID, "profile mode must be 0, 1 or 2");
+}
+
+fmm_status fmm_profile_select(fmm_plan_t P, uint32_t phase_mask, int32_t every) {
+    if (!P) return FMM_E_INVALID;
+    if (every < 1) return fail(P, FMM_E_INVALID, "profile sampling interval must be >= 1");
+    if (P->prof_on) return fail(P, FMM_E_INVALID, "select phases before fmm_profile mode 1");
+    P->prof_mask = phase_mask;
+    P->prof_every = every;
+    return FMM_OK;
 }
 
 fmm_status fmm_plan_info(fmm_plan_t P, int64_t out[8]) {

@@ -53,7 +53,7 @@ class fmm_params(ctypes.Structure):
 
 EXPORTS = ["fmm_plan_create", "fmm_eval", "fmm_eval_adjoint", "fmm_eval_batched",
            "fmm_sync_check", "fmm_last_error", "fmm_plan_destroy", "fmm_profile",
-           "fmm_plan_info", "fmm_host_operator"]
+           "fmm_profile_select", "fmm_plan_info", "fmm_host_operator"]
 PHASES = ["bin", "p2m", "m2m", "root", "m2l", "l2l", "near_far", "reduce"]
 
 _lib = None
@@ -92,6 +92,8 @@ def load_library(path: str = LIB_PATH):
     lib.fmm_plan_destroy.argtypes = [vp]
     lib.fmm_profile.restype = ctypes.c_int
     lib.fmm_profile.argtypes = [vp, i32, i32, vp]
+    lib.fmm_profile_select.restype = ctypes.c_int
+    lib.fmm_profile_select.argtypes = [vp, ctypes.c_uint32, i32]
     lib.fmm_plan_info.restype = ctypes.c_int
     lib.fmm_plan_info.argtypes = [vp, vp]
     lib.fmm_host_operator.restype = ctypes.c_int64
@@ -143,6 +145,10 @@ def fmm_eval_batched(plan, R, atom_off, site_off, x, qA, qB, site_local, lam, bo
 def fmm_profile(plan, mode: int, capacity: int = 0, out=None) -> int:
     return load_library().fmm_profile(plan, mode, capacity,
                                       ctypes.c_void_p(0) if out is None else out.ctypes.data)
+
+
+def fmm_profile_select(plan, phase_mask: int, every: int = 1) -> int:
+    return load_library().fmm_profile_select(plan, phase_mask, every)
 
 
 def fmm_host_operator(order_p: int, which: int, point=None) -> np.ndarray:
@@ -306,6 +312,12 @@ class Plan:
                               _ptr(out["phi"]), _ptr(out["dVdl"]))
         self._raise(st, "fmm_eval_batched")
         return out
+
+    def profile_select(self, phases=None, every: int = 1):
+        """Record events only at the boundaries of `phases` (names from PHASES;
+        None = all), on every `every`-th evaluation.  Call before profile_start."""
+        mask = 0xFFFFFFFF if phases is None else sum(1 << PHASES.index(p) for p in phases)
+        self._raise(fmm_profile_select(self.handle, mask, every), "fmm_profile_select")
 
     def profile_start(self, capacity: int):
         self._raise(fmm_profile(self.handle, 1, capacity), "fmm_profile")
