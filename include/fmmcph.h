@@ -178,7 +178,8 @@ void fmm_plan_destroy(fmm_plan_t plan);
 
 /* Per-phase timing with HIP events recorded on the plan's stream (a
  * measurement aid; it changes no result).  The phases of one evaluation are
- *   0 binning (charges, leaf keys, counting sort, gather), 1 P2M,
+ *   0 binning (leaf keys, counting sort), 1 leaf sort + gather (interpolated
+ *   charges) + P2M,
  *   2 M2M with the periodic root and lattice operator (one launch),
  *   3 root of a depth-0 periodic tree (empty otherwise), 4 M2L, 5 L2L,
  *   6 near field + far-field evaluation + outputs (P2P, L2P), 7 reductions.

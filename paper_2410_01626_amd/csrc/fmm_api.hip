@@ -238,6 +238,12 @@ void mark(fmm_plan_t P, int phase) {
     P->prof_open = sel;
 }
 
+// Dynamic LDS of the leaf kernel: the sort buffer, later the P2M rows.
+template <typename T>
+size_t leaf_lds_bytes(int K) {
+    return std::max<size_t>((size_t)fmmk::kSortCap * 4, (size_t)64 * (K + 1) * sizeof(T));
+}
+
 inline unsigned nblocks(int64_t n, int b) { return (unsigned)std::max<int64_t>(1, (n + b - 1) / b); }
 
 // Matrix-core M2L launch: the kernel instance for the plan's precision and row
@@ -346,12 +352,10 @@ fmm_status enqueue_eval(fmm_plan_t P, const std::vector<fmmk::RepDesc>& rd, cons
     T* mult = (T*)P->mult;
     T* loc = (T*)P->loc;
     const dim3 lg(g.nleaf, R);
-    k_leaf_sort_gather<T><<<lg, 256, 0, st>>>(g, reps, x, qA, qB, site, lam, P->dom,
-                                              P->leaf_start, P->perm, pos, P->status);
     mark(P, 1);
-    k_p2m<T><<<lg, 64, (size_t)64 * (g.K + 1) * sizeof(T), st>>>(g, pos, P->leaf_start, P->dom,
-                                                                  mult, P->leaf_part,
-                                                                  (uint16_t*)P->msplit, P->mg.KP);
+    k_leaf_p2m<T><<<lg, kLeafThreads, leaf_lds_bytes<T>(g.K), st>>>(
+        g, reps, x, qA, qB, site, lam, P->dom, P->leaf_start, P->perm, pos, P->status, mult,
+        P->leaf_part, (uint16_t*)P->msplit, P->mg.KP);
     // upward pass: one launch per level down to the coarsest interacting
     // level (1 periodic, 2 open); the periodic root and its lattice operator
     // are formed at the start of the downward pass
@@ -819,11 +823,12 @@ fmm_status fmm_plan_create(const fmm_params* prm, void* hip_stream, fmm_plan_t* 
         if (ea != hipSuccess) e = ea;
     }
     if (e == hipSuccess) {
-        const int p2m_lds = 64 * ((int)K + 1) * (int)P->tsz;
-        e = P->fp64 ? hipFuncSetAttribute((const void*)&fmmk::k_p2m<double>,
-                                          hipFuncAttributeMaxDynamicSharedMemorySize, p2m_lds)
-                    : hipFuncSetAttribute((const void*)&fmmk::k_p2m<float>,
-                                          hipFuncAttributeMaxDynamicSharedMemorySize, p2m_lds);
+        e = P->fp64 ? hipFuncSetAttribute((const void*)&fmmk::k_leaf_p2m<double>,
+                                          hipFuncAttributeMaxDynamicSharedMemorySize,
+                                          (int)leaf_lds_bytes<double>((int)K))
+                    : hipFuncSetAttribute((const void*)&fmmk::k_leaf_p2m<float>,
+                                          hipFuncAttributeMaxDynamicSharedMemorySize,
+                                          (int)leaf_lds_bytes<float>((int)K));
     }
     std::vector<double> dom0(8 * RM, 0.0);
     up(P->dom, dom0.data(), dom0.size() * 8);

@@ -127,6 +127,44 @@ __device__ __forceinline__ void for_each_rho(int p, const RhoLds<T>& rc, T x, T 
     }
 }
 
+// Like for_each_rho, but only the orders m = m0, m0 + dm, ... are visited (the
+// diagonal Rh_m^m chain is still advanced for every m): lets several
+// wavefronts share one expansion evaluation.
+template <typename T, typename Fn>
+__device__ __forceinline__ void for_rho_orders(int p, const RhoLds<T>& rc, int m0, int dm, T x, T y, T z,
+                                               Fn&& fn) {
+    const T r2 = x * x + y * y + z * z;
+    T cre = T(1), cim = T(0);
+    for (int m = 0; m <= p; ++m) {
+        if (m > 0) {
+            const T fm = rc.f[m];
+            const T nre = fm * (x * cre - y * cim);
+            const T nim = fm * (x * cim + y * cre);
+            cre = nre;
+            cim = nim;
+        }
+        if (m < m0 || (m - m0) % dm != 0) continue;
+        const int k0 = (m == 0) ? 0 : 2 * m - 1;
+        fn(m * m + k0, m > 0, cre, cim);
+        if (m + 1 > p) continue;
+        T p0re = cre, p0im = cim;
+        T p1re = rc.a[(m + 1) * (kPMax + 1) + m] * z * cre;
+        T p1im = rc.a[(m + 1) * (kPMax + 1) + m] * z * cim;
+        fn((m + 1) * (m + 1) + k0, m > 0, p1re, p1im);
+        for (int l = m + 2; l <= p; ++l) {
+            const T al = rc.a[l * (kPMax + 1) + m];
+            const T bl = rc.b[l * (kPMax + 1) + m];
+            const T nre = al * z * p1re - bl * r2 * p0re;
+            const T nim = al * z * p1im - bl * r2 * p0im;
+            p0re = p1re;
+            p0im = p1im;
+            p1re = nre;
+            p1im = nim;
+            fn(l * l + k0, m > 0, p1re, p1im);
+        }
+    }
+}
+
 template <typename T>
 __device__ __forceinline__ T wave_sum(T v) {
 #pragma unroll
@@ -491,150 +529,159 @@ __device__ void lds_sort(int32_t* v, int n) {
         }
 }
 
-// Per leaf: sort the leaf's atoms by caller index (stable binning) and gather
-// (x - c_leaf, q) into the sorted particle array.
+// Per leaf, one block of 256 threads: sort the leaf's atoms by caller index
+// (stable binning), gather (x - c_leaf, q) into the sorted particle array with
+// the interpolated charge q = qA + lambda_s (qB - qA) formed in FP64, and form
+// the leaf multipole mu~_leaf = sum_j q_j rho((x_j - c_leaf) / h) (P2M).
+// P2M runs in passes of 64 atoms, the harmonic orders split over the 4
+// wavefronts: each writes its part of q rho of every atom into the atom's LDS
+// row, and thread k then sums column k in atom order.  The row buffer reuses
+// the sort buffer once the sorted indices are in registers.  Periodic: also per-leaf FP64 partial sums
+// of q |t/L|^2 and q (t relative to the cell centre).  Dynamic LDS:
+// max(kSortCap ints, 64 x (K + 1) elements of T).
+constexpr int kLeafThreads = 256;
+constexpr int kLeafIdx = kSortCap / kLeafThreads;  // sorted indices per thread
 template <typename T>
-__global__ __launch_bounds__(256) void k_leaf_sort_gather(
+__global__ __launch_bounds__(kLeafThreads) void k_leaf_p2m(
     Geo g, const RepDesc* __restrict__ reps, const T* __restrict__ x, const T* __restrict__ qA,
     const T* __restrict__ qB, const int32_t* __restrict__ site, const double* __restrict__ lam,
     const double* __restrict__ dom_all, const int32_t* __restrict__ leaf_start_all,
-    int32_t* __restrict__ perm, vec4_t<T>* __restrict__ pos, int32_t* __restrict__ status) {
-    __shared__ int32_t buf[kSortCap];
+    int32_t* __restrict__ perm, vec4_t<T>* __restrict__ pos, int32_t* __restrict__ status,
+    T* __restrict__ mult_all, double* __restrict__ leaf_part_all, uint16_t* __restrict__ msplit_all,
+    int split_kp) {
+    extern __shared__ __align__(16) unsigned char leaf_lds[];
+    __shared__ RhoLds<T> rho;
+    __shared__ double ps[2][kLeafThreads / 64];
+    int32_t* sbuf = (int32_t*)leaf_lds;
+    T* rows = (T*)leaf_lds;
     const RepDesc rd = reps[blockIdx.y];
     const int64_t n_sites = rd.S;
     lam += rd.s0;
     const double* dom = dom_all + 8 * blockIdx.y;
     const int32_t* leaf_start = leaf_start_all + (size_t)blockIdx.y * (g.nleaf + 1);
-    const int leaf = blockIdx.x;
-    const int b = leaf_start[leaf], n = leaf_start[leaf + 1] - b;
-    if (n == 0) return;
-    const bool sorted = n <= kSortCap;
-    if (sorted) {
-        for (int i = threadIdx.x; i < n; i += blockDim.x) buf[i] = perm[b + i];
-        __syncthreads();
-        lds_sort<kSortCap>(buf, n);
-    } else if (threadIdx.x == 0) {
-        atomicOr(&status[1], kInfoBigLeaf);
-    }
-    const double edge = dom[3];
-    const double h = edge / g.nb;
-    int cx, cy, cz;
-    unmorton((uint32_t)leaf, cx, cy, cz);
-    const double cc[3] = {dom[0] + (cx + 0.5) * h, dom[1] + (cy + 0.5) * h, dom[2] + (cz + 0.5) * h};
-    for (int j = threadIdx.x; j < n; j += blockDim.x) {
-        const int32_t i = sorted ? buf[j] : perm[b + j];
-        if (sorted) perm[b + j] = i;
-        double s[3];
-        for (int a = 0; a < 3; ++a) {
-            double v = (double)x[3 * i + a];
-            if (g.periodic) v -= edge * floor(v / edge);
-            s[a] = v - cc[a];
-        }
-        int32_t st = site[i];
-        double q = (double)qA[i];
-        if (st >= 0 && st < n_sites) q += lam[st] * ((double)qB[i] - (double)qA[i]);
-        vec4_t<T> o;
-        o.x = (T)s[0];
-        o.y = (T)s[1];
-        o.z = (T)s[2];
-        o.w = (T)q;
-        pos[b + j] = o;
-    }
-}
-
-// ------------------------------------------------------------------ upward pass
-
-// P2M: mu~_leaf = sum_j q_j rho((x_j - c_leaf) / h), one wavefront per leaf.
-// Each lane writes q rho of its atom as one LDS row; the coefficient sums are
-// then column sums (lane k owns coefficients k, k + 64, ...), in atom order.
-// Periodic: also per-leaf FP64 partial sums of q |t/L|^2 and q (t relative to
-// the cell centre).  Dynamic LDS: 64 x (K + 1) elements of T.
-template <typename T>
-__global__ __launch_bounds__(64) void k_p2m(Geo g, const vec4_t<T>* __restrict__ pos,
-                                            const int32_t* __restrict__ leaf_start_all,
-                                            const double* __restrict__ dom_all,
-                                            T* __restrict__ mult_all,
-                                            double* __restrict__ leaf_part_all,
-                                            uint16_t* __restrict__ msplit_all, int split_kp) {
-    extern __shared__ __align__(16) unsigned char p2m_lds[];
-    __shared__ RhoLds<T> rho;
-    const int32_t* leaf_start = leaf_start_all + (size_t)blockIdx.y * (g.nleaf + 1);
-    const double* dom = dom_all + 8 * blockIdx.y;
     T* mult = mult_all + (size_t)blockIdx.y * g.nbox * g.Kp;
     double* leaf_part = leaf_part_all + (size_t)blockIdx.y * g.nleaf * 2;
-    T* buf = (T*)p2m_lds;
-    const int S = g.K + 1;
     const int leaf = blockIdx.x;
-    const int lane = threadIdx.x;
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     const int b = leaf_start[leaf], n = leaf_start[leaf + 1] - b;
     const double edge = dom[3];
-    load_rho_lds<T, 64>(rho, g.p);  // in flight with the leaf bounds
-    __syncthreads();
+    const double dlo[3] = {dom[0], dom[1], dom[2]};
+    load_rho_lds<T, kLeafThreads>(rho, g.p);
+    const bool sorted = n <= kSortCap;
+    int32_t idx[kLeafIdx];
+    if (sorted) {
+        for (int i = tid; i < n; i += kLeafThreads) sbuf[i] = perm[b + i];
+        __syncthreads();
+        lds_sort<kSortCap>(sbuf, n);
+#pragma unroll
+        for (int m = 0; m < kLeafIdx; ++m) {
+            const int j = tid + m * kLeafThreads;
+            idx[m] = j < n ? sbuf[j] : 0;
+        }
+    } else {
+        if (tid == 0) atomicOr(&status[1], kInfoBigLeaf);
+#pragma unroll
+        for (int m = 0; m < kLeafIdx; ++m) idx[m] = 0;
+    }
+    __syncthreads();  // sorted indices are in registers: the LDS is free for P2M rows
     const double h = edge / g.nb;
     const T ih = (T)(1.0 / h);
-    double s2 = 0.0, qs = 0.0;
     int cx, cy, cz;
     unmorton((uint32_t)leaf, cx, cy, cz);
+    const double cc[3] = {dlo[0] + (cx + 0.5) * h, dlo[1] + (cy + 0.5) * h, dlo[2] + (cz + 0.5) * h};
     const double off[3] = {(cx + 0.5) * h - 0.5 * edge, (cy + 0.5) * h - 0.5 * edge,
                            (cz + 0.5) * h - 0.5 * edge};
-    T acc[kKMax / 64];
-#pragma unroll
-    for (int i = 0; i < kKMax / 64; ++i) acc[i] = T(0);
-    for (int c0 = 0; c0 < n; c0 += 64) {
-        const int j = c0 + lane;
-        vec4_t<T> a;
-        if (j < n) a = pos[b + j];
-        else { a.x = a.y = a.z = a.w = T(0); }
-        const T q = a.w;
-        if (g.periodic && j < n) {
-            double t0 = (double)a.x + off[0], t1 = (double)a.y + off[1], t2 = (double)a.z + off[2];
-            s2 += (double)q * (t0 * t0 + t1 * t1 + t2 * t2) / (edge * edge);
-            qs += (double)q;
+    // gather; this thread's first atom stays in registers for P2M
+    vec4_t<T> mine;
+    mine.x = mine.y = mine.z = mine.w = T(0);
+    double s2 = 0.0, qs = 0.0;
+    for (int j = tid, m = 0; j < n; j += kLeafThreads, ++m) {
+        const int32_t i = sorted ? (m < kLeafIdx ? idx[m] : 0) : perm[b + j];
+        if (sorted) perm[b + j] = i;
+        const double xv[3] = {(double)x[3 * i], (double)x[3 * i + 1], (double)x[3 * i + 2]};
+        const int32_t st = site[i];
+        const double a0 = (double)qA[i], b0 = (double)qB[i];
+        double sv[3];
+        for (int d = 0; d < 3; ++d) {
+            double v = xv[d];
+            if (g.periodic) v -= edge * floor(v / edge);
+            sv[d] = v - cc[d];
         }
-        T* row = buf + lane * S;
-        for_each_rho<T>(g.p, rho, a.x * ih, a.y * ih, a.z * ih, [&](int kc, bool hs, T re, T im) {
-            row[kc] = q * re;
-            if (hs) row[kc + 1] = q * im;
-        });
-        __syncthreads();
-        const int rows = min(64, n - c0);
-#pragma unroll
-        for (int i = 0; i < kKMax / 64; ++i) {
-            const int k = lane + 64 * i;
-            if (k < g.K) {
-                // four interleaved partial sums keep the LDS reads in flight
-                T v0 = T(0), v1 = T(0), v2 = T(0), v3 = T(0);
-                int r = 0;
-                for (; r + 4 <= rows; r += 4) {
-                    v0 += buf[r * S + k];
-                    v1 += buf[(r + 1) * S + k];
-                    v2 += buf[(r + 2) * S + k];
-                    v3 += buf[(r + 3) * S + k];
-                }
-                for (; r < rows; ++r) v0 += buf[r * S + k];
-                acc[i] += (v0 + v1) + (v2 + v3);
-            }
-        }
-        __syncthreads();
-    }
-    T* dst = mult + (size_t)(g.lev_off[g.depth] + leaf) * g.Kp;
-    uint16_t* msplit = msplit_all ? msplit_all + (size_t)blockIdx.y * (g.nbox + 1) * 2 * split_kp : nullptr;
-#pragma unroll
-    for (int i = 0; i < kKMax / 64; ++i) {
-        const int k = lane + 64 * i;
-        if (k < g.K) {
-            dst[k] = acc[i];
-            if constexpr (sizeof(T) == 4)
-                if (msplit) store_split(msplit, split_kp, g.lev_off[g.depth] + leaf, k, acc[i]);
+        double q = a0;
+        if (st >= 0 && st < n_sites) q += lam[st] * (b0 - a0);
+        vec4_t<T> o;
+        o.x = (T)sv[0];
+        o.y = (T)sv[1];
+        o.z = (T)sv[2];
+        o.w = (T)q;
+        pos[b + j] = o;
+        if (m == 0) mine = o;
+        if (g.periodic) {
+            const double t0 = (double)o.x + off[0], t1 = (double)o.y + off[1], t2 = (double)o.z + off[2];
+            s2 += (double)o.w * (t0 * t0 + t1 * t1 + t2 * t2) / (edge * edge);
+            qs += (double)o.w;
         }
     }
     if (g.periodic) {
         s2 = wave_sum<double>(s2);
         qs = wave_sum<double>(qs);
         if (lane == 0) {
-            leaf_part[2 * leaf] = s2;
-            leaf_part[2 * leaf + 1] = qs;
+            ps[0][wave] = s2;
+            ps[1][wave] = qs;
         }
+    }
+    __syncthreads();  // pos of every atom written (later P2M passes read it back)
+    // P2M in passes of 64 atoms (lane j of every wavefront takes atom c0 + j):
+    // wavefront w writes the orders m = w, w + 4, ... of q rho into the atom's
+    // LDS row, then thread k sums column k (one coefficient per thread, K <= 256)
+    // in atom order
+    constexpr int kWaves = kLeafThreads / 64;
+    const int S = g.K + 1;
+    T acc = T(0);
+    for (int c0 = 0; c0 < n; c0 += 64) {
+        const int j = c0 + lane;
+        vec4_t<T> a;
+        a.x = a.y = a.z = a.w = T(0);
+        if (j < n) a = (c0 == 0 && wave == 0) ? mine : pos[b + j];
+        const T q = a.w;
+        T* row = rows + lane * S;
+        for_rho_orders<T>(g.p, rho, wave, kWaves, a.x * ih, a.y * ih, a.z * ih,
+                          [&](int kc, bool hs, T re, T im) {
+                              row[kc] = q * re;
+                              if (hs) row[kc + 1] = q * im;
+                          });
+        __syncthreads();
+        const int nr = min(64, n - c0);
+        if (tid < g.K) {
+            // four interleaved partial sums keep the LDS reads in flight
+            T v0 = T(0), v1 = T(0), v2 = T(0), v3 = T(0);
+            int r = 0;
+            for (; r + 4 <= nr; r += 4) {
+                v0 += rows[r * S + tid];
+                v1 += rows[(r + 1) * S + tid];
+                v2 += rows[(r + 2) * S + tid];
+                v3 += rows[(r + 3) * S + tid];
+            }
+            for (; r < nr; ++r) v0 += rows[r * S + tid];
+            acc += (v0 + v1) + (v2 + v3);
+        }
+        __syncthreads();
+    }
+    const int64_t gb = g.lev_off[g.depth] + leaf;
+    if (tid < g.K) {
+        mult[(size_t)gb * g.Kp + tid] = acc;
+        if constexpr (sizeof(T) == 4)
+            if (msplit_all)
+                store_split(msplit_all + (size_t)blockIdx.y * (g.nbox + 1) * 2 * split_kp, split_kp, gb, tid, acc);
+    }
+    if (g.periodic && tid == 0) {
+        double a2 = 0.0, aq = 0.0;
+        for (int w = 0; w < kWaves; ++w) {
+            a2 += ps[0][w];
+            aq += ps[1][w];
+        }
+        leaf_part[2 * leaf] = a2;
+        leaf_part[2 * leaf + 1] = aq;
     }
 }
 
@@ -1522,43 +1569,6 @@ template <typename T> __device__ __forceinline__ T inv_sqrt(T v);
 template <> __device__ __forceinline__ float inv_sqrt<float>(float v) { return __builtin_amdgcn_rsqf(v); }
 template <> __device__ __forceinline__ double inv_sqrt<double>(double v) { return rsqrt(v); }
 
-// Like for_each_rho, but only the orders m = m0, m0 + dm, ... are visited (the
-// diagonal Rh_m^m chain is still advanced for every m): lets several
-// wavefronts share one expansion evaluation.
-template <typename T, typename Fn>
-__device__ __forceinline__ void for_rho_orders(int p, const RhoLds<T>& rc, int m0, int dm, T x, T y, T z,
-                                               Fn&& fn) {
-    const T r2 = x * x + y * y + z * z;
-    T cre = T(1), cim = T(0);
-    for (int m = 0; m <= p; ++m) {
-        if (m > 0) {
-            const T fm = rc.f[m];
-            const T nre = fm * (x * cre - y * cim);
-            const T nim = fm * (x * cim + y * cre);
-            cre = nre;
-            cim = nim;
-        }
-        if (m < m0 || (m - m0) % dm != 0) continue;
-        const int k0 = (m == 0) ? 0 : 2 * m - 1;
-        fn(m * m + k0, m > 0, cre, cim);
-        if (m + 1 > p) continue;
-        T p0re = cre, p0im = cim;
-        T p1re = rc.a[(m + 1) * (kPMax + 1) + m] * z * cre;
-        T p1im = rc.a[(m + 1) * (kPMax + 1) + m] * z * cim;
-        fn((m + 1) * (m + 1) + k0, m > 0, p1re, p1im);
-        for (int l = m + 2; l <= p; ++l) {
-            const T al = rc.a[l * (kPMax + 1) + m];
-            const T bl = rc.b[l * (kPMax + 1) + m];
-            const T nre = al * z * p1re - bl * r2 * p0re;
-            const T nim = al * z * p1im - bl * r2 * p0im;
-            p0re = p1re;
-            p0im = p1im;
-            p1re = nre;
-            p1im = nim;
-            fn(l * l + k0, m > 0, p1re, p1im);
-        }
-    }
-}
 
 // Per target leaf (kNW wavefronts, one lane per target): the sources of the 27
 // neighbour leaves (periodic images through integer leaf offsets) are staged
