@@ -88,7 +88,10 @@ typedef enum { FMM_FP64 = 0, FMM_MIXED_F32 = 1, FMM_MIXED_BF16X3 = 2 } fmm_preci
  *   m2l_kernel  0 = automatic, 1 = plain (vector ALU) M2L, 2 = matrix-core M2L
  *               (available for p <= 10; FP64 needs p <= 8)
  *   m2l_chunk   offsets per matrix-core M2L work-group (0 = automatic, else 1..189)
- *   p2p_waves   wavefronts per leaf in the near-field kernel: 4, 8 or 16 (0 = 8)
+ *   p2p_waves   wavefronts per near-field block: 4, 8 or 16 (0 = 8)
+ *   p2p_split   near-field blocks per leaf, 1 to 4 (0 = 1): with more than one,
+ *               block s of a leaf takes its targets 32 s .. 32 s + 31 (the last
+ *               block all the rest), so the hardware can balance uneven leaves
  *   graph       1 = record the launch sequence of an evaluation in a HIP graph on
  *               first use and replay the graph while every argument (pointers,
  *               sizes, boxes, replica offsets) is unchanged; needs a non-NULL
@@ -107,6 +110,8 @@ typedef struct {
     int32_t m2l_chunk;
     int32_t p2p_waves;
     int32_t graph;
+    int32_t p2p_split;
+    int32_t reserved_;  /* zero */
 } fmm_params;
 
 /* Create a plan on the current HIP device.  hip_stream is a hipStream_t (NULL =
@@ -202,10 +207,11 @@ fmm_status fmm_profile_select(fmm_plan_t plan, uint32_t phase_mask, int32_t ever
 /* Resolved launch configuration of a plan (host only, no GPU work):
  *   out[0] M2L kernel (0 plain, 1 FP32, 2 FP64, 3 bf16x3 matrix cores)
  *   out[1] offsets per M2L work-group   out[2] offset chunks
- *   out[3] M2L work-groups per replica  out[4] near-field wavefronts per leaf
+ *   out[3] M2L work-groups per replica  out[4] wavefronts per near-field block
  *   out[5] M2L LDS bytes per work-group out[6] device workspace bytes
- *   out[7] graph replay enabled */
-fmm_status fmm_plan_info(fmm_plan_t plan, int64_t out[8]);
+ *   out[7] graph replay enabled         out[8] near-field blocks per leaf
+ *   out[9] zero (reserved) */
+fmm_status fmm_plan_info(fmm_plan_t plan, int64_t out[10]);
 
 /* Host-only access to the FP64 operator tables a plan of order p uploads; no
  * GPU is touched.  which: 0 = M2L bank (343 x K x K), 1 = M2M (8 x K x K),

@@ -53,7 +53,8 @@ struct fmm_plan_s {
     hipGraphExec_t graph_exec = nullptr;
     int R_max = 1;
     // matrix-core M2L
-    int p2p_waves = 8;  // wavefronts per leaf in the near-field kernel (4, 8 or 16)
+    int p2p_waves = 8;  // wavefronts per near-field block (4, 8 or 16)
+    int p2p_split = 1;  // near-field blocks per leaf (1 to 4)
     int m2l_mode = 0;  // 0 plain, 1 f32, 2 f64, 3 bf16x3
     fmmk::M2LGeom mg{};
     int m2l_rt = 0;
@@ -390,9 +391,9 @@ fmm_status enqueue_eval(fmm_plan_t P, const std::vector<fmmk::RepDesc>& rd, cons
     switch (P->p2p_waves) {
 #define FMM_NEAR(NWV)                                                                            \
     case NWV:                                                                                    \
-        k_near_far<T, NWV><<<lg, 64 * NWV, 0, st>>>(g, reps, pos, P->leaf_start, P->perm, P->dom, \
-                                                    loc, P->gidx, (const T*)P->gcoef, qA, qB, site, \
-                                                    phi, F, P->leaf_energy, P->cphi);              \
+        k_near_far<T, NWV><<<dim3(g.nleaf * P->p2p_split, R), 64 * NWV, 0, st>>>(               \
+            g, P->p2p_split, reps, pos, P->leaf_start, P->perm, P->dom, loc, P->gidx,              \
+            (const T*)P->gcoef, qA, qB, site, phi, F, P->leaf_energy, P->cphi);                    \
         break;
         FMM_NEAR(4)
         FMM_NEAR(8)
@@ -400,7 +401,8 @@ fmm_status enqueue_eval(fmm_plan_t P, const std::vector<fmmk::RepDesc>& rd, cons
         default: break;
     }
     mark(P, 7);
-    k_reduce<<<(unsigned)(R + S_tot), 256, 0, st>>>(g, R, P->leaf_energy, P->site_start,
+    k_reduce<<<(unsigned)(R + S_tot), 256, 0, st>>>(g, R, g.nleaf * P->p2p_split, P->leaf_energy,
+                                                    P->site_start,
                                                     P->site_members, P->cphi, E, dVdl, P->status);
     mark(P, -1);
     hipError_t e = hipGetLastError();
@@ -516,7 +518,8 @@ fmm_status fmm_plan_create(const fmm_params* prm, void* hip_stream, fmm_plan_t* 
         !std::isfinite(prm->coulomb_k) || prm->max_atoms > INT32_MAX ||
         prm->m2l_kernel < 0 || prm->m2l_kernel > 2 || prm->m2l_chunk < 0 || prm->m2l_chunk > 189 ||
         (prm->p2p_waves != 0 && prm->p2p_waves != 4 && prm->p2p_waves != 8 &&
-         prm->p2p_waves != 16) || prm->graph < 0 || prm->graph > 1)
+         prm->p2p_waves != 16) || prm->graph < 0 || prm->graph > 1 || prm->p2p_split < 0 ||
+        prm->p2p_split > fmmk::kMaxSplit || prm->reserved_ != 0)
         return FMM_E_INVALID;
     {
         const int K = (prm->order_p + 1) * (prm->order_p + 1);
@@ -532,6 +535,7 @@ fmm_status fmm_plan_create(const fmm_params* prm, void* hip_stream, fmm_plan_t* 
     }
     P->fp64 = prm->precision == FMM_FP64;
     P->p2p_waves = prm->p2p_waves ? prm->p2p_waves : 8;
+    P->p2p_split = prm->p2p_split ? prm->p2p_split : 1;
     P->tsz = P->fp64 ? 8 : 4;
     const int p = prm->order_p, d = prm->depth;
     P->K = (p + 1) * (p + 1);
@@ -578,7 +582,7 @@ fmm_status fmm_plan_create(const fmm_params* prm, void* hip_stream, fmm_plan_t* 
     ok &= dev_alloc(P, (void**)&P->bbox_part, RM * kBboxBlocks * 6 * 8);
     ok &= dev_alloc(P, (void**)&P->leaf_part, RM * P->nleaf * 2 * 8);
     ok &= dev_alloc(P, (void**)&P->box_part, RM * P->nbox * 2 * 8);
-    ok &= dev_alloc(P, (void**)&P->leaf_energy, RM * P->nleaf * 8);
+    ok &= dev_alloc(P, (void**)&P->leaf_energy, RM * P->nleaf * fmmk::kMaxSplit * 8);
     ok &= dev_alloc(P, (void**)&P->reps, RM * sizeof(fmmk::RepDesc));
     ok &= dev_alloc(P, (void**)&P->cphi, N * 8);
     ok &= dev_alloc(P, (void**)&P->status, 4 * 4);
@@ -1005,7 +1009,7 @@ fmm_status fmm_profile_select(fmm_plan_t P, uint32_t phase_mask, int32_t every) 
     return FMM_OK;
 }
 
-fmm_status fmm_plan_info(fmm_plan_t P, int64_t out[8]) {
+fmm_status fmm_plan_info(fmm_plan_t P, int64_t out[10]) {
     if (!P || !out) return FMM_E_INVALID;
     out[0] = P->m2l_mode;
     out[1] = P->m2l_mode ? P->mg.csize : 0;
@@ -1015,6 +1019,8 @@ fmm_status fmm_plan_info(fmm_plan_t P, int64_t out[8]) {
     out[5] = (int64_t)P->m2l_lds;
     out[6] = (int64_t)P->ws_bytes;
     out[7] = P->prm.graph;
+    out[8] = P->p2p_split;
+    out[9] = 0;
     return FMM_OK;
 }
 

@@ -11,6 +11,7 @@ constexpr int kKMax = (kPMax + 1) * (kPMax + 1);  // 256 coefficients
 constexpr int kKgMax = kPMax * kPMax;       // gradient coefficients (order p-1)
 constexpr int kSortCap = 4096;              // largest leaf sorted in LDS
 constexpr int kSiteCap = 1024;              // largest site sorted in LDS
+constexpr int kMaxSplit = 4;                // near-field blocks per leaf, at most
 constexpr int kScanFuseCap = 4096;          // leaf / site counts scanned inside the scatter kernel
 constexpr double kPi = 3.14159265358979323846;
 

@@ -1579,7 +1579,7 @@ template <> __device__ __forceinline__ double inv_sqrt<double>(double v) { retur
 // force, the per-leaf energy partial and (qB - qA) phi for the site sums.
 template <typename T, int kNW>
 __global__ __launch_bounds__(64 * kNW) void k_near_far(
-    Geo g, const RepDesc* __restrict__ reps, const vec4_t<T>* __restrict__ pos,
+    Geo g, int nsplit, const RepDesc* __restrict__ reps, const vec4_t<T>* __restrict__ pos,
     const int32_t* __restrict__ leaf_start_all, const int32_t* __restrict__ perm,
     const double* __restrict__ dom_all, const T* __restrict__ loc_all,
     const int32_t* __restrict__ gidx, const T* __restrict__ gcoef,
@@ -1593,7 +1593,7 @@ __global__ __launch_bounds__(64 * kNW) void k_near_far(
     const int32_t* leaf_start = leaf_start_all + (size_t)blockIdx.y * (g.nleaf + 1);
     const double* dom = dom_all + 8 * blockIdx.y;
     const T* loc = loc_all + (size_t)blockIdx.y * g.nbox * g.Kp;
-    double* leaf_energy = leaf_energy_all + (size_t)blockIdx.y * g.nleaf;
+    double* leaf_energy = leaf_energy_all + (size_t)blockIdx.y * g.nleaf * nsplit;
     __shared__ vec4_t<T> tile[CAP];
     __shared__ int nb_start[28], nb_cnt[28], nb_pre[29];
     __shared__ T nb_off[27][3];
@@ -1603,13 +1603,35 @@ __global__ __launch_bounds__(64 * kNW) void k_near_far(
     load_rho_lds<T, 64 * kNW>(rho, g.p);
     __shared__ T part[kNW][4][64];
     __shared__ double esum_part[kNW][64];
-    const int leaf = blockIdx.x;
+    __shared__ int32_t t_idx[NT], t_site[NT];
+    __shared__ double t_dq[NT];
+    // block `sub` of the leaf takes targets 32 sub .. 32 sub + 31 (the last
+    // block of the leaf all the rest); one block per leaf takes them all
+    const int leaf = blockIdx.x / nsplit, sub = blockIdx.x - leaf * nsplit;
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-    const int tb = leaf_start[leaf], tn = leaf_start[leaf + 1] - tb;
-    if (tn == 0) {
-        if (tid == 0) leaf_energy[leaf] = 0.0;
+    const int lb = leaf_start[leaf], ln = leaf_start[leaf + 1] - lb;
+    const int ta = 32 * sub;
+    const int tb = lb + ta, tn = sub + 1 == nsplit ? ln - ta : min(32, ln - ta);
+    if (tn <= 0) {
+        if (tid == 0) leaf_energy[blockIdx.x] = 0.0;
         return;
     }
+    const bool far = g.has_far;
+    // loads issued up front, in flight with the neighbour set-up: the gradient
+    // table entries of this thread and, for the first NT targets, the caller
+    // index, site and qB - qA needed by the outputs
+    const bool ge = far && tid < 3 * g.Kg;
+    int32_t gi4[4];
+    T gc4[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+        gi4[t] = ge ? gidx[(size_t)tid * 4 + t] : -1;
+        gc4[t] = ge ? gcoef[(size_t)tid * 4 + t] : T(0);
+    }
+    const bool tpre = tid < tn;
+    const int32_t pre_i = tpre ? perm[tb + tid] : 0;
+    const int32_t pre_s = tpre ? site[pre_i] : -1;
+    const double pre_dq = tpre ? (double)qB[pre_i] - (double)qA[pre_i] : 0.0;
     const double edge = dom[3];
     const double h = edge / g.nb;
     int cx, cy, cz;
@@ -1637,7 +1659,6 @@ __global__ __launch_bounds__(64 * kNW) void k_near_far(
         nb_off[tid][1] = (T)(dy * h);
         nb_off[tid][2] = (T)(dz * h);
     }
-    const bool far = g.has_far;
     if (far) {
         const T* lsrc = loc + (size_t)(g.lev_off[g.depth] + leaf) * g.Kp;
         for (int k = tid; k < g.K; k += NT) lam[k] = lsrc[k];
@@ -1649,15 +1670,27 @@ __global__ __launch_bounds__(64 * kNW) void k_near_far(
         nb_pre[28] = 0x7fffffff;
     }
     if (far) {
-        for (int e = tid; e < 3 * g.Kg; e += NT) {
+        if (ge) {
+            T v = T(0);
+#pragma unroll
+            for (int t = 0; t < 4; ++t)
+                if (gi4[t] >= 0) v += gc4[t] * lam[gi4[t]];
+            gr[tid / g.Kg][tid % g.Kg] = v;
+        }
+        for (int e = tid + NT; e < 3 * g.Kg; e += NT) {  // orders p > 13 only
             const int a = e / g.Kg, r = e % g.Kg;
             T v = T(0);
             for (int t = 0; t < 4; ++t) {
-                const int k = gidx[(size_t)e * 4 + t];
-                if (k >= 0) v += gcoef[(size_t)e * 4 + t] * lam[k];
+                const int kk = gidx[(size_t)e * 4 + t];
+                if (kk >= 0) v += gcoef[(size_t)e * 4 + t] * lam[kk];
             }
             gr[a][r] = v;
         }
+    }
+    if (tpre) {
+        t_idx[tid] = pre_i;
+        t_site[tid] = pre_s;
+        t_dq[tid] = pre_dq;
     }
     __syncthreads();
     const int total = nb_pre[27];
@@ -1709,31 +1742,65 @@ __global__ __launch_bounds__(64 * kNW) void k_near_far(
         for (int s0 = 0; s0 < total; s0 += CAP) {
             const int cnt = min(CAP, total - s0);
             __syncthreads();
-            // stage the pass's sources, CAP / NT loads in flight per thread
-            constexpr int G = CAP / NT;
-            vec4_t<T> a[G];
-            int lo_[G];
+            if (total <= CAP) {
+                // the whole neighbourhood in one pass: wavefront w copies
+                // neighbours w, w + kNW, ..., lane j their atom j (all loads
+                // in flight together), larger neighbours in extra rounds
+                constexpr int J = (27 + kNW - 1) / kNW;
+                vec4_t<T> a[J];
 #pragma unroll
-            for (int m = 0; m < G; ++m) {
-                const int gsrc = s0 + min(tid + m * NT, cnt - 1);
-                // neighbour holding source gsrc: largest i with nb_pre[i] <= gsrc
-                int lo = 0, hi = 27;
-                while (hi - lo > 1) {
-                    const int mid = (lo + hi) >> 1;
-                    if (nb_pre[mid] <= gsrc) lo = mid;
-                    else hi = mid;
+                for (int m = 0; m < J; ++m) {
+                    const int nbk = min(wave + kNW * m, 26);
+                    // an empty neighbour reads entry 0 (never stored)
+                    const int c = nb_cnt[nbk];
+                    a[m] = pos[c > 0 ? nb_start[nbk] + min(lane, c - 1) : 0];
                 }
-                lo_[m] = lo;
-                a[m] = pos[nb_start[lo] + (gsrc - nb_pre[lo])];
-            }
 #pragma unroll
-            for (int m = 0; m < G; ++m) {
-                if (tid + m * NT < cnt) {
-                    vec4_t<T> v = a[m];
-                    v.x += nb_off[lo_[m]][0];
-                    v.y += nb_off[lo_[m]][1];
-                    v.z += nb_off[lo_[m]][2];
-                    tile[tid + m * NT] = v;
+                for (int m = 0; m < J; ++m) {
+                    const int nbk = wave + kNW * m;
+                    if (nbk < 27 && lane < nb_cnt[nbk]) {
+                        vec4_t<T> v = a[m];
+                        v.x += nb_off[nbk][0];
+                        v.y += nb_off[nbk][1];
+                        v.z += nb_off[nbk][2];
+                        tile[nb_pre[nbk] + lane] = v;
+                    }
+                }
+                for (int nbk = wave; nbk < 27; nbk += kNW)
+                    for (int j = 64 + lane; j < nb_cnt[nbk]; j += 64) {
+                        vec4_t<T> v = pos[nb_start[nbk] + j];
+                        v.x += nb_off[nbk][0];
+                        v.y += nb_off[nbk][1];
+                        v.z += nb_off[nbk][2];
+                        tile[nb_pre[nbk] + j] = v;
+                    }
+            } else {
+                // stage the pass's sources, CAP / NT loads in flight per thread
+                constexpr int G = CAP / NT;
+                vec4_t<T> a[G];
+                int lo_[G];
+#pragma unroll
+                for (int m = 0; m < G; ++m) {
+                    const int gsrc = s0 + min(tid + m * NT, cnt - 1);
+                    // neighbour holding source gsrc: largest i with nb_pre[i] <= gsrc
+                    int lo = 0, hi = 27;
+                    while (hi - lo > 1) {
+                        const int mid = (lo + hi) >> 1;
+                        if (nb_pre[mid] <= gsrc) lo = mid;
+                        else hi = mid;
+                    }
+                    lo_[m] = lo;
+                    a[m] = pos[nb_start[lo] + (gsrc - nb_pre[lo])];
+                }
+#pragma unroll
+                for (int m = 0; m < G; ++m) {
+                    if (tid + m * NT < cnt) {
+                        vec4_t<T> v = a[m];
+                        v.x += nb_off[lo_[m]][0];
+                        v.y += nb_off[lo_[m]][1];
+                        v.z += nb_off[lo_[m]][2];
+                        tile[tid + m * NT] = v;
+                    }
                 }
             }
             __syncthreads();
@@ -1826,7 +1893,8 @@ __global__ __launch_bounds__(64 * kNW) void k_near_far(
                 ey -= (T)(4.0 * kPi / 3.0 * Q * t1v / V);
                 ez -= (T)(4.0 * kPi / 3.0 * Q * t2v / V);
             }
-            const int32_t i = perm[tb + tj];
+            const bool pre = tj < NT;  // prefetched at the start
+            const int32_t i = pre ? t_idx[tj] : perm[tb + tj];
             const T q = me.w;
             const T ke = (T)g.coulomb_k;
             if (phi_out) phi_out[i] = ke * p;
@@ -1837,9 +1905,11 @@ __global__ __launch_bounds__(64 * kNW) void k_near_far(
             }
             const double qp = (double)q * (double)p;
             esum_part[wave][lane] = qp;
-            const int32_t st = site[i];
-            if (st >= 0 && st < n_sites)
-                cphi[i] = g.coulomb_k * ((double)qB[i] - (double)qA[i]) * (double)p;
+            const int32_t st = pre ? t_site[tj] : site[i];
+            if (st >= 0 && st < n_sites) {
+                const double dq = pre ? t_dq[tj] : (double)qB[i] - (double)qA[i];
+                cphi[i] = g.coulomb_k * dq * (double)p;
+            }
         } else if (slice == 0) {
             esum_part[wave][lane] = 0.0;
         }
@@ -1853,14 +1923,15 @@ __global__ __launch_bounds__(64 * kNW) void k_near_far(
     }
     if (wave == 0) {
         esum = wave_sum<double>(esum);
-        if (lane == 0) leaf_energy[leaf] = esum;
+        if (lane == 0) leaf_energy[blockIdx.x] = esum;
     }
 }
 
 // Final reductions: block r < R -> E_r = k_e / 2 sum of replica r's leaf
 // partials (fixed order); block R + s -> dVdl_s = sum over global site s's
 // atoms in caller order.
-__global__ __launch_bounds__(256) void k_reduce(Geo g, int R, const double* __restrict__ leaf_energy,
+__global__ __launch_bounds__(256) void k_reduce(Geo g, int R, int64_t nparts,
+                                                const double* __restrict__ leaf_energy,
                                                 const int32_t* __restrict__ site_start,
                                                 const int32_t* __restrict__ site_members,
                                                 const double* __restrict__ cphi,
@@ -1872,7 +1943,7 @@ __global__ __launch_bounds__(256) void k_reduce(Geo g, int R, const double* __re
     const int b = blockIdx.x;
     double v = 0.0;
     if (b < R) {
-        for (int i = t; i < g.nleaf; i += 256) v += leaf_energy[(size_t)b * g.nleaf + i];
+        for (int64_t i = t; i < nparts; i += 256) v += leaf_energy[(size_t)b * nparts + i];
     } else {
         const int s = b - R;
         const int m0 = site_start[s], n = site_start[s + 1] - m0;

@@ -48,6 +48,8 @@ class fmm_params(ctypes.Structure):
         ("m2l_chunk", ctypes.c_int32),
         ("p2p_waves", ctypes.c_int32),
         ("graph", ctypes.c_int32),
+        ("p2p_split", ctypes.c_int32),
+        ("reserved_", ctypes.c_int32),
     ]
 
 
@@ -184,7 +186,7 @@ class Plan:
                  precision: str = "fp64", coulomb_k: float = 1.0, max_atoms: int = 1,
                  max_sites: int = 1, max_replicas: int = 1, check: bool = False,
                  stream=None, device=None, m2l_kernel: int = 0, m2l_chunk: int = 0,
-                 p2p_waves: int = 0, graph: bool = False):
+                 p2p_waves: int = 0, graph: bool = False, p2p_split: int = 0):
         import torch
         dev = torch.device(device) if device is not None else torch.device("cuda")
         if dev.type == "cuda" and dev.index is None:
@@ -197,7 +199,7 @@ class Plan:
                                  PRECISIONS[precision], float(coulomb_k), int(max_atoms),
                                  int(max_sites), int(max_replicas), 1 if check else 0,
                                  int(m2l_kernel), int(m2l_chunk), int(p2p_waves),
-                                 1 if graph else 0)
+                                 1 if graph else 0, int(p2p_split), 0)
         self.periodic = periodic
         self.precision = precision
         self.dtype = torch.float64 if precision == "fp64" else torch.float32
@@ -333,11 +335,11 @@ class Plan:
 
     def info(self):
         """Resolved launch configuration of the plan (see fmm_plan_info)."""
-        out = (ctypes.c_int64 * 8)()
+        out = (ctypes.c_int64 * 10)()
         self._raise(load_library().fmm_plan_info(self.handle, ctypes.cast(out, ctypes.c_void_p)),
                     "fmm_plan_info")
         keys = ["m2l_kernel", "m2l_chunk", "m2l_chunks", "m2l_workgroups", "p2p_waves",
-                "m2l_lds_bytes", "workspace_bytes", "graph"]
+                "m2l_lds_bytes", "workspace_bytes", "graph", "p2p_split"]
         return dict(zip(keys, list(out)))
 
     def m2l_kernel_mode(self):

@@ -231,6 +231,20 @@ def test_near_field_wave_count_invariant(waves):
     np.testing.assert_allclose(b["F"], a["F"], rtol=1e-11, atol=1e-11 * np.abs(a["F"]).max())
 
 
+@pytest.mark.parametrize("waves,split", [(4, 2), (4, 4), (8, 3), (16, 4)])
+def test_near_field_split_invariant(waves, split):
+    """Several near-field blocks per leaf (targets in windows of 32) only regroup
+    the near-field sums; leaves here hold 60-92 atoms, so windows of every kind
+    (full, remainder, empty) occur."""
+    d = W.tiny_periodic(37, n=5000, edge=2.0, n_sites=3, depth=2, order=6)
+    a = run(d, "fp64", p2p_waves=8, p2p_split=1)
+    b = run(d, "fp64", p2p_waves=waves, p2p_split=split)
+    np.testing.assert_allclose(b["phi"], a["phi"], rtol=1e-12, atol=1e-12 * np.abs(a["phi"]).max())
+    np.testing.assert_allclose(b["F"], a["F"], rtol=1e-11, atol=1e-11 * np.abs(a["F"]).max())
+    assert abs(b["E"] - a["E"]) <= 1e-12 * abs(a["E"])
+    np.testing.assert_allclose(b["dVdl"], a["dVdl"], rtol=1e-12, atol=1e-12 * np.abs(a["dVdl"]).max())
+
+
 def test_autotuner_picks_valid_shapes(tmp_path):
     import torch
     from paper_2410_01626_amd import autotune, fmm

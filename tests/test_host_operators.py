@@ -31,8 +31,8 @@ def test_library_exports_every_declared_symbol():
 
 
 def test_params_struct_layout():
-    # int32 x4, double, int64 x2, int32 x6 -> 64 bytes with natural alignment
-    assert ctypes.sizeof(fmm.fmm_params) == 64
+    # int32 x4, double, int64 x2, int32 x8 -> 72 bytes with natural alignment
+    assert ctypes.sizeof(fmm.fmm_params) == 72
     assert fmm.fmm_params.coulomb_k.offset == 16
     assert fmm.fmm_params.max_atoms.offset == 24
 
@@ -43,7 +43,8 @@ def test_plan_create_rejects_bad_params_without_gpu():
     for bad in (dict(depth=-1), dict(depth=7), dict(order_p=0), dict(order_p=16),
                 dict(boundary=2), dict(precision=3), dict(max_replicas=0),
                 dict(max_atoms=-5), dict(coulomb_k=float("nan")), dict(m2l_kernel=3),
-                dict(m2l_chunk=190), dict(graph=2), dict(p2p_waves=5), dict(order_p=11, m2l_kernel=2),
+                dict(m2l_chunk=190), dict(graph=2), dict(p2p_waves=5), dict(p2p_split=5),
+                dict(p2p_split=-1), dict(reserved_=1), dict(order_p=11, m2l_kernel=2),
                 dict(order_p=9, precision=0, m2l_kernel=2)):
         kw = dict(depth=2, order_p=4, boundary=0, precision=0, coulomb_k=1.0,
                   max_atoms=10, max_sites=1, max_replicas=1, check=0, m2l_kernel=0,
