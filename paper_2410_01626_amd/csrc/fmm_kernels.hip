@@ -135,6 +135,7 @@ __device__ __forceinline__ void for_rho_orders(int p, const RhoLds<T>& rc, int m
                                                Fn&& fn) {
     const T r2 = x * x + y * y + z * z;
     T cre = T(1), cim = T(0);
+    int next = m0;  // next order to visit (no integer division in the loop)
     for (int m = 0; m <= p; ++m) {
         if (m > 0) {
             const T fm = rc.f[m];
@@ -143,7 +144,8 @@ __device__ __forceinline__ void for_rho_orders(int p, const RhoLds<T>& rc, int m
             cre = nre;
             cim = nim;
         }
-        if (m < m0 || (m - m0) % dm != 0) continue;
+        if (m != next) continue;
+        next += dm;
         const int k0 = (m == 0) ? 0 : 2 * m - 1;
         fn(m * m + k0, m > 0, cre, cim);
         if (m + 1 > p) continue;
@@ -1636,6 +1638,7 @@ __global__ __launch_bounds__(64 * kNW) void k_near_far(
     const double h = edge / g.nb;
     int cx, cy, cz;
     unmorton((uint32_t)leaf, cx, cy, cz);
+    int my_cnt = 0;
     if (tid < 27) {
         const int dx = tid / 9 - 1, dy = (tid / 3) % 3 - 1, dz = tid % 3 - 1;
         int nx = cx + dx, ny = cy + dy, nz = cz + dz;
@@ -1655,20 +1658,30 @@ __global__ __launch_bounds__(64 * kNW) void k_near_far(
         }
         nb_start[tid] = s;
         nb_cnt[tid] = c;
+        my_cnt = c;
         nb_off[tid][0] = (T)(dx * h);
         nb_off[tid][1] = (T)(dy * h);
         nb_off[tid][2] = (T)(dz * h);
+    }
+    if (wave == 0) {
+        // inclusive scan of the 27 counts across lanes (shuffles, in registers)
+        int v = my_cnt;
+#pragma unroll
+        for (int off = 1; off < 32; off <<= 1) {
+            const int u = __shfl_up(v, off, 64);
+            if (lane >= off) v += u;
+        }
+        if (lane < 27) nb_pre[lane + 1] = v;
+        if (lane == 0) {
+            nb_pre[0] = 0;
+            nb_pre[28] = 0x7fffffff;
+        }
     }
     if (far) {
         const T* lsrc = loc + (size_t)(g.lev_off[g.depth] + leaf) * g.Kp;
         for (int k = tid; k < g.K; k += NT) lam[k] = lsrc[k];
     }
     __syncthreads();
-    if (tid == 0) {
-        nb_pre[0] = 0;
-        for (int i = 0; i < 27; ++i) nb_pre[i + 1] = nb_pre[i] + nb_cnt[i];
-        nb_pre[28] = 0x7fffffff;
-    }
     if (far) {
         if (ge) {
             T v = T(0);
