@@ -171,6 +171,33 @@ fmm_status fmm_eval_batched(fmm_plan_t plan, int32_t R, const int64_t* atom_off,
                             const double* lambda, const double* boxes, double* E,
                             void* F, void* phi, double* dVdl);
 
+/* Four-form sites (protonation tautomers; Methods, eq 2, in charge-
+ * interpolated form).  Every site s carries two coordinates, lambda_p[s]
+ * (protonation) and lambda_t[s] (tautomer), and its atoms carry four charge
+ * forms A, B, C, D; with u~ := 1 - u,
+ *   q_i = lp~ (lt~ qA_i + lt qB_i) + lp (lt~ qC_i + lt qD_i)   (s(i) >= 0)
+ *   q_i = qA_i                                                 (s(i) = -1)
+ * and the two site derivatives of V = E are
+ *   dVdl_p[s] = sum_{i in s} phi_i (lt~ (qC_i - qA_i) + lt (qD_i - qB_i))
+ *   dVdl_t[s] = sum_{i in s} phi_i (lp~ (qB_i - qA_i) + lp (qD_i - qC_i))
+ * (phi including k_e).  A site without tautomers is qB = qA and qD = qC: then
+ * q and dVdl_p are those of fmm_eval with forms (qA, qC) and lambda_p, and
+ * dVdl_t = 0.  qC and qD have the type of qA; lambda_t has S doubles; dVdl_t
+ * receives S doubles (either derivative pointer may be NULL).  Everything else
+ * (arguments, ownership, errors, asynchrony) is as in fmm_eval and
+ * fmm_eval_batched. */
+fmm_status fmm_eval_tautomer(fmm_plan_t plan, int64_t n, const void* x, const void* qA,
+                             const void* qB, const void* qC, const void* qD,
+                             const int32_t* site, int64_t n_sites, const double* lambda_p,
+                             const double* lambda_t, const double* box, double* E, void* F,
+                             void* phi, double* dVdl_p, double* dVdl_t);
+fmm_status fmm_eval_tautomer_batched(fmm_plan_t plan, int32_t R, const int64_t* atom_off,
+                                     const int64_t* site_off, const void* x, const void* qA,
+                                     const void* qB, const void* qC, const void* qD,
+                                     const int32_t* site_local, const double* lambda_p,
+                                     const double* lambda_t, const double* boxes, double* E,
+                                     void* F, void* phi, double* dVdl_p, double* dVdl_t);
+
 /* Wait for the plan's stream and report device-side check flags raised since
  * the previous call (FMM_E_NONFINITE, FMM_E_SITE), or FMM_E_HIP. */
 fmm_status fmm_sync_check(fmm_plan_t plan);

@@ -74,6 +74,13 @@ def _load():
                                 ctypes.c_int64, _f64p, _f64p, ctypes.c_double,
                                 ctypes.POINTER(ctypes.c_double), ctypes.c_void_p,
                                 ctypes.c_void_p]
+    lib.orc_tautomer_charges.restype = ctypes.c_int
+    lib.orc_tautomer_charges.argtypes = [ctypes.c_int64, _f64p, _f64p, _f64p, _f64p, _i32p,
+                                         ctypes.c_int64, _f64p, _f64p, _f64p]
+    lib.orc_tautomer_dvdl.restype = ctypes.c_int
+    lib.orc_tautomer_dvdl.argtypes = [ctypes.c_int64, _f64p, _f64p, _f64p, _f64p, _i32p,
+                                      ctypes.c_int64, _f64p, _f64p, _f64p, ctypes.c_double,
+                                      _f64p, _f64p]
     _lib = lib
     return lib
 
@@ -186,3 +193,39 @@ def solve(x, qA, qB, site, lam, box=None, periodic=False, k_e=1.0, eps=1e-13,
         phi, field = direct(x, q)
     E, F, dVdl = outputs(q, qA, qB, site, lam.size, phi, field, k_e)
     return {"E": E, "F": F, "phi": k_e * phi, "dVdl": dVdl, "q": q}
+
+
+def tautomer_charges(qA, qB, qC, qD, site, lam_p, lam_t):
+    """eq 2 in charge-interpolated form: q = lp~ (lt~ qA + lt qB) + lp (lt~ qC + lt qD)."""
+    qA, qB, qC, qD = _f64(qA), _f64(qB), _f64(qC), _f64(qD)
+    lam_p, lam_t = _f64(np.atleast_1d(lam_p)), _f64(np.atleast_1d(lam_t))
+    if lam_p.size != lam_t.size:
+        raise ValueError("lambda_p and lambda_t must have one value per site")
+    site = np.ascontiguousarray(site, dtype=np.int32)
+    q = np.empty_like(qA)
+    rc = _load().orc_tautomer_charges(qA.size, qA, qB, qC, qD, site, lam_p.size, lam_p, lam_t, q)
+    if rc != 0:
+        raise ValueError("site index outside [-1, n_sites)")
+    return q
+
+
+def solve_tautomer(x, qA, qB, qC, qD, site, lam_p, lam_t, box=None, periodic=False, k_e=1.0,
+                   eps=1e-13, ewald_kw=None):
+    """Full four-form oracle solve (Methods, eq 2).  Returns dict(E, F, phi,
+    dVdl_p, dVdl_t, q), all FP64; phi includes k_e."""
+    lam_p, lam_t = _f64(np.atleast_1d(lam_p)), _f64(np.atleast_1d(lam_t))
+    q = tautomer_charges(qA, qB, qC, qD, site, lam_p, lam_t)
+    if periodic:
+        phi, field = ewald(x, q, box, eps=eps, **(ewald_kw or {}))
+    else:
+        phi, field = direct(x, q)
+    site = np.ascontiguousarray(site, dtype=np.int32)
+    # E and F from the generic outputs (their site sums are not used here)
+    E, F, _ = outputs(q, q, q, site, lam_p.size, phi, field, k_e)
+    dp = np.empty(lam_p.size)
+    dt = np.empty(lam_p.size)
+    rc = _load().orc_tautomer_dvdl(q.size, _f64(qA), _f64(qB), _f64(qC), _f64(qD), site,
+                                   lam_p.size, lam_p, lam_t, _f64(phi), float(k_e), dp, dt)
+    if rc != 0:
+        raise ValueError("site index outside [-1, n_sites)")
+    return {"E": E, "F": F, "phi": k_e * phi, "dVdl_p": dp, "dVdl_t": dt, "q": q}

@@ -279,3 +279,53 @@ int orc_outputs(int64_t n, const double* q, const double* qA, const double* qB,
     free(d);
     return 0;
 }
+
+/* Four charge forms per site (protonation tautomers; Methods, eq 2, where the
+ * Hamiltonian is interpolated bilinearly between forms A, B, C, D by the
+ * protonation coordinate lambda_p and the tautomer coordinate lambda_t; here
+ * in charge-interpolated form, as eq 1 above).  With u~ = 1 - u:
+ *   q_i = lp~ (lt~ qA_i + lt qB_i) + lp (lt~ qC_i + lt qD_i)    (q_i = qA_i if s(i) = -1)
+ * Returns 0, or -1 if a site index lies outside [-1, nsites). */
+int orc_tautomer_charges(int64_t n, const double* qA, const double* qB, const double* qC,
+                         const double* qD, const int32_t* site, int64_t nsites,
+                         const double* lp, const double* lt, double* q) {
+    for (int64_t i = 0; i < n; ++i) {
+        int32_t s = site ? site[i] : -1;
+        if (s < -1 || s >= nsites) return -1;
+        if (s < 0) {
+            q[i] = qA[i];
+        } else {
+            const double p = lp[s], t = lt[s];
+            q[i] = (1.0 - p) * ((1.0 - t) * qA[i] + t * qB[i]) + p * ((1.0 - t) * qC[i] + t * qD[i]);
+        }
+    }
+    return 0;
+}
+
+/* The two site derivatives of the four-form energy: q_i is bilinear in
+ * (lambda_p, lambda_t), so with phi including k_e
+ *   dV/dlambda_p[s] = k_e sum_{i in s} phi_i (dq_i/dlambda_p)
+ *                   = k_e sum_{i in s} phi_i (lt~ (qC_i - qA_i) + lt (qD_i - qB_i))
+ *   dV/dlambda_t[s] = k_e sum_{i in s} phi_i (lp~ (qB_i - qA_i) + lp (qD_i - qC_i))
+ * (phi here without k_e, as orc_outputs).  Returns 0, or -1 on a bad site. */
+int orc_tautomer_dvdl(int64_t n, const double* qA, const double* qB, const double* qC,
+                      const double* qD, const int32_t* site, int64_t nsites, const double* lp,
+                      const double* lt, const double* phi, double k_e, double* dVdlp,
+                      double* dVdlt) {
+    acc_t* d = (acc_t*)calloc((size_t)(2 * (nsites > 0 ? nsites : 1)), sizeof(acc_t));
+    if (!d) return -1;
+    for (int64_t i = 0; i < n; ++i) {
+        int32_t s = site ? site[i] : -1;
+        if (s < -1 || s >= nsites) { free(d); return -1; }
+        if (s < 0) continue;
+        const double p = lp[s], t = lt[s];
+        acc_add(&d[2 * s], phi[i] * ((1.0 - t) * (qC[i] - qA[i]) + t * (qD[i] - qB[i])));
+        acc_add(&d[2 * s + 1], phi[i] * ((1.0 - p) * (qB[i] - qA[i]) + p * (qD[i] - qC[i])));
+    }
+    for (int64_t s = 0; s < nsites; ++s) {
+        dVdlp[s] = k_e * acc_get(&d[2 * s]);
+        dVdlt[s] = k_e * acc_get(&d[2 * s + 1]);
+    }
+    free(d);
+    return 0;
+}

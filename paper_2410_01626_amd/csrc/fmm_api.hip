@@ -301,7 +301,9 @@ void launch_m2l_mma(fmm_plan_t P, const Geo& g, int R) {
 template <typename T>
 fmm_status enqueue_eval(fmm_plan_t P, const std::vector<fmmk::RepDesc>& rd, const T* x,
                         const T* qA, const T* qB, const int32_t* site, const double* lam,
-                        double* E, T* F, T* phi, double* dVdl) {
+                        double* E, T* F, T* phi, double* dVdl,
+                        const fmmk::FormArgs<T> fa = {nullptr, nullptr, nullptr},
+                        double* dVdl_t = nullptr) {
     using namespace fmmk;
     hipStream_t st = P->stream;
     const Geo g = make_geo(P);
@@ -334,7 +336,7 @@ fmm_status enqueue_eval(fmm_plan_t P, const std::vector<fmmk::RepDesc>& rd, cons
         k_bbox<T><<<dim3(nb, R), 256, 0, st>>>(x, reps, P->bbox_part);
         k_bbox_final<<<R, 64, 0, st>>>(P->bbox_part, nb, P->dom);
     }
-    k_charge_key<T><<<dim3(ab, R), 256, 0, st>>>(g, reps, x, qA, qB, site, lam, P->dom, P->key,
+    k_charge_key<T><<<dim3(ab, R), 256, 0, st>>>(g, reps, x, qA, qB, site, lam, fa, P->dom, P->key,
                                                  P->rank, P->leaf_count, P->site_count,
                                                  P->site_rank, P->status);
     if (g.nleaf <= kScanFuseCap && S_tot <= kScanFuseCap) {
@@ -355,7 +357,7 @@ fmm_status enqueue_eval(fmm_plan_t P, const std::vector<fmmk::RepDesc>& rd, cons
     const dim3 lg(g.nleaf, R);
     mark(P, 1);
     k_leaf_p2m<T><<<lg, kLeafThreads, leaf_lds_bytes<T>(g.K), st>>>(
-        g, reps, x, qA, qB, site, lam, P->dom, P->leaf_start, P->perm, pos, P->status, mult,
+        g, reps, x, qA, qB, site, lam, fa, P->dom, P->leaf_start, P->perm, pos, P->status, mult,
         P->leaf_part, (uint16_t*)P->msplit, P->mg.KP);
     // upward pass: one launch per level down to the coarsest interacting
     // level (1 periodic, 2 open); the periodic root and its lattice operator
@@ -393,7 +395,7 @@ fmm_status enqueue_eval(fmm_plan_t P, const std::vector<fmmk::RepDesc>& rd, cons
     case NWV:                                                                                    \
         k_near_far<T, NWV><<<dim3(g.nleaf * P->p2p_split, R), 64 * NWV, 0, st>>>(               \
             g, P->p2p_split, reps, pos, P->leaf_start, P->perm, P->dom, loc, P->gidx,              \
-            (const T*)P->gcoef, qA, qB, site, phi, F, P->leaf_energy, P->cphi);                    \
+            (const T*)P->gcoef, qA, qB, site, phi, F, P->leaf_energy, P->cphi, fa.qC != nullptr);  \
         break;
         FMM_NEAR(4)
         FMM_NEAR(8)
@@ -401,9 +403,9 @@ fmm_status enqueue_eval(fmm_plan_t P, const std::vector<fmmk::RepDesc>& rd, cons
         default: break;
     }
     mark(P, 7);
-    k_reduce<<<(unsigned)(R + S_tot), 256, 0, st>>>(g, R, g.nleaf * P->p2p_split, P->leaf_energy,
-                                                    P->site_start,
-                                                    P->site_members, P->cphi, E, dVdl, P->status);
+    k_reduce<T><<<(unsigned)(R + S_tot), 256, 0, st>>>(g, R, g.nleaf * P->p2p_split, P->leaf_energy,
+                                                       P->site_start, P->site_members, P->cphi, E,
+                                                       dVdl, P->status, qA, qB, lam, fa, dVdl_t);
     mark(P, -1);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return fail(P, FMM_E_HIP, std::string("kernel launch: ") + hipGetErrorString(e));
@@ -726,7 +728,8 @@ fmm_status fmm_plan_create(const fmm_params* prm, void* hip_stream, fmm_plan_t* 
                     int x;
                     if (mg.nchunk >= kXcd) x = ch % kXcd;
                     else x = ch + mg.nchunk * ((c * ntile + t) % (kXcd / mg.nchunk));
-                    byx[x].push_back({c, t, ch, 0});
+                    const int o0 = cstart[c * (mg.nchunk + 1) + ch], o1 = cstart[c * (mg.nchunk + 1) + ch + 1];
+                    byx[x].push_back({c, t, ch, o0, o1, {0, 0, 0}});
                 }
         std::vector<fmmk::M2LTask> tl;
         size_t longest = 0;
@@ -946,6 +949,63 @@ fmm_status fmm_eval_batched(fmm_plan_t P, int32_t R, const int64_t* atom_off,
         return enqueue_eval<float>(P, rd, (const float*)x, (const float*)qA, (const float*)qB,
                                    site_local, lam, E, (float*)F, (float*)phi, dVdl);
     });
+}
+
+fmm_status fmm_eval_tautomer_batched(fmm_plan_t P, int32_t R, const int64_t* atom_off,
+                                     const int64_t* site_off, const void* x, const void* qA,
+                                     const void* qB, const void* qC, const void* qD,
+                                     const int32_t* site_local, const double* lam_p,
+                                     const double* lam_t, const double* boxes, double* E, void* F,
+                                     void* phi, double* dVdl_p, double* dVdl_t) {
+    if (!P) return FMM_E_INVALID;
+    if (R < 1 || R > P->prm.max_replicas || !atom_off || !site_off)
+        return fail(P, FMM_E_INVALID, "bad replica count or offsets");
+    if (atom_off[0] != 0 || site_off[0] != 0)
+        return fail(P, FMM_E_INVALID, "offsets must start at 0");
+    std::vector<fmmk::RepDesc> rd((size_t)R);
+    for (int r = 0; r < R; ++r) {
+        const int64_t n = atom_off[r + 1] - atom_off[r], S = site_off[r + 1] - site_off[r];
+        if (n < 0 || S < 0) return fail(P, FMM_E_INVALID, "offsets must be non-decreasing");
+        fmm_status s = check_common(P, n, x, qA, qB, site_local, S, lam_p);
+        if (s != FMM_OK) return s;
+        if (n > 0 && (!qC || !qD)) return fail(P, FMM_E_INVALID, "null input pointer");
+        if (S > 0 && !lam_t) return fail(P, FMM_E_INVALID, "null lambda pointer");
+        double L = 0;
+        if (P->prm.boundary == FMM_PERIODIC && !boxes)
+            return fail(P, FMM_E_INVALID, "periodic plan needs boxes");
+        if ((s = check_box(P, boxes ? boxes + 3 * r : nullptr, &L)) != FMM_OK) return s;
+        rd[r] = {atom_off[r], n, site_off[r], S, L, 0};
+    }
+    if (atom_off[R] > P->prm.max_atoms || site_off[R] > P->prm.max_sites)
+        return fail(P, FMM_E_INVALID, "total atoms or sites above the plan maxima");
+    P->err.clear();
+    KeyBuf key;
+    key.add(4).add(R);
+    for (const fmmk::RepDesc& d : rd) key.add(d);
+    key.add(x).add(qA).add(qB).add(qC).add(qD).add(site_local).add(lam_p).add(lam_t).add(E).add(F)
+        .add(phi).add(dVdl_p).add(dVdl_t);
+    return run_maybe_graph(P, key.b, [&]() {
+        if (P->fp64)
+            return enqueue_eval<double>(P, rd, (const double*)x, (const double*)qA,
+                                        (const double*)qB, site_local, lam_p, E, (double*)F,
+                                        (double*)phi, dVdl_p,
+                                        {(const double*)qC, (const double*)qD, lam_t}, dVdl_t);
+        return enqueue_eval<float>(P, rd, (const float*)x, (const float*)qA, (const float*)qB,
+                                   site_local, lam_p, E, (float*)F, (float*)phi, dVdl_p,
+                                   {(const float*)qC, (const float*)qD, lam_t}, dVdl_t);
+    });
+}
+
+fmm_status fmm_eval_tautomer(fmm_plan_t P, int64_t n, const void* x, const void* qA,
+                             const void* qB, const void* qC, const void* qD, const int32_t* site,
+                             int64_t S, const double* lam_p, const double* lam_t,
+                             const double* box, double* E, void* F, void* phi, double* dVdl_p,
+                             double* dVdl_t) {
+    if (!P) return FMM_E_INVALID;
+    if (n < 0 || S < 0) return fail(P, FMM_E_INVALID, "negative size");
+    const int64_t ao[2] = {0, n}, so[2] = {0, S};
+    return fmm_eval_tautomer_batched(P, 1, ao, so, x, qA, qB, qC, qD, site, lam_p, lam_t, box, E,
+                                     F, phi, dVdl_p, dVdl_t);
 }
 
 fmm_status fmm_sync_check(fmm_plan_t P) {

@@ -76,11 +76,21 @@ constexpr int kM2LTile = 16 * kM2LWaves;     // target columns per work-group
 constexpr int kM2LMaxRT = 8;    // row tiles of 16: K <= 128 (p <= 10)
 constexpr int kM2LMaxKs = 4;    // bf16 k-steps of 32: K <= 128
 
+// Four-form sites (tautomers): the extra charge forms C, D and the second
+// coordinate lambda_t per site; all null for two-form evaluations.
+template <typename T>
+struct FormArgs {
+    const T* qC;
+    const T* qD;
+    const double* lam_t;
+};
+
 // One M2L work item: child class (4 bx + 2 by + bz), tile of that class's
 // target columns (the class's boxes of every level, deepest level first) and
-// chunk of translation offsets (a range of the global offset set).
+// chunk of translation offsets (a range of the global offset set), with the
+// chunk's first and end positions in the class's offset list.
 struct M2LTask {
-    int32_t cls, tile, chunk, pad;
+    int32_t cls, tile, chunk, o0, o1, pad[3];
 };
 
 }  // namespace fmmk

@@ -322,7 +322,7 @@ template <typename T>
 __global__ __launch_bounds__(256) void k_charge_key(
     Geo g, const RepDesc* __restrict__ reps, const T* __restrict__ x, const T* __restrict__ qA,
     const T* __restrict__ qB, const int32_t* __restrict__ site,
-    const double* __restrict__ lam, double* __restrict__ dom_all,
+    const double* __restrict__ lam, FormArgs<T> fa, double* __restrict__ dom_all,
     int32_t* __restrict__ key, int32_t* __restrict__ rank, int32_t* __restrict__ leaf_count_all,
     int32_t* __restrict__ site_count, int32_t* __restrict__ site_rank,
     int32_t* __restrict__ status) {
@@ -385,6 +385,10 @@ __global__ __launch_bounds__(256) void k_charge_key(
     if (g.check) {
         bad |= !finite_d((double)qA[i]) || !finite_d((double)qB[i]);
         if (s >= 0) bad |= !finite_d(lam[rd.s0 + s]);
+        if (fa.qC) {
+            bad |= !finite_d((double)fa.qC[i]) || !finite_d((double)fa.qD[i]);
+            if (s >= 0) bad |= !finite_d(fa.lam_t[rd.s0 + s]);
+        }
         if (bad) atomicOr(&status[0], kStatusNonFinite);
     }
 }
@@ -547,7 +551,7 @@ template <typename T>
 __global__ __launch_bounds__(kLeafThreads) void k_leaf_p2m(
     Geo g, const RepDesc* __restrict__ reps, const T* __restrict__ x, const T* __restrict__ qA,
     const T* __restrict__ qB, const int32_t* __restrict__ site, const double* __restrict__ lam,
-    const double* __restrict__ dom_all, const int32_t* __restrict__ leaf_start_all,
+    FormArgs<T> fa, const double* __restrict__ dom_all, const int32_t* __restrict__ leaf_start_all,
     int32_t* __restrict__ perm, vec4_t<T>* __restrict__ pos, int32_t* __restrict__ status,
     T* __restrict__ mult_all, double* __restrict__ leaf_part_all, uint16_t* __restrict__ msplit_all,
     int split_kp) {
@@ -603,6 +607,8 @@ __global__ __launch_bounds__(kLeafThreads) void k_leaf_p2m(
         const double xv[3] = {(double)x[3 * i], (double)x[3 * i + 1], (double)x[3 * i + 2]};
         const int32_t st = site[i];
         const double a0 = (double)qA[i], b0 = (double)qB[i];
+        const bool four = fa.qC != nullptr;
+        const double c0 = four ? (double)fa.qC[i] : 0.0, d0 = four ? (double)fa.qD[i] : 0.0;
         double sv[3];
         for (int d = 0; d < 3; ++d) {
             double v = xv[d];
@@ -610,7 +616,15 @@ __global__ __launch_bounds__(kLeafThreads) void k_leaf_p2m(
             sv[d] = v - cc[d];
         }
         double q = a0;
-        if (st >= 0 && st < n_sites) q += lam[st] * (b0 - a0);
+        if (st >= 0 && st < n_sites) {
+            if (four) {
+                // four forms (Methods, eq 2): bilinear in (lambda_p, lambda_t)
+                const double lp = lam[st], lt = fa.lam_t[rd.s0 + st];
+                q = (1.0 - lp) * ((1.0 - lt) * a0 + lt * b0) + lp * ((1.0 - lt) * c0 + lt * d0);
+            } else {
+                q += lam[st] * (b0 - a0);
+            }
+        }
         vec4_t<T> o;
         o.x = (T)sv[0];
         o.y = (T)sv[1];
@@ -1428,12 +1442,17 @@ __global__ __launch_bounds__(kM2LThreads) void k_m2l_bf16x3(Geo g, M2LGeom mg,
     const int cn = 1 << clev;
     const int64_t clo = lev_offset(clev);
     if (tid < kM2LTile) col_box[tid] = col_ok ? (int)(clo + morton(ctx, cty, ctz)) : -1;
-    const int o0 = cstart[tk.cls * (mg.nchunk + 1) + tk.chunk];
-    const int o1 = cstart[tk.cls * (mg.nchunk + 1) + tk.chunk + 1];
+    const int o0 = tk.o0, o1 = tk.o1;
+    // the chunk's offsets, 64 at a time in a register (lane i: offset o0 + i)
+    const int16_t* ol = olist + tk.cls * 189;
+    int ol_reg = lane < o1 - o0 ? ol[o0 + lane] : 0;
     const int fx = (tk.cls & 4) ? -1 : 1, fy = (tk.cls & 2) ? -1 : 1, fz = (tk.cls & 1) ? -1 : 1;
 
     auto issue = [&](int oc, uint4* dst) {
-        const int oi = olist[tk.cls * 189 + oc];  // canonical offset; operator slot oc
+        const int st = oc - o0;
+        if (st > 0 && (st & 63) == 0) ol_reg = ol[min(oc + lane, o1 - 1)];
+        // canonical offset; operator slot oc
+        const int oi = __builtin_amdgcn_readlane(ol_reg, st & 63);
         const uint4* src = bank + (size_t)oc * a_chunks;
         for (int c0 = 0; c0 < a_chunks; c0 += kM2LThreads)
             if (c0 + tid < a_chunks) lds_dma16(src + c0 + tid, dst + c0 + 64 * wave);
@@ -1587,7 +1606,7 @@ __global__ __launch_bounds__(64 * kNW) void k_near_far(
     const int32_t* __restrict__ gidx, const T* __restrict__ gcoef,
     const T* __restrict__ qA, const T* __restrict__ qB, const int32_t* __restrict__ site,
     T* __restrict__ phi_out, T* __restrict__ F_out,
-    double* __restrict__ leaf_energy_all, double* __restrict__ cphi) {
+    double* __restrict__ leaf_energy_all, double* __restrict__ cphi, int unit_dq) {
     constexpr int NT = 64 * kNW;
     // sources staged per pass: the whole 27-leaf neighbourhood of a typical leaf
     constexpr int CAP = sizeof(T) == 4 ? 2048 : 1024;
@@ -1633,7 +1652,9 @@ __global__ __launch_bounds__(64 * kNW) void k_near_far(
     const bool tpre = tid < tn;
     const int32_t pre_i = tpre ? perm[tb + tid] : 0;
     const int32_t pre_s = tpre ? site[pre_i] : -1;
-    const double pre_dq = tpre ? (double)qB[pre_i] - (double)qA[pre_i] : 0.0;
+    // site weight of phi: qB - qA (two forms), or 1 (four forms: the site sums
+    // weight phi by the form coordinates themselves)
+    const double pre_dq = tpre ? (unit_dq ? 1.0 : (double)qB[pre_i] - (double)qA[pre_i]) : 0.0;
     const double edge = dom[3];
     const double h = edge / g.nb;
     int cx, cy, cz;
@@ -1920,7 +1941,7 @@ __global__ __launch_bounds__(64 * kNW) void k_near_far(
             esum_part[wave][lane] = qp;
             const int32_t st = pre ? t_site[tj] : site[i];
             if (st >= 0 && st < n_sites) {
-                const double dq = pre ? t_dq[tj] : (double)qB[i] - (double)qA[i];
+                const double dq = pre ? t_dq[tj] : (unit_dq ? 1.0 : (double)qB[i] - (double)qA[i]);
                 cphi[i] = g.coulomb_k * dq * (double)p;
             }
         } else if (slice == 0) {
@@ -1942,19 +1963,36 @@ __global__ __launch_bounds__(64 * kNW) void k_near_far(
 
 // Final reductions: block r < R -> E_r = k_e / 2 sum of replica r's leaf
 // partials (fixed order); block R + s -> dVdl_s = sum over global site s's
-// atoms in caller order.
+// atoms in caller order (four forms: dV/dlambda_p and dV/dlambda_t of site s).
+template <typename T>
 __global__ __launch_bounds__(256) void k_reduce(Geo g, int R, int64_t nparts,
                                                 const double* __restrict__ leaf_energy,
                                                 const int32_t* __restrict__ site_start,
                                                 const int32_t* __restrict__ site_members,
                                                 const double* __restrict__ cphi,
                                                 double* __restrict__ E, double* __restrict__ dVdl,
-                                                int32_t* __restrict__ status) {
-    __shared__ double red[256];
+                                                int32_t* __restrict__ status, const T* __restrict__ qA,
+                                                const T* __restrict__ qB, const double* __restrict__ lam,
+                                                FormArgs<T> fa, double* __restrict__ dVdl_t) {
+    __shared__ double red[256], red_t[256];
     __shared__ int32_t mem[kSiteCap];
     const int t = threadIdx.x;
     const int b = blockIdx.x;
-    double v = 0.0;
+    const bool four = fa.qC != nullptr && b >= R;
+    double v = 0.0, vt = 0.0;
+    // four forms: cphi = k_e phi, and the two site derivatives (Methods, eq 2)
+    // weight it by
+    // dq/dlambda_p = lt~ (qC - qA) + lt (qD - qB), dq/dlambda_t = lp~ (qB - qA) + lp (qD - qC)
+    auto add = [&](int32_t i) {
+        if (!four) {
+            v += cphi[i];
+            return;
+        }
+        const double lp = lam[b - R], lt = fa.lam_t[b - R];
+        const double a0 = (double)qA[i], b0 = (double)qB[i], c0 = (double)fa.qC[i], d0 = (double)fa.qD[i];
+        v += cphi[i] * ((1.0 - lt) * (c0 - a0) + lt * (d0 - b0));
+        vt += cphi[i] * ((1.0 - lp) * (b0 - a0) + lp * (d0 - c0));
+    };
     if (b < R) {
         for (int64_t i = t; i < nparts; i += 256) v += leaf_energy[(size_t)b * nparts + i];
     } else {
@@ -1964,23 +2002,28 @@ __global__ __launch_bounds__(256) void k_reduce(Geo g, int R, int64_t nparts,
             for (int i = t; i < n; i += 256) mem[i] = site_members[m0 + i];
             __syncthreads();
             lds_sort<kSiteCap>(mem, n);
-            for (int i = t; i < n; i += 256) v += cphi[mem[i]];
+            for (int i = t; i < n; i += 256) add(mem[i]);
         } else {
             if (t == 0) atomicOr(&status[1], kInfoBigSite);
-            for (int i = t; i < n; i += 256) v += cphi[site_members[m0 + i]];
+            for (int i = t; i < n; i += 256) add(site_members[m0 + i]);
         }
     }
     red[t] = v;
+    red_t[t] = vt;
     __syncthreads();
     for (int st = 128; st > 0; st >>= 1) {
-        if (t < st) red[t] += red[t + st];
+        if (t < st) {
+            red[t] += red[t + st];
+            red_t[t] += red_t[t + st];
+        }
         __syncthreads();
     }
     if (t == 0) {
         if (b < R) {
             if (E) E[b] = 0.5 * g.coulomb_k * red[0];
-        } else if (dVdl) {
-            dVdl[b - R] = red[0];
+        } else {
+            if (dVdl) dVdl[b - R] = red[0];
+            if (four && dVdl_t) dVdl_t[b - R] = red_t[0];
         }
     }
 }

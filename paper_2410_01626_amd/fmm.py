@@ -54,6 +54,7 @@ class fmm_params(ctypes.Structure):
 
 
 EXPORTS = ["fmm_plan_create", "fmm_eval", "fmm_eval_adjoint", "fmm_eval_batched",
+           "fmm_eval_tautomer", "fmm_eval_tautomer_batched",
            "fmm_sync_check", "fmm_last_error", "fmm_plan_destroy", "fmm_profile",
            "fmm_profile_select", "fmm_plan_info", "fmm_host_operator"]
 PHASES = ["bin", "p2m", "m2m", "root", "m2l", "l2l", "near_far", "reduce"]
@@ -86,6 +87,12 @@ def load_library(path: str = LIB_PATH):
                                      vp, vp, vp, vp, vp, vp, vp, vp]
     lib.fmm_eval_batched.restype = ctypes.c_int
     lib.fmm_eval_batched.argtypes = [vp, i32, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]
+    lib.fmm_eval_tautomer.restype = ctypes.c_int
+    lib.fmm_eval_tautomer.argtypes = [vp, i64, vp, vp, vp, vp, vp, vp, i64, vp, vp, vp, vp, vp,
+                                      vp, vp, vp]
+    lib.fmm_eval_tautomer_batched.restype = ctypes.c_int
+    lib.fmm_eval_tautomer_batched.argtypes = [vp, i32, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp,
+                                              vp, vp, vp, vp, vp, vp]
     lib.fmm_sync_check.restype = ctypes.c_int
     lib.fmm_sync_check.argtypes = [vp]
     lib.fmm_last_error.restype = ctypes.c_char_p
@@ -142,6 +149,19 @@ def fmm_eval_batched(plan, R, atom_off, site_off, x, qA, qB, site_local, lam, bo
                      phi, dVdl) -> int:
     return load_library().fmm_eval_batched(plan, R, atom_off, site_off, x, qA, qB, site_local,
                                            lam, boxes, E, F, phi, dVdl)
+
+
+def fmm_eval_tautomer(plan, n, x, qA, qB, qC, qD, site, n_sites, lam_p, lam_t, box, E, F, phi,
+                      dVdl_p, dVdl_t) -> int:
+    return load_library().fmm_eval_tautomer(plan, n, x, qA, qB, qC, qD, site, n_sites, lam_p,
+                                            lam_t, box, E, F, phi, dVdl_p, dVdl_t)
+
+
+def fmm_eval_tautomer_batched(plan, R, atom_off, site_off, x, qA, qB, qC, qD, site_local, lam_p,
+                              lam_t, boxes, E, F, phi, dVdl_p, dVdl_t) -> int:
+    return load_library().fmm_eval_tautomer_batched(plan, R, atom_off, site_off, x, qA, qB, qC,
+                                                    qD, site_local, lam_p, lam_t, boxes, E, F,
+                                                    phi, dVdl_p, dVdl_t)
 
 
 def fmm_profile(plan, mode: int, capacity: int = 0, out=None) -> int:
@@ -313,6 +333,65 @@ class Plan:
                               _ptr(site_local), _ptr(lam), bp, _ptr(out["E"]), _ptr(out["F"]),
                               _ptr(out["phi"]), _ptr(out["dVdl"]))
         self._raise(st, "fmm_eval_batched")
+        return out
+
+    def _forms(self, n, S, qC, qD, lam_t):
+        import torch
+        self._check(qC, self.dtype, (n,), "qC")
+        self._check(qD, self.dtype, (n,), "qD")
+        self._check(lam_t, torch.float64, (S,), "lambda_t")
+
+    def eval_tautomer(self, x, qA, qB, qC, qD, site, lam_p, lam_t, box=None,
+                      want=("E", "F", "phi", "dVdl_p", "dVdl_t"), out=None):
+        """Enqueue fmm_eval_tautomer (four charge forms per site, two lambda
+        coordinates); returns dict of output tensors."""
+        import torch
+        n, S = self._inputs(x, qA, qB, site, lam_p)
+        self._forms(n, S, qC, qD, lam_t)
+        if out is None:
+            opt = dict(device=self.device)
+            out = {"E": torch.empty(1, dtype=torch.float64, **opt)}
+            out["F"] = torch.empty((n, 3), dtype=self.dtype, **opt) if "F" in want else None
+            out["phi"] = torch.empty(n, dtype=self.dtype, **opt) if "phi" in want else None
+            for k in ("dVdl_p", "dVdl_t"):
+                out[k] = torch.empty(S, dtype=torch.float64, **opt) if k in want else None
+        b, bp = self._box(box)
+        st = fmm_eval_tautomer(self.handle, n, _ptr(x), _ptr(qA), _ptr(qB), _ptr(qC), _ptr(qD),
+                               _ptr(site), S, _ptr(lam_p), _ptr(lam_t), bp, _ptr(out["E"]),
+                               _ptr(out["F"]), _ptr(out["phi"]), _ptr(out["dVdl_p"]),
+                               _ptr(out["dVdl_t"]))
+        self._raise(st, "fmm_eval_tautomer")
+        return out
+
+    def eval_tautomer_batched(self, atom_off, site_off, x, qA, qB, qC, qD, site_local, lam_p,
+                              lam_t, boxes=None):
+        """Enqueue fmm_eval_tautomer_batched over R replicas (host offsets)."""
+        import torch
+        ao = np.ascontiguousarray(atom_off, dtype=np.int64)
+        so = np.ascontiguousarray(site_off, dtype=np.int64)
+        R = ao.size - 1
+        n, S = self._inputs(x, qA, qB, site_local, lam_p)
+        self._forms(n, S, qC, qD, lam_t)
+        if ao[-1] != n or so[-1] != S:
+            raise ValueError("offsets do not match the concatenated arrays")
+        opt = dict(device=self.device)
+        out = {"E": torch.empty(R, dtype=torch.float64, **opt),
+               "F": torch.empty((n, 3), dtype=self.dtype, **opt),
+               "phi": torch.empty(n, dtype=self.dtype, **opt),
+               "dVdl_p": torch.empty(S, dtype=torch.float64, **opt),
+               "dVdl_t": torch.empty(S, dtype=torch.float64, **opt)}
+        if self.periodic:
+            bx = np.ascontiguousarray(np.asarray(boxes, dtype=np.float64).reshape(R, 3))
+            bp = ctypes.c_void_p(bx.ctypes.data)
+        else:
+            bx, bp = None, ctypes.c_void_p(0)
+        st = fmm_eval_tautomer_batched(self.handle, R, ctypes.c_void_p(ao.ctypes.data),
+                                       ctypes.c_void_p(so.ctypes.data), _ptr(x), _ptr(qA),
+                                       _ptr(qB), _ptr(qC), _ptr(qD), _ptr(site_local),
+                                       _ptr(lam_p), _ptr(lam_t), bp, _ptr(out["E"]),
+                                       _ptr(out["F"]), _ptr(out["phi"]), _ptr(out["dVdl_p"]),
+                                       _ptr(out["dVdl_t"]))
+        self._raise(st, "fmm_eval_tautomer_batched")
         return out
 
     def profile_select(self, phases=None, every: int = 1):

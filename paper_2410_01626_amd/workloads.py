@@ -30,6 +30,13 @@ densities, charge scales and site structure):
   0, |lambda - end| ~ U(0, 0.1).
 * ``large_box`` (500,000 atoms, periodic 17 nm): 160,000 waters around a
   20,000-atom cluster (radius 3.63 nm), 200 sites.
+
+``with_tautomers(d)`` adds four-form sites (protonation tautomers) to any of
+these: forms A = qA and C = qB of the workload (the two protonation states),
+B = A + tau and D = C + tau' with tau, tau' moving charge between the site's
+atoms without changing its net charge (tau = 0.5 (w - 1/size), w ~
+Dirichlet(1,...,1)), on every other site; the remaining sites have no
+tautomers (B = A, D = C).  lambda_t ~ U(0, 1) per site.
 """
 from __future__ import annotations
 
@@ -45,7 +52,7 @@ WATER_HOH_DEG = 104.52
 
 __all__ = [
     "open_cube", "water_box", "replicas", "large_box", "tiny_periodic",
-    "random_open", "by_name", "CONFIGS",
+    "random_open", "by_name", "CONFIGS", "with_tautomers",
 ]
 
 
@@ -323,3 +330,28 @@ CONFIGS = {
 
 def by_name(name, **kw):
     return CONFIGS[name](**kw)
+
+
+def with_tautomers(d, seed=SEED_BASE + 7):
+    """A copy of workload `d` with four charge forms per site (qA, qB, qC, qD)
+    and a second coordinate lam_t per site; the workload's lam becomes lam_p."""
+    rng = np.random.default_rng(seed)
+    qA = d["qA"].astype(np.float64)
+    qC = d["qB"].astype(np.float64)
+    qB = qA.copy()
+    qD = qC.copy()
+    site = d["site"]
+    S = int(d["lam"].size)
+    for s in range(0, S, 2):  # every other site has tautomers
+        idx = np.nonzero(site == s)[0]
+        if idx.size < 2:
+            continue
+        w1 = rng.dirichlet(np.ones(idx.size))
+        w2 = rng.dirichlet(np.ones(idx.size))
+        qB[idx] = qA[idx] + 0.5 * (w1 - 1.0 / idx.size)
+        qD[idx] = qC[idx] + 0.5 * (w2 - 1.0 / idx.size)
+    out = dict(d)
+    out.update(name=d["name"] + "_tautomers", qA=_f32(qA), qB=_f32(qB), qC=_f32(qC), qD=_f32(qD),
+               lam_p=np.ascontiguousarray(d["lam"], dtype=np.float64),
+               lam_t=np.ascontiguousarray(rng.uniform(0.0, 1.0, S), dtype=np.float64))
+    return out
