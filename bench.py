@@ -195,6 +195,32 @@ def main():
         t1 = time.perf_counter()
     sec_graph = (t1 - t0) / args.steps
 
+    # the same box with four charge forms on every site (protonation tautomers,
+    # two lambda coordinates per site): fmm_eval_tautomer
+    dt4 = workloads.with_tautomers(d)
+    tplan = fmm.Plan(depth, order, periodic=True, precision="bf16x3", max_atoms=n, max_sites=S,
+                     device=dev)
+    t4 = (torch.tensor(dt4["x"], dtype=torch.float32, device=dev),
+          *(torch.tensor(dt4[k], dtype=torch.float32, device=dev) for k in ("qA", "qB", "qC", "qD")),
+          torch.tensor(dt4["site"], dtype=torch.int32, device=dev),
+          torch.tensor(dt4["lam_p"], dtype=torch.float64, device=dev),
+          torch.tensor(dt4["lam_t"], dtype=torch.float64, device=dev))
+    for _ in range(args.warmup):
+        tplan.eval_tautomer(*t4, box=d["box"])
+    torch.cuda.synchronize(dev)
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        tplan.eval_tautomer(*t4, box=d["box"])
+    torch.cuda.synchronize(dev)
+    t1 = time.perf_counter()
+    sec_taut = (t1 - t0) / args.steps
+
+    # the same box under Hamiltonian interpolation (eq 1 taken literally: the
+    # intra-site correction is added to E, F and dV/dlambda)
+    hplan = fmm.Plan(depth, order, periodic=True, precision="bf16x3", max_atoms=n, max_sites=S,
+                     device=dev, hamiltonian=True)
+    sec_ham, _ = timed(hplan, inp, args.steps, args.warmup)
+
     # 16 open replicas of 10k-60k atoms at pH 2-9 in one batched call per step
     batched = None
     if not args.no_batched:
@@ -280,6 +306,12 @@ def main():
         "f32": {"value": 1.0 / sec32, "ms_per_step": sec32 * 1e3, "steps": args.fp64_steps},
         "speedup_mixed_vs_fp64": sec64 / sec,
         "graph_replay": {"value": 1.0 / sec_graph, "ms_per_step": sec_graph * 1e3},
+        "hamiltonian": {"value": 1.0 / sec_ham, "ms_per_step": sec_ham * 1e3,
+                        "workload": "same box, Hamiltonian interpolation (intra-site "
+                                    "correction on E, F, dV/dlambda)"},
+        "tautomers": {"value": 1.0 / sec_taut, "ms_per_step": sec_taut * 1e3,
+                      "workload": "same box, four charge forms per site (half the sites with "
+                                  "tautomers), E+F+dV/dlambda_p+dV/dlambda_t"},
         "batched": batched,
         "phase_ms": phase_ms,
         "phase_ms_fp64": phase_ms64,

@@ -95,7 +95,19 @@ typedef enum { FMM_FP64 = 0, FMM_MIXED_F32 = 1, FMM_MIXED_BF16X3 = 2 } fmm_preci
  *   graph       1 = record the launch sequence of an evaluation in a HIP graph on
  *               first use and replay the graph while every argument (pointers,
  *               sizes, boxes, replica offsets) is unchanged; needs a non-NULL
- *               stream.  Per-phase profiling (fmm_profile) runs eagerly. */
+ *               stream.  Per-phase profiling (fmm_profile) runs eagerly.
+ *   hamiltonian 0 = charge interpolation (q = qA + lambda (qB - qA) in one
+ *               Coulomb energy); 1 = Hamiltonian interpolation (Methods, eq 1:
+ *               H = (1 - lambda) H_A + lambda H_B per site, multilinear over
+ *               sites).  The two differ only inside each site: with
+ *               d_i = qA_i - qB_i and psi the pair potential (1/r, or the periodic
+ *               Green's function with psi(0) its self-image limit), eq 1 adds
+ *                 dE_s = k_e lambda_s (1 - lambda_s) 1/2 sum_{i,j in s} d_i d_j psi(r_ij)
+ *               (i = j only for periodic cells), and fmm_eval / fmm_eval_batched
+ *               add dE to E, its lambda-derivative (1 - 2 lambda_s)/(lambda_s
+ *               (1 - lambda_s)) dE_s to dVdl and its position derivative to F; phi
+ *               stays the potential of the interpolated charges.  fmm_eval_adjoint
+ *               and the four-form calls return FMM_E_UNSUPPORTED on such a plan. */
 typedef struct {
     int32_t depth;
     int32_t order_p;
@@ -111,7 +123,7 @@ typedef struct {
     int32_t p2p_waves;
     int32_t graph;
     int32_t p2p_split;
-    int32_t reserved_;  /* zero */
+    int32_t hamiltonian;
 } fmm_params;
 
 /* Create a plan on the current HIP device.  hip_stream is a hipStream_t (NULL =
@@ -244,6 +256,9 @@ fmm_status fmm_plan_info(fmm_plan_t plan, int64_t out[10]);
  * GPU is touched.  which: 0 = M2L bank (343 x K x K), 1 = M2M (8 x K x K),
  * 2 = L2L (8 x K x K), 3 = periodic lattice operator (K x K), 4 = regular
  * harmonics rho(r) at the point out[0..2] (K values, written over out).
+ * 5 = real local coefficients of the smooth part h of the unit cube's periodic
+ * Green's function, psi(u) = sum_{n in {-1,0,1}^3} 1/|u+n| + (2 pi/3)|u|^2 + h(u)
+ * (K values; degree p).
  * Layouts as documented in the library's operators.h; K = (p+1)^2.  Returns
  * the number of doubles written, or -1 for a bad argument. */
 int64_t fmm_host_operator(int32_t order_p, int32_t which, double* out);

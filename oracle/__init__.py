@@ -180,10 +180,13 @@ def outputs(q, qA, qB, site, n_sites, phi, field, k_e=1.0):
 
 
 def solve(x, qA, qB, site, lam, box=None, periodic=False, k_e=1.0, eps=1e-13,
-          ewald_kw=None):
+          ewald_kw=None, hamiltonian=False):
     """Full oracle solve.  Returns dict(E, F, phi, dVdl, q), all FP64.
 
-    phi is returned already multiplied by k_e.
+    phi is returned already multiplied by k_e.  With hamiltonian=True the
+    energy is that of eq 1 taken literally (each site's two end Hamiltonians
+    mixed linearly): see hamiltonian_correction; phi stays the potential of the
+    interpolated charges.
     """
     lam = _f64(np.atleast_1d(lam))
     q = lambda_charges(qA, qB, site, lam)
@@ -192,7 +195,41 @@ def solve(x, qA, qB, site, lam, box=None, periodic=False, k_e=1.0, eps=1e-13,
     else:
         phi, field = direct(x, q)
     E, F, dVdl = outputs(q, qA, qB, site, lam.size, phi, field, k_e)
+    if hamiltonian:
+        dE, dF, dD = hamiltonian_correction(x, qA, qB, site, lam, box, periodic, k_e, eps)
+        E, F, dVdl = E + dE, F + dF, dVdl + dD
     return {"E": E, "F": F, "phi": k_e * phi, "dVdl": dVdl, "q": q}
+
+
+def hamiltonian_correction(x, qA, qB, site, lam, box=None, periodic=False, k_e=1.0, eps=1e-13):
+    """Hamiltonian minus charge interpolation (Methods, eq 1).
+
+    The Coulomb energy is a quadratic form E(q) = 1/2 q^T Psi q (Psi: the pair
+    potential, with the self-image term on the diagonal for periodic cells).
+    Mixing a site's two end states linearly, (1 - l) E(a) + l E(b), exceeds
+    E((1 - l) a + l b) by l (1 - l) 1/2 (a - b)^T Psi (a - b) for the site's
+    own block of Psi; every cross-site term is bilinear and agrees.  Per site
+    this is the energy of the charges d = qA - qB placed on the site's atoms
+    alone, which the direct or Ewald sum gives.  Returns (dE, dF, d dE/dlambda)."""
+    x = _f64(x).reshape(-1, 3)
+    qA, qB, lam = _f64(qA), _f64(qB), _f64(np.atleast_1d(lam))
+    site = np.asarray(site)
+    dE, dF, dD = 0.0, np.zeros_like(x), np.zeros(lam.size)
+    for s in range(lam.size):
+        idx = np.nonzero(site == s)[0]
+        if idx.size == 0:
+            continue
+        d = qA[idx] - qB[idx]
+        if periodic:
+            ph, fd = ewald(x[idx], d, box, eps=eps)
+        else:
+            ph, fd = direct(x[idx], d)
+        e = 0.5 * float(np.dot(d, ph))
+        w = lam[s] * (1.0 - lam[s])
+        dE += k_e * w * e
+        dD[s] = k_e * (1.0 - 2.0 * lam[s]) * e
+        dF[idx] += k_e * w * d[:, None] * fd
+    return dE, dF, dD
 
 
 def tautomer_charges(qA, qB, qC, qD, site, lam_p, lam_t):

@@ -43,6 +43,10 @@ struct fmm_plan_s {
            *cphi = nullptr;
     int32_t* status = nullptr;
     void *F_tmp = nullptr, *phi_tmp = nullptr;
+    // Hamiltonian interpolation: per-site energy and lambda-derivative
+    // corrections, and (periodic) the Green's function coefficients of the
+    // unit cube (degree kPMax) followed by those of its gradient (3 x kPMax^2)
+    double *hc_e = nullptr, *hc_dl = nullptr, *green = nullptr;
     double* dVdl_tmp = nullptr;
     double* E_tmp = nullptr;
     fmmk::RepDesc* reps = nullptr;  // device replica descriptors (max_replicas)
@@ -403,9 +407,16 @@ fmm_status enqueue_eval(fmm_plan_t P, const std::vector<fmmk::RepDesc>& rd, cons
         default: break;
     }
     mark(P, 7);
+    const bool ham = P->prm.hamiltonian != 0;
+    if (ham && S_tot > 0)
+        k_hcorr<T><<<(unsigned)S_tot, 256, 0, st>>>(g, R, reps, P->site_start, P->site_members, x, qA,
+                                                    qB, lam, P->green, F, P->hc_e, P->hc_dl,
+                                                    P->status);
     k_reduce<T><<<(unsigned)(R + S_tot), 256, 0, st>>>(g, R, g.nleaf * P->p2p_split, P->leaf_energy,
                                                        P->site_start, P->site_members, P->cphi, E,
-                                                       dVdl, P->status, qA, qB, lam, fa, dVdl_t);
+                                                       dVdl, P->status, qA, qB, lam, fa, dVdl_t, reps,
+                                                       ham && S_tot > 0 ? P->hc_e : nullptr,
+                                                       ham && S_tot > 0 ? P->hc_dl : nullptr);
     mark(P, -1);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return fail(P, FMM_E_HIP, std::string("kernel launch: ") + hipGetErrorString(e));
@@ -521,7 +532,7 @@ fmm_status fmm_plan_create(const fmm_params* prm, void* hip_stream, fmm_plan_t* 
         prm->m2l_kernel < 0 || prm->m2l_kernel > 2 || prm->m2l_chunk < 0 || prm->m2l_chunk > 189 ||
         (prm->p2p_waves != 0 && prm->p2p_waves != 4 && prm->p2p_waves != 8 &&
          prm->p2p_waves != 16) || prm->graph < 0 || prm->graph > 1 || prm->p2p_split < 0 ||
-        prm->p2p_split > fmmk::kMaxSplit || prm->reserved_ != 0)
+        prm->p2p_split > fmmk::kMaxSplit || prm->hamiltonian < 0 || prm->hamiltonian > 1)
         return FMM_E_INVALID;
     {
         const int K = (prm->order_p + 1) * (prm->order_p + 1);
@@ -589,6 +600,11 @@ fmm_status fmm_plan_create(const fmm_params* prm, void* hip_stream, fmm_plan_t* 
     ok &= dev_alloc(P, (void**)&P->cphi, N * 8);
     ok &= dev_alloc(P, (void**)&P->status, 4 * 4);
     ok &= dev_alloc(P, &P->F_tmp, N * 3 * ts);
+    if (prm->hamiltonian) {
+        ok &= dev_alloc(P, (void**)&P->hc_e, S * 8);
+        ok &= dev_alloc(P, (void**)&P->hc_dl, S * 8);
+        ok &= dev_alloc(P, (void**)&P->green, (fmmk::kKMax + 3 * fmmk::kKgMax) * 8);
+    }
     ok &= dev_alloc(P, &P->phi_tmp, N * ts);
     ok &= dev_alloc(P, (void**)&P->dVdl_tmp, S * 8);
     ok &= dev_alloc(P, (void**)&P->E_tmp, RM * 8);
@@ -839,6 +855,25 @@ fmm_status fmm_plan_create(const fmm_params* prm, void* hip_stream, fmm_plan_t* 
     }
     std::vector<double> dom0(8 * RM, 0.0);
     up(P->dom, dom0.data(), dom0.size() * 8);
+    if (prm->hamiltonian) {
+        // periodic pair potential: h of the unit cube to degree kPMax and the
+        // coefficients of its gradient (degree kPMax - 1); zero for open cells
+        const int PH = fmmk::kPMax, KH = fmmk::kKMax, KG = fmmk::kKgMax;
+        std::vector<double> gv((size_t)KH + 3 * KG, 0.0);
+        if (prm->boundary == FMM_PERIODIC) {
+            fmmops::build_periodic_green(PH, gv.data());
+            std::vector<int32_t> hi((size_t)3 * KG * 4);
+            std::vector<double> hcf((size_t)3 * KG * 4);
+            fmmops::build_grad_table(PH, hi.data(), hcf.data());
+            for (int q = 0; q < 3 * KG; ++q) {
+                double v = 0.0;
+                for (int t = 0; t < 4; ++t)
+                    if (hi[(size_t)q * 4 + t] >= 0) v += hcf[(size_t)q * 4 + t] * gv[hi[(size_t)q * 4 + t]];
+                gv[(size_t)KH + q] = v;
+            }
+        }
+        up(P->green, gv.data(), gv.size() * 8);
+    }
     int32_t z[4] = {0, 0, 0, 0};
     up(P->status, z, sizeof(z));
     if (e != hipSuccess) {
@@ -893,6 +928,8 @@ fmm_status fmm_eval_adjoint(fmm_plan_t P, int64_t n, const void* x, const void* 
     fmm_status s = check_common(P, n, x, qA, qB, site, S, lam);
     if (s != FMM_OK) return s;
     if (!gE) return fail(P, FMM_E_INVALID, "null upstream weight");
+    if (P->prm.hamiltonian)
+        return fail(P, FMM_E_UNSUPPORTED, "the adjoint covers charge interpolation only");
     double L = 0;
     if ((s = check_box(P, box, &L)) != FMM_OK) return s;
     P->err.clear();
@@ -958,6 +995,8 @@ fmm_status fmm_eval_tautomer_batched(fmm_plan_t P, int32_t R, const int64_t* ato
                                      const double* lam_t, const double* boxes, double* E, void* F,
                                      void* phi, double* dVdl_p, double* dVdl_t) {
     if (!P) return FMM_E_INVALID;
+    if (P->prm.hamiltonian)
+        return fail(P, FMM_E_UNSUPPORTED, "four-form sites use charge interpolation");
     if (R < 1 || R > P->prm.max_replicas || !atom_off || !site_off)
         return fail(P, FMM_E_INVALID, "bad replica count or offsets");
     if (atom_off[0] != 0 || site_off[0] != 0)
@@ -1097,6 +1136,7 @@ int64_t fmm_host_operator(int32_t p, int32_t which, double* out) {
             fmmops::eval_rho(p, r, out);
             return K;
         }
+        case 5: fmmops::build_periodic_green(p, out); return K;
         default: return -1;
     }
 }

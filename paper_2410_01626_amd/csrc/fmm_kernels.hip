@@ -1961,6 +1961,146 @@ __global__ __launch_bounds__(64 * kNW) void k_near_far(
     }
 }
 
+// Hamiltonian interpolation (Methods, eq 1) against the charge-interpolated
+// energy, one block per site s (global index): eq 1 mixes each site's two end
+// Hamiltonians linearly, and the Coulomb energy is a quadratic form in the
+// charges, so the two interpolations differ by
+//   dE_s = k_e lambda (1 - lambda) 1/2 sum_{i,j in s} d_i d_j psi(r_ij),  d = qA - qB,
+// psi = 1/r (open; i != j) or the periodic Green's function of the cell
+// (psi(0) = its self-image limit).  Writes dE_s and d(dE_s)/dlambda_s (hc_e,
+// hc_dl; added by k_reduce) and adds -d(dE_s)/dr_i to F_i (each atom belongs
+// to one site: no two blocks touch the same force).  Periodic psi of a cell of
+// edge L at r: u = minimum image of r / L,
+//   psi = (1/L) [sum_{n in {-1,0,1}^3} 1/|u + n| + (2 pi / 3)|u|^2 + h(u)],
+// with h from its degree-kPMax harmonic coefficients (green) and grad h from
+// the gradient coefficients that follow them.  All arithmetic is FP64.
+template <typename T>
+__global__ __launch_bounds__(256) void k_hcorr(Geo g, int R, const RepDesc* __restrict__ reps,
+                                               const int32_t* __restrict__ site_start,
+                                               const int32_t* __restrict__ site_members,
+                                               const T* __restrict__ x, const T* __restrict__ qA,
+                                               const T* __restrict__ qB, const double* __restrict__ lam,
+                                               const double* __restrict__ green, T* __restrict__ F,
+                                               double* __restrict__ hc_e, double* __restrict__ hc_dl,
+                                               int32_t* __restrict__ status) {
+    constexpr int kH = kSiteCap / 4;  // atoms of a site staged in LDS
+    __shared__ int32_t mem[kSiteCap];
+    __shared__ double sp[kH][4];  // x, y, z, d
+    __shared__ double gc[kKMax + 3 * kKgMax];
+    __shared__ RhoLds<double> rho;
+    __shared__ double red[256];
+    const int s = blockIdx.x, t = threadIdx.x;
+    int r = 0;
+    while (r + 1 < R && s >= reps[r].s0 + reps[r].S) ++r;
+    const double L = reps[r].box;
+    const int m0 = site_start[s], n = site_start[s + 1] - m0;
+    const double lm = lam[s], w = lm * (1.0 - lm);
+    if (n > kH) {
+        // sites are a few atoms; a site this large is reported and left alone
+        if (t == 0) {
+            atomicOr(&status[1], kInfoBigSite);
+            hc_e[s] = 0.0;
+            hc_dl[s] = 0.0;
+        }
+        return;
+    }
+    for (int i = t; i < n; i += 256) mem[i] = site_members[m0 + i];
+    if (g.periodic) {
+        for (int k = t; k < kKMax + 3 * kKgMax; k += 256) gc[k] = green[k];
+        load_rho_lds<double, 256>(rho, kPMax);
+    }
+    __syncthreads();
+    lds_sort<kSiteCap>(mem, n);  // caller order: a fixed summation order
+    for (int i = t; i < n; i += 256) {
+        const int32_t a = mem[i];
+        sp[i][0] = (double)x[3 * (size_t)a];
+        sp[i][1] = (double)x[3 * (size_t)a + 1];
+        sp[i][2] = (double)x[3 * (size_t)a + 2];
+        sp[i][3] = (double)qA[a] - (double)qB[a];
+    }
+    __syncthreads();
+    // self-image limit of the unit cube: sum over the 26 neighbour images + h(0)
+    const double psi0 = 6.0 + 12.0 / sqrt(2.0) + 8.0 / sqrt(3.0) + gc[0];
+    double v = 0.0;
+    for (int i = t; i < n; i += 256) {
+        double e = 0.0, gx = 0.0, gy = 0.0, gz = 0.0;
+        for (int j = 0; j < n; ++j) {
+            const double dj = sp[j][3];
+            if (j == i) {
+                if (g.periodic) e += dj * psi0 / L;
+                continue;
+            }
+            double rx = sp[i][0] - sp[j][0], ry = sp[i][1] - sp[j][1], rz = sp[i][2] - sp[j][2];
+            double psi, px, py, pz;  // psi and its gradient with respect to r_i
+            if (!g.periodic) {
+                const double r2 = rx * rx + ry * ry + rz * rz, ir = 1.0 / sqrt(r2), ir3 = ir * ir * ir;
+                psi = ir;
+                px = -rx * ir3;
+                py = -ry * ir3;
+                pz = -rz * ir3;
+            } else {
+                double u[3] = {rx / L, ry / L, rz / L};
+                for (int c = 0; c < 3; ++c) u[c] -= rint(u[c]);
+                double ps = 2.0 * kPi / 3.0 * (u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
+                double qx = 4.0 * kPi / 3.0 * u[0], qy = 4.0 * kPi / 3.0 * u[1], qz = 4.0 * kPi / 3.0 * u[2];
+                for (int a = -1; a <= 1; ++a)
+                    for (int b = -1; b <= 1; ++b)
+                        for (int c = -1; c <= 1; ++c) {
+                            const double vx = u[0] + a, vy = u[1] + b, vz = u[2] + c;
+                            const double r2 = vx * vx + vy * vy + vz * vz, ir = 1.0 / sqrt(r2);
+                            const double ir3 = ir * ir * ir;
+                            ps += ir;
+                            qx -= vx * ir3;
+                            qy -= vy * ir3;
+                            qz -= vz * ir3;
+                        }
+                const double* gh = gc + kKMax;
+                for_each_rho<double>(kPMax, rho, u[0], u[1], u[2], [&](int kc, bool has_s, double re, double im) {
+                    ps += gc[kc] * re;
+                    if (has_s) ps += gc[kc + 1] * im;
+                    if (kc < kKgMax) {
+                        qx += gh[kc] * re;
+                        qy += gh[kKgMax + kc] * re;
+                        qz += gh[2 * kKgMax + kc] * re;
+                        if (has_s) {
+                            qx += gh[kc + 1] * im;
+                            qy += gh[kKgMax + kc + 1] * im;
+                            qz += gh[2 * kKgMax + kc + 1] * im;
+                        }
+                    }
+                });
+                psi = ps / L;
+                px = qx / (L * L);
+                py = qy / (L * L);
+                pz = qz / (L * L);
+            }
+            e += dj * psi;
+            gx += dj * px;
+            gy += dj * py;
+            gz += dj * pz;
+        }
+        const double di = sp[i][3];
+        v += di * e;
+        if (F) {
+            const int32_t a = mem[i];
+            const double f = -g.coulomb_k * w * di;
+            F[3 * (size_t)a] += (T)(f * gx);
+            F[3 * (size_t)a + 1] += (T)(f * gy);
+            F[3 * (size_t)a + 2] += (T)(f * gz);
+        }
+    }
+    red[t] = v;
+    __syncthreads();
+    for (int st = 128; st > 0; st >>= 1) {
+        if (t < st) red[t] += red[t + st];
+        __syncthreads();
+    }
+    if (t == 0) {
+        hc_e[s] = 0.5 * g.coulomb_k * w * red[0];
+        hc_dl[s] = 0.5 * g.coulomb_k * (1.0 - 2.0 * lm) * red[0];
+    }
+}
+
 // Final reductions: block r < R -> E_r = k_e / 2 sum of replica r's leaf
 // partials (fixed order); block R + s -> dVdl_s = sum over global site s's
 // atoms in caller order (four forms: dV/dlambda_p and dV/dlambda_t of site s).
@@ -1973,7 +2113,10 @@ __global__ __launch_bounds__(256) void k_reduce(Geo g, int R, int64_t nparts,
                                                 double* __restrict__ E, double* __restrict__ dVdl,
                                                 int32_t* __restrict__ status, const T* __restrict__ qA,
                                                 const T* __restrict__ qB, const double* __restrict__ lam,
-                                                FormArgs<T> fa, double* __restrict__ dVdl_t) {
+                                                FormArgs<T> fa, double* __restrict__ dVdl_t,
+                                                const RepDesc* __restrict__ reps,
+                                                const double* __restrict__ hc_e,
+                                                const double* __restrict__ hc_dl) {
     __shared__ double red[256], red_t[256];
     __shared__ int32_t mem[kSiteCap];
     const int t = threadIdx.x;
@@ -2020,9 +2163,14 @@ __global__ __launch_bounds__(256) void k_reduce(Geo g, int R, int64_t nparts,
     }
     if (t == 0) {
         if (b < R) {
-            if (E) E[b] = 0.5 * g.coulomb_k * red[0];
+            double e = 0.5 * g.coulomb_k * red[0];
+            if (hc_e) {  // Hamiltonian interpolation: the replica's site corrections, in order
+                const RepDesc rd = reps[b];
+                for (int64_t q = 0; q < rd.S; ++q) e += hc_e[rd.s0 + q];
+            }
+            if (E) E[b] = e;
         } else {
-            if (dVdl) dVdl[b - R] = red[0];
+            if (dVdl) dVdl[b - R] = red[0] + (hc_dl ? hc_dl[b - R] : 0.0);
             if (four && dVdl_t) dVdl_t[b - R] = red_t[0];
         }
     }

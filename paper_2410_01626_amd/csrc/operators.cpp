@@ -409,4 +409,24 @@ void build_lattice(int p, double* out) {
     cache[p].assign(out, out + (size_t)ncoef(p) * ncoef(p));
 }
 
+void build_periodic_green(int P, double* out) {
+    static std::mutex mu;
+    static std::map<int, std::vector<double>> cache;
+    {
+        std::lock_guard<std::mutex> lk(mu);
+        auto it = cache.find(P);
+        if (it != cache.end()) {
+            std::memcpy(out, it->second.data(), it->second.size() * sizeof(double));
+            return;
+        }
+    }
+    std::vector<cplx> c;
+    lattice_coeffs(P, c);
+    // h(u) = sum_L sum_M c_L^M R_L^M(u) is a potential: its real local
+    // coefficients follow the local-expansion convention of the translations
+    complex_to_real(P, Kind::Local, c, out);
+    std::lock_guard<std::mutex> lk(mu);
+    cache[P].assign(out, out + (size_t)ncoef(P));
+}
+
 }  // namespace fmmops

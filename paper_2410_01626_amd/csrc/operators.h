@@ -54,6 +54,14 @@ void build_grad_table(int p, int32_t* out_idx, double* out_coef);
 // out: K*K row-major.
 void build_lattice(int p, double* out);
 
+// Periodic Green's function of the unit cube (tin-foil, neutralising
+// background, zero mean) near the origin:
+//   psi(u) = sum_{n in {-1,0,1}^3} 1/|u + n| + (2 pi / 3)|u|^2 + h(u),
+// with h harmonic for |u| < 2.  out: the K = (P+1)^2 real local coefficients
+// of h (h(u) = sum_k out[k] rho_k(u)); psi of a cell of edge L at r is
+// psi(r / L) / L.
+void build_periodic_green(int P, double* out);
+
 // Evaluate the real normalised regular harmonics rho(r) (K values) -- the same
 // recurrence the kernels use, exposed for host-side checks.
 void eval_rho(int p, const double r[3], double* out);

@@ -49,7 +49,7 @@ class fmm_params(ctypes.Structure):
         ("p2p_waves", ctypes.c_int32),
         ("graph", ctypes.c_int32),
         ("p2p_split", ctypes.c_int32),
-        ("reserved_", ctypes.c_int32),
+        ("hamiltonian", ctypes.c_int32),
     ]
 
 
@@ -176,7 +176,7 @@ def fmm_profile_select(plan, phase_mask: int, every: int = 1) -> int:
 def fmm_host_operator(order_p: int, which: int, point=None) -> np.ndarray:
     """FP64 operator tables a plan uploads (host only, no GPU needed)."""
     K = (order_p + 1) ** 2
-    size = {0: 343 * K * K, 1: 8 * K * K, 2: 8 * K * K, 3: K * K, 4: K}[which]
+    size = {0: 343 * K * K, 1: 8 * K * K, 2: 8 * K * K, 3: K * K, 4: K, 5: K}[which]
     out = np.zeros(max(size, 3))
     if which == 4:
         out[:3] = np.asarray(point, dtype=np.float64)
@@ -206,7 +206,8 @@ class Plan:
                  precision: str = "fp64", coulomb_k: float = 1.0, max_atoms: int = 1,
                  max_sites: int = 1, max_replicas: int = 1, check: bool = False,
                  stream=None, device=None, m2l_kernel: int = 0, m2l_chunk: int = 0,
-                 p2p_waves: int = 0, graph: bool = False, p2p_split: int = 0):
+                 p2p_waves: int = 0, graph: bool = False, p2p_split: int = 0,
+                 hamiltonian: bool = False):
         import torch
         dev = torch.device(device) if device is not None else torch.device("cuda")
         if dev.type == "cuda" and dev.index is None:
@@ -219,7 +220,7 @@ class Plan:
                                  PRECISIONS[precision], float(coulomb_k), int(max_atoms),
                                  int(max_sites), int(max_replicas), 1 if check else 0,
                                  int(m2l_kernel), int(m2l_chunk), int(p2p_waves),
-                                 1 if graph else 0, int(p2p_split), 0)
+                                 1 if graph else 0, int(p2p_split), 1 if hamiltonian else 0)
         self.periodic = periodic
         self.precision = precision
         self.dtype = torch.float64 if precision == "fp64" else torch.float32

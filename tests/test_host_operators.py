@@ -44,7 +44,7 @@ def test_plan_create_rejects_bad_params_without_gpu():
                 dict(boundary=2), dict(precision=3), dict(max_replicas=0),
                 dict(max_atoms=-5), dict(coulomb_k=float("nan")), dict(m2l_kernel=3),
                 dict(m2l_chunk=190), dict(graph=2), dict(p2p_waves=5), dict(p2p_split=5),
-                dict(p2p_split=-1), dict(reserved_=1), dict(order_p=11, m2l_kernel=2),
+                dict(p2p_split=-1), dict(hamiltonian=2), dict(hamiltonian=-1), dict(order_p=11, m2l_kernel=2),
                 dict(order_p=9, precision=0, m2l_kernel=2)):
         kw = dict(depth=2, order_p=4, boundary=0, precision=0, coulomb_k=1.0,
                   max_atoms=10, max_sites=1, max_replicas=1, check=0, m2l_kernel=0,
@@ -216,3 +216,25 @@ def test_lattice_operator_matches_ewald(neutral):
     err = np.abs(phi - ref).max() / np.abs(ref).max()
     assert err < 2e-5, err
     assert abs(np.mean(phi - ref)) < 2e-5 * np.abs(ref).max()
+
+
+def test_periodic_green_function_matches_ewald():
+    """The pair potential of the Hamiltonian-interpolation correction: the unit
+    cube's periodic Green's function rebuilt from the host coefficients of its
+    smooth part, sum_{27 images} 1/|u+n| + (2 pi/3)|u|^2 + h(u), against the
+    FP64 Ewald potential of one unit charge (tin-foil, background, zero mean),
+    and its self-image limit against the Ewald self term."""
+    P = 15
+    c = fmm.fmm_host_operator(P, 5)
+    imgs = np.array([[a, b, cc] for a in (-1, 0, 1) for b in (-1, 0, 1) for cc in (-1, 0, 1)],
+                    dtype=np.float64)
+    rng = np.random.default_rng(9)
+    for u in list(rng.uniform(-0.3, 0.3, (6, 3))) + [np.array([0.5, -0.2, 0.1])]:
+        psi = np.sum(1.0 / np.linalg.norm(u + imgs, axis=1))
+        psi += 2 * math.pi / 3 * float(u @ u) + float(c @ _rho(P, u)[0])
+        ref, _ = oracle.ewald(np.array([u, [0.0, 0.0, 0.0]]), np.array([0.0, 1.0]), [1.0] * 3,
+                              eps=1e-14)
+        assert psi == pytest.approx(ref[0], rel=1e-9, abs=1e-9), (u, psi, ref[0])
+    near = np.sum([1.0 / np.linalg.norm(n) for n in imgs if np.any(n)])
+    ref0, _ = oracle.ewald(np.zeros((1, 3)), np.ones(1), [1.0] * 3, eps=1e-14)
+    assert near + c[0] == pytest.approx(ref0[0], rel=1e-10, abs=1e-10)
