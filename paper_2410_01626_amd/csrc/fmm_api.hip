@@ -318,18 +318,21 @@ fmm_status enqueue_eval(fmm_plan_t P, const std::vector<fmmk::RepDesc>& rd, cons
         S_tot += d.S;
     }
     mark(P, 0);
-    // first launch: replica descriptors (up to kRepsPerSet, by value) and the
-    // cleared leaf and site counters; further descriptor sets follow
-    for (int f = 0; f < R; f += kRepsPerSet) {
-        RepSet set{};
-        set.first = f;
-        set.count = std::min(kRepsPerSet, R - f);
-        for (int i = 0; i < set.count; ++i) set.d[i] = rd[f + i];
-        if (f == 0) {
-            const int64_t nl = (int64_t)R * g.nleaf;
-            k_prologue<<<nblocks(std::max(nl, S_tot), 256), 256, 0, st>>>(set, P->reps, P->leaf_count,
-                                                                          nl, P->site_count, S_tot);
-        } else {
+    // replica descriptors: by value to the first kernel (which stores them)
+    // when they fit one set, else stored by k_set_reps launches first.  The
+    // leaf and site counters are already zero (plan creation, then the final
+    // reduction of every evaluation).
+    RepSet set0{};
+    if (R <= kRepsPerSet) {
+        set0.first = 0;
+        set0.count = R;
+        for (int i = 0; i < R; ++i) set0.d[i] = rd[i];
+    } else {
+        for (int f = 0; f < R; f += kRepsPerSet) {
+            RepSet set{};
+            set.first = f;
+            set.count = std::min(kRepsPerSet, R - f);
+            for (int i = 0; i < set.count; ++i) set.d[i] = rd[f + i];
             k_set_reps<<<1, kRepsPerSet, 0, st>>>(set, P->reps);
         }
     }
@@ -337,10 +340,11 @@ fmm_status enqueue_eval(fmm_plan_t P, const std::vector<fmmk::RepDesc>& rd, cons
     const unsigned ab = nblocks(maxn, 256);
     if (!g.periodic) {
         const int nb = (int)std::min<int64_t>(kBboxBlocks, ab);
-        k_bbox<T><<<dim3(nb, R), 256, 0, st>>>(x, reps, P->bbox_part);
+        k_bbox<T><<<dim3(nb, R), 256, 0, st>>>(x, set0, P->reps, P->bbox_part);
         k_bbox_final<<<R, 64, 0, st>>>(P->bbox_part, nb, P->dom);
+        set0.count = 0;  // stored by k_bbox
     }
-    k_charge_key<T><<<dim3(ab, R), 256, 0, st>>>(g, reps, x, qA, qB, site, lam, fa, P->dom, P->key,
+    k_charge_key<T><<<dim3(ab, R), 256, 0, st>>>(g, set0, P->reps, x, qA, qB, site, lam, fa, P->dom, P->key,
                                                  P->rank, P->leaf_count, P->site_count,
                                                  P->site_rank, P->status);
     if (g.nleaf <= kScanFuseCap && S_tot <= kScanFuseCap) {
@@ -416,7 +420,8 @@ fmm_status enqueue_eval(fmm_plan_t P, const std::vector<fmmk::RepDesc>& rd, cons
                                                        P->site_start, P->site_members, P->cphi, E,
                                                        dVdl, P->status, qA, qB, lam, fa, dVdl_t, reps,
                                                        ham && S_tot > 0 ? P->hc_e : nullptr,
-                                                       ham && S_tot > 0 ? P->hc_dl : nullptr);
+                                                       ham && S_tot > 0 ? P->hc_dl : nullptr,
+                                                       P->leaf_count, P->site_count);
     mark(P, -1);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return fail(P, FMM_E_HIP, std::string("kernel launch: ") + hipGetErrorString(e));
@@ -855,6 +860,10 @@ fmm_status fmm_plan_create(const fmm_params* prm, void* hip_stream, fmm_plan_t* 
     }
     std::vector<double> dom0(8 * RM, 0.0);
     up(P->dom, dom0.data(), dom0.size() * 8);
+    // counters start at zero; every evaluation's final reduction re-zeroes
+    // the ones it used
+    if (e == hipSuccess) e = hipMemset(P->leaf_count, 0, RM * (size_t)P->nleaf * 4);
+    if (e == hipSuccess) e = hipMemset(P->site_count, 0, (size_t)S * 4);
     if (prm->hamiltonian) {
         // periodic pair potential: h of the unit cube to degree kPMax and the
         // coefficients of its gradient (degree kPMax - 1); zero for open cells

@@ -206,27 +206,28 @@ __global__ void k_set_reps(RepSet set, RepDesc* __restrict__ reps) {
     if (i < set.count) reps[set.first + i] = set.d[i];
 }
 
-// Start of an evaluation: replica descriptors of the first set, leaf and site
-// counters cleared (a fill kernel: graph replays record no memset nodes).
-__global__ void k_prologue(RepSet set, RepDesc* __restrict__ reps, int32_t* __restrict__ leaf_count,
-                           int64_t nl, int32_t* __restrict__ site_count, int64_t ns) {
-    const int64_t i0 = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (i0 < set.count) reps[set.first + i0] = set.d[i0];
-    for (int64_t i = i0; i < nl || i < ns; i += (int64_t)gridDim.x * blockDim.x) {
-        if (i < nl) leaf_count[i] = 0;
-        if (i < ns) site_count[i] = 0;
-    }
+// The first kernel of an evaluation of at most kRepsPerSet replicas takes the
+// descriptors by value (set.count > 0): its blocks read them from the
+// argument and block (0, 0) stores them for the later kernels, so no launch
+// of its own is needed.  Otherwise (set.count = 0) k_set_reps stored them.
+__device__ __forceinline__ RepDesc first_rep(const RepSet& set, const RepDesc* reps, int r) {
+    return set.count > 0 ? set.d[r] : reps[r];
+}
+__device__ __forceinline__ void store_reps(const RepSet& set, RepDesc* reps) {
+    if (set.count > 0 && blockIdx.x == 0 && blockIdx.y == 0 && (int)threadIdx.x < set.count)
+        reps[set.first + threadIdx.x] = set.d[threadIdx.x];
 }
 
 // ------------------------------------------------------------------ domain
 
 // Per-block min/max of the coordinates (open boundaries): part[b] = {min xyz, max xyz}.
 template <typename T>
-__global__ __launch_bounds__(256) void k_bbox(const T* __restrict__ x,
-                                              const RepDesc* __restrict__ reps,
+__global__ __launch_bounds__(256) void k_bbox(const T* __restrict__ x, RepSet set,
+                                              RepDesc* __restrict__ reps,
                                               double* __restrict__ part) {
     __shared__ double smin[3][256], smax[3][256];
-    const RepDesc rd = reps[blockIdx.y];
+    store_reps(set, reps);
+    const RepDesc rd = first_rep(set, reps, blockIdx.y);
     double mn[3] = {1e300, 1e300, 1e300}, mx[3] = {-1e300, -1e300, -1e300};
     for (int64_t i = rd.a0 + blockIdx.x * 256 + threadIdx.x; i < rd.a0 + rd.n;
          i += (int64_t)gridDim.x * 256)
@@ -320,14 +321,15 @@ __device__ __forceinline__ int32_t agg_slot(const AggPlan& pl, int32_t got) {
 // formed in FP64 when the atoms are gathered into leaf order.
 template <typename T>
 __global__ __launch_bounds__(256) void k_charge_key(
-    Geo g, const RepDesc* __restrict__ reps, const T* __restrict__ x, const T* __restrict__ qA,
+    Geo g, RepSet set, RepDesc* __restrict__ reps, const T* __restrict__ x, const T* __restrict__ qA,
     const T* __restrict__ qB, const int32_t* __restrict__ site,
     const double* __restrict__ lam, FormArgs<T> fa, double* __restrict__ dom_all,
     int32_t* __restrict__ key, int32_t* __restrict__ rank, int32_t* __restrict__ leaf_count_all,
     int32_t* __restrict__ site_count, int32_t* __restrict__ site_rank,
     int32_t* __restrict__ status) {
     const int r = blockIdx.y;
-    const RepDesc rd = reps[r];
+    store_reps(set, reps);
+    const RepDesc rd = first_rep(set, reps, r);
     const double box = rd.box;
     double* dom = dom_all + 8 * r;
     int32_t* leaf_count = leaf_count_all + (size_t)r * g.nleaf;
@@ -1640,7 +1642,8 @@ __global__ __launch_bounds__(64 * kNW) void k_near_far(
     const bool far = g.has_far;
     // loads issued up front, in flight with the neighbour set-up: the gradient
     // table entries of this thread and, for the first NT targets, the caller
-    // index, site and qB - qA needed by the outputs
+    // index (their site and charges are loaded after the pair loop, which
+    // hides that latency)
     const bool ge = far && tid < 3 * g.Kg;
     int32_t gi4[4];
     T gc4[4];
@@ -1651,10 +1654,6 @@ __global__ __launch_bounds__(64 * kNW) void k_near_far(
     }
     const bool tpre = tid < tn;
     const int32_t pre_i = tpre ? perm[tb + tid] : 0;
-    const int32_t pre_s = tpre ? site[pre_i] : -1;
-    // site weight of phi: qB - qA (two forms), or 1 (four forms: the site sums
-    // weight phi by the form coordinates themselves)
-    const double pre_dq = tpre ? (unit_dq ? 1.0 : (double)qB[pre_i] - (double)qA[pre_i]) : 0.0;
     const double edge = dom[3];
     const double h = edge / g.nb;
     int cx, cy, cz;
@@ -1721,11 +1720,6 @@ __global__ __launch_bounds__(64 * kNW) void k_near_far(
             gr[a][r] = v;
         }
     }
-    if (tpre) {
-        t_idx[tid] = pre_i;
-        t_site[tid] = pre_s;
-        t_dq[tid] = pre_dq;
-    }
     __syncthreads();
     const int total = nb_pre[27];
     const T ih = (T)(1.0 / h);
@@ -1740,29 +1734,48 @@ __global__ __launch_bounds__(64 * kNW) void k_near_far(
     __shared__ int w_first[kNW + 1];
     for (int t0 = 0; t0 < tn; t0 += 64 * kNW) {
         const int nch = min(kNW, (tn - t0 + 63) / 64);
-        if (tid == 0) {
-            int w[kNW];
-            int gs[kNW];
-            for (int c = 0; c < nch; ++c) {
-                const int tc = min(64, tn - t0 - 64 * c);
-                int gz = 1;
-                while (gz < tc) gz <<= 1;
-                gs[c] = gz;
-                w[c] = 1;
-            }
-            for (int k = nch; k < kNW; ++k) {
-                int best = 0;
-                for (int c = 1; c < nch; ++c)  // largest gs / w, ties to the lower chunk
-                    if (gs[c] * w[best] > gs[best] * w[c]) best = c;
-                ++w[best];
-            }
-            w_first[0] = 0;
-            for (int c = 0; c < nch; ++c) w_first[c + 1] = w_first[c] + w[c];
+        // every thread derives the same split (no barrier): w[c] wavefronts
+        // for chunk c, each extra one to the largest gs / w (ties: lower c);
+        // all indices are compile-time, so the arrays stay in registers
+        int w[kNW], gs[kNW], wf[kNW + 1];
+#pragma unroll
+        for (int c = 0; c < kNW; ++c) {
+            const int tc = min(64, tn - t0 - 64 * c);
+            int gz = 1;
+            while (gz < tc) gz <<= 1;
+            gs[c] = gz;
+            w[c] = c < nch ? 1 : 0;
         }
-        __syncthreads();
-        int chunk = 0;
-        while (chunk + 1 < nch && w_first[chunk + 1] <= wave) ++chunk;
-        const int wpc = w_first[chunk + 1] - w_first[chunk], slice = wave - w_first[chunk];
+        for (int e = nch; e < kNW; ++e) {
+            int best = 0, wb = w[0], gb = gs[0];
+#pragma unroll
+            for (int c = 1; c < kNW; ++c)
+                if (c < nch && gs[c] * wb > gb * w[c]) {
+                    best = c;
+                    wb = w[c];
+                    gb = gs[c];
+                }
+#pragma unroll
+            for (int c = 0; c < kNW; ++c) w[c] += c == best ? 1 : 0;
+        }
+        wf[0] = 0;
+#pragma unroll
+        for (int c = 0; c < kNW; ++c) wf[c + 1] = wf[c] + w[c];
+        int chunk = 0, wc0 = 0, wc1 = wf[1];
+#pragma unroll
+        for (int c = 1; c < kNW; ++c)
+            if (c < nch && wf[c] <= wave) {
+                chunk = c;
+                wc0 = wf[c];
+                wc1 = wf[c + 1];
+            }
+        const int wpc = wc1 - wc0, slice = wave - wc0;
+        // kept for the energy sum at the end of the round (read after barriers)
+        if (tid <= kNW) {
+#pragma unroll
+            for (int c = 0; c <= kNW; ++c)
+                if (c == tid) w_first[c] = wf[c];
+        }
         const int tc = min(64, tn - t0 - 64 * chunk);
         int gsz = 1;
         while (gsz < tc) gsz <<= 1;
@@ -1775,7 +1788,7 @@ __global__ __launch_bounds__(64 * kNW) void k_near_far(
         T ph = T(0), fx = T(0), fy = T(0), fz = T(0);
         for (int s0 = 0; s0 < total; s0 += CAP) {
             const int cnt = min(CAP, total - s0);
-            __syncthreads();
+            if (t0 > 0 || s0 > 0) __syncthreads();  // the tile's previous readers are done
             if (total <= CAP) {
                 // the whole neighbourhood in one pass: wavefront w copies
                 // neighbours w, w + kNW, ..., lane j their atom j (all loads
@@ -1868,6 +1881,16 @@ __global__ __launch_bounds__(64 * kNW) void k_near_far(
             sweep(max(jb, own_b), min(je, own_e), std::true_type{});
             sweep(max(jb, own_e), je, std::false_type{});
         }
+        // sites and charges of the first NT targets (for the outputs), in
+        // flight during the far-field evaluation
+        int32_t pre_s = -1;
+        double pre_dq = 0.0;
+        if (t0 == 0 && tpre) {
+            pre_s = site[pre_i];
+            // site weight of phi: qB - qA (two forms), or 1 (four forms: the
+            // site sums weight phi by the form coordinates themselves)
+            pre_dq = unit_dq ? 1.0 : (double)qB[pre_i] - (double)qA[pre_i];
+        }
         if (far && tv) {
             // far field, orders m = slice + wpc grp, stepping by wpc ngrp
             T fp = T(0), gx = T(0), gy = T(0), gz = T(0);
@@ -1904,6 +1927,11 @@ __global__ __launch_bounds__(64 * kNW) void k_near_far(
             part[wave][1][tl] = fx;
             part[wave][2][tl] = fy;
             part[wave][3][tl] = fz;
+        }
+        if (t0 == 0 && tpre) {
+            t_idx[tid] = pre_i;
+            t_site[tid] = pre_s;
+            t_dq[tid] = pre_dq;
         }
         __syncthreads();
         // the first wavefront of each chunk adds the chunk's slices in order
@@ -2104,6 +2132,7 @@ __global__ __launch_bounds__(256) void k_hcorr(Geo g, int R, const RepDesc* __re
 // Final reductions: block r < R -> E_r = k_e / 2 sum of replica r's leaf
 // partials (fixed order); block R + s -> dVdl_s = sum over global site s's
 // atoms in caller order (four forms: dV/dlambda_p and dV/dlambda_t of site s).
+// Also clears the evaluation's leaf and site counters.
 template <typename T>
 __global__ __launch_bounds__(256) void k_reduce(Geo g, int R, int64_t nparts,
                                                 const double* __restrict__ leaf_energy,
@@ -2116,11 +2145,20 @@ __global__ __launch_bounds__(256) void k_reduce(Geo g, int R, int64_t nparts,
                                                 FormArgs<T> fa, double* __restrict__ dVdl_t,
                                                 const RepDesc* __restrict__ reps,
                                                 const double* __restrict__ hc_e,
-                                                const double* __restrict__ hc_dl) {
+                                                const double* __restrict__ hc_dl,
+                                                int32_t* __restrict__ leaf_count,
+                                                int32_t* __restrict__ site_count) {
     __shared__ double red[256], red_t[256];
     __shared__ int32_t mem[kSiteCap];
     const int t = threadIdx.x;
     const int b = blockIdx.x;
+    // the leaf and site counters of this evaluation are spent: leave them
+    // zero for the next one (the plan clears them once at creation)
+    if (b < R) {
+        for (int i = t; i < g.nleaf; i += 256) leaf_count[(size_t)b * g.nleaf + i] = 0;
+    } else if (t == 0) {
+        site_count[b - R] = 0;
+    }
     const bool four = fa.qC != nullptr && b >= R;
     double v = 0.0, vt = 0.0;
     // four forms: cphi = k_e phi, and the two site derivatives (Methods, eq 2)
