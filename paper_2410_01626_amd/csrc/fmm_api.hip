@@ -413,7 +413,7 @@ fmm_status enqueue_eval(fmm_plan_t P, const std::vector<fmmk::RepDesc>& rd, cons
     mark(P, 7);
     const bool ham = P->prm.hamiltonian != 0;
     if (ham && S_tot > 0)
-        k_hcorr<T><<<(unsigned)S_tot, 256, 0, st>>>(g, R, reps, P->site_start, P->site_members, x, qA,
+        k_hcorr<T><<<(unsigned)S_tot, kHcorrThreads, 0, st>>>(g, R, reps, P->site_start, P->site_members, x, qA,
                                                     qB, lam, P->green, F, P->hc_e, P->hc_dl,
                                                     P->status);
     k_reduce<T><<<(unsigned)(R + S_tot), 256, 0, st>>>(g, R, g.nleaf * P->p2p_split, P->leaf_energy,

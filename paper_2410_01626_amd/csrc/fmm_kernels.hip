@@ -2002,8 +2002,9 @@ __global__ __launch_bounds__(64 * kNW) void k_near_far(
 //   psi = (1/L) [sum_{n in {-1,0,1}^3} 1/|u + n| + (2 pi / 3)|u|^2 + h(u)],
 // with h from its degree-kPMax harmonic coefficients (green) and grad h from
 // the gradient coefficients that follow them.  All arithmetic is FP64.
+constexpr int kHcorrThreads = 1024;  // threads of a correction block
 template <typename T>
-__global__ __launch_bounds__(256) void k_hcorr(Geo g, int R, const RepDesc* __restrict__ reps,
+__global__ __launch_bounds__(kHcorrThreads) void k_hcorr(Geo g, int R, const RepDesc* __restrict__ reps,
                                                const int32_t* __restrict__ site_start,
                                                const int32_t* __restrict__ site_members,
                                                const T* __restrict__ x, const T* __restrict__ qA,
@@ -2012,11 +2013,14 @@ __global__ __launch_bounds__(256) void k_hcorr(Geo g, int R, const RepDesc* __re
                                                double* __restrict__ hc_e, double* __restrict__ hc_dl,
                                                int32_t* __restrict__ status) {
     constexpr int kH = kSiteCap / 4;  // atoms of a site staged in LDS
+    constexpr int kHPair = 8;         // sites up to this size: pair tables (n^2 <= 64)
+    constexpr int kHW = kHcorrThreads / 64;     // wavefronts: one harmonic order each
+    __shared__ double pp[kHW][kHPair * kHPair][4];
     __shared__ int32_t mem[kSiteCap];
     __shared__ double sp[kH][4];  // x, y, z, d
     __shared__ double gc[kKMax + 3 * kKgMax];
     __shared__ RhoLds<double> rho;
-    __shared__ double red[256];
+    __shared__ double red[kHcorrThreads];
     const int s = blockIdx.x, t = threadIdx.x;
     int r = 0;
     while (r + 1 < R && s >= reps[r].s0 + reps[r].S) ++r;
@@ -2032,14 +2036,14 @@ __global__ __launch_bounds__(256) void k_hcorr(Geo g, int R, const RepDesc* __re
         }
         return;
     }
-    for (int i = t; i < n; i += 256) mem[i] = site_members[m0 + i];
+    for (int i = t; i < n; i += kHcorrThreads) mem[i] = site_members[m0 + i];
     if (g.periodic) {
-        for (int k = t; k < kKMax + 3 * kKgMax; k += 256) gc[k] = green[k];
-        load_rho_lds<double, 256>(rho, kPMax);
+        for (int k = t; k < kKMax + 3 * kKgMax; k += kHcorrThreads) gc[k] = green[k];
+        load_rho_lds<double, kHcorrThreads>(rho, kPMax);
     }
     __syncthreads();
     lds_sort<kSiteCap>(mem, n);  // caller order: a fixed summation order
-    for (int i = t; i < n; i += 256) {
+    for (int i = t; i < n; i += kHcorrThreads) {
         const int32_t a = mem[i];
         sp[i][0] = (double)x[3 * (size_t)a];
         sp[i][1] = (double)x[3 * (size_t)a + 1];
@@ -2050,12 +2054,97 @@ __global__ __launch_bounds__(256) void k_hcorr(Geo g, int R, const RepDesc* __re
     // self-image limit of the unit cube: sum over the 26 neighbour images + h(0)
     const double psi0 = 6.0 + 12.0 / sqrt(2.0) + 8.0 / sqrt(3.0) + gc[0];
     double v = 0.0;
-    for (int i = t; i < n; i += 256) {
+    if (n <= kHPair) {
+        // sites of up to 8 atoms: lane q of every wavefront takes ordered
+        // pair q (up to 64 pairs); wavefront w takes harmonic order w of h
+        // and every 16th of the 27 direct images, so every lane of a
+        // wavefront runs the same recurrence steps; the partial tables are
+        // added in wavefront order
+        const int np = n * n, wv = t >> 6, q = t & 63;
+        const int i = q < np ? q / n : 0, j = q < np ? q - i * n : 0;
+        double ps = 0.0, qx = 0.0, qy = 0.0, qz = 0.0;
+        if (q < np && i != j) {
+            const double rx = sp[i][0] - sp[j][0], ry = sp[i][1] - sp[j][1], rz = sp[i][2] - sp[j][2];
+            if (!g.periodic) {
+                if (wv == 0) {
+                    const double r2 = rx * rx + ry * ry + rz * rz, ir = 1.0 / sqrt(r2);
+                    const double ir3 = ir * ir * ir;
+                    ps = ir;
+                    qx = -rx * ir3;
+                    qy = -ry * ir3;
+                    qz = -rz * ir3;
+                }
+            } else {
+                double u[3] = {rx / L, ry / L, rz / L};
+                for (int c = 0; c < 3; ++c) u[c] -= rint(u[c]);
+                if (wv == 0) {
+                    ps = 2.0 * kPi / 3.0 * (u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
+                    qx = 4.0 * kPi / 3.0 * u[0];
+                    qy = 4.0 * kPi / 3.0 * u[1];
+                    qz = 4.0 * kPi / 3.0 * u[2];
+                }
+                for (int im = wv; im < 27; im += kHW) {
+                    const double vx = u[0] + (im / 9 - 1), vy = u[1] + ((im / 3) % 3 - 1),
+                                 vz = u[2] + (im % 3 - 1);
+                    const double r2 = vx * vx + vy * vy + vz * vz, ir = 1.0 / sqrt(r2);
+                    const double ir3 = ir * ir * ir;
+                    ps += ir;
+                    qx -= vx * ir3;
+                    qy -= vy * ir3;
+                    qz -= vz * ir3;
+                }
+                const double* gh = gc + kKMax;
+                for_rho_orders<double>(kPMax, rho, wv, kHW, u[0], u[1], u[2],
+                                       [&](int kc, bool has_s, double re, double im_) {
+                                           ps += gc[kc] * re;
+                                           if (has_s) ps += gc[kc + 1] * im_;
+                                           if (kc < kKgMax) {
+                                               qx += gh[kc] * re;
+                                               qy += gh[kKgMax + kc] * re;
+                                               qz += gh[2 * kKgMax + kc] * re;
+                                               if (has_s) {
+                                                   qx += gh[kc + 1] * im_;
+                                                   qy += gh[kKgMax + kc + 1] * im_;
+                                                   qz += gh[2 * kKgMax + kc + 1] * im_;
+                                               }
+                                           }
+                                       });
+                ps /= L;
+                qx /= L * L;
+                qy /= L * L;
+                qz /= L * L;
+            }
+        }
+        if (q < np) {
+            pp[wv][q][0] = ps;
+            pp[wv][q][1] = qx;
+            pp[wv][q][2] = qy;
+            pp[wv][q][3] = qz;
+        }
+        __syncthreads();
+        // table sums in wavefront order, one thread per (pair, component)
+        double acc = 0.0;
+        const int qc = t >> 2, cc = t & 3;
+        if (qc < np)
+            for (int w = 0; w < kHW; ++w) acc += pp[w][qc][cc];
+        __syncthreads();
+        if (qc < np) pp[0][qc][cc] = acc;
+        __syncthreads();
+    }
+    for (int i = t; i < n; i += kHcorrThreads) {
         double e = 0.0, gx = 0.0, gy = 0.0, gz = 0.0;
         for (int j = 0; j < n; ++j) {
             const double dj = sp[j][3];
             if (j == i) {
                 if (g.periodic) e += dj * psi0 / L;
+                continue;
+            }
+            if (n <= kHPair) {  // psi and its gradient from the pair tables
+                const int q = i * n + j;
+                e += dj * pp[0][q][0];
+                gx += dj * pp[0][q][1];
+                gy += dj * pp[0][q][2];
+                gz += dj * pp[0][q][3];
                 continue;
             }
             double rx = sp[i][0] - sp[j][0], ry = sp[i][1] - sp[j][1], rz = sp[i][2] - sp[j][2];
@@ -2119,7 +2208,7 @@ __global__ __launch_bounds__(256) void k_hcorr(Geo g, int R, const RepDesc* __re
     }
     red[t] = v;
     __syncthreads();
-    for (int st = 128; st > 0; st >>= 1) {
+    for (int st = kHcorrThreads / 2; st > 0; st >>= 1) {
         if (t < st) red[t] += red[t + st];
         __syncthreads();
     }
