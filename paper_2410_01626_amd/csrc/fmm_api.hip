@@ -47,6 +47,7 @@ struct fmm_plan_s {
     // corrections, and (periodic) the Green's function coefficients of the
     // unit cube (degree kPMax) followed by those of its gradient (3 x kPMax^2)
     double *hc_e = nullptr, *hc_dl = nullptr, *green = nullptr;
+    int32_t* leaf_order = nullptr;  // near-field order of the leaves (largest work first)
     double* dVdl_tmp = nullptr;
     double* E_tmp = nullptr;
     fmmk::RepDesc* reps = nullptr;  // device replica descriptors (max_replicas)
@@ -392,18 +393,25 @@ fmm_status enqueue_eval(fmm_plan_t P, const std::vector<fmmk::RepDesc>& rd, cons
     // downward pass: ancestors' local expansions and the L2L into the leaves
     mark(P, 5);
     const int l0 = g.periodic ? 0 : g.lmin;
-    if (g.depth >= 1 && g.depth - 1 >= l0)
-        k_downward<T><<<dim3(1u << (3 * (g.depth - 1)), R), kTreeThreads, 0, st>>>(
+    // the downward launch carries one extra block per replica that orders the
+    // leaves for the near field by decreasing work
+    int32_t* order = nullptr;
+    if (g.depth >= 1 && g.depth - 1 >= l0) {
+        if (g.nleaf <= kOrderCap) order = P->leaf_order;
+        const unsigned nbx = (1u << (3 * (g.depth - 1))) + (order ? 1u : 0u);
+        k_downward<T><<<dim3(nbx, R), kTreeThreads, 0, st>>>(
             g, l0, loc, (const T*)P->l2lT, (const T*)P->l2l_seg, mult, (const T*)P->m2mT,
             (const T*)P->m2m_seg, P->leaf_part, P->box_part, P->latT, P->lat_seg, P->root_m, P->root_l,
-            P->dom);
+            P->dom, P->leaf_start, order);
+    }
     mark(P, 6);
     switch (P->p2p_waves) {
 #define FMM_NEAR(NWV)                                                                            \
     case NWV:                                                                                    \
         k_near_far<T, NWV><<<dim3(g.nleaf * P->p2p_split, R), 64 * NWV, 0, st>>>(               \
             g, P->p2p_split, reps, pos, P->leaf_start, P->perm, P->dom, loc, P->gidx,              \
-            (const T*)P->gcoef, qA, qB, site, phi, F, P->leaf_energy, P->cphi, fa.qC != nullptr);  \
+            (const T*)P->gcoef, qA, qB, site, phi, F, P->leaf_energy, P->cphi, fa.qC != nullptr,   \
+            order);                                                                                \
         break;
         FMM_NEAR(4)
         FMM_NEAR(8)
@@ -578,6 +586,7 @@ fmm_status fmm_plan_create(const fmm_params* prm, void* hip_stream, fmm_plan_t* 
     ok &= dev_alloc(P, (void**)&P->rank, N * 4);
     ok &= dev_alloc(P, (void**)&P->leaf_count, RM * P->nleaf * 4);
     ok &= dev_alloc(P, (void**)&P->leaf_start, RM * ((size_t)P->nleaf + 1) * 4);
+    ok &= dev_alloc(P, (void**)&P->leaf_order, RM * (size_t)P->nleaf * 4);
     ok &= dev_alloc(P, (void**)&P->site_count, S * 4);
     ok &= dev_alloc(P, (void**)&P->site_start, (S + 1) * 4);
     ok &= dev_alloc(P, (void**)&P->site_rank, N * 4);

@@ -886,6 +886,27 @@ __global__ __launch_bounds__(kTreeThreads) void k_m2m(Geo g, int lev, T* __restr
     }
 }
 
+// Near-field block order: leaves by decreasing atom count, so that the
+// largest leaves are dispatched first and the smaller ones fill in behind
+// them (longest-processing-time order; with 512 leaves on 256 compute units
+// the unordered tail costs ~15% of the near field; ordering by the full work,
+// own atoms x neighbourhood atoms, gains < 1% more).  Key: count above the
+// leaf index (ties: lower leaf first); needs nleaf <= kOrderCap.
+// buf: kOrderCap ints of LDS.
+constexpr int kOrderCap = 4096;
+__device__ void leaf_work_order(const Geo& g, const int32_t* __restrict__ leaf_start,
+                                int32_t* __restrict__ order, int32_t* key) {
+    const int nl = g.nleaf;
+    constexpr int kMaxKey = (1 << 19) - 1;
+    for (int i = threadIdx.x; i < nl; i += blockDim.x) {
+        const int c = min(leaf_start[i + 1] - leaf_start[i], kMaxKey);
+        key[i] = ((kMaxKey - c) << 12) | i;
+    }
+    __syncthreads();
+    lds_sort<kOrderCap>(key, nl);
+    for (int i = threadIdx.x; i < nl; i += blockDim.x) order[i] = key[i] & (kOrderCap - 1);
+}
+
 // Downward pass in one launch: one block per box b of level depth - 1 forms
 // lambda~ of its ancestors from level l0 down (L2L of the parent's total plus
 // the box's own M2L sum, in FP64) and adds the L2L of lambda~_b into its 8
@@ -901,8 +922,15 @@ __global__ __launch_bounds__(kTreeThreads) void k_downward(
     const T* __restrict__ mult_all, const T* __restrict__ m2m0, const T* __restrict__ m2m0_seg,
     const double* __restrict__ leaf_part_all, const double* __restrict__ box_part_all,
     const double* __restrict__ latT, const double* __restrict__ lat_seg, double* __restrict__ root_m_all,
-    double* __restrict__ root_l_all, double* __restrict__ dom_all) {
+    double* __restrict__ root_l_all, double* __restrict__ dom_all,
+    const int32_t* __restrict__ leaf_start_all, int32_t* __restrict__ leaf_order_all) {
     __shared__ double xs[8 * kKMax], part[8 * kTreeThreads];
+    if (leaf_order_all && blockIdx.x + 1 == gridDim.x) {
+        // the extra last block: the near-field order of this replica's leaves
+        leaf_work_order(g, leaf_start_all + (size_t)blockIdx.y * (g.nleaf + 1),
+                        leaf_order_all + (size_t)blockIdx.y * g.nleaf, (int32_t*)part);
+        return;
+    }
     __shared__ double v[kKMax], ps[16];
     __shared__ T anc[kDMax * kKMax];
     TriPart<T, kTriUpper> tp;
@@ -1608,7 +1636,8 @@ __global__ __launch_bounds__(64 * kNW) void k_near_far(
     const int32_t* __restrict__ gidx, const T* __restrict__ gcoef,
     const T* __restrict__ qA, const T* __restrict__ qB, const int32_t* __restrict__ site,
     T* __restrict__ phi_out, T* __restrict__ F_out,
-    double* __restrict__ leaf_energy_all, double* __restrict__ cphi, int unit_dq) {
+    double* __restrict__ leaf_energy_all, double* __restrict__ cphi, int unit_dq,
+    const int32_t* __restrict__ leaf_order_all) {
     constexpr int NT = 64 * kNW;
     // sources staged per pass: the whole 27-leaf neighbourhood of a typical leaf
     constexpr int CAP = sizeof(T) == 4 ? 2048 : 1024;
@@ -1630,7 +1659,9 @@ __global__ __launch_bounds__(64 * kNW) void k_near_far(
     __shared__ double t_dq[NT];
     // block `sub` of the leaf takes targets 32 sub .. 32 sub + 31 (the last
     // block of the leaf all the rest); one block per leaf takes them all
-    const int leaf = blockIdx.x / nsplit, sub = blockIdx.x - leaf * nsplit;
+    // leaves in the order given by leaf_work_order (largest first), if any
+    const int lslot = blockIdx.x / nsplit, sub = blockIdx.x - lslot * nsplit;
+    const int leaf = leaf_order_all ? leaf_order_all[(size_t)blockIdx.y * g.nleaf + lslot] : lslot;
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     const int lb = leaf_start[leaf], ln = leaf_start[leaf + 1] - lb;
     const int ta = 32 * sub;
