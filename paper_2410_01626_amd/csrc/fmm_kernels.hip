@@ -577,7 +577,23 @@ __global__ __launch_bounds__(kLeafThreads) void k_leaf_p2m(
     load_rho_lds<T, kLeafThreads>(rho, g.p);
     const bool sorted = n <= kSortCap;
     int32_t idx[kLeafIdx];
-    if (sorted) {
+    if (n <= kLeafThreads) {
+        // one atom per thread: its place in caller order is the number of the
+        // leaf's (distinct) atom indices below its own
+        __shared__ int32_t srt[kLeafThreads];
+        const int32_t mine_i = tid < n ? perm[b + tid] : 0;
+        if (tid < n) sbuf[tid] = mine_i;
+        __syncthreads();
+        if (tid < n) {
+            int r = 0;
+            for (int k = 0; k < n; ++k) r += sbuf[k] < mine_i ? 1 : 0;
+            srt[r] = mine_i;
+        }
+        __syncthreads();
+        idx[0] = tid < n ? srt[tid] : 0;
+#pragma unroll
+        for (int m = 1; m < kLeafIdx; ++m) idx[m] = 0;
+    } else if (sorted) {
         for (int i = tid; i < n; i += kLeafThreads) sbuf[i] = perm[b + i];
         __syncthreads();
         lds_sort<kSortCap>(sbuf, n);
