@@ -538,8 +538,10 @@ __device__ void lds_sort(int32_t* v, int n) {
 }
 
 // Per leaf, one block of 256 threads: sort the leaf's atoms by caller index
-// (stable binning), gather (x - c_leaf, q) into the sorted particle array with
-// the interpolated charge q = qA + lambda_s (qB - qA) formed in FP64, and form
+// (stable binning; leaves of up to 256 atoms by counting ranks, larger ones by
+// a bitonic sort), gather (x - c_leaf, q) into the sorted particle array with
+// the interpolated charge (q = qA + lambda_s (qB - qA); four forms: eq 2)
+// formed in FP64, and form
 // the leaf multipole mu~_leaf = sum_j q_j rho((x_j - c_leaf) / h) (P2M).
 // P2M runs in passes of 64 atoms, the harmonic orders split over the 4
 // wavefronts: each writes its part of q rho of every atom into the atom's LDS
