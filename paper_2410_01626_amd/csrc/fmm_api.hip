@@ -772,8 +772,8 @@ fmm_status fmm_plan_create(const fmm_params* prm, void* hip_stream, fmm_plan_t* 
         P->m2l_lds = esz * ((size_t)mg.RP * mg.SA + (size_t)fmmk::kM2LTile * mg.SB);
         const int KC = mg.KP / 8;
         if (P->m2l_mode == 3) {
-            // one staging buffer: operator (2 KC RP chunks) + sources (2 KC 80 chunks)
-            const size_t one = (size_t)16 * 2 * KC * (mg.RP + fmmk::kM2LTile);
+            // one staging buffer: operator (2 KC RP chunks) + sources ((2 KC + 1) 80 chunks)
+            const size_t one = (size_t)16 * (2 * KC * mg.RP + (2 * KC + 1) * fmmk::kM2LTile);
             P->m2l_nbuf = 2 * one <= fmmk::kLdsBytes ? 2 : 1;
             P->m2l_lds = P->m2l_nbuf * one;
         }

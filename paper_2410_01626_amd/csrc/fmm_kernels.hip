@@ -1443,9 +1443,13 @@ __global__ __launch_bounds__(64 * kM2LWaves) void k_m2l_f64(Geo g, M2LGeom mg, c
 //               k = 8 kc .. 8 kc + 7), 2 KC RP chunks, zero padded;
 //   box b:      [part][KC] chunks, row nbox of each replica all zero.
 // A step (one offset) copies the operator contiguously and, per target
-// column, the source box's 2 KC chunks into [part][KC][column] order; the
-// fragment reads of both are then 16 consecutive 16-byte chunks per quarter
-// wavefront (no LDS bank conflicts).  With two buffers the copy of offset
+// column, the source box's 2 KC chunks plus one pad chunk, consecutive lanes
+// on consecutive chunks of one source row (a few cache lines per copy
+// instruction instead of one per lane); the source box of every column for
+// the offset two steps ahead is tabulated in LDS by the column's thread.  The
+// odd row stride 2 KC + 1 puts the 16 columns of a fragment read in distinct
+// LDS banks, and the operator fragments are 16 consecutive 16-byte chunks per
+// quarter wavefront.  With two buffers the copy of offset
 // i + 1 is in flight while offset i is multiplied: one wait and one barrier
 // per offset.  Products Th mh + Th ml + Tl mh accumulate in FP32.
 //
@@ -1457,7 +1461,8 @@ __global__ __launch_bounds__(64 * kM2LWaves) void k_m2l_f64(Geo g, M2LGeom mg, c
 // on the B fragments) and its result is S times the accumulator (at the
 // store).  Offset chunks are then equal for all classes.
 constexpr int kM2LThreads = 64 * kM2LWaves;
-static_assert(kM2LThreads == 4 * kM2LTile, "source copy mapping: 4 lanes per column");
+// source copy slots per lane: kM2LTile columns of up to 2 KC + 1 = 33 chunks
+constexpr int kM2LSlots = (kM2LTile * (8 * kM2LMaxKs + 1) + kM2LThreads - 1) / kM2LThreads;
 
 __device__ __forceinline__ void lds_dma16(const uint4* gsrc, uint4* lds_wave_base) {
     __builtin_amdgcn_global_load_lds((const void*)gsrc,
@@ -1475,18 +1480,21 @@ __global__ __launch_bounds__(kM2LThreads) void k_m2l_bf16x3(Geo g, M2LGeom mg,
                                                            float* __restrict__ loc, float* __restrict__ part) {
     extern __shared__ __align__(16) uint4 lds_q[];
     __shared__ int col_box[kM2LTile];
+    __shared__ int src_box[2][kM2LTile];  // source box per column, two offsets ahead
     const int KC = mg.KP / 8;
-    const int a_chunks = 2 * KC * mg.RP, b_chunks = 2 * KC * kM2LTile;
+    // sources: per target column its 2 KC chunks and one pad chunk (odd row
+    // stride: the 16 columns of a fragment read fall in distinct LDS banks)
+    const int SBc = 2 * KC + 1;
+    const int a_chunks = 2 * KC * mg.RP, b_chunks = SBc * kM2LTile;
     const M2LTask tk = tasks[blockIdx.x];
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     msplit += (size_t)blockIdx.y * (g.nbox + 1) * 2 * KC;
     loc += (size_t)blockIdx.y * g.nbox * g.Kp;
     if (part) part += (size_t)blockIdx.y * mg.nchunk * mg.nt_all * g.Kp;
     const bool active = tk.tile * kM2LTile + 16 * wave < mg.ncol;
-    // the staging lane's source column and its place in the tree
-    const int jc = tid % kM2LTile, q = tid / kM2LTile;
+    // threads < kM2LTile: their target column and its place in the tree
     int clev = 0, ctx = 0, cty = 0, ctz = 0;
-    const bool col_ok = m2l_column(g, tk.cls, tk.tile, jc, clev, ctx, cty, ctz);
+    const bool col_ok = tid < kM2LTile && m2l_column(g, tk.cls, tk.tile, tid, clev, ctx, cty, ctz);
     const int cn = 1 << clev;
     const int64_t clo = lev_offset(clev);
     if (tid < kM2LTile) col_box[tid] = col_ok ? (int)(clo + morton(ctx, cty, ctz)) : -1;
@@ -1495,29 +1503,44 @@ __global__ __launch_bounds__(kM2LThreads) void k_m2l_bf16x3(Geo g, M2LGeom mg,
     const int16_t* ol = olist + tk.cls * 189;
     int ol_reg = lane < o1 - o0 ? ol[o0 + lane] : 0;
     const int fx = (tk.cls & 4) ? -1 : 1, fy = (tk.cls & 2) ? -1 : 1, fz = (tk.cls & 1) ? -1 : 1;
-
-    auto issue = [&](int oc, uint4* dst) {
+    // source copy: buffer chunk e = t kM2LThreads + tid is chunk sc[t] of column
+    // sj[t], so consecutive lanes read consecutive chunks of one source row
+    int sj[kM2LSlots], sc[kM2LSlots];
+#pragma unroll
+    for (int t = 0; t < kM2LSlots; ++t) {
+        const int e = t * kM2LThreads + tid;
+        sj[t] = min(e / SBc, kM2LTile - 1);
+        const int c = e - (e / SBc) * SBc;
+        sc[t] = e < b_chunks ? (c == 2 * KC ? 0 : c) : -1;  // pad chunk: any in-bounds source
+    }
+    // the source boxes of offset slot oc for the block's columns (threads < kM2LTile)
+    auto sources = [&](int oc, int* dst) {
         const int st = oc - o0;
         if (st > 0 && (st & 63) == 0) ol_reg = ol[min(oc + lane, o1 - 1)];
-        // canonical offset; operator slot oc
-        const int oi = __builtin_amdgcn_readlane(ol_reg, st & 63);
+        const int oi = __builtin_amdgcn_readlane(ol_reg, st & 63);  // canonical offset
+        if (tid < kM2LTile) {
+            const int ox = fx * (oi / 49 - 3), oy = fy * ((oi / 7) % 7 - 3), oz = fz * (oi % 7 - 3);
+            int sx = ctx - ox, sy = cty - oy, sz = ctz - oz;
+            bool ok = col_ok;
+            if (g.periodic) {
+                sx &= cn - 1;
+                sy &= cn - 1;
+                sz &= cn - 1;
+            } else {
+                ok = ok && sx >= 0 && sy >= 0 && sz >= 0 && sx < cn && sy < cn && sz < cn;
+            }
+            dst[tid] = ok ? (int)(clo + morton(sx, sy, sz)) : (int)g.nbox;
+        }
+    };
+    auto issue = [&](int oc, uint4* dst) {
         const uint4* src = bank + (size_t)oc * a_chunks;
         for (int c0 = 0; c0 < a_chunks; c0 += kM2LThreads)
             if (c0 + tid < a_chunks) lds_dma16(src + c0 + tid, dst + c0 + 64 * wave);
-        const int ox = fx * (oi / 49 - 3), oy = fy * ((oi / 7) % 7 - 3), oz = fz * (oi % 7 - 3);
-        int sx = ctx - ox, sy = cty - oy, sz = ctz - oz;
-        bool ok = col_ok;
-        if (g.periodic) {
-            sx &= cn - 1;
-            sy &= cn - 1;
-            sz &= cn - 1;
-        } else {
-            ok = ok && sx >= 0 && sy >= 0 && sz >= 0 && sx < cn && sy < cn && sz < cn;
-        }
-        const int64_t b = ok ? clo + morton(sx, sy, sz) : g.nbox;
-        const uint4* s = msplit + b * 2 * KC + q;
+        const int* sb = src_box[(oc - o0) & 1];
         uint4* d = dst + a_chunks;
-        for (int m = 0; m < 2 * KC / 4; ++m) lds_dma16(s + 4 * m, d + m * kM2LThreads + 64 * wave);
+#pragma unroll
+        for (int t = 0; t < kM2LSlots; ++t)
+            if (sc[t] >= 0) lds_dma16(msplit + (size_t)sb[sj[t]] * 2 * KC + sc[t], d + t * kM2LThreads + 64 * wave);
     };
 
     mf4 acc[RT];
@@ -1529,6 +1552,9 @@ __global__ __launch_bounds__(kM2LThreads) void k_m2l_bf16x3(Geo g, M2LGeom mg,
     uint4 bsg[kM2LMaxKs];
 #pragma unroll
     for (int si = 0; si < kM2LMaxKs; ++si) bsg[si] = sign_tab[tk.cls * 4 * kM2LMaxKs + 4 * si + kq];
+    if (o0 < o1) sources(o0, src_box[0]);
+    if (o0 + 1 < o1) sources(o0 + 1, src_box[1]);
+    __syncthreads();
     if (o0 < o1) issue(o0, lds_q);
     for (int oc = o0; oc < o1; ++oc) {
         const int st = oc - o0;
@@ -1536,6 +1562,9 @@ __global__ __launch_bounds__(kM2LThreads) void k_m2l_bf16x3(Geo g, M2LGeom mg,
         __builtin_amdgcn_s_waitcnt(0);  // this lane's copies of offset oc have landed
         __syncthreads();                // everyone's have; the other buffer is free
         if (nbuf == 2 && oc + 1 < o1) issue(oc + 1, lds_q + (size_t)((st + 1) & 1) * (a_chunks + b_chunks));
+        // the table slot of offset oc was last read by issue(oc) (before the
+        // barrier): it now takes offset oc + 2
+        if (oc + 2 < o1) sources(oc + 2, src_box[st & 1]);
         if (active) {
             const uint4* A = cur;
             const uint4* B = cur + a_chunks;
@@ -1543,7 +1572,7 @@ __global__ __launch_bounds__(kM2LThreads) void k_m2l_bf16x3(Geo g, M2LGeom mg,
             for (int si = 0; si < kM2LMaxKs; ++si) {
                 if (4 * si >= KC) break;
                 const int kc = 4 * si + kq;
-                uint4 uh = B[kc * kM2LTile + col], ul = B[(KC + kc) * kM2LTile + col];
+                uint4 uh = B[col * SBc + kc], ul = B[col * SBc + KC + kc];
                 uh.x ^= bsg[si].x;
                 uh.y ^= bsg[si].y;
                 uh.z ^= bsg[si].z;
