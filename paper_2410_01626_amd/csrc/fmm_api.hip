@@ -255,7 +255,7 @@ inline unsigned nblocks(int64_t n, int b) { return (unsigned)std::max<int64_t>(1
 // Matrix-core M2L launch: the kernel instance for the plan's precision and row
 // tile count, then the fixed-order chunk reduction.
 template <typename T>
-void launch_m2l_mma(fmm_plan_t P, const Geo& g, int R) {
+bool launch_m2l_mma(fmm_plan_t P, const Geo& g, int R, bool want_root) {
     using namespace fmmk;
     hipStream_t st = P->stream;
     const M2LGeom mg = P->mg;
@@ -296,8 +296,13 @@ void launch_m2l_mma(fmm_plan_t P, const Geo& g, int R) {
     if (mg.nchunk > 1) {
         const int64_t tot = mg.nt_all * g.Kp;
         const unsigned nb = (unsigned)std::min<int64_t>(4096, (tot + 255) / 256);
-        k_m2l_reduce<T><<<dim3(nb, (unsigned)R), 256, 0, st>>>(g, mg, part, loc);
+        // periodic trees with a downward pass: the extra block forms the root
+        k_m2l_reduce<T><<<dim3(nb + (want_root ? 1u : 0u), (unsigned)R), kTreeThreads, 0, st>>>(
+            g, mg, part, loc, want_root ? 1 : 0, mult, (const T*)P->m2mT, (const T*)P->m2m_seg,
+            P->leaf_part, P->box_part, P->latT, P->lat_seg, P->root_m, P->root_l, P->dom);
+        return want_root;
     }
+    return false;
 }
 
 // Enqueue one evaluation of R replicas (arguments already validated; rd holds
@@ -381,13 +386,14 @@ fmm_status enqueue_eval(fmm_plan_t P, const std::vector<fmmk::RepDesc>& rd, cons
         k_root<T><<<R, 256, 0, st>>>(g, P->leaf_part, P->root_m, mult, P->latT, P->root_l, loc,
                                      P->dom);
     mark(P, 4);
+    bool root_ready = false;  // the periodic root formed by the M2L reduction launch
     if (g.depth >= g.lmin) {
         if (P->m2l_mode == 0) {
             int64_t nt = 0;
             for (int l = g.lmin; l <= g.depth; ++l) nt += (int64_t)1 << (3 * l);
             k_m2l_plain<T><<<dim3((unsigned)nt, R), 256, 0, st>>>(g, mult, (const T*)P->bankT, loc);
         } else {
-            launch_m2l_mma<T>(P, g, R);
+            root_ready = launch_m2l_mma<T>(P, g, R, g.periodic && g.depth >= 1);
         }
     }
     // downward pass: ancestors' local expansions and the L2L into the leaves
@@ -402,7 +408,7 @@ fmm_status enqueue_eval(fmm_plan_t P, const std::vector<fmmk::RepDesc>& rd, cons
         k_downward<T><<<dim3(nbx, R), kTreeThreads, 0, st>>>(
             g, l0, loc, (const T*)P->l2lT, (const T*)P->l2l_seg, mult, (const T*)P->m2mT,
             (const T*)P->m2m_seg, P->leaf_part, P->box_part, P->latT, P->lat_seg, P->root_m, P->root_l,
-            P->dom, P->leaf_start, order);
+            P->dom, P->leaf_start, order, root_ready ? 1 : 0);
     }
     mark(P, 6);
     switch (P->p2p_waves) {

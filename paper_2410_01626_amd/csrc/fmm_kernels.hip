@@ -925,6 +925,50 @@ __device__ void leaf_work_order(const Geo& g, const int32_t* __restrict__ leaf_s
     for (int i = threadIdx.x; i < nl; i += blockDim.x) order[i] = key[i] & (kOrderCap - 1);
 }
 
+// Periodic root of replica rp (a block of kTreeThreads threads): mu~_0 by
+// M2M from the 8 level-1 multipoles and lambda~_0 = Lat mu~_0 +
+// (2 pi / 3) sum q |s/L|^2 e_0, left in v (FP64); with `store` it also writes
+// mu~_0, lambda~_0 and dom[4] = Q.  xs: 8 kKMax doubles, part: 8 kTreeThreads
+// doubles, ps: 16 doubles of LDS.
+template <typename T>
+__device__ void periodic_root(const Geo& g, int rp, const T* __restrict__ mult_all,
+                              const T* __restrict__ m2m0, const T* __restrict__ m2m0_seg,
+                              const double* __restrict__ leaf_part_all,
+                              const double* __restrict__ box_part_all, const double* __restrict__ latT,
+                              const double* __restrict__ lat_seg, double* __restrict__ root_m_all,
+                              double* __restrict__ root_l_all, double* __restrict__ dom_all, double* xs,
+                              double* part, double* v, double* ps, bool store) {
+    const int K = g.K;
+    TriPart<T, kTriLower> tm;
+    tm.load(K, m2m0_seg);
+    TriPart<double, kTriFull> tl;
+    tl.load(K, lat_seg);
+    gather_children<T>(g, 1, 0, mult_all + (size_t)rp * g.nbox * g.Kp,
+                       leaf_part_all + (size_t)rp * g.nleaf * 2, box_part_all + (size_t)rp * g.nbox * 2,
+                       xs, ps);
+    __syncthreads();
+    tri_matvec<T, 8, kTriLower>(tm, K, m2m0, xs, part, xs);
+    for (int r = threadIdx.x; r < K; r += kTreeThreads) v[r] = combine_octants(xs, K, r);
+    __syncthreads();
+    for (int k = threadIdx.x; k < K; k += kTreeThreads) xs[k] = v[k];
+    __syncthreads();
+    tri_matvec<double, 1, kTriFull>(tl, K, latT, xs, part, xs);
+    double s2 = 0.0, qs = 0.0;
+    for (int c = 0; c < 8; ++c) {
+        s2 += ps[2 * c];
+        qs += ps[2 * c + 1];
+    }
+    for (int r = threadIdx.x; r < K; r += kTreeThreads) {
+        const double lr = xs[r] + (r == 0 ? 2.0 * kPi / 3.0 * s2 : 0.0);
+        if (store) {
+            root_m_all[(size_t)rp * K + r] = v[r];
+            root_l_all[(size_t)rp * K + r] = lr;
+        }
+        v[r] = lr;
+    }
+    if (store && threadIdx.x == 0) dom_all[8 * rp + 4] = qs;
+}
+
 // Downward pass in one launch: one block per box b of level depth - 1 forms
 // lambda~ of its ancestors from level l0 down (L2L of the parent's total plus
 // the box's own M2L sum, in FP64) and adds the L2L of lambda~_b into its 8
@@ -933,7 +977,8 @@ __device__ void leaf_work_order(const Geo& g, const int32_t* __restrict__ leaf_s
 // (2 pi / 3) sum q |s/L|^2 e_0 itself (block 0 also stores mu~_0, lambda~_0 and
 // dom[4] = Q).  Ancestors shared by several blocks are recomputed by each;
 // only the leaf expansions are stored.  Open systems start at level l0 from
-// its M2L sum alone.
+// its M2L sum alone.  With root_ready the periodic root was already formed
+// (by the M2L reduction launch) and is read from root_l.
 template <typename T>
 __global__ __launch_bounds__(kTreeThreads) void k_downward(
     Geo g, int l0, T* __restrict__ loc_all, const T* __restrict__ l2l0, const T* __restrict__ l2l0_seg,
@@ -941,7 +986,8 @@ __global__ __launch_bounds__(kTreeThreads) void k_downward(
     const double* __restrict__ leaf_part_all, const double* __restrict__ box_part_all,
     const double* __restrict__ latT, const double* __restrict__ lat_seg, double* __restrict__ root_m_all,
     double* __restrict__ root_l_all, double* __restrict__ dom_all,
-    const int32_t* __restrict__ leaf_start_all, int32_t* __restrict__ leaf_order_all) {
+    const int32_t* __restrict__ leaf_start_all, int32_t* __restrict__ leaf_order_all,
+    int root_ready) {
     __shared__ double xs[8 * kKMax], part[8 * kTreeThreads];
     if (leaf_order_all && blockIdx.x + 1 == gridDim.x) {
         // the extra last block: the near-field order of this replica's leaves
@@ -980,36 +1026,13 @@ __global__ __launch_bounds__(kTreeThreads) void k_downward(
         const int i = threadIdx.x + m * kTreeThreads;
         if (i < nanc) anc[i] = av[m];
     }
-    if (g.periodic) {
-        TriPart<T, kTriLower> tm;
-        tm.load(K, m2m0_seg);
-        TriPart<double, kTriFull> tl;
-        tl.load(K, lat_seg);
-        gather_children<T>(g, 1, 0, mult_all + (size_t)rp * g.nbox * g.Kp,
-                           leaf_part_all + (size_t)rp * g.nleaf * 2, box_part_all + (size_t)rp * g.nbox * 2,
-                           xs, ps);
+    if (g.periodic && root_ready) {
+        // formed by the extra block of the M2L reduction launch
         __syncthreads();
-        tri_matvec<T, 8, kTriLower>(tm, K, m2m0, xs, part, xs);
-        for (int r = threadIdx.x; r < K; r += kTreeThreads) v[r] = combine_octants(xs, K, r);
-        __syncthreads();
-        for (int k = threadIdx.x; k < K; k += kTreeThreads) xs[k] = v[k];
-        __syncthreads();
-        tri_matvec<double, 1, kTriFull>(tl, K, latT, xs, part, xs);
-        double s2 = 0.0, qs = 0.0;
-        for (int c = 0; c < 8; ++c) {
-            s2 += ps[2 * c];
-            qs += ps[2 * c + 1];
-        }
-        const bool first = b == 0;
-        for (int r = threadIdx.x; r < K; r += kTreeThreads) {
-            const double lr = xs[r] + (r == 0 ? 2.0 * kPi / 3.0 * s2 : 0.0);
-            if (first) {
-                root_m_all[(size_t)rp * K + r] = v[r];
-                root_l_all[(size_t)rp * K + r] = lr;
-            }
-            v[r] = lr;
-        }
-        if (first && threadIdx.x == 0) dom_all[8 * rp + 4] = qs;
+        for (int k = threadIdx.x; k < K; k += kTreeThreads) v[k] = root_l_all[(size_t)rp * K + k];
+    } else if (g.periodic) {
+        periodic_root<T>(g, rp, mult_all, m2m0, m2m0_seg, leaf_part_all, box_part_all, latT, lat_seg,
+                         root_m_all, root_l_all, dom_all, xs, part, v, ps, b == 0);
     } else {
         __syncthreads();
         for (int k = threadIdx.x; k < K; k += kTreeThreads) v[k] = (double)anc[k];
@@ -1632,14 +1655,28 @@ __global__ __launch_bounds__(kM2LThreads) void k_m2l_bf16x3(Geo g, M2LGeom mg,
 }
 
 // Sum the offset-chunk partials into the local expansions (fixed chunk order).
+// For periodic systems the launch carries one extra block per replica (the
+// last, blockDim = kTreeThreads) that forms the root expansion (periodic_root),
+// which then stays off the downward pass's critical path.
 template <typename T>
-__global__ __launch_bounds__(256) void k_m2l_reduce(Geo g, M2LGeom mg, const T* __restrict__ part_all,
-                                                    T* __restrict__ loc_all) {
+__global__ __launch_bounds__(kTreeThreads) void k_m2l_reduce(
+    Geo g, M2LGeom mg, const T* __restrict__ part_all, T* __restrict__ loc_all, int root_block,
+    const T* __restrict__ mult_all, const T* __restrict__ m2m0, const T* __restrict__ m2m0_seg,
+    const double* __restrict__ leaf_part_all, const double* __restrict__ box_part_all,
+    const double* __restrict__ latT, const double* __restrict__ lat_seg, double* __restrict__ root_m_all,
+    double* __restrict__ root_l_all, double* __restrict__ dom_all) {
+    const int nred = (int)gridDim.x - (root_block ? 1 : 0);
+    if ((int)blockIdx.x >= nred) {
+        __shared__ double xs[8 * kKMax], tp[8 * kTreeThreads], v[kKMax], ps[16];
+        periodic_root<T>(g, blockIdx.y, mult_all, m2m0, m2m0_seg, leaf_part_all, box_part_all, latT,
+                         lat_seg, root_m_all, root_l_all, dom_all, xs, tp, v, ps, true);
+        return;
+    }
     const int64_t tot = mg.nt_all * g.Kp;
     const T* part = part_all + (size_t)blockIdx.y * mg.nchunk * tot;
     T* loc = loc_all + (size_t)blockIdx.y * g.nbox * g.Kp;
     for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < tot;
-         e += (int64_t)gridDim.x * blockDim.x) {
+         e += (int64_t)nred * blockDim.x) {
         if ((int)(e % g.Kp) >= g.K) continue;
         // four independent partial sums keep 16 loads in flight; fixed order
         T s0 = T(0), s1 = T(0), s2 = T(0), s3 = T(0);
