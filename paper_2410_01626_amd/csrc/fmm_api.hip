@@ -33,6 +33,7 @@ struct fmm_plan_s {
             *site_members = nullptr;
     void *mult = nullptr, *loc = nullptr;
     double *root_m = nullptr, *root_l = nullptr;
+    double* root_part = nullptr;  // periodic: the 8 level-1 shares of the root multipole
     void *bankT = nullptr, *m2mT = nullptr, *l2lT = nullptr, *gcoef = nullptr;
     void *m2m_seg = nullptr, *l2l_seg = nullptr;  // tree-pass register caches (thread order)
     double* lat_seg = nullptr;
@@ -299,7 +300,8 @@ bool launch_m2l_mma(fmm_plan_t P, const Geo& g, int R, bool want_root) {
         // periodic trees with a downward pass: the extra block forms the root
         k_m2l_reduce<T><<<dim3(nb + (want_root ? 1u : 0u), (unsigned)R), kTreeThreads, 0, st>>>(
             g, mg, part, loc, want_root ? 1 : 0, mult, (const T*)P->m2mT, (const T*)P->m2m_seg,
-            P->leaf_part, P->box_part, P->latT, P->lat_seg, P->root_m, P->root_l, P->dom);
+            P->leaf_part, P->box_part, P->latT, P->lat_seg, P->root_m, P->root_l, P->dom,
+            g.depth >= 2 ? P->root_part : nullptr);
         return want_root;
     }
     return false;
@@ -375,12 +377,16 @@ fmm_status enqueue_eval(fmm_plan_t P, const std::vector<fmmk::RepDesc>& rd, cons
         P->leaf_part, (uint16_t*)P->msplit, P->mg.KP);
     // upward pass: one launch per level down to the coarsest interacting
     // level (1 periodic, 2 open); the periodic root and its lattice operator
-    // are formed at the start of the downward pass
+    // are formed by the M2L reduction launch (or else at the start of the
+    // downward pass)
     mark(P, 2);
+    // periodic trees whose M2L ends in a reduction launch form the root there;
+    // the level-1 M2M blocks then also leave their shares of the root multipole
+    const bool root_in_reduce = g.periodic && g.depth >= 1 && P->m2l_mode != 0 && P->mg.nchunk > 1;
     for (int lev = g.depth - 1; lev >= g.lmin; --lev)
         k_m2m<T><<<dim3(1u << (3 * lev), R), kTreeThreads, 0, st>>>(
             g, lev, mult, (const T*)P->m2mT, (const T*)P->m2m_seg, P->leaf_part, P->box_part,
-            (uint16_t*)P->msplit, P->mg.KP);
+            (uint16_t*)P->msplit, P->mg.KP, root_in_reduce && lev == 1 ? P->root_part : nullptr);
     mark(P, 3);
     if (g.periodic && g.depth == 0)
         k_root<T><<<R, 256, 0, st>>>(g, P->leaf_part, P->root_m, mult, P->latT, P->root_l, loc,
@@ -393,7 +399,7 @@ fmm_status enqueue_eval(fmm_plan_t P, const std::vector<fmmk::RepDesc>& rd, cons
             for (int l = g.lmin; l <= g.depth; ++l) nt += (int64_t)1 << (3 * l);
             k_m2l_plain<T><<<dim3((unsigned)nt, R), 256, 0, st>>>(g, mult, (const T*)P->bankT, loc);
         } else {
-            root_ready = launch_m2l_mma<T>(P, g, R, g.periodic && g.depth >= 1);
+            root_ready = launch_m2l_mma<T>(P, g, R, root_in_reduce);
         }
     }
     // downward pass: ancestors' local expansions and the L2L into the leaves
@@ -601,6 +607,7 @@ fmm_status fmm_plan_create(const fmm_params* prm, void* hip_stream, fmm_plan_t* 
     ok &= dev_alloc(P, &P->loc, RM * P->nbox * P->Kp * ts);
     ok &= dev_alloc(P, (void**)&P->root_m, RM * K * 8);
     ok &= dev_alloc(P, (void**)&P->root_l, RM * K * 8);
+    ok &= dev_alloc(P, (void**)&P->root_part, RM * 8 * K * 8);
     ok &= dev_alloc(P, &P->bankT, 343 * K * K * ts);
     ok &= dev_alloc(P, &P->m2mT, K * K * ts);  // octant 0; the others are its reflections
     ok &= dev_alloc(P, &P->l2lT, K * K * ts);

@@ -878,8 +878,9 @@ __global__ __launch_bounds__(kTreeThreads) void k_m2m(Geo g, int lev, T* __restr
                                                       const T* __restrict__ op0_seg,
                                                       const double* __restrict__ leaf_part_all,
                                                       double* __restrict__ box_part_all,
-                                                      uint16_t* __restrict__ msplit_all, int split_kp) {
-    __shared__ double xs[8 * kKMax], part[8 * kTreeThreads], ps[16];
+                                                      uint16_t* __restrict__ msplit_all, int split_kp,
+                                                      double* __restrict__ root_part_all) {
+    __shared__ double xs[8 * kKMax], part[8 * kTreeThreads], ps[16], vb[kKMax];
     TriPart<T, kTriLower> tp;
     tp.load(g.K, op0_seg);
     const int rp = blockIdx.y, K = g.K, box = blockIdx.x;
@@ -893,6 +894,7 @@ __global__ __launch_bounds__(kTreeThreads) void k_m2m(Geo g, int lev, T* __restr
     for (int r = threadIdx.x; r < K; r += kTreeThreads) {
         const double v = combine_octants(xs, K, r);
         mult[(size_t)gb * g.Kp + r] = (T)v;
+        vb[r] = v;
         if constexpr (sizeof(T) == 4)
             if (msplit_all)
                 store_split(msplit_all + (size_t)rp * (g.nbox + 1) * 2 * split_kp, split_kp, gb, r, (float)v);
@@ -901,6 +903,17 @@ __global__ __launch_bounds__(kTreeThreads) void k_m2m(Geo g, int lev, T* __restr
         double v = 0.0;
         for (int c = 0; c < 8; ++c) v += ps[2 * c + threadIdx.x];
         box_part[2 * gb + threadIdx.x] = v;
+    }
+    if (root_part_all) {
+        // level 1 of a periodic tree: this box's share of the root multipole,
+        // S_c A_0 S_c mu (octant c = box), in FP64 from the unrounded sums;
+        // the root is the fixed-order sum of the eight shares
+        __syncthreads();
+        for (int k = threadIdx.x; k < K; k += kTreeThreads) xs[k] = refl_sign(box, refl_bits(k)) * vb[k];
+        __syncthreads();
+        tri_matvec<T, 1, kTriLower>(tp, K, op0, xs, part, xs);
+        double* rpart = root_part_all + ((size_t)rp * 8 + box) * K;
+        for (int r = threadIdx.x; r < K; r += kTreeThreads) rpart[r] = refl_sign(box, refl_bits(r)) * xs[r];
     }
 }
 
@@ -930,6 +943,45 @@ __device__ void leaf_work_order(const Geo& g, const int32_t* __restrict__ leaf_s
 // (2 pi / 3) sum q |s/L|^2 e_0, left in v (FP64); with `store` it also writes
 // mu~_0, lambda~_0 and dom[4] = Q.  xs: 8 kKMax doubles, part: 8 kTreeThreads
 // doubles, ps: 16 doubles of LDS.
+// As periodic_root, from the eight level-1 shares of the root multipole
+// (k_m2m at level 1) and the level-1 partial sums of q |s/L|^2 and q.
+__device__ void periodic_root_from_shares(const Geo& g, int rp, const double* __restrict__ root_part_all,
+                                          const double* __restrict__ box_part_all,
+                                          const double* __restrict__ latT,
+                                          const double* __restrict__ lat_seg,
+                                          double* __restrict__ root_m_all, double* __restrict__ root_l_all,
+                                          double* __restrict__ dom_all, double* xs, double* part, double* v) {
+    const int K = g.K;
+    TriPart<double, kTriFull> tl;
+    tl.load(K, lat_seg);
+    const double* rpart = root_part_all + (size_t)rp * 8 * K;
+    const double* bpart = box_part_all + ((size_t)rp * g.nbox + g.lev_off[1]) * 2;
+    double sh[8];
+#pragma unroll
+    for (int c = 0; c < 8; ++c) sh[c] = (int)threadIdx.x < K ? rpart[(size_t)c * K + threadIdx.x] : 0.0;
+    double s2 = 0.0, qs = 0.0;
+    for (int c = 0; c < 8; ++c) {
+        s2 += bpart[2 * c];
+        qs += bpart[2 * c + 1];
+    }
+    if ((int)threadIdx.x < K) {
+        double m = 0.0;
+#pragma unroll
+        for (int c = 0; c < 8; ++c) m += sh[c];
+        v[threadIdx.x] = m;
+        xs[threadIdx.x] = m;
+    }
+    __syncthreads();
+    tri_matvec<double, 1, kTriFull>(tl, K, latT, xs, part, xs);
+    for (int r = threadIdx.x; r < K; r += kTreeThreads) {
+        const double lr = xs[r] + (r == 0 ? 2.0 * kPi / 3.0 * s2 : 0.0);
+        root_m_all[(size_t)rp * K + r] = v[r];
+        root_l_all[(size_t)rp * K + r] = lr;
+        v[r] = lr;
+    }
+    if (threadIdx.x == 0) dom_all[8 * rp + 4] = qs;
+}
+
 template <typename T>
 __device__ void periodic_root(const Geo& g, int rp, const T* __restrict__ mult_all,
                               const T* __restrict__ m2m0, const T* __restrict__ m2m0_seg,
@@ -1664,12 +1716,16 @@ __global__ __launch_bounds__(kTreeThreads) void k_m2l_reduce(
     const T* __restrict__ mult_all, const T* __restrict__ m2m0, const T* __restrict__ m2m0_seg,
     const double* __restrict__ leaf_part_all, const double* __restrict__ box_part_all,
     const double* __restrict__ latT, const double* __restrict__ lat_seg, double* __restrict__ root_m_all,
-    double* __restrict__ root_l_all, double* __restrict__ dom_all) {
+    double* __restrict__ root_l_all, double* __restrict__ dom_all, const double* __restrict__ root_part_all) {
     const int nred = (int)gridDim.x - (root_block ? 1 : 0);
     if ((int)blockIdx.x >= nred) {
         __shared__ double xs[8 * kKMax], tp[8 * kTreeThreads], v[kKMax], ps[16];
-        periodic_root<T>(g, blockIdx.y, mult_all, m2m0, m2m0_seg, leaf_part_all, box_part_all, latT,
-                         lat_seg, root_m_all, root_l_all, dom_all, xs, tp, v, ps, true);
+        if (root_part_all)
+            periodic_root_from_shares(g, blockIdx.y, root_part_all, box_part_all, latT, lat_seg, root_m_all,
+                                      root_l_all, dom_all, xs, tp, v);
+        else
+            periodic_root<T>(g, blockIdx.y, mult_all, m2m0, m2m0_seg, leaf_part_all, box_part_all, latT,
+                             lat_seg, root_m_all, root_l_all, dom_all, xs, tp, v, ps, true);
         return;
     }
     const int64_t tot = mg.nt_all * g.Kp;
