@@ -263,6 +263,98 @@ fmm_status fmm_plan_info(fmm_plan_t plan, int64_t out[10]);
  * the number of doubles written, or -1 for a bad argument. */
 int64_t fmm_host_operator(int32_t order_p, int32_t which, double* out);
 
+/* ---- lambda dynamics around the solve ------------------------------------
+ * The lambda coordinates of R replicas are one FP64 array of C entries;
+ * replica r owns [coord_off[r], coord_off[r+1]) (device int32 array of R + 1
+ * ascending offsets in [0, C]; entries outside are clamped into it).  Units:
+ * energies kJ/mol (run the solve with coulomb_k = 138.935458 so that its
+ * dV/dlambda is in kJ/mol), mass u, time ps, temperature K.  All pointers are
+ * device pointers owned by the caller; nothing is allocated.  The calls
+ * validate their arguments on the host (FMM_E_INVALID, nothing enqueued),
+ * enqueue one launch on hip_stream and return FMM_E_HIP if the launch fails.
+ * The bias of coordinate c (Methods, eq 3) is V_MM + V_pH + V_dw:
+ *   V_MM: dV_MM/dlambda = -G(lambda_c, lambda_partner), the negated fit of the
+ *         reference compound's mean dH/dlambda ("Calibration of Protonation
+ *         Dynamics"), G = sum_{i,j=0..5} mm[36 c + 6 i + j] lambda_c^i
+ *         lambda_partner^j (lambda_partner = 0 when partner[c] < 0 or partner
+ *         is NULL; mm NULL = no V_MM);
+ *   V_pH = lambda ln(10) k_B T (pKa[c] - pH[r]) (eq 4 with a linear profile;
+ *         pKa NaN or pka NULL = none, as for tautomer coordinates);
+ *   V_dw: cubic Hermite spline through the knots (p0 - 0.3, 30), (p0, 0),
+ *         ((p0 + p1)/2, B), (p1, y1), (p1 + 0.3, y1 + 30) with slopes -300, 0,
+ *         0, 0, 300 per unit lambda, linear beyond the end knots, from
+ *         dwp[4 c ..] = (B, p0, p1, y1) (dwp NULL = none). */
+typedef struct {
+    double mass;         /* lambda-particle mass, u (the paper uses 60) */
+    double dt;           /* time step, ps */
+    double temperature;  /* K */
+    double tau;          /* Bussi coupling time, ps; <= 0 = no thermostat */
+    double near0;        /* DBO statistics: lambda < near0 is near well 0 (0.2) */
+    double near1;        /* lambda > near1 is near well 1 (0.8) */
+} fmm_lambda_params;
+
+/* One velocity-Verlet step of the lambda particles ("Constant pH
+ * Parameters"), with the forces -dH/dlambda at lambda (eq 1: dvdl[c] is the
+ * solve's dV_Coul/dlambda for coordinate c, plus the bias above):
+ *   v_n = v + dt/2 F/m (omitted when first = 1: v is then the full-step v_n);
+ *   v_n *= alpha per replica, the Bussi-Donadio-Parrinello rescaling of the
+ *        replica's lambda kinetic energy K (N_f = its coordinate count) with
+ *        c = exp(-dt/tau), K' = K + (1-c)(K_bar (R1^2 + X)/N_f - K)
+ *        + 2 R1 sqrt(c (1-c) K K_bar / N_f), K_bar = N_f k_B T / 2,
+ *        alpha = sqrt(K'/K) (skipped for tau <= 0, N_f = 0 or K = 0); R1 =
+ *        noise[2 r] is a standard normal and X = noise[2 r + 1] a chi-square
+ *        sample with N_f - 1 degrees of freedom, drawn by the caller;
+ *   v = v_n + dt/2 F/m (written back, the half-step velocity) and
+ *   lam_new = lam + dt v (lam_new must not alias lam).
+ * kin[r] (optional) receives K before the rescaling, e_bias[r] (optional)
+ * the sum of V_pH + V_dw at lam.  stats_w (C x 5: steps, steps near 0, sum of
+ * lambda near 0, steps near 1, sum near 1) and stats_b (C x 2: steps, steps
+ * with near0 <= lambda <= near1), both optional, accumulate the DBO block
+ * statistics of lam. */
+fmm_status fmm_lambda_step(void* hip_stream, int32_t R, const int32_t* coord_off, int64_t C,
+                           const fmm_lambda_params* prm, int32_t first, const double* lam,
+                           double* lam_new, double* v, const double* dvdl, const int32_t* partner,
+                           const double* pka, const double* ph, const double* mm, const double* dwp,
+                           const double* noise, double* stats_w, double* stats_b, double* kin,
+                           double* e_bias);
+
+/* Dynamic Barrier and Well Optimization ("Dynamic Barrier and Well
+ * Optimization"); NULL = the paper's values {0.2, 0.8, 0.7, 0.03, 0.5, 0.08,
+ * 0.25, 0.05, 1.0, 1.0, 20.0} in field order. */
+typedef struct {
+    double near0, near1;   /* thresholds of the well statistics (the step's) */
+    double occupancy;      /* fraction of a block near a well before it moves */
+    double well_tol;       /* |mean - ideal| that moves a well */
+    double well_gain;      /* the well moves by -well_gain (mean - ideal) */
+    double max_shift;      /* |well - ideal end point| <= max_shift */
+    double target;         /* in-transition fraction aimed for */
+    double target_tol;     /* dead band around it */
+    double barrier_step;   /* kJ/mol per adjustment */
+    double barrier_min, barrier_max;
+} fmm_dbo_params;
+
+/* At the end of a DBO block: mode bit 0 applies the well rule from stats_w,
+ * bit 1 the barrier rule from stats_b, to dwp (in place), and clears the
+ * statistics it used.  With pfc = 1 every coordinate whose well or barrier
+ * moved gets the partition function correction below.  adjusted[c]
+ * (optional) is set to 1 for a moved coordinate, else 0 (for censoring the
+ * trajectory after a change). */
+fmm_status fmm_lambda_dbo(void* hip_stream, int32_t R, const int32_t* coord_off, int64_t C,
+                          int32_t mode, int32_t pfc, const fmm_dbo_params* prm, double temperature,
+                          const double* pka, const double* ph, double* dwp, double* stats_w,
+                          double* stats_b, int32_t* adjusted);
+
+/* Partition function correction ("Partition Function Correction") of every
+ * coordinate: sets y1 = dwp[4 c + 3] so that the free energy of
+ * deprotonation -k_B T ln(Z_1 / Z_0) of V_pH + V_dw, Z_0 and Z_1 the integrals
+ * of exp(-(V_pH + V_dw)/k_B T) over [0, 1/2] and [1/2, 1], equals
+ * ln(10) k_B T (pKa - pH) (0 without pKa); Gauss-Legendre quadrature on the
+ * spline pieces and bisection on y1 in [-200, 200] kJ/mol.  The free energy
+ * grows with y1 but is bounded (the barrier-top part of [1/2, 1] does not
+ * move with y1): a target out of reach leaves y1 at the nearer end. */
+fmm_status fmm_lambda_pfc(void* hip_stream, int32_t R, const int32_t* coord_off, int64_t C,
+                          double temperature, const double* pka, const double* ph, double* dwp);
+
 #ifdef __cplusplus
 }
 #endif

@@ -36,7 +36,9 @@ Readings of the paper taken here (each also listed in the design notes):
   * PFC: the free energy of deprotonation -k_B T ln(Z_deprot / Z_prot), with
     the integrals over [0, 1/2] and [1/2, 1] as the paper writes them, of
     exp(-(V_pH + V_dw) / k_B T), matched to ln(10) k_B T (pKa_ref - pH)
-    (0 for a coordinate without pKa) by moving the height y1 of well 1.
+    (0 for a coordinate without pKa) by moving the height y1 of well 1 within
+    [-200, 200] kJ/mol; a target out of reach there (large pKa_ref - pH over a
+    low barrier) leaves y1 at the nearer end.
   * DBO: a well moves by -gain (mean - ideal) when the coordinate spent more
     than the occupancy threshold of the block near it and |mean - ideal|
     exceeds the tolerance, its total offset from the ideal end point clamped
@@ -222,6 +224,13 @@ def pfc_solve(B, p0, p1, pka, ph_c, T):
     slope = 0.0 if math.isnan(pka) else LN10 * KB * T * (pka - ph_c)
     target = pfc_target(pka, ph_c, T)
     g = lambda y1: pfc_dg(pfc_landscape(B, p0, p1, y1, slope), T) - target
+    # the free energy grows with y1 but is bounded above (the part of
+    # [1/2, 1] left of the barrier top does not move with y1): a target out
+    # of reach leaves y1 at the end of the search range nearest to it
+    if g(-200.0) >= 0.0:
+        return -200.0
+    if g(200.0) <= 0.0:
+        return 200.0
     return brentq(g, -200.0, 200.0, xtol=1e-13, rtol=1e-15, maxiter=500)
 
 

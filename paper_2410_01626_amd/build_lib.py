@@ -9,7 +9,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libfmmcph.so")
-SOURCES = [os.path.join(CSRC, "fmm_api.hip"), os.path.join(CSRC, "operators.cpp")]
+SOURCES = [os.path.join(CSRC, "fmm_api.hip"), os.path.join(CSRC, "lambda_dynamics.hip"),
+           os.path.join(CSRC, "operators.cpp")]
 HEADERS = [os.path.join(CSRC, f) for f in ("fmm_kernels.hip", "fmm_internal.h", "operators.h")] + [
     os.path.join(ROOT, "include", "fmmcph.h")]
 

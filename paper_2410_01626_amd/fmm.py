@@ -56,7 +56,8 @@ class fmm_params(ctypes.Structure):
 EXPORTS = ["fmm_plan_create", "fmm_eval", "fmm_eval_adjoint", "fmm_eval_batched",
            "fmm_eval_tautomer", "fmm_eval_tautomer_batched",
            "fmm_sync_check", "fmm_last_error", "fmm_plan_destroy", "fmm_profile",
-           "fmm_profile_select", "fmm_plan_info", "fmm_host_operator"]
+           "fmm_profile_select", "fmm_plan_info", "fmm_host_operator",
+           "fmm_lambda_step", "fmm_lambda_dbo", "fmm_lambda_pfc"]
 PHASES = ["bin", "p2m", "m2m", "root", "m2l", "l2l", "near_far", "reduce"]
 
 _lib = None
@@ -107,6 +108,12 @@ def load_library(path: str = LIB_PATH):
     lib.fmm_plan_info.argtypes = [vp, vp]
     lib.fmm_host_operator.restype = ctypes.c_int64
     lib.fmm_host_operator.argtypes = [i32, i32, dp]
+    lib.fmm_lambda_step.restype = ctypes.c_int
+    lib.fmm_lambda_step.argtypes = [vp, i32, vp, i64, vp, i32] + [vp] * 14
+    lib.fmm_lambda_dbo.restype = ctypes.c_int
+    lib.fmm_lambda_dbo.argtypes = [vp, i32, vp, i64, i32, i32, vp, ctypes.c_double] + [vp] * 6
+    lib.fmm_lambda_pfc.restype = ctypes.c_int
+    lib.fmm_lambda_pfc.argtypes = [vp, i32, vp, i64, ctypes.c_double, vp, vp, vp]
     _lib = lib
     return lib
 

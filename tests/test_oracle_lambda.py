@@ -188,6 +188,17 @@ def test_pfc_solve_hits_the_target():
         assert dg == pytest.approx(math.log(10) * L.KB * T * (pka - ph), abs=1e-9)
 
 
+def test_pfc_out_of_reach_stays_at_the_bound():
+    # low barrier, pKa - pH = 8: the barrier-top half of [1/2, 1] alone keeps
+    # the free energy below the 46 kJ/mol target whatever y1 is
+    T = 300.0
+    y1 = L.pfc_solve(1.0, 0.0, 1.0, 12.0, 4.0, T)
+    assert y1 == 200.0
+    dg = L.pfc_dg(L.pfc_landscape(1.0, 0.0, 1.0, 200.0, math.log(10) * L.KB * T * 8.0), T)
+    assert dg < math.log(10) * L.KB * T * 8.0
+    assert L.pfc_solve(1.0, 0.0, 1.0, 4.0, 12.0, T) > -200.0  # the other side is reachable
+
+
 def test_dbo_rules_follow_the_paper_constants():
     dwp = np.array([[6.0, 0.0, 1.0, 0.0]] * 6)
     n = 100.0
