@@ -221,6 +221,56 @@ def main():
                      device=dev, hamiltonian=True)
     sec_ham, _ = timed(hplan, inp, args.steps, args.warmup)
 
+    # constant-pH dynamics of the same box: every step one solve (kJ/mol) and
+    # one velocity-Verlet step of the 20 lambda particles (bias V_pH + V_dw,
+    # Bussi thermostat; pKa_ref 4.0 at pH 4.0)
+    from paper_2410_01626_amd import lambda_dynamics as LD
+    lplan = fmm.Plan(depth, order, periodic=True, precision="bf16x3", coulomb_k=138.935458,
+                     max_atoms=n, max_sites=S, device=dev)
+    # V_MM from a synthetic calibration: each site alone in vacuum is its
+    # reference compound, whose dV/dlambda is linear in lambda (the Coulomb
+    # energy is quadratic in the charges), so two solves at lambda = 0 and 1
+    # (all sites as replicas of one batched call) give G = g_00 + g_10 lambda
+    mm = np.zeros((S, 36))
+    members = [np.nonzero(d["site"] == s_)[0] for s_ in range(S)]
+    cao = np.cumsum([0] + [m_.size for m_ in members])
+    cso = np.arange(S + 1)
+    idx = np.concatenate(members)
+    cplan = fmm.Plan(1, 8, periodic=False, precision="fp64", coulomb_k=138.935458,
+                     max_atoms=int(cao[-1]), max_sites=S, max_replicas=S, device=dev)
+    cin = [torch.tensor(d[k][idx], dtype=torch.float64, device=dev) for k in ("x", "qA", "qB")]
+    csite = torch.zeros(int(cao[-1]), dtype=torch.int32, device=dev)
+    g_end = [cplan.eval_batched(cao, cso, *cin, csite, torch.full((S,), float(e), dtype=torch.float64,
+                                                                   device=dev))["dVdl"].cpu().numpy()
+             for e in (0.0, 1.0)]
+    mm[:, 0], mm[:, 6] = g_end[0], g_end[1] - g_end[0]
+    dyn = LD.LambdaDynamics([0, S], d["lam"], [4.0], np.full(S, 4.0), mm=mm, seed=1, device=dev)
+    lout = lplan.eval(inp[0], inp[1], inp[2], inp[3], dyn.lam, box=d["box"])
+
+    def md_steps(k):
+        for _ in range(k):
+            lplan.eval(inp[0], inp[1], inp[2], inp[3], dyn.lam, box=d["box"], out=lout)
+            dyn.step(lout["dVdl"])
+
+    md_steps(args.warmup)
+    torch.cuda.synchronize(dev)
+    t0 = time.perf_counter()
+    md_steps(args.steps)
+    torch.cuda.synchronize(dev)
+    sec_md = (time.perf_counter() - t0) / args.steps
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        dyn.step(lout["dVdl"])
+    torch.cuda.synchronize(dev)
+    sec_lstep = (time.perf_counter() - t0) / args.steps
+    lam_dyn = {"workload": "same box, 20 lambda particles (m = 60 u, dt = 2 fs, 300 K, Bussi "
+                           "tau = 1 ps, barrier 6 kJ/mol, V_MM from each isolated site), k_e in "
+                           "kJ/mol",
+               "md_steps_per_s": 1.0 / sec_md, "ms_per_step": sec_md * 1e3,
+               "lambda_step_us": sec_lstep * 1e6,
+               "lambda_range": [float(dyn.lam.min().item()), float(dyn.lam.max().item())],
+               "end_state_fraction": float(((dyn.lam < 0.2) | (dyn.lam > 0.8)).double().mean().item())}
+
     # 16 open replicas of 10k-60k atoms at pH 2-9 in one batched call per step
     batched = None
     if not args.no_batched:
@@ -255,6 +305,25 @@ def main():
                    "batch_evals_per_s": 1.0 / bsec, "replica_evals_per_s": len(reps) / bsec,
                    "ms_per_batch": bsec * 1e3, "atoms_per_s": float(ao[-1]) / bsec,
                    "phase_ms": {k: (v[0] / v[1] if v[1] else 0.0) for k, v in bprof.items()}}
+        # constant-pH dynamics of the replicas: one batched solve (kJ/mol) and
+        # one lambda step of all replicas' sites per step, each replica at its pH
+        bplan_k = fmm.Plan(3, 8, periodic=False, precision="bf16x3", coulomb_k=138.935458,
+                           max_atoms=int(ao[-1]), max_sites=int(so[-1]), max_replicas=len(reps),
+                           device=dev)
+        bdyn = LD.LambdaDynamics(so, cat["lam"], [r["pH"] for r in reps], np.full(int(so[-1]), 4.0),
+                                 seed=2, device=dev)
+        for _ in range(2):
+            bout = bplan_k.eval_batched(ao, so, bin_[0], bin_[1], bin_[2], bin_[3], bdyn.lam)
+            bdyn.step(bout["dVdl"])
+        torch.cuda.synchronize(dev)
+        t0 = time.perf_counter()
+        for _ in range(args.batched_steps):
+            bout = bplan_k.eval_batched(ao, so, bin_[0], bin_[1], bin_[2], bin_[3], bdyn.lam)
+            bdyn.step(bout["dVdl"])
+        torch.cuda.synchronize(dev)
+        bmd = (time.perf_counter() - t0) / args.batched_steps
+        batched["lambda_dynamics"] = {"md_steps_per_s": 1.0 / bmd, "ms_per_step": bmd * 1e3,
+                                      "lambda_particles": int(so[-1])}
 
     # the dominant kernel's work over its duration measured inside the timed region
     pairs = p2p_pairs(leaf_counts(d["x"], box, depth))
@@ -312,6 +381,7 @@ def main():
         "tautomers": {"value": 1.0 / sec_taut, "ms_per_step": sec_taut * 1e3,
                       "workload": "same box, four charge forms per site (half the sites with "
                                   "tautomers), E+F+dV/dlambda_p+dV/dlambda_t"},
+        "lambda_dynamics": lam_dyn,
         "batched": batched,
         "phase_ms": phase_ms,
         "phase_ms_fp64": phase_ms64,

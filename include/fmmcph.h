@@ -282,7 +282,8 @@ int64_t fmm_host_operator(int32_t order_p, int32_t which, double* out);
  *         pKa NaN or pka NULL = none, as for tautomer coordinates);
  *   V_dw: cubic Hermite spline through the knots (p0 - 0.3, 30), (p0, 0),
  *         ((p0 + p1)/2, B), (p1, y1), (p1 + 0.3, y1 + 30) with slopes -300, 0,
- *         0, 0, 300 per unit lambda, linear beyond the end knots, from
+ *         0, 0, 300 per unit lambda, continued linearly beyond the end knots
+ *         plus a confining 10^4 d^2 (d the distance past the end knot), from
  *         dwp[4 c ..] = (B, p0, p1, y1) (dwp NULL = none). */
 typedef struct {
     double mass;         /* lambda-particle mass, u (the paper uses 60) */

@@ -27,7 +27,8 @@ Readings of the paper taken here (each also listed in the design notes):
     pKa (tautomer coordinates) have no pH term.
   * V_dw is the cubic Hermite spline of five knots built from (B, p0, p1, y1)
     by dw_knots below (synthetic shape: the calibrated splines are not
-    available), extended linearly beyond its end knots.
+    available), extended linearly beyond its end knots plus a confining
+    quadratic wall there.
   * Thermostat: one Bussi thermostat per replica over all its lambda
     coordinates (N_f = their number), applied to the full-step velocities,
     positive square root of the kinetic-energy ratio; the random numbers
@@ -55,8 +56,9 @@ KB = 8.314462618e-3  # Boltzmann constant, kJ mol^-1 K^-1 (molar gas constant)
 LN10 = math.log(10.0)
 
 # synthetic double-well template: wall knots 0.3 from each well, 30 kJ/mol
-# above it, with slope 300 kJ/mol per unit lambda
-WALL_DX, WALL_DY, WALL_SLOPE = 0.3, 30.0, 300.0
+# above it, with slope 300 kJ/mol per unit lambda; beyond them the linear
+# continuation gains a confining (WALL_K / 2) d^2, d the distance past the knot
+WALL_DX, WALL_DY, WALL_SLOPE, WALL_K = 0.3, 30.0, 300.0, 2.0e4
 
 # DBO constants as the paper states them ("Dynamic Barrier and Well Optimization")
 DBO_DEFAULTS = dict(near0=0.2, near1=0.8, occupancy=0.7, well_tol=0.03, well_gain=0.5,
@@ -105,7 +107,9 @@ def v_dw(dwp, lam):
     for c in range(lam.size):
         x, y, s = dw_knots(*dwp[c])
         v, d = hermite(x, y, s, lam[c:c + 1])
-        V[c], dV[c] = v[0], d[0]
+        past = min(lam[c] - x[0], 0.0) + max(lam[c] - x[-1], 0.0)
+        V[c] = v[0] + 0.5 * WALL_K * past * past
+        dV[c] = d[0] + WALL_K * past
     return V, dV
 
 
@@ -209,8 +213,8 @@ def pfc_dg(V, T):
 
 
 def pfc_landscape(B, p0, p1, y1, slope_ph):
-    x, y, s = dw_knots(B, p0, p1, y1)
-    return lambda t: slope_ph * t + hermite(x, y, s, np.array([t]))[0][0]
+    dwp = np.array([[B, p0, p1, y1]])
+    return lambda t: slope_ph * t + v_dw(dwp, np.array([t]))[0][0]
 
 
 def pfc_target(pka, ph_c, T):

@@ -3,8 +3,9 @@
 // thermostat, the DBO block statistics and rules, and the partition function
 // correction (constant-pH paper, Methods: eq 1, eq 3, eq 4, "Partition
 // Function Correction", "Dynamic Barrier and Well Optimization", "Constant pH
-// Parameters").  All arithmetic is FP64.  One work-group per replica; its
-// lambda coordinates are a contiguous range.
+// Parameters").  All arithmetic is FP64.  The step runs one work-group per
+// replica (its lambda coordinates are a contiguous range), DBO and the
+// correction one wavefront per coordinate.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -17,8 +18,9 @@ namespace fmml {
 constexpr double kKB = 8.314462618e-3;  // kJ mol^-1 K^-1
 constexpr double kLn10 = 2.302585092994045684;
 // synthetic double-well shape: wall knots 0.3 from each well, 30 kJ/mol above
-// it, slope 300 kJ/mol per unit lambda
-constexpr double kWallDx = 0.3, kWallDy = 30.0, kWallSlope = 300.0;
+// it, slope 300 kJ/mol per unit lambda; past them the linear continuation
+// gains a confining (kWallK / 2) d^2, d the distance past the end knot
+constexpr double kWallDx = 0.3, kWallDy = 30.0, kWallSlope = 300.0, kWallK = 2.0e4;
 constexpr int kThreads = 256;
 constexpr int kGL = 16;     // Gauss-Legendre points per panel
 constexpr int kPanels = 4;  // panels per smooth piece of the PFC integrands
@@ -63,6 +65,14 @@ __device__ void hermite(const Knots& k, double t, double& V, double& dV) {
     const double y0 = k.y[i], y1 = k.y[i + 1], m0 = h * k.s[i], m1 = h * k.s[i + 1];
     V = (2 * u3 - 3 * u2 + 1) * y0 + (u3 - 2 * u2 + u) * m0 + (-2 * u3 + 3 * u2) * y1 + (u3 - u2) * m1;
     dV = ((6 * u2 - 6 * u) * y0 + (3 * u2 - 4 * u + 1) * m0 + (-6 * u2 + 6 * u) * y1 + (3 * u2 - 2 * u) * m1) / h;
+}
+
+// V_dw and its derivative: the spline plus the confining walls.
+__device__ void double_well(const Knots& k, double t, double& V, double& dV) {
+    hermite(k, t, V, dV);
+    const double past = fmin(t - k.x[0], 0.0) + fmax(t - k.x[4], 0.0);
+    V += 0.5 * kWallK * past * past;
+    dV += kWallK * past;
 }
 
 struct StepArgs {
@@ -126,7 +136,7 @@ __device__ double lambda_force(const StepArgs& A, int64_t c, double ph_r, double
     if (A.dwp) {
         const double* d = A.dwp + 4 * c;
         double V, dV;
-        hermite(dw_knots(d[0], d[1], d[2], d[3]), l, V, dV);
+        double_well(dw_knots(d[0], d[1], d[2], d[3]), l, V, dV);
         dH += dV;
         eb += V;
     }
@@ -222,8 +232,11 @@ __global__ __launch_bounds__(kThreads) void k_lambda_step(StepArgs A) {
 
 // Free energy of deprotonation -k_B T ln(Z_deprot / Z_prot) of V_pH + V_dw,
 // Z over [0, 1/2] and [1/2, 1]: Gauss-Legendre on kPanels panels of every
-// piece between the knots that fall inside.
+// piece between the knots that fall inside.  One wavefront: lane l takes the
+// quadrature points l, l + 64, ...; the lane sums are added in a fixed tree
+// and lane 0's total is broadcast, so every lane returns the same value.
 __device__ double pfc_dg(const Knots& k, double slope, double beta, const GaussLegendre& gl) {
+    const int lane = threadIdx.x & 63;
     double z[2];
     for (int h = 0; h < 2; ++h) {
         const double lo = 0.5 * h, hi = lo + 0.5;
@@ -233,34 +246,33 @@ __device__ double pfc_dg(const Knots& k, double slope, double beta, const GaussL
         for (int i = 0; i < 5; ++i)
             if (k.x[i] > lo && k.x[i] < hi) cuts[n++] = k.x[i];  // knots ascend
         cuts[n++] = hi;
+        const int per_piece = kPanels * kGL, npts = (n - 1) * per_piece;
         double sum = 0.0;
-        for (int p = 0; p + 1 < n; ++p) {
-            const double w = (cuts[p + 1] - cuts[p]) / kPanels;
-            for (int q = 0; q < kPanels; ++q) {
-                const double c0 = cuts[p] + q * w, mid = c0 + 0.5 * w, hw = 0.5 * w;
-                for (int g = 0; g < kGL; ++g) {
-                    const double x = mid + hw * gl.x[g];
-                    double V, dV;
-                    hermite(k, x, V, dV);
-                    sum += hw * gl.w[g] * exp(-beta * (V + slope * x));
-                }
-            }
+        for (int j = lane; j < npts; j += 64) {
+            const int p = j / per_piece, q = (j % per_piece) / kGL, g = j % kGL;
+            const double w = (cuts[p + 1] - cuts[p]) / kPanels, hw = 0.5 * w;
+            const double x = cuts[p] + q * w + hw + hw * gl.x[g];
+            double V, dV;
+            double_well(k, x, V, dV);
+            sum += hw * gl.w[g] * exp(-beta * (V + slope * x));
         }
-        z[h] = sum;
+        for (int off = 32; off > 0; off >>= 1) sum += __shfl_down(sum, off, 64);
+        z[h] = __shfl(sum, 0, 64);
     }
     return -log(z[1] / z[0]) / beta;
 }
 
 // y1 for which the free energy of deprotonation of V_pH + V_dw equals
 // ln(10) k_B T (pKa - pH) (0 without pKa): bisection on [-200, 200] kJ/mol
-// (the free energy increases with y1).
+// (the free energy increases with y1); wave-uniform (every lane takes the
+// same branches).
 __device__ double pfc_solve(double B, double p0, double p1, double pk, double ph_r, double T,
                             const GaussLegendre& gl) {
     const double beta = 1.0 / (kKB * T);
     const double slope = isnan(pk) ? 0.0 : kLn10 * kKB * T * (pk - ph_r);
     const double target = slope;  // V_pH(1) - V_pH(0)
     double lo = -200.0, hi = 200.0;
-    for (int it = 0; it < 200 && hi - lo > 0.0; ++it) {
+    for (int it = 0; it < 200; ++it) {
         const double mid = 0.5 * (lo + hi);
         if (mid <= lo || mid >= hi) break;
         if (pfc_dg(dw_knots(B, p0, p1, mid), slope, beta, gl) < target) lo = mid;
@@ -271,6 +283,7 @@ __device__ double pfc_solve(double B, double p0, double p1, double pk, double ph
 
 struct DboArgs {
     const int32_t* coord_off;
+    int R;
     int64_t C;
     int mode, pfc, all;  // all: correct every coordinate (no rules)
     fmm_dbo_params prm;
@@ -283,58 +296,77 @@ struct DboArgs {
     int32_t* adjusted;
 };
 
+constexpr int kDboWaves = 4;
+
 // DBO rules at the end of a block (mode bit 0: wells from stats_w, bit 1:
 // barrier from stats_b), then the partition function correction of every
-// adjusted coordinate; the used statistics are cleared.
-__global__ __launch_bounds__(64) void k_lambda_dbo(DboArgs A, GaussLegendre gl) {
-    const int r = blockIdx.x;
+// adjusted coordinate; the used statistics are cleared.  One wavefront per
+// coordinate: every lane evaluates the rules on the same values (uniform
+// branches), lane 0 writes, all lanes share the quadrature.
+__global__ __launch_bounds__(64 * kDboWaves) void k_lambda_dbo(DboArgs A, GaussLegendre gl) {
+    const int64_t c = (int64_t)blockIdx.x * kDboWaves + (threadIdx.x >> 6);
+    const bool w0 = (threadIdx.x & 63) == 0;
+    if (c >= A.C) return;  // whole wavefront
+    // replica of c: the last r with (clamped) coord_off[r] <= c
+    int lo = 0, hi = A.R;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (min<int64_t>(max<int64_t>(A.coord_off[mid], 0), A.C) <= c) lo = mid;
+        else hi = mid;
+    }
     int64_t a, b;
-    replica_range(A.coord_off, A.C, r, a, b);
-    const double ph_r = A.ph[r];
+    replica_range(A.coord_off, A.C, lo, a, b);
+    if (c < a || c >= b) return;  // outside every replica's range
+    const double ph_r = A.ph[lo];
     const fmm_dbo_params& P = A.prm;
-    for (int64_t c = a + threadIdx.x; c < b; c += blockDim.x) {
-        double* d = A.dwp + 4 * c;
-        bool adj = false;
-        if (A.mode & 1) {
-            double* s = A.stats_w + 5 * c;
-            if (s[0] > 0.0) {
-                for (int w = 0; w < 2; ++w) {
-                    const double cnt = s[1 + 2 * w], tot = s[2 + 2 * w];
-                    if (cnt > P.occupancy * s[0]) {
-                        const double dev = tot / cnt - (double)w;
-                        if (fabs(dev) > P.well_tol) {
-                            const double pos = d[1 + w] - P.well_gain * dev;
-                            const double nw = fmin(fmax(pos, (double)w - P.max_shift), (double)w + P.max_shift);
-                            if (nw != d[1 + w]) {
-                                d[1 + w] = nw;
-                                adj = true;
-                            }
+    double d[4] = {A.dwp[4 * c], A.dwp[4 * c + 1], A.dwp[4 * c + 2], A.dwp[4 * c + 3]};
+    bool adj = false;
+    if (A.mode & 1) {
+        double* s = A.stats_w + 5 * c;
+        const double s0 = s[0], cnt[2] = {s[1], s[3]}, tot[2] = {s[2], s[4]};
+        if (s0 > 0.0) {
+            for (int w = 0; w < 2; ++w) {
+                if (cnt[w] > P.occupancy * s0) {
+                    const double dev = tot[w] / cnt[w] - (double)w;
+                    if (fabs(dev) > P.well_tol) {
+                        const double pos = d[1 + w] - P.well_gain * dev;
+                        const double nw = fmin(fmax(pos, (double)w - P.max_shift), (double)w + P.max_shift);
+                        if (nw != d[1 + w]) {
+                            d[1 + w] = nw;
+                            adj = true;
                         }
                     }
                 }
             }
-            for (int k = 0; k < 5; ++k) s[k] = 0.0;
         }
-        if (A.mode & 2) {
-            double* s = A.stats_b + 2 * c;
-            if (s[0] > 0.0) {
-                const double frac = s[1] / s[0];
-                double B = d[0];
-                if (frac < P.target - P.target_tol) B -= P.barrier_step;
-                else if (frac > P.target + P.target_tol) B += P.barrier_step;
-                B = fmin(fmax(B, P.barrier_min), P.barrier_max);
-                if (B != d[0]) {
-                    d[0] = B;
-                    adj = true;
-                }
+        if (w0)
+            for (int k = 0; k < 5; ++k) s[k] = 0.0;
+    }
+    if (A.mode & 2) {
+        double* s = A.stats_b + 2 * c;
+        const double s0 = s[0], s1 = s[1];
+        if (s0 > 0.0) {
+            const double frac = s1 / s0;
+            double B = d[0];
+            if (frac < P.target - P.target_tol) B -= P.barrier_step;
+            else if (frac > P.target + P.target_tol) B += P.barrier_step;
+            B = fmin(fmax(B, P.barrier_min), P.barrier_max);
+            if (B != d[0]) {
+                d[0] = B;
+                adj = true;
             }
+        }
+        if (w0) {
             s[0] = 0.0;
             s[1] = 0.0;
         }
-        if ((adj && A.pfc) || A.all) {
-            const double pk = A.pka ? A.pka[c] : NAN;
-            d[3] = pfc_solve(d[0], d[1], d[2], pk, ph_r, A.T, gl);
-        }
+    }
+    if ((adj && A.pfc) || A.all) {
+        const double pk = A.pka ? A.pka[c] : NAN;
+        d[3] = pfc_solve(d[0], d[1], d[2], pk, ph_r, A.T, gl);
+    }
+    if (w0) {
+        for (int k = 0; k < 4; ++k) A.dwp[4 * c + k] = d[k];
         if (A.adjusted) A.adjusted[c] = adj ? 1 : 0;
     }
 }
@@ -407,8 +439,10 @@ fmm_status fmm_lambda_dbo(void* hip_stream, int32_t R, const int32_t* coord_off,
         return FMM_E_INVALID;
     if (C > 0 && (!dwp || ((mode & 1) && !stats_w) || ((mode & 2) && !stats_b))) return FMM_E_INVALID;
     fmm_dbo_params P = prm ? *prm : fmm_dbo_params{0.2, 0.8, 0.7, 0.03, 0.5, 0.08, 0.25, 0.05, 1.0, 1.0, 20.0};
-    DboArgs A{coord_off, C, mode, pfc, 0, P, temperature, pka, ph, dwp, stats_w, stats_b, adjusted};
-    k_lambda_dbo<<<R, 64, 0, (hipStream_t)hip_stream>>>(A, gl_table());
+    if (C == 0) return FMM_OK;
+    DboArgs A{coord_off, R, C, mode, pfc, 0, P, temperature, pka, ph, dwp, stats_w, stats_b, adjusted};
+    const unsigned nb = (unsigned)((C + kDboWaves - 1) / kDboWaves);
+    k_lambda_dbo<<<nb, 64 * kDboWaves, 0, (hipStream_t)hip_stream>>>(A, gl_table());
     return hipGetLastError() == hipSuccess ? FMM_OK : FMM_E_HIP;
 }
 
@@ -418,9 +452,11 @@ fmm_status fmm_lambda_pfc(void* hip_stream, int32_t R, const int32_t* coord_off,
     if (R < 1 || C < 0 || !coord_off || !ph || !(temperature > 0) || !std::isfinite(temperature))
         return FMM_E_INVALID;
     if (C > 0 && !dwp) return FMM_E_INVALID;
-    DboArgs A{coord_off, C, 0, 1, 1, fmm_dbo_params{}, temperature, pka, ph, dwp, nullptr, nullptr,
+    if (C == 0) return FMM_OK;
+    DboArgs A{coord_off, R, C, 0, 1, 1, fmm_dbo_params{}, temperature, pka, ph, dwp, nullptr, nullptr,
               nullptr};
-    k_lambda_dbo<<<R, 64, 0, (hipStream_t)hip_stream>>>(A, gl_table());
+    const unsigned nb = (unsigned)((C + kDboWaves - 1) / kDboWaves);
+    k_lambda_dbo<<<nb, 64 * kDboWaves, 0, (hipStream_t)hip_stream>>>(A, gl_table());
     return hipGetLastError() == hipSuccess ? FMM_OK : FMM_E_HIP;
 }
 

@@ -157,7 +157,10 @@ class LambdaDynamics:
         self.adjusted = torch.zeros(self.C, dtype=torch.int32, device=self.dev)
         self.kin = torch.zeros(self.R, **f64)
         self.e_bias = torch.zeros(self.R, **f64)
-        self.noise = torch.zeros(2 * self.R, **f64)
+        # thermostat random numbers, drawn for noise_block steps at a time
+        self.noise_block = 1000
+        self.noise_bank = torch.zeros((self.noise_block, 2 * self.R), **f64)
+        self.noise = self.noise_bank[0]
         # wells: 40 ps blocks, barrier: 1 ns blocks ("Dynamic Barrier and Well Optimization")
         self.well_block = well_block if well_block is not None else int(round(40.0 / dt))
         self.barrier_block = barrier_block if barrier_block is not None else int(round(1000.0 / dt))
@@ -165,19 +168,25 @@ class LambdaDynamics:
         lambda_pfc(self.coord_off, self.dwp, self.ph, temperature, pka=self.pka)
 
     def draw_noise(self):
-        """One standard normal and one chi-square sample with N_f - 1 degrees
-        of freedom per replica (chi^2_k = 2 Gamma(k / 2, 1); 0 for k = 0)."""
+        """For each of the next noise_block steps, one standard normal and one
+        chi-square sample with N_f - 1 degrees of freedom per replica
+        (chi^2_k = 2 Gamma(k / 2, 1); 0 for k = 0)."""
         import torch
-        r1 = torch.randn(self.R, generator=self.gen, dtype=torch.float64, device=self.dev)
-        k = torch.clamp(self.nf - 1, min=0)
+        nb, R = self.noise_block, self.R
+        r1 = torch.randn((nb, R), generator=self.gen, dtype=torch.float64, device=self.dev)
+        k = torch.clamp(self.nf - 1, min=0).expand(nb, R).contiguous()
         g = torch._standard_gamma(torch.clamp(k / 2, min=1e-300), generator=self.gen)
         chi2 = torch.where(k > 0, 2 * g, torch.zeros_like(g))
-        self.noise.view(self.R, 2)[:, 0] = r1
-        self.noise.view(self.R, 2)[:, 1] = chi2
+        bank = self.noise_bank.view(nb, R, 2)
+        bank[:, :, 0] = r1
+        bank[:, :, 1] = chi2
 
     def step(self, dvdl):
         if self.params.tau > 0:
-            self.draw_noise()
+            i = self.n % self.noise_block
+            if i == 0:
+                self.draw_noise()
+            self.noise = self.noise_bank[i]
         lambda_step(self.coord_off, self.lam, self.lam_next, self.v, dvdl, self.ph, self.params,
                     first=self.n == 0, partner=self.partner, pka=self.pka, mm=self.mm,
                     dwp=self.dwp, noise=self.noise if self.params.tau > 0 else None,

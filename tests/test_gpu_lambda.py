@@ -196,11 +196,47 @@ def test_driver_around_the_solve():
         out = plan.eval(x, qA, qB, site, lam, box=d["box"])
         dyn.step(out["dVdl"])
         torch.cuda.synchronize()
-        noise = dyn.noise.cpu().numpy().reshape(1, 2)
+        noise = dyn.noise.cpu().numpy().reshape(1, 2)  # the step's own row of the bank
         rl, rv, _, _ = L.lambda_step(np.array([0, S]), lam.cpu().numpy(), v.cpu().numpy(),
                                      out["dVdl"].cpu().numpy(), np.full(S, -1), pka, np.array([5.5]),
                                      None, dwp.cpu().numpy().reshape(S, 4), noise, 60.0, 0.002,
                                      300.0, 0.5, it == 0)
         _close(dyn.lam.cpu().numpy(), rl)
         _close(dyn.v.cpu().numpy(), rv)
+    plan.close()
+
+
+def test_mm_calibration_flattens_an_isolated_site():
+    # the reference compound of a site is the site alone: its dV/dlambda is
+    # linear in lambda, so G from two solves (lambda = 0, 1) cancels the
+    # solve's derivative at every lambda (the step then feels no force)
+    import torch
+    from paper_2410_01626_amd import fmm
+    from paper_2410_01626_amd import lambda_dynamics as LD
+    rng = np.random.default_rng(17)
+    S = 5
+    x = np.concatenate([rng.normal(0, 0.15, (4, 3)) + rng.uniform(0, 3, 3) for _ in range(S)])
+    qA = rng.uniform(-1, 1, 4 * S)
+    qB = qA + rng.uniform(-0.5, 0.5, 4 * S)
+    ao, so = np.arange(0, 4 * S + 1, 4), np.arange(S + 1)
+    plan = fmm.Plan(1, 8, periodic=False, precision="fp64", coulomb_k=138.935458, max_atoms=4 * S,
+                    max_sites=S, max_replicas=S, device="cuda:0")
+    t = [_t(a) for a in (x, qA, qB)]
+    site = torch.zeros(4 * S, dtype=torch.int32, device="cuda:0")
+    dv = lambda lam: plan.eval_batched(ao, so, *t, site, _t(lam))["dVdl"]
+    g0, g1 = dv(np.zeros(S)).cpu().numpy(), dv(np.ones(S)).cpu().numpy()
+    mm = np.zeros((S, 36))
+    mm[:, 0], mm[:, 6] = g0, g1 - g0
+    lam = rng.uniform(-0.1, 1.1, S)
+    dvdl = dv(lam)
+    v = torch.zeros(S, dtype=torch.float64, device="cuda:0")
+    lam_new = torch.empty(S, dtype=torch.float64, device="cuda:0")
+    prm = LD.LambdaParams(60.0, 0.002, 300.0, 0.0, 0.2, 0.8)
+    LD.lambda_step(_t(np.array([0, S]), torch.int32), _t(lam), lam_new, v, dvdl,
+                   _t(np.array([7.0])), prm, first=True, mm=_t(mm.ravel()))
+    torch.cuda.synchronize()
+    scale = np.abs(dvdl.cpu().numpy()).max()
+    # v = dt/2 F/m: F vanishes up to rounding of the solve
+    F = v.cpu().numpy() * 60.0 / 0.001
+    assert np.abs(F).max() <= 1e-9 * scale
     plan.close()

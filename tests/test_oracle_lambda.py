@@ -35,14 +35,19 @@ def test_double_well_template_shape():
     V, dV = L.v_dw(np.tile([B, p0, p1, y1], (3, 1)), np.array([p0, 0.5 * (p0 + p1), p1]))
     assert np.allclose(V, [0.0, B, y1]) and np.allclose(dV, 0.0)
     # derivative agrees with central differences of the value
-    t = np.linspace(-0.5, 1.5, 41)
+    # (off the knots, where the second derivative jumps; past the end knots
+    # the confining quadratic wall)
+    t = np.linspace(-0.5, 1.5, 41) + 0.0123
     dwp = np.tile([B, p0, p1, y1], (t.size, 1))
     h = 1e-6
     Vp, _ = L.v_dw(dwp, t + h)
     Vm, _ = L.v_dw(dwp, t - h)
     _, dV = L.v_dw(dwp, t)
-    # (at a knot the second derivative jumps: central differences err by ~h V'')
     assert np.allclose((Vp - Vm) / (2 * h), dV, atol=1e-4)
+    # the walls: linear continuation of the end slope plus (k / 2) d^2
+    V, dV = L.v_dw(np.tile([B, p0, p1, y1], (2, 1)), np.array([p0 - 0.4, p1 + 0.5]))
+    assert V[0] == pytest.approx(30.0 + 300.0 * 0.1 + 0.5 * L.WALL_K * 0.1 ** 2)
+    assert dV[1] == pytest.approx(300.0 + L.WALL_K * 0.2)
 
 
 def test_mm_bias_flattens_the_reference_landscape():
