@@ -179,14 +179,38 @@ def outputs(q, qA, qB, site, n_sites, phi, field, k_e=1.0):
     return E.value, F, dVdl
 
 
+def exclusion_terms(x, q, excl_start, excl_idx, box=None, periodic=False):
+    """Potential and field at every atom from its excluded partners alone:
+    phi_i = sum_{j in excl(i)} q_j / r_ij, field_i = sum q_j r_ij / r_ij^3,
+    r_ij = x_i - x_j (periodic: the minimum image, each component wrapped
+    into [-L/2, L/2]).  Plain numpy loops over the listed pairs."""
+    x = _f64(x).reshape(-1, 3)
+    q = _f64(q)
+    phi, field = np.zeros(q.size), np.zeros((q.size, 3))
+    for i in range(len(excl_start) - 1):
+        for e in range(excl_start[i], excl_start[i + 1]):
+            j = int(excl_idx[e])
+            d = x[i] - x[j]
+            if periodic:
+                L = float(np.atleast_1d(box)[0])
+                d = d - L * np.round(d / L)
+            r = math.sqrt(float(d @ d))
+            phi[i] += q[j] / r
+            field[i] += q[j] * d / r ** 3
+    return phi, field
+
+
 def solve(x, qA, qB, site, lam, box=None, periodic=False, k_e=1.0, eps=1e-13,
-          ewald_kw=None, hamiltonian=False):
+          ewald_kw=None, hamiltonian=False, exclusions=None):
     """Full oracle solve.  Returns dict(E, F, phi, dVdl, q), all FP64.
 
     phi is returned already multiplied by k_e.  With hamiltonian=True the
     energy is that of eq 1 taken literally (each site's two end Hamiltonians
     mixed linearly): see hamiltonian_correction; phi stays the potential of the
-    interpolated charges.
+    interpolated charges.  exclusions = (start, idx), a symmetric per-atom
+    list of excluded partners: their pair terms (the minimum image for a
+    periodic cell; the other images stay) are removed from phi and the field
+    before the outputs are formed.
     """
     lam = _f64(np.atleast_1d(lam))
     q = lambda_charges(qA, qB, site, lam)
@@ -194,6 +218,9 @@ def solve(x, qA, qB, site, lam, box=None, periodic=False, k_e=1.0, eps=1e-13,
         phi, field = ewald(x, q, box, eps=eps, **(ewald_kw or {}))
     else:
         phi, field = direct(x, q)
+    if exclusions is not None:
+        ephi, efield = exclusion_terms(x, q, exclusions[0], exclusions[1], box, periodic)
+        phi, field = phi - ephi, field - efield
     E, F, dVdl = outputs(q, qA, qB, site, lam.size, phi, field, k_e)
     if hamiltonian:
         dE, dF, dD = hamiltonian_correction(x, qA, qB, site, lam, box, periodic, k_e, eps)
