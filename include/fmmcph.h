@@ -217,6 +217,23 @@ fmm_status fmm_sync_check(fmm_plan_t plan);
 /* Human-readable description of the last error on this plan (never NULL). */
 const char* fmm_last_error(fmm_plan_t plan);
 
+/* Bonded exclusions (not in the paper: MD topologies exclude the Coulomb
+ * terms of bonded neighbours).  start[0..n] (ascending, start[0] = 0) and
+ * idx[start[i] .. start[i+1]) list the excluded partners of atom i: host
+ * arrays, copied to the device now (this call allocates; evaluations do
+ * not).  Every list ascends without repeats, never names i itself, and each
+ * pair appears from both sides.  From then on every evaluation of this plan
+ * (single, batched with n = the total atom count, four-form, adjoint) removes
+ * the listed pairs' terms: k_e q_j / r from phi_i, their force from F_i and
+ * energy from E, and the matching site terms from dV/dlambda, with r the
+ * minimum-image distance for a periodic cell (the pair's other images stay);
+ * partners in another replica are skipped.  An evaluation whose total atom
+ * count differs from n returns FMM_E_INVALID.  n = 0 removes the lists.
+ * FMM_E_UNSUPPORTED on a Hamiltonian plan; FMM_E_INVALID for a malformed
+ * list (nothing changes); FMM_E_OOM / FMM_E_HIP if the upload fails (the
+ * plan is left without exclusions). */
+fmm_status fmm_set_exclusions(fmm_plan_t plan, int64_t n, const int32_t* start, const int32_t* idx);
+
 /* Release the plan and its device workspace (NULL is ignored). */
 void fmm_plan_destroy(fmm_plan_t plan);
 

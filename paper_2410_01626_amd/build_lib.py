@@ -11,7 +11,8 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libfmmcph.so")
 SOURCES = [os.path.join(CSRC, "fmm_api.hip"), os.path.join(CSRC, "lambda_dynamics.hip"),
            os.path.join(CSRC, "operators.cpp")]
-HEADERS = [os.path.join(CSRC, f) for f in ("fmm_kernels.hip", "fmm_internal.h", "operators.h")] + [
+HEADERS = [os.path.join(CSRC, f) for f in ("fmm_kernels.hip", "exclusions.hip", "fmm_internal.h",
+                                           "operators.h")] + [
     os.path.join(ROOT, "include", "fmmcph.h")]
 
 

@@ -11,6 +11,7 @@
 #include <vector>
 
 #include "fmm_kernels.hip"
+#include "exclusions.hip"
 #include "fmmcph.h"
 #include "operators.h"
 
@@ -49,6 +50,11 @@ struct fmm_plan_s {
     // unit cube (degree kPMax) followed by those of its gradient (3 x kPMax^2)
     double *hc_e = nullptr, *hc_dl = nullptr, *green = nullptr;
     int32_t* leaf_order = nullptr;  // near-field order of the leaves (largest work first)
+    // bonded exclusions (fmm_set_exclusions): per-atom partner lists for
+    // excl_n atoms and the per-block energy partials of their removal
+    int64_t excl_n = 0;
+    int32_t *excl_start = nullptr, *excl_idx = nullptr;
+    double* excl_e = nullptr;
     double* dVdl_tmp = nullptr;
     double* E_tmp = nullptr;
     fmmk::RepDesc* reps = nullptr;  // device replica descriptors (max_replicas)
@@ -321,10 +327,14 @@ fmm_status enqueue_eval(fmm_plan_t P, const std::vector<fmmk::RepDesc>& rd, cons
     const Geo g = make_geo(P);
     const int R = (int)rd.size();
     int64_t maxn = 0, S_tot = 0;
+    int64_t n_tot = 0;
     for (const RepDesc& d : rd) {
         maxn = std::max(maxn, d.n);
         S_tot += d.S;
+        n_tot += d.n;
     }
+    if (P->excl_n > 0 && n_tot != P->excl_n)
+        return fail(P, FMM_E_INVALID, "the exclusion lists were set for a different atom count");
     mark(P, 0);
     // replica descriptors: by value to the first kernel (which stores them)
     // when they fit one set, else stored by k_set_reps launches first.  The
@@ -430,6 +440,10 @@ fmm_status enqueue_eval(fmm_plan_t P, const std::vector<fmmk::RepDesc>& rd, cons
         FMM_NEAR(16)
         default: break;
     }
+    if (P->excl_n > 0)
+        k_excl<T><<<dim3(ab, R), 256, 0, st>>>(g, reps, x, qA, qB, site, lam, fa, P->dom, P->excl_start,
+                                               P->excl_idx, phi, F, P->cphi, fa.qC != nullptr,
+                                               P->excl_e);
     mark(P, 7);
     const bool ham = P->prm.hamiltonian != 0;
     if (ham && S_tot > 0)
@@ -442,6 +456,7 @@ fmm_status enqueue_eval(fmm_plan_t P, const std::vector<fmmk::RepDesc>& rd, cons
                                                        ham && S_tot > 0 ? P->hc_e : nullptr,
                                                        ham && S_tot > 0 ? P->hc_dl : nullptr,
                                                        P->leaf_count, P->site_count);
+    if (P->excl_n > 0 && E) k_excl_energy<<<R, 64, 0, st>>>((int)ab, g.coulomb_k, P->excl_e, E);
     mark(P, -1);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return fail(P, FMM_E_HIP, std::string("kernel launch: ") + hipGetErrorString(e));
@@ -920,8 +935,54 @@ void fmm_plan_destroy(fmm_plan_t P) {
     if (P->graph_exec) (void)hipGraphExecDestroy(P->graph_exec);
     if (P->graph) (void)hipGraphDestroy(P->graph);
     for (hipEvent_t ev : P->prof_ev) (void)hipEventDestroy(ev);
+    for (void* a : {(void*)P->excl_start, (void*)P->excl_idx, (void*)P->excl_e})
+        if (a) (void)hipFree(a);
     for (void* a : P->allocs) (void)hipFree(a);
     delete P;
+}
+
+fmm_status fmm_set_exclusions(fmm_plan_t P, int64_t n, const int32_t* start, const int32_t* idx) {
+    if (!P) return FMM_E_INVALID;
+    if (n < 0 || n > P->prm.max_atoms) return fail(P, FMM_E_INVALID, "exclusion atom count outside [0, max_atoms]");
+    if (n > 0 && P->prm.hamiltonian)
+        return fail(P, FMM_E_UNSUPPORTED, "exclusions with Hamiltonian interpolation");
+    if (n > 0 && (!start || (start[n] > 0 && !idx))) return fail(P, FMM_E_INVALID, "null exclusion list");
+    if (n > 0) {
+        if (start[0] != 0) return fail(P, FMM_E_INVALID, "exclusion offsets must start at 0");
+        for (int64_t i = 0; i < n; ++i)
+            if (start[i + 1] < start[i]) return fail(P, FMM_E_INVALID, "exclusion offsets must not decrease");
+        // partners in range, not the atom itself, each list ascending without
+        // repeats, and every pair listed from both sides
+        for (int64_t i = 0; i < n; ++i)
+            for (int32_t k = start[i]; k < start[i + 1]; ++k) {
+                const int32_t j = idx[k];
+                if (j < 0 || j >= n || j == i) return fail(P, FMM_E_INVALID, "exclusion partner out of range");
+                if (k > start[i] && idx[k - 1] >= j)
+                    return fail(P, FMM_E_INVALID, "exclusion lists must ascend without repeats");
+                if (!std::binary_search(idx + start[j], idx + start[j + 1], (int32_t)i))
+                    return fail(P, FMM_E_INVALID, "exclusion lists must be symmetric");
+            }
+    }
+    for (int32_t** a : {&P->excl_start, &P->excl_idx}) {
+        if (*a) (void)hipFree(*a);
+        *a = nullptr;
+    }
+    if (P->excl_e) (void)hipFree(P->excl_e);
+    P->excl_e = nullptr;
+    P->excl_n = 0;
+    P->graph_valid = false;  // the launch sequence changes
+    if (n == 0) return FMM_OK;
+    const size_t ne = (size_t)start[n];
+    const size_t parts = (size_t)P->R_max * std::max<int64_t>(1, (P->prm.max_atoms + 255) / 256);
+    if (hipMalloc((void**)&P->excl_start, (n + 1) * 4) != hipSuccess ||
+        hipMalloc((void**)&P->excl_idx, std::max<size_t>(ne, 1) * 4) != hipSuccess ||
+        hipMalloc((void**)&P->excl_e, parts * 8) != hipSuccess)
+        return fail(P, FMM_E_OOM, "exclusion lists do not fit");
+    if (hipMemcpy(P->excl_start, start, (n + 1) * 4, hipMemcpyHostToDevice) != hipSuccess ||
+        (ne && hipMemcpy(P->excl_idx, idx, ne * 4, hipMemcpyHostToDevice) != hipSuccess))
+        return fail(P, FMM_E_HIP, "exclusion upload failed");
+    P->excl_n = n;
+    return FMM_OK;
 }
 
 const char* fmm_last_error(fmm_plan_t P) {

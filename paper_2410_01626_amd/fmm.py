@@ -57,7 +57,7 @@ EXPORTS = ["fmm_plan_create", "fmm_eval", "fmm_eval_adjoint", "fmm_eval_batched"
            "fmm_eval_tautomer", "fmm_eval_tautomer_batched",
            "fmm_sync_check", "fmm_last_error", "fmm_plan_destroy", "fmm_profile",
            "fmm_profile_select", "fmm_plan_info", "fmm_host_operator",
-           "fmm_lambda_step", "fmm_lambda_dbo", "fmm_lambda_pfc"]
+           "fmm_lambda_step", "fmm_lambda_dbo", "fmm_lambda_pfc", "fmm_set_exclusions"]
 PHASES = ["bin", "p2m", "m2m", "root", "m2l", "l2l", "near_far", "reduce"]
 
 _lib = None
@@ -108,6 +108,8 @@ def load_library(path: str = LIB_PATH):
     lib.fmm_plan_info.argtypes = [vp, vp]
     lib.fmm_host_operator.restype = ctypes.c_int64
     lib.fmm_host_operator.argtypes = [i32, i32, dp]
+    lib.fmm_set_exclusions.restype = ctypes.c_int
+    lib.fmm_set_exclusions.argtypes = [vp, i64, vp, vp]
     lib.fmm_lambda_step.restype = ctypes.c_int
     lib.fmm_lambda_step.argtypes = [vp, i32, vp, i64, vp, i32] + [vp] * 14
     lib.fmm_lambda_dbo.restype = ctypes.c_int
@@ -419,6 +421,19 @@ class Plan:
         out = np.zeros(2 * len(PHASES))
         self._raise(fmm_profile(self.handle, 2, 0, out), "fmm_profile")
         return {ph: (out[i], int(out[len(PHASES) + i])) for i, ph in enumerate(PHASES)}
+
+    def set_exclusions(self, start, idx):
+        """fmm_set_exclusions from host arrays (start: n + 1 offsets, idx: the
+        partners); start=None removes the lists."""
+        if start is None:
+            self._raise(load_library().fmm_set_exclusions(self.handle, 0, None, None),
+                        "fmm_set_exclusions")
+            return
+        st = np.ascontiguousarray(start, dtype=np.int32)
+        ix = np.ascontiguousarray(idx, dtype=np.int32)
+        self._raise(load_library().fmm_set_exclusions(self.handle, st.size - 1, st.ctypes.data,
+                                                      ix.ctypes.data if ix.size else None),
+                    "fmm_set_exclusions")
 
     def info(self):
         """Resolved launch configuration of the plan (see fmm_plan_info)."""

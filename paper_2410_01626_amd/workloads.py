@@ -245,6 +245,26 @@ def water_box(seed=SEED_BASE + 2, buffers=False, depth=3, order=8):
                      "water_box", buffers)
 
 
+def small_water_box(seed=SEED_BASE + 7, depth=2, order=6):
+    """2,300 atoms: 700 waters + a 200-atom cluster, periodic 3 nm cube, 4 sites
+    (the water box recipe at a size the oracle finishes in seconds)."""
+    return _solvated(seed, 3.0, 700, 200, 0.9, 4, 10, depth, order, "small_water_box")
+
+
+def water_exclusions(n_water, n_atoms):
+    """Per-atom excluded partners of the first n_water three-atom waters (each
+    atom excludes the other two atoms of its molecule); the other atoms have
+    none.  Returns (start, idx) as int32 arrays."""
+    start = np.zeros(n_atoms + 1, dtype=np.int32)
+    idx = []
+    for i in range(n_atoms):
+        if i < 3 * n_water:
+            m = 3 * (i // 3)
+            idx += [j for j in (m, m + 1, m + 2) if j != i]
+        start[i + 1] = len(idx)
+    return start, np.array(idx, dtype=np.int32)
+
+
 def large_box(seed=SEED_BASE + 5, depth=5, order=10):
     """500,000 atoms: 160,000 waters + a 20,000-atom cluster, periodic 17 nm."""
     return _solvated(seed, 17.0, 160000, 20000, 3.63, 200, 56, depth, order,

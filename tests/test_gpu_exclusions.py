@@ -1,0 +1,157 @@
+"""Bonded exclusions through the C ABI against the FP64 oracle with the same
+excluded pairs (minimum image), single, batched and adjoint, and the
+argument checks of fmm_set_exclusions."""
+import numpy as np
+import pytest
+
+import oracle
+from gpu_util import assert_within, errors
+from paper_2410_01626_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def _plan(d, prec, **kw):
+    from paper_2410_01626_amd import fmm
+    n, S = d["x"].shape[0], d["lam"].size
+    return fmm.Plan(d["depth"], d["order"], periodic=d["periodic"], precision=prec,
+                    max_atoms=n, max_sites=max(S, 1), device="cuda:0", **kw)
+
+
+def _inputs(d, dt):
+    import torch
+    return [torch.tensor(d[k], dtype=dt, device="cuda:0") for k in ("x", "qA", "qB")] + [
+        torch.tensor(d["site"], dtype=torch.int32, device="cuda:0"),
+        torch.tensor(d["lam"], dtype=torch.float64, device="cuda:0")]
+
+
+def _host(out):
+    return {"E": out["E"].item() if out["E"].numel() == 1 else out["E"].cpu().numpy(),
+            "F": out["F"].double().cpu().numpy(), "phi": out["phi"].double().cpu().numpy(),
+            "dVdl": out["dVdl"].cpu().numpy()}
+
+
+@pytest.mark.parametrize("prec", ["fp64", "bf16x3"])
+def test_water_exclusions_match_oracle(prec):
+    import torch
+    d = W.small_water_box()
+    n = d["x"].shape[0]
+    ex = W.water_exclusions(700, n)
+    ref = oracle.solve(d["x"], d["qA"], d["qB"], d["site"], d["lam"], box=d["box"], periodic=True,
+                       exclusions=ex)
+    plan = _plan(d, prec)
+    plan.set_exclusions(*ex)
+    out = _host(plan.eval(*_inputs(d, plan.dtype), box=d["box"]))
+    torch.cuda.synchronize()
+    assert_within(errors(out, ref), d["order"], label="exclusions %s" % prec)
+    # the exclusions are a large change: the plain solve is far outside the bound
+    plain = oracle.solve(d["x"], d["qA"], d["qB"], d["site"], d["lam"], box=d["box"], periodic=True)
+    assert abs(plain["E"] - ref["E"]) > 100 * abs(out["E"] - ref["E"])
+    # removing the lists restores the plain solve
+    plan.set_exclusions(None, None)
+    out2 = _host(plan.eval(*_inputs(d, plan.dtype), box=d["box"]))
+    assert_within(errors(out2, plain), d["order"], label="cleared %s" % prec)
+    plan.close()
+
+
+def test_open_exclusions_exact_without_far_field():
+    # depth 1 open: every pair is a near pair, so the result is exact
+    d = W.random_open(31, n=600, edge=1.5, n_sites=4, depth=1, order=4)
+    n = d["x"].shape[0]
+    rng = np.random.default_rng(2)
+    # random symmetric partner lists: each atom excludes up to 3 others
+    nbr = [set() for _ in range(n)]
+    for i in range(n):
+        for j in rng.choice(n, 2, replace=False):
+            if j != i:
+                nbr[i].add(int(j))
+                nbr[int(j)].add(i)
+    start = np.concatenate([[0], np.cumsum([len(s) for s in nbr])]).astype(np.int32)
+    idx = np.concatenate([sorted(s) for s in nbr]).astype(np.int32)
+    ref = oracle.solve(d["x"], d["qA"], d["qB"], d["site"], d["lam"], exclusions=(start, idx))
+    plan = _plan(d, "fp64")
+    plan.set_exclusions(start, idx)
+    out = _host(plan.eval(*_inputs(d, plan.dtype)))
+    scale = np.abs(ref["F"]).max()
+    assert np.abs(out["F"] - ref["F"]).max() <= 1e-11 * scale
+    assert np.abs(out["phi"] - ref["phi"]).max() <= 1e-11 * np.abs(ref["phi"]).max()
+    assert out["E"] == pytest.approx(ref["E"], rel=1e-11)
+    assert np.allclose(out["dVdl"], ref["dVdl"], rtol=1e-10, atol=1e-10 * np.abs(ref["dVdl"]).max())
+    plan.close()
+
+
+def test_batched_and_adjoint_with_exclusions():
+    import torch
+    from paper_2410_01626_amd import fmm
+    reps = [W.tiny_periodic(50 + i, n=n, edge=e, n_sites=2, depth=2, order=6)
+            for i, (n, e) in enumerate([(900, 1.6), (1200, 1.8)])]
+    # exclude consecutive triples (atoms 3m, 3m+1, 3m+2) of each replica
+    parts, base = [], 0
+    starts, idxs = [0], []
+    for d in reps:
+        nr = d["x"].shape[0]
+        st, ix = W.water_exclusions(nr // 3, nr)
+        parts.append((st, ix))
+        idxs.append(ix + base)
+        starts.extend((st[1:] + starts[-1]).tolist())
+        base += nr
+    start, idx = np.array(starts, dtype=np.int32), np.concatenate(idxs).astype(np.int32)
+    ao = np.cumsum([0] + [d["x"].shape[0] for d in reps])
+    so = np.cumsum([0] + [d["lam"].size for d in reps])
+    cat = {k: np.concatenate([d[k] for d in reps]) for k in ("x", "qA", "qB", "site", "lam")}
+    plan = fmm.Plan(2, 6, periodic=True, precision="fp64", max_atoms=int(ao[-1]),
+                    max_sites=int(so[-1]), max_replicas=2, device="cuda:0")
+    plan.set_exclusions(start, idx)
+    t = [torch.tensor(cat[k], dtype=torch.float64, device="cuda:0") for k in ("x", "qA", "qB")]
+    site = torch.tensor(cat["site"], dtype=torch.int32, device="cuda:0")
+    lam = torch.tensor(cat["lam"], dtype=torch.float64, device="cuda:0")
+    boxes = np.stack([d["box"] for d in reps])
+    out = plan.eval_batched(ao, so, *t, site, lam, boxes=boxes)
+    torch.cuda.synchronize()
+    for r, d in enumerate(reps):
+        ref = oracle.solve(d["x"], d["qA"], d["qB"], d["site"], d["lam"], box=d["box"],
+                           periodic=True, exclusions=parts[r])
+        a, b = ao[r], ao[r + 1]
+        got = {"E": out["E"][r].item(), "F": out["F"][a:b].cpu().numpy(),
+               "phi": out["phi"][a:b].cpu().numpy(), "dVdl": out["dVdl"][so[r]:so[r + 1]].cpu().numpy()}
+        assert_within(errors(got, ref), 6, label="batched replica %d" % r)
+    plan.close()
+    # adjoint of one replica: dE/dx is -F of the excluded solve
+    d = reps[0]
+    plan = _plan(d, "fp64")
+    plan.set_exclusions(*parts[0])
+    inp = _inputs(d, torch.float64)
+    fwd = plan.eval(*inp, box=d["box"])
+    g = torch.ones(1, dtype=torch.float64, device="cuda:0")
+    adj = plan.eval_adjoint(*inp, g, box=d["box"])
+    torch.cuda.synchronize()
+    assert torch.allclose(adj["grad_x"], -fwd["F"], rtol=1e-12, atol=1e-12)
+    plan.close()
+
+
+def test_set_exclusions_rejects_bad_lists():
+    from paper_2410_01626_amd import fmm
+    d = W.tiny_periodic(60, n=30, edge=1.0, n_sites=1, depth=1, order=4)
+    plan = _plan(d, "f32")
+    bad = [
+        ([0, 1, 1], [1]),                 # 0 -> 1 but not 1 -> 0
+        ([0, 1, 2], [0, 0]),              # self partner
+        ([0, 2, 3, 4], [2, 1, 0, 0]),     # list of 0 not ascending
+        ([1, 2, 3], [1, 0]),              # offsets do not start at 0
+        ([0, 1, 2], [1, 5]),              # partner 5 outside n = 2
+    ]
+    for st, ix in bad:
+        with pytest.raises(fmm.FmmError) as e:
+            plan.set_exclusions(np.array(st), np.array(ix))
+        assert e.value.status == fmm.FMM_E_INVALID, (st, ix)
+    # lists for 2 atoms, a call with 30: rejected at the call
+    plan.set_exclusions(np.array([0, 1, 2]), np.array([1, 0]))
+    with pytest.raises(fmm.FmmError) as e:
+        plan.eval(*_inputs(d, plan.dtype), box=d["box"])
+    assert e.value.status == fmm.FMM_E_INVALID
+    plan.close()
+    ham = _plan(d, "f32", hamiltonian=True)
+    with pytest.raises(fmm.FmmError) as e:
+        ham.set_exclusions(np.array([0, 1, 2]), np.array([1, 0]))
+    assert e.value.status == fmm.FMM_E_UNSUPPORTED
+    ham.close()
