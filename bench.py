@@ -221,6 +221,12 @@ def main():
                      device=dev, hamiltonian=True)
     sec_ham, _ = timed(hplan, inp, args.steps, args.warmup)
 
+    # the same box with the intramolecular pairs of its 9,000 waters excluded
+    xplan = fmm.Plan(depth, order, periodic=True, precision="bf16x3", max_atoms=n, max_sites=S,
+                     device=dev)
+    xplan.set_exclusions(*workloads.water_exclusions(9000, n))
+    sec_excl, _ = timed(xplan, inp, args.steps, args.warmup)
+
     # constant-pH dynamics of the same box: every step one solve (kJ/mol) and
     # one velocity-Verlet step of the 20 lambda particles (bias V_pH + V_dw,
     # Bussi thermostat; pKa_ref 4.0 at pH 4.0)
@@ -381,6 +387,9 @@ def main():
         "tautomers": {"value": 1.0 / sec_taut, "ms_per_step": sec_taut * 1e3,
                       "workload": "same box, four charge forms per site (half the sites with "
                                   "tautomers), E+F+dV/dlambda_p+dV/dlambda_t"},
+        "exclusions": {"value": 1.0 / sec_excl, "ms_per_step": sec_excl * 1e3,
+                       "workload": "same box, the 3 intramolecular pairs of each of the 9,000 "
+                                   "waters excluded (54,000 partner entries)"},
         "lambda_dynamics": lam_dyn,
         "batched": batched,
         "phase_ms": phase_ms,
