@@ -28,8 +28,8 @@ __device__ __forceinline__ double excl_charge(const RepDesc& rd, int64_t i, cons
 // k_e q_j / r from phi_i, k_e q_i q_j r / r^3 from F_i and the matching site
 // term from cphi_i for every listed partner j of i, and leaves the block's
 // share of the energy change (sum of -q_i dphi_i / k_e, in the units of the
-// leaf energy partials) in excl_e.  Partners outside the atom's replica are
-// skipped.
+// leaf energy partials, which the final reduction adds) in excl_e.  Partners
+// outside the atom's replica are skipped.
 template <typename T>
 __global__ __launch_bounds__(256) void k_excl(Geo g, const RepDesc* __restrict__ reps,
                                               const T* __restrict__ x, const T* __restrict__ qA,
@@ -85,17 +85,6 @@ __global__ __launch_bounds__(256) void k_excl(Geo g, const RepDesc* __restrict__
         __syncthreads();
     }
     if (t == 0) excl_e[(size_t)r * gridDim.x + blockIdx.x] = red[0];
-}
-
-// E[r] += k_e / 2 (sum of replica r's partials), in block order.
-__global__ __launch_bounds__(64) void k_excl_energy(int nparts, double coulomb_k,
-                                                    const double* __restrict__ excl_e,
-                                                    double* __restrict__ E) {
-    if (threadIdx.x != 0) return;
-    const int r = blockIdx.x;
-    double s = 0.0;
-    for (int b = 0; b < nparts; ++b) s += excl_e[(size_t)r * nparts + b];
-    E[r] += 0.5 * coulomb_k * s;
 }
 
 }  // namespace fmmk

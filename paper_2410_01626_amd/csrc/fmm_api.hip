@@ -455,8 +455,8 @@ fmm_status enqueue_eval(fmm_plan_t P, const std::vector<fmmk::RepDesc>& rd, cons
                                                        dVdl, P->status, qA, qB, lam, fa, dVdl_t, reps,
                                                        ham && S_tot > 0 ? P->hc_e : nullptr,
                                                        ham && S_tot > 0 ? P->hc_dl : nullptr,
-                                                       P->leaf_count, P->site_count);
-    if (P->excl_n > 0 && E) k_excl_energy<<<R, 64, 0, st>>>((int)ab, g.coulomb_k, P->excl_e, E);
+                                                       P->leaf_count, P->site_count,
+                                                       P->excl_n > 0 ? P->excl_e : nullptr, (int)ab);
     mark(P, -1);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return fail(P, FMM_E_HIP, std::string("kernel launch: ") + hipGetErrorString(e));

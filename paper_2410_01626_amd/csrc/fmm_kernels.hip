@@ -2407,7 +2407,8 @@ __global__ __launch_bounds__(256) void k_reduce(Geo g, int R, int64_t nparts,
                                                 const double* __restrict__ hc_e,
                                                 const double* __restrict__ hc_dl,
                                                 int32_t* __restrict__ leaf_count,
-                                                int32_t* __restrict__ site_count) {
+                                                int32_t* __restrict__ site_count,
+                                                const double* __restrict__ excl_e, int excl_parts) {
     __shared__ double red[256], red_t[256];
     __shared__ int32_t mem[kSiteCap];
     const int t = threadIdx.x;
@@ -2436,6 +2437,9 @@ __global__ __launch_bounds__(256) void k_reduce(Geo g, int R, int64_t nparts,
     };
     if (b < R) {
         for (int64_t i = t; i < nparts; i += 256) v += leaf_energy[(size_t)b * nparts + i];
+        // bonded exclusions: the removed pair energies, same units
+        if (excl_e)
+            for (int i = t; i < excl_parts; i += 256) v += excl_e[(size_t)b * excl_parts + i];
     } else {
         const int s = b - R;
         const int m0 = site_start[s], n = site_start[s + 1] - m0;

@@ -143,29 +143,37 @@ __device__ double lambda_force(const StepArgs& A, int64_t c, double ph_r, double
     return -dH;
 }
 
-// Fixed-order block sum of two values (result in thread 0).
+// Fixed-order block sum of two values (result in thread 0): a shuffle tree
+// per wavefront, then the wavefront sums in order.
 __device__ void block_sum2(double& a, double& b) {
-    __shared__ double sa[kThreads], sb[kThreads];
+    __shared__ double sa[kThreads / 64], sb[kThreads / 64];
     const int t = threadIdx.x;
-    sa[t] = a;
-    sb[t] = b;
-    __syncthreads();
-    for (int s = kThreads / 2; s > 0; s >>= 1) {
-        if (t < s) {
-            sa[t] += sa[t + s];
-            sb[t] += sb[t + s];
-        }
-        __syncthreads();
+    for (int off = 32; off > 0; off >>= 1) {
+        a += __shfl_down(a, off, 64);
+        b += __shfl_down(b, off, 64);
     }
-    a = sa[0];
-    b = sb[0];
+    if ((t & 63) == 0) {
+        sa[t >> 6] = a;
+        sb[t >> 6] = b;
+    }
+    __syncthreads();
+    if (t == 0) {
+        a = sa[0];
+        b = sb[0];
+        for (int w = 1; w < kThreads / 64; ++w) {
+            a += sa[w];
+            b += sb[w];
+        }
+    }
 }
 
 // One velocity-Verlet step of replica blockIdx.x with the forces at lambda_n:
 // closing half kick (unless first), Bussi rescaling of the full-step
-// velocities, half kick, drift into lam_new.  The force is evaluated twice
-// (before and after the kinetic-energy sum) from the unmodified inputs, so
-// both passes see identical values.
+// velocities, half kick, drift into lam_new.  A thread keeps the force and
+// full-step velocity of its first kKeep coordinates in registers; further
+// coordinates evaluate the force again after the kinetic-energy sum (from the
+// unmodified inputs, so both evaluations agree).
+constexpr int kKeep = 4;
 __global__ __launch_bounds__(kThreads) void k_lambda_step(StepArgs A) {
     const int r = blockIdx.x, t = threadIdx.x;
     int64_t a, b;
@@ -173,11 +181,19 @@ __global__ __launch_bounds__(kThreads) void k_lambda_step(StepArgs A) {
     const double ph_r = A.ph[r];
     const double hm = 0.5 * A.prm.dt / A.prm.mass;
     double K = 0.0, E = 0.0;
-    for (int64_t c = a + t; c < b; c += kThreads) {
+    double keepF[kKeep], keepV[kKeep];
+    int m = 0;
+    for (int64_t c = a + t; c < b; c += kThreads, ++m) {
         double eb;
         const double F = lambda_force(A, c, ph_r, eb);
         double v = A.v[c];
         if (!A.first) v += hm * F;
+#pragma unroll
+        for (int k = 0; k < kKeep; ++k)
+            if (k == m) {
+                keepF[k] = F;
+                keepV[k] = v;
+            }
         K += 0.5 * A.prm.mass * v * v;
         E += eb;
         const double l = A.lam[c];
@@ -219,11 +235,23 @@ __global__ __launch_bounds__(kThreads) void k_lambda_step(StepArgs A) {
     }
     __syncthreads();
     const double alpha = alpha_s;
-    for (int64_t c = a + t; c < b; c += kThreads) {
-        double eb;
-        const double F = lambda_force(A, c, ph_r, eb);
-        double v = A.v[c];
-        if (!A.first) v += hm * F;
+    m = 0;
+    for (int64_t c = a + t; c < b; c += kThreads, ++m) {
+        double F = 0.0, v = 0.0;
+        bool kept = false;
+#pragma unroll
+        for (int k = 0; k < kKeep; ++k)
+            if (k == m) {
+                F = keepF[k];
+                v = keepV[k];
+                kept = true;
+            }
+        if (!kept) {
+            double eb;
+            F = lambda_force(A, c, ph_r, eb);
+            v = A.v[c];
+            if (!A.first) v += hm * F;
+        }
         v = v * alpha + hm * F;
         A.v[c] = v;
         A.lam_new[c] = A.lam[c] + A.prm.dt * v;
