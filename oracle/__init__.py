@@ -228,6 +228,37 @@ def solve(x, qA, qB, site, lam, box=None, periodic=False, k_e=1.0, eps=1e-13,
     return {"E": E, "F": F, "phi": k_e * phi, "dVdl": dVdl, "q": q}
 
 
+def adjoint_phi(x, qA, qB, site, lam, gE, gphi, box=None, periodic=False, k_e=1.0, eps=1e-13):
+    """Gradients of L = gE E + sum_i gphi_i phi_i (phi as solve returns it,
+    with k_e) with respect to x, qA, qB and lambda.  phi = k_e Psi q is
+    linear in q with the symmetric pair matrix Psi, so dL/dq = gE phi +
+    k_e Psi gphi (the potential of charges gphi), and
+    dL/dx_k = -gE F_k - k_e (gphi_k field_k(q) + q_k field_k(gphi)),
+    field(c) the field of charges c at the atoms.  Returns (gx, gqA, gqB, glam)."""
+    x = _f64(x).reshape(-1, 3)
+    qA, qB, gphi = _f64(qA), _f64(qB), _f64(gphi)
+    lam = _f64(np.atleast_1d(lam))
+    site = np.ascontiguousarray(site, dtype=np.int32)
+    q = lambda_charges(qA, qB, site, lam)
+    if periodic:
+        pq, fq = ewald(x, q, box, eps=eps)
+        pg, fg = ewald(x, gphi, box, eps=eps)
+    else:
+        pq, fq = direct(x, q)
+        pg, fg = direct(x, gphi)
+    gq = k_e * (gE * pq + pg)
+    gx = -k_e * (gE * q[:, None] * fq + gphi[:, None] * fq + q[:, None] * fg)
+    insite = (site >= 0)
+    lam_i = np.where(insite, lam[np.maximum(site, 0)], 0.0)
+    gqA = (1.0 - lam_i) * gq
+    gqB = lam_i * gq
+    glam = np.zeros(lam.size)
+    for s in range(lam.size):
+        m = site == s
+        glam[s] = np.sum((qB[m] - qA[m]) * gq[m])
+    return gx, gqA, gqB, glam
+
+
 def hamiltonian_correction(x, qA, qB, site, lam, box=None, periodic=False, k_e=1.0, eps=1e-13):
     """Hamiltonian minus charge interpolation (Methods, eq 1).
 
