@@ -169,6 +169,24 @@ fmm_status fmm_eval_adjoint(fmm_plan_t plan, int64_t n, const void* x, const voi
                             double* grad_lambda, double* E, void* F, void* phi,
                             double* dVdl);
 
+/* Adjoint of L = gE E + sum_i gphi_i phi_i: upstream weights on the energy
+ * (gE, a HOST double here) and on the potential output (gphi, n values of the
+ * plan's type, device).  phi = k_e Psi q is linear in the charges with a
+ * symmetric pair matrix Psi, so with phi3 the potential of the charges gphi:
+ *   dL/dq_i     = gE phi_i + phi3_i  -> grad_qA, grad_qB as in fmm_eval_adjoint
+ *   grad_lambda = gE dVdl + sum_{i in s} (qB_i - qA_i) phi3_i
+ *   grad_x      = -gE F - F(q + gphi) + F(q) + F(gphi)
+ * (the last line from k_e gphi^T Psi q = E(q + gphi) - E(q) - E(gphi)).  Three
+ * solves on the plan's stream (charges q, q + gphi and gphi) and one combine
+ * kernel; exclusions set on the plan apply to all three.  Pointers as in
+ * fmm_eval_adjoint; FMM_E_UNSUPPORTED on a Hamiltonian plan.  Upstream
+ * weights on F would need dipole sources and are not provided. */
+fmm_status fmm_eval_adjoint_phi(fmm_plan_t plan, int64_t n, const void* x, const void* qA,
+                                const void* qB, const int32_t* site, int64_t n_sites,
+                                const double* lambda, const double* box, double gE,
+                                const void* gphi, void* grad_x, void* grad_qA, void* grad_qB,
+                                double* grad_lambda, double* E, void* F, void* phi, double* dVdl);
+
 /* R independent systems (replicas) in one call.  Atoms and sites of replica r
  * occupy [atom_off[r], atom_off[r+1]) and [site_off[r], site_off[r+1]) of the
  * concatenated arrays; atom_off and site_off are HOST arrays of R+1 int64

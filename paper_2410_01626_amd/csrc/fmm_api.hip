@@ -55,6 +55,11 @@ struct fmm_plan_s {
     int64_t excl_n = 0;
     int32_t *excl_start = nullptr, *excl_idx = nullptr;
     double* excl_e = nullptr;
+    // potential-weight adjoint: charges q + g, and the outputs of the solves
+    // with q + g and with g (F2, phi2, F3, phi3), their site sums and energies
+    void *adj_qA = nullptr, *adj_qB = nullptr, *adj_F2 = nullptr, *adj_phi2 = nullptr,
+         *adj_F3 = nullptr, *adj_phi3 = nullptr;
+    double *adj_dl2 = nullptr, *adj_dl3 = nullptr, *adj_E = nullptr;
     double* dVdl_tmp = nullptr;
     double* E_tmp = nullptr;
     fmmk::RepDesc* reps = nullptr;  // device replica descriptors (max_replicas)
@@ -480,6 +485,34 @@ fmm_status enqueue_adjoint(fmm_plan_t P, const std::vector<fmmk::RepDesc>& rd, c
     return hipGetLastError() == hipSuccess ? FMM_OK : fail(P, FMM_E_HIP, "adjoint launch failed");
 }
 
+// Gradients of gE E + gphi . phi: three solves (q, q + gphi, gphi) on the
+// plan's stream, then the combine kernel.
+template <typename T>
+fmm_status enqueue_adjoint_phi(fmm_plan_t P, const std::vector<fmmk::RepDesc>& rd, const T* x,
+                               const T* qA, const T* qB, const int32_t* site, const double* lam,
+                               double gE, const T* gphi, T* gx, T* gqA, T* gqB, double* glam,
+                               double* E, T* F, T* phi, double* dVdl) {
+    const int64_t n = rd[0].n, S = rd[0].S;
+    T* Fw = F ? F : (T*)P->F_tmp;
+    T* pw = phi ? phi : (T*)P->phi_tmp;
+    double* dw = dVdl ? dVdl : P->dVdl_tmp;
+    fmm_status s = enqueue_eval<T>(P, rd, x, qA, qB, site, lam, E ? E : P->E_tmp, Fw, pw, dw);
+    if (s != FMM_OK) return s;
+    const unsigned nb = nblocks(std::max(n, S), 256);
+    fmmk::k_add_weights<T><<<nblocks(n, 256), 256, 0, P->stream>>>(n, qA, qB, gphi, (T*)P->adj_qA,
+                                                                   (T*)P->adj_qB);
+    s = enqueue_eval<T>(P, rd, x, (const T*)P->adj_qA, (const T*)P->adj_qB, site, lam, P->adj_E,
+                        (T*)P->adj_F2, (T*)P->adj_phi2, P->adj_dl2);
+    if (s != FMM_OK) return s;
+    s = enqueue_eval<T>(P, rd, x, gphi, gphi, site, lam, P->adj_E, (T*)P->adj_F3, (T*)P->adj_phi3,
+                        P->adj_dl3);
+    if (s != FMM_OK) return s;
+    fmmk::k_adjoint_phi<T><<<nb, 256, 0, P->stream>>>(n, S, site, lam, gE, Fw, pw, dw, (const T*)P->adj_F2,
+                                                      P->adj_dl2, (const T*)P->adj_F3,
+                                                      (const T*)P->adj_phi3, gx, gqA, gqB, glam);
+    return hipGetLastError() == hipSuccess ? FMM_OK : fail(P, FMM_E_HIP, "adjoint launch failed");
+}
+
 // Run `enqueue` eagerly, or (params.graph) replay the cached graph when the
 // argument key matches, else capture a new graph and replay it.
 template <class Fn>
@@ -650,6 +683,11 @@ fmm_status fmm_plan_create(const fmm_params* prm, void* hip_stream, fmm_plan_t* 
     ok &= dev_alloc(P, &P->phi_tmp, N * ts);
     ok &= dev_alloc(P, (void**)&P->dVdl_tmp, S * 8);
     ok &= dev_alloc(P, (void**)&P->E_tmp, RM * 8);
+    for (void** a : {&P->adj_qA, &P->adj_qB, &P->adj_phi2, &P->adj_phi3}) ok &= dev_alloc(P, a, N * ts);
+    for (void** a : {&P->adj_F2, &P->adj_F3}) ok &= dev_alloc(P, a, N * 3 * ts);
+    ok &= dev_alloc(P, (void**)&P->adj_dl2, S * 8);
+    ok &= dev_alloc(P, (void**)&P->adj_dl3, S * 8);
+    ok &= dev_alloc(P, (void**)&P->adj_E, RM * 8);
     if (!ok) {
         fmm_plan_destroy(P);
         return FMM_E_OOM;
@@ -1039,6 +1077,37 @@ fmm_status fmm_eval_adjoint(fmm_plan_t P, int64_t n, const void* x, const void* 
         return enqueue_adjoint<float>(P, rd, (const float*)x, (const float*)qA, (const float*)qB,
                                       site, lam, gE, (float*)grad_x, (float*)grad_qA,
                                       (float*)grad_qB, grad_lambda, E, (float*)F, (float*)phi, dVdl);
+    });
+}
+
+fmm_status fmm_eval_adjoint_phi(fmm_plan_t P, int64_t n, const void* x, const void* qA,
+                                const void* qB, const int32_t* site, int64_t S, const double* lam,
+                                const double* box, double gE, const void* gphi, void* grad_x,
+                                void* grad_qA, void* grad_qB, double* grad_lambda, double* E, void* F,
+                                void* phi, double* dVdl) {
+    fmm_status s = check_common(P, n, x, qA, qB, site, S, lam);
+    if (s != FMM_OK) return s;
+    if (!gphi || !std::isfinite(gE)) return fail(P, FMM_E_INVALID, "null or non-finite upstream weight");
+    if (P->prm.hamiltonian)
+        return fail(P, FMM_E_UNSUPPORTED, "the adjoint covers charge interpolation only");
+    double L = 0;
+    if ((s = check_box(P, box, &L)) != FMM_OK) return s;
+    P->err.clear();
+    std::vector<fmmk::RepDesc> rd(1);
+    rd[0] = {0, n, 0, S, L, 0};
+    KeyBuf key;
+    key.add(5).add(rd[0]).add(x).add(qA).add(qB).add(site).add(lam).add(gE).add(gphi).add(grad_x)
+        .add(grad_qA).add(grad_qB).add(grad_lambda).add(E).add(F).add(phi).add(dVdl);
+    return run_maybe_graph(P, key.b, [&]() {
+        if (P->fp64)
+            return enqueue_adjoint_phi<double>(P, rd, (const double*)x, (const double*)qA,
+                                               (const double*)qB, site, lam, gE, (const double*)gphi,
+                                               (double*)grad_x, (double*)grad_qA, (double*)grad_qB,
+                                               grad_lambda, E, (double*)F, (double*)phi, dVdl);
+        return enqueue_adjoint_phi<float>(P, rd, (const float*)x, (const float*)qA, (const float*)qB,
+                                          site, lam, gE, (const float*)gphi, (float*)grad_x,
+                                          (float*)grad_qA, (float*)grad_qB, grad_lambda, E, (float*)F,
+                                          (float*)phi, dVdl);
     });
 }
 
