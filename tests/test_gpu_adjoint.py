@@ -136,6 +136,27 @@ def test_second_order_request_is_rejected():
     plan = _plan(d, "fp64", dev)
     x, qA, qB, site, lam = _tensors(d, torch.float64, dev)
     E, F, phi, dVdl = fmm_coulomb(plan, x, qA, qB, site, lam)
-    assert not F.requires_grad and not phi.requires_grad
+    assert not F.requires_grad and not dVdl.requires_grad
     with pytest.raises(RuntimeError):
         F.sum().backward()
+
+
+def test_potential_is_differentiable():
+    # L = w E + g . phi through autograd equals the oracle's analytic gradient
+    import torch
+    import oracle
+    from paper_2410_01626_amd.autograd import fmm_coulomb
+    dev = torch.device("cuda:0")
+    d = W.random_open(81, n=400, edge=1.3, n_sites=3, depth=1, order=4)
+    plan = _plan(d, "fp64", dev)
+    x, qA, qB, site, lam = _tensors(d, torch.float64, dev)
+    g = torch.tensor(np.random.default_rng(9).normal(0, 1, d["x"].shape[0]), device=dev)
+    E, F, phi, dVdl = fmm_coulomb(plan, x, qA, qB, site, lam)
+    assert phi.requires_grad
+    L = 0.4 * E.sum() + (g * phi).sum()
+    gx, gA, gB, gl = torch.autograd.grad(L, [x, qA, qB, lam])
+    rx, rA, rB, rl = oracle.adjoint_phi(d["x"], d["qA"], d["qB"], d["site"], d["lam"], 0.4,
+                                        g.cpu().numpy())
+    for got, ref in ((gx, rx), (gA, rA), (gB, rB), (gl, rl)):
+        got = got.cpu().numpy()
+        assert np.abs(got - ref).max() <= 1e-9 * max(1.0, np.abs(ref).max())
