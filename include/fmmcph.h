@@ -238,8 +238,9 @@ const char* fmm_last_error(fmm_plan_t plan);
 /* Bonded exclusions (not in the paper: MD topologies exclude the Coulomb
  * terms of bonded neighbours).  start[0..n] (ascending, start[0] = 0) and
  * idx[start[i] .. start[i+1]) list the excluded partners of atom i: host
- * arrays, copied to the device now (this call allocates; evaluations do
- * not).  Every list ascends without repeats, never names i itself, and each
+ * arrays, copied to the device now (this call allocates, and waits for the
+ * plan's stream before replacing lists already set; evaluations allocate
+ * nothing).  Every list ascends without repeats, never names i itself, and each
  * pair appears from both sides.  From then on every evaluation of this plan
  * (single, batched with n = the total atom count, four-form, adjoint) removes
  * the listed pairs' terms: k_e q_j / r from phi_i, their force from F_i and

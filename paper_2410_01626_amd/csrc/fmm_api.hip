@@ -1001,6 +1001,9 @@ fmm_status fmm_set_exclusions(fmm_plan_t P, int64_t n, const int32_t* start, con
                     return fail(P, FMM_E_INVALID, "exclusion lists must be symmetric");
             }
     }
+    // evaluations already enqueued may still read the old lists
+    if (P->excl_n > 0 && hipStreamSynchronize(P->stream) != hipSuccess)
+        return fail(P, FMM_E_HIP, "stream sync failed");
     for (int32_t** a : {&P->excl_start, &P->excl_idx}) {
         if (*a) (void)hipFree(*a);
         *a = nullptr;
