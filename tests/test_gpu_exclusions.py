@@ -155,3 +155,28 @@ def test_set_exclusions_rejects_bad_lists():
         ham.set_exclusions(np.array([0, 1, 2]), np.array([1, 0]))
     assert e.value.status == fmm.FMM_E_UNSUPPORTED
     ham.close()
+
+
+def test_four_form_path_removes_the_same_pairs():
+    # with B = A and D = C a four-form site is a two-form site with (A, C):
+    # the four-form call with exclusions equals the two-form call with them
+    # (which the tests above hold to the oracle), so the exclusion kernel's
+    # four-form charges and site weights are the two-form ones
+    import torch
+    d = W.small_water_box()
+    n = d["x"].shape[0]
+    ex = W.water_exclusions(700, n)
+    plan = _plan(d, "fp64")
+    plan.set_exclusions(*ex)
+    x, qA, qB, site, lam = _inputs(d, torch.float64)
+    two = plan.eval(x, qA, qB, site, lam, box=d["box"])
+    two = {k: v.clone() for k, v in two.items()}
+    lam_t = torch.full_like(lam, 0.3)
+    four = plan.eval_tautomer(x, qA, qA, qB, qB, site, lam, lam_t, box=d["box"])
+    torch.cuda.synchronize()
+    assert four["E"].item() == pytest.approx(two["E"].item(), rel=1e-12)
+    assert torch.allclose(four["F"], two["F"], rtol=1e-11, atol=1e-11 * two["F"].abs().max().item())
+    assert torch.allclose(four["phi"], two["phi"], rtol=1e-11, atol=1e-11 * two["phi"].abs().max().item())
+    assert torch.allclose(four["dVdl_p"], two["dVdl"], rtol=1e-10, atol=1e-10 * two["dVdl"].abs().max().item())
+    assert four["dVdl_t"].abs().max().item() <= 1e-9 * two["dVdl"].abs().max().item()
+    plan.close()
