@@ -66,3 +66,33 @@ def test_potential_weights_rejected_on_hamiltonian_plans():
     with pytest.raises(fmm.FmmError) as e:
         _run(d, "f32", 1.0, np.ones(100), hamiltonian=True)
     assert e.value.status == fmm.FMM_E_UNSUPPORTED
+
+
+def test_graph_replay_of_the_three_solves():
+    # a graph plan captures the three solves and the combine kernel once and
+    # replays them; every replay equals the eager plan bitwise
+    import torch
+    from paper_2410_01626_amd import fmm
+    d = W.tiny_periodic(74, n=1800, edge=2.0, n_sites=3, depth=3, order=6)
+    n, S = d["x"].shape[0], d["lam"].size
+    stream = torch.cuda.Stream("cuda:0")
+    kw = dict(periodic=True, precision="f32", max_atoms=n, max_sites=S, device="cuda:0")
+    eager = fmm.Plan(3, 6, **kw)
+    gplan = fmm.Plan(3, 6, stream=stream, graph=True, **kw)
+    t = [torch.tensor(d[k], dtype=torch.float32, device="cuda:0") for k in ("x", "qA", "qB")]
+    site = torch.tensor(d["site"], dtype=torch.int32, device="cuda:0")
+    lam = torch.tensor(d["lam"], dtype=torch.float64, device="cuda:0")
+    g = torch.tensor(np.random.default_rng(8).normal(0, 1, n), dtype=torch.float32, device="cuda:0")
+    ref = eager.eval_adjoint_phi(*t, site, lam, 0.5, g, box=d["box"])
+    torch.cuda.synchronize()
+    for _ in range(3):
+        with torch.cuda.stream(stream):
+            got = gplan.eval_adjoint_phi(*t, site, lam, 0.5, g, box=d["box"])
+        stream.synchronize()
+        junk = torch.randn(1000, device="cuda:0").sum()  # eager work between replays
+        torch.cuda.synchronize()
+        assert junk.isfinite()
+        for k in ("grad_x", "grad_qA", "grad_qB", "grad_lambda", "E", "F", "phi"):
+            assert torch.equal(got[k], ref[k]), k
+    eager.close()
+    gplan.close()
