@@ -386,7 +386,7 @@ fmm_status fmm_lambda_dbo(void* hip_stream, int32_t R, const int32_t* coord_off,
  * deprotonation -k_B T ln(Z_1 / Z_0) of V_pH + V_dw, Z_0 and Z_1 the integrals
  * of exp(-(V_pH + V_dw)/k_B T) over [0, 1/2] and [1/2, 1], equals
  * ln(10) k_B T (pKa - pH) (0 without pKa); Gauss-Legendre quadrature on the
- * spline pieces and bisection on y1 in [-200, 200] kJ/mol.  The free energy
+ * spline pieces and a safeguarded regula falsi on y1 in [-200, 200] kJ/mol.  The free energy
  * grows with y1 but is bounded (the barrier-top part of [1/2, 1] does not
  * move with y1): a target out of reach leaves y1 at the nearer end. */
 fmm_status fmm_lambda_pfc(void* hip_stream, int32_t R, const int32_t* coord_off, int64_t C,

@@ -291,22 +291,43 @@ __device__ double pfc_dg(const Knots& k, double slope, double beta, const GaussL
 }
 
 // y1 for which the free energy of deprotonation of V_pH + V_dw equals
-// ln(10) k_B T (pKa - pH) (0 without pKa): bisection on [-200, 200] kJ/mol
-// (the free energy increases with y1); wave-uniform (every lane takes the
-// same branches).
+// ln(10) k_B T (pKa - pH) (0 without pKa), searched in [-200, 200] kJ/mol
+// (the free energy increases with y1; a target out of reach leaves y1 at the
+// nearer end).  Safeguarded regula falsi: Illinois steps (the retained end's
+// residual halved when the same end is kept twice) alternate with bisection
+// steps, so every two steps at least halve the bracket; it stops once the
+// residual is below 1e-13 kJ/mol or the bracket below 1e-11; wave-uniform
+// (every lane holds the same residuals).
 __device__ double pfc_solve(double B, double p0, double p1, double pk, double ph_r, double T,
                             const GaussLegendre& gl) {
     const double beta = 1.0 / (kKB * T);
     const double slope = isnan(pk) ? 0.0 : kLn10 * kKB * T * (pk - ph_r);
     const double target = slope;  // V_pH(1) - V_pH(0)
+    auto resid = [&](double y1) { return pfc_dg(dw_knots(B, p0, p1, y1), slope, beta, gl) - target; };
     double lo = -200.0, hi = 200.0;
-    for (int it = 0; it < 200; ++it) {
-        const double mid = 0.5 * (lo + hi);
-        if (mid <= lo || mid >= hi) break;
-        if (pfc_dg(dw_knots(B, p0, p1, mid), slope, beta, gl) < target) lo = mid;
-        else hi = mid;
+    double glo = resid(lo), ghi = resid(hi);
+    if (glo >= 0.0) return lo;
+    if (ghi <= 0.0) return hi;
+    int side = 0;  // end kept by the last step: -1 lo, +1 hi
+    for (int it = 0; it < 200 && hi - lo > 1e-11; ++it) {
+        double x = (it & 1) ? 0.5 * (lo + hi) : (lo * ghi - hi * glo) / (ghi - glo);
+        if (!(x > lo && x < hi)) x = 0.5 * (lo + hi);
+        if (x <= lo || x >= hi) break;  // no representable point inside
+        const double gx = resid(x);
+        if (fabs(gx) < 1e-13) return x;  // kJ/mol: y1 then agrees to ~1e-10
+        if (gx < 0.0) {
+            lo = x;
+            glo = gx;
+            if (side == 1) ghi *= 0.5;
+            side = 1;
+        } else {
+            hi = x;
+            ghi = gx;
+            if (side == -1) glo *= 0.5;
+            side = -1;
+        }
     }
-    return 0.5 * (lo + hi);
+    return (lo * ghi - hi * glo) / (ghi - glo);
 }
 
 struct DboArgs {
