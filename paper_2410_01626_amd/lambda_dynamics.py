@@ -52,11 +52,22 @@ def _raise(st, name):
 
 def lambda_step(coord_off, lam, lam_new, v, dvdl, ph, params: LambdaParams, first=False,
                 partner=None, pka=None, mm=None, dwp=None, noise=None, stats_w=None,
-                stats_b=None, kin=None, e_bias=None, stream=None):
-    """fmm_lambda_step on device tensors (float64; coord_off, partner int32)."""
+                stats_b=None, kin=None, e_bias=None, stream=None, check=True):
+    """fmm_lambda_step on device tensors (float64; coord_off, partner int32).
+    check=False skips the checks of every tensor but dvdl (for a caller that
+    has already made them on the same tensors)."""
     import torch
     R = coord_off.numel() - 1
     C = lam.numel()
+    if not check:
+        _check(dvdl, C, torch.float64, "dvdl")
+        s = stream if stream is not None else torch.cuda.current_stream(lam.device)
+        st = load_library().fmm_lambda_step(
+            ctypes.c_void_p(s.cuda_stream), R, _p(coord_off), C, ctypes.byref(params),
+            1 if first else 0, _p(lam), _p(lam_new), _p(v), _p(dvdl), _p(partner), _p(pka), _p(ph),
+            _p(mm), _p(dwp), _p(noise), _p(stats_w), _p(stats_b), _p(kin), _p(e_bias))
+        _raise(st, "fmm_lambda_step")
+        return
     f64, i32 = torch.float64, torch.int32
     _check(coord_off, R + 1, i32, "coord_off")
     for t, n, nm in ((lam, C, "lam"), (lam_new, C, "lam_new"), (v, C, "v"), (dvdl, C, "dvdl"),
@@ -165,6 +176,7 @@ class LambdaDynamics:
         self.well_block = well_block if well_block is not None else int(round(40.0 / dt))
         self.barrier_block = barrier_block if barrier_block is not None else int(round(1000.0 / dt))
         self.n = 0
+        self._checked = None  # identities of the tensors the last full check saw
         lambda_pfc(self.coord_off, self.dwp, self.ph, temperature, pka=self.pka)
 
     def draw_noise(self):
@@ -187,10 +199,19 @@ class LambdaDynamics:
             if i == 0:
                 self.draw_noise()
             self.noise = self.noise_bank[i]
+        # the full tensor checks run again whenever a tensor was replaced
+        # (lam and lam_next alternate; the noise row moves through one bank)
+        # (dvdl, usually a fresh tensor per solve, is checked on every call)
+        seen = tuple(id(t) for t in (self.coord_off, self.v, self.ph, self.partner, self.pka,
+                                     self.mm, self.dwp, self.noise_bank, self.stats_w,
+                                     self.stats_b, self.kin, self.e_bias)) + (
+            frozenset((id(self.lam), id(self.lam_next))),)
         lambda_step(self.coord_off, self.lam, self.lam_next, self.v, dvdl, self.ph, self.params,
                     first=self.n == 0, partner=self.partner, pka=self.pka, mm=self.mm,
                     dwp=self.dwp, noise=self.noise if self.params.tau > 0 else None,
-                    stats_w=self.stats_w, stats_b=self.stats_b, kin=self.kin, e_bias=self.e_bias)
+                    stats_w=self.stats_w, stats_b=self.stats_b, kin=self.kin, e_bias=self.e_bias,
+                    check=seen != self._checked)
+        self._checked = seen
         self.lam, self.lam_next = self.lam_next, self.lam
         self.n += 1
         mode = (1 if self.n % self.well_block == 0 else 0) | (2 if self.n % self.barrier_block == 0 else 0)
