@@ -81,6 +81,13 @@ def _load():
     lib.orc_tautomer_dvdl.argtypes = [ctypes.c_int64, _f64p, _f64p, _f64p, _f64p, _i32p,
                                       ctypes.c_int64, _f64p, _f64p, _f64p, ctypes.c_double,
                                       _f64p, _f64p]
+    lib.orc_direct_wpair.restype = None
+    lib.orc_direct_wpair.argtypes = [ctypes.c_int64, _f64p, _f64p, _f64p, ctypes.c_int64,
+                                     ctypes.c_void_p, _f64p, _f64p]
+    lib.orc_ewald_wpair.restype = ctypes.c_int
+    lib.orc_ewald_wpair.argtypes = [ctypes.c_int64, _f64p, _f64p, _f64p, _f64p, ctypes.c_double,
+                                    ctypes.c_double, _i32p, ctypes.c_int64, ctypes.c_void_p,
+                                    _f64p, _f64p]
     _lib = lib
     return lib
 
@@ -250,6 +257,89 @@ def adjoint_phi(x, qA, qB, site, lam, gE, gphi, box=None, periodic=False, k_e=1.
     gx = -k_e * (gE * q[:, None] * fq + gphi[:, None] * fq + q[:, None] * fg)
     insite = (site >= 0)
     lam_i = np.where(insite, lam[np.maximum(site, 0)], 0.0)
+    gqA = (1.0 - lam_i) * gq
+    gqB = lam_i * gq
+    glam = np.zeros(lam.size)
+    for s in range(lam.size):
+        m = site == s
+        glam[s] = np.sum((qB[m] - qA[m]) * gq[m])
+    return gx, gqA, gqB, glam
+
+
+def _ewald_setup(box, beta, rcut, kmax, eps):
+    box = _f64(np.broadcast_to(np.asarray(box, dtype=np.float64), (3,)))
+    b0, r0, k0 = ewald_params(box, eps, rcut)
+    beta = b0 if beta is None else float(beta)
+    rcut = r0 if rcut is None else float(rcut)
+    if kmax is None:
+        s = beta * rcut
+        kmax = np.array([int(math.ceil(2 * beta * s * L / (2 * math.pi))) for L in box],
+                        dtype=np.int32)
+    kmax = np.ascontiguousarray(np.broadcast_to(np.asarray(kmax), (3,)), dtype=np.int32)
+    return box, beta, rcut, kmax
+
+
+def force_weight_sums(x, q, w, box=None, periodic=False, beta=None, rcut=None, kmax=None,
+                      eps=1e-13, targets=None):
+    """Pair sums of the force-weight adjoint at every target m (w: n x 3
+    weights, one per atom's force):
+        hw_m = sum_j q_j [grad grad psi](r_m - r_j) (w_m - w_j)
+        ew_m = sum_j q_j e(r_m - r_j) . (w_m - w_j),  e = -grad psi,
+    psi = 1/r (open, j != m) or the Ewald potential (periodic, all images).
+    Returns (hw, ew)."""
+    x, q = _f64(x).reshape(-1, 3), _f64(q)
+    w = _f64(w).reshape(-1, 3)
+    t, nt, tp = _targets(targets, q.size)
+    hw = np.empty((nt, 3))
+    ew = np.empty(nt)
+    if periodic:
+        box, beta, rcut, kmax = _ewald_setup(box, beta, rcut, kmax, eps)
+        rc = _load().orc_ewald_wpair(q.size, x, q, w, box, beta, rcut, kmax, nt, tp, hw, ew)
+        if rc != 0:
+            raise ValueError("orc_ewald_wpair: bad arguments or out of memory")
+    else:
+        _load().orc_direct_wpair(q.size, x, q, w, nt, tp, hw, ew)
+    return hw, ew
+
+
+def adjoint_full(x, qA, qB, site, lam, gE=0.0, gphi=None, gF=None, box=None, periodic=False,
+                 k_e=1.0, eps=1e-13):
+    """Gradients of L = gE E + sum_i gphi_i phi_i + sum_i gF_i . F_i (phi and F
+    as solve returns them, with k_e) with respect to x, qA, qB and lambda.
+
+    E = 1/2 k_e q^T Psi q, phi = k_e Psi q and F_m = k_e q_m sum_j q_j e(r_mj)
+    (Psi the symmetric pair matrix of psi, e = -grad psi).  Differentiating
+    each term:
+        dL/dq_m = gE phi_m + k_e (Psi gphi)_m + k_e ew_m
+        dL/dx_m = -gE F_m - k_e (gphi_m field_m(q) + q_m field_m(gphi)) - k_e q_m hw_m
+    with hw, ew the force-weight pair sums (force_weight_sums); then
+    dL/dqA = (1 - lambda_s) dL/dq, dL/dqB = lambda_s dL/dq (site -1: qB gets 0)
+    and dL/dlambda_s = sum_{m in s} (qB_m - qA_m) dL/dq_m.
+    Returns (gx, gqA, gqB, glam)."""
+    x = _f64(x).reshape(-1, 3)
+    qA, qB = _f64(qA), _f64(qB)
+    lam = _f64(np.atleast_1d(lam))
+    site = np.ascontiguousarray(site, dtype=np.int32)
+    n = qA.size
+    q = lambda_charges(qA, qB, site, lam)
+
+    def field_of(c):
+        return ewald(x, c, box, eps=eps) if periodic else direct(x, c)
+
+    pq, fq = field_of(q)
+    gq = k_e * gE * pq
+    gx = -k_e * gE * q[:, None] * fq
+    if gphi is not None:
+        gphi = _f64(gphi)
+        pg, fg = field_of(gphi)
+        gq = gq + k_e * pg
+        gx = gx - k_e * (gphi[:, None] * fq + q[:, None] * fg)
+    if gF is not None:
+        hw, ew = force_weight_sums(x, q, _f64(gF).reshape(n, 3), box, periodic, eps=eps)
+        gq = gq + k_e * ew
+        gx = gx - k_e * q[:, None] * hw
+    insite = site >= 0
+    lam_i = np.where(insite, np.append(lam, 0.0)[np.where(insite, site, lam.size)], 0.0)
     gqA = (1.0 - lam_i) * gq
     gqB = lam_i * gq
     glam = np.zeros(lam.size)

@@ -329,3 +329,168 @@ int orc_tautomer_dvdl(int64_t n, const double* qA, const double* qB, const doubl
     free(d);
     return 0;
 }
+
+/* ---- upstream weights on the forces (second-order adjoint) ----------------
+ * For L_F = sum_m w_m . F_m (w: one 3-vector weight per atom) the gradient
+ * needs, per target atom m, two pair sums over all other atoms j (and, for a
+ * periodic cell, every image of every atom, self images included):
+ *
+ *   hw_m = sum_j q_j [grad grad psi](r_m - r_j) (w_m - w_j)        (3-vector)
+ *   ew_m = sum_j q_j e(r_m - r_j) . (w_m - w_j),   e = -grad psi   (scalar)
+ *
+ * because F_m = k_e q_m sum_j q_j e(r_m - r_j) gives
+ *   dL_F / dx_m = -k_e q_m hw_m   and   dL_F / dq_m = k_e ew_m
+ * (the j = m terms of both sums vanish: w_m - w_m = 0).  psi = 1/r for open
+ * boundaries: grad grad (1/r) = (3 r r^T - r^2 I) / r^5, e = r / r^3.
+ * w is n x 3 row-major; outputs per target t (atom i = targets[t]). */
+void orc_direct_wpair(int64_t n, const double* x, const double* q, const double* w,
+                      int64_t ntarget, const int64_t* targets, double* hw, double* ew) {
+    if (!targets) ntarget = n;
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t t = 0; t < ntarget; ++t) {
+        int64_t i = targets ? targets[t] : t;
+        acc_t h0 = {0, 0}, h1 = {0, 0}, h2 = {0, 0}, e = {0, 0};
+        for (int64_t j = 0; j < n; ++j) {
+            if (j == i) continue;
+            double r[3], dw[3];
+            for (int a = 0; a < 3; ++a) {
+                r[a] = x[3 * i + a] - x[3 * j + a];
+                dw[a] = w[3 * i + a] - w[3 * j + a];
+            }
+            double r2 = r[0] * r[0] + r[1] * r[1] + r[2] * r[2];
+            double rr = sqrt(r2);
+            double r3 = r2 * rr, r5 = r3 * r2;
+            double rdw = r[0] * dw[0] + r[1] * dw[1] + r[2] * dw[2];
+            /* (3 r r^T / r^5 - I / r^3) dw */
+            acc_add(&h0, q[j] * (3.0 * r[0] * rdw / r5 - dw[0] / r3));
+            acc_add(&h1, q[j] * (3.0 * r[1] * rdw / r5 - dw[1] / r3));
+            acc_add(&h2, q[j] * (3.0 * r[2] * rdw / r5 - dw[2] / r3));
+            acc_add(&e, q[j] * rdw / r3);
+        }
+        hw[3 * t] = acc_get(&h0);
+        hw[3 * t + 1] = acc_get(&h1);
+        hw[3 * t + 2] = acc_get(&h2);
+        ew[t] = acc_get(&e);
+    }
+}
+
+/* The same pair sums for the Ewald potential of an orthorhombic box (the
+ * conventions of orc_ewald).  Real space, every image within rcut:
+ *   grad grad [erfc(b r)/r] = C r r^T - B I,  e = B r,
+ *   B = [erfc(b r) + c r exp(-b^2 r^2)] / r^3,
+ *   C = [3 erfc(b r) + c r (3 + 2 b^2 r^2) exp(-b^2 r^2)] / r^5,  c = 2 b / sqrt(pi).
+ * Reciprocal space, psi_rec(r) = sum_k c_k cos(k.r) over the half space k
+ * (c_k = 2 (4 pi / V) exp(-k^2 / 4 b^2) / k^2): grad grad psi_rec =
+ * -sum c_k k k^T cos(k.r) and e_rec = sum c_k k sin(k.r); with
+ * S(k) = sum_j q_j exp(i k.r_j) and P(k) = sum_j q_j w_j exp(i k.r_j),
+ *   sum_j q_j (w_m - w_j) cos(k.r_mj) = w_m Re[S e^{-ik.r_m}] - Re[P e^{-ik.r_m}],
+ *   sum_j q_j (w_m - w_j) sin(k.r_mj) = -(w_m Im[S e^{-ik.r_m}] - Im[P e^{-ik.r_m}]).
+ * The self and background terms of the potential are constants or cancel in
+ * w_m - w_j, so they add nothing.  Returns 0, or -1 on bad arguments. */
+int orc_ewald_wpair(int64_t n, const double* x, const double* q, const double* w,
+                    const double* box, double beta, double rcut, const int32_t* kmax,
+                    int64_t ntarget, const int64_t* targets, double* hw, double* ew) {
+    if (!targets) ntarget = n;
+    if (box[0] <= 0 || box[1] <= 0 || box[2] <= 0 || beta <= 0 || rcut <= 0) return -1;
+    if (kmax[0] < 0 || kmax[1] < 0 || kmax[2] < 0) return -1;
+    const double L[3] = {box[0], box[1], box[2]};
+    const double V = L[0] * L[1] * L[2];
+    const double rc2 = rcut * rcut;
+    const double cb = 2.0 * beta / sqrt(ORC_PI);
+    const int kx = kmax[0], ky = kmax[1], kz = kmax[2];
+    int64_t nk_max = (int64_t)(2 * kx + 1) * (2 * ky + 1) * (2 * kz + 1);
+    double* kv = (double*)malloc(sizeof(double) * 3 * (size_t)nk_max);
+    double* kc = (double*)malloc(sizeof(double) * (size_t)nk_max);
+    /* per k: S re, S im, then P re/im for x, y, z */
+    double* sf = (double*)calloc((size_t)(nk_max ? nk_max : 1) * 8, sizeof(double));
+    if (!kv || !kc || !sf) { free(kv); free(kc); free(sf); return -1; }
+    int64_t nk = 0;
+    for (int mx = 0; mx <= kx; ++mx)
+        for (int my = -ky; my <= ky; ++my)
+            for (int mz = -kz; mz <= kz; ++mz) {
+                if (mx == 0 && (my < 0 || (my == 0 && mz <= 0))) continue;
+                double g0 = 2 * ORC_PI * mx / L[0], g1 = 2 * ORC_PI * my / L[1],
+                       g2 = 2 * ORC_PI * mz / L[2];
+                double k2 = g0 * g0 + g1 * g1 + g2 * g2;
+                kv[3 * nk] = g0; kv[3 * nk + 1] = g1; kv[3 * nk + 2] = g2;
+                kc[nk] = 2.0 * (4.0 * ORC_PI / V) * exp(-k2 / (4 * beta * beta)) / k2;
+                ++nk;
+            }
+#pragma omp parallel for schedule(static)
+    for (int64_t k = 0; k < nk; ++k) {
+        acc_t a[8];
+        for (int c = 0; c < 8; ++c) { a[c].s = 0; a[c].c = 0; }
+        for (int64_t j = 0; j < n; ++j) {
+            double ph = kv[3 * k] * x[3 * j] + kv[3 * k + 1] * x[3 * j + 1] +
+                        kv[3 * k + 2] * x[3 * j + 2];
+            double cr = cos(ph), si = sin(ph);
+            acc_add(&a[0], q[j] * cr);
+            acc_add(&a[1], q[j] * si);
+            for (int d = 0; d < 3; ++d) {
+                acc_add(&a[2 + 2 * d], q[j] * w[3 * j + d] * cr);
+                acc_add(&a[3 + 2 * d], q[j] * w[3 * j + d] * si);
+            }
+        }
+        for (int c = 0; c < 8; ++c) sf[8 * k + c] = acc_get(&a[c]);
+    }
+#pragma omp parallel for schedule(dynamic, 8)
+    for (int64_t t = 0; t < ntarget; ++t) {
+        int64_t i = targets ? targets[t] : t;
+        acc_t h0 = {0, 0}, h1 = {0, 0}, h2 = {0, 0}, e = {0, 0};
+        for (int64_t j = 0; j < n; ++j) {
+            double d0[3], dw[3];
+            int lo[3], hi[3];
+            for (int a = 0; a < 3; ++a) {
+                d0[a] = x[3 * i + a] - x[3 * j + a];
+                dw[a] = w[3 * i + a] - w[3 * j + a];
+                lo[a] = (int)ceil((-rcut - d0[a]) / L[a]);
+                hi[a] = (int)floor((rcut - d0[a]) / L[a]);
+            }
+            for (int a = lo[0]; a <= hi[0]; ++a)
+                for (int b = lo[1]; b <= hi[1]; ++b)
+                    for (int c = lo[2]; c <= hi[2]; ++c) {
+                        if (j == i && a == 0 && b == 0 && c == 0) continue;
+                        double r[3] = {d0[0] + a * L[0], d0[1] + b * L[1], d0[2] + c * L[2]};
+                        double r2 = r[0] * r[0] + r[1] * r[1] + r[2] * r[2];
+                        if (r2 >= rc2) continue;
+                        double rr = sqrt(r2);
+                        double ex = exp(-beta * beta * r2), ec = erfc(beta * rr);
+                        double B = (ec + cb * rr * ex) / (r2 * rr);
+                        double C = (3.0 * ec + cb * rr * (3.0 + 2.0 * beta * beta * r2) * ex) /
+                                   (r2 * r2 * rr);
+                        double rdw = r[0] * dw[0] + r[1] * dw[1] + r[2] * dw[2];
+                        acc_add(&h0, q[j] * (C * r[0] * rdw - B * dw[0]));
+                        acc_add(&h1, q[j] * (C * r[1] * rdw - B * dw[1]));
+                        acc_add(&h2, q[j] * (C * r[2] * rdw - B * dw[2]));
+                        acc_add(&e, q[j] * B * rdw);
+                    }
+        }
+        for (int64_t k = 0; k < nk; ++k) {
+            const double* kk = kv + 3 * k;
+            const double* s = sf + 8 * k;
+            double ph = kk[0] * x[3 * i] + kk[1] * x[3 * i + 1] + kk[2] * x[3 * i + 2];
+            double er = cos(ph), ei = -sin(ph); /* e^{-ik.r_i} */
+            double sre = s[0] * er - s[1] * ei, sim = s[0] * ei + s[1] * er;
+            double cosv[3], sinv[3];  /* sum_j q_j (w_i - w_j) cos / sin (k.r_ij) */
+            for (int d = 0; d < 3; ++d) {
+                double pre = s[2 + 2 * d] * er - s[3 + 2 * d] * ei;
+                double pim = s[2 + 2 * d] * ei + s[3 + 2 * d] * er;
+                cosv[d] = w[3 * i + d] * sre - pre;
+                sinv[d] = -(w[3 * i + d] * sim - pim);
+            }
+            double kc_ = kc[k];
+            double kcos = kk[0] * cosv[0] + kk[1] * cosv[1] + kk[2] * cosv[2];
+            double ksin = kk[0] * sinv[0] + kk[1] * sinv[1] + kk[2] * sinv[2];
+            acc_add(&h0, -kc_ * kk[0] * kcos);
+            acc_add(&h1, -kc_ * kk[1] * kcos);
+            acc_add(&h2, -kc_ * kk[2] * kcos);
+            acc_add(&e, kc_ * ksin);
+        }
+        hw[3 * t] = acc_get(&h0);
+        hw[3 * t + 1] = acc_get(&h1);
+        hw[3 * t + 2] = acc_get(&h2);
+        ew[t] = acc_get(&e);
+    }
+    free(kv); free(kc); free(sf);
+    return 0;
+}
