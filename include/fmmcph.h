@@ -169,18 +169,37 @@ fmm_status fmm_eval_adjoint(fmm_plan_t plan, int64_t n, const void* x, const voi
                             double* grad_lambda, double* E, void* F, void* phi,
                             double* dVdl);
 
-/* Adjoint of L = gE E + sum_i gphi_i phi_i: upstream weights on the energy
- * (gE, a HOST double here) and on the potential output (gphi, n values of the
- * plan's type, device).  phi = k_e Psi q is linear in the charges with a
- * symmetric pair matrix Psi, so with phi3 the potential of the charges gphi:
- *   dL/dq_i     = gE phi_i + phi3_i  -> grad_qA, grad_qB as in fmm_eval_adjoint
- *   grad_lambda = gE dVdl + sum_{i in s} (qB_i - qA_i) phi3_i
- *   grad_x      = -gE F - F(q + gphi) + F(q) + F(gphi)
- * (the last line from k_e gphi^T Psi q = E(q + gphi) - E(q) - E(gphi)).  Three
- * solves on the plan's stream (charges q, q + gphi and gphi) and one combine
- * kernel; exclusions set on the plan apply to all three.  Pointers as in
- * fmm_eval_adjoint; FMM_E_UNSUPPORTED on a Hamiltonian plan.  Upstream
- * weights on F would need dipole sources and are not provided. */
+/* Adjoint with upstream weights on the energy, the potentials and the forces
+ * (reverse mode of the whole solve; "Coulomb interactions and their
+ * derivatives" are what the paper's lambda-dynamics consumes, Methods):
+ *   L = gE E + sum_i gphi_i phi_i + sum_i gF_i . F_i.
+ * With phi = k_e Psi q (Psi the symmetric pair matrix of psi), F_i = k_e q_i
+ * E_i(q) (E_i(c) the field of charges c at atom i), the dipoles p_j = q_j gF_j
+ * and w = gF:
+ *   dL/dq_i   = gE phi_i + k_e [phi_i(gphi) - phi_i(p) + w_i . E_i(q)]
+ *   dL/dx_i   = -gE F_i - k_e gphi_i E_i(q)
+ *               - k_e q_i [E_i(gphi) - E_i(p) - (grad E(q))_i w_i]
+ *   grad_qA_i = (1 - lambda_s(i)) dL/dq_i   (dL/dq_i if s(i) = -1)
+ *   grad_qB_i = lambda_s(i) dL/dq_i         (0 if s(i) = -1)
+ *   grad_lambda_s = sum_{i in s} (qB_i - qA_i) dL/dq_i          [double]
+ * (phi(p), E(p): potential and field of the dipoles).  One tree pass: the
+ * charges and the second sources (charges gphi, dipoles -p) share the octree
+ * and every translation; nothing is kept from a previous call.
+ *   gE       DEVICE pointer to 1 double (NULL = 0)
+ *   gphi     n weights on phi, or NULL                 [float | double, device]
+ *   gF       n x 3 weights on F, or NULL               [float | double, device]
+ * Any gradient pointer, and each of E, F, phi, dVdl (the forward outputs, as
+ * in fmm_eval), may be NULL.  One system per call; bonded exclusions set on
+ * the plan apply.  FMM_E_UNSUPPORTED on a Hamiltonian plan. */
+fmm_status fmm_eval_adjoint_full(fmm_plan_t plan, int64_t n, const void* x, const void* qA,
+                                 const void* qB, const int32_t* site, int64_t n_sites,
+                                 const double* lambda, const double* box, const double* gE,
+                                 const void* gphi, const void* gF, void* grad_x, void* grad_qA,
+                                 void* grad_qB, double* grad_lambda, double* E, void* F, void* phi,
+                                 double* dVdl);
+
+/* fmm_eval_adjoint_full with gF = NULL and the energy weight gE given as a
+ * HOST double; gphi must be non-NULL. */
 fmm_status fmm_eval_adjoint_phi(fmm_plan_t plan, int64_t n, const void* x, const void* qA,
                                 const void* qB, const int32_t* site, int64_t n_sites,
                                 const double* lambda, const double* box, double gE,

@@ -303,7 +303,7 @@ def force_weight_sums(x, q, w, box=None, periodic=False, beta=None, rcut=None, k
 
 
 def adjoint_full(x, qA, qB, site, lam, gE=0.0, gphi=None, gF=None, box=None, periodic=False,
-                 k_e=1.0, eps=1e-13):
+                 k_e=1.0, eps=1e-13, targets=None):
     """Gradients of L = gE E + sum_i gphi_i phi_i + sum_i gF_i . F_i (phi and F
     as solve returns them, with k_e) with respect to x, qA, qB and lambda.
 
@@ -315,6 +315,9 @@ def adjoint_full(x, qA, qB, site, lam, gE=0.0, gphi=None, gF=None, box=None, per
     with hw, ew the force-weight pair sums (force_weight_sums); then
     dL/dqA = (1 - lambda_s) dL/dq, dL/dqB = lambda_s dL/dq (site -1: qB gets 0)
     and dL/dlambda_s = sum_{m in s} (qB_m - qA_m) dL/dq_m.
+    With targets (atom indices), the per-atom gradients are returned for those
+    atoms only (the sums still run over every atom), and glam only when every
+    site atom is among them (else None).
     Returns (gx, gqA, gqB, glam)."""
     x = _f64(x).reshape(-1, 3)
     qA, qB = _f64(qA), _f64(qB)
@@ -322,30 +325,36 @@ def adjoint_full(x, qA, qB, site, lam, gE=0.0, gphi=None, gF=None, box=None, per
     site = np.ascontiguousarray(site, dtype=np.int32)
     n = qA.size
     q = lambda_charges(qA, qB, site, lam)
+    t = np.arange(n) if targets is None else np.asarray(targets, dtype=np.int64)
 
     def field_of(c):
-        return ewald(x, c, box, eps=eps) if periodic else direct(x, c)
+        return (ewald(x, c, box, eps=eps, targets=t) if periodic else direct(x, c, targets=t))
 
     pq, fq = field_of(q)
+    qt = q[t]
     gq = k_e * gE * pq
-    gx = -k_e * gE * q[:, None] * fq
+    gx = -k_e * gE * qt[:, None] * fq
     if gphi is not None:
         gphi = _f64(gphi)
         pg, fg = field_of(gphi)
         gq = gq + k_e * pg
-        gx = gx - k_e * (gphi[:, None] * fq + q[:, None] * fg)
+        gx = gx - k_e * (gphi[t][:, None] * fq + qt[:, None] * fg)
     if gF is not None:
-        hw, ew = force_weight_sums(x, q, _f64(gF).reshape(n, 3), box, periodic, eps=eps)
+        hw, ew = force_weight_sums(x, q, _f64(gF).reshape(n, 3), box, periodic, eps=eps,
+                                   targets=t)
         gq = gq + k_e * ew
-        gx = gx - k_e * q[:, None] * hw
-    insite = site >= 0
-    lam_i = np.where(insite, np.append(lam, 0.0)[np.where(insite, site, lam.size)], 0.0)
+        gx = gx - k_e * qt[:, None] * hw
+    st = site[t]
+    insite = st >= 0
+    lam_i = np.where(insite, np.append(lam, 0.0)[np.where(insite, st, lam.size)], 0.0)
     gqA = (1.0 - lam_i) * gq
     gqB = lam_i * gq
+    if np.count_nonzero(insite) != np.count_nonzero(site >= 0):
+        return gx, gqA, gqB, None
     glam = np.zeros(lam.size)
     for s in range(lam.size):
-        m = site == s
-        glam[s] = np.sum((qB[m] - qA[m]) * gq[m])
+        m = st == s
+        glam[s] = np.sum((qB[t][m] - qA[t][m]) * gq[m])
     return gx, gqA, gqB, glam
 
 

@@ -1,15 +1,15 @@
-"""torch.autograd wrapper of the solver: forward = fmm_eval, backward =
-fmm_eval_adjoint, which rebuilds the octree and every expansion from the
-saved inputs instead of storing them.
+"""torch.autograd wrapper of the solver: forward = fmm_eval, backward = one of
+the library's adjoint calls, which rebuild the octree and every expansion
+from the saved inputs instead of storing them.
 
-The energy E and the potential phi are differentiable.  F and dV/dlambda are
-returned as non-differentiable outputs: an upstream gradient on F would need
-a Hessian-vector pass with dipole sources that this library does not provide.
-For an upstream weight w on E alone the hand-written adjoint returns
+E, F and phi are differentiable; dV/dlambda is returned as a
+non-differentiable output.  For an upstream weight w on E alone,
+fmm_eval_adjoint returns
     dE/dx = -w F,  dE/dqA = w (1 - lambda_s) phi,  dE/dqB = w lambda_s phi,
     dE/dlambda = w dV/dlambda
-(sites -1: dE/dqA = w phi, dE/dqB = 0); with weights g on phi as well,
-fmm_eval_adjoint_phi (three solves) returns the gradient of w E + g . phi.
+(sites -1: dE/dqA = w phi, dE/dqB = 0); with weights on phi or F as well,
+fmm_eval_adjoint_full returns the gradient of w E + gphi . phi + gF . F in one
+tree pass (charges and, as second sources, charges gphi with dipoles -q gF).
 """
 from __future__ import annotations
 
@@ -23,24 +23,25 @@ class FmmCoulomb(torch.autograd.Function):
         ctx.save_for_backward(x, qA, qB, lam, site)
         ctx.plan = plan
         ctx.box = box
-        ctx.mark_non_differentiable(out["F"], out["dVdl"])
+        ctx.mark_non_differentiable(out["dVdl"])
         return out["E"], out["F"], out["phi"], out["dVdl"]
 
     @staticmethod
     def backward(ctx, gE, gF, gphi, gdVdl):
-        for g, name in ((gF, "F"), (gdVdl, "dVdl")):
-            if g is not None and bool(torch.any(g != 0)):
-                raise NotImplementedError(
-                    "only the energy and the potential are differentiable; got a gradient on %s"
-                    % name)
+        if gdVdl is not None and bool(torch.any(gdVdl != 0)):
+            raise NotImplementedError("dV/dlambda is not differentiable; got a gradient on it")
         x, qA, qB, lam, site = ctx.saved_tensors
-        if gphi is not None and bool(torch.any(gphi != 0)):
-            w = 0.0 if gE is None else float(gE.reshape(-1)[0].item())
-            adj = ctx.plan.eval_adjoint_phi(x, qA, qB, site, lam, w,
-                                            gphi.to(x.dtype).contiguous(), box=ctx.box)
+        w = (gE if gE is not None else torch.zeros(1, device=x.device)).to(torch.float64)
+        w = w.reshape(1).contiguous()
+        use_phi = gphi is not None and bool(torch.any(gphi != 0))
+        use_F = gF is not None and bool(torch.any(gF != 0))
+        if use_phi or use_F:
+            adj = ctx.plan.eval_adjoint_full(
+                x, qA, qB, site, lam, gE=w,
+                gphi=gphi.to(x.dtype).contiguous() if use_phi else None,
+                gF=gF.to(x.dtype).contiguous() if use_F else None, box=ctx.box)
         else:
-            w = (gE if gE is not None else torch.zeros(1, device=x.device)).to(torch.float64)
-            adj = ctx.plan.eval_adjoint(x, qA, qB, site, lam, w.reshape(1).contiguous(), box=ctx.box)
+            adj = ctx.plan.eval_adjoint(x, qA, qB, site, lam, w, box=ctx.box)
         return (adj["grad_x"] if ctx.needs_input_grad[0] else None,
                 adj["grad_qA"] if ctx.needs_input_grad[1] else None,
                 adj["grad_qB"] if ctx.needs_input_grad[2] else None,
@@ -49,6 +50,7 @@ class FmmCoulomb(torch.autograd.Function):
 
 
 def fmm_coulomb(plan, x, qA, qB, site, lam, box=None):
-    """Differentiable energy and potential (and non-differentiable F, dV/dlambda)."""
+    """Differentiable energy, forces and potential (and non-differentiable
+    dV/dlambda)."""
     E, F, phi, dVdl = FmmCoulomb.apply(x, qA, qB, lam, plan, site, box)
     return E, F, phi, dVdl

@@ -1,6 +1,5 @@
 // Bonded exclusions: the pair terms of listed partners removed from the
-// solve's potential, forces, site derivatives and energy; and the combine
-// kernels of the potential-weight adjoint.  A pair (i, j) is
+// solve's potential, forces, site derivatives and energy.  A pair (i, j) is
 // excluded through its minimum image (for a periodic cell the other images
 // of the pair stay), the usual convention for bonded neighbours.  Included
 // by fmm_api.hip after fmm_kernels.hip.
@@ -86,48 +85,6 @@ __global__ __launch_bounds__(256) void k_excl(Geo g, const RepDesc* __restrict__
         __syncthreads();
     }
     if (t == 0) excl_e[(size_t)r * gridDim.x + blockIdx.x] = red[0];
-}
-
-// qA2 = qA + g, qB2 = qB + g (the charges q + g for the polarization
-// identity of the potential-weight adjoint).
-template <typename T>
-__global__ __launch_bounds__(256) void k_add_weights(int64_t n, const T* __restrict__ qA,
-                                                     const T* __restrict__ qB, const T* __restrict__ g,
-                                                     T* __restrict__ qA2, T* __restrict__ qB2) {
-    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (i >= n) return;
-    qA2[i] = (T)((double)qA[i] + (double)g[i]);
-    qB2[i] = (T)((double)qB[i] + (double)g[i]);
-}
-
-// Gradients of L = gE E + sum_i g_i phi_i from three solves: with the
-// charges q (F, phi, dVdl), q + g (F2, dVdl2) and g (F3, phi3).  phi is
-// linear in the charges with a symmetric pair matrix, so dL/dq = gE phi +
-// phi3, and k_e g^T Psi q = E(q + g) - E(q) - E(g) gives
-// dL/dx = -gE F - F2 + F + F3; the site derivative of the potential term is
-// dVdl2 - dVdl.
-template <typename T>
-__global__ __launch_bounds__(256) void k_adjoint_phi(int64_t n, int64_t S, const int32_t* __restrict__ site,
-                                                     const double* __restrict__ lam, double gE,
-                                                     const T* __restrict__ F, const T* __restrict__ phi,
-                                                     const double* __restrict__ dVdl, const T* __restrict__ F2,
-                                                     const double* __restrict__ dVdl2, const T* __restrict__ F3,
-                                                     const T* __restrict__ phi3, T* __restrict__ gx,
-                                                     T* __restrict__ gqA, T* __restrict__ gqB,
-                                                     double* __restrict__ glam) {
-    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (glam && i < S) glam[i] = gE * dVdl[i] + (dVdl2[i] - dVdl[i]);
-    if (i >= n) return;
-    if (gx)
-        for (int a = 0; a < 3; ++a) {
-            const int64_t k = 3 * i + a;
-            gx[k] = (T)(-gE * (double)F[k] - (double)F2[k] + (double)F[k] + (double)F3[k]);
-        }
-    const int32_t s = site[i];
-    const double l = (s >= 0 && s < S) ? lam[s] : 0.0;
-    const double gq = gE * (double)phi[i] + (double)phi3[i];
-    if (gqA) gqA[i] = (T)((1.0 - l) * gq);
-    if (gqB) gqB[i] = (T)(l * gq);
 }
 
 }  // namespace fmmk

@@ -12,6 +12,7 @@
 
 #include "fmm_kernels.hip"
 #include "exclusions.hip"
+#include "adjoint.hip"
 #include "fmmcph.h"
 #include "operators.h"
 
@@ -55,11 +56,11 @@ struct fmm_plan_s {
     int64_t excl_n = 0;
     int32_t *excl_start = nullptr, *excl_idx = nullptr;
     double* excl_e = nullptr;
-    // potential-weight adjoint: charges q + g, and the outputs of the solves
-    // with q + g and with g (F2, phi2, F3, phi3), their site sums and energies
-    void *adj_qA = nullptr, *adj_qB = nullptr, *adj_F2 = nullptr, *adj_phi2 = nullptr,
-         *adj_F3 = nullptr, *adj_phi3 = nullptr;
-    double *adj_dl2 = nullptr, *adj_dl3 = nullptr, *adj_E = nullptr;
+    // adjoint with weights on E, phi and F: the second sources (w, g) in leaf
+    // order, the per-atom (phi, E, A, B) of the leaf pass, the site terms of
+    // dL/dq and the energy partials of the combine kernel
+    void *adj_src2 = nullptr, *adj_acc = nullptr;
+    double *adj_cphi2 = nullptr, *adj_part = nullptr;
     double* dVdl_tmp = nullptr;
     double* E_tmp = nullptr;
     fmmk::RepDesc* reps = nullptr;  // device replica descriptors (max_replicas)
@@ -262,6 +263,12 @@ size_t leaf_lds_bytes(int K) {
     return std::max<size_t>((size_t)fmmk::kSortCap * 4, (size_t)64 * (K + 1) * sizeof(T));
 }
 
+// Dynamic LDS of the second-source leaf kernel of the adjoint: the P2M rows.
+template <typename T>
+size_t src2_lds_bytes(int K) {
+    return (size_t)64 * (K + 1) * sizeof(T);
+}
+
 inline unsigned nblocks(int64_t n, int b) { return (unsigned)std::max<int64_t>(1, (n + b - 1) / b); }
 
 // Matrix-core M2L launch: the kernel instance for the plan's precision and row
@@ -318,43 +325,32 @@ bool launch_m2l_mma(fmm_plan_t P, const Geo& g, int R, bool want_root) {
     return false;
 }
 
-// Enqueue one evaluation of R replicas (arguments already validated; rd holds
-// the host copy of the replica descriptors).  Every phase is one launch over
-// all replicas (grid y = replica).
+// Binning and leaf multipoles of R replicas (grid y = replica): replica
+// descriptors, the open bounding cube, leaf keys, the counting sort and the
+// leaf kernel (sort in leaf, gather with the interpolated charges, P2M).
+// nstore replica descriptors are stored (nstore >= R: extra slots describe
+// the same systems for kernels run on more expansion slots later).
 template <typename T>
-fmm_status enqueue_eval(fmm_plan_t P, const std::vector<fmmk::RepDesc>& rd, const T* x,
-                        const T* qA, const T* qB, const int32_t* site, const double* lam,
-                        double* E, T* F, T* phi, double* dVdl,
-                        const fmmk::FormArgs<T> fa = {nullptr, nullptr, nullptr},
-                        double* dVdl_t = nullptr) {
+void enqueue_bin_p2m(fmm_plan_t P, const fmmk::Geo& g, const std::vector<fmmk::RepDesc>& rd, int R,
+                     const T* x, const T* qA, const T* qB, const int32_t* site, const double* lam,
+                     const fmmk::FormArgs<T>& fa, int64_t maxn, int64_t S_tot) {
     using namespace fmmk;
     hipStream_t st = P->stream;
-    const Geo g = make_geo(P);
-    const int R = (int)rd.size();
-    int64_t maxn = 0, S_tot = 0;
-    int64_t n_tot = 0;
-    for (const RepDesc& d : rd) {
-        maxn = std::max(maxn, d.n);
-        S_tot += d.S;
-        n_tot += d.n;
-    }
-    if (P->excl_n > 0 && n_tot != P->excl_n)
-        return fail(P, FMM_E_INVALID, "the exclusion lists were set for a different atom count");
-    mark(P, 0);
+    const int nstore = (int)rd.size();
     // replica descriptors: by value to the first kernel (which stores them)
     // when they fit one set, else stored by k_set_reps launches first.  The
     // leaf and site counters are already zero (plan creation, then the final
     // reduction of every evaluation).
     RepSet set0{};
-    if (R <= kRepsPerSet) {
+    if (nstore <= kRepsPerSet) {
         set0.first = 0;
-        set0.count = R;
-        for (int i = 0; i < R; ++i) set0.d[i] = rd[i];
+        set0.count = nstore;
+        for (int i = 0; i < nstore; ++i) set0.d[i] = rd[i];
     } else {
-        for (int f = 0; f < R; f += kRepsPerSet) {
+        for (int f = 0; f < nstore; f += kRepsPerSet) {
             RepSet set{};
             set.first = f;
-            set.count = std::min(kRepsPerSet, R - f);
+            set.count = std::min(kRepsPerSet, nstore - f);
             for (int i = 0; i < set.count; ++i) set.d[i] = rd[f + i];
             k_set_reps<<<1, kRepsPerSet, 0, st>>>(set, P->reps);
         }
@@ -382,14 +378,22 @@ fmm_status enqueue_eval(fmm_plan_t P, const std::vector<fmmk::RepDesc>& rd, cons
                                                site, P->site_rank, P->site_start, P->site_members);
     }
     using V4 = vec4_t<T>;
-    V4* pos = (V4*)P->pos;
+    mark(P, 1);
+    k_leaf_p2m<T><<<dim3(g.nleaf, R), kLeafThreads, leaf_lds_bytes<T>(g.K), st>>>(
+        g, reps, x, qA, qB, site, lam, fa, P->dom, P->leaf_start, P->perm, (V4*)P->pos, P->status,
+        (T*)P->mult, P->leaf_part, (uint16_t*)P->msplit, P->mg.KP);
+}
+
+// The tree passes of R expansion slots (grid y = slot): M2M per level, the
+// periodic root with its lattice operator, M2L at every level and the
+// downward pass into the leaves.  With want_order the downward launch's extra
+// block orders the leaves for the near field; returns that order (or null).
+template <typename T>
+int32_t* enqueue_tree(fmm_plan_t P, const fmmk::Geo& g, int R, bool want_order) {
+    using namespace fmmk;
+    hipStream_t st = P->stream;
     T* mult = (T*)P->mult;
     T* loc = (T*)P->loc;
-    const dim3 lg(g.nleaf, R);
-    mark(P, 1);
-    k_leaf_p2m<T><<<lg, kLeafThreads, leaf_lds_bytes<T>(g.K), st>>>(
-        g, reps, x, qA, qB, site, lam, fa, P->dom, P->leaf_start, P->perm, pos, P->status, mult,
-        P->leaf_part, (uint16_t*)P->msplit, P->mg.KP);
     // upward pass: one launch per level down to the coarsest interacting
     // level (1 periodic, 2 open); the periodic root and its lattice operator
     // are formed by the M2L reduction launch (or else at the start of the
@@ -424,13 +428,46 @@ fmm_status enqueue_eval(fmm_plan_t P, const std::vector<fmmk::RepDesc>& rd, cons
     // leaves for the near field by decreasing work
     int32_t* order = nullptr;
     if (g.depth >= 1 && g.depth - 1 >= l0) {
-        if (g.nleaf <= kOrderCap) order = P->leaf_order;
+        if (want_order && g.nleaf <= kOrderCap) order = P->leaf_order;
         const unsigned nbx = (1u << (3 * (g.depth - 1))) + (order ? 1u : 0u);
         k_downward<T><<<dim3(nbx, R), kTreeThreads, 0, st>>>(
             g, l0, loc, (const T*)P->l2lT, (const T*)P->l2l_seg, mult, (const T*)P->m2mT,
             (const T*)P->m2m_seg, P->leaf_part, P->box_part, P->latT, P->lat_seg, P->root_m, P->root_l,
             P->dom, P->leaf_start, order, root_ready ? 1 : 0);
     }
+    return order;
+}
+
+// Enqueue one evaluation of R replicas (arguments already validated; rd holds
+// the host copy of the replica descriptors).  Every phase is one launch over
+// all replicas (grid y = replica).
+template <typename T>
+fmm_status enqueue_eval(fmm_plan_t P, const std::vector<fmmk::RepDesc>& rd, const T* x,
+                        const T* qA, const T* qB, const int32_t* site, const double* lam,
+                        double* E, T* F, T* phi, double* dVdl,
+                        const fmmk::FormArgs<T> fa = {nullptr, nullptr, nullptr},
+                        double* dVdl_t = nullptr) {
+    using namespace fmmk;
+    hipStream_t st = P->stream;
+    const Geo g = make_geo(P);
+    const int R = (int)rd.size();
+    int64_t maxn = 0, S_tot = 0;
+    int64_t n_tot = 0;
+    for (const RepDesc& d : rd) {
+        maxn = std::max(maxn, d.n);
+        S_tot += d.S;
+        n_tot += d.n;
+    }
+    if (P->excl_n > 0 && n_tot != P->excl_n)
+        return fail(P, FMM_E_INVALID, "the exclusion lists were set for a different atom count");
+    mark(P, 0);
+    enqueue_bin_p2m<T>(P, g, rd, R, x, qA, qB, site, lam, fa, maxn, S_tot);
+    int32_t* order = enqueue_tree<T>(P, g, R, true);
+    const RepDesc* reps = P->reps;
+    const unsigned ab = nblocks(maxn, 256);
+    using V4 = vec4_t<T>;
+    const V4* pos = (const V4*)P->pos;
+    const T* loc = (const T*)P->loc;
     mark(P, 6);
     switch (P->p2p_waves) {
 #define FMM_NEAR(NWV)                                                                            \
@@ -461,7 +498,8 @@ fmm_status enqueue_eval(fmm_plan_t P, const std::vector<fmmk::RepDesc>& rd, cons
                                                        ham && S_tot > 0 ? P->hc_e : nullptr,
                                                        ham && S_tot > 0 ? P->hc_dl : nullptr,
                                                        P->leaf_count, P->site_count,
-                                                       P->excl_n > 0 ? P->excl_e : nullptr, (int)ab);
+                                                       P->excl_n > 0 ? P->excl_e : nullptr, (int)ab,
+                                                       nullptr, nullptr);
     mark(P, -1);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return fail(P, FMM_E_HIP, std::string("kernel launch: ") + hipGetErrorString(e));
@@ -485,32 +523,51 @@ fmm_status enqueue_adjoint(fmm_plan_t P, const std::vector<fmmk::RepDesc>& rd, c
     return hipGetLastError() == hipSuccess ? FMM_OK : fail(P, FMM_E_HIP, "adjoint launch failed");
 }
 
-// Gradients of gE E + gphi . phi: three solves (q, q + gphi, gphi) on the
-// plan's stream, then the combine kernel.
+// Gradients of gE E + gphi . phi + gF . F for one system in one tree pass:
+// the charges q in expansion slot 0 and the second sources (charges gphi,
+// dipoles -q gF) in slot 1, then the leaf pass of both, the combine kernel
+// (exclusions, outputs) and the fixed-order reductions (E, dV/dlambda and the
+// lambda gradient).  gE is read from device memory when gE_dev is set.
 template <typename T>
-fmm_status enqueue_adjoint_phi(fmm_plan_t P, const std::vector<fmmk::RepDesc>& rd, const T* x,
-                               const T* qA, const T* qB, const int32_t* site, const double* lam,
-                               double gE, const T* gphi, T* gx, T* gqA, T* gqB, double* glam,
-                               double* E, T* F, T* phi, double* dVdl) {
-    const int64_t n = rd[0].n, S = rd[0].S;
-    T* Fw = F ? F : (T*)P->F_tmp;
-    T* pw = phi ? phi : (T*)P->phi_tmp;
-    double* dw = dVdl ? dVdl : P->dVdl_tmp;
-    fmm_status s = enqueue_eval<T>(P, rd, x, qA, qB, site, lam, E ? E : P->E_tmp, Fw, pw, dw);
-    if (s != FMM_OK) return s;
-    const unsigned nb = nblocks(std::max(n, S), 256);
-    fmmk::k_add_weights<T><<<nblocks(n, 256), 256, 0, P->stream>>>(n, qA, qB, gphi, (T*)P->adj_qA,
-                                                                   (T*)P->adj_qB);
-    s = enqueue_eval<T>(P, rd, x, (const T*)P->adj_qA, (const T*)P->adj_qB, site, lam, P->adj_E,
-                        (T*)P->adj_F2, (T*)P->adj_phi2, P->adj_dl2);
-    if (s != FMM_OK) return s;
-    s = enqueue_eval<T>(P, rd, x, gphi, gphi, site, lam, P->adj_E, (T*)P->adj_F3, (T*)P->adj_phi3,
-                        P->adj_dl3);
-    if (s != FMM_OK) return s;
-    fmmk::k_adjoint_phi<T><<<nb, 256, 0, P->stream>>>(n, S, site, lam, gE, Fw, pw, dw, (const T*)P->adj_F2,
-                                                      P->adj_dl2, (const T*)P->adj_F3,
-                                                      (const T*)P->adj_phi3, gx, gqA, gqB, glam);
-    return hipGetLastError() == hipSuccess ? FMM_OK : fail(P, FMM_E_HIP, "adjoint launch failed");
+fmm_status enqueue_adjoint_full(fmm_plan_t P, const fmmk::RepDesc& r0, const T* x, const T* qA,
+                                const T* qB, const int32_t* site, const double* lam,
+                                const double* gE_dev, double gE, const T* gphi, const T* gF, T* gx,
+                                T* gqA, T* gqB, double* glam, double* E, T* F, T* phi,
+                                double* dVdl) {
+    using namespace fmmk;
+    hipStream_t st = P->stream;
+    const Geo g = make_geo(P);
+    const int64_t n = r0.n, S = r0.S;
+    if (P->excl_n > 0 && n != P->excl_n)
+        return fail(P, FMM_E_INVALID, "the exclusion lists were set for a different atom count");
+    const std::vector<RepDesc> rd{r0, r0};  // slot 1: the second sources of the same system
+    const FormArgs<T> fa{nullptr, nullptr, nullptr};
+    mark(P, 0);
+    enqueue_bin_p2m<T>(P, g, rd, 1, x, qA, qB, site, lam, fa, n, S);
+    using V4 = vec4_t<T>;
+    k_leaf_src2<T><<<g.nleaf, kLeafThreads, src2_lds_bytes<T>(g.K), st>>>(
+        g, (const V4*)P->pos, P->perm, P->leaf_start, gphi, gF, P->dom, (V4*)P->adj_src2, (T*)P->mult,
+        P->leaf_part, (uint16_t*)P->msplit, P->mg.KP);
+    enqueue_tree<T>(P, g, 2, false);
+    mark(P, 6);
+    k_near_adj<T><<<g.nleaf, kAdjThreads, 0, st>>>(g, (const V4*)P->pos, (const V4*)P->adj_src2,
+                                                   P->leaf_start, P->perm, P->dom, (const T*)P->loc,
+                                                   P->gidx, (const T*)P->gcoef, (T*)P->adj_acc);
+    const unsigned nb = nblocks(n, 256);
+    k_adj_combine<T><<<nb, 256, 0, st>>>(g, n, S, x, qA, qB, site, lam, gphi, gF, gE_dev, gE, P->dom,
+                                         P->excl_n > 0 ? P->excl_start : nullptr, P->excl_idx,
+                                         (const T*)P->adj_acc, phi, F, gx, gqA, gqB, P->cphi,
+                                         P->adj_cphi2, P->adj_part);
+    mark(P, 7);
+    k_reduce<T><<<(unsigned)(1 + S), 256, 0, st>>>(g, 1, (int64_t)nb, P->adj_part, P->site_start,
+                                                    P->site_members, P->cphi, E ? E : P->E_tmp, dVdl,
+                                                    P->status, qA, qB, lam, fa, nullptr, P->reps, nullptr,
+                                                    nullptr, P->leaf_count, P->site_count, nullptr, 0,
+                                                    P->adj_cphi2, glam);
+    mark(P, -1);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return fail(P, FMM_E_HIP, std::string("kernel launch: ") + hipGetErrorString(e));
+    return FMM_OK;
 }
 
 // Run `enqueue` eagerly, or (params.graph) replay the cached graph when the
@@ -637,7 +694,10 @@ fmm_status fmm_plan_create(const fmm_params* prm, void* hip_stream, fmm_plan_t* 
     init_rho_coef();
     const int64_t N = std::max<int64_t>(prm->max_atoms, 1), S = std::max<int64_t>(prm->max_sites, 1);
     const size_t ts = P->tsz, K = P->K;
-    const size_t RM = (size_t)prm->max_replicas;
+    // replica slots of the tree workspace: at least two (the adjoint runs its
+    // second sources through slot 1); the M2L tiling still follows max_replicas
+    const size_t RM = (size_t)std::max(prm->max_replicas, 2);
+    const size_t RT = (size_t)prm->max_replicas;
     P->R_max = prm->max_replicas;
     bool ok = true;
     ok &= dev_alloc(P, &P->pos, N * 4 * ts);
@@ -683,11 +743,10 @@ fmm_status fmm_plan_create(const fmm_params* prm, void* hip_stream, fmm_plan_t* 
     ok &= dev_alloc(P, &P->phi_tmp, N * ts);
     ok &= dev_alloc(P, (void**)&P->dVdl_tmp, S * 8);
     ok &= dev_alloc(P, (void**)&P->E_tmp, RM * 8);
-    for (void** a : {&P->adj_qA, &P->adj_qB, &P->adj_phi2, &P->adj_phi3}) ok &= dev_alloc(P, a, N * ts);
-    for (void** a : {&P->adj_F2, &P->adj_F3}) ok &= dev_alloc(P, a, N * 3 * ts);
-    ok &= dev_alloc(P, (void**)&P->adj_dl2, S * 8);
-    ok &= dev_alloc(P, (void**)&P->adj_dl3, S * 8);
-    ok &= dev_alloc(P, (void**)&P->adj_E, RM * 8);
+    ok &= dev_alloc(P, &P->adj_src2, N * 4 * ts);
+    ok &= dev_alloc(P, &P->adj_acc, N * 8 * ts);
+    ok &= dev_alloc(P, (void**)&P->adj_cphi2, N * 8);
+    ok &= dev_alloc(P, (void**)&P->adj_part, ((N + 255) / 256) * 8);
     if (!ok) {
         fmm_plan_destroy(P);
         return FMM_E_OOM;
@@ -765,7 +824,7 @@ fmm_status fmm_plan_create(const fmm_params* prm, void* hip_stream, fmm_plan_t* 
         mg.ncol = (int)ncol;
         mg.nt_all = nt_all;
         const int ntile = (int)((ncol + fmmk::kM2LTile - 1) / fmmk::kM2LTile);
-        const int64_t items = 8 * (int64_t)ntile * (int64_t)RM;
+        const int64_t items = 8 * (int64_t)ntile * (int64_t)RT;
         int csize = prm->m2l_chunk;
         if (csize == 0) {
             // bf16x3 runs one double-buffered work-group per CU: about one task per CU;
@@ -933,6 +992,14 @@ fmm_status fmm_plan_create(const fmm_params* prm, void* hip_stream, fmm_plan_t* 
                                           hipFuncAttributeMaxDynamicSharedMemorySize,
                                           (int)leaf_lds_bytes<float>((int)K));
     }
+    if (e == hipSuccess) {
+        e = P->fp64 ? hipFuncSetAttribute((const void*)&fmmk::k_leaf_src2<double>,
+                                          hipFuncAttributeMaxDynamicSharedMemorySize,
+                                          (int)src2_lds_bytes<double>((int)K))
+                    : hipFuncSetAttribute((const void*)&fmmk::k_leaf_src2<float>,
+                                          hipFuncAttributeMaxDynamicSharedMemorySize,
+                                          (int)src2_lds_bytes<float>((int)K));
+    }
     std::vector<double> dom0(8 * RM, 0.0);
     up(P->dom, dom0.data(), dom0.size() * 8);
     // counters start at zero; every evaluation's final reduction re-zeroes
@@ -1083,35 +1150,55 @@ fmm_status fmm_eval_adjoint(fmm_plan_t P, int64_t n, const void* x, const void* 
     });
 }
 
-fmm_status fmm_eval_adjoint_phi(fmm_plan_t P, int64_t n, const void* x, const void* qA,
-                                const void* qB, const int32_t* site, int64_t S, const double* lam,
-                                const double* box, double gE, const void* gphi, void* grad_x,
-                                void* grad_qA, void* grad_qB, double* grad_lambda, double* E, void* F,
-                                void* phi, double* dVdl) {
+// Shared validation and launch of the one-pass adjoint (weights on E, phi, F).
+static fmm_status adjoint_full_entry(fmm_plan_t P, int key_tag, int64_t n, const void* x, const void* qA,
+                                     const void* qB, const int32_t* site, int64_t S, const double* lam,
+                                     const double* box, const double* gE_dev, double gE, const void* gphi,
+                                     const void* gF, void* grad_x, void* grad_qA, void* grad_qB,
+                                     double* grad_lambda, double* E, void* F, void* phi, double* dVdl) {
     fmm_status s = check_common(P, n, x, qA, qB, site, S, lam);
     if (s != FMM_OK) return s;
-    if (!gphi || !std::isfinite(gE)) return fail(P, FMM_E_INVALID, "null or non-finite upstream weight");
+    if (!std::isfinite(gE)) return fail(P, FMM_E_INVALID, "non-finite upstream weight");
     if (P->prm.hamiltonian)
         return fail(P, FMM_E_UNSUPPORTED, "the adjoint covers charge interpolation only");
     double L = 0;
     if ((s = check_box(P, box, &L)) != FMM_OK) return s;
     P->err.clear();
-    std::vector<fmmk::RepDesc> rd(1);
-    rd[0] = {0, n, 0, S, L, 0};
+    const fmmk::RepDesc r0{0, n, 0, S, L, 0};
     KeyBuf key;
-    key.add(5).add(rd[0]).add(x).add(qA).add(qB).add(site).add(lam).add(gE).add(gphi).add(grad_x)
-        .add(grad_qA).add(grad_qB).add(grad_lambda).add(E).add(F).add(phi).add(dVdl);
+    key.add(key_tag).add(r0).add(x).add(qA).add(qB).add(site).add(lam).add(gE_dev).add(gE).add(gphi)
+        .add(gF).add(grad_x).add(grad_qA).add(grad_qB).add(grad_lambda).add(E).add(F).add(phi).add(dVdl);
     return run_maybe_graph(P, key.b, [&]() {
         if (P->fp64)
-            return enqueue_adjoint_phi<double>(P, rd, (const double*)x, (const double*)qA,
-                                               (const double*)qB, site, lam, gE, (const double*)gphi,
-                                               (double*)grad_x, (double*)grad_qA, (double*)grad_qB,
-                                               grad_lambda, E, (double*)F, (double*)phi, dVdl);
-        return enqueue_adjoint_phi<float>(P, rd, (const float*)x, (const float*)qA, (const float*)qB,
-                                          site, lam, gE, (const float*)gphi, (float*)grad_x,
-                                          (float*)grad_qA, (float*)grad_qB, grad_lambda, E, (float*)F,
-                                          (float*)phi, dVdl);
+            return enqueue_adjoint_full<double>(P, r0, (const double*)x, (const double*)qA,
+                                                (const double*)qB, site, lam, gE_dev, gE,
+                                                (const double*)gphi, (const double*)gF, (double*)grad_x,
+                                                (double*)grad_qA, (double*)grad_qB, grad_lambda, E,
+                                                (double*)F, (double*)phi, dVdl);
+        return enqueue_adjoint_full<float>(P, r0, (const float*)x, (const float*)qA, (const float*)qB,
+                                           site, lam, gE_dev, gE, (const float*)gphi, (const float*)gF,
+                                           (float*)grad_x, (float*)grad_qA, (float*)grad_qB, grad_lambda,
+                                           E, (float*)F, (float*)phi, dVdl);
     });
+}
+
+fmm_status fmm_eval_adjoint_phi(fmm_plan_t P, int64_t n, const void* x, const void* qA,
+                                const void* qB, const int32_t* site, int64_t S, const double* lam,
+                                const double* box, double gE, const void* gphi, void* grad_x,
+                                void* grad_qA, void* grad_qB, double* grad_lambda, double* E, void* F,
+                                void* phi, double* dVdl) {
+    if (P && !gphi) return fail(P, FMM_E_INVALID, "null potential weights");
+    return adjoint_full_entry(P, 5, n, x, qA, qB, site, S, lam, box, nullptr, gE, gphi, nullptr, grad_x,
+                              grad_qA, grad_qB, grad_lambda, E, F, phi, dVdl);
+}
+
+fmm_status fmm_eval_adjoint_full(fmm_plan_t P, int64_t n, const void* x, const void* qA,
+                                 const void* qB, const int32_t* site, int64_t S, const double* lam,
+                                 const double* box, const double* gE, const void* gphi, const void* gF,
+                                 void* grad_x, void* grad_qA, void* grad_qB, double* grad_lambda,
+                                 double* E, void* F, void* phi, double* dVdl) {
+    return adjoint_full_entry(P, 6, n, x, qA, qB, site, S, lam, box, gE, 0.0, gphi, gF, grad_x, grad_qA,
+                              grad_qB, grad_lambda, E, F, phi, dVdl);
 }
 
 fmm_status fmm_eval_batched(fmm_plan_t P, int32_t R, const int64_t* atom_off,

@@ -2391,7 +2391,8 @@ __global__ __launch_bounds__(kHcorrThreads) void k_hcorr(Geo g, int R, const Rep
 
 // Final reductions: block r < R -> E_r = k_e / 2 sum of replica r's leaf
 // partials (fixed order); block R + s -> dVdl_s = sum over global site s's
-// atoms in caller order (four forms: dV/dlambda_p and dV/dlambda_t of site s).
+// atoms in caller order (four forms: dV/dlambda_p and dV/dlambda_t of site s;
+// with cphi2, the adjoint's glam_s = sum of cphi2 over the same atoms).
 // Also clears the evaluation's leaf and site counters.
 template <typename T>
 __global__ __launch_bounds__(256) void k_reduce(Geo g, int R, int64_t nparts,
@@ -2408,7 +2409,9 @@ __global__ __launch_bounds__(256) void k_reduce(Geo g, int R, int64_t nparts,
                                                 const double* __restrict__ hc_dl,
                                                 int32_t* __restrict__ leaf_count,
                                                 int32_t* __restrict__ site_count,
-                                                const double* __restrict__ excl_e, int excl_parts) {
+                                                const double* __restrict__ excl_e, int excl_parts,
+                                                const double* __restrict__ cphi2,
+                                                double* __restrict__ glam) {
     __shared__ double red[256], red_t[256];
     __shared__ int32_t mem[kSiteCap];
     const int t = threadIdx.x;
@@ -2428,6 +2431,7 @@ __global__ __launch_bounds__(256) void k_reduce(Geo g, int R, int64_t nparts,
     auto add = [&](int32_t i) {
         if (!four) {
             v += cphi[i];
+            if (cphi2) vt += cphi2[i];
             return;
         }
         const double lp = lam[b - R], lt = fa.lam_t[b - R];
@@ -2474,6 +2478,7 @@ __global__ __launch_bounds__(256) void k_reduce(Geo g, int R, int64_t nparts,
         } else {
             if (dVdl) dVdl[b - R] = red[0] + (hc_dl ? hc_dl[b - R] : 0.0);
             if (four && dVdl_t) dVdl_t[b - R] = red_t[0];
+            if (glam) glam[b - R] = red_t[0];
         }
     }
 }

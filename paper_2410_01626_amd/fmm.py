@@ -58,7 +58,7 @@ EXPORTS = ["fmm_plan_create", "fmm_eval", "fmm_eval_adjoint", "fmm_eval_batched"
            "fmm_sync_check", "fmm_last_error", "fmm_plan_destroy", "fmm_profile",
            "fmm_profile_select", "fmm_plan_info", "fmm_host_operator",
            "fmm_lambda_step", "fmm_lambda_dbo", "fmm_lambda_pfc", "fmm_set_exclusions",
-           "fmm_eval_adjoint_phi"]
+           "fmm_eval_adjoint_phi", "fmm_eval_adjoint_full"]
 PHASES = ["bin", "p2m", "m2m", "root", "m2l", "l2l", "near_far", "reduce"]
 
 _lib = None
@@ -112,6 +112,9 @@ def load_library(path: str = LIB_PATH):
     lib.fmm_eval_adjoint_phi.restype = ctypes.c_int
     lib.fmm_eval_adjoint_phi.argtypes = [vp, i64, vp, vp, vp, vp, i64, vp, vp, ctypes.c_double,
                                          vp, vp, vp, vp, vp, vp, vp, vp, vp]
+    lib.fmm_eval_adjoint_full.restype = ctypes.c_int
+    lib.fmm_eval_adjoint_full.argtypes = [vp, i64, vp, vp, vp, vp, i64, vp, vp, vp, vp, vp,
+                                          vp, vp, vp, vp, vp, vp, vp, vp]
     lib.fmm_set_exclusions.restype = ctypes.c_int
     lib.fmm_set_exclusions.argtypes = [vp, i64, vp, vp]
     lib.fmm_lambda_step.restype = ctypes.c_int
@@ -345,6 +348,36 @@ class Plan:
             _ptr(out["grad_lambda"]), _ptr(out["E"]), _ptr(out["F"]), _ptr(out["phi"]),
             _ptr(out["dVdl"]))
         self._raise(st, "fmm_eval_adjoint_phi")
+        return out
+
+    def eval_adjoint_full(self, x, qA, qB, site, lam, gE=None, gphi=None, gF=None, box=None):
+        """Enqueue fmm_eval_adjoint_full: gradients of gE E + gphi . phi + gF . F
+        (gE a 1-element FP64 device tensor or None; gphi (n,) and gF (n, 3) of
+        the plan's type or None); returns dict of gradients and forward outputs."""
+        import torch
+        n, S = self._inputs(x, qA, qB, site, lam)
+        if gE is not None:
+            self._check(gE, torch.float64, (1,), "gE")
+        if gphi is not None:
+            self._check(gphi, self.dtype, (n,), "gphi")
+        if gF is not None:
+            self._check(gF, self.dtype, (n, 3), "gF")
+        opt = dict(device=self.device)
+        out = {"E": torch.empty(1, dtype=torch.float64, **opt),
+               "F": torch.empty((n, 3), dtype=self.dtype, **opt),
+               "phi": torch.empty(n, dtype=self.dtype, **opt),
+               "dVdl": torch.empty(S, dtype=torch.float64, **opt),
+               "grad_x": torch.empty((n, 3), dtype=self.dtype, **opt),
+               "grad_qA": torch.empty(n, dtype=self.dtype, **opt),
+               "grad_qB": torch.empty(n, dtype=self.dtype, **opt),
+               "grad_lambda": torch.empty(S, dtype=torch.float64, **opt)}
+        b, bp = self._box(box)
+        st = load_library().fmm_eval_adjoint_full(
+            self.handle, n, _ptr(x), _ptr(qA), _ptr(qB), _ptr(site), S, _ptr(lam), bp, _ptr(gE),
+            _ptr(gphi), _ptr(gF), _ptr(out["grad_x"]), _ptr(out["grad_qA"]), _ptr(out["grad_qB"]),
+            _ptr(out["grad_lambda"]), _ptr(out["E"]), _ptr(out["F"]), _ptr(out["phi"]),
+            _ptr(out["dVdl"]))
+        self._raise(st, "fmm_eval_adjoint_full")
         return out
 
     def eval_batched(self, atom_off, site_off, x, qA, qB, site_local, lam, boxes=None):

@@ -19,6 +19,35 @@ def _tensors(d, dt, dev):
             torch.tensor(d["lam"], dtype=torch.float64, device=dev, requires_grad=True))
 
 
+def _leaf_grid(d, periodic):
+    """Origin and leaf edge of the plan's tree: the periodic cell from 0, or the
+    open bounding cube (largest extent enlarged by 2^-20, origin moved down by
+    2^-21 of it, so no atom sits on the far face)."""
+    nb = 1 << d["depth"]
+    x = d["x"]
+    if periodic:
+        return np.zeros(3), d["box"][0] / nb
+    lo, hi = x.min(axis=0), x.max(axis=0)
+    e = (hi - lo).max() * (1.0 + 2.0 ** -20)
+    return lo - 2.0 ** -21 * e, e / nb
+
+
+def _interior_atoms(d, periodic, h, k, seed=0):
+    """k atoms whose coordinates lie at least 2 h from every leaf face (and, open,
+    from the bounding cube's extremes, so a step does not move the cube)."""
+    org, hl = _leaf_grid(d, periodic)
+    x = d["x"] - (d["box"][0] * np.floor(d["x"] / d["box"][0]) if periodic else 0.0)
+    u = (x - org) / hl
+    frac = u - np.floor(u)
+    ok = np.all((frac * hl >= 2 * h) & ((1 - frac) * hl >= 2 * h), axis=1)
+    if not periodic:
+        lo, hi = d["x"].min(axis=0), d["x"].max(axis=0)
+        ok &= np.all((d["x"] - lo >= 2 * h) & (hi - d["x"] >= 2 * h), axis=1)
+    cand = np.flatnonzero(ok)
+    assert cand.size >= k
+    return np.random.default_rng(seed).choice(cand, k, replace=False)
+
+
 def _plan(d, prec, dev):
     from paper_2410_01626_amd import fmm
     return fmm.Plan(d["depth"], d["order"], periodic=d["periodic"], precision=prec,
@@ -47,11 +76,11 @@ def test_adjoint_matches_finite_differences_fp64(periodic):
         out = plan.eval(args["x"], args["qA"], args["qB"], site, args["lam"], box=box)
         return out["E"].item()
 
-    # positions: central difference h = 1e-4 nm on atoms at least h from leaf faces
-    edge = d["box"][0] if periodic else d["edge"]
+    # positions: central difference h = 1e-4 nm on atoms at least h from every
+    # leaf face of the plan's tree (a step across a face differences a
+    # discontinuous FMM energy)
     h = 1e-4
-    rng = np.random.default_rng(0)
-    picks = rng.choice(d["x"].shape[0], 8, replace=False)
+    picks = _interior_atoms(d, periodic, h, 8)
     gx = x.grad.cpu().numpy()
     for i in picks:
         for a in range(3):
@@ -128,7 +157,9 @@ def test_backward_recomputes_from_inputs():
         assert torch.equal(a, b)
 
 
-def test_second_order_request_is_rejected():
+def test_lambda_force_gradient_request_is_rejected():
+    """dV/dlambda is a non-differentiable output (E, F and phi are
+    differentiable)."""
     import torch
     from paper_2410_01626_amd.autograd import fmm_coulomb
     dev = torch.device("cuda:0")
@@ -136,9 +167,9 @@ def test_second_order_request_is_rejected():
     plan = _plan(d, "fp64", dev)
     x, qA, qB, site, lam = _tensors(d, torch.float64, dev)
     E, F, phi, dVdl = fmm_coulomb(plan, x, qA, qB, site, lam)
-    assert not F.requires_grad and not dVdl.requires_grad
+    assert F.requires_grad and phi.requires_grad and not dVdl.requires_grad
     with pytest.raises(RuntimeError):
-        F.sum().backward()
+        dVdl.sum().backward()
 
 
 def test_potential_is_differentiable():

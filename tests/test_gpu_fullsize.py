@@ -68,6 +68,22 @@ def test_large_box_sampled(prec):
     np.testing.assert_array_equal(gx.cpu().numpy(), -F.detach().cpu().numpy())
     np.testing.assert_allclose(gl.cpu().numpy(), dn, rtol=0, atol=0)
     assert np.isfinite(E.item())
+    # and the gradients themselves against the oracle's on 600 sampled atoms
+    # and every site atom: dE/dx = -F, dE/dqA = (1 - l) phi, dE/dqB = l phi
+    rng = np.random.default_rng(11)
+    samp = np.union1d(rng.choice(n, 600, replace=False), np.flatnonzero(d["site"] >= 0))
+    q, phi_o, F_o = _oracle_sample(d, samp, True)
+    lam_s = np.where(d["site"] >= 0, d["lam"][np.maximum(d["site"], 0)], 0.0)[samp]
+    tol = TOL_F[d["order"]]
+    for got, exp in ((gx.double().cpu().numpy()[samp], -F_o),
+                     (gqA.double().cpu().numpy()[samp], (1 - lam_s) * phi_o),
+                     (gqB.double().cpu().numpy()[samp], lam_s * phi_o)):
+        nz = np.sum(exp ** 2)
+        if nz == 0:
+            assert np.all(got == 0)
+            continue
+        err = np.sqrt(np.sum((got - exp) ** 2) / nz)
+        assert err <= tol, err
 
 
 def test_replicas_full_size_sampled():

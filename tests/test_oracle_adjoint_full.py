@@ -118,3 +118,22 @@ def test_force_weights_in_a_large_cell_approach_the_direct_sum():
         h, e = oracle.force_weight_sums(xs, q, w, [L] * 3, True, eps=1e-12)
         errs.append(np.abs(h - h0).max() / np.abs(h0).max())
     assert errs[1] < errs[0] < 2e-3, errs
+
+
+@pytest.mark.parametrize("periodic", [False, True])
+def test_targets_subset_equals_full_gradient(periodic):
+    """The per-target form (the sums still over every atom) returns the rows
+    of the full gradient, and glam once every site atom is a target."""
+    d, x, qA, qB, site, lam = _system(periodic, seed=15, n=28)
+    rng = np.random.default_rng(10)
+    gphi = rng.normal(0, 1, x.shape[0])
+    gF = rng.normal(0, 1, x.shape)
+    kw = dict(box=d["box"], periodic=True) if periodic else {}
+    full = oracle.adjoint_full(x, qA, qB, site, lam, 0.4, gphi, gF, **kw)
+    t = np.union1d(rng.choice(x.shape[0], 7, replace=False), np.flatnonzero(site >= 0))
+    part = oracle.adjoint_full(x, qA, qB, site, lam, 0.4, gphi, gF, targets=t, **kw)
+    for a, b in zip(full[:3], part[:3]):
+        np.testing.assert_allclose(b, a[t], rtol=1e-12, atol=1e-12 * np.abs(a).max())
+    np.testing.assert_allclose(part[3], full[3], rtol=1e-12, atol=1e-12)
+    t2 = np.setdiff1d(t, np.flatnonzero(site >= 0)[:1])
+    assert oracle.adjoint_full(x, qA, qB, site, lam, 0.4, gphi, gF, targets=t2, **kw)[3] is None
