@@ -62,7 +62,7 @@ def test_large_box_sampled(prec):
     E, F, phi, dVdl = fmm_coulomb(plan, x, qA, qB, site, lam, d["box"])
     gx, gqA, gqB, gl = torch.autograd.grad(E, [x, qA, qB, lam])
     torch.cuda.synchronize()
-    Fn, pn, dn = F.double().cpu().numpy(), phi.detach().double().cpu().numpy(), dVdl.cpu().numpy()
+    Fn, pn, dn = F.detach().double().cpu().numpy(), phi.detach().double().cpu().numpy(), dVdl.cpu().numpy()
     _check(d, pn, Fn, dn, True, d["order"])
     # the adjoint of a unit weight is (-F, (1-l) phi, l phi, dV/dl) of the same solve
     np.testing.assert_array_equal(gx.cpu().numpy(), -F.detach().cpu().numpy())
