@@ -153,6 +153,25 @@ fmm_status fmm_eval(fmm_plan_t plan, int64_t n, const void* x, const void* qA,
                     const double* lambda, const double* box, double* E, void* F,
                     void* phi, double* dVdl);
 
+/* fmm_eval for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * same evaluation, arguments and results as fmm_eval, but the per-evaluation
+ * workspace (sorted particles, counters, expansions, partial sums) is laid
+ * out in a static device array of the library (32 MiB per GPU, held until the
+ * process ends) instead of the plan's own workspace.  The call allocates
+ * nothing.  It clears the counters it needs at its start (fill kernels);
+ * every call on one GPU shares the array, so calls that overlap on one GPU
+ * (other streams, other threads) race.  FMM_E_INVALID, with nothing
+ * enqueued, when n atoms and n_sites sites on this plan need more than the
+ * array holds (about 60 bytes per atom in mixed precision plus the tree's
+ * expansions and partial sums, some 7 MB at depth 3, p = 8: about 400,000
+ * atoms there); fmm_last_error() gives the sizes.  Never replayed from a
+ * graph. */
+fmm_status fmm_eval_noalloc(fmm_plan_t plan, int64_t n, const void* x, const void* qA,
+                            const void* qB, const int32_t* site, int64_t n_sites,
+                            const double* lambda, const double* box, double* E, void* F,
+                            void* phi, double* dVdl);
+
 /* Adjoint of E (reverse mode for an upstream weight gE on the energy).  The
  * tree and every expansion are recomputed from the inputs (nothing is kept
  * from a previous forward call).  With w = *gE (a DEVICE double):

@@ -7,7 +7,9 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "fmm_kernels.hip"
@@ -18,6 +20,36 @@
 
 using fmmk::Geo;
 
+// Per-evaluation scratch of a plan: the buffers every evaluation rewrites
+// (sorted particles, keys, counters, expansions, partial sums).  They live in
+// one arena: the plan's own allocation, or (fmm_eval_noalloc) the library's
+// static scratch array.
+struct Workspace {
+    void* pos = nullptr;
+    int32_t *perm = nullptr, *key = nullptr, *rank = nullptr;
+    int32_t *leaf_count = nullptr, *leaf_start = nullptr, *leaf_order = nullptr;
+    int32_t *site_count = nullptr, *site_start = nullptr, *site_rank = nullptr,
+            *site_members = nullptr;
+    void *mult = nullptr, *loc = nullptr;
+    double *root_m = nullptr, *root_l = nullptr;
+    double* root_part = nullptr;  // periodic: the 8 level-1 shares of the root multipole
+    double* box_part = nullptr;   // per-box FP64 sums of q |t/L|^2 and q (upward pass)
+    double *dom = nullptr, *bbox_part = nullptr, *leaf_part = nullptr, *leaf_energy = nullptr,
+           *cphi = nullptr;
+    fmmk::RepDesc* reps = nullptr;  // device replica descriptors
+    void *F_tmp = nullptr, *phi_tmp = nullptr;
+    double *dVdl_tmp = nullptr, *E_tmp = nullptr;
+    // adjoint with weights on E, phi and F: the second sources (w, g) in leaf
+    // order, the per-atom (phi, E, A, B) of the leaf pass, the site terms of
+    // dL/dq and the energy partials of the combine kernel
+    void *adj_src2 = nullptr, *adj_acc = nullptr;
+    double *adj_cphi2 = nullptr, *adj_part = nullptr;
+    // Hamiltonian interpolation: per-site energy and lambda-derivative corrections
+    double *hc_e = nullptr, *hc_dl = nullptr;
+    void* msplit = nullptr;    // bf16x3: source expansions split into hi/lo (replicas x (nbox + 1) rows)
+    void* m2l_part = nullptr;  // matrix-core M2L: partial sums of the offset chunks
+};
+
 struct fmm_plan_s {
     fmm_params prm{};
     hipStream_t stream = nullptr;
@@ -27,43 +59,23 @@ struct fmm_plan_s {
     int K = 0, Kp = 0, Kg = 0, nleaf = 0;
     int64_t nbox = 0;
     int64_t lev_off[fmmk::kDMax + 2] = {};
-    // workspace (device)
-    void* pos = nullptr;
-    int32_t *perm = nullptr, *key = nullptr, *rank = nullptr;
-    int32_t *leaf_count = nullptr, *leaf_start = nullptr;
-    int32_t *site_count = nullptr, *site_start = nullptr, *site_rank = nullptr,
-            *site_members = nullptr;
-    void *mult = nullptr, *loc = nullptr;
-    double *root_m = nullptr, *root_l = nullptr;
-    double* root_part = nullptr;  // periodic: the 8 level-1 shares of the root multipole
+    Workspace ws;
+    void* ws_arena = nullptr;  // the plan's own workspace allocation
+    // operator tables (device)
     void *bankT = nullptr, *m2mT = nullptr, *l2lT = nullptr, *gcoef = nullptr;
     void *m2m_seg = nullptr, *l2l_seg = nullptr;  // tree-pass register caches (thread order)
     double* lat_seg = nullptr;
     double* latT = nullptr;
     int32_t* gidx = nullptr;
-    double *box_part = nullptr;  // per-box FP64 sums of q |t/L|^2 and q (upward pass)
-    double *dom = nullptr, *bbox_part = nullptr, *leaf_part = nullptr, *leaf_energy = nullptr,
-           *cphi = nullptr;
     int32_t* status = nullptr;
-    void *F_tmp = nullptr, *phi_tmp = nullptr;
-    // Hamiltonian interpolation: per-site energy and lambda-derivative
-    // corrections, and (periodic) the Green's function coefficients of the
-    // unit cube (degree kPMax) followed by those of its gradient (3 x kPMax^2)
-    double *hc_e = nullptr, *hc_dl = nullptr, *green = nullptr;
-    int32_t* leaf_order = nullptr;  // near-field order of the leaves (largest work first)
+    // Hamiltonian interpolation (periodic): the Green's function coefficients of
+    // the unit cube (degree kPMax) followed by those of its gradient (3 x kPMax^2)
+    double* green = nullptr;
     // bonded exclusions (fmm_set_exclusions): per-atom partner lists for
     // excl_n atoms and the per-block energy partials of their removal
     int64_t excl_n = 0;
     int32_t *excl_start = nullptr, *excl_idx = nullptr;
     double* excl_e = nullptr;
-    // adjoint with weights on E, phi and F: the second sources (w, g) in leaf
-    // order, the per-atom (phi, E, A, B) of the leaf pass, the site terms of
-    // dL/dq and the energy partials of the combine kernel
-    void *adj_src2 = nullptr, *adj_acc = nullptr;
-    double *adj_cphi2 = nullptr, *adj_part = nullptr;
-    double* dVdl_tmp = nullptr;
-    double* E_tmp = nullptr;
-    fmmk::RepDesc* reps = nullptr;  // device replica descriptors (max_replicas)
     // graph replay (params.graph): the last captured evaluation and its argument key
     bool graph_valid = false;
     std::vector<unsigned char> graph_key;
@@ -81,8 +93,7 @@ struct fmm_plan_s {
     fmmk::M2LTask* tasks = nullptr;
     int16_t* olist = nullptr;
     int16_t* cstart = nullptr;
-    void *bank_mma = nullptr, *bank_mma_lo = nullptr, *m2l_part = nullptr;
-    void* msplit = nullptr;  // bf16x3: source expansions split into hi/lo (replicas x (nbox + 1) rows)
+    void *bank_mma = nullptr;
     void* sign_tab = nullptr;  // bf16x3: reflection sign-bit masks [class][k chunk of 8]
     int m2l_nbuf = 1;        // bf16x3: LDS staging buffers (2: copy of the next offset overlaps)
     std::vector<void*> allocs;
@@ -99,13 +110,61 @@ struct fmm_plan_s {
     bool prof_sample = false, prof_open = false;
 };
 
+// Static scratch of fmm_eval_noalloc, for callers that cannot allocate
+// device memory: the per-evaluation workspace is laid out in this array
+// instead of the plan's own.  Every GPU the library runs on holds one copy
+// until the process ends; calls that overlap on one GPU share it and race.
+constexpr size_t kScratchBytes = (size_t)32 << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
 namespace {
 
 constexpr int kBboxBlocks = 256;
 
+// Device address of each GPU's copy of `scratch`, looked up once per device
+// with that device current (plan creation); host code uses only these
+// addresses, never the array's name.
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+bool scratch_lookup(int dev) {
+    if (dev < 0 || dev >= kMaxDevices) return false;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (g_scratch_ptr[dev]) return true;
+    void* ptr = nullptr;
+    if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) return false;
+    g_scratch_ptr[dev] = ptr;
+    return true;
+}
+
+void* scratch_address(int dev) {
+    if (dev < 0 || dev >= kMaxDevices) return nullptr;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    return g_scratch_ptr[dev];
+}
+
 fmm_status fail(fmm_plan_t p, fmm_status st, const std::string& msg) {
     if (p) p->err = msg;
     return st;
+}
+
+// A view of the host replica descriptors of one call (a vector or an array on
+// the stack).
+struct RepSpan {
+    const fmmk::RepDesc* p;
+    size_t n;
+    RepSpan(const std::vector<fmmk::RepDesc>& v) : p(v.data()), n(v.size()) {}
+    RepSpan(const fmmk::RepDesc* q, size_t m) : p(q), n(m) {}
+    size_t size() const { return n; }
+    const fmmk::RepDesc& operator[](size_t i) const { return p[i]; }
+    const fmmk::RepDesc* begin() const { return p; }
+    const fmmk::RepDesc* end() const { return p + n; }
+};
+
+// Bytes of the bf16x3 split source rows: (nbox + 1) rows of 2 KP bf16 per slot.
+size_t msplit_bytes(const fmm_plan_s* P, size_t RM) {
+    return RM * ((size_t)P->nbox + 1) * 2 * P->mg.KP * 2;
 }
 
 bool dev_alloc(fmm_plan_t p, void** ptr, size_t bytes) {
@@ -118,6 +177,73 @@ bool dev_alloc(fmm_plan_t p, void** ptr, size_t bytes) {
 
 // Reflection parity bits of real coefficient k (bit 2: x -> -x, bit 1:
 // y -> -y, bit 0: z -> -z), as the kernels' refl_bits.
+// Lay out a plan's per-evaluation buffers for up to N atoms, S sites and RM
+// expansion slots (adjoint: with the adjoint's buffers) from base, each
+// buffer aligned to 256 bytes; returns the arena size.  base = NULL only
+// sizes it.  The matrix-core M2L geometry (mg, m2l_mode) must be set.
+size_t ws_layout(const fmm_plan_s* P, int64_t N, int64_t S, size_t RM, bool adjoint, char* base,
+                 Workspace* w) {
+    N = std::max<int64_t>(N, 1);
+    S = std::max<int64_t>(S, 1);
+    Workspace tmp;
+    if (!w) w = &tmp;
+    size_t off = 0;
+    auto take = [&](auto*& ptr, size_t bytes) {
+        using PT = std::remove_reference_t<decltype(ptr)>;
+        ptr = base ? reinterpret_cast<PT>(base + off) : nullptr;
+        off += (std::max<size_t>(bytes, 1) + 255) & ~size_t(255);
+    };
+    const size_t ts = P->tsz, K = P->K, nl = P->nleaf, nb = P->nbox, Kp = P->Kp;
+    take(w->pos, N * 4 * ts);
+    take(w->perm, N * 4);
+    take(w->key, N * 4);
+    take(w->rank, N * 4);
+    take(w->leaf_count, RM * nl * 4);
+    take(w->leaf_start, RM * (nl + 1) * 4);
+    take(w->leaf_order, RM * nl * 4);
+    take(w->site_count, S * 4);
+    take(w->site_start, (S + 1) * 4);
+    take(w->site_rank, N * 4);
+    take(w->site_members, N * 4);
+    take(w->mult, RM * nb * Kp * ts);
+    take(w->loc, RM * nb * Kp * ts);
+    take(w->root_m, RM * K * 8);
+    take(w->root_l, RM * K * 8);
+    take(w->root_part, RM * 8 * K * 8);
+    take(w->dom, RM * 8 * 8);
+    take(w->bbox_part, RM * kBboxBlocks * 6 * 8);
+    take(w->leaf_part, RM * nl * 2 * 8);
+    take(w->box_part, RM * nb * 2 * 8);
+    take(w->leaf_energy, RM * nl * fmmk::kMaxSplit * 8);
+    take(w->reps, RM * sizeof(fmmk::RepDesc));
+    take(w->cphi, N * 8);
+    take(w->F_tmp, N * 3 * ts);
+    take(w->phi_tmp, N * ts);
+    take(w->dVdl_tmp, S * 8);
+    take(w->E_tmp, RM * 8);
+    if (adjoint) {
+        take(w->adj_src2, N * 4 * ts);
+        take(w->adj_acc, N * 8 * ts);
+        take(w->adj_cphi2, N * 8);
+        take(w->adj_part, ((N + 255) / 256) * 8);
+    } else {
+        w->adj_src2 = w->adj_acc = nullptr;
+        w->adj_cphi2 = w->adj_part = nullptr;
+    }
+    if (P->prm.hamiltonian) {
+        take(w->hc_e, S * 8);
+        take(w->hc_dl, S * 8);
+    } else {
+        w->hc_e = w->hc_dl = nullptr;
+    }
+    if (P->m2l_mode == 3) take(w->msplit, msplit_bytes(P, RM));
+    else w->msplit = nullptr;
+    if (P->m2l_mode != 0 && P->mg.nchunk > 1)
+        take(w->m2l_part, RM * P->mg.nchunk * P->mg.nt_all * Kp * ts);
+    else w->m2l_part = nullptr;
+    return off;
+}
+
 int refl_bits_host(int k) {
     const int l = (int)std::floor(std::sqrt((double)k + 0.5));
     const int rem = k - l * l;
@@ -280,9 +406,9 @@ bool launch_m2l_mma(fmm_plan_t P, const Geo& g, int R, bool want_root) {
     const M2LGeom mg = P->mg;
     const dim3 nt((unsigned)P->n_tasks, (unsigned)R);
     const size_t lds = P->m2l_lds;
-    T* loc = (T*)P->loc;
-    T* part = (T*)P->m2l_part;
-    const T* mult = (const T*)P->mult;
+    T* loc = (T*)P->ws.loc;
+    T* part = (T*)P->ws.m2l_part;
+    const T* mult = (const T*)P->ws.mult;
     switch (P->m2l_mode * 16 + P->m2l_rt) {
 #define FMM_M2L_F32(RTV)                                                                    \
     case 16 + RTV:                                                                          \
@@ -299,7 +425,7 @@ bool launch_m2l_mma(fmm_plan_t P, const Geo& g, int R, bool want_root) {
 #define FMM_M2L_BF(RTV)                                                                         \
     case 48 + RTV:                                                                              \
         k_m2l_bf16x3<RTV><<<nt, kM2LThreads, lds, st>>>(g, mg, P->tasks, P->olist, P->cstart,   \
-                                                (const uint4*)P->msplit,                        \
+                                                (const uint4*)P->ws.msplit,                        \
                                                 (const uint4*)P->bank_mma, P->m2l_nbuf,         \
                                                 (const uint4*)P->sign_tab, (float*)loc,         \
                                                 (float*)part);                                  \
@@ -318,8 +444,8 @@ bool launch_m2l_mma(fmm_plan_t P, const Geo& g, int R, bool want_root) {
         // periodic trees with a downward pass: the extra block forms the root
         k_m2l_reduce<T><<<dim3(nb + (want_root ? 1u : 0u), (unsigned)R), kTreeThreads, 0, st>>>(
             g, mg, part, loc, want_root ? 1 : 0, mult, (const T*)P->m2mT, (const T*)P->m2m_seg,
-            P->leaf_part, P->box_part, P->latT, P->lat_seg, P->root_m, P->root_l, P->dom,
-            g.depth >= 2 ? P->root_part : nullptr);
+            P->ws.leaf_part, P->ws.box_part, P->latT, P->lat_seg, P->ws.root_m, P->ws.root_l, P->ws.dom,
+            g.depth >= 2 ? P->ws.root_part : nullptr);
         return want_root;
     }
     return false;
@@ -331,7 +457,7 @@ bool launch_m2l_mma(fmm_plan_t P, const Geo& g, int R, bool want_root) {
 // nstore replica descriptors are stored (nstore >= R: extra slots describe
 // the same systems for kernels run on more expansion slots later).
 template <typename T>
-void enqueue_bin_p2m(fmm_plan_t P, const fmmk::Geo& g, const std::vector<fmmk::RepDesc>& rd, int R,
+void enqueue_bin_p2m(fmm_plan_t P, const fmmk::Geo& g, RepSpan rd, int R,
                      const T* x, const T* qA, const T* qB, const int32_t* site, const double* lam,
                      const fmmk::FormArgs<T>& fa, int64_t maxn, int64_t S_tot) {
     using namespace fmmk;
@@ -352,36 +478,36 @@ void enqueue_bin_p2m(fmm_plan_t P, const fmmk::Geo& g, const std::vector<fmmk::R
             set.first = f;
             set.count = std::min(kRepsPerSet, nstore - f);
             for (int i = 0; i < set.count; ++i) set.d[i] = rd[f + i];
-            k_set_reps<<<1, kRepsPerSet, 0, st>>>(set, P->reps);
+            k_set_reps<<<1, kRepsPerSet, 0, st>>>(set, P->ws.reps);
         }
     }
-    const RepDesc* reps = P->reps;
+    const RepDesc* reps = P->ws.reps;
     const unsigned ab = nblocks(maxn, 256);
     if (!g.periodic) {
         const int nb = (int)std::min<int64_t>(kBboxBlocks, ab);
-        k_bbox<T><<<dim3(nb, R), 256, 0, st>>>(x, set0, P->reps, P->bbox_part);
-        k_bbox_final<<<R, 64, 0, st>>>(P->bbox_part, nb, P->dom);
+        k_bbox<T><<<dim3(nb, R), 256, 0, st>>>(x, set0, P->ws.reps, P->ws.bbox_part);
+        k_bbox_final<<<R, 64, 0, st>>>(P->ws.bbox_part, nb, P->ws.dom);
         set0.count = 0;  // stored by k_bbox
     }
-    k_charge_key<T><<<dim3(ab, R), 256, 0, st>>>(g, set0, P->reps, x, qA, qB, site, lam, fa, P->dom, P->key,
-                                                 P->rank, P->leaf_count, P->site_count,
-                                                 P->site_rank, P->status);
+    k_charge_key<T><<<dim3(ab, R), 256, 0, st>>>(g, set0, P->ws.reps, x, qA, qB, site, lam, fa, P->ws.dom, P->ws.key,
+                                                 P->ws.rank, P->ws.leaf_count, P->ws.site_count,
+                                                 P->ws.site_rank, P->status);
     if (g.nleaf <= kScanFuseCap && S_tot <= kScanFuseCap) {
-        k_scan_scatter<<<dim3(ab, R), 256, 0, st>>>(g, reps, P->key, P->rank, P->leaf_count,
-                                                    P->leaf_start, P->perm, site, P->site_rank,
-                                                    P->site_count, P->site_start, (int)S_tot,
-                                                    P->site_members);
+        k_scan_scatter<<<dim3(ab, R), 256, 0, st>>>(g, reps, P->ws.key, P->ws.rank, P->ws.leaf_count,
+                                                    P->ws.leaf_start, P->ws.perm, site, P->ws.site_rank,
+                                                    P->ws.site_count, P->ws.site_start, (int)S_tot,
+                                                    P->ws.site_members);
     } else {
-        k_scan2<<<R + 1, 1024, 0, st>>>(reps, R, P->leaf_count, P->leaf_start, g.nleaf,
-                                        P->site_count, P->site_start, S_tot);
-        k_scatter<<<dim3(ab, R), 256, 0, st>>>(g, reps, P->key, P->rank, P->leaf_start, P->perm,
-                                               site, P->site_rank, P->site_start, P->site_members);
+        k_scan2<<<R + 1, 1024, 0, st>>>(reps, R, P->ws.leaf_count, P->ws.leaf_start, g.nleaf,
+                                        P->ws.site_count, P->ws.site_start, S_tot);
+        k_scatter<<<dim3(ab, R), 256, 0, st>>>(g, reps, P->ws.key, P->ws.rank, P->ws.leaf_start, P->ws.perm,
+                                               site, P->ws.site_rank, P->ws.site_start, P->ws.site_members);
     }
     using V4 = vec4_t<T>;
     mark(P, 1);
     k_leaf_p2m<T><<<dim3(g.nleaf, R), kLeafThreads, leaf_lds_bytes<T>(g.K), st>>>(
-        g, reps, x, qA, qB, site, lam, fa, P->dom, P->leaf_start, P->perm, (V4*)P->pos, P->status,
-        (T*)P->mult, P->leaf_part, (uint16_t*)P->msplit, P->mg.KP);
+        g, reps, x, qA, qB, site, lam, fa, P->ws.dom, P->ws.leaf_start, P->ws.perm, (V4*)P->ws.pos, P->status,
+        (T*)P->ws.mult, P->ws.leaf_part, (uint16_t*)P->ws.msplit, P->mg.KP);
 }
 
 // The tree passes of R expansion slots (grid y = slot): M2M per level, the
@@ -392,8 +518,8 @@ template <typename T>
 int32_t* enqueue_tree(fmm_plan_t P, const fmmk::Geo& g, int R, bool want_order) {
     using namespace fmmk;
     hipStream_t st = P->stream;
-    T* mult = (T*)P->mult;
-    T* loc = (T*)P->loc;
+    T* mult = (T*)P->ws.mult;
+    T* loc = (T*)P->ws.loc;
     // upward pass: one launch per level down to the coarsest interacting
     // level (1 periodic, 2 open); the periodic root and its lattice operator
     // are formed by the M2L reduction launch (or else at the start of the
@@ -404,12 +530,12 @@ int32_t* enqueue_tree(fmm_plan_t P, const fmmk::Geo& g, int R, bool want_order) 
     const bool root_in_reduce = g.periodic && g.depth >= 1 && P->m2l_mode != 0 && P->mg.nchunk > 1;
     for (int lev = g.depth - 1; lev >= g.lmin; --lev)
         k_m2m<T><<<dim3(1u << (3 * lev), R), kTreeThreads, 0, st>>>(
-            g, lev, mult, (const T*)P->m2mT, (const T*)P->m2m_seg, P->leaf_part, P->box_part,
-            (uint16_t*)P->msplit, P->mg.KP, root_in_reduce && lev == 1 ? P->root_part : nullptr);
+            g, lev, mult, (const T*)P->m2mT, (const T*)P->m2m_seg, P->ws.leaf_part, P->ws.box_part,
+            (uint16_t*)P->ws.msplit, P->mg.KP, root_in_reduce && lev == 1 ? P->ws.root_part : nullptr);
     mark(P, 3);
     if (g.periodic && g.depth == 0)
-        k_root<T><<<R, 256, 0, st>>>(g, P->leaf_part, P->root_m, mult, P->latT, P->root_l, loc,
-                                     P->dom);
+        k_root<T><<<R, 256, 0, st>>>(g, P->ws.leaf_part, P->ws.root_m, mult, P->latT, P->ws.root_l, loc,
+                                     P->ws.dom);
     mark(P, 4);
     bool root_ready = false;  // the periodic root formed by the M2L reduction launch
     if (g.depth >= g.lmin) {
@@ -428,12 +554,12 @@ int32_t* enqueue_tree(fmm_plan_t P, const fmmk::Geo& g, int R, bool want_order) 
     // leaves for the near field by decreasing work
     int32_t* order = nullptr;
     if (g.depth >= 1 && g.depth - 1 >= l0) {
-        if (want_order && g.nleaf <= kOrderCap) order = P->leaf_order;
+        if (want_order && g.nleaf <= kOrderCap) order = P->ws.leaf_order;
         const unsigned nbx = (1u << (3 * (g.depth - 1))) + (order ? 1u : 0u);
         k_downward<T><<<dim3(nbx, R), kTreeThreads, 0, st>>>(
             g, l0, loc, (const T*)P->l2lT, (const T*)P->l2l_seg, mult, (const T*)P->m2mT,
-            (const T*)P->m2m_seg, P->leaf_part, P->box_part, P->latT, P->lat_seg, P->root_m, P->root_l,
-            P->dom, P->leaf_start, order, root_ready ? 1 : 0);
+            (const T*)P->m2m_seg, P->ws.leaf_part, P->ws.box_part, P->latT, P->lat_seg, P->ws.root_m, P->ws.root_l,
+            P->ws.dom, P->ws.leaf_start, order, root_ready ? 1 : 0);
     }
     return order;
 }
@@ -442,7 +568,7 @@ int32_t* enqueue_tree(fmm_plan_t P, const fmmk::Geo& g, int R, bool want_order) 
 // the host copy of the replica descriptors).  Every phase is one launch over
 // all replicas (grid y = replica).
 template <typename T>
-fmm_status enqueue_eval(fmm_plan_t P, const std::vector<fmmk::RepDesc>& rd, const T* x,
+fmm_status enqueue_eval(fmm_plan_t P, RepSpan rd, const T* x,
                         const T* qA, const T* qB, const int32_t* site, const double* lam,
                         double* E, T* F, T* phi, double* dVdl,
                         const fmmk::FormArgs<T> fa = {nullptr, nullptr, nullptr},
@@ -463,18 +589,18 @@ fmm_status enqueue_eval(fmm_plan_t P, const std::vector<fmmk::RepDesc>& rd, cons
     mark(P, 0);
     enqueue_bin_p2m<T>(P, g, rd, R, x, qA, qB, site, lam, fa, maxn, S_tot);
     int32_t* order = enqueue_tree<T>(P, g, R, true);
-    const RepDesc* reps = P->reps;
+    const RepDesc* reps = P->ws.reps;
     const unsigned ab = nblocks(maxn, 256);
     using V4 = vec4_t<T>;
-    const V4* pos = (const V4*)P->pos;
-    const T* loc = (const T*)P->loc;
+    const V4* pos = (const V4*)P->ws.pos;
+    const T* loc = (const T*)P->ws.loc;
     mark(P, 6);
     switch (P->p2p_waves) {
 #define FMM_NEAR(NWV)                                                                            \
     case NWV:                                                                                    \
         k_near_far<T, NWV><<<dim3(g.nleaf * P->p2p_split, R), 64 * NWV, 0, st>>>(               \
-            g, P->p2p_split, reps, pos, P->leaf_start, P->perm, P->dom, loc, P->gidx,              \
-            (const T*)P->gcoef, qA, qB, site, phi, F, P->leaf_energy, P->cphi, fa.qC != nullptr,   \
+            g, P->p2p_split, reps, pos, P->ws.leaf_start, P->ws.perm, P->ws.dom, loc, P->gidx,              \
+            (const T*)P->gcoef, qA, qB, site, phi, F, P->ws.leaf_energy, P->ws.cphi, fa.qC != nullptr,   \
             order);                                                                                \
         break;
         FMM_NEAR(4)
@@ -483,21 +609,21 @@ fmm_status enqueue_eval(fmm_plan_t P, const std::vector<fmmk::RepDesc>& rd, cons
         default: break;
     }
     if (P->excl_n > 0)
-        k_excl<T><<<dim3(ab, R), 256, 0, st>>>(g, reps, x, qA, qB, site, lam, fa, P->dom, P->excl_start,
-                                               P->excl_idx, phi, F, P->cphi, fa.qC != nullptr,
+        k_excl<T><<<dim3(ab, R), 256, 0, st>>>(g, reps, x, qA, qB, site, lam, fa, P->ws.dom, P->excl_start,
+                                               P->excl_idx, phi, F, P->ws.cphi, fa.qC != nullptr,
                                                P->excl_e);
     mark(P, 7);
     const bool ham = P->prm.hamiltonian != 0;
     if (ham && S_tot > 0)
-        k_hcorr<T><<<(unsigned)S_tot, kHcorrThreads, 0, st>>>(g, R, reps, P->site_start, P->site_members, x, qA,
-                                                    qB, lam, P->green, F, P->hc_e, P->hc_dl,
+        k_hcorr<T><<<(unsigned)S_tot, kHcorrThreads, 0, st>>>(g, R, reps, P->ws.site_start, P->ws.site_members, x, qA,
+                                                    qB, lam, P->green, F, P->ws.hc_e, P->ws.hc_dl,
                                                     P->status);
-    k_reduce<T><<<(unsigned)(R + S_tot), 256, 0, st>>>(g, R, g.nleaf * P->p2p_split, P->leaf_energy,
-                                                       P->site_start, P->site_members, P->cphi, E,
+    k_reduce<T><<<(unsigned)(R + S_tot), 256, 0, st>>>(g, R, g.nleaf * P->p2p_split, P->ws.leaf_energy,
+                                                       P->ws.site_start, P->ws.site_members, P->ws.cphi, E,
                                                        dVdl, P->status, qA, qB, lam, fa, dVdl_t, reps,
-                                                       ham && S_tot > 0 ? P->hc_e : nullptr,
-                                                       ham && S_tot > 0 ? P->hc_dl : nullptr,
-                                                       P->leaf_count, P->site_count,
+                                                       ham && S_tot > 0 ? P->ws.hc_e : nullptr,
+                                                       ham && S_tot > 0 ? P->ws.hc_dl : nullptr,
+                                                       P->ws.leaf_count, P->ws.site_count,
                                                        P->excl_n > 0 ? P->excl_e : nullptr, (int)ab,
                                                        nullptr, nullptr);
     mark(P, -1);
@@ -507,19 +633,19 @@ fmm_status enqueue_eval(fmm_plan_t P, const std::vector<fmmk::RepDesc>& rd, cons
 }
 
 template <typename T>
-fmm_status enqueue_adjoint(fmm_plan_t P, const std::vector<fmmk::RepDesc>& rd, const T* x,
+fmm_status enqueue_adjoint(fmm_plan_t P, RepSpan rd, const T* x,
                            const T* qA, const T* qB, const int32_t* site, const double* lam,
                            const double* gE, T* gx, T* gqA, T* gqB, double* glam, double* E, T* F,
                            T* phi, double* dVdl) {
-    T* Fw = F ? F : (T*)P->F_tmp;
-    T* pw = phi ? phi : (T*)P->phi_tmp;
-    double* dw = dVdl ? dVdl : P->dVdl_tmp;
-    fmm_status s = enqueue_eval<T>(P, rd, x, qA, qB, site, lam, E ? E : P->E_tmp, Fw, pw, dw);
+    T* Fw = F ? F : (T*)P->ws.F_tmp;
+    T* pw = phi ? phi : (T*)P->ws.phi_tmp;
+    double* dw = dVdl ? dVdl : P->ws.dVdl_tmp;
+    fmm_status s = enqueue_eval<T>(P, rd, x, qA, qB, site, lam, E ? E : P->ws.E_tmp, Fw, pw, dw);
     if (s != FMM_OK) return s;
     int64_t m = 0;
     for (const fmmk::RepDesc& d : rd) m = std::max(m, std::max(d.n, d.S));
     fmmk::k_adjoint<T><<<dim3(nblocks(m, 256), (unsigned)rd.size()), 256, 0, P->stream>>>(
-        P->reps, site, lam, gE, Fw, pw, dw, gx, gqA, gqB, glam);
+        P->ws.reps, site, lam, gE, Fw, pw, dw, gx, gqA, gqB, glam);
     return hipGetLastError() == hipSuccess ? FMM_OK : fail(P, FMM_E_HIP, "adjoint launch failed");
 }
 
@@ -540,30 +666,31 @@ fmm_status enqueue_adjoint_full(fmm_plan_t P, const fmmk::RepDesc& r0, const T* 
     const int64_t n = r0.n, S = r0.S;
     if (P->excl_n > 0 && n != P->excl_n)
         return fail(P, FMM_E_INVALID, "the exclusion lists were set for a different atom count");
-    const std::vector<RepDesc> rd{r0, r0};  // slot 1: the second sources of the same system
+    const RepDesc rd2[2] = {r0, r0};  // slot 1: the second sources of the same system
+    const RepSpan rd(rd2, 2);
     const FormArgs<T> fa{nullptr, nullptr, nullptr};
     mark(P, 0);
     enqueue_bin_p2m<T>(P, g, rd, 1, x, qA, qB, site, lam, fa, n, S);
     using V4 = vec4_t<T>;
     k_leaf_src2<T><<<g.nleaf, kLeafThreads, src2_lds_bytes<T>(g.K), st>>>(
-        g, (const V4*)P->pos, P->perm, P->leaf_start, gphi, gF, P->dom, (V4*)P->adj_src2, (T*)P->mult,
-        P->leaf_part, (uint16_t*)P->msplit, P->mg.KP);
+        g, (const V4*)P->ws.pos, P->ws.perm, P->ws.leaf_start, gphi, gF, P->ws.dom, (V4*)P->ws.adj_src2, (T*)P->ws.mult,
+        P->ws.leaf_part, (uint16_t*)P->ws.msplit, P->mg.KP);
     enqueue_tree<T>(P, g, 2, false);
     mark(P, 6);
-    k_near_adj<T><<<g.nleaf, kAdjThreads, 0, st>>>(g, (const V4*)P->pos, (const V4*)P->adj_src2,
-                                                   P->leaf_start, P->perm, P->dom, (const T*)P->loc,
-                                                   P->gidx, (const T*)P->gcoef, (T*)P->adj_acc);
+    k_near_adj<T><<<g.nleaf, kAdjThreads, 0, st>>>(g, (const V4*)P->ws.pos, (const V4*)P->ws.adj_src2,
+                                                   P->ws.leaf_start, P->ws.perm, P->ws.dom, (const T*)P->ws.loc,
+                                                   P->gidx, (const T*)P->gcoef, (T*)P->ws.adj_acc);
     const unsigned nb = nblocks(n, 256);
-    k_adj_combine<T><<<nb, 256, 0, st>>>(g, n, S, x, qA, qB, site, lam, gphi, gF, gE_dev, gE, P->dom,
+    k_adj_combine<T><<<nb, 256, 0, st>>>(g, n, S, x, qA, qB, site, lam, gphi, gF, gE_dev, gE, P->ws.dom,
                                          P->excl_n > 0 ? P->excl_start : nullptr, P->excl_idx,
-                                         (const T*)P->adj_acc, phi, F, gx, gqA, gqB, P->cphi,
-                                         P->adj_cphi2, P->adj_part);
+                                         (const T*)P->ws.adj_acc, phi, F, gx, gqA, gqB, P->ws.cphi,
+                                         P->ws.adj_cphi2, P->ws.adj_part);
     mark(P, 7);
-    k_reduce<T><<<(unsigned)(1 + S), 256, 0, st>>>(g, 1, (int64_t)nb, P->adj_part, P->site_start,
-                                                    P->site_members, P->cphi, E ? E : P->E_tmp, dVdl,
-                                                    P->status, qA, qB, lam, fa, nullptr, P->reps, nullptr,
-                                                    nullptr, P->leaf_count, P->site_count, nullptr, 0,
-                                                    P->adj_cphi2, glam);
+    k_reduce<T><<<(unsigned)(1 + S), 256, 0, st>>>(g, 1, (int64_t)nb, P->ws.adj_part, P->ws.site_start,
+                                                    P->ws.site_members, P->ws.cphi, E ? E : P->ws.E_tmp, dVdl,
+                                                    P->status, qA, qB, lam, fa, nullptr, P->ws.reps, nullptr,
+                                                    nullptr, P->ws.leaf_count, P->ws.site_count, nullptr, 0,
+                                                    P->ws.adj_cphi2, glam);
     mark(P, -1);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return fail(P, FMM_E_HIP, std::string("kernel launch: ") + hipGetErrorString(e));
@@ -672,7 +799,7 @@ fmm_status fmm_plan_create(const fmm_params* prm, void* hip_stream, fmm_plan_t* 
     fmm_plan_s* P = new fmm_plan_s();
     P->prm = *prm;
     P->stream = (hipStream_t)hip_stream;
-    if (hipGetDevice(&P->device) != hipSuccess) {
+    if (hipGetDevice(&P->device) != hipSuccess || !scratch_lookup(P->device)) {
         delete P;
         return FMM_E_HIP;
     }
@@ -700,22 +827,6 @@ fmm_status fmm_plan_create(const fmm_params* prm, void* hip_stream, fmm_plan_t* 
     const size_t RT = (size_t)prm->max_replicas;
     P->R_max = prm->max_replicas;
     bool ok = true;
-    ok &= dev_alloc(P, &P->pos, N * 4 * ts);
-    ok &= dev_alloc(P, (void**)&P->perm, N * 4);
-    ok &= dev_alloc(P, (void**)&P->key, N * 4);
-    ok &= dev_alloc(P, (void**)&P->rank, N * 4);
-    ok &= dev_alloc(P, (void**)&P->leaf_count, RM * P->nleaf * 4);
-    ok &= dev_alloc(P, (void**)&P->leaf_start, RM * ((size_t)P->nleaf + 1) * 4);
-    ok &= dev_alloc(P, (void**)&P->leaf_order, RM * (size_t)P->nleaf * 4);
-    ok &= dev_alloc(P, (void**)&P->site_count, S * 4);
-    ok &= dev_alloc(P, (void**)&P->site_start, (S + 1) * 4);
-    ok &= dev_alloc(P, (void**)&P->site_rank, N * 4);
-    ok &= dev_alloc(P, (void**)&P->site_members, N * 4);
-    ok &= dev_alloc(P, &P->mult, RM * P->nbox * P->Kp * ts);
-    ok &= dev_alloc(P, &P->loc, RM * P->nbox * P->Kp * ts);
-    ok &= dev_alloc(P, (void**)&P->root_m, RM * K * 8);
-    ok &= dev_alloc(P, (void**)&P->root_l, RM * K * 8);
-    ok &= dev_alloc(P, (void**)&P->root_part, RM * 8 * K * 8);
     ok &= dev_alloc(P, &P->bankT, 343 * K * K * ts);
     ok &= dev_alloc(P, &P->m2mT, K * K * ts);  // octant 0; the others are its reflections
     ok &= dev_alloc(P, &P->l2lT, K * K * ts);
@@ -726,27 +837,8 @@ fmm_status fmm_plan_create(const fmm_params* prm, void* hip_stream, fmm_plan_t* 
     ok &= dev_alloc(P, (void**)&P->lat_seg, seg * 8);
     ok &= dev_alloc(P, (void**)&P->gidx, 3 * (size_t)P->Kg * 4 * 4);
     ok &= dev_alloc(P, &P->gcoef, 3 * (size_t)P->Kg * 4 * ts);
-    ok &= dev_alloc(P, (void**)&P->dom, RM * 8 * 8);
-    ok &= dev_alloc(P, (void**)&P->bbox_part, RM * kBboxBlocks * 6 * 8);
-    ok &= dev_alloc(P, (void**)&P->leaf_part, RM * P->nleaf * 2 * 8);
-    ok &= dev_alloc(P, (void**)&P->box_part, RM * P->nbox * 2 * 8);
-    ok &= dev_alloc(P, (void**)&P->leaf_energy, RM * P->nleaf * fmmk::kMaxSplit * 8);
-    ok &= dev_alloc(P, (void**)&P->reps, RM * sizeof(fmmk::RepDesc));
-    ok &= dev_alloc(P, (void**)&P->cphi, N * 8);
     ok &= dev_alloc(P, (void**)&P->status, 4 * 4);
-    ok &= dev_alloc(P, &P->F_tmp, N * 3 * ts);
-    if (prm->hamiltonian) {
-        ok &= dev_alloc(P, (void**)&P->hc_e, S * 8);
-        ok &= dev_alloc(P, (void**)&P->hc_dl, S * 8);
-        ok &= dev_alloc(P, (void**)&P->green, (fmmk::kKMax + 3 * fmmk::kKgMax) * 8);
-    }
-    ok &= dev_alloc(P, &P->phi_tmp, N * ts);
-    ok &= dev_alloc(P, (void**)&P->dVdl_tmp, S * 8);
-    ok &= dev_alloc(P, (void**)&P->E_tmp, RM * 8);
-    ok &= dev_alloc(P, &P->adj_src2, N * 4 * ts);
-    ok &= dev_alloc(P, &P->adj_acc, N * 8 * ts);
-    ok &= dev_alloc(P, (void**)&P->adj_cphi2, N * 8);
-    ok &= dev_alloc(P, (void**)&P->adj_part, ((N + 255) / 256) * 8);
+    if (prm->hamiltonian) ok &= dev_alloc(P, (void**)&P->green, (fmmk::kKMax + 3 * fmmk::kKgMax) * 8);
     if (!ok) {
         fmm_plan_destroy(P);
         return FMM_E_OOM;
@@ -909,15 +1001,7 @@ fmm_status fmm_plan_create(const fmm_params* prm, void* hip_stream, fmm_plan_t* 
         ok2 &= dev_alloc(P, (void**)&P->cstart, cstart.size() * sizeof(int16_t));
         const size_t nb = (size_t)343 * mg.RP * mg.KP;
         ok2 &= dev_alloc(P, &P->bank_mma, nb * esz * (P->m2l_mode == 3 ? 2 : 1));
-        if (P->m2l_mode == 3) {
-            const size_t ms = RM * ((size_t)P->nbox + 1) * 2 * mg.KP * 2;
-            ok2 &= dev_alloc(P, &P->msplit, ms);
-            // the zero row and the padding past K are never written again
-            if (ok2) ok2 &= hipMemset(P->msplit, 0, ms) == hipSuccess;
-            ok2 &= dev_alloc(P, &P->sign_tab, 8 * 4 * fmmk::kM2LMaxKs * 16);
-        }
-        if (mg.nchunk > 1)
-            ok2 &= dev_alloc(P, &P->m2l_part, RM * mg.nchunk * nt_all * P->Kp * P->tsz);
+        if (P->m2l_mode == 3) ok2 &= dev_alloc(P, &P->sign_tab, 8 * 4 * fmmk::kM2LMaxKs * 16);
         if (!ok2) {
             fmm_plan_destroy(P);
             return FMM_E_OOM;
@@ -1000,12 +1084,19 @@ fmm_status fmm_plan_create(const fmm_params* prm, void* hip_stream, fmm_plan_t* 
                                           hipFuncAttributeMaxDynamicSharedMemorySize,
                                           (int)src2_lds_bytes<float>((int)K));
     }
-    std::vector<double> dom0(8 * RM, 0.0);
-    up(P->dom, dom0.data(), dom0.size() * 8);
-    // counters start at zero; every evaluation's final reduction re-zeroes
-    // the ones it used
-    if (e == hipSuccess) e = hipMemset(P->leaf_count, 0, RM * (size_t)P->nleaf * 4);
-    if (e == hipSuccess) e = hipMemset(P->site_count, 0, (size_t)S * 4);
+    // the workspace: one arena for every per-evaluation buffer, cleared once
+    // (counters start at zero, and every evaluation's final reduction
+    // re-zeroes the ones it used; the bf16 split rows' zero row and padding
+    // past K are never written)
+    if (e == hipSuccess) {
+        const size_t bytes = ws_layout(P, N, S, RM, true, nullptr, nullptr);
+        if (!dev_alloc(P, &P->ws_arena, bytes)) {
+            fmm_plan_destroy(P);
+            return FMM_E_OOM;
+        }
+        ws_layout(P, N, S, RM, true, (char*)P->ws_arena, &P->ws);
+        e = hipMemset(P->ws_arena, 0, bytes);
+    }
     if (prm->hamiltonian) {
         // periodic pair potential: h of the unit cube to degree kPMax and the
         // coefficients of its gradient (degree kPMax - 1); zero for open cells
@@ -1118,6 +1209,52 @@ fmm_status fmm_eval(fmm_plan_t P, int64_t n, const void* x, const void* qA, cons
         return enqueue_eval<float>(P, rd, (const float*)x, (const float*)qA, (const float*)qB, site,
                                    lam, E, (float*)F, (float*)phi, dVdl);
     });
+}
+
+fmm_status fmm_eval_noalloc(fmm_plan_t P, int64_t n, const void* x, const void* qA, const void* qB,
+                            const int32_t* site, int64_t S, const double* lam, const double* box,
+                            double* E, void* F, void* phi, double* dVdl) {
+    fmm_status s = check_common(P, n, x, qA, qB, site, S, lam);
+    if (s != FMM_OK) return s;
+    double L = 0;
+    if ((s = check_box(P, box, &L)) != FMM_OK) return s;
+    void* base = scratch_address(P->device);
+    if (!base) return fail(P, FMM_E_HIP, "no static scratch address for this device");
+    const size_t need = ws_layout(P, n, S, 1, false, nullptr, nullptr);
+    if (need > kScratchBytes) {
+        char msg[160];
+        std::snprintf(msg, sizeof msg, "fmm_eval_noalloc: %zu bytes of scratch needed, the static "
+                      "scratch holds %zu (fewer atoms or a shallower tree)", need, kScratchBytes);
+        return fail(P, FMM_E_INVALID, msg);
+    }
+    P->err.clear();
+    Workspace sw;
+    ws_layout(P, n, S, 1, false, (char*)base, &sw);
+    const fmmk::RepDesc rd{0, n, 0, S, L, 0};
+    // what must start at zero: the leaf and site counters, the cube record
+    // and the bf16 split rows (the zero row and the padding past K); fill
+    // kernels, no memset nodes
+    hipStream_t st = P->stream;
+    fmmk::k_fill_i32<<<nblocks(P->nleaf, 256), 256, 0, st>>>(sw.leaf_count, P->nleaf, 0);
+    fmmk::k_fill_i32<<<nblocks(std::max<int64_t>(S, 1), 256), 256, 0, st>>>(sw.site_count,
+                                                                            std::max<int64_t>(S, 1), 0);
+    fmmk::k_fill_f64<<<1, 64, 0, st>>>(sw.dom, 8, 0.0);
+    if (sw.msplit) {
+        const int64_t words = (int64_t)(msplit_bytes(P, 1) / 4);
+        fmmk::k_fill_i32<<<(unsigned)std::min<int64_t>(1024, (words + 255) / 256), 256, 0, st>>>(
+            (int32_t*)sw.msplit, words, 0);
+    }
+    const Workspace own = P->ws;
+    P->ws = sw;
+    const RepSpan rs(&rd, 1);
+    if (P->fp64)
+        s = enqueue_eval<double>(P, rs, (const double*)x, (const double*)qA, (const double*)qB, site, lam,
+                                 E, (double*)F, (double*)phi, dVdl);
+    else
+        s = enqueue_eval<float>(P, rs, (const float*)x, (const float*)qA, (const float*)qB, site, lam, E,
+                                (float*)F, (float*)phi, dVdl);
+    P->ws = own;
+    return s;
 }
 
 fmm_status fmm_eval_adjoint(fmm_plan_t P, int64_t n, const void* x, const void* qA,

@@ -58,7 +58,7 @@ EXPORTS = ["fmm_plan_create", "fmm_eval", "fmm_eval_adjoint", "fmm_eval_batched"
            "fmm_sync_check", "fmm_last_error", "fmm_plan_destroy", "fmm_profile",
            "fmm_profile_select", "fmm_plan_info", "fmm_host_operator",
            "fmm_lambda_step", "fmm_lambda_dbo", "fmm_lambda_pfc", "fmm_set_exclusions",
-           "fmm_eval_adjoint_phi", "fmm_eval_adjoint_full"]
+           "fmm_eval_adjoint_phi", "fmm_eval_adjoint_full", "fmm_eval_noalloc"]
 PHASES = ["bin", "p2m", "m2m", "root", "m2l", "l2l", "near_far", "reduce"]
 
 _lib = None
@@ -84,6 +84,8 @@ def load_library(path: str = LIB_PATH):
     lib.fmm_plan_create.argtypes = [ctypes.POINTER(fmm_params), vp, ctypes.POINTER(vp)]
     lib.fmm_eval.restype = ctypes.c_int
     lib.fmm_eval.argtypes = [vp, i64, vp, vp, vp, vp, i64, vp, vp, vp, vp, vp, vp]
+    lib.fmm_eval_noalloc.restype = ctypes.c_int
+    lib.fmm_eval_noalloc.argtypes = [vp, i64, vp, vp, vp, vp, i64, vp, vp, vp, vp, vp, vp]
     lib.fmm_eval_adjoint.restype = ctypes.c_int
     lib.fmm_eval_adjoint.argtypes = [vp, i64, vp, vp, vp, vp, i64, vp, vp, vp,
                                      vp, vp, vp, vp, vp, vp, vp, vp]
@@ -302,6 +304,24 @@ class Plan:
         st = fmm_eval(self.handle, n, _ptr(x), _ptr(qA), _ptr(qB), _ptr(site), S, _ptr(lam), bp,
                       _ptr(out["E"]), _ptr(out["F"]), _ptr(out["phi"]), _ptr(out["dVdl"]))
         self._raise(st, "fmm_eval")
+        return out
+
+    def eval_noalloc(self, x, qA, qB, site, lam, box=None, out=None):
+        """Enqueue fmm_eval_noalloc (the evaluation of eval() with its scratch in
+        the library's static array); `out` as in eval()."""
+        import torch
+        n, S = self._inputs(x, qA, qB, site, lam)
+        if out is None:
+            opt = dict(device=self.device)
+            out = {"E": torch.empty(1, dtype=torch.float64, **opt),
+                   "F": torch.empty((n, 3), dtype=self.dtype, **opt),
+                   "phi": torch.empty(n, dtype=self.dtype, **opt),
+                   "dVdl": torch.empty(S, dtype=torch.float64, **opt)}
+        b, bp = self._box(box)
+        st = load_library().fmm_eval_noalloc(
+            self.handle, n, _ptr(x), _ptr(qA), _ptr(qB), _ptr(site), S, _ptr(lam), bp,
+            _ptr(out["E"]), _ptr(out["F"]), _ptr(out["phi"]), _ptr(out["dVdl"]))
+        self._raise(st, "fmm_eval_noalloc")
         return out
 
     def eval_adjoint(self, x, qA, qB, site, lam, gE, box=None):
