@@ -74,6 +74,25 @@ def measured_traffic(phase):
     return int(m.group(1)) if m else None
 
 
+def eval_bytes(n, S, depth, order, ts=4):
+    """Algorithmic HBM bytes of one evaluation outside the near-field and M2L
+    arithmetic: inputs read once (x, qA, qB, site: 24 B per atom), outputs
+    written once (F, phi: 16 B), the sorted particle array written and read
+    (2 x 16 B) with its permutation (2 x 4 B) and leaf keys (2 x 4 B), every
+    box's multipole and local expansion written and read (4 x Kp x 4 B) with
+    its bf16 hi/lo split (2 x 2 Kp x 2 B), the bf16 hi/lo operators of the 189
+    canonical translations read once (189 x 2 Kp' x K x 2 B, Kp' = K rounded to
+    32), and the sites' lambda and dV/dlambda."""
+    K = (order + 1) ** 2
+    Kp = (K + 3) // 4 * 4
+    Kb = (K + 31) // 32 * 32
+    nbox = sum(8 ** l for l in range(depth + 1))
+    per_atom = 24 + 16 + 32 + 8 + 8
+    boxes = nbox * (4 * Kp * ts + 2 * 2 * Kp * 2)
+    bank = 189 * 2 * Kb * K * 2
+    return n * per_atom + boxes + bank + 16 * S
+
+
 def m2l_translations(depth, periodic=True):
     lmin = 1 if periodic else 2
     return sum(189 * 8 ** l for l in range(lmin, depth + 1))
@@ -88,6 +107,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
     ap.add_argument("--no-batched", action="store_true", help="skip the replica-batch leg")
     ap.add_argument("--batched-steps", type=int, default=10)
+    ap.add_argument("--no-large", action="store_true", help="skip the 500,000-atom leg")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain 256 MiB device copy (3 times): the reference for "
                          "scaling the FETCH_SIZE / WRITE_SIZE counters")
@@ -168,6 +188,8 @@ def main():
     phase_ms = breakdown(plan, inp)
     dom = max(phase_ms, key=phase_ms.get)
     sec, dom_ms = timed(plan, inp, args.steps, args.warmup, roof_phase=dom)
+    # four more timed runs of the same K steps (no events): spread and median of five
+    rep = [sec] + [timed(plan, inp, args.steps, 0)[0] for _ in range(4)]
     plan32, inp32 = make("f32")
     sec32, _ = timed(plan32, inp32, args.fp64_steps, max(2, args.warmup // 4))
     phase_ms32 = breakdown(plan32, inp32)
@@ -306,8 +328,43 @@ def main():
             bplan.eval_batched(ao, so, *bin_)
         bplan.profile_stop()
         bprof = bplan.profile_read()
+        # the same batch with the depth and launch shapes picked by the
+        # autotuner (depth 3 or 4), replayed from a HIP graph
+        from paper_2410_01626_amd import autotune
+
+        def make_run(pl):
+            return lambda: pl.eval_batched(ao, so, *bin_)
+        make_run.max_sites = int(so[-1])
+        tune_res = autotune.tune_depth(make_run, (3, 4), 8, False, "bf16x3", int(ao[-1]),
+                                       replicas=len(reps), steps=3, device=dev)
+        gs_ = torch.cuda.Stream(dev)
+        tplan = fmm.Plan(tune_res["depth"], 8, periodic=False, precision="bf16x3",
+                         max_atoms=int(ao[-1]), max_sites=int(so[-1]), max_replicas=len(reps),
+                         device=dev, stream=gs_, graph=True, m2l_chunk=tune_res["m2l_chunk"],
+                         p2p_waves=tune_res["p2p_waves"])
+        nb_ = int(ao[-1])
+        tout = {"E": torch.empty(len(reps), dtype=torch.float64, device=dev),
+                "F": torch.empty((nb_, 3), dtype=torch.float32, device=dev),
+                "phi": torch.empty(nb_, dtype=torch.float32, device=dev),
+                "dVdl": torch.empty(int(so[-1]), dtype=torch.float64, device=dev)}
+        torch.cuda.synchronize(dev)
+        with torch.cuda.stream(gs_):
+            for _ in range(2):
+                tplan.eval_batched(ao, so, *bin_, out=tout)
+            gs_.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(args.batched_steps):
+                tplan.eval_batched(ao, so, *bin_, out=tout)
+            gs_.synchronize()
+            tsec = (time.perf_counter() - t0) / args.batched_steps
+        tuned = {"depth": tune_res["depth"], "m2l_chunk": tune_res["m2l_chunk"],
+                 "p2p_waves": tune_res["p2p_waves"], "depth_ms": tune_res.get("depth_ms"),
+                 "graph_replay": True, "batch_evals_per_s": 1.0 / tsec,
+                 "replica_evals_per_s": len(reps) / tsec, "ms_per_batch": tsec * 1e3}
+        tplan.close()
         batched = {"workload": "16 open replicas, 10,000-60,000 atoms (%d total), depth 3, p = 8, "
                                "pH 2-9" % int(ao[-1]),
+                   "tuned": tuned,
                    "batch_evals_per_s": 1.0 / bsec, "replica_evals_per_s": len(reps) / bsec,
                    "ms_per_batch": bsec * 1e3, "atoms_per_s": float(ao[-1]) / bsec,
                    "phase_ms": {k: (v[0] / v[1] if v[1] else 0.0) for k, v in bprof.items()}}
@@ -331,6 +388,80 @@ def main():
         batched["lambda_dynamics"] = {"md_steps_per_s": 1.0 / bmd, "ms_per_step": bmd * 1e3,
                                       "lambda_particles": int(so[-1])}
 
+    def wall(fn, steps, warm=3):
+        for _ in range(warm):
+            fn()
+        torch.cuda.synchronize(dev)
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            fn()
+        torch.cuda.synchronize(dev)
+        return (time.perf_counter() - t0) / steps
+
+    # site-count sweep on the same box (the paper: the cost of the charge
+    # interpolation does not grow with the number of titratable sites)
+    sweep = {}
+    for S_ in (0, 20, 200, 2000):
+        ds = workloads.with_sites(d, S_)
+        splan = fmm.Plan(depth, order, periodic=True, precision="bf16x3", max_atoms=n,
+                         max_sites=max(S_, 1), device=dev)
+        sin = (inp[0], inp[1], torch.tensor(ds["qB"], dtype=torch.float32, device=dev),
+               torch.tensor(ds["site"], dtype=torch.int32, device=dev),
+               torch.tensor(ds["lam"], dtype=torch.float64, device=dev))
+        tS = wall(lambda: splan.eval(*sin, box=d["box"]), args.steps, args.warmup)
+        sweep[str(S_)] = {"evals_per_s": 1.0 / tS, "ms_per_step": tS * 1e3,
+                          "site_atoms": int((ds["site"] >= 0).sum())}
+        splan.close()
+
+    # forward + backward at the 30k shape (FP32 positions and charges, upstream
+    # weight on E): fmm_eval then fmm_eval_adjoint (tree rebuilt in backward);
+    # and the one-pass adjoint with weights on E, phi and F
+    gE1 = torch.ones(1, dtype=torch.float64, device=dev)
+    rng_ = np.random.default_rng(5)
+    gphi_ = torch.tensor(rng_.normal(0, 1, n), dtype=torch.float32, device=dev)
+    gF_ = torch.tensor(rng_.normal(0, 1, (n, 3)), dtype=torch.float32, device=dev)
+
+    def fwd_bwd():
+        plan.eval(*inp, box=d["box"])
+        plan.eval_adjoint(*inp, gE1, box=d["box"])
+
+    t_fb = wall(fwd_bwd, args.steps // 2)
+    t_full = wall(lambda: plan.eval_adjoint_full(*inp, gE=gE1, gphi=gphi_, gF=gF_, box=d["box"]),
+                  args.steps // 2)
+    diff = {"workload": "same box, forward (fmm_eval) + backward (fmm_eval_adjoint, weight on E)",
+            "fwd_bwd_per_s": 1.0 / t_fb, "ms_per_fwd_bwd": t_fb * 1e3,
+            "adjoint_full_per_s": 1.0 / t_full, "ms_per_adjoint_full": t_full * 1e3,
+            "adjoint_full": "fmm_eval_adjoint_full, weights on E, phi and F (one tree pass, "
+                            "second sources in expansion slot 1)"}
+
+    # the 500,000-atom periodic box (17 nm, depth 5, p = 10): forward and
+    # forward + adjoint
+    large = None
+    if not args.no_large:
+        dl = workloads.large_box()
+        nl_, Sl_ = dl["x"].shape[0], dl["lam"].size
+        lplan5 = fmm.Plan(dl["depth"], dl["order"], periodic=True, precision="bf16x3",
+                          max_atoms=nl_, max_sites=Sl_, device=dev)
+        lin = (torch.tensor(dl["x"], dtype=torch.float32, device=dev),
+               torch.tensor(dl["qA"], dtype=torch.float32, device=dev),
+               torch.tensor(dl["qB"], dtype=torch.float32, device=dev),
+               torch.tensor(dl["site"], dtype=torch.int32, device=dev),
+               torch.tensor(dl["lam"], dtype=torch.float64, device=dev))
+        t_l = wall(lambda: lplan5.eval(*lin, box=dl["box"]), 10)
+        t_la = wall(lambda: lplan5.eval_adjoint(*lin, gE1, box=dl["box"]), 10)
+        lplan5.profile_start(3)
+        for _ in range(3):
+            lplan5.eval(*lin, box=dl["box"])
+        lplan5.profile_stop()
+        lprof = lplan5.profile_read()
+        large = {"workload": "large_box: 500,000 atoms (160,000 waters + 20,000-atom cluster), "
+                             "periodic 17 nm, 200 sites, depth 5, p = 10, bf16x3 M2L",
+                 "evals_per_s": 1.0 / t_l, "ms_per_eval": t_l * 1e3,
+                 "fwd_adjoint_per_s": 1.0 / t_la, "ms_per_fwd_adjoint": t_la * 1e3,
+                 "atoms_per_s": nl_ / t_l,
+                 "phase_ms": {k: (v[0] / v[1] if v[1] else 0.0) for k, v in lprof.items()}}
+        lplan5.close()
+
     # the dominant kernel's work over its duration measured inside the timed region
     pairs = p2p_pairs(leaf_counts(d["x"], box, depth))
     n_m2l = m2l_translations(depth)
@@ -351,14 +482,43 @@ def main():
                 "unit": "GB/s", "frac": None, "traffic": None}
 
     cpu = None
+    errors = None
     if not args.no_cpu:
         import oracle
         t0 = time.perf_counter()
-        oracle.solve(d["x"], d["qA"], d["qB"], d["site"], d["lam"], box=d["box"], periodic=True)
+        ref = oracle.solve(d["x"], d["qA"], d["qB"], d["site"], d["lam"], box=d["box"],
+                           periodic=True)
         t1 = time.perf_counter()
         cpu = {"value": 1.0 / (t1 - t0), "unit": "evals/s", "cores": oracle.num_threads(),
-               "kind": "oracle",
+               "nproc": len(os.sched_getaffinity(0)), "kind": "oracle",
                "sample": "one full FP64 Ewald evaluation of the 30,000-atom box (all atoms)"}
+        # each plan's error against that oracle result (relative RMS of F and
+        # phi, energy error over 1/2 sum |q phi|, max dV/dlambda error over
+        # the RMS of dV/dlambda)
+        errors = {}
+        for name_, (pl_, in_) in (("bf16x3", (plan, inp)), ("f32", (plan32, inp32)),
+                                  ("fp64", (plan64, inp64))):
+            o = pl_.eval(*in_, box=d["box"])
+            torch.cuda.synchronize(dev)
+            F_ = o["F"].double().cpu().numpy()
+            p_ = o["phi"].double().cpu().numpy()
+            dv = ref["dVdl"]
+            errors[name_] = {
+                "F": float(np.sqrt(np.sum((F_ - ref["F"]) ** 2) / np.sum(ref["F"] ** 2))),
+                "phi": float(np.sqrt(np.sum((p_ - ref["phi"]) ** 2) / np.sum(ref["phi"] ** 2))),
+                "E": float(abs(o["E"].item() - ref["E"]) / (0.5 * np.sum(np.abs(ref["q"] * ref["phi"])))),
+                "dVdl": float(np.abs(o["dVdl"].cpu().numpy() - dv).max() / np.sqrt(np.mean(dv ** 2)))}
+
+    # whole evaluation against its ideal time: each phase at its own ceiling
+    # (near field: FP32 vector; M2L: bf16 matrix cores, three products per
+    # translation; every other byte once at the HBM rate)
+    tree_bytes = eval_bytes(n, S, depth, order)
+    t_ideal = {"near_field_us": 1e6 * 20.0 * pairs / PEAK["fp32_vector"],
+               "m2l_us": 1e6 * 3 * 2.0 * K * K * n_m2l / PEAK["bf16_mfma"],
+               "tree_and_io_us": 1e6 * tree_bytes / PEAK["hbm"]}
+    t_ideal_us = sum(t_ideal.values())
+    eval_roof = {"t_ideal_us": t_ideal_us, "t_measured_us": sec * 1e6, "frac": t_ideal_us / (sec * 1e6),
+                 "parts": t_ideal, "tree_and_io_bytes": tree_bytes}
 
     res = {
         "metric": "E+F+dV/dlambda evals/s at 30k atoms p=8 (mixed vs FP64 FMM), roofline %",
@@ -392,6 +552,13 @@ def main():
                                    "waters excluded (54,000 partner entries)"},
         "lambda_dynamics": lam_dyn,
         "batched": batched,
+        "repeats": {"values": [1.0 / t for t in rep], "median": 1.0 / float(np.median(rep)),
+                    "steps_each": args.steps},
+        "errors": errors,
+        "eval_roofline": eval_roof,
+        "site_sweep": sweep,
+        "differentiation": diff,
+        "large": large,
         "phase_ms": phase_ms,
         "phase_ms_fp64": phase_ms64,
         "phase_ms_f32": phase_ms32,

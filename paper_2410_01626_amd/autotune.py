@@ -1,12 +1,14 @@
-"""Autotuner for the two launch-shape knobs of a plan.
+"""Autotuner for the tree depth and the two launch-shape knobs of a plan.
 
 * ``m2l_chunk``: translation offsets handled per matrix-core M2L work-group
   (fewer offsets per group = more groups in flight, more partial sums).
 * ``p2p_waves``: wavefronts per leaf in the near-field kernel (4, 8 or 16).
 
 The two knobs act on different phases, so each is tuned on its own phase time,
-measured with HIP events on the plan's stream (fmm_profile).  Results are
-cached in a JSON file keyed by GPU architecture and problem shape.
+measured with HIP events on the plan's stream (fmm_profile).  ``tune_depth``
+first picks the depth from candidate depths by whole-evaluation time, then
+tunes the two knobs at that depth.  Results are cached in a JSON file keyed by
+GPU architecture and problem shape.
 """
 from __future__ import annotations
 
@@ -85,6 +87,62 @@ def tune(make_run, depth, order, periodic, precision, n_atoms, replicas=1, steps
            "p2p_waves": min(wave_t, key=wave_t.get),
            "m2l_ms": {str(k): v for k, v in chunk_t.items()},
            "near_far_ms": {str(k): v for k, v in wave_t.items()}}
+    db = _load(cache)
+    db[key] = res
+    try:
+        with open(cache + ".tmp", "w") as f:
+            json.dump(db, f, indent=1, sort_keys=True)
+        os.replace(cache + ".tmp", cache)
+    except OSError:
+        pass
+    return res
+
+
+def _eval_time(plan, run, steps):
+    """Seconds per evaluation (wall clock, stream synchronised) after a warm-up."""
+    import time
+
+    import torch
+    run()
+    torch.cuda.synchronize(plan.device)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        run()
+    torch.cuda.synchronize(plan.device)
+    return (time.perf_counter() - t0) / steps
+
+
+def tune_depth(make_run, depths, order, periodic, precision, n_atoms, replicas=1, steps=5,
+               cache=DEFAULT_CACHE, device=None, verbose=False):
+    """Pick the tree depth among `depths` by whole-evaluation time (default
+    launch shapes), then the launch shapes at that depth (tune).  The depth
+    trades near-field pairs (fewer at a deeper tree) against translations and
+    tree passes (more).  Returns tune()'s dict with "depth" and the measured
+    "depth_ms" added; cached like tune()."""
+    import torch
+
+    from . import fmm
+    dev = torch.device(device) if device is not None else torch.device("cuda", 0)
+    arch = torch.cuda.get_device_properties(dev).gcnArchName.split(":")[0]
+    key = _key(arch, n_atoms, -1, order, periodic, precision, replicas) + "|depths" + ",".join(
+        str(d) for d in depths)
+    db = _load(cache)
+    if key in db:
+        return db[key]
+    base = dict(periodic=periodic, precision=precision, max_atoms=n_atoms,
+                max_sites=make_run.max_sites, max_replicas=replicas, device=dev)
+    depth_t = {}
+    for d in depths:
+        plan = fmm.Plan(d, order, **base)
+        depth_t[d] = _eval_time(plan, make_run(plan), steps)
+        plan.close()
+        if verbose:
+            print("depth %d: %.1f us" % (d, 1e6 * depth_t[d]), flush=True)
+    best = min(depth_t, key=depth_t.get)
+    res = dict(tune(make_run, best, order, periodic, precision, n_atoms, replicas, steps, cache,
+                    device, verbose))
+    res["depth"] = best
+    res["depth_ms"] = {str(k): 1e3 * v for k, v in depth_t.items()}
     db = _load(cache)
     db[key] = res
     try:

@@ -400,8 +400,11 @@ class Plan:
         self._raise(st, "fmm_eval_adjoint_full")
         return out
 
-    def eval_batched(self, atom_off, site_off, x, qA, qB, site_local, lam, boxes=None):
-        """Enqueue fmm_eval_batched over R replicas (offsets are host sequences)."""
+    def eval_batched(self, atom_off, site_off, x, qA, qB, site_local, lam, boxes=None,
+                     out=None):
+        """Enqueue fmm_eval_batched over R replicas (offsets are host sequences);
+        `out` may hold preallocated outputs (reused pointers let a graph plan
+        replay)."""
         import torch
         ao = np.ascontiguousarray(atom_off, dtype=np.int64)
         so = np.ascontiguousarray(site_off, dtype=np.int64)
@@ -409,11 +412,12 @@ class Plan:
         n, S = self._inputs(x, qA, qB, site_local, lam)
         if ao[-1] != n or so[-1] != S:
             raise ValueError("offsets do not match the concatenated arrays")
-        opt = dict(device=self.device)
-        out = {"E": torch.empty(R, dtype=torch.float64, **opt),
-               "F": torch.empty((n, 3), dtype=self.dtype, **opt),
-               "phi": torch.empty(n, dtype=self.dtype, **opt),
-               "dVdl": torch.empty(S, dtype=torch.float64, **opt)}
+        if out is None:
+            opt = dict(device=self.device)
+            out = {"E": torch.empty(R, dtype=torch.float64, **opt),
+                   "F": torch.empty((n, 3), dtype=self.dtype, **opt),
+                   "phi": torch.empty(n, dtype=self.dtype, **opt),
+                   "dVdl": torch.empty(S, dtype=torch.float64, **opt)}
         if self.periodic:
             bx = np.ascontiguousarray(np.asarray(boxes, dtype=np.float64).reshape(R, 3))
             bp = ctypes.c_void_p(bx.ctypes.data)

@@ -236,7 +236,8 @@ def _solvated(seed, edge, n_water, n_cluster, r_cluster, n_sites, lattice_n,
             site[oxy[s]] = s
             qB[oxy[s]] = qA[oxy[s]] - sigma[s]
     lam = rng.uniform(0, 1, n_sites)
-    return _finish(name, x, qA, qB, site, lam, [edge] * 3, True, depth, order)
+    return _finish(name, x, qA, qB, site, lam, [edge] * 3, True, depth, order,
+                   n_water=n_water, n_cluster=n_cluster)
 
 
 def water_box(seed=SEED_BASE + 2, buffers=False, depth=3, order=8):
@@ -249,6 +250,38 @@ def small_water_box(seed=SEED_BASE + 7, depth=2, order=6):
     """2,300 atoms: 700 waters + a 200-atom cluster, periodic 3 nm cube, 4 sites
     (the water box recipe at a size the oracle finishes in seconds)."""
     return _solvated(seed, 3.0, 700, 200, 0.9, 4, 10, depth, order, "small_water_box")
+
+
+def with_sites(d, n_sites, seed=SEED_BASE + 8, max_cluster_sites=500):
+    """The same solvated box with its titratable sites redrawn: n_sites sites,
+    the first min(n_sites, max_cluster_sites) of four nearest cluster atoms
+    (as in the water box recipe), the rest whole water molecules (three-atom
+    sites, in molecule order); qB = qA + sigma w per site (w ~ Dirichlet,
+    sigma = +-1), lambda ~ U(0, 1).  Positions and qA are unchanged, so only
+    the site bookkeeping differs between the boxes of a site-count sweep."""
+    rng = np.random.default_rng(seed)
+    x, qA = d["x"], d["qA"]
+    n = x.shape[0]
+    n_water, n_cluster = d["n_water"], d["n_cluster"]
+    off = 3 * n_water
+    site = np.full(n, -1, dtype=np.int32)
+    qB = qA.astype(np.float64).copy()
+    n_cl = min(n_sites, max_cluster_sites)
+    n_w = n_sites - n_cl
+    if n_w > n_water:
+        raise ValueError("more sites than the box can hold")
+    groups = []
+    if n_cl:
+        groups += list(_pick_sites(rng, x[off:off + n_cluster], np.arange(n_cluster), n_cl) + off)
+    for k in range(n_w):
+        groups.append(np.arange(3 * k, 3 * k + 3))
+    for s, idx in enumerate(groups):
+        w = rng.dirichlet(np.ones(idx.size))
+        site[idx] = s
+        qB[idx] = qA[idx] + rng.choice([-1.0, 1.0]) * w
+    lam = rng.uniform(0, 1, n_sites)
+    return _finish(d["name"] + "_S%d" % n_sites, x, qA, qB, site, lam, d["box"], d["periodic"],
+                   d["depth"], d["order"], n_water=n_water, n_cluster=n_cluster)
 
 
 def water_exclusions(n_water, n_atoms):

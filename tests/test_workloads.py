@@ -62,3 +62,21 @@ def test_buffers_keep_total_charge():
         m = d["site"] == s
         assert m.sum() == 5
         assert abs((d["qB"] - d["qA"])[m].sum()) < 1e-6
+
+
+def test_site_count_sweep_boxes():
+    """with_sites keeps positions and qA and draws the requested number of
+    sites: four-atom cluster sites first, then whole waters, each changing
+    its charge by +-1 in total."""
+    d = W.water_box()
+    for S in (0, 20, 200, 2000):
+        e = W.with_sites(d, S)
+        assert e["lam"].size == S
+        np.testing.assert_array_equal(e["x"], d["x"])
+        np.testing.assert_array_equal(e["qA"], d["qA"])
+        assert set(np.unique(e["site"])) <= set(range(-1, S))
+        for s in range(S):
+            m = e["site"] == s
+            assert m.sum() in (3, 4)
+            assert abs(abs(float(np.sum(e["qB"][m].astype(np.float64) - e["qA"][m]))) - 1.0) < 1e-6
+        assert np.all(e["qB"][e["site"] < 0] == e["qA"][e["site"] < 0])
