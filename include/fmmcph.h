@@ -46,9 +46,10 @@
  * host before anything is enqueued; on error the call returns a non-zero
  * status, enqueues nothing and leaves the outputs untouched, and
  * fmm_last_error() describes the problem.  With params.check = 1 the kernels
- * also flag non-finite inputs and site indices outside [-1, S); such flags are
- * reported by fmm_sync_check().  Without check the result for such inputs is
- * undefined.
+ * also flag non-finite inputs, site indices outside [-1, S) and coincident
+ * atoms (two atoms at one position, periodic images included: their pair term
+ * is infinite); such flags are reported by fmm_sync_check().  Without check
+ * the result for such inputs is undefined (a coincident pair is skipped).
  */
 #ifndef FMMCPH_H
 #define FMMCPH_H
@@ -68,7 +69,8 @@ typedef enum {
     FMM_E_HIP = 3,          /* a HIP runtime call failed */
     FMM_E_UNSUPPORTED = 4,  /* valid but unsupported (non-cubic periodic box, ...) */
     FMM_E_NONFINITE = 5,    /* check mode: non-finite input seen by a kernel */
-    FMM_E_SITE = 6          /* check mode: site index outside [-1, S) */
+    FMM_E_SITE = 6,         /* check mode: site index outside [-1, S) */
+    FMM_E_COINCIDENT = 7    /* check mode: two atoms at the same position */
 } fmm_status;
 
 typedef enum { FMM_OPEN = 0, FMM_PERIODIC = 1 } fmm_boundary;
@@ -267,7 +269,7 @@ fmm_status fmm_eval_tautomer_batched(fmm_plan_t plan, int32_t R, const int64_t* 
                                      void* F, void* phi, double* dVdl_p, double* dVdl_t);
 
 /* Wait for the plan's stream and report device-side check flags raised since
- * the previous call (FMM_E_NONFINITE, FMM_E_SITE), or FMM_E_HIP. */
+ * the previous call (FMM_E_NONFINITE, FMM_E_SITE, FMM_E_COINCIDENT), or FMM_E_HIP. */
 fmm_status fmm_sync_check(fmm_plan_t plan);
 
 /* Human-readable description of the last error on this plan (never NULL). */
@@ -358,7 +360,15 @@ int64_t fmm_host_operator(int32_t order_p, int32_t which, double* out);
  *         ((p0 + p1)/2, B), (p1, y1), (p1 + 0.3, y1 + 30) with slopes -300, 0,
  *         0, 0, 300 per unit lambda, continued linearly beyond the end knots
  *         plus a confining 10^4 d^2 (d the distance past the end knot), from
- *         dwp[4 c ..] = (B, p0, p1, y1) (dwp NULL = none). */
+ *         dwp[4 c ..] = (B, p0, p1, y1) (dwp NULL = none).
+ * Tautomer coordinates (pKa NaN and a partner, the site's protonation
+ * coordinate) may carry a second barrier: with dwp2 (C x 2, NULL = none),
+ * V_dw takes (B, y1) = (dwp2[2 c], dwp2[2 c + 1]) instead while the site is
+ * deprotonated, lambda_partner >= 1/2 (lambda = 0 is protonated; "Dynamic
+ * Barrier and Well Optimization": the tautomeric force nearly vanishes in one
+ * protonation state, so its barrier is tuned separately); the wells p0, p1
+ * are shared.  The switch is a step in lambda_partner: it adds no force on
+ * the partner. */
 typedef struct {
     double mass;         /* lambda-particle mass, u (the paper uses 60) */
     double dt;           /* time step, ps */
@@ -385,13 +395,15 @@ typedef struct {
  * the sum of V_pH + V_dw at lam.  stats_w (C x 5: steps, steps near 0, sum of
  * lambda near 0, steps near 1, sum near 1) and stats_b (C x 2: steps, steps
  * with near0 <= lambda <= near1), both optional, accumulate the DBO block
- * statistics of lam. */
+ * statistics of lam; with stats_b2 (C x 2, needs dwp2 and stats_b) the
+ * barrier statistics of tautomer coordinates in their second state go there
+ * instead.  dwp2 needs dwp and partner. */
 fmm_status fmm_lambda_step(void* hip_stream, int32_t R, const int32_t* coord_off, int64_t C,
                            const fmm_lambda_params* prm, int32_t first, const double* lam,
                            double* lam_new, double* v, const double* dvdl, const int32_t* partner,
                            const double* pka, const double* ph, const double* mm, const double* dwp,
                            const double* noise, double* stats_w, double* stats_b, double* kin,
-                           double* e_bias);
+                           double* e_bias, const double* dwp2, double* stats_b2);
 
 /* Dynamic Barrier and Well Optimization ("Dynamic Barrier and Well
  * Optimization"); NULL = the paper's values {0.2, 0.8, 0.7, 0.03, 0.5, 0.08,
@@ -413,11 +425,15 @@ typedef struct {
  * statistics it used.  With pfc = 1 every coordinate whose well or barrier
  * moved gets the partition function correction below.  adjusted[c]
  * (optional) is set to 1 for a moved coordinate, else 0 (for censoring the
- * trajectory after a change). */
+ * trajectory after a change).  With dwp2 (then partner, and stats_b2 for
+ * mode bit 1, are required) a tautomer coordinate's second barrier moves by
+ * the same rule from stats_b2, and the correction also gives the second
+ * state its own y1 (dwp2[2 c + 1]). */
 fmm_status fmm_lambda_dbo(void* hip_stream, int32_t R, const int32_t* coord_off, int64_t C,
                           int32_t mode, int32_t pfc, const fmm_dbo_params* prm, double temperature,
                           const double* pka, const double* ph, double* dwp, double* stats_w,
-                          double* stats_b, int32_t* adjusted);
+                          double* stats_b, int32_t* adjusted, const int32_t* partner, double* dwp2,
+                          double* stats_b2);
 
 /* Partition function correction ("Partition Function Correction") of every
  * coordinate: sets y1 = dwp[4 c + 3] so that the free energy of
@@ -426,9 +442,12 @@ fmm_status fmm_lambda_dbo(void* hip_stream, int32_t R, const int32_t* coord_off,
  * ln(10) k_B T (pKa - pH) (0 without pKa); Gauss-Legendre quadrature on the
  * spline pieces and a safeguarded regula falsi on y1 in [-200, 200] kJ/mol.  The free energy
  * grows with y1 but is bounded (the barrier-top part of [1/2, 1] does not
- * move with y1): a target out of reach leaves y1 at the nearer end. */
+ * move with y1): a target out of reach leaves y1 at the nearer end.  With
+ * dwp2 (and partner) tautomer coordinates also get y1 of their second state,
+ * from (dwp2[2 c], p0, p1). */
 fmm_status fmm_lambda_pfc(void* hip_stream, int32_t R, const int32_t* coord_off, int64_t C,
-                          double temperature, const double* pka, const double* ph, double* dwp);
+                          double temperature, const double* pka, const double* ph, double* dwp,
+                          const int32_t* partner, double* dwp2);
 
 #ifdef __cplusplus
 }

@@ -601,7 +601,7 @@ fmm_status enqueue_eval(fmm_plan_t P, RepSpan rd, const T* x,
         k_near_far<T, NWV><<<dim3(g.nleaf * P->p2p_split, R), 64 * NWV, 0, st>>>(               \
             g, P->p2p_split, reps, pos, P->ws.leaf_start, P->ws.perm, P->ws.dom, loc, P->gidx,              \
             (const T*)P->gcoef, qA, qB, site, phi, F, P->ws.leaf_energy, P->ws.cphi, fa.qC != nullptr,   \
-            order);                                                                                \
+            order, P->status);                                                                     \
         break;
         FMM_NEAR(4)
         FMM_NEAR(8)
@@ -1446,6 +1446,8 @@ fmm_status fmm_sync_check(fmm_plan_t P) {
         return fail(P, FMM_E_HIP, "status reset failed");
     if (st[0] & fmmk::kStatusSite) return fail(P, FMM_E_SITE, "site index outside [-1, n_sites)");
     if (st[0] & fmmk::kStatusNonFinite) return fail(P, FMM_E_NONFINITE, "non-finite input");
+    if (st[0] & fmmk::kStatusCoincident)
+        return fail(P, FMM_E_COINCIDENT, "two atoms at the same position (after the periodic wrap)");
     return FMM_OK;
 }
 

@@ -18,6 +18,7 @@ constexpr double kPi = 3.14159265358979323846;
 // status[0]: errors raised in check mode; status[1]: informational bits
 constexpr int32_t kStatusNonFinite = 1;
 constexpr int32_t kStatusSite = 2;
+constexpr int32_t kStatusCoincident = 4;  // two atoms at one position (after the periodic wrap)
 constexpr int32_t kInfoBigLeaf = 1;  // a leaf above kSortCap kept its atomic order
 constexpr int32_t kInfoBigSite = 2;  // a site above kSiteCap summed in atomic order
 

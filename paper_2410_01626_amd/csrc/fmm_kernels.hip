@@ -1777,7 +1777,7 @@ __global__ __launch_bounds__(64 * kNW) void k_near_far(
     const T* __restrict__ qA, const T* __restrict__ qB, const int32_t* __restrict__ site,
     T* __restrict__ phi_out, T* __restrict__ F_out,
     double* __restrict__ leaf_energy_all, double* __restrict__ cphi, int unit_dq,
-    const int32_t* __restrict__ leaf_order_all) {
+    const int32_t* __restrict__ leaf_order_all, int32_t* __restrict__ status) {
     constexpr int NT = 64 * kNW;
     // sources staged per pass: the whole 27-leaf neighbourhood of a typical leaf
     constexpr int CAP = sizeof(T) == 4 ? 2048 : 1024;
@@ -2051,6 +2051,19 @@ __global__ __launch_bounds__(64 * kNW) void k_near_far(
             sweep(jb, min(je, own_b), std::false_type{});
             sweep(max(jb, own_b), min(je, own_e), std::true_type{});
             sweep(max(jb, own_e), je, std::false_type{});
+            if (g.check && tv) {
+                // check mode: a zero distance to any source of the own leaf
+                // other than the target itself is a coincident pair
+                const int self_j = nb_pre[13] + ta + tj - s0;
+                const int j0 = max(jb, own_b), j1 = min(je, own_e);
+                bool bad = false;
+                for (int j = j0 + ((grp - (j0 - jb)) & (ngrp - 1)); j < j1; j += ngrp) {
+                    const vec4_t<T> s = tile[j];
+                    const T dx = me.x - s.x, dy = me.y - s.y, dz = me.z - s.z;
+                    bad |= j != self_j && !(dx * dx + dy * dy + dz * dz > T(0));
+                }
+                if (bad) atomicOr(&status[0], kStatusCoincident);
+            }
         }
         // sites and charges of the first NT targets (for the outputs), in
         // flight during the far-field evaluation

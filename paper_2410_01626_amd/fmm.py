@@ -22,8 +22,10 @@ FMM_E_HIP = 3
 FMM_E_UNSUPPORTED = 4
 FMM_E_NONFINITE = 5
 FMM_E_SITE = 6
+FMM_E_COINCIDENT = 7
 STATUS_NAMES = {0: "FMM_OK", 1: "FMM_E_INVALID", 2: "FMM_E_OOM", 3: "FMM_E_HIP",
-                4: "FMM_E_UNSUPPORTED", 5: "FMM_E_NONFINITE", 6: "FMM_E_SITE"}
+                4: "FMM_E_UNSUPPORTED", 5: "FMM_E_NONFINITE", 6: "FMM_E_SITE",
+                7: "FMM_E_COINCIDENT"}
 
 FMM_OPEN = 0
 FMM_PERIODIC = 1
@@ -120,11 +122,11 @@ def load_library(path: str = LIB_PATH):
     lib.fmm_set_exclusions.restype = ctypes.c_int
     lib.fmm_set_exclusions.argtypes = [vp, i64, vp, vp]
     lib.fmm_lambda_step.restype = ctypes.c_int
-    lib.fmm_lambda_step.argtypes = [vp, i32, vp, i64, vp, i32] + [vp] * 14
+    lib.fmm_lambda_step.argtypes = [vp, i32, vp, i64, vp, i32] + [vp] * 16
     lib.fmm_lambda_dbo.restype = ctypes.c_int
-    lib.fmm_lambda_dbo.argtypes = [vp, i32, vp, i64, i32, i32, vp, ctypes.c_double] + [vp] * 6
+    lib.fmm_lambda_dbo.argtypes = [vp, i32, vp, i64, i32, i32, vp, ctypes.c_double] + [vp] * 9
     lib.fmm_lambda_pfc.restype = ctypes.c_int
-    lib.fmm_lambda_pfc.argtypes = [vp, i32, vp, i64, ctypes.c_double, vp, vp, vp]
+    lib.fmm_lambda_pfc.argtypes = [vp, i32, vp, i64, ctypes.c_double, vp, vp, vp, vp, vp]
     _lib = lib
     return lib
 

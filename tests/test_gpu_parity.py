@@ -175,6 +175,30 @@ def test_check_mode_reports_bad_input():
     assert e.value.status == fmm.FMM_E_NONFINITE
 
 
+@pytest.mark.parametrize("periodic", [False, True])
+def test_check_mode_reports_coincident_atoms(periodic):
+    """Two atoms at one position (periodic: an atom and another one whole cell
+    away, which the wrap puts on the same point) are flagged in check mode;
+    valid inputs, with one or several near-field blocks per leaf, are not."""
+    from paper_2410_01626_amd import fmm
+    if periodic:
+        d = W.tiny_periodic(16, n=300, edge=1.5, n_sites=2, depth=2, order=4)
+    else:
+        d = W.random_open(16, n=300, edge=1.5, n_sites=2, depth=2, order=4)
+    for split in (1, 3):
+        run(d, "fp64", check=True, p2p_split=split)  # no flag
+        run(d, "f32", check=True, p2p_split=split)
+    x = d["x"].copy()
+    x[123] = np.round(x[123] * 4096) / 4096  # on a grid where +-L stays exact in FP32
+    x[7] = x[123] + (np.array([1.5, 0.0, -1.5]) if periodic else 0.0)
+    d2 = dict(d)
+    d2["x"] = x
+    for prec in ("fp64", "f32"):
+        with pytest.raises(fmm.FmmError) as e:
+            run(d2, prec, check=True, p2p_split=2)
+        assert e.value.status == fmm.FMM_E_COINCIDENT
+
+
 # ---------------------------------------------------------------- matrix-core M2L
 
 @pytest.mark.parametrize("prec", ["fp64", "f32", "bf16x3"])
