@@ -45,6 +45,13 @@ Readings of the paper taken here (each also listed in the design notes):
     exceeds the tolerance, its total offset from the ideal end point clamped
     to +-max_shift; the barrier moves one step down (up) when the in-transition
     fraction is below (above) target -+ tolerance, clamped to [B_min, B_max].
+  * Tautomer coordinates (no pKa, a partner: the site's protonation
+    coordinate) may carry a second barrier (dwp2 = (B2, y1_2) per coordinate):
+    V_dw uses (B, y1) while the site is protonated (partner lambda < 1/2,
+    lambda = 0 being protonated) and (B2, y1_2) while it is deprotonated; the
+    in-transition statistics of the two states go to stats_b and stats_b2,
+    and DBO adjusts each barrier from its own statistics; the correction
+    gives each state its own y1.  The wells are shared.
 """
 from __future__ import annotations
 
@@ -100,6 +107,28 @@ def hermite(x, y, s, t):
     return V, dV
 
 
+def second_state(lam, partner, pka, dwp2):
+    """Per coordinate: True where the second barrier applies (a tautomer
+    coordinate, i.e. no pKa and a partner, whose partner is deprotonated,
+    lambda_partner >= 1/2); all False without dwp2."""
+    lam = np.asarray(lam, dtype=np.float64)
+    if dwp2 is None or partner is None:
+        return np.zeros(lam.size, dtype=bool)
+    partner = np.asarray(partner)
+    taut = (partner >= 0) & np.isnan(np.asarray(pka, dtype=np.float64))
+    return taut & (lam[np.maximum(partner, 0)] >= 0.5)
+
+
+def dw_params(dwp, dwp2, second):
+    """C x 4 (B, p0, p1, y1) in force: the second set (B2, p0, p1, y1_2) where
+    `second`."""
+    d = np.array(dwp, dtype=np.float64)
+    if dwp2 is not None:
+        d[second, 0] = np.asarray(dwp2)[second, 0]
+        d[second, 3] = np.asarray(dwp2)[second, 1]
+    return d
+
+
 def v_dw(dwp, lam):
     """V_dw and dV_dw/dlambda per coordinate; dwp is C x 4 (B, p0, p1, y1)."""
     lam = np.asarray(lam, dtype=np.float64)
@@ -132,15 +161,16 @@ def mm_slope(mm, lam, partner):
     return -G
 
 
-def lambda_forces(lam, dvdl, partner, pka, ph_c, mm, dwp, T):
+def lambda_forces(lam, dvdl, partner, pka, ph_c, mm, dwp, T, dwp2=None):
     """Force -dH/dlambda on every coordinate (eq 1 and eq 3) and the per-
     coordinate bias energy V_pH + V_dw; dwp None: no double well; mm None:
-    no V_MM."""
+    no V_MM; dwp2: second barriers of tautomer coordinates (second_state)."""
     lam = np.asarray(lam, dtype=np.float64)
     if dwp is None:
         Vdw, dVdw = np.zeros_like(lam), np.zeros_like(lam)
     else:
-        Vdw, dVdw = v_dw(dwp, lam)
+        sec = second_state(lam, partner, pka, dwp2)
+        Vdw, dVdw = v_dw(dw_params(dwp, dwp2, sec), lam)
     if mm is None:
         mm = np.zeros((lam.size, 36))
     sph = ph_slope(pka, ph_c, T)
@@ -156,7 +186,7 @@ def bussi_kinetic(K, nf, kbar, c, R1, chi2):
 
 
 def lambda_step(coord_off, lam, v, dvdl, partner, pka, ph, mm, dwp, noise, mass, dt, T, tau,
-                first):
+                first, dwp2=None):
     """One velocity-Verlet step of the lambda particles with the forces at the
     current lambda (from the solve that just ran):
       v_n = v_{n-1/2} + dt/2 F_n / m        (skipped when first: v is v_n)
@@ -170,7 +200,7 @@ def lambda_step(coord_off, lam, v, dvdl, partner, pka, ph, mm, dwp, noise, mass,
     ph_c = np.empty_like(lam)
     for r in range(R):
         ph_c[coord_off[r]:coord_off[r + 1]] = ph[r]
-    F, eb = lambda_forces(lam, dvdl, partner, pka, ph_c, mm, dwp, T)
+    F, eb = lambda_forces(lam, dvdl, partner, pka, ph_c, mm, dwp, T, dwp2)
     if not first:
         v = v + 0.5 * dt * F / mass
     kin = np.zeros(R)
@@ -189,16 +219,22 @@ def lambda_step(coord_off, lam, v, dvdl, partner, pka, ph, mm, dwp, noise, mass,
     return lam + dt * v, v, kin, ebias
 
 
-def accumulate_stats(lam, stats_w, stats_b, near0=0.2, near1=0.8):
+def accumulate_stats(lam, stats_w, stats_b, near0=0.2, near1=0.8, stats_b2=None, second=None):
     """DBO block statistics of the full-step lambda: stats_w per coordinate
     (steps, steps near 0, sum of lambda near 0, steps near 1, sum near 1),
-    stats_b (steps, steps in transition near0 < lambda < near1)."""
+    stats_b (steps, steps in transition near0 < lambda < near1); with
+    stats_b2, the barrier statistics of coordinates in their second state
+    (`second`, see second_state) go there instead.  Returns (stats_w,
+    stats_b) or, with stats_b2, (stats_w, stats_b, stats_b2)."""
     lam = np.asarray(lam, dtype=np.float64)
     n0, n1 = lam < near0, lam > near1
     stats_w = stats_w + np.stack([np.ones_like(lam), n0, np.where(n0, lam, 0.0), n1,
                                   np.where(n1, lam, 0.0)], axis=1)
-    stats_b = stats_b + np.stack([np.ones_like(lam), ~n0 & ~n1], axis=1)
-    return stats_w, stats_b
+    inc = np.stack([np.ones_like(lam), ~n0 & ~n1], axis=1).astype(np.float64)
+    if stats_b2 is None:
+        return stats_w, stats_b + inc
+    sec = np.zeros(lam.size, dtype=bool) if second is None else np.asarray(second)
+    return stats_w, stats_b + inc * ~sec[:, None], stats_b2 + inc * sec[:, None]
 
 
 def pfc_dg(V, T):
@@ -238,16 +274,36 @@ def pfc_solve(B, p0, p1, pka, ph_c, T):
     return brentq(g, -200.0, 200.0, xtol=1e-13, rtol=1e-15, maxiter=500)
 
 
-def dbo_update(stats_w, stats_b, dwp, mode, pka, ph_c, T, pfc=True, **kw):
+def _barrier_rule(B, sb_c, p):
+    """The barrier after one block with statistics sb_c = (steps, steps in
+    transition)."""
+    frac = sb_c[1] / sb_c[0]
+    if frac < p["target"] - p["target_tol"]:
+        B -= p["barrier_step"]
+    elif frac > p["target"] + p["target_tol"]:
+        B += p["barrier_step"]
+    return min(max(B, p["barrier_min"]), p["barrier_max"])
+
+
+def dbo_update(stats_w, stats_b, dwp, mode, pka, ph_c, T, pfc=True, dwp2=None, stats_b2=None,
+               partner=None, **kw):
     """Apply the DBO rules at the end of a block: mode bit 0 = well block
     (stats_w), bit 1 = barrier block (stats_b).  Returns (new dwp, adjusted
     flags, cleared stats_w, cleared stats_b); adjusted coordinates get a new
-    y1 from the partition function correction when pfc."""
+    y1 from the partition function correction when pfc.  With dwp2 (and
+    stats_b2, partner), tautomer coordinates also move their second barrier
+    from stats_b2 and get a new y1_2; then returns (dwp, adj, sw, sb, dwp2,
+    sb2)."""
     p = dict(DBO_DEFAULTS)
     p.update(kw)
     dwp = np.array(dwp, dtype=np.float64)
     sw, sb = np.array(stats_w, dtype=np.float64), np.array(stats_b, dtype=np.float64)
     adj = np.zeros(dwp.shape[0], dtype=np.int32)
+    two = dwp2 is not None
+    if two:
+        dwp2 = np.array(dwp2, dtype=np.float64)
+        sb2 = np.array(stats_b2, dtype=np.float64)
+        taut = (np.asarray(partner) >= 0) & np.isnan(np.asarray(pka, dtype=np.float64))
     for c in range(dwp.shape[0]):
         if mode & 1 and sw[c, 0] > 0:
             for w, (cnt, tot) in enumerate(((sw[c, 1], sw[c, 2]), (sw[c, 3], sw[c, 4]))):
@@ -261,20 +317,25 @@ def dbo_update(stats_w, stats_b, dwp, mode, pka, ph_c, T, pfc=True, **kw):
                             dwp[c, 1 + w] = new
                             adj[c] = 1
         if mode & 2 and sb[c, 0] > 0:
-            frac = sb[c, 1] / sb[c, 0]
-            B = dwp[c, 0]
-            if frac < p["target"] - p["target_tol"]:
-                B -= p["barrier_step"]
-            elif frac > p["target"] + p["target_tol"]:
-                B += p["barrier_step"]
-            B = min(max(B, p["barrier_min"]), p["barrier_max"])
+            B = _barrier_rule(dwp[c, 0], sb[c], p)
             if B != dwp[c, 0]:
                 dwp[c, 0] = B
                 adj[c] = 1
+        if two and taut[c] and mode & 2 and sb2[c, 0] > 0:
+            B2 = _barrier_rule(dwp2[c, 0], sb2[c], p)
+            if B2 != dwp2[c, 0]:
+                dwp2[c, 0] = B2
+                adj[c] = 1
         if adj[c] and pfc:
             dwp[c, 3] = pfc_solve(dwp[c, 0], dwp[c, 1], dwp[c, 2], pka[c], ph_c[c], T)
+            if two and taut[c]:
+                dwp2[c, 1] = pfc_solve(dwp2[c, 0], dwp[c, 1], dwp[c, 2], pka[c], ph_c[c], T)
     if mode & 1:
         sw[:] = 0.0
     if mode & 2:
         sb[:] = 0.0
+        if two:
+            sb2[:] = 0.0
+    if two:
+        return dwp, adj, sw, sb, dwp2, sb2
     return dwp, adj, sw, sb

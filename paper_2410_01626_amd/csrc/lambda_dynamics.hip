@@ -94,7 +94,24 @@ struct StepArgs {
     double* stats_b;
     double* kin;
     double* e_bias;
+    const double* dwp2;  // tautomer coordinates: (B2, y1_2) of the deprotonated state, or null
+    double* stats_b2;    // their barrier statistics in that state, or null
 };
+
+// A tautomer coordinate (no pKa, a partner: the site's protonation
+// coordinate) uses its second barrier set while the site is deprotonated
+// (partner lambda >= 1/2; lambda = 0 is protonated).
+// Evaluated without per-lane early exits: every load is in bounds (an
+// invalid partner reads the coordinate's own lambda) and the answer is one
+// predicate.
+__device__ __forceinline__ bool second_state(const StepArgs& A, int64_t c) {
+    if (!A.dwp2 || !A.partner) return false;
+    const int32_t pc = A.partner[c];
+    const bool paired = pc >= 0 && pc < A.C;
+    const bool no_pka = !A.pka || isnan(A.pka[c]);
+    const double lp = A.lam[paired ? (int64_t)pc : c];
+    return paired && no_pka && lp >= 0.5;
+}
 
 __device__ __forceinline__ void replica_range(const int32_t* off, int64_t C, int r, int64_t& a, int64_t& b) {
     a = min<int64_t>(max<int64_t>(off[r], 0), C);
@@ -135,8 +152,10 @@ __device__ double lambda_force(const StepArgs& A, int64_t c, double ph_r, double
     }
     if (A.dwp) {
         const double* d = A.dwp + 4 * c;
+        const bool sec = second_state(A, c);
+        const double B = sec ? A.dwp2[2 * c] : d[0], y1 = sec ? A.dwp2[2 * c + 1] : d[3];
         double V, dV;
-        double_well(dw_knots(d[0], d[1], d[2], d[3]), l, V, dV);
+        double_well(dw_knots(B, d[1], d[2], y1), l, V, dV);
         dH += dV;
         eb += V;
     }
@@ -211,9 +230,19 @@ __global__ __launch_bounds__(kThreads) void k_lambda_step(StepArgs A) {
             }
         }
         if (A.stats_b) {
-            double* s = A.stats_b + 2 * c;
-            s[0] += 1.0;
-            if (!(l < A.prm.near0) && !(l > A.prm.near1)) s[1] += 1.0;
+            // tautomer coordinates in their second state count into stats_b2.
+            // Both arrays take a masked increment (adding 0 is exact) instead
+            // of one update through a per-lane choice of array: hipcc
+            // (ROCm 7.2, -O3) lost the choice of array in that form, sending
+            // every paired coordinate to stats_b2.
+            const double tr = (!(l < A.prm.near0) && !(l > A.prm.near1)) ? 1.0 : 0.0;
+            const double u = (A.stats_b2 && second_state(A, c)) ? 1.0 : 0.0;
+            A.stats_b[2 * c] += 1.0 - u;
+            A.stats_b[2 * c + 1] += (1.0 - u) * tr;
+            if (A.stats_b2) {
+                A.stats_b2[2 * c] += u;
+                A.stats_b2[2 * c + 1] += u * tr;
+            }
         }
     }
     block_sum2(K, E);
@@ -295,9 +324,10 @@ __device__ double pfc_dg(const Knots& k, double slope, double beta, const GaussL
 // (the free energy increases with y1; a target out of reach leaves y1 at the
 // nearer end).  Safeguarded regula falsi: Illinois steps (the retained end's
 // residual halved when the same end is kept twice) alternate with bisection
-// steps, so every two steps at least halve the bracket; it stops once the
-// residual is below 1e-13 kJ/mol or the bracket below 1e-11; wave-uniform
-// (every lane holds the same residuals).
+// steps, so every two steps at least halve the bracket; it stops on the
+// bracket width alone (below 1e-11 kJ/mol; a residual test would not bound the
+// error in y1 where the free energy saturates and its slope in y1 is small),
+// or on an exact zero; wave-uniform (every lane holds the same residuals).
 __device__ double pfc_solve(double B, double p0, double p1, double pk, double ph_r, double T,
                             const GaussLegendre& gl) {
     const double beta = 1.0 / (kKB * T);
@@ -314,7 +344,7 @@ __device__ double pfc_solve(double B, double p0, double p1, double pk, double ph
         if (!(x > lo && x < hi)) x = 0.5 * (lo + hi);
         if (x <= lo || x >= hi) break;  // no representable point inside
         const double gx = resid(x);
-        if (fabs(gx) < 1e-13) return x;  // kJ/mol: y1 then agrees to ~1e-10
+        if (gx == 0.0) return x;
         if (gx < 0.0) {
             lo = x;
             glo = gx;
@@ -343,6 +373,9 @@ struct DboArgs {
     double* stats_w;
     double* stats_b;
     int32_t* adjusted;
+    const int32_t* partner;  // with dwp2: the protonation partner of each coordinate
+    double* dwp2;            // tautomer coordinates: (B2, y1_2), or null
+    double* stats_b2;
 };
 
 constexpr int kDboWaves = 4;
@@ -410,12 +443,39 @@ __global__ __launch_bounds__(64 * kDboWaves) void k_lambda_dbo(DboArgs A, GaussL
             s[1] = 0.0;
         }
     }
+    // tautomer coordinate with a second barrier (the deprotonated state's)
+    const double pk = A.pka ? A.pka[c] : NAN;
+    const bool taut = A.dwp2 && A.partner && A.partner[c] >= 0 && A.partner[c] < A.C && isnan(pk);
+    double d2[2] = {taut ? A.dwp2[2 * c] : 0.0, taut ? A.dwp2[2 * c + 1] : 0.0};
+    if (taut && (A.mode & 2) && A.stats_b2) {
+        double* s = A.stats_b2 + 2 * c;
+        const double s0 = s[0], s1 = s[1];
+        if (s0 > 0.0) {
+            const double frac = s1 / s0;
+            double B = d2[0];
+            if (frac < P.target - P.target_tol) B -= P.barrier_step;
+            else if (frac > P.target + P.target_tol) B += P.barrier_step;
+            B = fmin(fmax(B, P.barrier_min), P.barrier_max);
+            if (B != d2[0]) {
+                d2[0] = B;
+                adj = true;
+            }
+        }
+        if (w0) {
+            s[0] = 0.0;
+            s[1] = 0.0;
+        }
+    }
     if ((adj && A.pfc) || A.all) {
-        const double pk = A.pka ? A.pka[c] : NAN;
         d[3] = pfc_solve(d[0], d[1], d[2], pk, ph_r, A.T, gl);
+        if (taut) d2[1] = pfc_solve(d2[0], d[1], d[2], pk, ph_r, A.T, gl);
     }
     if (w0) {
         for (int k = 0; k < 4; ++k) A.dwp[4 * c + k] = d[k];
+        if (taut) {
+            A.dwp2[2 * c] = d2[0];
+            A.dwp2[2 * c + 1] = d2[1];
+        }
         if (A.adjusted) A.adjusted[c] = adj ? 1 : 0;
     }
 }
@@ -466,14 +526,16 @@ fmm_status fmm_lambda_step(void* hip_stream, int32_t R, const int32_t* coord_off
                            double* lam_new, double* v, const double* dvdl, const int32_t* partner,
                            const double* pka, const double* ph, const double* mm, const double* dwp,
                            const double* noise, double* stats_w, double* stats_b, double* kin,
-                           double* e_bias) {
+                           double* e_bias, const double* dwp2, double* stats_b2) {
     using namespace fmml;
     if (R < 1 || C < 0 || !coord_off || !fmml::valid_params(prm) || !ph || (first != 0 && first != 1))
         return FMM_E_INVALID;
     if (C > 0 && (!lam || !lam_new || !v || !dvdl || lam == lam_new)) return FMM_E_INVALID;
     if (prm->tau > 0 && (!noise || !(prm->temperature > 0))) return FMM_E_INVALID;
+    if (C > 0 && dwp2 && (!dwp || !partner)) return FMM_E_INVALID;
+    if (C > 0 && stats_b2 && (!dwp2 || !stats_b)) return FMM_E_INVALID;
     StepArgs A{coord_off, C, *prm, first, lam, lam_new, v, dvdl, partner, pka, ph, mm, dwp,
-               noise, stats_w, stats_b, kin, e_bias};
+               noise, stats_w, stats_b, kin, e_bias, dwp2, stats_b2};
     k_lambda_step<<<R, kThreads, 0, (hipStream_t)hip_stream>>>(A);
     return hipGetLastError() == hipSuccess ? FMM_OK : FMM_E_HIP;
 }
@@ -481,29 +543,33 @@ fmm_status fmm_lambda_step(void* hip_stream, int32_t R, const int32_t* coord_off
 fmm_status fmm_lambda_dbo(void* hip_stream, int32_t R, const int32_t* coord_off, int64_t C,
                           int32_t mode, int32_t pfc, const fmm_dbo_params* prm, double temperature,
                           const double* pka, const double* ph, double* dwp, double* stats_w,
-                          double* stats_b, int32_t* adjusted) {
+                          double* stats_b, int32_t* adjusted, const int32_t* partner, double* dwp2,
+                          double* stats_b2) {
     using namespace fmml;
     if (R < 1 || C < 0 || !coord_off || !ph || mode < 0 || mode > 3 || (pfc != 0 && pfc != 1) ||
         !(temperature > 0) || !std::isfinite(temperature))
         return FMM_E_INVALID;
     if (C > 0 && (!dwp || ((mode & 1) && !stats_w) || ((mode & 2) && !stats_b))) return FMM_E_INVALID;
+    if (C > 0 && dwp2 && (!partner || ((mode & 2) && !stats_b2))) return FMM_E_INVALID;
     fmm_dbo_params P = prm ? *prm : fmm_dbo_params{0.2, 0.8, 0.7, 0.03, 0.5, 0.08, 0.25, 0.05, 1.0, 1.0, 20.0};
     if (C == 0) return FMM_OK;
-    DboArgs A{coord_off, R, C, mode, pfc, 0, P, temperature, pka, ph, dwp, stats_w, stats_b, adjusted};
+    DboArgs A{coord_off, R, C, mode, pfc, 0, P, temperature, pka, ph, dwp, stats_w, stats_b, adjusted,
+              partner, dwp2, stats_b2};
     const unsigned nb = (unsigned)((C + kDboWaves - 1) / kDboWaves);
     k_lambda_dbo<<<nb, 64 * kDboWaves, 0, (hipStream_t)hip_stream>>>(A, gl_table());
     return hipGetLastError() == hipSuccess ? FMM_OK : FMM_E_HIP;
 }
 
 fmm_status fmm_lambda_pfc(void* hip_stream, int32_t R, const int32_t* coord_off, int64_t C,
-                          double temperature, const double* pka, const double* ph, double* dwp) {
+                          double temperature, const double* pka, const double* ph, double* dwp,
+                          const int32_t* partner, double* dwp2) {
     using namespace fmml;
     if (R < 1 || C < 0 || !coord_off || !ph || !(temperature > 0) || !std::isfinite(temperature))
         return FMM_E_INVALID;
-    if (C > 0 && !dwp) return FMM_E_INVALID;
+    if (C > 0 && (!dwp || (dwp2 && !partner))) return FMM_E_INVALID;
     if (C == 0) return FMM_OK;
     DboArgs A{coord_off, R, C, 0, 1, 1, fmm_dbo_params{}, temperature, pka, ph, dwp, nullptr, nullptr,
-              nullptr};
+              nullptr, partner, dwp2, nullptr};
     const unsigned nb = (unsigned)((C + kDboWaves - 1) / kDboWaves);
     k_lambda_dbo<<<nb, 64 * kDboWaves, 0, (hipStream_t)hip_stream>>>(A, gl_table());
     return hipGetLastError() == hipSuccess ? FMM_OK : FMM_E_HIP;

@@ -52,7 +52,8 @@ def _raise(st, name):
 
 def lambda_step(coord_off, lam, lam_new, v, dvdl, ph, params: LambdaParams, first=False,
                 partner=None, pka=None, mm=None, dwp=None, noise=None, stats_w=None,
-                stats_b=None, kin=None, e_bias=None, stream=None, check=True):
+                stats_b=None, kin=None, e_bias=None, stream=None, check=True, dwp2=None,
+                stats_b2=None):
     """fmm_lambda_step on device tensors (float64; coord_off, partner int32).
     check=False skips the checks of every tensor but dvdl (for a caller that
     has already made them on the same tensors)."""
@@ -65,7 +66,8 @@ def lambda_step(coord_off, lam, lam_new, v, dvdl, ph, params: LambdaParams, firs
         st = load_library().fmm_lambda_step(
             ctypes.c_void_p(s.cuda_stream), R, _p(coord_off), C, ctypes.byref(params),
             1 if first else 0, _p(lam), _p(lam_new), _p(v), _p(dvdl), _p(partner), _p(pka), _p(ph),
-            _p(mm), _p(dwp), _p(noise), _p(stats_w), _p(stats_b), _p(kin), _p(e_bias))
+            _p(mm), _p(dwp), _p(noise), _p(stats_w), _p(stats_b), _p(kin), _p(e_bias), _p(dwp2),
+            _p(stats_b2))
         _raise(st, "fmm_lambda_step")
         return
     f64, i32 = torch.float64, torch.int32
@@ -76,18 +78,21 @@ def lambda_step(coord_off, lam, lam_new, v, dvdl, ph, params: LambdaParams, firs
     _check(partner, C, i32, "partner", True)
     for t, n, nm in ((pka, C, "pka"), (mm, 36 * C, "mm"), (dwp, 4 * C, "dwp"),
                      (noise, 2 * R, "noise"), (stats_w, 5 * C, "stats_w"),
-                     (stats_b, 2 * C, "stats_b"), (kin, R, "kin"), (e_bias, R, "e_bias")):
+                     (stats_b, 2 * C, "stats_b"), (kin, R, "kin"), (e_bias, R, "e_bias"),
+                     (dwp2, 2 * C, "dwp2"), (stats_b2, 2 * C, "stats_b2")):
         _check(t, n, f64, nm, True)
     s = stream if stream is not None else torch.cuda.current_stream(lam.device)
     st = load_library().fmm_lambda_step(
         ctypes.c_void_p(s.cuda_stream), R, _p(coord_off), C, ctypes.byref(params),
         1 if first else 0, _p(lam), _p(lam_new), _p(v), _p(dvdl), _p(partner), _p(pka), _p(ph),
-        _p(mm), _p(dwp), _p(noise), _p(stats_w), _p(stats_b), _p(kin), _p(e_bias))
+        _p(mm), _p(dwp), _p(noise), _p(stats_w), _p(stats_b), _p(kin), _p(e_bias), _p(dwp2),
+        _p(stats_b2))
     _raise(st, "fmm_lambda_step")
 
 
 def lambda_dbo(coord_off, dwp, ph, temperature, mode=3, pfc=True, pka=None, stats_w=None,
-               stats_b=None, adjusted=None, params: DboParams | None = None, stream=None):
+               stats_b=None, adjusted=None, params: DboParams | None = None, stream=None,
+               partner=None, dwp2=None, stats_b2=None):
     """fmm_lambda_dbo on device tensors."""
     import torch
     R = coord_off.numel() - 1
@@ -99,15 +104,19 @@ def lambda_dbo(coord_off, dwp, ph, temperature, mode=3, pfc=True, pka=None, stat
     _check(stats_w, 5 * C, torch.float64, "stats_w", True)
     _check(stats_b, 2 * C, torch.float64, "stats_b", True)
     _check(adjusted, C, torch.int32, "adjusted", True)
+    _check(partner, C, torch.int32, "partner", True)
+    _check(dwp2, 2 * C, torch.float64, "dwp2", True)
+    _check(stats_b2, 2 * C, torch.float64, "stats_b2", True)
     s = stream if stream is not None else torch.cuda.current_stream(dwp.device)
     st = load_library().fmm_lambda_dbo(
         ctypes.c_void_p(s.cuda_stream), R, _p(coord_off), C, int(mode), 1 if pfc else 0,
         ctypes.byref(params) if params is not None else ctypes.c_void_p(0), float(temperature),
-        _p(pka), _p(ph), _p(dwp), _p(stats_w), _p(stats_b), _p(adjusted))
+        _p(pka), _p(ph), _p(dwp), _p(stats_w), _p(stats_b), _p(adjusted), _p(partner), _p(dwp2),
+        _p(stats_b2))
     _raise(st, "fmm_lambda_dbo")
 
 
-def lambda_pfc(coord_off, dwp, ph, temperature, pka=None, stream=None):
+def lambda_pfc(coord_off, dwp, ph, temperature, pka=None, stream=None, partner=None, dwp2=None):
     """fmm_lambda_pfc on device tensors."""
     import torch
     R = coord_off.numel() - 1
@@ -116,9 +125,12 @@ def lambda_pfc(coord_off, dwp, ph, temperature, pka=None, stream=None):
     _check(dwp, 4 * C, torch.float64, "dwp")
     _check(ph, R, torch.float64, "ph")
     _check(pka, C, torch.float64, "pka", True)
+    _check(partner, C, torch.int32, "partner", True)
+    _check(dwp2, 2 * C, torch.float64, "dwp2", True)
     s = stream if stream is not None else torch.cuda.current_stream(dwp.device)
     st = load_library().fmm_lambda_pfc(ctypes.c_void_p(s.cuda_stream), R, _p(coord_off), C,
-                                       float(temperature), _p(pka), _p(ph), _p(dwp))
+                                       float(temperature), _p(pka), _p(ph), _p(dwp), _p(partner),
+                                       _p(dwp2))
     _raise(st, "fmm_lambda_pfc")
 
 
@@ -132,7 +144,9 @@ class LambdaDynamics:
     `barrier_block` steps, applies DBO (with the partition function
     correction).  The bias parameters default to the paper's barrier of
     6 kJ/mol with wells at 0 and 1 and no V_MM (synthetic: the calibration
-    polynomials are inputs, mm)."""
+    polynomials are inputs, mm).  Tautomer coordinates (pKa NaN with a
+    partner) get a second barrier for the deprotonated state, starting at the
+    same height and tuned by DBO from its own statistics."""
 
     def __init__(self, site_off, lam0, ph, pka, mass=60.0, dt=0.002, temperature=300.0,
                  tau=1.0, barrier=6.0, mm=None, partner=None, well_block=None,
@@ -156,6 +170,12 @@ class LambdaDynamics:
         dwp = np.zeros((self.C, 4))
         dwp[:, 0], dwp[:, 2] = barrier, 1.0
         self.dwp = torch.tensor(dwp, **f64)
+        taut = (partner is not None and np.any((np.asarray(partner) >= 0)
+                                               & np.isnan(np.asarray(pka, dtype=np.float64))))
+        # second barrier and y1 of tautomer coordinates (others ignore them)
+        self.dwp2 = torch.tensor(np.stack([np.full(self.C, barrier), np.zeros(self.C)], axis=1),
+                                 **f64) if taut else None
+        self.stats_b2 = torch.zeros(2 * self.C, **f64) if taut else None
         self.params = LambdaParams(mass, dt, temperature, tau, 0.2, 0.8)
         self.T = temperature
         self.gen = torch.Generator(device=self.dev)
@@ -176,22 +196,51 @@ class LambdaDynamics:
         self.well_block = well_block if well_block is not None else int(round(40.0 / dt))
         self.barrier_block = barrier_block if barrier_block is not None else int(round(1000.0 / dt))
         self.n = 0
-        self._checked = None  # identities of the tensors the last full check saw
-        lambda_pfc(self.coord_off, self.dwp, self.ph, temperature, pka=self.pka)
+        self._checked = None  # the tensors (and their metadata) the last full check saw
+        lambda_pfc(self.coord_off, self.dwp, self.ph, temperature, pka=self.pka,
+                   partner=self.partner if self.dwp2 is not None else None, dwp2=self.dwp2)
 
     def draw_noise(self):
         """For each of the next noise_block steps, one standard normal and one
-        chi-square sample with N_f - 1 degrees of freedom per replica
-        (chi^2_k = 2 Gamma(k / 2, 1); 0 for k = 0)."""
+        chi-square sample with N_f - 1 degrees of freedom per replica: by its
+        definition, the sum of N_f - 1 squared standard normals (0 for none),
+        drawn in chunks of 256 degrees of freedom."""
         import torch
         nb, R = self.noise_block, self.R
-        r1 = torch.randn((nb, R), generator=self.gen, dtype=torch.float64, device=self.dev)
-        k = torch.clamp(self.nf - 1, min=0).expand(nb, R).contiguous()
-        g = torch._standard_gamma(torch.clamp(k / 2, min=1e-300), generator=self.gen)
-        chi2 = torch.where(k > 0, 2 * g, torch.zeros_like(g))
+        f64 = dict(dtype=torch.float64, device=self.dev)
+        r1 = torch.randn((nb, R), generator=self.gen, **f64)
+        k = torch.clamp(self.nf - 1, min=0).reshape(R)
+        chi2 = torch.zeros((nb, R), **f64)
+        kmax = int(k.max().item()) if R else 0
+        for k0 in range(0, kmax, 256):
+            w = min(256, kmax - k0)
+            z = torch.randn((nb, R, w), generator=self.gen, **f64)
+            used = (k0 + torch.arange(w, device=self.dev))[None, :] < k[:, None]
+            chi2 += (z * z * used).sum(-1)
         bank = self.noise_bank.view(nb, R, 2)
         bank[:, :, 0] = r1
         bank[:, :, 1] = chi2
+
+    @staticmethod
+    def _meta(t):
+        return None if t is None else (t.data_ptr(), t.numel(), t.dtype, t.device)
+
+    def _fingerprint(self):
+        ts = (self.coord_off, self.v, self.ph, self.partner, self.pka, self.mm, self.dwp,
+              self.noise_bank, self.stats_w, self.stats_b, self.kin, self.e_bias,
+              getattr(self, "dwp2", None), getattr(self, "stats_b2", None))
+        return ([(t, self._meta(t)) for t in ts],
+                sorted([(self.lam, self._meta(self.lam)), (self.lam_next, self._meta(self.lam_next))],
+                       key=lambda e: e[1][0]))
+
+    @staticmethod
+    def _same(a, b):
+        """Same tensor objects (compared with `is`) with unchanged metadata."""
+        if a is None or b is None:
+            return False
+        pa = a[0] + a[1]
+        pb = b[0] + b[1]
+        return len(pa) == len(pb) and all(x[0] is y[0] and x[1] == y[1] for x, y in zip(pa, pb))
 
     def step(self, dvdl):
         if self.params.tau > 0:
@@ -199,18 +248,18 @@ class LambdaDynamics:
             if i == 0:
                 self.draw_noise()
             self.noise = self.noise_bank[i]
-        # the full tensor checks run again whenever a tensor was replaced
-        # (lam and lam_next alternate; the noise row moves through one bank)
-        # (dvdl, usually a fresh tensor per solve, is checked on every call)
-        seen = tuple(id(t) for t in (self.coord_off, self.v, self.ph, self.partner, self.pka,
-                                     self.mm, self.dwp, self.noise_bank, self.stats_w,
-                                     self.stats_b, self.kin, self.e_bias)) + (
-            frozenset((id(self.lam), id(self.lam_next))),)
+        # the full tensor checks run again whenever a tensor was replaced or
+        # changed in place (lam and lam_next alternate; the noise row moves
+        # through one bank; dvdl, usually a fresh tensor per solve, is checked
+        # on every call): the last checked tensors are kept (so their
+        # identities cannot be reused) with their storage, size, type and device
+        seen = self._fingerprint()
         lambda_step(self.coord_off, self.lam, self.lam_next, self.v, dvdl, self.ph, self.params,
                     first=self.n == 0, partner=self.partner, pka=self.pka, mm=self.mm,
                     dwp=self.dwp, noise=self.noise if self.params.tau > 0 else None,
                     stats_w=self.stats_w, stats_b=self.stats_b, kin=self.kin, e_bias=self.e_bias,
-                    check=seen != self._checked)
+                    check=not self._same(seen, self._checked), dwp2=self.dwp2,
+                    stats_b2=self.stats_b2)
         self._checked = seen
         self.lam, self.lam_next = self.lam_next, self.lam
         self.n += 1
@@ -218,5 +267,7 @@ class LambdaDynamics:
         if mode:
             lambda_dbo(self.coord_off, self.dwp, self.ph, self.T, mode=mode, pfc=True,
                        pka=self.pka, stats_w=self.stats_w, stats_b=self.stats_b,
-                       adjusted=self.adjusted)
+                       adjusted=self.adjusted,
+                       partner=self.partner if self.dwp2 is not None else None,
+                       dwp2=self.dwp2, stats_b2=self.stats_b2)
         return self.lam

@@ -80,6 +80,68 @@ def test_step_matches_oracle(first, tau):
     assert np.array_equal(lam.cpu().numpy(), d["lam"])  # the input is untouched
 
 
+def test_step_with_tautomer_second_barriers():
+    """Tautomer coordinates (no pKa, a partner) switch to their second barrier
+    set while the partner is deprotonated, and their barrier statistics go to
+    stats_b2 in that state; both match the oracle."""
+    import torch
+    from paper_2410_01626_amd import lambda_dynamics as LD
+    d = _case(9, [40, 90])
+    C, R = d["lam"].size, d["ph"].size
+    rng = np.random.default_rng(4)
+    dwp2 = np.stack([rng.uniform(1, 12, C), rng.uniform(-3, 3, C)], axis=1)
+    sec = L.second_state(d["lam"], d["partner"], d["pka"], dwp2)
+    assert sec.sum() >= 5 and (~sec & np.isnan(d["pka"]) & (d["partner"] >= 0)).sum() >= 5
+    m, dt, T, tau = 60.0, 0.002, 300.0, 0.5
+    lam, lam_new, v = _t(d["lam"]), torch.empty(C, dtype=torch.float64, device="cuda:0"), _t(d["v"])
+    z = lambda k: torch.zeros(k, dtype=torch.float64, device="cuda:0")
+    sw, sb, sb2, kin, eb = z(5 * C), z(2 * C), z(2 * C), z(R), z(R)
+    prm = LD.LambdaParams(m, dt, T, tau, 0.2, 0.8)
+    LD.lambda_step(_t(d["off"], torch.int32), lam, lam_new, v, _t(d["dvdl"]), _t(d["ph"]), prm,
+                   partner=_t(d["partner"]), pka=_t(d["pka"]), mm=_t(d["mm"].ravel()),
+                   dwp=_t(d["dwp"].ravel()), noise=_t(d["noise"].ravel()), stats_w=sw, stats_b=sb,
+                   kin=kin, e_bias=eb, dwp2=_t(dwp2.ravel()), stats_b2=sb2)
+    torch.cuda.synchronize()
+    rl, rv, rk, re = L.lambda_step(d["off"], d["lam"], d["v"], d["dvdl"], d["partner"], d["pka"],
+                                   d["ph"], d["mm"], d["dwp"], d["noise"], m, dt, T, tau, False,
+                                   dwp2=dwp2)
+    rsw, rsb, rsb2 = L.accumulate_stats(d["lam"], np.zeros((C, 5)), np.zeros((C, 2)),
+                                        stats_b2=np.zeros((C, 2)), second=sec)
+    _close(lam_new.cpu().numpy(), rl)
+    _close(v.cpu().numpy(), rv)
+    _close(eb.cpu().numpy(), re)
+    assert np.array_equal(sb.cpu().numpy().reshape(C, 2), rsb)
+    assert np.array_equal(sb2.cpu().numpy().reshape(C, 2), rsb2)
+    # the second barrier matters: the one-barrier step differs
+    rl1, _, _, _ = L.lambda_step(d["off"], d["lam"], d["v"], d["dvdl"], d["partner"], d["pka"],
+                                 d["ph"], d["mm"], d["dwp"], d["noise"], m, dt, T, tau, False)
+    assert np.abs(rl1 - rl).max() > 1e-9
+    # DBO of both barriers and the correction of both states
+    nst = np.zeros((C, 2))
+    nst[:, 0] = 100.0
+    nst[:, 1] = rng.integers(0, 60, C)
+    nst2 = nst.copy()
+    nst2[:, 1] = rng.integers(0, 60, C)
+    swn = np.zeros((C, 5))
+    g_dwp, g_dwp2, g_sb, g_sb2 = _t(d["dwp"].ravel()), _t(dwp2.ravel()), _t(nst.ravel()), _t(nst2.ravel())
+    adj = torch.zeros(C, dtype=torch.int32, device="cuda:0")
+    LD.lambda_dbo(_t(d["off"], torch.int32), g_dwp, _t(d["ph"]), T, mode=2, pfc=True,
+                  pka=_t(d["pka"]), stats_w=_t(swn.ravel()), stats_b=g_sb, adjusted=adj,
+                  partner=_t(d["partner"]), dwp2=g_dwp2, stats_b2=g_sb2)
+    torch.cuda.synchronize()
+    ph_c = np.repeat(d["ph"], np.diff(d["off"]))
+    rd, radj, _, _, rd2, _ = L.dbo_update(swn, nst, d["dwp"], 2, d["pka"], ph_c, T, pfc=True,
+                                          dwp2=dwp2, stats_b2=nst2, partner=d["partner"])
+    assert np.array_equal(adj.cpu().numpy(), radj)
+    got, got2 = g_dwp.cpu().numpy().reshape(C, 4), g_dwp2.cpu().numpy().reshape(C, 2)
+    taut = np.isnan(d["pka"]) & (d["partner"] >= 0)
+    assert np.array_equal(got[:, 0], rd[:, 0]) and np.array_equal(got2[taut, 0], rd2[taut, 0])
+    assert np.allclose(got[:, 3], rd[:, 3], atol=1e-8, rtol=0)
+    assert np.allclose(got2[taut, 1], rd2[taut, 1], atol=1e-8, rtol=0)
+    assert np.array_equal(got2[~taut], dwp2[~taut])  # other coordinates keep dwp2
+    assert not g_sb.any() and not g_sb2[torch.tensor(np.repeat(taut, 2), device="cuda:0")].any()
+
+
 def test_step_without_optional_terms():
     # no partner, pKa, V_MM, double well, statistics or outputs: only the
     # Coulomb derivative moves lambda
@@ -150,6 +212,38 @@ def test_dbo_and_pfc_match_oracle():
                   stats_w=g_sw2, stats_b=g_sb2)
     torch.cuda.synchronize()
     assert not g_sw2.any() and np.array_equal(g_sb2.cpu().numpy(), sb.ravel())
+
+
+def test_pfc_near_the_unreachable_target():
+    """Targets just inside and just past the largest free energy a low barrier
+    allows (1 kJ/mol, wells at 0 and 1, pH 7): the free energy saturates in y1
+    there (slope ~0.006), so the root finder must stop on the bracket, not on
+    the residual.  y1 equals the oracle's to 1e-8 and solves the oracle's
+    equation; past the edge y1 stays at the bound."""
+    import torch
+    from paper_2410_01626_amd import lambda_dynamics as LD
+    from scipy.optimize import brentq
+    T, ph = 300.0, 7.0
+
+    def g(pk, y1):
+        slope = L.LN10 * L.KB * T * (pk - ph)
+        return L.pfc_dg(L.pfc_landscape(1.0, 0.0, 1.0, y1, slope), T) - L.pfc_target(pk, ph, T)
+
+    edge = brentq(lambda pk: g(pk, 200.0), 8.0, 10.0, xtol=1e-12)
+    pka = edge + np.array([-0.5, -0.1, -0.02, -0.005, -0.001, 0.01, 0.2])
+    C = pka.size
+    dwp = np.stack([np.ones(C), np.zeros(C), np.ones(C), np.zeros(C)], axis=1)
+    g_dwp = _t(dwp.ravel())
+    LD.lambda_pfc(_t(np.array([0, C]), torch.int32), g_dwp, _t(np.array([ph])), T, pka=_t(pka))
+    torch.cuda.synchronize()
+    got = g_dwp.cpu().numpy().reshape(C, 4)[:, 3]
+    for c in range(C):
+        y1 = L.pfc_solve(1.0, 0.0, 1.0, pka[c], ph, T)
+        assert got[c] == pytest.approx(y1, abs=1e-8), (c, got[c], y1)
+        if pka[c] < edge:
+            assert abs(g(pka[c], got[c])) < 1e-10, c
+        else:
+            assert got[c] == 200.0
 
 
 def test_thermostat_samples_the_canonical_kinetic_energy():

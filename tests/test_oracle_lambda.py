@@ -249,3 +249,70 @@ def test_block_statistics():
     assert list(sw[:, 3]) == [0, 0, 1, 0, 0, 0]
     assert sw[3, 2] == -0.05 and sw[2, 4] == 0.9
     assert list(sb[:, 1]) == [0, 1, 0, 0, 1, 1]
+
+
+def _tautomer_site():
+    # coordinates 0 (protonation, pKa 5) and 1 (its tautomer, no pKa) form one
+    # site; coordinate 2 is a plain protonation coordinate without a partner
+    partner = np.array([1, 0, -1])
+    pka = np.array([5.0, np.nan, 6.0])
+    dwp = np.array([[6.0, 0.0, 1.0, 0.4], [6.0, 0.02, 0.98, 0.0], [5.0, 0.0, 1.0, -0.3]])
+    dwp2 = np.array([[9.0, 1.0], [2.0, 0.3], [11.0, 2.0]])
+    return partner, pka, dwp, dwp2
+
+
+def test_tautomer_second_barrier_switches_with_the_protonation_state():
+    """The tautomer coordinate takes its second barrier only while its site is
+    deprotonated (partner lambda >= 1/2, lambda = 0 protonated); protonation
+    coordinates ignore dwp2; with B2 = B the forces are the one-barrier ones."""
+    partner, pka, dwp, dwp2 = _tautomer_site()
+    for lp, expect in ((0.1, False), (0.49, False), (0.5, True), (0.93, True)):
+        lam = np.array([lp, 0.37, 0.8])
+        sec = L.second_state(lam, partner, pka, dwp2)
+        assert list(sec) == [False, expect, False]
+        F, eb = L.lambda_forces(lam, np.zeros(3), partner, pka, np.full(3, 7.0), None, dwp, 300.0,
+                                dwp2)
+        used = dwp.copy()
+        if expect:
+            used[1, 0], used[1, 3] = dwp2[1]
+        Fr, ebr = L.lambda_forces(lam, np.zeros(3), partner, pka, np.full(3, 7.0), None, used, 300.0)
+        assert np.array_equal(F, Fr) and np.array_equal(eb, ebr)
+        # the tautomer coordinate's barrier top value is the barrier in force
+        m = 0.5 * (dwp[1, 1] + dwp[1, 2])
+        V, _ = L.v_dw(L.dw_params(dwp, dwp2, sec), np.array([0.0, m, 0.0]))
+        assert V[1] == pytest.approx(dwp2[1, 0] if expect else dwp[1, 0])
+    same = dwp2.copy()
+    same[1] = [dwp[1, 0], dwp[1, 3]]
+    lam = np.array([0.8, 0.37, 0.8])
+    a = L.lambda_forces(lam, np.zeros(3), partner, pka, np.full(3, 7.0), None, dwp, 300.0, same)
+    b = L.lambda_forces(lam, np.zeros(3), partner, pka, np.full(3, 7.0), None, dwp, 300.0)
+    assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+
+
+def test_tautomer_barrier_statistics_and_dbo_per_state():
+    """In-transition statistics of the deprotonated state go to stats_b2 and
+    move only the second barrier (down when the tautomer rarely crosses in
+    that state, the paper's reason for a lower barrier there); the correction
+    gives each state its own y1: for symmetric wells without pKa the free
+    energy of either state is zero at y1 = 0, whatever the barrier."""
+    partner, pka, dwp, dwp2 = _tautomer_site()
+    dwp[1] = [6.0, 0.0, 1.0, 0.4]
+    sw, sb, sb2 = np.zeros((3, 5)), np.zeros((3, 2)), np.zeros((3, 2))
+    # 100 steps protonated with the tautomer half in transition, then 100
+    # deprotonated with it never in transition
+    for k in range(200):
+        lp = 0.1 if k < 100 else 0.9
+        lt = 0.5 if (k < 100 and k % 2) else 0.05
+        lam = np.array([lp, lt, 0.5])
+        sec = L.second_state(lam, partner, pka, dwp2)
+        sw, sb, sb2 = L.accumulate_stats(lam, sw, sb, stats_b2=sb2, second=sec)
+    assert np.array_equal(sb[1], [100, 50]) and np.array_equal(sb2[1], [100, 0])
+    assert np.array_equal(sb[0], [200, 0]) and np.array_equal(sb2[0], [0, 0])
+    d, adj, _, sbc, d2, sb2c = L.dbo_update(sw, sb, dwp, 2, pka, np.full(3, 7.0), 300.0,
+                                            dwp2=dwp2, stats_b2=sb2, partner=partner)
+    assert d[1, 0] == 7.0          # 50% in transition: above target + tol, up one step
+    assert d2[1, 0] == 1.0         # 0% in the deprotonated state: down, clamped at 1
+    assert d2[0, 0] == dwp2[0, 0]  # protonation coordinates keep their dwp2 untouched
+    assert adj[1] == 1
+    assert d[1, 3] == pytest.approx(0.0, abs=1e-9) and d2[1, 1] == pytest.approx(0.0, abs=1e-9)
+    assert not sbc.any() and not sb2c.any()
