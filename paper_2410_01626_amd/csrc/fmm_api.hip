@@ -30,6 +30,9 @@ struct Workspace {
     int32_t *leaf_count = nullptr, *leaf_start = nullptr, *leaf_order = nullptr;
     int32_t *site_count = nullptr, *site_start = nullptr, *site_rank = nullptr,
             *site_members = nullptr;
+    // leaf buckets of the binning (trees of at most kScanFuseCap leaves):
+    // replicas x leaves x leaf_cap atom indices, the overflow list and its length
+    int32_t *bucket = nullptr, *ovf = nullptr, *ovf_n = nullptr;
     void *mult = nullptr, *loc = nullptr;
     double *root_m = nullptr, *root_l = nullptr;
     double* root_part = nullptr;  // periodic: the 8 level-1 shares of the root multipole
@@ -82,6 +85,7 @@ struct fmm_plan_s {
     hipGraph_t graph = nullptr;
     hipGraphExec_t graph_exec = nullptr;
     int R_max = 1;
+    int leaf_cap = 0;  // leaf bucket capacity (0: binning by scan and scatter)
     // matrix-core M2L
     int p2p_waves = 8;  // wavefronts per near-field block (4, 8 or 16)
     int p2p_split = 1;  // near-field blocks per leaf (1 to 4)
@@ -205,6 +209,13 @@ size_t ws_layout(const fmm_plan_s* P, int64_t N, int64_t S, size_t RM, bool adjo
     take(w->site_start, (S + 1) * 4);
     take(w->site_rank, N * 4);
     take(w->site_members, N * 4);
+    if (P->leaf_cap > 0) {
+        take(w->bucket, RM * nl * (size_t)P->leaf_cap * 4);
+        take(w->ovf, N * 4);
+        take(w->ovf_n, 4);
+    } else {
+        w->bucket = w->ovf = w->ovf_n = nullptr;
+    }
     take(w->mult, RM * nb * Kp * ts);
     take(w->loc, RM * nb * Kp * ts);
     take(w->root_m, RM * K * 8);
@@ -386,7 +397,12 @@ void mark(fmm_plan_t P, int phase) {
 // Dynamic LDS of the leaf kernel: the sort buffer, later the P2M rows.
 template <typename T>
 size_t leaf_lds_bytes(int K) {
-    return std::max<size_t>((size_t)fmmk::kSortCap * 4, (size_t)64 * (K + 1) * sizeof(T));
+    return (size_t)fmmk::leaf_lds_base(K, (int)sizeof(T));
+}
+// ... and its largest form: bucket binning with kScanFuseCap sites
+template <typename T>
+size_t leaf_lds_bytes_max(int K) {
+    return leaf_lds_bytes<T>(K) + (size_t)(256 + fmmk::kScanFuseCap + 1) * 4;
 }
 
 // Dynamic LDS of the second-source leaf kernel of the adjoint: the P2M rows.
@@ -489,10 +505,16 @@ void enqueue_bin_p2m(fmm_plan_t P, const fmmk::Geo& g, RepSpan rd, int R,
         k_bbox_final<<<R, 64, 0, st>>>(P->ws.bbox_part, nb, P->ws.dom);
         set0.count = 0;  // stored by k_bbox
     }
+    // bucket binning: the leaf kernel finds each leaf's atoms in its bucket and
+    // forms the leaf and site starts itself (no scan or scatter launch)
+    const bool binned = P->ws.bucket && g.nleaf <= kScanFuseCap && S_tot <= kScanFuseCap;
+    const Bins bins{binned ? P->ws.bucket : nullptr, P->leaf_cap, P->ws.ovf, P->ws.ovf_n};
     k_charge_key<T><<<dim3(ab, R), 256, 0, st>>>(g, set0, P->ws.reps, x, qA, qB, site, lam, fa, P->ws.dom, P->ws.key,
                                                  P->ws.rank, P->ws.leaf_count, P->ws.site_count,
-                                                 P->ws.site_rank, P->status);
-    if (g.nleaf <= kScanFuseCap && S_tot <= kScanFuseCap) {
+                                                 P->ws.site_rank, P->status, bins);
+    if (binned) {
+        // nothing between the key and leaf launches
+    } else if (g.nleaf <= kScanFuseCap && S_tot <= kScanFuseCap) {
         k_scan_scatter<<<dim3(ab, R), 256, 0, st>>>(g, reps, P->ws.key, P->ws.rank, P->ws.leaf_count,
                                                     P->ws.leaf_start, P->ws.perm, site, P->ws.site_rank,
                                                     P->ws.site_count, P->ws.site_start, (int)S_tot,
@@ -505,9 +527,12 @@ void enqueue_bin_p2m(fmm_plan_t P, const fmmk::Geo& g, RepSpan rd, int R,
     }
     using V4 = vec4_t<T>;
     mark(P, 1);
-    k_leaf_p2m<T><<<dim3(g.nleaf, R), kLeafThreads, leaf_lds_bytes<T>(g.K), st>>>(
+    const LeafBinArgs lb{P->ws.leaf_count, P->ws.key,          P->ws.rank,         P->ws.site_count,
+                         P->ws.site_rank,  P->ws.site_start,   P->ws.site_members, (int)S_tot};
+    const size_t lds = leaf_lds_bytes<T>(g.K) + (binned && S_tot > 0 ? (size_t)(256 + S_tot + 1) * 4 : 0);
+    k_leaf_p2m<T><<<dim3(g.nleaf, R), kLeafThreads, lds, st>>>(
         g, reps, x, qA, qB, site, lam, fa, P->ws.dom, P->ws.leaf_start, P->ws.perm, (V4*)P->ws.pos, P->status,
-        (T*)P->ws.mult, P->ws.leaf_part, (uint16_t*)P->ws.msplit, P->mg.KP);
+        (T*)P->ws.mult, P->ws.leaf_part, (uint16_t*)P->ws.msplit, P->mg.KP, bins, lb);
 }
 
 // The tree passes of R expansion slots (grid y = slot): M2M per level, the
@@ -625,7 +650,7 @@ fmm_status enqueue_eval(fmm_plan_t P, RepSpan rd, const T* x,
                                                        ham && S_tot > 0 ? P->ws.hc_dl : nullptr,
                                                        P->ws.leaf_count, P->ws.site_count,
                                                        P->excl_n > 0 ? P->excl_e : nullptr, (int)ab,
-                                                       nullptr, nullptr);
+                                                       nullptr, nullptr, P->ws.ovf_n);
     mark(P, -1);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return fail(P, FMM_E_HIP, std::string("kernel launch: ") + hipGetErrorString(e));
@@ -690,7 +715,7 @@ fmm_status enqueue_adjoint_full(fmm_plan_t P, const fmmk::RepDesc& r0, const T* 
                                                     P->ws.site_members, P->ws.cphi, E ? E : P->ws.E_tmp, dVdl,
                                                     P->status, qA, qB, lam, fa, nullptr, P->ws.reps, nullptr,
                                                     nullptr, P->ws.leaf_count, P->ws.site_count, nullptr, 0,
-                                                    P->ws.adj_cphi2, glam);
+                                                    P->ws.adj_cphi2, glam, P->ws.ovf_n);
     mark(P, -1);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return fail(P, FMM_E_HIP, std::string("kernel launch: ") + hipGetErrorString(e));
@@ -826,6 +851,15 @@ fmm_status fmm_plan_create(const fmm_params* prm, void* hip_stream, fmm_plan_t* 
     const size_t RM = (size_t)std::max(prm->max_replicas, 2);
     const size_t RT = (size_t)prm->max_replicas;
     P->R_max = prm->max_replicas;
+    // leaf buckets hold about three times a replica's mean leaf population
+    // (at least one leaf block's threads, at most the in-LDS sort size);
+    // fuller leaves spill into the overflow list
+    if (P->nleaf <= fmmk::kScanFuseCap) {
+        const int64_t mean = (N + (int64_t)P->R_max * P->nleaf - 1) / ((int64_t)P->R_max * P->nleaf);
+        int cap = fmmk::kLeafBucketMin;
+        while (cap < 3 * mean && cap < fmmk::kSortCap) cap <<= 1;
+        P->leaf_cap = cap;
+    }
     bool ok = true;
     ok &= dev_alloc(P, &P->bankT, 343 * K * K * ts);
     ok &= dev_alloc(P, &P->m2mT, K * K * ts);  // octant 0; the others are its reflections
@@ -1071,10 +1105,10 @@ fmm_status fmm_plan_create(const fmm_params* prm, void* hip_stream, fmm_plan_t* 
     if (e == hipSuccess) {
         e = P->fp64 ? hipFuncSetAttribute((const void*)&fmmk::k_leaf_p2m<double>,
                                           hipFuncAttributeMaxDynamicSharedMemorySize,
-                                          (int)leaf_lds_bytes<double>((int)K))
+                                          (int)leaf_lds_bytes_max<double>((int)K))
                     : hipFuncSetAttribute((const void*)&fmmk::k_leaf_p2m<float>,
                                           hipFuncAttributeMaxDynamicSharedMemorySize,
-                                          (int)leaf_lds_bytes<float>((int)K));
+                                          (int)leaf_lds_bytes_max<float>((int)K));
     }
     if (e == hipSuccess) {
         e = P->fp64 ? hipFuncSetAttribute((const void*)&fmmk::k_leaf_src2<double>,
@@ -1239,6 +1273,7 @@ fmm_status fmm_eval_noalloc(fmm_plan_t P, int64_t n, const void* x, const void* 
     fmmk::k_fill_i32<<<nblocks(std::max<int64_t>(S, 1), 256), 256, 0, st>>>(sw.site_count,
                                                                             std::max<int64_t>(S, 1), 0);
     fmmk::k_fill_f64<<<1, 64, 0, st>>>(sw.dom, 8, 0.0);
+    if (sw.ovf_n) fmmk::k_fill_i32<<<1, 64, 0, st>>>(sw.ovf_n, 1, 0);
     if (sw.msplit) {
         const int64_t words = (int64_t)(msplit_bytes(P, 1) / 4);
         fmmk::k_fill_i32<<<(unsigned)std::min<int64_t>(1024, (words + 255) / 256), 256, 0, st>>>(

@@ -14,6 +14,13 @@ constexpr int kSiteCap = 1024;              // largest site sorted in LDS
 constexpr int kMaxSplit = 4;                // near-field blocks per leaf, at most
 constexpr int kScanFuseCap = 4096;          // leaf / site counts scanned inside the scatter kernel
 constexpr double kPi = 3.14159265358979323846;
+constexpr int kLeafBucketMin = 256;         // leaf bucket capacity, at least (one leaf block's threads)
+
+// Dynamic LDS of the leaf kernel before its site-scan area: the sort buffer
+// or the 64 P2M rows, whichever is larger.
+constexpr int leaf_lds_base(int K, int tsz) {
+    return kSortCap * 4 > 64 * (K + 1) * tsz ? kSortCap * 4 : 64 * (K + 1) * tsz;
+}
 
 // status[0]: errors raised in check mode; status[1]: informational bits
 constexpr int32_t kStatusNonFinite = 1;

@@ -314,9 +314,38 @@ __device__ __forceinline__ int32_t agg_slot(const AggPlan& pl, int32_t got) {
     return pl.off < 0 ? -1 : base + pl.off;
 }
 
+// Leaf buckets of the binning: atom indices filed per (replica, leaf) at
+// their rank below cap, the rest appended to one overflow list (ovf_n: its
+// length, zeroed by the final reduction).  bucket == null: binning by a
+// global scan and scatter instead.
+struct Bins {
+    int32_t* bucket;
+    int32_t cap;
+    int32_t* ovf;
+    int32_t* ovf_n;
+};
+
+// What the leaf kernel needs besides the buckets to bin without a scatter
+// pass: per-leaf counts (its start), keys and ranks (overflow atoms), and the
+// site counts and ranks (it files every site atom in its site's list and
+// publishes the site starts).
+struct LeafBinArgs {
+    const int32_t* leaf_count;
+    const int32_t* key;
+    const int32_t* rank;
+    const int32_t* site_count;
+    const int32_t* site_rank;
+    int32_t* site_start;
+    int32_t* site_members;
+    int S_tot;
+};
+
 // Leaf key (Morton code of the leaf cell) of every atom, its rank inside the
 // leaf and inside its site (atomic counters: ranks are made stable later by
-// sorting), and the input checks.  The interpolated charge itself,
+// sorting), and the input checks.  With leaf buckets (Bins.bucket set) the
+// atom is also filed under its leaf at its rank (ranks >= Bins.cap go to the
+// overflow list), so the leaf kernel finds a leaf's atoms without a global
+// scatter pass.  The interpolated charge itself,
 // q_i = qA_i + lambda_s (qB_i - qA_i) (eq 1 with interpolated charges), is
 // formed in FP64 when the atoms are gathered into leaf order.
 template <typename T>
@@ -326,7 +355,7 @@ __global__ __launch_bounds__(256) void k_charge_key(
     const double* __restrict__ lam, FormArgs<T> fa, double* __restrict__ dom_all,
     int32_t* __restrict__ key, int32_t* __restrict__ rank, int32_t* __restrict__ leaf_count_all,
     int32_t* __restrict__ site_count, int32_t* __restrict__ site_rank,
-    int32_t* __restrict__ status) {
+    int32_t* __restrict__ status, Bins bins) {
     const int r = blockIdx.y;
     store_reps(set, reps);
     const RepDesc rd = first_rep(set, reps, r);
@@ -384,6 +413,10 @@ __global__ __launch_bounds__(256) void k_charge_key(
     key[i] = (int32_t)k;
     rank[i] = lr;
     site_rank[i] = sr;
+    if (bins.bucket) {
+        if (lr < bins.cap) bins.bucket[((size_t)r * g.nleaf + k) * bins.cap + lr] = (int32_t)i;
+        else bins.ovf[atomicAdd(bins.ovf_n, 1)] = (int32_t)i;
+    }
     if (g.check) {
         bad |= !finite_d((double)qA[i]) || !finite_d((double)qB[i]);
         if (s >= 0) bad |= !finite_d(lam[rd.s0 + s]);
@@ -555,35 +588,83 @@ template <typename T>
 __global__ __launch_bounds__(kLeafThreads) void k_leaf_p2m(
     Geo g, const RepDesc* __restrict__ reps, const T* __restrict__ x, const T* __restrict__ qA,
     const T* __restrict__ qB, const int32_t* __restrict__ site, const double* __restrict__ lam,
-    FormArgs<T> fa, const double* __restrict__ dom_all, const int32_t* __restrict__ leaf_start_all,
+    FormArgs<T> fa, const double* __restrict__ dom_all, int32_t* __restrict__ leaf_start_all,
     int32_t* __restrict__ perm, vec4_t<T>* __restrict__ pos, int32_t* __restrict__ status,
     T* __restrict__ mult_all, double* __restrict__ leaf_part_all, uint16_t* __restrict__ msplit_all,
-    int split_kp) {
+    int split_kp, Bins bins, LeafBinArgs lb) {
     extern __shared__ __align__(16) unsigned char leaf_lds[];
     __shared__ RhoLds<T> rho;
     __shared__ double ps[2][kLeafThreads / 64];
+    __shared__ int32_t wpre[kLeafThreads / 64];
     int32_t* sbuf = (int32_t*)leaf_lds;
     T* rows = (T*)leaf_lds;
     const RepDesc rd = reps[blockIdx.y];
     const int64_t n_sites = rd.S;
     lam += rd.s0;
     const double* dom = dom_all + 8 * blockIdx.y;
-    const int32_t* leaf_start = leaf_start_all + (size_t)blockIdx.y * (g.nleaf + 1);
+    int32_t* leaf_start = leaf_start_all + (size_t)blockIdx.y * (g.nleaf + 1);
     T* mult = mult_all + (size_t)blockIdx.y * g.nbox * g.Kp;
     double* leaf_part = leaf_part_all + (size_t)blockIdx.y * g.nleaf * 2;
     const int leaf = blockIdx.x;
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-    const int b = leaf_start[leaf], n = leaf_start[leaf + 1] - b;
+    const bool binned = bins.bucket != nullptr;
+    // bucket binning: the site starts are scanned into LDS past the sort / P2M
+    // rows (the gather files each site atom in its site's list)
+    int32_t* sscan = (int32_t*)(leaf_lds + leaf_lds_base(g.K, (int)sizeof(T)));
+    int32_t* site_st = sscan + 256;
+    int b, n;
+    if (binned) {
+        // this leaf's first atom: the replica's first atom plus the counts of
+        // the leaves before it; the block publishes it as leaf_start
+        const int32_t* lc = lb.leaf_count + (size_t)blockIdx.y * g.nleaf;
+        int32_t pre = 0;
+        for (int l = tid; l < leaf; l += kLeafThreads) pre += lc[l];
+        n = lc[leaf];
+        pre = wave_sum<int32_t>(pre);
+        if (lane == 0) wpre[wave] = pre;
+        if (lb.S_tot > 0) block_scan_256(lb.site_count, lb.S_tot, 0, site_st, sscan);
+        else __syncthreads();
+        b = (int)rd.a0;
+#pragma unroll
+        for (int w = 0; w < kLeafThreads / 64; ++w) b += wpre[w];
+        if (tid == 0) {
+            leaf_start[leaf] = b;
+            if (leaf == g.nleaf - 1) leaf_start[g.nleaf] = b + n;
+        }
+        if (blockIdx.x == 0 && blockIdx.y == 0)
+            for (int i = tid; i <= lb.S_tot; i += kLeafThreads) lb.site_start[i] = lb.S_tot > 0 ? site_st[i] : 0;
+    } else {
+        b = leaf_start[leaf];
+        n = leaf_start[leaf + 1] - b;
+    }
+    // the leaf's atoms in rank order: from its bucket (ranks below bins.cap)
+    // and the overflow list, or from the scattered permutation
+    const int32_t* bk = binned ? bins.bucket + ((size_t)blockIdx.y * g.nleaf + leaf) * bins.cap : nullptr;
+    auto fill_members = [&](int32_t* dst) {
+        for (int r = tid; r < min(n, bins.cap); r += kLeafThreads) dst[r] = bk[r];
+        if (n > bins.cap) {
+            const int no = *bins.ovf_n;
+            for (int o = tid; o < no; o += kLeafThreads) {
+                const int32_t i = bins.ovf[o];
+                if (i >= rd.a0 && i < rd.a0 + rd.n && lb.key[i] == leaf) dst[lb.rank[i]] = i;
+            }
+        }
+    };
     const double edge = dom[3];
     const double dlo[3] = {dom[0], dom[1], dom[2]};
     load_rho_lds<T, kLeafThreads>(rho, g.p);
     const bool sorted = n <= kSortCap;
+    if (binned && !sorted) {
+        // too large to sort: the permutation in rank order, read back below
+        fill_members(perm + b);
+        __syncthreads();
+    }
     int32_t idx[kLeafIdx];
     if (n <= kLeafThreads) {
         // one atom per thread: its place in caller order is the number of the
         // leaf's (distinct) atom indices below its own
         __shared__ int32_t srt[kLeafThreads];
-        const int32_t mine_i = tid < n ? perm[b + tid] : 0;
+        const int32_t mine_i = tid < n ? (binned ? bk[tid] : perm[b + tid]) : 0;
         if (tid < n) sbuf[tid] = mine_i;
         __syncthreads();
         if (tid < n) {
@@ -596,7 +677,9 @@ __global__ __launch_bounds__(kLeafThreads) void k_leaf_p2m(
 #pragma unroll
         for (int m = 1; m < kLeafIdx; ++m) idx[m] = 0;
     } else if (sorted) {
-        for (int i = tid; i < n; i += kLeafThreads) sbuf[i] = perm[b + i];
+        if (binned) fill_members(sbuf);
+        else
+            for (int i = tid; i < n; i += kLeafThreads) sbuf[i] = perm[b + i];
         __syncthreads();
         lds_sort<kSortCap>(sbuf, n);
 #pragma unroll
@@ -626,6 +709,7 @@ __global__ __launch_bounds__(kLeafThreads) void k_leaf_p2m(
         if (sorted) perm[b + j] = i;
         const double xv[3] = {(double)x[3 * i], (double)x[3 * i + 1], (double)x[3 * i + 2]};
         const int32_t st = site[i];
+        if (binned && st >= 0 && st < n_sites) lb.site_members[site_st[rd.s0 + st] + lb.site_rank[i]] = i;
         const double a0 = (double)qA[i], b0 = (double)qB[i];
         const bool four = fa.qC != nullptr;
         const double c0 = four ? (double)fa.qC[i] : 0.0, d0 = four ? (double)fa.qD[i] : 0.0;
@@ -921,21 +1005,45 @@ __global__ __launch_bounds__(kTreeThreads) void k_m2m(Geo g, int lev, T* __restr
 // largest leaves are dispatched first and the smaller ones fill in behind
 // them (longest-processing-time order; with 512 leaves on 256 compute units
 // the unordered tail costs ~15% of the near field; ordering by the full work,
-// own atoms x neighbourhood atoms, gains < 1% more).  Key: count above the
-// leaf index (ties: lower leaf first); needs nleaf <= kOrderCap.
+// own atoms x neighbourhood atoms, gains < 1% more).  Work-groups go
+// round-robin over the 8 XCDs, so slot i runs on XCD i mod 8: when the eight
+// level-1 octants hold similar atom counts (none above 9/8 of the mean),
+// octant x's leaves take the slots of XCD x, largest first, and each XCD
+// reads one octant's neighbourhoods through its own L2; otherwise all leaves
+// go largest first.  Key: octant, count (capped at 2^16 - 1), leaf index
+// (ties: lower leaf first); needs nleaf <= kOrderCap.
 // buf: kOrderCap ints of LDS.
 constexpr int kOrderCap = 4096;
 __device__ void leaf_work_order(const Geo& g, const int32_t* __restrict__ leaf_start,
                                 int32_t* __restrict__ order, int32_t* key) {
     const int nl = g.nleaf;
-    constexpr int kMaxKey = (1 << 19) - 1;
+    constexpr int kMaxCnt = (1 << 16) - 1;
+    __shared__ int32_t oct[8];
+    const int shift = g.depth > 0 ? 3 * (g.depth - 1) : 0;
+    if (threadIdx.x < 8) oct[threadIdx.x] = 0;
+    __syncthreads();
+    if (nl >= 8)
+        for (int i = threadIdx.x; i < nl; i += blockDim.x)
+            atomicAdd(&oct[i >> shift], leaf_start[i + 1] - leaf_start[i]);
+    __syncthreads();
+    int64_t tot = 0, mx = 0;
+    for (int x = 0; x < 8; ++x) {
+        tot += oct[x];
+        mx = max(mx, (int64_t)oct[x]);
+    }
+    const bool by_xcd = nl >= 8 && 64 * mx <= 9 * tot;
     for (int i = threadIdx.x; i < nl; i += blockDim.x) {
-        const int c = min(leaf_start[i + 1] - leaf_start[i], kMaxKey);
-        key[i] = ((kMaxKey - c) << 12) | i;
+        const int c = min(leaf_start[i + 1] - leaf_start[i], kMaxCnt);
+        key[i] = (by_xcd ? (i >> shift) << 28 : 0) | ((kMaxCnt - c) << 12) | i;
     }
     __syncthreads();
     lds_sort<kOrderCap>(key, nl);
-    for (int i = threadIdx.x; i < nl; i += blockDim.x) order[i] = key[i] & (kOrderCap - 1);
+    const int per = nl >> 3;
+    for (int i = threadIdx.x; i < nl; i += blockDim.x) {
+        const int32_t leaf = key[i] & (kOrderCap - 1);
+        if (by_xcd) order[8 * (i % per) + i / per] = leaf;
+        else order[i] = leaf;
+    }
 }
 
 // Periodic root of replica rp (a block of kTreeThreads threads): mu~_0 by
@@ -2424,7 +2532,7 @@ __global__ __launch_bounds__(256) void k_reduce(Geo g, int R, int64_t nparts,
                                                 int32_t* __restrict__ site_count,
                                                 const double* __restrict__ excl_e, int excl_parts,
                                                 const double* __restrict__ cphi2,
-                                                double* __restrict__ glam) {
+                                                double* __restrict__ glam, int32_t* __restrict__ ovf_n) {
     __shared__ double red[256], red_t[256];
     __shared__ int32_t mem[kSiteCap];
     const int t = threadIdx.x;
@@ -2433,6 +2541,7 @@ __global__ __launch_bounds__(256) void k_reduce(Geo g, int R, int64_t nparts,
     // zero for the next one (the plan clears them once at creation)
     if (b < R) {
         for (int i = t; i < g.nleaf; i += 256) leaf_count[(size_t)b * g.nleaf + i] = 0;
+        if (b == 0 && t == 0 && ovf_n) *ovf_n = 0;
     } else if (t == 0) {
         site_count[b - R] = 0;
     }

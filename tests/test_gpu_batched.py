@@ -142,3 +142,46 @@ def test_graph_batched_replay():
         assert torch.equal(got["E"], ref["E"])
         assert torch.equal(got["F"], ref["F"])
         assert torch.equal(got["dVdl"], ref["dVdl"])
+
+
+def _clumped(seed, n_spread, n_clump, lo, width, n_sites=2):
+    """An open system whose atoms mostly sit in one small clump: the clump's
+    leaf holds far more atoms than the mean."""
+    rng = np.random.default_rng(seed)
+    d = W.random_open(seed, n=n_spread + n_clump, edge=3.0, n_sites=n_sites, depth=3, order=8)
+    x = d["x"].copy()
+    x[:n_clump] = lo + rng.uniform(0, width, (n_clump, 3))
+    d["x"] = x.astype(np.float32).astype(np.float64)
+    return d
+
+
+def test_crowded_leaves_in_batched_replicas():
+    """Binning with crowded leaves, in one batch: replica 1 has a leaf above
+    the bucket capacity (its extra atoms go through the overflow list), replica
+    2 a leaf above the in-LDS sort size (4096 atoms, kept in binning order);
+    every replica matches the oracle, and replicas 0 and 1 match their single
+    evaluations bitwise."""
+    import torch
+    from paper_2410_01626_amd import fmm
+    dev = torch.device("cuda:0")
+    reps = [W.random_open(81, n=2000, edge=2.5, n_sites=3, depth=3, order=8),
+            _clumped(82, 300, 700, 1.0, 0.08),
+            _clumped(83, 200, 4500, 1.0, 0.1)]
+    ao, so, cat, _ = _concat(reps)
+    plan = fmm.Plan(3, 8, periodic=False, precision="fp64", max_atoms=int(ao[-1]),
+                    max_sites=int(so[-1]), max_replicas=len(reps), device=dev)
+    out = plan.eval_batched(ao, so, *_dev(cat, plan.dtype, dev))
+    torch.cuda.synchronize()
+    for r, d in enumerate(reps):
+        a0, a1, s0, s1 = ao[r], ao[r + 1], so[r], so[r + 1]
+        got = {"E": out["E"][r].item(), "F": out["F"][a0:a1].double().cpu().numpy(),
+               "phi": out["phi"][a0:a1].double().cpu().numpy(),
+               "dVdl": out["dVdl"][s0:s1].cpu().numpy()}
+        assert_within(errors(got, reference(d)), 8, label="replica %d" % r)
+        if r < 2:
+            single = plan.eval(*_dev(d, plan.dtype, dev))
+            torch.cuda.synchronize()
+            assert out["E"][r].item() == single["E"].item(), r
+            assert torch.equal(out["F"][a0:a1], single["F"]), r
+            assert torch.equal(out["phi"][a0:a1], single["phi"]), r
+    plan.close()
