@@ -33,6 +33,9 @@ struct Workspace {
     // leaf buckets of the binning (trees of at most kScanFuseCap leaves):
     // replicas x leaves x leaf_cap atom indices, the overflow list and its length
     int32_t *bucket = nullptr, *ovf = nullptr, *ovf_n = nullptr;
+    // the leaves' M2M terms into their parents (FP64, K per leaf), when the
+    // leaf kernel takes the first M2M step
+    double* m2m_part = nullptr;
     void *mult = nullptr, *loc = nullptr;
     double *root_m = nullptr, *root_l = nullptr;
     double* root_part = nullptr;  // periodic: the 8 level-1 shares of the root multipole
@@ -217,6 +220,9 @@ size_t ws_layout(const fmm_plan_s* P, int64_t N, int64_t S, size_t RM, bool adjo
         w->bucket = w->ovf = w->ovf_n = nullptr;
     }
     take(w->mult, RM * nb * Kp * ts);
+    if (P->prm.depth - 2 >= (P->prm.boundary == FMM_PERIODIC ? 1 : 2) && nl <= (size_t)fmmk::kScanFuseCap)
+        take(w->m2m_part, RM * nl * K * 8);
+    else w->m2m_part = nullptr;
     take(w->loc, RM * nb * Kp * ts);
     take(w->root_m, RM * K * 8);
     take(w->root_l, RM * K * 8);
@@ -475,7 +481,7 @@ bool launch_m2l_mma(fmm_plan_t P, const Geo& g, int R, bool want_root) {
 template <typename T>
 void enqueue_bin_p2m(fmm_plan_t P, const fmmk::Geo& g, RepSpan rd, int R,
                      const T* x, const T* qA, const T* qB, const int32_t* site, const double* lam,
-                     const fmmk::FormArgs<T>& fa, int64_t maxn, int64_t S_tot) {
+                     const fmmk::FormArgs<T>& fa, int64_t maxn, int64_t S_tot, bool fold) {
     using namespace fmmk;
     hipStream_t st = P->stream;
     const int nstore = (int)rd.size();
@@ -530,9 +536,13 @@ void enqueue_bin_p2m(fmm_plan_t P, const fmmk::Geo& g, RepSpan rd, int R,
     const LeafBinArgs lb{P->ws.leaf_count, P->ws.key,          P->ws.rank,         P->ws.site_count,
                          P->ws.site_rank,  P->ws.site_start,   P->ws.site_members, (int)S_tot};
     const size_t lds = leaf_lds_bytes<T>(g.K) + (binned && S_tot > 0 ? (size_t)(256 + S_tot + 1) * 4 : 0);
-    k_leaf_p2m<T><<<dim3(g.nleaf, R), kLeafThreads, lds, st>>>(
+    // the folded first M2M step is its own instantiation (it needs more
+    // registers, which would lower every other launch's occupancy)
+    auto leaf = fold ? k_leaf_p2m<T, true> : k_leaf_p2m<T, false>;
+    leaf<<<dim3(g.nleaf, R), kLeafThreads, lds, st>>>(
         g, reps, x, qA, qB, site, lam, fa, P->ws.dom, P->ws.leaf_start, P->ws.perm, (V4*)P->ws.pos, P->status,
-        (T*)P->ws.mult, P->ws.leaf_part, (uint16_t*)P->ws.msplit, P->mg.KP, bins, lb);
+        (T*)P->ws.mult, P->ws.leaf_part, (uint16_t*)P->ws.msplit, P->mg.KP, bins, lb, (const T*)P->m2mT,
+        (const T*)P->m2m_seg, fold ? P->ws.m2m_part : nullptr);
 }
 
 // The tree passes of R expansion slots (grid y = slot): M2M per level, the
@@ -540,7 +550,7 @@ void enqueue_bin_p2m(fmm_plan_t P, const fmmk::Geo& g, RepSpan rd, int R,
 // downward pass into the leaves.  With want_order the downward launch's extra
 // block orders the leaves for the near field; returns that order (or null).
 template <typename T>
-int32_t* enqueue_tree(fmm_plan_t P, const fmmk::Geo& g, int R, bool want_order) {
+int32_t* enqueue_tree(fmm_plan_t P, const fmmk::Geo& g, int R, bool want_order, bool folded) {
     using namespace fmmk;
     hipStream_t st = P->stream;
     T* mult = (T*)P->ws.mult;
@@ -553,10 +563,14 @@ int32_t* enqueue_tree(fmm_plan_t P, const fmmk::Geo& g, int R, bool want_order) 
     // periodic trees whose M2L ends in a reduction launch form the root there;
     // the level-1 M2M blocks then also leave their shares of the root multipole
     const bool root_in_reduce = g.periodic && g.depth >= 1 && P->m2l_mode != 0 && P->mg.nchunk > 1;
-    for (int lev = g.depth - 1; lev >= g.lmin; --lev)
+    // folded: the leaf kernel left each leaf's term of level d - 1, and the
+    // first launch (level d - 2) forms level d - 1 from them first
+    const int top = folded ? g.depth - 2 : g.depth - 1;
+    for (int lev = top; lev >= g.lmin; --lev)
         k_m2m<T><<<dim3(1u << (3 * lev), R), kTreeThreads, 0, st>>>(
             g, lev, mult, (const T*)P->m2mT, (const T*)P->m2m_seg, P->ws.leaf_part, P->ws.box_part,
-            (uint16_t*)P->ws.msplit, P->mg.KP, root_in_reduce && lev == 1 ? P->ws.root_part : nullptr);
+            (uint16_t*)P->ws.msplit, P->mg.KP, root_in_reduce && lev == 1 ? P->ws.root_part : nullptr,
+            folded && lev == top ? P->ws.m2m_part : nullptr);
     mark(P, 3);
     if (g.periodic && g.depth == 0)
         k_root<T><<<R, 256, 0, st>>>(g, P->ws.leaf_part, P->ws.root_m, mult, P->latT, P->ws.root_l, loc,
@@ -612,8 +626,13 @@ fmm_status enqueue_eval(fmm_plan_t P, RepSpan rd, const T* x,
     if (P->excl_n > 0 && n_tot != P->excl_n)
         return fail(P, FMM_E_INVALID, "the exclusion lists were set for a different atom count");
     mark(P, 0);
-    enqueue_bin_p2m<T>(P, g, rd, R, x, qA, qB, site, lam, fa, maxn, S_tot);
-    int32_t* order = enqueue_tree<T>(P, g, R, true);
+    // the leaf kernel takes the first M2M step when a later M2M launch is
+    // left to add its terms (depth - 2 >= the coarsest interacting level) and
+    // the tree is small enough for launch latency to matter (deeper trees
+    // keep the separate launch, which then costs little next to the work)
+    const bool fold = P->ws.m2m_part != nullptr && g.depth - 2 >= g.lmin && g.nleaf <= kScanFuseCap;
+    enqueue_bin_p2m<T>(P, g, rd, R, x, qA, qB, site, lam, fa, maxn, S_tot, fold);
+    int32_t* order = enqueue_tree<T>(P, g, R, true, fold);
     const RepDesc* reps = P->ws.reps;
     const unsigned ab = nblocks(maxn, 256);
     using V4 = vec4_t<T>;
@@ -695,12 +714,12 @@ fmm_status enqueue_adjoint_full(fmm_plan_t P, const fmmk::RepDesc& r0, const T* 
     const RepSpan rd(rd2, 2);
     const FormArgs<T> fa{nullptr, nullptr, nullptr};
     mark(P, 0);
-    enqueue_bin_p2m<T>(P, g, rd, 1, x, qA, qB, site, lam, fa, n, S);
+    enqueue_bin_p2m<T>(P, g, rd, 1, x, qA, qB, site, lam, fa, n, S, false);
     using V4 = vec4_t<T>;
     k_leaf_src2<T><<<g.nleaf, kLeafThreads, src2_lds_bytes<T>(g.K), st>>>(
         g, (const V4*)P->ws.pos, P->ws.perm, P->ws.leaf_start, gphi, gF, P->ws.dom, (V4*)P->ws.adj_src2, (T*)P->ws.mult,
         P->ws.leaf_part, (uint16_t*)P->ws.msplit, P->mg.KP);
-    enqueue_tree<T>(P, g, 2, false);
+    enqueue_tree<T>(P, g, 2, false, false);
     mark(P, 6);
     k_near_adj<T><<<g.nleaf, kAdjThreads, 0, st>>>(g, (const V4*)P->ws.pos, (const V4*)P->ws.adj_src2,
                                                    P->ws.leaf_start, P->ws.perm, P->ws.dom, (const T*)P->ws.loc,
@@ -1102,13 +1121,14 @@ fmm_status fmm_plan_create(const fmm_params* prm, void* hip_stream, fmm_plan_t* 
         }
         if (ea != hipSuccess) e = ea;
     }
-    if (e == hipSuccess) {
-        e = P->fp64 ? hipFuncSetAttribute((const void*)&fmmk::k_leaf_p2m<double>,
-                                          hipFuncAttributeMaxDynamicSharedMemorySize,
-                                          (int)leaf_lds_bytes_max<double>((int)K))
-                    : hipFuncSetAttribute((const void*)&fmmk::k_leaf_p2m<float>,
-                                          hipFuncAttributeMaxDynamicSharedMemorySize,
-                                          (int)leaf_lds_bytes_max<float>((int)K));
+    for (int fold = 0; fold < 2 && e == hipSuccess; ++fold) {
+        const void* f = P->fp64 ? (fold ? (const void*)&fmmk::k_leaf_p2m<double, true>
+                                        : (const void*)&fmmk::k_leaf_p2m<double, false>)
+                                : (fold ? (const void*)&fmmk::k_leaf_p2m<float, true>
+                                        : (const void*)&fmmk::k_leaf_p2m<float, false>);
+        e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                P->fp64 ? (int)leaf_lds_bytes_max<double>((int)K)
+                                        : (int)leaf_lds_bytes_max<float>((int)K));
     }
     if (e == hipSuccess) {
         e = P->fp64 ? hipFuncSetAttribute((const void*)&fmmk::k_leaf_src2<double>,

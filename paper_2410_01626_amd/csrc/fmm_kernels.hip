@@ -570,6 +570,115 @@ __device__ void lds_sort(int32_t* v, int n) {
         }
 }
 
+// ------------------------------------------------------------------ tree operators
+//
+// The eight child-octant operators of M2M (and of L2L) are one operator seen
+// through the reflections of the axes: reflecting x, y or z maps every real
+// harmonic onto +-itself, so A_c = S_c A_0 S_c with S_c diagonal +-1 (exactly,
+// entry by entry).  The tree kernels (and the leaf kernel's first M2M step)
+// load rows of the octant-0 operator once and apply them to signed children.
+
+// Reflection parity of real coefficient k: bit 2 set when the coefficient
+// changes sign under x -> -x, bit 1 under y -> -y, bit 0 under z -> -z.  The
+// octant index c = 4 bx + 2 by + bz flips the axes whose bit is set, so the
+// sign of coefficient k for octant c is (-1)^popcount(c & bits).
+__device__ __forceinline__ int refl_bits(int k) {
+    const int l = (int)sqrtf((float)k + 0.5f);
+    const int rem = k - l * l;
+    const int m = (rem + 1) >> 1;
+    const int sn = (rem > 0 && !(rem & 1)) ? 1 : 0;  // sine part
+    const int xo = sn ? !(m & 1) : (m & 1);
+    return (xo << 2) | (sn << 1) | ((l + m) & 1);
+}
+__device__ __forceinline__ double refl_sign(int c, int bits) {
+    return (__popc((unsigned)(c & bits)) & 1) ? -1.0 : 1.0;
+}
+
+
+// One thread's share of a degree-triangular K x K operator A (given
+// transposed, At[k K + r]): a row r and a contiguous k range [kb, ke) of it.
+// Output degree l takes input degrees <= l (M2M, kTriLower), >= l (L2L,
+// kTriUpper) or all (kTriFull).  Each row is cut into nseg = 512 / K
+// segments (at most 8), so a block of kTreeThreads holds every (segment,
+// row) pair once.  The first kTriCache entries of the range are loaded once
+// into registers and reused by every product the block forms.
+// The register cache comes from a table packed on the host in the same
+// thread order (entry j of thread t at j kTreeThreads + t, zero past the
+// range), so its loads are coalesced.
+template <typename TO, int kShape, int kCache = kTriCache>
+struct TriPart {
+    int r, s, kb, ke;
+    TO a[kCache];
+    __device__ __forceinline__ void load(int K, const TO* __restrict__ packed) {
+        load(K, packed, (int)threadIdx.x);
+    }
+    // the share of (virtual) thread it < kTreeThreads
+    __device__ __forceinline__ void load(int K, const TO* __restrict__ packed, int it) {
+        const int nseg = tri_nseg(K);
+        const int slen = (K + nseg - 1) / nseg;
+        r = -1;
+        s = kb = ke = 0;
+        if (it < nseg * K) {
+            s = it / K;
+            r = it - s * K;
+            const int l = (int)sqrtf((float)r + 0.5f);
+            kb = max(s * slen, kShape == kTriUpper ? l * l : 0);
+            ke = min(min(K, (s + 1) * slen), kShape == kTriLower ? (l + 1) * (l + 1) : K);
+        }
+#pragma unroll
+        for (int j = 0; j < kCache; ++j) a[j] = packed[j * kTreeThreads + it];
+    }
+};
+
+// ys[c][r] = sum_k A[r][k] xs[c][k] for the NC right-hand sides in LDS
+// (FP64), with the thread's part of A from `tp` and any entries past the
+// register cache loaded 16 at a time.  Segment sums are added in a fixed
+// order.  part: LDS scratch of kTreeThreads * NC doubles; ys may alias xs.
+// The (segment, row) share of one thread: part[(s NC + c) K + r] =
+// sum_{k in [kb, ke)} A[r][k] xs[c][k] (FP64, k ascending).
+template <typename TO, int NC, int kShape, int kCache>
+__device__ __forceinline__ void tri_dot(const TriPart<TO, kShape, kCache>& tp, int K, const TO* __restrict__ At,
+                                        const double* xs, double* part) {
+    if (tp.r < 0) return;
+    double acc[NC];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) acc[c] = 0.0;
+    const int n = tp.ke - tp.kb;
+#pragma unroll
+    for (int j = 0; j < kCache; ++j)
+        if (j < n)
+#pragma unroll
+            for (int c = 0; c < NC; ++c) acc[c] += (double)tp.a[j] * xs[c * K + tp.kb + j];
+    for (int k0 = tp.kb + kCache; k0 < tp.ke; k0 += 16) {
+        TO a[16];
+#pragma unroll
+        for (int j = 0; j < 16; ++j) a[j] = At[(size_t)min(k0 + j, tp.ke - 1) * K + tp.r];
+#pragma unroll
+        for (int j = 0; j < 16; ++j) {
+            const int k = min(k0 + j, tp.ke - 1);
+            const double aj = (k0 + j < tp.ke) ? (double)a[j] : 0.0;
+#pragma unroll
+            for (int c = 0; c < NC; ++c) acc[c] += aj * xs[c * K + k];
+        }
+    }
+#pragma unroll
+    for (int c = 0; c < NC; ++c) part[(tp.s * NC + c) * K + tp.r] = acc[c];
+}
+
+template <typename TO, int NC, int kShape>
+__device__ void tri_matvec(const TriPart<TO, kShape>& tp, int K, const TO* __restrict__ At, double* xs,
+                           double* part, double* ys) {
+    const int nseg = tri_nseg(K);
+    tri_dot<TO, NC, kShape, kTriCache>(tp, K, At, xs, part);
+    __syncthreads();
+    for (int it = threadIdx.x; it < NC * K; it += kTreeThreads) {
+        double v = 0.0;
+        for (int s = 0; s < nseg; ++s) v += part[s * NC * K + it];
+        ys[it] = v;
+    }
+    __syncthreads();
+}
+
 // Per leaf, one block of 256 threads: sort the leaf's atoms by caller index
 // (stable binning; leaves of up to 256 atoms by counting ranks, larger ones by
 // a bitonic sort), gather (x - c_leaf, q) into the sorted particle array with
@@ -581,21 +690,27 @@ __device__ void lds_sort(int32_t* v, int n) {
 // row, and thread k then sums column k in atom order.  The row buffer reuses
 // the sort buffer once the sorted indices are in registers.  Periodic: also per-leaf FP64 partial sums
 // of q |t/L|^2 and q (t relative to the cell centre).  Dynamic LDS:
-// max(kSortCap ints, 64 x (K + 1) elements of T).
+// max(kSortCap ints, 64 x (K + 1) elements of T), then with bucket binning
+// and sites 256 + S + 1 ints for the site scan.
 constexpr int kLeafThreads = 256;
+// operator entries a leaf thread keeps per share for the folded M2M step
+// (p = 8: segments of 14 entries fit; longer ones load the rest on use)
+constexpr int kLeafTriCache = 16;
 constexpr int kLeafIdx = kSortCap / kLeafThreads;  // sorted indices per thread
-template <typename T>
+template <typename T, bool FOLD>
 __global__ __launch_bounds__(kLeafThreads) void k_leaf_p2m(
     Geo g, const RepDesc* __restrict__ reps, const T* __restrict__ x, const T* __restrict__ qA,
     const T* __restrict__ qB, const int32_t* __restrict__ site, const double* __restrict__ lam,
     FormArgs<T> fa, const double* __restrict__ dom_all, int32_t* __restrict__ leaf_start_all,
     int32_t* __restrict__ perm, vec4_t<T>* __restrict__ pos, int32_t* __restrict__ status,
     T* __restrict__ mult_all, double* __restrict__ leaf_part_all, uint16_t* __restrict__ msplit_all,
-    int split_kp, Bins bins, LeafBinArgs lb) {
+    int split_kp, Bins bins, LeafBinArgs lb, const T* __restrict__ m2m0, const T* __restrict__ m2m0_seg,
+    double* __restrict__ m2m_part_all) {
+    static_assert(2 * kLeafThreads == kTreeThreads, "two tree-operator shares per leaf thread");
     extern __shared__ __align__(16) unsigned char leaf_lds[];
     __shared__ RhoLds<T> rho;
     __shared__ double ps[2][kLeafThreads / 64];
-    __shared__ int32_t wpre[kLeafThreads / 64];
+    __shared__ int32_t wpre[kLeafThreads / 64], wsite[kLeafThreads / 64];
     int32_t* sbuf = (int32_t*)leaf_lds;
     T* rows = (T*)leaf_lds;
     const RepDesc rd = reps[blockIdx.y];
@@ -612,34 +727,58 @@ __global__ __launch_bounds__(kLeafThreads) void k_leaf_p2m(
     // rows (the gather files each site atom in its site's list)
     int32_t* sscan = (int32_t*)(leaf_lds + leaf_lds_base(g.K, (int)sizeof(T)));
     int32_t* site_st = sscan + 256;
+    // the leaf's atoms in rank order: from its bucket (ranks below bins.cap)
+    // and the overflow list, or from the scattered permutation
+    const int32_t* bk = binned ? bins.bucket + ((size_t)blockIdx.y * g.nleaf + leaf) * bins.cap : nullptr;
+    int32_t mine_b = 0;
     int b, n;
     if (binned) {
-        // this leaf's first atom: the replica's first atom plus the counts of
-        // the leaves before it; the block publishes it as leaf_start
+        // every load first: the bucket slot of this thread (all slots below
+        // bins.cap >= kLeafThreads exist; used where tid < n), the counts of
+        // the leaves before this one and its own, and one site count per
+        // thread when they fit
         const int32_t* lc = lb.leaf_count + (size_t)blockIdx.y * g.nleaf;
+        mine_b = bk[tid];
+        const bool one_pass = lb.S_tot <= kLeafThreads;
+        const int32_t sc = (one_pass && tid < lb.S_tot) ? lb.site_count[tid] : 0;
         int32_t pre = 0;
         for (int l = tid; l < leaf; l += kLeafThreads) pre += lc[l];
         n = lc[leaf];
+        // this leaf's first atom: the replica's first atom plus the counts of
+        // the leaves before it (published as leaf_start); the site starts by
+        // a scan of the counts, within each wavefront by shuffles
         pre = wave_sum<int32_t>(pre);
-        if (lane == 0) wpre[wave] = pre;
-        if (lb.S_tot > 0) block_scan_256(lb.site_count, lb.S_tot, 0, site_st, sscan);
-        else __syncthreads();
-        b = (int)rd.a0;
+        int32_t inc = sc;
 #pragma unroll
-        for (int w = 0; w < kLeafThreads / 64; ++w) b += wpre[w];
+        for (int off = 1; off < 64; off <<= 1) {
+            const int32_t u = __shfl_up(inc, off, 64);
+            if (lane >= off) inc += u;
+        }
+        if (lane == 0) wpre[wave] = pre;
+        if (lane == 63) wsite[wave] = inc;
+        __syncthreads();
+        b = (int)rd.a0;
+        int32_t sbase = 0;
+#pragma unroll
+        for (int w = 0; w < kLeafThreads / 64; ++w) {
+            b += wpre[w];
+            sbase += w < wave ? wsite[w] : 0;
+        }
         if (tid == 0) {
             leaf_start[leaf] = b;
             if (leaf == g.nleaf - 1) leaf_start[g.nleaf] = b + n;
         }
-        if (blockIdx.x == 0 && blockIdx.y == 0)
-            for (int i = tid; i <= lb.S_tot; i += kLeafThreads) lb.site_start[i] = lb.S_tot > 0 ? site_st[i] : 0;
+        if (one_pass) {
+            if (tid < lb.S_tot) site_st[tid] = sbase + inc - sc;
+            if (tid == lb.S_tot - 1) site_st[lb.S_tot] = sbase + inc;
+        } else {
+            block_scan_256(lb.site_count, lb.S_tot, 0, site_st, sscan);
+        }
+        // site_st is read after the barriers below
     } else {
         b = leaf_start[leaf];
         n = leaf_start[leaf + 1] - b;
     }
-    // the leaf's atoms in rank order: from its bucket (ranks below bins.cap)
-    // and the overflow list, or from the scattered permutation
-    const int32_t* bk = binned ? bins.bucket + ((size_t)blockIdx.y * g.nleaf + leaf) * bins.cap : nullptr;
     auto fill_members = [&](int32_t* dst) {
         for (int r = tid; r < min(n, bins.cap); r += kLeafThreads) dst[r] = bk[r];
         if (n > bins.cap) {
@@ -650,6 +789,14 @@ __global__ __launch_bounds__(kLeafThreads) void k_leaf_p2m(
             }
         }
     };
+    // folded first M2M step: this thread's two (segment, row) shares of the
+    // octant-0 operator, loaded now so that they are in registers at the end
+    // (only this instantiation pays the registers)
+    TriPart<T, kTriLower, kLeafTriCache> tpa, tpb;
+    if constexpr (FOLD) {
+        tpa.load(g.K, m2m0_seg, tid);
+        tpb.load(g.K, m2m0_seg, tid + kLeafThreads);
+    }
     const double edge = dom[3];
     const double dlo[3] = {dom[0], dom[1], dom[2]};
     load_rho_lds<T, kLeafThreads>(rho, g.p);
@@ -664,7 +811,7 @@ __global__ __launch_bounds__(kLeafThreads) void k_leaf_p2m(
         // one atom per thread: its place in caller order is the number of the
         // leaf's (distinct) atom indices below its own
         __shared__ int32_t srt[kLeafThreads];
-        const int32_t mine_i = tid < n ? (binned ? bk[tid] : perm[b + tid]) : 0;
+        const int32_t mine_i = tid < n ? (binned ? mine_b : perm[b + tid]) : 0;
         if (tid < n) sbuf[tid] = mine_i;
         __syncthreads();
         if (tid < n) {
@@ -693,6 +840,8 @@ __global__ __launch_bounds__(kLeafThreads) void k_leaf_p2m(
         for (int m = 0; m < kLeafIdx; ++m) idx[m] = 0;
     }
     __syncthreads();  // sorted indices are in registers: the LDS is free for P2M rows
+    if (binned && blockIdx.x == 0 && blockIdx.y == 0)
+        for (int i = tid; i <= lb.S_tot; i += kLeafThreads) lb.site_start[i] = lb.S_tot > 0 ? site_st[i] : 0;
     const double h = edge / g.nb;
     const T ih = (T)(1.0 / h);
     int cx, cy, cz;
@@ -803,107 +952,30 @@ __global__ __launch_bounds__(kLeafThreads) void k_leaf_p2m(
         leaf_part[2 * leaf] = a2;
         leaf_part[2 * leaf + 1] = aq;
     }
+    if constexpr (FOLD) {
+        // the leaf's term of its parent's multipole, s_c(r) (A_0 S_c mu)[r]
+        // for child octant c (FP64, the tree kernels' segment split and sum
+        // order); the next M2M launch adds the eight terms of every parent.
+        // This thread takes the tree kernels' (segment, row) shares tid and
+        // tid + kLeafThreads.
+        double* xsm = (double*)leaf_lds;  // K doubles, then nseg K doubles
+        double* pm = xsm + g.K;
+        const int c = leaf & 7;
+        if (tid < g.K) xsm[tid] = refl_sign(c, refl_bits(tid)) * (double)acc;
+        __syncthreads();
+        tri_dot<T, 1, kTriLower, kLeafTriCache>(tpa, g.K, m2m0, xsm, pm);
+        tri_dot<T, 1, kTriLower, kLeafTriCache>(tpb, g.K, m2m0, xsm, pm);
+        __syncthreads();
+        if (tid < g.K) {
+            const int nseg = tri_nseg(g.K);
+            double v = 0.0;
+            for (int sg = 0; sg < nseg; ++sg) v += pm[sg * g.K + tid];
+            m2m_part_all[((size_t)blockIdx.y * g.nleaf + leaf) * g.K + tid] = refl_sign(c, refl_bits(tid)) * v;
+        }
+    }
 }
 
 // ------------------------------------------------------------------ tree passes
-//
-// The eight child-octant operators of M2M (and of L2L) are one operator seen
-// through the reflections of the axes: reflecting x, y or z maps every real
-// harmonic onto +-itself, so A_c = S_c A_0 S_c with S_c diagonal +-1 (exactly,
-// entry by entry).  The tree kernels load rows of the octant-0 operator once
-// and apply them to all eight signed children.
-
-
-// Reflection parity of real coefficient k: bit 2 set when the coefficient
-// changes sign under x -> -x, bit 1 under y -> -y, bit 0 under z -> -z.  The
-// octant index c = 4 bx + 2 by + bz flips the axes whose bit is set, so the
-// sign of coefficient k for octant c is (-1)^popcount(c & bits).
-__device__ __forceinline__ int refl_bits(int k) {
-    const int l = (int)sqrtf((float)k + 0.5f);
-    const int rem = k - l * l;
-    const int m = (rem + 1) >> 1;
-    const int sn = (rem > 0 && !(rem & 1)) ? 1 : 0;  // sine part
-    const int xo = sn ? !(m & 1) : (m & 1);
-    return (xo << 2) | (sn << 1) | ((l + m) & 1);
-}
-__device__ __forceinline__ double refl_sign(int c, int bits) {
-    return (__popc((unsigned)(c & bits)) & 1) ? -1.0 : 1.0;
-}
-
-
-// One thread's share of a degree-triangular K x K operator A (given
-// transposed, At[k K + r]): a row r and a contiguous k range [kb, ke) of it.
-// Output degree l takes input degrees <= l (M2M, kTriLower), >= l (L2L,
-// kTriUpper) or all (kTriFull).  Each row is cut into nseg = 512 / K
-// segments (at most 8), so a block of kTreeThreads holds every (segment,
-// row) pair once.  The first kTriCache entries of the range are loaded once
-// into registers and reused by every product the block forms.
-// The register cache comes from a table packed on the host in the same
-// thread order (entry j of thread t at j kTreeThreads + t, zero past the
-// range), so its loads are coalesced.
-template <typename TO, int kShape>
-struct TriPart {
-    int r, s, kb, ke;
-    TO a[kTriCache];
-    __device__ __forceinline__ void load(int K, const TO* __restrict__ packed) {
-        const int nseg = tri_nseg(K);
-        const int slen = (K + nseg - 1) / nseg;
-        const int it = threadIdx.x;
-        r = -1;
-        s = kb = ke = 0;
-        if (it < nseg * K) {
-            s = it / K;
-            r = it - s * K;
-            const int l = (int)sqrtf((float)r + 0.5f);
-            kb = max(s * slen, kShape == kTriUpper ? l * l : 0);
-            ke = min(min(K, (s + 1) * slen), kShape == kTriLower ? (l + 1) * (l + 1) : K);
-        }
-#pragma unroll
-        for (int j = 0; j < kTriCache; ++j) a[j] = packed[j * kTreeThreads + it];
-    }
-};
-
-// ys[c][r] = sum_k A[r][k] xs[c][k] for the NC right-hand sides in LDS
-// (FP64), with the thread's part of A from `tp` and any entries past the
-// register cache loaded 16 at a time.  Segment sums are added in a fixed
-// order.  part: LDS scratch of kTreeThreads * NC doubles; ys may alias xs.
-template <typename TO, int NC, int kShape>
-__device__ void tri_matvec(const TriPart<TO, kShape>& tp, int K, const TO* __restrict__ At, double* xs,
-                           double* part, double* ys) {
-    const int nseg = tri_nseg(K);
-    if (tp.r >= 0) {
-        double acc[NC];
-#pragma unroll
-        for (int c = 0; c < NC; ++c) acc[c] = 0.0;
-        const int n = tp.ke - tp.kb;
-#pragma unroll
-        for (int j = 0; j < kTriCache; ++j)
-            if (j < n)
-#pragma unroll
-                for (int c = 0; c < NC; ++c) acc[c] += (double)tp.a[j] * xs[c * K + tp.kb + j];
-        for (int k0 = tp.kb + kTriCache; k0 < tp.ke; k0 += 16) {
-            TO a[16];
-#pragma unroll
-            for (int j = 0; j < 16; ++j) a[j] = At[(size_t)min(k0 + j, tp.ke - 1) * K + tp.r];
-#pragma unroll
-            for (int j = 0; j < 16; ++j) {
-                const int k = min(k0 + j, tp.ke - 1);
-                const double aj = (k0 + j < tp.ke) ? (double)a[j] : 0.0;
-#pragma unroll
-                for (int c = 0; c < NC; ++c) acc[c] += aj * xs[c * K + k];
-            }
-        }
-#pragma unroll
-        for (int c = 0; c < NC; ++c) part[(tp.s * NC + c) * K + tp.r] = acc[c];
-    }
-    __syncthreads();
-    for (int it = threadIdx.x; it < NC * K; it += kTreeThreads) {
-        double v = 0.0;
-        for (int s = 0; s < nseg; ++s) v += part[s * NC * K + it];
-        ys[it] = v;
-    }
-    __syncthreads();
-}
 
 // First box of level l in the level-major box order: (8^l - 1) / 7.
 __device__ __forceinline__ int64_t lev_offset(int l) { return (((int64_t)1 << (3 * l)) - 1) / 7; }
@@ -943,6 +1015,54 @@ __device__ __forceinline__ void gather_children(const Geo& g, int clev, int64_t 
     if (g.periodic && threadIdx.x < 16) ps[threadIdx.x] = pv;
 }
 
+// As gather_children for the children (level d - 1) of level-(d - 2) box
+// `box` when the leaf kernel has left each leaf's signed M2M term in part
+// (K doubles per leaf): child c = sum over its eight leaves, in octant order,
+// stored (T, its bf16 split, periodic partial sums) before it is used.
+template <typename T>
+__device__ __forceinline__ void gather_children_parts(const Geo& g, int64_t box, const double* part, T* mult,
+                                                      const double* leaf_part, double* box_part,
+                                                      uint16_t* msplit, int split_kp, double* xs,
+                                                      double* ps) {
+    const int K = g.K, clev = g.depth - 1;
+    const double* src = part + (size_t)64 * box * K;
+    double v[kGatherPer];
+#pragma unroll
+    for (int m = 0; m < kGatherPer; ++m) {
+        const int i = min((int)threadIdx.x + m * kTreeThreads, 8 * K - 1);
+        const int c = i / K, k = i - c * K;
+        double t[8];
+#pragma unroll
+        for (int c2 = 0; c2 < 8; ++c2) t[c2] = src[(size_t)(8 * c + c2) * K + k];
+        double a = 0.0;
+#pragma unroll
+        for (int c2 = 0; c2 < 8; ++c2) a += t[c2];
+        v[m] = a;
+    }
+    double pv = 0.0;
+    if (g.periodic && threadIdx.x < 16) {
+        const int c = threadIdx.x >> 1, w = threadIdx.x & 1;
+        for (int c2 = 0; c2 < 8; ++c2) pv += leaf_part[2 * (64 * box + 8 * c + c2) + w];
+    }
+    const int64_t cb = g.lev_off[clev] + 8 * box;
+#pragma unroll
+    for (int m = 0; m < kGatherPer; ++m) {
+        const int i = threadIdx.x + m * kTreeThreads;
+        if (i < 8 * K) {
+            const int c = i / K, k = i - c * K;
+            const T tv = (T)v[m];
+            mult[(size_t)(cb + c) * g.Kp + k] = tv;
+            if constexpr (sizeof(T) == 4)
+                if (msplit) store_split(msplit, split_kp, cb + c, k, (float)tv);
+            xs[i] = refl_sign(c, refl_bits(k)) * (double)tv;
+        }
+    }
+    if (g.periodic && threadIdx.x < 16) {
+        ps[threadIdx.x] = pv;
+        box_part[2 * (cb + (threadIdx.x >> 1)) + (threadIdx.x & 1)] = pv;
+    }
+}
+
 // parent[r] = sum_c s_c(r) (A_0 S_c mu_c)[r] from the products in ys.
 __device__ __forceinline__ double combine_octants(const double* ys, int K, int r) {
     const int b = refl_bits(r);
@@ -963,15 +1083,23 @@ __global__ __launch_bounds__(kTreeThreads) void k_m2m(Geo g, int lev, T* __restr
                                                       const double* __restrict__ leaf_part_all,
                                                       double* __restrict__ box_part_all,
                                                       uint16_t* __restrict__ msplit_all, int split_kp,
-                                                      double* __restrict__ root_part_all) {
+                                                      double* __restrict__ root_part_all,
+                                                      const double* __restrict__ m2m_part_all) {
     __shared__ double xs[8 * kKMax], part[8 * kTreeThreads], ps[16], vb[kKMax];
     TriPart<T, kTriLower> tp;
     tp.load(g.K, op0_seg);
     const int rp = blockIdx.y, K = g.K, box = blockIdx.x;
     T* mult = mult_all + (size_t)rp * g.nbox * g.Kp;
     double* box_part = box_part_all + (size_t)rp * g.nbox * 2;
-    gather_children<T>(g, lev + 1, 8 * (int64_t)box, mult, leaf_part_all + (size_t)rp * g.nleaf * 2,
-                       box_part, xs, ps);
+    if (m2m_part_all)
+        // lev = d - 2: the children's multipoles from the leaves' M2M terms
+        gather_children_parts<T>(g, box, m2m_part_all + (size_t)rp * g.nleaf * K, mult,
+                                 leaf_part_all + (size_t)rp * g.nleaf * 2, box_part,
+                                 msplit_all ? msplit_all + (size_t)rp * (g.nbox + 1) * 2 * split_kp : nullptr,
+                                 split_kp, xs, ps);
+    else
+        gather_children<T>(g, lev + 1, 8 * (int64_t)box, mult, leaf_part_all + (size_t)rp * g.nleaf * 2,
+                           box_part, xs, ps);
     __syncthreads();
     tri_matvec<T, 8, kTriLower>(tp, K, op0, xs, part, xs);
     const int64_t gb = g.lev_off[lev] + box;
