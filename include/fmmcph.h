@@ -88,7 +88,9 @@ typedef enum { FMM_FP64 = 0, FMM_MIXED_F32 = 1, FMM_MIXED_BF16X3 = 2 } fmm_preci
  *   max_replicas largest replica count of fmm_eval_batched (>= 1)
  *   check       1 = run the device-side input checks described above
  *   m2l_kernel  0 = automatic, 1 = plain (vector ALU) M2L, 2 = matrix-core M2L
- *               (available for p <= 10; FP64 needs p <= 8)
+ *               (available for p <= 10; FP64 needs p <= 8), 3 = matrix-core M2L
+ *               that copies every column's source per offset even where the
+ *               bf16x3 kernel could keep a class's sources resident (depth <= 3)
  *   m2l_chunk   offsets per matrix-core M2L work-group (0 = automatic, else 1..189)
  *   p2p_waves   wavefronts per near-field block: 4, 8 or 16 (0 = 8)
  *   p2p_split   near-field blocks per leaf, 1 to 4 (0 = 1): with more than one,

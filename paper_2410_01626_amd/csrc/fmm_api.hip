@@ -103,6 +103,7 @@ struct fmm_plan_s {
     void *bank_mma = nullptr;
     void* sign_tab = nullptr;  // bf16x3: reflection sign-bit masks [class][k chunk of 8]
     int m2l_nbuf = 1;        // bf16x3: LDS staging buffers (2: copy of the next offset overlaps)
+    bool m2l_rs = false;     // bf16x3 with resident sources (one tile per class, parity-group chunks)
     std::vector<void*> allocs;
     size_t ws_bytes = 0;
     std::string err;
@@ -419,6 +420,16 @@ size_t src2_lds_bytes(int K) {
 
 inline unsigned nblocks(int64_t n, int b) { return (unsigned)std::max<int64_t>(1, (n + b - 1) / b); }
 
+// The resident-source bf16x3 M2L for a row-tile count whose static staging
+// fits the LDS (up to 7 row tiles: p <= 9).
+template <int RTV>
+void launch_m2l_rs(fmm_plan_t P, const Geo& g, const fmmk::M2LGeom& mg, dim3 nt, float* loc, float* part) {
+    if constexpr (RTV <= fmmk::kM2LRsMaxRT)
+        fmmk::k_m2l_bf16x3_rs<RTV><<<nt, fmmk::kM2LThreads, 0, P->stream>>>(
+            g, mg, P->tasks, P->olist, (const uint4*)P->ws.msplit, (const uint4*)P->bank_mma,
+            (const uint4*)P->sign_tab, loc, part);
+}
+
 // Matrix-core M2L launch: the kernel instance for the plan's precision and row
 // tile count, then the fixed-order chunk reduction.
 template <typename T>
@@ -446,7 +457,10 @@ bool launch_m2l_mma(fmm_plan_t P, const Geo& g, int R, bool want_root) {
         break;
 #define FMM_M2L_BF(RTV)                                                                         \
     case 48 + RTV:                                                                              \
-        k_m2l_bf16x3<RTV><<<nt, kM2LThreads, lds, st>>>(g, mg, P->tasks, P->olist, P->cstart,   \
+        if (P->m2l_rs)                                                                          \
+            launch_m2l_rs<RTV>(P, g, mg, nt, (float*)loc, (float*)part);                         \
+        else                                                                                    \
+            k_m2l_bf16x3<RTV><<<nt, kM2LThreads, lds, st>>>(g, mg, P->tasks, P->olist, P->cstart, \
                                                 (const uint4*)P->ws.msplit,                        \
                                                 (const uint4*)P->bank_mma, P->m2l_nbuf,         \
                                                 (const uint4*)P->sign_tab, (float*)loc,         \
@@ -830,7 +844,7 @@ fmm_status fmm_plan_create(const fmm_params* prm, void* hip_stream, fmm_plan_t* 
         (prm->precision != FMM_FP64 && prm->precision != FMM_MIXED_F32 &&
          prm->precision != FMM_MIXED_BF16X3) ||
         !std::isfinite(prm->coulomb_k) || prm->max_atoms > INT32_MAX ||
-        prm->m2l_kernel < 0 || prm->m2l_kernel > 2 || prm->m2l_chunk < 0 || prm->m2l_chunk > 189 ||
+        prm->m2l_kernel < 0 || prm->m2l_kernel > 3 || prm->m2l_chunk < 0 || prm->m2l_chunk > 189 ||
         (prm->p2p_waves != 0 && prm->p2p_waves != 4 && prm->p2p_waves != 8 &&
          prm->p2p_waves != 16) || prm->graph < 0 || prm->graph > 1 || prm->p2p_split < 0 ||
         prm->p2p_split > fmmk::kMaxSplit || prm->hamiltonian < 0 || prm->hamiltonian > 1)
@@ -838,7 +852,7 @@ fmm_status fmm_plan_create(const fmm_params* prm, void* hip_stream, fmm_plan_t* 
     {
         const int K = (prm->order_p + 1) * (prm->order_p + 1);
         const bool mma_ok = K <= 16 * fmmk::kM2LMaxRT && (prm->precision != FMM_FP64 || K <= 96);
-        if (prm->m2l_kernel == 2 && !mma_ok) return FMM_E_INVALID;
+        if (prm->m2l_kernel >= 2 && !mma_ok) return FMM_E_INVALID;
     }
     fmm_plan_s* P = new fmm_plan_s();
     P->prm = *prm;
@@ -970,8 +984,26 @@ fmm_status fmm_plan_create(const fmm_params* prm, void* hip_stream, fmm_plan_t* 
         mg.nt_all = nt_all;
         const int ntile = (int)((ncol + fmmk::kM2LTile - 1) / fmmk::kM2LTile);
         const int64_t items = 8 * (int64_t)ntile * (int64_t)RT;
+        // bf16x3 with one tile per class: resident sources, chunks within the
+        // canonical offsets' parity groups
+        P->m2l_rs = P->m2l_mode == 3 && ntile == 1 && prm->m2l_kernel != 3 && P->m2l_rt <= fmmk::kM2LRsMaxRT &&
+                    mg.KP / 8 == fmmk::m2l_rs_kc(P->m2l_rt);
+        // chunks of the parity groups (sizes of class 0's list: 26, 3 x 25,
+        // 3 x 23, 19) for a chunk size
+        auto rs_chunks = [](int cs) {
+            const int gs[8] = {26, 25, 25, 25, 23, 23, 23, 19};
+            int n = 0;
+            for (int gz : gs) n += (gz + cs - 1) / cs;
+            return n;
+        };
         int csize = prm->m2l_chunk;
-        if (csize == 0) {
+        if (csize == 0 && P->m2l_rs) {
+            // about one work-group per CU over all replicas: the smallest chunk
+            // size with at most 256 work-groups (7 for one replica: 31 chunks
+            // per class, 248 work-groups), at least one chunk per group
+            csize = 1;
+            while (csize < 26 && 8 * (int64_t)RT * rs_chunks(csize) > 256) ++csize;
+        } else if (csize == 0) {
             // bf16x3 runs one double-buffered work-group per CU: about one task per CU;
             // the others overlap two single-buffered work-groups per CU
             const int64_t target = P->m2l_mode == 3 ? 256 : 2048, cap = P->m2l_mode == 3 ? 63 : 27;
@@ -980,6 +1012,13 @@ fmm_status fmm_plan_create(const fmm_params* prm, void* hip_stream, fmm_plan_t* 
         }
         mg.csize = csize;
         mg.nchunk = (189 + csize - 1) / csize;
+        // resident sources: the canonical offsets ordered by parity group
+        // (x, y, z parities of o' = (oi / 49 - 3, (oi / 7) % 7 - 3, oi % 7 - 3)),
+        // each group cut into near-equal chunks of at most csize
+        std::vector<int> rs_bound;  // chunk boundaries in list positions
+        auto parity = [](int oi) {
+            return (((oi / 49 - 3) & 1) << 2) | ((((oi / 7) % 7 - 3) & 1) << 1) | ((oi % 7 - 3) & 1);
+        };
         // Offset chunks are contiguous ranges of the global (bank-index sorted)
         // offset set, so a chunk's operators are the same for every class; each
         // class takes the part of its 189 offsets that falls in the range.
@@ -992,7 +1031,26 @@ fmm_status fmm_plan_create(const fmm_params* prm, void* hip_stream, fmm_plan_t* 
                 if (seen[o]) used.push_back(o);
         }
         std::vector<int16_t> cstart(8 * (mg.nchunk + 1));
-        if (P->m2l_mode == 3) {
+        if (P->m2l_mode == 3 && P->m2l_rs) {
+            std::sort(cls_off.begin(), cls_off.begin() + 189, [&](int16_t a, int16_t b) {
+                const int pa = parity(a), pb = parity(b);
+                return pa != pb ? pa < pb : a < b;
+            });
+            for (int c = 1; c < 8; ++c)
+                std::copy(cls_off.begin(), cls_off.begin() + 189, cls_off.begin() + 189 * c);
+            rs_bound.push_back(0);
+            for (int g0 = 0; g0 < 189;) {
+                int g1 = g0;
+                while (g1 < 189 && parity(cls_off[g1]) == parity(cls_off[g0])) ++g1;
+                const int sz = g1 - g0, nch = (sz + csize - 1) / csize;
+                for (int k = 1; k <= nch; ++k) rs_bound.push_back(g0 + k * sz / nch);
+                g0 = g1;
+            }
+            mg.nchunk = (int)rs_bound.size() - 1;
+            cstart.assign(8 * (mg.nchunk + 1), 0);
+            for (int c = 0; c < 8; ++c)
+                for (int k = 0; k <= mg.nchunk; ++k) cstart[c * (mg.nchunk + 1) + k] = (int16_t)rs_bound[k];
+        } else if (P->m2l_mode == 3) {
             // every class runs on class 0's (canonical) offsets, mirrored by
             // the class's reflection; chunks are equal slices of that list
             std::sort(cls_off.begin(), cls_off.begin() + 189);
@@ -1041,7 +1099,11 @@ fmm_status fmm_plan_create(const fmm_params* prm, void* hip_stream, fmm_plan_t* 
         const size_t esz = P->m2l_mode == 2 ? 8 : (P->m2l_mode == 1 ? 4 : 2);
         P->m2l_lds = esz * ((size_t)mg.RP * mg.SA + (size_t)fmmk::kM2LTile * mg.SB);
         const int KC = mg.KP / 8;
-        if (P->m2l_mode == 3) {
+        if (P->m2l_mode == 3 && P->m2l_rs) {
+            // resident source rows and two operator buffers: static LDS
+            P->m2l_nbuf = 2;
+            P->m2l_lds = 0;
+        } else if (P->m2l_mode == 3) {
             // one staging buffer: operator (2 KC RP chunks) + sources ((2 KC + 1) 80 chunks)
             const size_t one = (size_t)16 * (2 * KC * mg.RP + (2 * KC + 1) * fmmk::kM2LTile);
             P->m2l_nbuf = 2 * one <= fmmk::kLdsBytes ? 2 : 1;
@@ -1119,6 +1181,7 @@ fmm_status fmm_plan_create(const fmm_params* prm, void* hip_stream, fmm_plan_t* 
             FMM_LDS_ALL(3, fmmk::k_m2l_bf16x3)
             default: break;
         }
+
         if (ea != hipSuccess) e = ea;
     }
     for (int fold = 0; fold < 2 && e == hipSuccess; ++fold) {

@@ -1491,10 +1491,10 @@ __device__ __forceinline__ bool m2l_column(const Geo& g, int cls, int tile, int 
                                            int& ty, int& tz) {
     int u = tile * kM2LTile + j;
     for (lev = g.depth; lev >= g.lmin; --lev) {
-        const int half = 1 << (lev - 1);
-        const int ntc = half * half * half;
+        const int sh = lev - 1, half = 1 << sh;  // half = 2^(lev - 1): shifts, not divisions
+        const int ntc = 1 << (3 * sh);
         if (u < ntc) {
-            const int ux = u / (half * half), uy = (u / half) % half, uz = u % half;
+            const int ux = u >> (2 * sh), uy = (u >> sh) & (half - 1), uz = u & (half - 1);
             tx = 2 * ux + ((cls >> 2) & 1);
             ty = 2 * uy + ((cls >> 1) & 1);
             tz = 2 * uz + (cls & 1);
@@ -1939,6 +1939,176 @@ __global__ __launch_bounds__(kM2LThreads) void k_m2l_bf16x3(Geo g, M2LGeom mg,
                          ? loc + (size_t)box * g.Kp
                          : part + ((size_t)tk.chunk * mg.nt_all + (box - lev_offset(g.lmin))) * g.Kp;
         *(float4*)(dst + 4 * q4) = *(const float4*)(tt + j * ts + 4 * q4);
+    }
+}
+
+// bf16x3 M2L with resident sources, for trees whose classes have at most
+// kM2LTile target columns (depth <= 3: one tile per class).  The target
+// columns of class c sit at coordinates 2u + c (per axis, at every level), so
+// the source of every column for a canonical offset o' is a box of parity
+// q = c XOR (o' mod 2) at the column's level, and over all columns the
+// sources are exactly that parity class of every level: one box per column.
+// Chunks of offsets are cut within parity groups, so a work-group copies its
+// class's source rows once (2 KC chunks each, the rows in column order, plus
+// the zero row for open-boundary sources outside the domain) and per offset
+// only the operator; a column reads its source at the row of the source's
+// own column index (the rows are a permutation of the columns).  Staging,
+// fragments and signs are those of k_m2l_bf16x3; results go to memory
+// straight from the accumulators.
+constexpr int kM2LRsMaxRT = 7;  // row tiles whose resident-source staging fits the LDS
+
+// Largest staging sizes (16-byte chunks) of a row-tile count: the operator
+// (2 KC RP) and the resident source rows (kM2LTile + 1 rows of 2 KC + 1).
+__host__ __device__ constexpr int m2l_rs_kc(int rt) { return ((16 * rt + 31) / 32) * 4; }
+__host__ __device__ constexpr int m2l_rs_op_chunks(int rt) { return 2 * m2l_rs_kc(rt) * 16 * rt; }
+__host__ __device__ constexpr int m2l_rs_src_chunks(int rt) { return (kM2LTile + 1) * (2 * m2l_rs_kc(rt) + 1); }
+
+template <int RT>
+__global__ __launch_bounds__(kM2LThreads) void k_m2l_bf16x3_rs(Geo g, M2LGeom mg,
+                                                              const M2LTask* __restrict__ tasks,
+                                                              const int16_t* __restrict__ olist,
+                                                              const uint4* __restrict__ msplit,
+                                                              const uint4* __restrict__ bank,
+                                                              const uint4* __restrict__ sign_tab,
+                                                              float* __restrict__ loc, float* __restrict__ part) {
+    // three distinct LDS objects: the copy into one operator buffer provably
+    // does not touch the other buffer or the source rows, so fragment reads
+    // need not wait for it (one buffer in a single array made the compiler
+    // wait for every copy before any LDS read)
+    __shared__ uint4 opb0[m2l_rs_op_chunks(RT)], opb1[m2l_rs_op_chunks(RT)];
+    __shared__ uint4 res[m2l_rs_src_chunks(RT)];
+    __shared__ int col_box[kM2LTile], row_box[kM2LTile + 1];
+    // KC = KP / 8 follows from the row-tile count (KP = K rounded up to 32)
+    constexpr int KC = m2l_rs_kc(RT);
+    constexpr int SBc = 2 * KC + 1;  // odd row stride: a fragment read's 16 rows fall in distinct banks
+    constexpr int a_chunks = 2 * KC * 16 * RT;
+    const int nres = mg.ncol + 1;  // source rows: one per column, then the zero row
+    const M2LTask tk = tasks[blockIdx.x];
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    msplit += (size_t)blockIdx.y * (g.nbox + 1) * 2 * KC;
+    loc += (size_t)blockIdx.y * g.nbox * g.Kp;
+    if (part) part += (size_t)blockIdx.y * mg.nchunk * mg.nt_all * g.Kp;
+    const bool active = 16 * wave < mg.ncol;
+    const int o0 = tk.o0, o1 = tk.o1;
+    const int16_t* ol = olist + tk.cls * 189;
+    int ol_reg = lane < o1 - o0 ? ol[o0 + lane] : 0;
+    // parity class of the chunk's sources (every offset of the chunk has the
+    // same parity)
+    const int oi0 = __builtin_amdgcn_readlane(ol_reg, 0);
+    const int q = tk.cls ^ ((((oi0 / 49 - 3) & 1) << 2) | ((((oi0 / 7) % 7 - 3) & 1) << 1) | ((oi0 % 7 - 3) & 1));
+    auto issue = [&](int oc, uint4* dst) {
+        const uint4* src = bank + (size_t)oc * a_chunks;
+        for (int c0 = 0; c0 < a_chunks; c0 += kM2LThreads)
+            if (c0 + tid < a_chunks) lds_dma16(src + c0 + tid, dst + c0 + 64 * wave);
+    };
+    // the first operator's copy, then the boxes of the target columns and of
+    // the source rows (one per thread), then the source rows' copy
+    if (o0 < o1) issue(o0, opb0);
+    if (tid < kM2LTile) {
+        int l, x, y, z;
+        col_box[tid] = m2l_column(g, tk.cls, 0, tid, l, x, y, z) ? (int)(lev_offset(l) + morton(x, y, z)) : -1;
+    } else if (tid < kM2LTile + nres) {
+        const int j = tid - kM2LTile;
+        int l, x, y, z;
+        row_box[j] = (j < mg.ncol && m2l_column(g, q, 0, j, l, x, y, z)) ? (int)(lev_offset(l) + morton(x, y, z))
+                                                                       : (int)g.nbox;
+    }
+    __syncthreads();
+    // chunk e = t kM2LThreads + tid is chunk e % SBc of row e / SBc (the pad
+    // chunk copies chunk 0 again)
+    for (int e0 = 0; e0 < nres * SBc; e0 += kM2LThreads) {
+        const int e = e0 + tid;
+        if (e < nres * SBc) {
+            const int j = e / SBc, c = e - j * SBc;
+            lds_dma16(msplit + (size_t)row_box[j] * 2 * KC + (c == 2 * KC ? 0 : c), res + e0 + 64 * wave);
+        }
+    }
+    // this lane's column and its place: source row = column index - u(t) + u(s)
+    const int col = 16 * wave + (lane & 15), kq = lane >> 4, row = lane & 15;
+    int clev = 0, ctx = 0, cty = 0, ctz = 0;
+    const bool cok = m2l_column(g, tk.cls, 0, col, clev, ctx, cty, ctz);
+    const int chalf = 1 << max(clev - 1, 0), cn = 1 << clev;
+    const int cu = ((ctx >> 1) * chalf + (cty >> 1)) * chalf + (ctz >> 1);
+    const int fx = (tk.cls & 4) ? -1 : 1, fy = (tk.cls & 2) ? -1 : 1, fz = (tk.cls & 1) ? -1 : 1;
+    mf4 acc[RT];
+#pragma unroll
+    for (int r = 0; r < RT; ++r) acc[r] = mf4{0.f, 0.f, 0.f, 0.f};
+    uint4 bsg[kM2LMaxKs];
+#pragma unroll
+    for (int si = 0; si < kM2LMaxKs; ++si) bsg[si] = sign_tab[tk.cls * 4 * kM2LMaxKs + 4 * si + kq];
+    // one offset: wait for its operator (and, first, the source rows), start
+    // the next operator's copy into the other buffer, multiply
+    auto step = [&](int oc, const uint4* A, uint4* nxt) {
+        const int st = oc - o0;
+        if (st > 0 && (st & 63) == 0) ol_reg = ol[min(oc + lane, o1 - 1)];
+        const int oi = __builtin_amdgcn_readlane(ol_reg, st & 63);
+        __builtin_amdgcn_s_waitcnt(0);  // this lane's copies have landed
+        __syncthreads();                // everyone's have; the other buffer is free
+        if (oc + 1 < o1) issue(oc + 1, nxt);
+        if (!active) return;
+        int srow = mg.ncol;  // zero row
+        if (cok) {
+            int sx = ctx - fx * (oi / 49 - 3), sy = cty - fy * ((oi / 7) % 7 - 3), sz = ctz - fz * (oi % 7 - 3);
+            bool ok = true;
+            if (g.periodic) {
+                sx &= cn - 1;
+                sy &= cn - 1;
+                sz &= cn - 1;
+            } else {
+                ok = sx >= 0 && sy >= 0 && sz >= 0 && sx < cn && sy < cn && sz < cn;
+            }
+            if (ok) srow = col - cu + ((sx >> 1) * chalf + (sy >> 1)) * chalf + (sz >> 1);
+        }
+        const uint4* B = res + (size_t)srow * SBc;
+#pragma unroll
+        for (int si = 0; si < kM2LMaxKs; ++si) {
+            if (4 * si >= KC) break;
+            const int kc = 4 * si + kq;
+            uint4 uh = B[kc], ul = B[KC + kc];
+            uh.x ^= bsg[si].x;
+            uh.y ^= bsg[si].y;
+            uh.z ^= bsg[si].z;
+            uh.w ^= bsg[si].w;
+            ul.x ^= bsg[si].x;
+            ul.y ^= bsg[si].y;
+            ul.z ^= bsg[si].z;
+            ul.w ^= bsg[si].w;
+            const mbf8 bh = __builtin_bit_cast(mbf8, uh);
+            const mbf8 bl = __builtin_bit_cast(mbf8, ul);
+#pragma unroll
+            for (int r = 0; r < RT; ++r) {
+                const mbf8 ah = __builtin_bit_cast(mbf8, A[kc * mg.RP + 16 * r + row]);
+                const mbf8 al = __builtin_bit_cast(mbf8, A[(KC + kc) * mg.RP + 16 * r + row]);
+                acc[r] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh, acc[r], 0, 0, 0);
+                acc[r] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl, acc[r], 0, 0, 0);
+                acc[r] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh, acc[r], 0, 0, 0);
+            }
+        }
+    };
+    for (int oc = o0; oc < o1; oc += 2) {
+        step(oc, opb0, opb1);
+        if (oc + 1 < o1) step(oc + 1, opb1, opb0);
+    }
+    // signs S on the output rows, stored straight from the accumulators: lane
+    // (col, kq) holds rows 16 r + 4 kq .. + 3 of its column, one 16-byte chunk
+    // of the box row per row tile (four lanes of a column: 64 bytes in a row)
+    const int box = cok ? col_box[col] : -1;
+    if (active && box >= 0) {
+        float* dst = mg.nchunk == 1
+                         ? loc + (size_t)box * g.Kp
+                         : part + ((size_t)tk.chunk * mg.nt_all + (box - lev_offset(g.lmin))) * g.Kp;
+#pragma unroll
+        for (int r = 0; r < RT; ++r) {
+            if (16 * r + 4 * kq >= g.Kp) break;  // padding rows past the stored row length
+            const uint4 m = sign_tab[tk.cls * 4 * kM2LMaxKs + 2 * r + (kq >> 1)];
+            const uint32_t lo = (kq & 1) ? m.z : m.x, hi = (kq & 1) ? m.w : m.y;
+            float4 o;
+            o.x = ((lo >> 15) & 1u) ? -acc[r][0] : acc[r][0];
+            o.y = ((lo >> 31) & 1u) ? -acc[r][1] : acc[r][1];
+            o.z = ((hi >> 15) & 1u) ? -acc[r][2] : acc[r][2];
+            o.w = ((hi >> 31) & 1u) ? -acc[r][3] : acc[r][3];
+            *(float4*)(dst + 16 * r + 4 * kq) = o;
+        }
     }
 }
 

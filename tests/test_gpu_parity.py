@@ -268,6 +268,47 @@ def test_m2l_offset_chunking_invariant(chunk):
     np.testing.assert_allclose(b["F"], a["F"], rtol=1e-11, atol=1e-11 * np.abs(a["F"]).max())
 
 
+@pytest.mark.parametrize("periodic", [False, True])
+def test_bf16x3_resident_source_chunking(periodic):
+    """Trees of at most 73 target columns per class run the bf16x3 M2L with
+    the class's sources resident and chunks cut within parity groups.  Every
+    chunk size (1 to 26 offsets: 189 to 8 partial sums per coefficient) keeps
+    the bound of the matrix-core test above against the FP64 plain solve: the
+    FP32 plain path's error plus 2^-16 kappa (kappa: the cancellation ratio
+    RMS phi(|q|) / RMS phi); against the oracle, the default chunking stays
+    within twice the FP64 FMM's own error on the same input."""
+    mk = W.tiny_periodic if periodic else W.random_open
+    d = mk(38, n=2500, edge=2.2, n_sites=3, depth=3, order=8)
+
+    def rel(u, v, k):
+        return np.sqrt(np.sum((u[k] - v[k]) ** 2) / np.sum(v[k] ** 2))
+    r = run(d, "fp64", m2l_kernel=1)
+    a = run(d, "f32", m2l_kernel=1)
+    da = dict(d)
+    da["periodic"] = False
+    da["qA"], da["qB"] = np.abs(d["qA"]), np.abs(d["qA"])
+    ab = run(da, "fp64", depth=1)
+    kappa = {k: np.sqrt(np.mean(ab[k] ** 2) / np.mean(r[k] ** 2)) for k in ("F", "phi")}
+    for chunk in (1, 7, 13, 26):
+        b = run(d, "bf16x3", m2l_chunk=chunk)
+        for k in ("F", "phi"):
+            bound = rel(a, r, k) + 2.0 ** -16 * kappa[k]
+            assert rel(b, r, k) <= bound, (chunk, k, rel(b, r, k), bound)
+    ref = reference(d)
+    e64, eb = errors(r, ref), errors(run(d, "bf16x3"), ref)
+    for k in ("F", "phi", "E", "dVdl"):
+        assert eb[k] <= 2.0 * e64[k] + 1e-9, (k, eb[k], e64[k])
+
+
+@pytest.mark.parametrize("periodic", [False, True])
+def test_bf16x3_deep_tree(periodic):
+    """Depth 4 (512 leaf columns per class): the bf16x3 M2L that stages
+    every column's source per offset."""
+    mk = W.tiny_periodic if periodic else W.random_open
+    d = mk(39, n=6000, edge=2.6, n_sites=4, depth=4, order=8)
+    assert_within(errors(run(d, "bf16x3"), reference(d)), 8, label="bf16x3 depth 4")
+
+
 @pytest.mark.parametrize("waves", [4, 16])
 def test_near_field_wave_count_invariant(waves):
     """4, 8 or 16 wavefronts per leaf only regroup the near-field sums."""

@@ -42,10 +42,10 @@ def test_plan_create_rejects_bad_params_without_gpu():
     out = ctypes.c_void_p()
     for bad in (dict(depth=-1), dict(depth=7), dict(order_p=0), dict(order_p=16),
                 dict(boundary=2), dict(precision=3), dict(max_replicas=0),
-                dict(max_atoms=-5), dict(coulomb_k=float("nan")), dict(m2l_kernel=3),
+                dict(max_atoms=-5), dict(coulomb_k=float("nan")), dict(m2l_kernel=4),
                 dict(m2l_chunk=190), dict(graph=2), dict(p2p_waves=5), dict(p2p_split=5),
                 dict(p2p_split=-1), dict(hamiltonian=2), dict(hamiltonian=-1), dict(order_p=11, m2l_kernel=2),
-                dict(order_p=9, precision=0, m2l_kernel=2)):
+                dict(order_p=11, m2l_kernel=3), dict(order_p=9, precision=0, m2l_kernel=2)):
         kw = dict(depth=2, order_p=4, boundary=0, precision=0, coulomb_k=1.0,
                   max_atoms=10, max_sites=1, max_replicas=1, check=0, m2l_kernel=0,
                   m2l_chunk=0, p2p_waves=0, graph=0)
