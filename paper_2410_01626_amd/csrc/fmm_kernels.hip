@@ -1981,7 +1981,9 @@ __global__ __launch_bounds__(kM2LThreads) void k_m2l_bf16x3_rs(Geo g, M2LGeom mg
     // KC = KP / 8 follows from the row-tile count (KP = K rounded up to 32)
     constexpr int KC = m2l_rs_kc(RT);
     constexpr int SBc = 2 * KC + 1;  // odd row stride: a fragment read's 16 rows fall in distinct banks
-    constexpr int a_chunks = 2 * KC * 16 * RT;
+    constexpr int RP = 16 * RT;      // operator rows (K padded to the row tiles)
+    constexpr int NKS = KC / 4;      // k-steps of 32
+    constexpr int a_chunks = 2 * KC * RP;
     const int nres = mg.ncol + 1;  // source rows: one per column, then the zero row
     const M2LTask tk = tasks[blockIdx.x];
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
@@ -2060,9 +2062,14 @@ __global__ __launch_bounds__(kM2LThreads) void k_m2l_bf16x3_rs(Geo g, M2LGeom mg
             if (ok) srow = col - cu + ((sx >> 1) * chalf + (sy >> 1)) * chalf + (sz >> 1);
         }
         const uint4* B = res + (size_t)srow * SBc;
-#pragma unroll
-        for (int si = 0; si < kM2LMaxKs; ++si) {
-            if (4 * si >= KC) break;
+        // fragments of k-step si into registers: B (signed by the class's S)
+        // and every row tile's A; the next k-step's are loaded while this
+        // one's products run, which are issued by product over independent
+        // accumulators (per accumulator still al bh, ah bl, ah bh in order)
+        struct Frags {
+            mbf8 bh, bl, ah[RT], al[RT];
+        };
+        auto load = [&](int si, Frags& f) {
             const int kc = 4 * si + kq;
             uint4 uh = B[kc], ul = B[KC + kc];
             uh.x ^= bsg[si].x;
@@ -2073,16 +2080,28 @@ __global__ __launch_bounds__(kM2LThreads) void k_m2l_bf16x3_rs(Geo g, M2LGeom mg
             ul.y ^= bsg[si].y;
             ul.z ^= bsg[si].z;
             ul.w ^= bsg[si].w;
-            const mbf8 bh = __builtin_bit_cast(mbf8, uh);
-            const mbf8 bl = __builtin_bit_cast(mbf8, ul);
+            f.bh = __builtin_bit_cast(mbf8, uh);
+            f.bl = __builtin_bit_cast(mbf8, ul);
 #pragma unroll
             for (int r = 0; r < RT; ++r) {
-                const mbf8 ah = __builtin_bit_cast(mbf8, A[kc * mg.RP + 16 * r + row]);
-                const mbf8 al = __builtin_bit_cast(mbf8, A[(KC + kc) * mg.RP + 16 * r + row]);
-                acc[r] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh, acc[r], 0, 0, 0);
-                acc[r] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl, acc[r], 0, 0, 0);
-                acc[r] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh, acc[r], 0, 0, 0);
+                f.ah[r] = __builtin_bit_cast(mbf8, A[kc * RP + 16 * r + row]);
+                f.al[r] = __builtin_bit_cast(mbf8, A[(KC + kc) * RP + 16 * r + row]);
             }
+        };
+        Frags fr[2];
+        load(0, fr[0]);
+#pragma unroll
+        for (int si = 0; si < NKS; ++si) {
+            if (si + 1 < NKS) load(si + 1, fr[(si + 1) & 1]);
+            // keep the next k-step's reads ahead of this k-step's products
+            __builtin_amdgcn_sched_barrier(0);
+            const Frags& f = fr[si & 1];
+#pragma unroll
+            for (int r = 0; r < RT; ++r) acc[r] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(f.al[r], f.bh, acc[r], 0, 0, 0);
+#pragma unroll
+            for (int r = 0; r < RT; ++r) acc[r] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(f.ah[r], f.bl, acc[r], 0, 0, 0);
+#pragma unroll
+            for (int r = 0; r < RT; ++r) acc[r] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(f.ah[r], f.bh, acc[r], 0, 0, 0);
         }
     };
     for (int oc = o0; oc < o1; oc += 2) {
