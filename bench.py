@@ -54,7 +54,7 @@ def p2p_pairs(cnt, periodic=True):
 
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_water_box_30k_p8.md")
 KERNEL_SRC = os.path.join(ROOT, "paper_2410_01626_amd", "csrc", "fmm_kernels.hip")
-PHASE_KERNEL = {"near_far": "k_near_far<float, 8>", "m2l": "k_m2l_bf16x3<6>"}
+PHASE_KERNEL = {"near_far": "k_near_far<float, 8>", "m2l": "k_m2l_bf16x3_rs<6>"}
 
 
 def measured_traffic(phase):
