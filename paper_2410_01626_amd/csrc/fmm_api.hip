@@ -423,17 +423,27 @@ inline unsigned nblocks(int64_t n, int b) { return (unsigned)std::max<int64_t>(1
 // The resident-source bf16x3 M2L for a row-tile count whose static staging
 // fits the LDS (up to 7 row tiles: p <= 9).
 template <int RTV>
-void launch_m2l_rs(fmm_plan_t P, const Geo& g, const fmmk::M2LGeom& mg, dim3 nt, float* loc, float* part) {
-    if constexpr (RTV <= fmmk::kM2LRsMaxRT)
-        fmmk::k_m2l_bf16x3_rs<RTV><<<nt, fmmk::kM2LThreads, 0, P->stream>>>(
+void launch_m2l_rs(fmm_plan_t P, const Geo& g, const fmmk::M2LGeom& mg, dim3 nt, float* loc, float* part,
+                   bool root) {
+    if constexpr (RTV <= fmmk::kM2LRsMaxRT) {
+        // with root: one extra work-group per replica forms the periodic root
+        const fmmk::RootArgs ra{P->ws.root_part, P->ws.box_part, P->latT, P->lat_seg,
+                                P->ws.root_m, root ? P->ws.root_l : nullptr, P->ws.dom};
+        const dim3 grid(nt.x + (root ? 1u : 0u), nt.y);
+        fmmk::k_m2l_bf16x3_rs<RTV><<<grid, fmmk::kM2LThreads, 0, P->stream>>>(
             g, mg, P->tasks, P->olist, (const uint4*)P->ws.msplit, (const uint4*)P->bank_mma,
-            (const uint4*)P->sign_tab, loc, part);
+            (const uint4*)P->sign_tab, loc, part, ra);
+    }
 }
 
 // Matrix-core M2L launch: the kernel instance for the plan's precision and row
-// tile count, then the fixed-order chunk reduction.
+// tile count, then the fixed-order chunk reduction.  Returns whether the
+// periodic root was formed (by the reduction launch or, with resident sources,
+// by the M2L launch itself); *fused is set when no reduction launch ran and
+// the downward pass adds the offset-chunk partials itself.
 template <typename T>
-bool launch_m2l_mma(fmm_plan_t P, const Geo& g, int R, bool want_root) {
+bool launch_m2l_mma(fmm_plan_t P, const Geo& g, int R, bool want_root, bool* fused) {
+    *fused = false;
     using namespace fmmk;
     hipStream_t st = P->stream;
     const M2LGeom mg = P->mg;
@@ -442,6 +452,12 @@ bool launch_m2l_mma(fmm_plan_t P, const Geo& g, int R, bool want_root) {
     T* loc = (T*)P->ws.loc;
     T* part = (T*)P->ws.m2l_part;
     const T* mult = (const T*)P->ws.mult;
+    // resident sources with offset chunks: the root (periodic trees of depth >= 2,
+    // whose level-1 M2M leaves the root shares) in an extra M2L work-group and
+    // the chunk sums in the downward pass, so no reduction launch
+    // (only where a downward launch follows: it forms every leaf's expansion)
+    const bool rs_fused = P->m2l_rs && mg.nchunk > 1 && (!g.periodic || (want_root && g.depth >= 2)) &&
+                          g.depth - 1 >= (g.periodic ? 0 : g.lmin);
     switch (P->m2l_mode * 16 + P->m2l_rt) {
 #define FMM_M2L_F32(RTV)                                                                    \
     case 16 + RTV:                                                                          \
@@ -458,7 +474,7 @@ bool launch_m2l_mma(fmm_plan_t P, const Geo& g, int R, bool want_root) {
 #define FMM_M2L_BF(RTV)                                                                         \
     case 48 + RTV:                                                                              \
         if (P->m2l_rs)                                                                          \
-            launch_m2l_rs<RTV>(P, g, mg, nt, (float*)loc, (float*)part);                         \
+            launch_m2l_rs<RTV>(P, g, mg, nt, (float*)loc, (float*)part, rs_fused && want_root);  \
         else                                                                                    \
             k_m2l_bf16x3<RTV><<<nt, kM2LThreads, lds, st>>>(g, mg, P->tasks, P->olist, P->cstart, \
                                                 (const uint4*)P->ws.msplit,                        \
@@ -473,6 +489,10 @@ bool launch_m2l_mma(fmm_plan_t P, const Geo& g, int R, bool want_root) {
         FMM_M2L_BF(1) FMM_M2L_BF(2) FMM_M2L_BF(3) FMM_M2L_BF(4)
         FMM_M2L_BF(5) FMM_M2L_BF(6) FMM_M2L_BF(7) FMM_M2L_BF(8)
         default: break;
+    }
+    if (rs_fused) {
+        *fused = true;
+        return g.periodic;
     }
     if (mg.nchunk > 1) {
         const int64_t tot = mg.nt_all * g.Kp;
@@ -590,14 +610,15 @@ int32_t* enqueue_tree(fmm_plan_t P, const fmmk::Geo& g, int R, bool want_order, 
         k_root<T><<<R, 256, 0, st>>>(g, P->ws.leaf_part, P->ws.root_m, mult, P->latT, P->ws.root_l, loc,
                                      P->ws.dom);
     mark(P, 4);
-    bool root_ready = false;  // the periodic root formed by the M2L reduction launch
+    bool root_ready = false;  // the periodic root formed by the M2L launches
+    bool fused = false;       // the downward pass adds the M2L chunk partials
     if (g.depth >= g.lmin) {
         if (P->m2l_mode == 0) {
             int64_t nt = 0;
             for (int l = g.lmin; l <= g.depth; ++l) nt += (int64_t)1 << (3 * l);
             k_m2l_plain<T><<<dim3((unsigned)nt, R), 256, 0, st>>>(g, mult, (const T*)P->bankT, loc);
         } else {
-            root_ready = launch_m2l_mma<T>(P, g, R, root_in_reduce);
+            root_ready = launch_m2l_mma<T>(P, g, R, root_in_reduce, &fused);
         }
     }
     // downward pass: ancestors' local expansions and the L2L into the leaves
@@ -612,7 +633,8 @@ int32_t* enqueue_tree(fmm_plan_t P, const fmmk::Geo& g, int R, bool want_order, 
         k_downward<T><<<dim3(nbx, R), kTreeThreads, 0, st>>>(
             g, l0, loc, (const T*)P->l2lT, (const T*)P->l2l_seg, mult, (const T*)P->m2mT,
             (const T*)P->m2m_seg, P->ws.leaf_part, P->ws.box_part, P->latT, P->lat_seg, P->ws.root_m, P->ws.root_l,
-            P->ws.dom, P->ws.leaf_start, order, root_ready ? 1 : 0);
+            P->ws.dom, P->ws.leaf_start, order, root_ready ? 1 : 0, fused ? (const T*)P->ws.m2l_part : nullptr,
+            P->mg.nchunk, P->mg.nt_all);
     }
     return order;
 }

@@ -1218,6 +1218,49 @@ __device__ void periodic_root_from_shares(const Geo& g, int rp, const double* __
     if (threadIdx.x == 0) dom_all[8 * rp + 4] = qs;
 }
 
+// periodic_root_from_shares for a work-group of nthr threads (any size): the
+// tree kernels' (segment, row) shares of the lattice operator are taken
+// kTreeThreads / nthr at a time, so products and sums are the same, bit for
+// bit.  xs: K doubles, part: nseg K doubles, v: K doubles of LDS.
+template <int kCache>
+__device__ void periodic_root_wg(const Geo& g, int rp, const double* __restrict__ root_part_all,
+                                 const double* __restrict__ box_part_all, const double* __restrict__ latT,
+                                 const double* __restrict__ lat_seg, double* __restrict__ root_m_all,
+                                 double* __restrict__ root_l_all, double* __restrict__ dom_all, double* xs,
+                                 double* part, double* v, int nthr) {
+    const int K = g.K, t = threadIdx.x;
+    const double* rpart = root_part_all + (size_t)rp * 8 * K;
+    const double* bpart = box_part_all + ((size_t)rp * g.nbox + g.lev_off[1]) * 2;
+    for (int r = t; r < K; r += nthr) {
+        double m = 0.0;
+#pragma unroll
+        for (int c = 0; c < 8; ++c) m += rpart[(size_t)c * K + r];
+        v[r] = m;
+        xs[r] = m;
+    }
+    __syncthreads();
+    for (int it = t; it < kTreeThreads; it += nthr) {
+        TriPart<double, kTriFull, kCache> tp;
+        tp.load(K, lat_seg, it);
+        tri_dot<double, 1, kTriFull, kCache>(tp, K, latT, xs, part);
+    }
+    __syncthreads();
+    double s2 = 0.0, qs = 0.0;
+    for (int c = 0; c < 8; ++c) {
+        s2 += bpart[2 * c];
+        qs += bpart[2 * c + 1];
+    }
+    const int nseg = tri_nseg(K);
+    for (int r = t; r < K; r += nthr) {
+        double y = 0.0;
+        for (int sg = 0; sg < nseg; ++sg) y += part[sg * K + r];
+        const double lr = y + (r == 0 ? 2.0 * kPi / 3.0 * s2 : 0.0);
+        root_m_all[(size_t)rp * K + r] = v[r];
+        root_l_all[(size_t)rp * K + r] = lr;
+    }
+    if (t == 0) dom_all[8 * rp + 4] = qs;
+}
+
 template <typename T>
 __device__ void periodic_root(const Geo& g, int rp, const T* __restrict__ mult_all,
                               const T* __restrict__ m2m0, const T* __restrict__ m2m0_seg,
@@ -1257,6 +1300,23 @@ __device__ void periodic_root(const Geo& g, int rp, const T* __restrict__ mult_a
     if (store && threadIdx.x == 0) dom_all[8 * rp + 4] = qs;
 }
 
+// The local-expansion entry e summed over the offset chunks in a fixed order
+// (four interleaved partial sums keep 16 loads in flight).
+template <typename T>
+__device__ __forceinline__ T m2l_chunk_sum(const T* __restrict__ part, int nchunk, int64_t tot, int64_t e) {
+    T s0 = T(0), s1 = T(0), s2 = T(0), s3 = T(0);
+    int c = 0;
+#pragma unroll 4
+    for (; c + 4 <= nchunk; c += 4) {
+        s0 += part[(size_t)c * tot + e];
+        s1 += part[(size_t)(c + 1) * tot + e];
+        s2 += part[(size_t)(c + 2) * tot + e];
+        s3 += part[(size_t)(c + 3) * tot + e];
+    }
+    for (; c < nchunk; ++c) s0 += part[(size_t)c * tot + e];
+    return (s0 + s1) + (s2 + s3);
+}
+
 // Downward pass in one launch: one block per box b of level depth - 1 forms
 // lambda~ of its ancestors from level l0 down (L2L of the parent's total plus
 // the box's own M2L sum, in FP64) and adds the L2L of lambda~_b into its 8
@@ -1275,7 +1335,7 @@ __global__ __launch_bounds__(kTreeThreads) void k_downward(
     const double* __restrict__ latT, const double* __restrict__ lat_seg, double* __restrict__ root_m_all,
     double* __restrict__ root_l_all, double* __restrict__ dom_all,
     const int32_t* __restrict__ leaf_start_all, int32_t* __restrict__ leaf_order_all,
-    int root_ready) {
+    int root_ready, const T* __restrict__ m2l_part_all, int m2l_nchunk, int64_t m2l_nt_all) {
     __shared__ double xs[8 * kKMax], part[8 * kTreeThreads];
     if (leaf_order_all && blockIdx.x + 1 == gridDim.x) {
         // the extra last block: the near-field order of this replica's leaves
@@ -1300,22 +1360,48 @@ __global__ __launch_bounds__(kTreeThreads) void k_downward(
     for (int m = 0; m < kAncPer; ++m) {
         const int i = min((int)threadIdx.x + m * kTreeThreads, max(nanc - 1, 0));
         const int li = i / K, k = i - li * K, lev = la + li;
-        av[m] = nanc > 0 ? loc[(size_t)(lev_offset(lev) + (b >> (3 * (D - 1 - lev)))) * g.Kp + k] : T(0);
+        av[m] = nanc > 0 && !m2l_part_all ? loc[(size_t)(lev_offset(lev) + (b >> (3 * (D - 1 - lev)))) * g.Kp + k]
+                                          : T(0);
     }
     T* dst = loc + (size_t)(lev_offset(D) + 8 * (size_t)b) * g.Kp;
 #pragma unroll
     for (int m = 0; m < kGatherPer; ++m) {
         const int i = min((int)threadIdx.x + m * kTreeThreads, 8 * K - 1);
         const int c = i / K, r = i - c * K;
-        lv[m] = dst[(size_t)c * g.Kp + r];
+        lv[m] = m2l_part_all ? T(0) : dst[(size_t)c * g.Kp + r];
     }
 #pragma unroll
     for (int m = 0; m < kAncPer; ++m) {
         const int i = threadIdx.x + m * kTreeThreads;
-        if (i < nanc) anc[i] = av[m];
+        if (i < nanc && !m2l_part_all) anc[i] = av[m];
+    }
+    // without a reduction launch: the ancestors' and the 8 leaves' M2L sums
+    // from the offset-chunk partials, added here in the reduction's order
+    __shared__ T lsum[8 * kKMax];
+    if (m2l_part_all) {
+        const int64_t tot = m2l_nt_all * g.Kp;
+        const T* pr = m2l_part_all + (size_t)rp * m2l_nchunk * tot;
+        const int64_t lo = lev_offset(g.lmin);
+        for (int i = threadIdx.x; i < nanc + 8 * K; i += kTreeThreads) {
+            int64_t box;
+            int k;
+            if (i < nanc) {
+                const int li = i / K, lev = la + li;
+                k = i - li * K;
+                box = lev_offset(lev) + (b >> (3 * (D - 1 - lev)));
+            } else {
+                const int j = i - nanc, c = j / K;
+                k = j - c * K;
+                box = lev_offset(D) + 8 * (int64_t)b + c;
+            }
+            const T sv = m2l_chunk_sum<T>(pr, m2l_nchunk, tot, (box - lo) * g.Kp + k);
+            if (i < nanc) anc[i] = sv;
+            else lsum[i - nanc] = sv;
+        }
     }
     if (g.periodic && root_ready) {
-        // formed by the extra block of the M2L reduction launch
+        // formed by the extra block of the M2L reduction launch, or by the
+        // resident-source M2L launch's extra work-group
         __syncthreads();
         for (int k = threadIdx.x; k < K; k += kTreeThreads) v[k] = root_l_all[(size_t)rp * K + k];
     } else if (g.periodic) {
@@ -1346,7 +1432,8 @@ __global__ __launch_bounds__(kTreeThreads) void k_downward(
         const int i = threadIdx.x + m * kTreeThreads;
         if (i < 8 * K) {
             const int c = i / K, r = i - c * K;
-            dst[(size_t)c * g.Kp + r] = (T)((double)lv[m] + refl_sign(c, refl_bits(r)) * xs[i]);
+            const T own = m2l_part_all ? lsum[i] : lv[m];
+            dst[(size_t)c * g.Kp + r] = (T)((double)own + refl_sign(c, refl_bits(r)) * xs[i]);
         }
     }
 }
@@ -1957,6 +2044,19 @@ __global__ __launch_bounds__(kM2LThreads) void k_m2l_bf16x3(Geo g, M2LGeom mg,
 // straight from the accumulators.
 constexpr int kM2LRsMaxRT = 7;  // row tiles whose resident-source staging fits the LDS
 
+// What the periodic root needs (root_l == null: no root work-group): the
+// level-1 shares of the root multipole, the level-1 partial sums of q |t/L|^2
+// and q, the lattice operator and where the root goes.
+struct RootArgs {
+    const double* root_part;
+    const double* box_part;
+    const double* latT;
+    const double* lat_seg;
+    double* root_m;
+    double* root_l;
+    double* dom;
+};
+
 // Largest staging sizes (16-byte chunks) of a row-tile count: the operator
 // (2 KC RP) and the resident source rows (kM2LTile + 1 rows of 2 KC + 1).
 __host__ __device__ constexpr int m2l_rs_kc(int rt) { return ((16 * rt + 31) / 32) * 4; }
@@ -1970,7 +2070,8 @@ __global__ __launch_bounds__(kM2LThreads) void k_m2l_bf16x3_rs(Geo g, M2LGeom mg
                                                               const uint4* __restrict__ msplit,
                                                               const uint4* __restrict__ bank,
                                                               const uint4* __restrict__ sign_tab,
-                                                              float* __restrict__ loc, float* __restrict__ part) {
+                                                              float* __restrict__ loc, float* __restrict__ part,
+                                                              RootArgs ra) {
     // three distinct LDS objects: the copy into one operator buffer provably
     // does not touch the other buffer or the source rows, so fragment reads
     // need not wait for it (one buffer in a single array made the compiler
@@ -1978,6 +2079,14 @@ __global__ __launch_bounds__(kM2LThreads) void k_m2l_bf16x3_rs(Geo g, M2LGeom mg
     __shared__ uint4 opb0[m2l_rs_op_chunks(RT)], opb1[m2l_rs_op_chunks(RT)];
     __shared__ uint4 res[m2l_rs_src_chunks(RT)];
     __shared__ int col_box[kM2LTile], row_box[kM2LTile + 1];
+    if (ra.root_l && blockIdx.x + 1 == gridDim.x) {
+        // the extra last work-group of a periodic tree: the root's local
+        // expansion from the level-1 shares, on a CU the M2L leaves free
+        double* xs = (double*)opb0;
+        periodic_root_wg<16>(g, blockIdx.y, ra.root_part, ra.box_part, ra.latT, ra.lat_seg, ra.root_m, ra.root_l,
+                             ra.dom, xs, xs + g.K, (double*)opb1, kM2LThreads);
+        return;
+    }
     // KC = KP / 8 follows from the row-tile count (KP = K rounded up to 32)
     constexpr int KC = m2l_rs_kc(RT);
     constexpr int SBc = 2 * KC + 1;  // odd row stride: a fragment read's 16 rows fall in distinct banks
@@ -2159,19 +2268,7 @@ __global__ __launch_bounds__(kTreeThreads) void k_m2l_reduce(
     for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < tot;
          e += (int64_t)nred * blockDim.x) {
         if ((int)(e % g.Kp) >= g.K) continue;
-        // four independent partial sums keep 16 loads in flight; fixed order
-        T s0 = T(0), s1 = T(0), s2 = T(0), s3 = T(0);
-        int c = 0;
-#pragma unroll 4
-        for (; c + 4 <= mg.nchunk; c += 4) {
-            s0 += part[(size_t)c * tot + e];
-            s1 += part[(size_t)(c + 1) * tot + e];
-            s2 += part[(size_t)(c + 2) * tot + e];
-            s3 += part[(size_t)(c + 3) * tot + e];
-        }
-        for (; c < mg.nchunk; ++c) s0 += part[(size_t)c * tot + e];
-        const T s = (s0 + s1) + (s2 + s3);
-        loc[(size_t)g.lev_off[g.lmin] * g.Kp + e] = s;
+        loc[(size_t)g.lev_off[g.lmin] * g.Kp + e] = m2l_chunk_sum<T>(part, mg.nchunk, tot, e);
     }
 }
 
