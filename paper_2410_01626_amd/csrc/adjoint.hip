@@ -195,38 +195,46 @@ __global__ __launch_bounds__(kLeafThreads) void k_leaf_src2(
     }
 }
 
-// Per target leaf (one block of kAdjThreads): the near field of the 27
-// neighbour leaves from LDS tiles of (x - c, q) and (w, g) and the far field of
-// both local expansions (slot 0: charges q; slot 1: charges g with dipoles
-// -q w), giving per target m, in caller order, acc[8 m ..] = (phi(q), E(q),
-// A, B) without k_e (the periodic background terms included).  A target
+// Per target leaf (one block of kAdjWaves wavefronts): the near field of the
+// 27 neighbour leaves from LDS tiles of (x - c, q) and (w, g) and the far
+// field of both local expansions (slot 0: charges q; slot 1: charges g with
+// dipoles -q w), giving per target m, in caller order, acc[8 m ..] = (phi(q),
+// E(q), A, B) without k_e (the periodic background terms included).  A target
 // chunk of tc atoms runs on lane groups of pow2ceil(tc) threads that take
 // interleaved sources and orders; the groups' partials are added in a fixed
-// order.
-constexpr int kAdjThreads = 256;
-template <typename T>
-__global__ __launch_bounds__(kAdjThreads) void k_near_adj(
+// order.  The neighbourhood is staged as in the forward near field (whole
+// neighbours per wavefront when it fits one tile, else a binary search of
+// the neighbour prefix sums with every thread's loads in flight), and only
+// the target's own leaf needs the zero-distance guard.
+constexpr int kAdjWaves = 8;
+template <typename T, int kNW>
+__global__ __launch_bounds__(64 * kNW, sizeof(T) == 4 ? 4 : 1) void k_near_adj(
     Geo g, const vec4_t<T>* __restrict__ pos, const vec4_t<T>* __restrict__ src2,
     const int32_t* __restrict__ leaf_start, const int32_t* __restrict__ perm,
     const double* __restrict__ dom_all, const T* __restrict__ loc_all, const int32_t* __restrict__ gidx,
     const T* __restrict__ gcoef, T* __restrict__ acc_out) {
-    constexpr int NT = kAdjThreads;
-    constexpr int CAP = sizeof(T) == 4 ? 1024 : 512;
+    constexpr int NT = 64 * kNW;
+    // sources staged per pass: a typical neighbourhood in one, two blocks per CU
+    constexpr int CAP = sizeof(T) == 4 ? 2048 : 1024;
+    static_assert(CAP % NT == 0, "whole staging rounds");
+    static_assert(8 * NT * sizeof(T) <= CAP * sizeof(vec4_t<T>), "partials fit the source tile");
     __shared__ vec4_t<T> tile[CAP], tilew[CAP];
-    __shared__ int nb_start[27], nb_cnt[27], nb_pre[28];
+    __shared__ int nb_start[27], nb_cnt[27], nb_pre[29];
     __shared__ T nb_off[27][3];
     __shared__ T lam0[kKMax], lam1[kKMax];
     __shared__ T gr0[3][kKgMax], gr1[3][kKgMax];
     __shared__ RhoLds<T> rho;
-    __shared__ T red[8][NT];
+    // the groups' partials (8 NT values) reuse the source tile after the sweep
+    T* red = reinterpret_cast<T*>(tile);
     load_rho_lds<T, NT>(rho, g.p);
-    const int leaf = blockIdx.x, tid = threadIdx.x;
+    const int leaf = blockIdx.x, tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     const int lb = leaf_start[leaf], ln = leaf_start[leaf + 1] - lb;
     if (ln == 0) return;
     const double edge = dom_all[3];
     const double h = edge / g.nb;
     int cx, cy, cz;
     unmorton((uint32_t)leaf, cx, cy, cz);
+    int my_cnt = 0;
     if (tid < 27) {
         const int dx = tid / 9 - 1, dy = (tid / 3) % 3 - 1, dz = tid % 3 - 1;
         int nx = cx + dx, ny = cy + dy, nz = cz + dz;
@@ -246,9 +254,24 @@ __global__ __launch_bounds__(kAdjThreads) void k_near_adj(
         }
         nb_start[tid] = s;
         nb_cnt[tid] = c;
+        my_cnt = c;
         nb_off[tid][0] = (T)(dx * h);
         nb_off[tid][1] = (T)(dy * h);
         nb_off[tid][2] = (T)(dz * h);
+    }
+    if (wave == 0) {
+        // inclusive scan of the 27 counts across lanes (shuffles, in registers)
+        int v = my_cnt;
+#pragma unroll
+        for (int off = 1; off < 32; off <<= 1) {
+            const int u = __shfl_up(v, off, 64);
+            if (lane >= off) v += u;
+        }
+        if (lane < 27) nb_pre[lane + 1] = v;
+        if (lane == 0) {
+            nb_pre[0] = 0;
+            nb_pre[28] = 0x7fffffff;
+        }
     }
     const bool far = g.has_far;
     if (far) {
@@ -259,14 +282,6 @@ __global__ __launch_bounds__(kAdjThreads) void k_near_adj(
         }
     }
     __syncthreads();
-    if (tid == 0) {
-        int v = 0;
-        for (int k = 0; k < 27; ++k) {
-            nb_pre[k] = v;
-            v += nb_cnt[k];
-        }
-        nb_pre[27] = v;
-    }
     if (far) {
         for (int e = tid; e < 3 * g.Kg; e += NT) {
             const int a = e / g.Kg, r = e - a * g.Kg;
@@ -304,45 +319,112 @@ __global__ __launch_bounds__(kAdjThreads) void k_near_adj(
         for (int s0 = 0; s0 < total; s0 += CAP) {
             const int cnt = min(CAP, total - s0);
             __syncthreads();  // the tiles' previous readers are done
-            for (int e = tid; e < cnt; e += NT) {
-                const int gs = s0 + e;
-                int nbk = 0;
-                while (nbk < 26 && nb_pre[nbk + 1] <= gs) ++nbk;
-                const int src = nb_start[nbk] + (gs - nb_pre[nbk]);
-                vec4_t<T> v = pos[src];
-                v.x += nb_off[nbk][0];
-                v.y += nb_off[nbk][1];
-                v.z += nb_off[nbk][2];
-                tile[e] = v;
-                tilew[e] = src2[src];
+            if (total <= CAP) {
+                // the whole neighbourhood in one pass: wavefront w copies
+                // neighbours w, w + kNW, ..., lane j their atom j (all loads
+                // in flight together), larger neighbours in extra rounds
+                constexpr int J = (27 + kNW - 1) / kNW;
+                vec4_t<T> a[J], aw[J];
+#pragma unroll
+                for (int m = 0; m < J; ++m) {
+                    const int nbk = min(wave + kNW * m, 26);
+                    // an empty neighbour reads entry 0 (never stored)
+                    const int c = nb_cnt[nbk];
+                    const int src = c > 0 ? nb_start[nbk] + min(lane, c - 1) : 0;
+                    a[m] = pos[src];
+                    aw[m] = src2[src];
+                }
+#pragma unroll
+                for (int m = 0; m < J; ++m) {
+                    const int nbk = wave + kNW * m;
+                    if (nbk < 27 && lane < nb_cnt[nbk]) {
+                        vec4_t<T> v = a[m];
+                        v.x += nb_off[nbk][0];
+                        v.y += nb_off[nbk][1];
+                        v.z += nb_off[nbk][2];
+                        tile[nb_pre[nbk] + lane] = v;
+                        tilew[nb_pre[nbk] + lane] = aw[m];
+                    }
+                }
+                for (int nbk = wave; nbk < 27; nbk += kNW)
+                    for (int j = 64 + lane; j < nb_cnt[nbk]; j += 64) {
+                        vec4_t<T> v = pos[nb_start[nbk] + j];
+                        v.x += nb_off[nbk][0];
+                        v.y += nb_off[nbk][1];
+                        v.z += nb_off[nbk][2];
+                        tile[nb_pre[nbk] + j] = v;
+                        tilew[nb_pre[nbk] + j] = src2[nb_start[nbk] + j];
+                    }
+            } else {
+                // stage the pass's sources, CAP / NT of each kind in flight per thread
+                constexpr int G = CAP / NT;
+                vec4_t<T> a[G], aw[G];
+                int lo_[G];
+#pragma unroll
+                for (int m = 0; m < G; ++m) {
+                    const int gsrc = s0 + min(tid + m * NT, cnt - 1);
+                    // neighbour holding source gsrc: largest i with nb_pre[i] <= gsrc
+                    int lo = 0, hi = 27;
+                    while (hi - lo > 1) {
+                        const int mid = (lo + hi) >> 1;
+                        if (nb_pre[mid] <= gsrc) lo = mid;
+                        else hi = mid;
+                    }
+                    lo_[m] = lo;
+                    const int src = nb_start[lo] + (gsrc - nb_pre[lo]);
+                    a[m] = pos[src];
+                    aw[m] = src2[src];
+                }
+#pragma unroll
+                for (int m = 0; m < G; ++m) {
+                    if (tid + m * NT < cnt) {
+                        vec4_t<T> v = a[m];
+                        v.x += nb_off[lo_[m]][0];
+                        v.y += nb_off[lo_[m]][1];
+                        v.z += nb_off[lo_[m]][2];
+                        tile[tid + m * NT] = v;
+                        tilew[tid + m * NT] = aw[m];
+                    }
+                }
             }
             __syncthreads();
             if (tv) {
-                // only the own leaf (neighbour 13) can hold the target itself
+                // Only the own leaf (neighbour 13) can hold the target itself
+                // or another atom at distance 0: the guard (zero weight at
+                // r = 0, which zeroes every term) runs on that range alone.
+                // Lane group grp takes the sources grp, grp + ngrp, ...
                 const int own_b = nb_pre[13] - s0, own_e = nb_pre[14] - s0;
-                for (int j = grp; j < cnt; j += ngrp) {
-                    const vec4_t<T> s = tile[j];
-                    const vec4_t<T> sw = tilew[j];
-                    const T dx = me.x - s.x, dy = me.y - s.y, dz = me.z - s.z;
-                    const T r2 = dx * dx + dy * dy + dz * dz;
-                    if (j >= own_b && j < own_e && !(r2 > T(0))) continue;
-                    const T ri = inv_sqrt<T>(r2);
-                    const T ri2 = ri * ri;
-                    const T ri3 = ri * ri2;
-                    const T qr = s.w * ri;
-                    const T qr3 = s.w * ri3;
-                    ph += qr;
-                    ex += qr3 * dx;
-                    ey += qr3 * dy;
-                    ez += qr3 * dz;
-                    const T vx = s.w * (sw.x - mw.x), vy = s.w * (sw.y - mw.y), vz = s.w * (sw.z - mw.z);
-                    const T vr = vx * dx + vy * dy + vz * dz;
-                    A += sw.w * ri - vr * ri3;
-                    const T c = sw.w - T(3) * vr * ri2;
-                    bx += ri3 * (c * dx + vx);
-                    by += ri3 * (c * dy + vy);
-                    bz += ri3 * (c * dz + vz);
-                }
+                auto sweep = [&](int j0, int j1, auto guard) {
+                    const int first = j0 + ((grp - j0) & (ngrp - 1));
+#pragma unroll 4
+                    for (int j = first; j < j1; j += ngrp) {
+                        const vec4_t<T> s = tile[j];
+                        const vec4_t<T> sw = tilew[j];
+                        const T dx = me.x - s.x, dy = me.y - s.y, dz = me.z - s.z;
+                        const T r2 = dx * dx + dy * dy + dz * dz;
+                        T ri;
+                        if constexpr (decltype(guard)::value) ri = r2 > T(0) ? inv_sqrt<T>(r2) : T(0);
+                        else ri = inv_sqrt<T>(r2);
+                        const T ri2 = ri * ri;
+                        const T ri3 = ri * ri2;
+                        const T qr = s.w * ri;
+                        const T qr3 = s.w * ri3;
+                        ph += qr;
+                        ex += qr3 * dx;
+                        ey += qr3 * dy;
+                        ez += qr3 * dz;
+                        const T vx = s.w * (sw.x - mw.x), vy = s.w * (sw.y - mw.y), vz = s.w * (sw.z - mw.z);
+                        const T vr = vx * dx + vy * dy + vz * dz;
+                        A += sw.w * ri - vr * ri3;
+                        const T c = sw.w - T(3) * vr * ri2;
+                        bx += ri3 * (c * dx + vx);
+                        by += ri3 * (c * dy + vy);
+                        bz += ri3 * (c * dz + vz);
+                    }
+                };
+                sweep(0, min(cnt, max(own_b, 0)), std::false_type{});
+                sweep(max(own_b, 0), min(cnt, own_e), std::true_type{});
+                sweep(max(own_e, 0), cnt, std::false_type{});
             }
         }
         if (far && tv) {
@@ -384,21 +466,22 @@ __global__ __launch_bounds__(kAdjThreads) void k_near_adj(
             by += (d0[1] - g1[1]) * ih2;
             bz += (d0[2] - g1[2]) * ih2;
         }
-        red[0][tid] = ph;
-        red[1][tid] = ex;
-        red[2][tid] = ey;
-        red[3][tid] = ez;
-        red[4][tid] = A;
-        red[5][tid] = bx;
-        red[6][tid] = by;
-        red[7][tid] = bz;
+        __syncthreads();  // every sweep is done with the tile
+        red[0 * NT + tid] = ph;
+        red[1 * NT + tid] = ex;
+        red[2 * NT + tid] = ey;
+        red[3 * NT + tid] = ez;
+        red[4 * NT + tid] = A;
+        red[5 * NT + tid] = bx;
+        red[6 * NT + tid] = by;
+        red[7 * NT + tid] = bz;
         __syncthreads();
         if (grp == 0 && tv) {
             double v[8];
 #pragma unroll
             for (int c = 0; c < 8; ++c) {
                 T s = T(0);
-                for (int q = 0; q < ngrp; ++q) s += red[c][q * gsz + tl];
+                for (int q = 0; q < ngrp; ++q) s += red[c * NT + q * gsz + tl];
                 v[c] = (double)s;
             }
             if (g.periodic) {

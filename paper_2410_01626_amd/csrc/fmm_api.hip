@@ -757,7 +757,7 @@ fmm_status enqueue_adjoint_full(fmm_plan_t P, const fmmk::RepDesc& r0, const T* 
         P->ws.leaf_part, (uint16_t*)P->ws.msplit, P->mg.KP);
     enqueue_tree<T>(P, g, 2, false, false);
     mark(P, 6);
-    k_near_adj<T><<<g.nleaf, kAdjThreads, 0, st>>>(g, (const V4*)P->ws.pos, (const V4*)P->ws.adj_src2,
+    k_near_adj<T, kAdjWaves><<<g.nleaf, 64 * kAdjWaves, 0, st>>>(g, (const V4*)P->ws.pos, (const V4*)P->ws.adj_src2,
                                                    P->ws.leaf_start, P->ws.perm, P->ws.dom, (const T*)P->ws.loc,
                                                    P->gidx, (const T*)P->gcoef, (T*)P->ws.adj_acc);
     const unsigned nb = nblocks(n, 256);
