@@ -629,8 +629,15 @@ int32_t* enqueue_tree(fmm_plan_t P, const fmmk::Geo& g, int R, bool want_order, 
     int32_t* order = nullptr;
     if (g.depth >= 1 && g.depth - 1 >= l0) {
         if (want_order && g.nleaf <= kOrderCap) order = P->ws.leaf_order;
-        const unsigned nbx = (1u << (3 * (g.depth - 1))) + (order ? 1u : 0u);
-        k_downward<T><<<dim3(nbx, R), kTreeThreads, 0, st>>>(
+        // up to 64 boxes above the leaves: two blocks per box (four leaves
+        // each), so that the latency-bound chain runs on twice the CUs (one
+        // block of 512 threads fits a CU; four blocks per box would leave the
+        // order block without one)
+        const unsigned nbox1 = 1u << (3 * (g.depth - 1));
+        const bool half = nbox1 <= 64;
+        const unsigned nbx = nbox1 * (half ? 2u : 1u) + (order ? 1u : 0u);
+        auto down = half ? k_downward<T, 4> : k_downward<T, 8>;
+        down<<<dim3(nbx, R), kTreeThreads, 0, st>>>(
             g, l0, loc, (const T*)P->l2lT, (const T*)P->l2l_seg, mult, (const T*)P->m2mT,
             (const T*)P->m2m_seg, P->ws.leaf_part, P->ws.box_part, P->latT, P->lat_seg, P->ws.root_m, P->ws.root_l,
             P->ws.dom, P->ws.leaf_start, order, root_ready ? 1 : 0, fused ? (const T*)P->ws.m2l_part : nullptr,

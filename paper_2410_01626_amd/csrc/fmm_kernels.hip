@@ -1136,7 +1136,8 @@ __global__ __launch_bounds__(kTreeThreads) void k_m2m(Geo g, int lev, T* __restr
 // own atoms x neighbourhood atoms, gains < 1% more).  Work-groups go
 // round-robin over the 8 XCDs, so slot i runs on XCD i mod 8: when the eight
 // level-1 octants hold similar atom counts (none above 9/8 of the mean),
-// octant x's leaves take the slots of XCD x, largest first, and each XCD
+// octant x's leaves take the slots of XCD x (largest first, paired on the
+// CUs as described below), and each XCD
 // reads one octant's neighbourhoods through its own L2; otherwise all leaves
 // go largest first.  Key: octant, count (capped at 2^16 - 1), leaf index
 // (ties: lower leaf first); needs nleaf <= kOrderCap.
@@ -1166,11 +1167,18 @@ __device__ void leaf_work_order(const Geo& g, const int32_t* __restrict__ leaf_s
     }
     __syncthreads();
     lds_sort<kOrderCap>(key, nl);
+    // an XCD's slots fill its CUs one work-group each, then a second round:
+    // its leaves (count descending) take the first round in order and the
+    // second in reverse, so each CU pairs a larger leaf with a smaller one
     const int per = nl >> 3;
     for (int i = threadIdx.x; i < nl; i += blockDim.x) {
         const int32_t leaf = key[i] & (kOrderCap - 1);
-        if (by_xcd) order[8 * (i % per) + i / per] = leaf;
-        else order[i] = leaf;
+        if (by_xcd) {
+            const int r = i % per, h = per >> 1;
+            order[8 * (r < h ? r : h + (per - 1 - r)) + i / per] = leaf;
+        } else {
+            order[i] = leaf;
+        }
     }
 }
 
@@ -1317,17 +1325,19 @@ __device__ __forceinline__ T m2l_chunk_sum(const T* __restrict__ part, int nchun
     return (s0 + s1) + (s2 + s3);
 }
 
-// Downward pass in one launch: one block per box b of level depth - 1 forms
-// lambda~ of its ancestors from level l0 down (L2L of the parent's total plus
-// the box's own M2L sum, in FP64) and adds the L2L of lambda~_b into its 8
-// leaves.  Periodic systems (l0 = 0) start from the root: every block forms
+// Downward pass in one launch: 8 / NC blocks per box b of level depth - 1,
+// each of which forms lambda~ of b and its ancestors from level l0 down (L2L
+// of the parent's total plus the box's own M2L sum, in FP64) and adds the L2L
+// of lambda~_b into NC of its 8 leaves (fewer leaves per block: more blocks
+// share the latency-bound work, each box's chain is formed by each of its
+// blocks).  Periodic systems (l0 = 0) start from the root: every block forms
 // mu~_0 by M2M from the 8 level-1 multipoles and lambda~_0 = Lat mu~_0 +
 // (2 pi / 3) sum q |s/L|^2 e_0 itself (block 0 also stores mu~_0, lambda~_0 and
 // dom[4] = Q).  Ancestors shared by several blocks are recomputed by each;
 // only the leaf expansions are stored.  Open systems start at level l0 from
 // its M2L sum alone.  With root_ready the periodic root was already formed
 // (by the M2L reduction launch) and is read from root_l.
-template <typename T>
+template <typename T, int NC>
 __global__ __launch_bounds__(kTreeThreads) void k_downward(
     Geo g, int l0, T* __restrict__ loc_all, const T* __restrict__ l2l0, const T* __restrict__ l2l0_seg,
     const T* __restrict__ mult_all, const T* __restrict__ m2m0, const T* __restrict__ m2m0_seg,
@@ -1347,11 +1357,13 @@ __global__ __launch_bounds__(kTreeThreads) void k_downward(
     __shared__ T anc[kDMax * kKMax];
     TriPart<T, kTriUpper> tp;
     tp.load(g.K, l2l0_seg);
+    static_assert(8 % NC == 0, "whole leaf groups per block");
     const int rp = blockIdx.y, K = g.K, D = g.depth;
     T* loc = loc_all + (size_t)rp * g.nbox * g.Kp;
-    const int b = blockIdx.x;
+    // box b of level D - 1, its leaves c0 .. c0 + NC - 1
+    const int b = blockIdx.x / (8 / NC), c0 = (blockIdx.x - b * (8 / NC)) * NC;
     // prefetch, all loads in flight together: the M2L sums of the ancestors at
-    // levels la .. D - 1 and the 8 leaves' own expansions
+    // levels la .. D - 1 and the NC leaves' own expansions
     const int la = g.periodic ? l0 + 1 : l0;
     constexpr int kAncPer = (kDMax * kKMax + kTreeThreads - 1) / kTreeThreads;
     const int nanc = (D - la) * K;
@@ -1363,10 +1375,10 @@ __global__ __launch_bounds__(kTreeThreads) void k_downward(
         av[m] = nanc > 0 && !m2l_part_all ? loc[(size_t)(lev_offset(lev) + (b >> (3 * (D - 1 - lev)))) * g.Kp + k]
                                           : T(0);
     }
-    T* dst = loc + (size_t)(lev_offset(D) + 8 * (size_t)b) * g.Kp;
+    T* dst = loc + (size_t)(lev_offset(D) + 8 * (size_t)b + c0) * g.Kp;
 #pragma unroll
     for (int m = 0; m < kGatherPer; ++m) {
-        const int i = min((int)threadIdx.x + m * kTreeThreads, 8 * K - 1);
+        const int i = min((int)threadIdx.x + m * kTreeThreads, NC * K - 1);
         const int c = i / K, r = i - c * K;
         lv[m] = m2l_part_all ? T(0) : dst[(size_t)c * g.Kp + r];
     }
@@ -1375,14 +1387,14 @@ __global__ __launch_bounds__(kTreeThreads) void k_downward(
         const int i = threadIdx.x + m * kTreeThreads;
         if (i < nanc && !m2l_part_all) anc[i] = av[m];
     }
-    // without a reduction launch: the ancestors' and the 8 leaves' M2L sums
+    // without a reduction launch: the ancestors' and the NC leaves' M2L sums
     // from the offset-chunk partials, added here in the reduction's order
     __shared__ T lsum[8 * kKMax];
     if (m2l_part_all) {
         const int64_t tot = m2l_nt_all * g.Kp;
         const T* pr = m2l_part_all + (size_t)rp * m2l_nchunk * tot;
         const int64_t lo = lev_offset(g.lmin);
-        for (int i = threadIdx.x; i < nanc + 8 * K; i += kTreeThreads) {
+        for (int i = threadIdx.x; i < nanc + NC * K; i += kTreeThreads) {
             int64_t box;
             int k;
             if (i < nanc) {
@@ -1392,7 +1404,7 @@ __global__ __launch_bounds__(kTreeThreads) void k_downward(
             } else {
                 const int j = i - nanc, c = j / K;
                 k = j - c * K;
-                box = lev_offset(D) + 8 * (int64_t)b + c;
+                box = lev_offset(D) + 8 * (int64_t)b + c0 + c;
             }
             const T sv = m2l_chunk_sum<T>(pr, m2l_nchunk, tot, (box - lo) * g.Kp + k);
             if (i < nanc) anc[i] = sv;
@@ -1406,7 +1418,7 @@ __global__ __launch_bounds__(kTreeThreads) void k_downward(
         for (int k = threadIdx.x; k < K; k += kTreeThreads) v[k] = root_l_all[(size_t)rp * K + k];
     } else if (g.periodic) {
         periodic_root<T>(g, rp, mult_all, m2m0, m2m0_seg, leaf_part_all, box_part_all, latT, lat_seg,
-                         root_m_all, root_l_all, dom_all, xs, part, v, ps, b == 0);
+                         root_m_all, root_l_all, dom_all, xs, part, v, ps, blockIdx.x == 0);
     } else {
         __syncthreads();
         for (int k = threadIdx.x; k < K; k += kTreeThreads) v[k] = (double)anc[k];
@@ -1421,19 +1433,19 @@ __global__ __launch_bounds__(kTreeThreads) void k_downward(
             v[r] = (double)anc[(lev - la) * K + r] + refl_sign(c, refl_bits(r)) * xs[r];
         __syncthreads();
     }
-    for (int i = threadIdx.x; i < 8 * K; i += kTreeThreads) {
+    for (int i = threadIdx.x; i < NC * K; i += kTreeThreads) {
         const int c = i / K, k = i - c * K;
-        xs[i] = refl_sign(c, refl_bits(k)) * v[k];
+        xs[i] = refl_sign(c0 + c, refl_bits(k)) * v[k];
     }
     __syncthreads();
-    tri_matvec<T, 8, kTriUpper>(tp, K, l2l0, xs, part, xs);
+    tri_matvec<T, NC, kTriUpper>(tp, K, l2l0, xs, part, xs);
 #pragma unroll
     for (int m = 0; m < kGatherPer; ++m) {
         const int i = threadIdx.x + m * kTreeThreads;
-        if (i < 8 * K) {
+        if (i < NC * K) {
             const int c = i / K, r = i - c * K;
             const T own = m2l_part_all ? lsum[i] : lv[m];
-            dst[(size_t)c * g.Kp + r] = (T)((double)own + refl_sign(c, refl_bits(r)) * xs[i]);
+            dst[(size_t)c * g.Kp + r] = (T)((double)own + refl_sign(c0 + c, refl_bits(r)) * xs[i]);
         }
     }
 }
