@@ -33,6 +33,7 @@ struct Workspace {
     // leaf buckets of the binning (trees of at most kScanFuseCap leaves):
     // replicas x leaves x leaf_cap atom indices, the overflow list and its length
     int32_t *bucket = nullptr, *ovf = nullptr, *ovf_n = nullptr;
+    int32_t ovf_cap = 0;  // entries of ovf
     // the leaves' M2M terms into their parents (FP64, K per leaf), when the
     // leaf kernel takes the first M2M step
     double* m2m_part = nullptr;
@@ -217,6 +218,7 @@ size_t ws_layout(const fmm_plan_s* P, int64_t N, int64_t S, size_t RM, bool adjo
         take(w->bucket, RM * nl * (size_t)P->leaf_cap * 4);
         take(w->ovf, N * 4);
         take(w->ovf_n, 4);
+        w->ovf_cap = (int32_t)N;
     } else {
         w->bucket = w->ovf = w->ovf_n = nullptr;
     }
@@ -548,7 +550,7 @@ void enqueue_bin_p2m(fmm_plan_t P, const fmmk::Geo& g, RepSpan rd, int R,
     // bucket binning: the leaf kernel finds each leaf's atoms in its bucket and
     // forms the leaf and site starts itself (no scan or scatter launch)
     const bool binned = P->ws.bucket && g.nleaf <= kScanFuseCap && S_tot <= kScanFuseCap;
-    const Bins bins{binned ? P->ws.bucket : nullptr, P->leaf_cap, P->ws.ovf, P->ws.ovf_n};
+    const Bins bins{binned ? P->ws.bucket : nullptr, P->leaf_cap, P->ws.ovf, P->ws.ovf_n, P->ws.ovf_cap};
     k_charge_key<T><<<dim3(ab, R), 256, 0, st>>>(g, set0, P->ws.reps, x, qA, qB, site, lam, fa, P->ws.dom, P->ws.key,
                                                  P->ws.rank, P->ws.leaf_count, P->ws.site_count,
                                                  P->ws.site_rank, P->status, bins);

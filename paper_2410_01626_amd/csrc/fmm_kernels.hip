@@ -315,14 +315,16 @@ __device__ __forceinline__ int32_t agg_slot(const AggPlan& pl, int32_t got) {
 }
 
 // Leaf buckets of the binning: atom indices filed per (replica, leaf) at
-// their rank below cap, the rest appended to one overflow list (ovf_n: its
-// length, zeroed by the final reduction).  bucket == null: binning by a
-// global scan and scatter instead.
+// their rank below cap, the rest appended to one overflow list of ovf_cap
+// entries (ovf_n: its length, zeroed by the final reduction; every atom is
+// appended at most once per evaluation, so ovf_cap = the atom count holds
+// them all).  bucket == null: binning by a global scan and scatter instead.
 struct Bins {
     int32_t* bucket;
     int32_t cap;
     int32_t* ovf;
     int32_t* ovf_n;
+    int32_t ovf_cap;
 };
 
 // What the leaf kernel needs besides the buckets to bin without a scatter
@@ -415,7 +417,10 @@ __global__ __launch_bounds__(256) void k_charge_key(
     site_rank[i] = sr;
     if (bins.bucket) {
         if (lr < bins.cap) bins.bucket[((size_t)r * g.nleaf + k) * bins.cap + lr] = (int32_t)i;
-        else bins.ovf[atomicAdd(bins.ovf_n, 1)] = (int32_t)i;
+        else {
+            const int32_t o = atomicAdd(bins.ovf_n, 1);
+            if (o < bins.ovf_cap) bins.ovf[o] = (int32_t)i;
+        }
     }
     if (g.check) {
         bad |= !finite_d((double)qA[i]) || !finite_d((double)qB[i]);
@@ -782,7 +787,7 @@ __global__ __launch_bounds__(kLeafThreads) void k_leaf_p2m(
     auto fill_members = [&](int32_t* dst) {
         for (int r = tid; r < min(n, bins.cap); r += kLeafThreads) dst[r] = bk[r];
         if (n > bins.cap) {
-            const int no = *bins.ovf_n;
+            const int no = min(*bins.ovf_n, bins.ovf_cap);
             for (int o = tid; o < no; o += kLeafThreads) {
                 const int32_t i = bins.ovf[o];
                 if (i >= rd.a0 && i < rd.a0 + rd.n && lb.key[i] == leaf) dst[lb.rank[i]] = i;
@@ -994,6 +999,8 @@ __device__ __forceinline__ void gather_children(const Geo& g, int clev, int64_t 
     T v[kGatherPer];
 #pragma unroll
     for (int m = 0; m < kGatherPer; ++m) {
+        v[m] = T(0);
+        if (m * kTreeThreads >= 8 * K) continue;  // a round with no coefficient
         const int i = min((int)threadIdx.x + m * kTreeThreads, 8 * K - 1);
         const int c = i / K, k = i - c * K;
         v[m] = src[(size_t)c * g.Kp + k];
@@ -1029,6 +1036,8 @@ __device__ __forceinline__ void gather_children_parts(const Geo& g, int64_t box,
     double v[kGatherPer];
 #pragma unroll
     for (int m = 0; m < kGatherPer; ++m) {
+        v[m] = 0.0;
+        if (m * kTreeThreads >= 8 * K) continue;  // a round with no coefficient
         const int i = min((int)threadIdx.x + m * kTreeThreads, 8 * K - 1);
         const int c = i / K, k = i - c * K;
         double t[8];
@@ -1085,7 +1094,7 @@ __global__ __launch_bounds__(kTreeThreads) void k_m2m(Geo g, int lev, T* __restr
                                                       uint16_t* __restrict__ msplit_all, int split_kp,
                                                       double* __restrict__ root_part_all,
                                                       const double* __restrict__ m2m_part_all) {
-    __shared__ double xs[8 * kKMax], part[8 * kTreeThreads], ps[16], vb[kKMax];
+    __shared__ double xs[8 * kKMax], part[8 * kTreeThreads], ps[16];
     TriPart<T, kTriLower> tp;
     tp.load(g.K, op0_seg);
     const int rp = blockIdx.y, K = g.K, box = blockIdx.x;
@@ -1106,7 +1115,9 @@ __global__ __launch_bounds__(kTreeThreads) void k_m2m(Geo g, int lev, T* __restr
     for (int r = threadIdx.x; r < K; r += kTreeThreads) {
         const double v = combine_octants(xs, K, r);
         mult[(size_t)gb * g.Kp + r] = (T)v;
-        vb[r] = v;
+        // the root share's input S_c mu (octant c = box) over column 0 of xs:
+        // this thread alone reads row r of every column above
+        if (root_part_all) xs[r] = refl_sign(box, refl_bits(r)) * v;
         if constexpr (sizeof(T) == 4)
             if (msplit_all)
                 store_split(msplit_all + (size_t)rp * (g.nbox + 1) * 2 * split_kp, split_kp, gb, r, (float)v);
@@ -1120,8 +1131,6 @@ __global__ __launch_bounds__(kTreeThreads) void k_m2m(Geo g, int lev, T* __restr
         // level 1 of a periodic tree: this box's share of the root multipole,
         // S_c A_0 S_c mu (octant c = box), in FP64 from the unrounded sums;
         // the root is the fixed-order sum of the eight shares
-        __syncthreads();
-        for (int k = threadIdx.x; k < K; k += kTreeThreads) xs[k] = refl_sign(box, refl_bits(k)) * vb[k];
         __syncthreads();
         tri_matvec<T, 1, kTriLower>(tp, K, op0, xs, part, xs);
         double* rpart = root_part_all + ((size_t)rp * 8 + box) * K;
