@@ -530,7 +530,7 @@ __global__ __launch_bounds__(256) void k_adj_combine(
     const T* __restrict__ acc, T* __restrict__ phi_out, T* __restrict__ F_out, T* __restrict__ gx,
     T* __restrict__ gqA, T* __restrict__ gqB, double* __restrict__ cphi, double* __restrict__ cphi2,
     double* __restrict__ part) {
-    __shared__ double red[256];
+    __shared__ double red[4];
     const int t = threadIdx.x;
     const int64_t i = (int64_t)blockIdx.x * 256 + t;
     const RepDesc rd{0, n, 0, S, 0.0, 0};
@@ -598,13 +598,11 @@ __global__ __launch_bounds__(256) void k_adj_combine(
         }
         e = qi * v[0];
     }
-    red[t] = e;
+    // fixed order: a butterfly within each wavefront, then the four sums in order
+    e = wave_sum<double>(e);
+    if ((t & 63) == 0) red[t >> 6] = e;
     __syncthreads();
-    for (int st = 128; st > 0; st >>= 1) {
-        if (t < st) red[t] += red[t + st];
-        __syncthreads();
-    }
-    if (t == 0) part[blockIdx.x] = red[0];
+    if (t == 0) part[blockIdx.x] = ((red[0] + red[1]) + red[2]) + red[3];
 }
 
 }  // namespace fmmk

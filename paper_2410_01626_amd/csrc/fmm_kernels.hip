@@ -2968,7 +2968,7 @@ __global__ __launch_bounds__(256) void k_reduce(Geo g, int R, int64_t nparts,
                                                 const double* __restrict__ excl_e, int excl_parts,
                                                 const double* __restrict__ cphi2,
                                                 double* __restrict__ glam, int32_t* __restrict__ ovf_n) {
-    __shared__ double red[256], red_t[256];
+    __shared__ double red[4], red_t[4];
     __shared__ int32_t mem[kSiteCap];
     const int t = threadIdx.x;
     const int b = blockIdx.x;
@@ -3014,17 +3014,18 @@ __global__ __launch_bounds__(256) void k_reduce(Geo g, int R, int64_t nparts,
             for (int i = t; i < n; i += 256) add(site_members[m0 + i]);
         }
     }
-    red[t] = v;
-    red_t[t] = vt;
-    __syncthreads();
-    for (int st = 128; st > 0; st >>= 1) {
-        if (t < st) {
-            red[t] += red[t + st];
-            red_t[t] += red_t[t + st];
-        }
-        __syncthreads();
+    // fixed order: a butterfly within each wavefront, then the four
+    // wavefronts' sums in order (one barrier)
+    v = wave_sum<double>(v);
+    vt = wave_sum<double>(vt);
+    if ((t & 63) == 0) {
+        red[t >> 6] = v;
+        red_t[t >> 6] = vt;
     }
+    __syncthreads();
     if (t == 0) {
+        red[0] = ((red[0] + red[1]) + red[2]) + red[3];
+        red_t[0] = ((red_t[0] + red_t[1]) + red_t[2]) + red_t[3];
         if (b < R) {
             double e = 0.5 * g.coulomb_k * red[0];
             if (hc_e) {  // Hamiltonian interpolation: the replica's site corrections, in order
