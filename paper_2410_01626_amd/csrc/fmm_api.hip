@@ -623,6 +623,15 @@ int32_t* enqueue_tree(fmm_plan_t P, const fmmk::Geo& g, int R, bool want_order, 
             root_ready = launch_m2l_mma<T>(P, g, R, root_in_reduce, &fused);
         }
     }
+    // deep periodic trees whose M2L launches did not form the root (no
+    // offset chunks): the root once (a single root block of the reduction
+    // kernel), instead of in every block of a downward pass of several rounds
+    if (g.periodic && !root_ready && !fused && g.depth >= 1 && (1u << (3 * (g.depth - 1))) > 256) {
+        k_m2l_reduce<T><<<dim3(1, R), kTreeThreads, 0, st>>>(
+            g, P->mg, (const T*)P->ws.m2l_part, loc, 1, mult, (const T*)P->m2mT, (const T*)P->m2m_seg,
+            P->ws.leaf_part, P->ws.box_part, P->latT, P->lat_seg, P->ws.root_m, P->ws.root_l, P->ws.dom, nullptr);
+        root_ready = true;
+    }
     // downward pass: ancestors' local expansions and the L2L into the leaves
     mark(P, 5);
     const int l0 = g.periodic ? 0 : g.lmin;
@@ -637,13 +646,24 @@ int32_t* enqueue_tree(fmm_plan_t P, const fmmk::Geo& g, int R, bool want_order, 
         // order block without one)
         const unsigned nbox1 = 1u << (3 * (g.depth - 1));
         const bool half = nbox1 <= 64;
+        // deep trees whose M2L sums are all in loc and whose root is formed:
+        // the levels from l0 + 1 to d - 2 one launch each (every box once),
+        // the downward launch from there (its blocks would otherwise each
+        // redo the whole ancestor chain)
+        int l_start = l0;
+        if (!fused && (root_ready || !g.periodic) && g.depth - 1 - l0 >= 4) {
+            for (int lev = l0 + 1; lev <= g.depth - 2; ++lev)
+                k_l2l_level<T><<<dim3(1u << (3 * lev), R), kTreeThreads, 0, st>>>(
+                    g, lev, l0, loc, (const T*)P->l2lT, (const T*)P->l2l_seg, P->ws.root_l);
+            l_start = g.depth - 2;
+        }
         const unsigned nbx = nbox1 * (half ? 2u : 1u) + (order ? 1u : 0u);
         auto down = half ? k_downward<T, 4> : k_downward<T, 8>;
         down<<<dim3(nbx, R), kTreeThreads, 0, st>>>(
             g, l0, loc, (const T*)P->l2lT, (const T*)P->l2l_seg, mult, (const T*)P->m2mT,
             (const T*)P->m2m_seg, P->ws.leaf_part, P->ws.box_part, P->latT, P->lat_seg, P->ws.root_m, P->ws.root_l,
             P->ws.dom, P->ws.leaf_start, order, root_ready ? 1 : 0, fused ? (const T*)P->ws.m2l_part : nullptr,
-            P->mg.nchunk, P->mg.nt_all);
+            P->mg.nchunk, P->mg.nt_all, l_start);
     }
     return order;
 }

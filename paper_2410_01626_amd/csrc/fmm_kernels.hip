@@ -1334,6 +1334,36 @@ __device__ __forceinline__ T m2l_chunk_sum(const T* __restrict__ part, int nchun
     return (s0 + s1) + (s2 + s3);
 }
 
+// One level of the downward pass for deep trees (one block per box of level
+// lev): lambda~_box = its M2L sum (in loc) + S_c A_0 S_c lambda~_parent, the
+// parent's whole expansion read from loc (the root's from root_l when the
+// parent is the periodic root), stored back into loc in T.  The blocks of the
+// next level, and the downward pass started below the stored levels, read it.
+template <typename T>
+__global__ __launch_bounds__(kTreeThreads) void k_l2l_level(Geo g, int lev, int l0, T* __restrict__ loc_all,
+                                                          const T* __restrict__ l2l0,
+                                                          const T* __restrict__ l2l0_seg,
+                                                          const double* __restrict__ root_l_all) {
+    __shared__ double xs[kKMax], part[kTreeThreads];
+    const int rp = blockIdx.y, K = g.K, box = blockIdx.x, c = box & 7;
+    TriPart<T, kTriUpper> tp;
+    tp.load(K, l2l0_seg);
+    T* loc = loc_all + (size_t)rp * g.nbox * g.Kp;
+    const int64_t gb = lev_offset(lev) + box;
+    const T own = (int)threadIdx.x < K ? loc[(size_t)gb * g.Kp + threadIdx.x] : T(0);
+    for (int k = threadIdx.x; k < K; k += kTreeThreads) {
+        const double pv = g.periodic && lev == l0 + 1
+                              ? root_l_all[(size_t)rp * K + k]
+                              : (double)loc[(size_t)(lev_offset(lev - 1) + (box >> 3)) * g.Kp + k];
+        xs[k] = refl_sign(c, refl_bits(k)) * pv;
+    }
+    __syncthreads();
+    tri_matvec<T, 1, kTriUpper>(tp, K, l2l0, xs, part, xs);
+    if ((int)threadIdx.x < K)
+        loc[(size_t)gb * g.Kp + threadIdx.x] =
+            (T)((double)own + refl_sign(c, refl_bits(threadIdx.x)) * xs[threadIdx.x]);
+}
+
 // Downward pass in one launch: 8 / NC blocks per box b of level depth - 1,
 // each of which forms lambda~ of b and its ancestors from level l0 down (L2L
 // of the parent's total plus the box's own M2L sum, in FP64) and adds the L2L
@@ -1354,7 +1384,7 @@ __global__ __launch_bounds__(kTreeThreads) void k_downward(
     const double* __restrict__ latT, const double* __restrict__ lat_seg, double* __restrict__ root_m_all,
     double* __restrict__ root_l_all, double* __restrict__ dom_all,
     const int32_t* __restrict__ leaf_start_all, int32_t* __restrict__ leaf_order_all,
-    int root_ready, const T* __restrict__ m2l_part_all, int m2l_nchunk, int64_t m2l_nt_all) {
+    int root_ready, const T* __restrict__ m2l_part_all, int m2l_nchunk, int64_t m2l_nt_all, int l_start) {
     __shared__ double xs[8 * kKMax], part[8 * kTreeThreads];
     if (leaf_order_all && blockIdx.x + 1 == gridDim.x) {
         // the extra last block: the near-field order of this replica's leaves
@@ -1420,7 +1450,12 @@ __global__ __launch_bounds__(kTreeThreads) void k_downward(
             else lsum[i - nanc] = sv;
         }
     }
-    if (g.periodic && root_ready) {
+    if (l_start > l0) {
+        // the ancestor at level l_start already holds its whole local
+        // expansion (k_l2l_level launches; no offset-chunk partials here)
+        __syncthreads();
+        for (int k = threadIdx.x; k < K; k += kTreeThreads) v[k] = (double)anc[(l_start - la) * K + k];
+    } else if (g.periodic && root_ready) {
         // formed by the extra block of the M2L reduction launch, or by the
         // resident-source M2L launch's extra work-group
         __syncthreads();
@@ -1433,7 +1468,7 @@ __global__ __launch_bounds__(kTreeThreads) void k_downward(
         for (int k = threadIdx.x; k < K; k += kTreeThreads) v[k] = (double)anc[k];
     }
     __syncthreads();
-    for (int lev = l0 + 1; lev < D; ++lev) {
+    for (int lev = l_start + 1; lev < D; ++lev) {
         const int a = b >> (3 * (D - 1 - lev)), c = a & 7;
         for (int k = threadIdx.x; k < K; k += kTreeThreads) xs[k] = refl_sign(c, refl_bits(k)) * v[k];
         __syncthreads();
