@@ -92,7 +92,8 @@ typedef enum { FMM_FP64 = 0, FMM_MIXED_F32 = 1, FMM_MIXED_BF16X3 = 2 } fmm_preci
  *               that copies every column's source per offset even where the
  *               bf16x3 kernel could keep a class's sources resident (depth <= 3)
  *   m2l_chunk   offsets per matrix-core M2L work-group (0 = automatic, else 1..189)
- *   p2p_waves   wavefronts per near-field block: 4, 8 or 16 (0 = 8)
+ *   p2p_waves   wavefronts per near-field block: 4, 8 or 16 (0 = automatic: 4
+ *               when max_atoms / (max_replicas 8^d) <= 32, else 8)
  *   p2p_split   near-field blocks per leaf, 1 to 4 (0 = 1): with more than one,
  *               block s of a leaf takes its targets 32 s .. 32 s + 31 (the last
  *               block all the rest), so the hardware can balance uneven leaves
