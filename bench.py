@@ -160,7 +160,7 @@ def main():
         prof = plan.profile_read()
         return {k: (v[0] / v[1] if v[1] else 0.0) for k, v in prof.items()}
 
-    def timed(plan, inp, steps, warmup, roof_phase=None, every=10):
+    def timed(plan, inp, steps, warmup, roof_phase=None, every=20):
         """Seconds per evaluation over `steps` timed evaluations; with roof_phase,
         HIP events on the plan's stream around that phase on every `every`-th
         timed evaluation give its mean duration (ms) inside the timed region."""
