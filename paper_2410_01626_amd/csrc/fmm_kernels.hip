@@ -297,8 +297,10 @@ __device__ __forceinline__ AggPlan agg_plan(uint32_t key, bool active) {
     uint64_t todo = __ballot(active);
     AggPlan pl{0, -1, 0};
     while (todo) {
+        // the leader is the same for every lane (from a wavefront-wide mask):
+        // its key by a scalar lane read, not a cross-lane permute through LDS
         const int leader = __ffsll((unsigned long long)todo) - 1;
-        const uint32_t lk = (uint32_t)__shfl((int)key, leader, 64);
+        const uint32_t lk = (uint32_t)__builtin_amdgcn_readlane((int)key, leader);
         const uint64_t peers = __ballot(active && key == lk) & todo;
         if (lane == leader) pl.count = __popcll(peers);
         if ((peers >> lane) & 1) {
