@@ -260,13 +260,8 @@ __global__ __launch_bounds__(64 * kNW, sizeof(T) == 4 ? 4 : 1) void k_near_adj(
         nb_off[tid][2] = (T)(dz * h);
     }
     if (wave == 0) {
-        // inclusive scan of the 27 counts across lanes (shuffles, in registers)
-        int v = my_cnt;
-#pragma unroll
-        for (int off = 1; off < 32; off <<= 1) {
-            const int u = __shfl_up(v, off, 64);
-            if (lane >= off) v += u;
-        }
+        // inclusive scan of the 27 counts across lanes (in registers)
+        const int v = wave_scan<int>(my_cnt);
         if (lane < 27) nb_pre[lane + 1] = v;
         if (lane == 0) {
             nb_pre[0] = 0;
@@ -598,7 +593,7 @@ __global__ __launch_bounds__(256) void k_adj_combine(
         }
         e = qi * v[0];
     }
-    // fixed order: a butterfly within each wavefront, then the four sums in order
+    // fixed order: a DPP scan within each wavefront, then the four sums in order
     e = wave_sum<double>(e);
     if ((t & 63) == 0) red[t >> 6] = e;
     __syncthreads();

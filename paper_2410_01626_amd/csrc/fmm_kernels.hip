@@ -167,11 +167,42 @@ __device__ __forceinline__ void for_rho_orders(int p, const RhoLds<T>& rc, int m
     }
 }
 
+// Inclusive scan across the 64 lanes by DPP moves (register to register, no
+// LDS crossbar): shifts by 1, 2, 4 and 8 lanes within each row of 16 (a lane
+// shifted in from outside the row reads 0), then the last lane of row 0 added
+// to row 1 and that of row 2 to row 3, then lane 31 (the first two rows'
+// total) added to rows 2 and 3.  Every lane of the wavefront must be active.
+template <typename T>
+__device__ __forceinline__ T wave_scan(T v) {
+    v += __builtin_amdgcn_update_dpp(T(0), v, 0x111, 0xf, 0xf, true);  // row_shr:1
+    v += __builtin_amdgcn_update_dpp(T(0), v, 0x112, 0xf, 0xf, true);  // row_shr:2
+    v += __builtin_amdgcn_update_dpp(T(0), v, 0x114, 0xf, 0xf, true);  // row_shr:4
+    v += __builtin_amdgcn_update_dpp(T(0), v, 0x118, 0xf, 0xf, true);  // row_shr:8
+    v += __builtin_amdgcn_update_dpp(T(0), v, 0x142, 0xa, 0xf, true);  // row_bcast:15
+    v += __builtin_amdgcn_update_dpp(T(0), v, 0x143, 0xc, 0xf, true);  // row_bcast:31
+    return v;
+}
+
+// Lane l's value as a wavefront-uniform one, bit for bit (the readlane
+// builtin returns int: a floating-point argument would be converted)
+template <typename T>
+__device__ __forceinline__ T lane_value(T v, int l) {
+    if constexpr (sizeof(T) == 8) {
+        const uint64_t u = __builtin_bit_cast(uint64_t, v);
+        const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)u, l);
+        const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(u >> 32), l);
+        return __builtin_bit_cast(T, ((uint64_t)hi << 32) | lo);
+    } else {
+        static_assert(sizeof(T) == 4, "32- or 64-bit lane values");
+        return __builtin_bit_cast(T, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), l));
+    }
+}
+
+// Sum over the 64 lanes in a fixed order (the scan's last lane), returned as
+// a wavefront-uniform value.  Every lane must be active.
 template <typename T>
 __device__ __forceinline__ T wave_sum(T v) {
-#pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
-    return v;
+    return lane_value<T>(wave_scan<T>(v), 63);
 }
 
 __device__ __forceinline__ bool finite_d(double v) { return isfinite(v); }
@@ -755,12 +786,7 @@ __global__ __launch_bounds__(kLeafThreads) void k_leaf_p2m(
         // the leaves before it (published as leaf_start); the site starts by
         // a scan of the counts, within each wavefront by shuffles
         pre = wave_sum<int32_t>(pre);
-        int32_t inc = sc;
-#pragma unroll
-        for (int off = 1; off < 64; off <<= 1) {
-            const int32_t u = __shfl_up(inc, off, 64);
-            if (lane >= off) inc += u;
-        }
+        const int32_t inc = wave_scan<int32_t>(sc);
         if (lane == 0) wpre[wave] = pre;
         if (lane == 63) wsite[wave] = inc;
         __syncthreads();
@@ -2435,13 +2461,8 @@ __global__ __launch_bounds__(64 * kNW) void k_near_far(
         nb_off[tid][2] = (T)(dz * h);
     }
     if (wave == 0) {
-        // inclusive scan of the 27 counts across lanes (shuffles, in registers)
-        int v = my_cnt;
-#pragma unroll
-        for (int off = 1; off < 32; off <<= 1) {
-            const int u = __shfl_up(v, off, 64);
-            if (lane >= off) v += u;
-        }
+        // inclusive scan of the 27 counts across lanes (in registers)
+        const int v = wave_scan<int>(my_cnt);
         if (lane < 27) nb_pre[lane + 1] = v;
         if (lane == 0) {
             nb_pre[0] = 0;
@@ -3051,7 +3072,7 @@ __global__ __launch_bounds__(256) void k_reduce(Geo g, int R, int64_t nparts,
             for (int i = t; i < n; i += 256) add(site_members[m0 + i]);
         }
     }
-    // fixed order: a butterfly within each wavefront, then the four
+    // fixed order: a DPP scan within each wavefront, then the four
     // wavefronts' sums in order (one barrier)
     v = wave_sum<double>(v);
     vt = wave_sum<double>(vt);
