@@ -784,7 +784,7 @@ __global__ __launch_bounds__(kLeafThreads) void k_leaf_p2m(
         n = lc[leaf];
         // this leaf's first atom: the replica's first atom plus the counts of
         // the leaves before it (published as leaf_start); the site starts by
-        // a scan of the counts, within each wavefront by shuffles
+        // a scan of the counts, within each wavefront by DPP moves
         pre = wave_sum<int32_t>(pre);
         const int32_t inc = wave_scan<int32_t>(sc);
         if (lane == 0) wpre[wave] = pre;
